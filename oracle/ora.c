@@ -1,0 +1,922 @@
+/*
+ * Oracle for the particle side of the coarse-grained CFD-DEM reduction model
+ * of arxiv 2311.03908.  TEST INFRASTRUCTURE ONLY (see ora.h).
+ *
+ * Plain FP64, single thread, ascending-id loops, built with
+ * -ffp-contract=off so that the contact predicate is evaluated exactly as
+ * written.  Function headers cite the paper's equations; readings of passages
+ * the paper leaves open are marked "reading:".
+ */
+#include "ora.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define RG 8.314 /* gas constant, Section 2.1 */
+#define PI 3.14159265358979323846
+#define HCAP 64  /* pair-history entries per parcel (partners with larger id) */
+
+/* molar masses in g/mol: Fe2O3, Fe3O4, FeO, Fe and H2, H2O, N2 */
+static const double MS[4] = {159.687, 231.531, 71.844, 55.845};
+static const double MG[3] = {2.016, 18.015, 28.013};
+/* Fuller diffusion volumes (cm3/mol) of H2, H2O, N2 (Section 2.3) */
+static const double VD[3] = {7.07, 12.7, 17.9};
+/* viscosity polynomials a1 + a2 T + a3 T^2 of H2, H2O, N2 (Table C2) */
+static const double MUC[3][3] = {{2.85e-6, 2.16e-8, -3.78e-12},
+                                 {-4.44e-6, 4.52e-8, -3.20e-12},
+                                 {7.86e-6, 3.87e-8, -5.11e-12}};
+/* K_eq = exp(a/T + b) of R1..R3 (Table 2) */
+static const double KEQ[3][2] = {{1433.4, 9.08}, {-7393.9, 7.56}, {-2023.8, 1.24}};
+
+typedef struct {
+  int partner;
+  double xi[3];
+} hist_t;
+
+struct ora_sys {
+  ora_params P;
+  ora_bed *beds;
+  ora_ore *ores;
+  int n, n_cells;
+  double *pos, *vel, *omg; /* 3 per parcel */
+  double *d, *k, *mass, *sp; /* sp: nh, nm, nw, nfe per parcel */
+  int *ore, *bed;
+  int *hcnt;
+  hist_t *hist;
+  double *wxi;          /* 6 walls x 3 per parcel */
+  unsigned char *won;   /* 6 per parcel */
+  double *eps;          /* gas voidage per cell from the last deposit */
+};
+
+/* ------------------------------------------------------------ vectors */
+static double dot3(const double a[3], const double b[3]) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+static void cross3(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double norm3(const double a[3]) { return sqrt(dot3(a, a)); }
+
+/* ------------------------------------------------------------ dual numbers
+ * Forward-mode derivatives with respect to the six kinetic parameters. */
+typedef struct {
+  double v, d[6];
+} dual;
+
+static dual D(double v) {
+  dual r;
+  r.v = v;
+  memset(r.d, 0, sizeof r.d);
+  return r;
+}
+static dual dadd(dual a, dual b) {
+  dual r;
+  r.v = a.v + b.v;
+  for (int i = 0; i < 6; i++) r.d[i] = a.d[i] + b.d[i];
+  return r;
+}
+static dual dsub(dual a, dual b) {
+  dual r;
+  r.v = a.v - b.v;
+  for (int i = 0; i < 6; i++) r.d[i] = a.d[i] - b.d[i];
+  return r;
+}
+static dual dmul(dual a, dual b) {
+  dual r;
+  r.v = a.v * b.v;
+  for (int i = 0; i < 6; i++) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+  return r;
+}
+static dual ddiv(dual a, dual b) {
+  dual r;
+  r.v = a.v / b.v;
+  for (int i = 0; i < 6; i++) r.d[i] = (a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v);
+  return r;
+}
+static dual dscale(dual a, double s) {
+  dual r;
+  r.v = a.v * s;
+  for (int i = 0; i < 6; i++) r.d[i] = a.d[i] * s;
+  return r;
+}
+static dual dpowc(dual a, double e) {
+  dual r;
+  r.v = pow(a.v, e);
+  double f = e * pow(a.v, e - 1.0);
+  for (int i = 0; i < 6; i++) r.d[i] = f * a.d[i];
+  return r;
+}
+static dual dinv(dual a) { return ddiv(D(1.0), a); }
+
+/* ------------------------------------------------------------ gas properties */
+
+/* eq. e3-53 (ideal gas) and eqs. e3-55/e3-56 (mass-weighted viscosity, Table C2) */
+void ora_gas_props(double T, double p, double xh2, double xh2o, double xn2, double mu_override,
+                   double *rho, double *mu) {
+  double xs[3] = {xh2, xh2o, xn2};
+  double Mg = 0.0; /* g/mol, eq. e2-1-2 written with mole fractions */
+  for (int j = 0; j < 3; j++) Mg += xs[j] * MG[j];
+  *rho = p * (Mg * 1e-3) / (RG * T);
+  if (mu_override > 0.0) {
+    *mu = mu_override;
+    return;
+  }
+  double m = 0.0;
+  for (int j = 0; j < 3; j++) {
+    double Y = xs[j] * MG[j] / Mg; /* mass fraction from eq. e2-1-1 */
+    m += Y * (MUC[j][0] + MUC[j][1] * T + MUC[j][2] * T * T);
+  }
+  *mu = m;
+}
+
+/* eq. e2-26: Fuller-Schettler-Giddings binary diffusivity in m2/s (M in g/mol) */
+double ora_fuller(double T, double p, int i, int j) {
+  double a = pow(VD[i], 1.0 / 3.0) + pow(VD[j], 1.0 / 3.0);
+  return 1e-7 * pow(T, 1.75) * sqrt(1.0 / MG[i] + 1.0 / MG[j]) / ((p / 101325.0) * a * a);
+}
+
+/* eq. e2-27: Wilke's molecular diffusivity of H2 in the mixture.
+ * reading: for a gas with no species but H2 the expression is 0/0; the
+ * binary H2-H2O coefficient is used. */
+double ora_wilke_h2(double T, double p, double xh2, double xh2o, double xn2) {
+  double others = xh2o + xn2;
+  if (others < 1e-12) return ora_fuller(T, p, 0, 1);
+  double s = xh2o / ora_fuller(T, p, 0, 1) + xn2 / ora_fuller(T, p, 0, 2);
+  return (1.0 - xh2) / s;
+}
+
+/* eq. e2-28: Knudsen diffusivity of H2, r_a in cm, result in m2/s */
+double ora_knudsen_h2(double T, double d_pore_cm) { return 0.97 * (0.5 * d_pore_cm) * sqrt(T / MG[0]); }
+
+/* Section 2.3: regime by lambda/d_a with lambda = 1.013/(p x_H2) cm; eq. e2-29 in the transition */
+double ora_pore_diff(double T, double p, double xh2, double xh2o, double xn2, double d_pore_cm) {
+  double Dm = ora_wilke_h2(T, p, xh2, xh2o, xn2);
+  double DK = ora_knudsen_h2(T, d_pore_cm);
+  double ratio = (xh2 > 0.0) ? (1.013 / (p * xh2)) / d_pore_cm : INFINITY;
+  if (ratio <= 0.01) return Dm;
+  if (ratio >= 10.0) return DK;
+  return 1.0 / (1.0 / Dm + 1.0 / DK);
+}
+
+/* eqs. e2-31..e2-36: porosity of the Fe2O3 core and of the Fe3O4, FeO, Fe layers */
+void ora_layer_porosity(const ora_ore *o, double xi[4]) {
+  double q_mh = 2.0 * MS[1] / (3.0 * MS[0]); /* 3Fe2O3 -> 2Fe3O4 */
+  double q_wm = 3.0 * MS[2] / MS[1];         /* Fe3O4 -> 3FeO */
+  double q_fw = MS[3] / MS[2];               /* FeO -> Fe */
+  double re_h = (1.0 - o->xi0) * o->rho_true[0];
+  double re_m = re_h * q_mh, re_w = re_m * q_wm, re_f = re_w * q_fw;
+  xi[0] = 1.0 - re_h / o->rho_true[0];
+  xi[1] = 1.0 - re_m / o->rho_true[1];
+  xi[2] = 1.0 - re_w / o->rho_true[2];
+  xi[3] = 1.0 - re_f / o->rho_true[3];
+}
+
+/* eq. e2-22 (Gunn) */
+double ora_sherwood(double eps, double Re, double Sc) {
+  double sc3 = pow(Sc, 1.0 / 3.0);
+  return (7.0 - 10.0 * eps + 5.0 * eps * eps) * (1.0 + 0.7 * pow(Re, 0.2) * sc3) +
+         (1.33 - 2.4 * eps + 1.2 * eps * eps) * pow(Re, 0.7) * sc3;
+}
+
+/* eqs. e2-20, e2-21, e2-23, e2-24: film resistance F = d_p / (Sh D_eff,f), with
+ * D_eff,f the molecular diffusivity (eq. e2-27) */
+double ora_film(double T, double p, double xh2, double xh2o, double xn2, double mu_override,
+                double eps, double slip, double dp) {
+  double rho, mu;
+  ora_gas_props(T, p, xh2, xh2o, xn2, mu_override, &rho, &mu);
+  double Df = ora_wilke_h2(T, p, xh2, xh2o, xn2);
+  double Re = rho * eps * dp * slip / mu;
+  double Sc = mu / (rho * Df);
+  return dp / (ora_sherwood(eps, Re, Sc) * Df);
+}
+
+/* Table 2 equilibrium constants and eq. e2-1-3 */
+double ora_keq(int i, double T) { return exp(KEQ[i][0] / T + KEQ[i][1]); }
+
+/* eq. e3-5-1 divided by eps_p = 1 - eps_g, so that F_d = (beta/eps_p) V (u_g - v)
+ * (eq. e3-5) stays finite in a cell of unit voidage.  reading: Gidaspow's
+ * inertial Ergun term carries eps_p (printed: eps_g, selectable); C_D is
+ * Schiller-Naumann with the eps-weighted Re of eq. e2-23; eps = 0.8 takes the
+ * Wen-Yu branch. */
+double ora_beta_over_epsp(double eps, double rho, double mu, double slip, double dp, int printed) {
+  double ep = 1.0 - eps;
+  if (eps < 0.8) {
+    double inertial = printed ? 1.75 * eps * rho * slip / (dp * ep) : 1.75 * rho * slip / dp;
+    return 150.0 * ep * mu / (eps * dp * dp) + inertial;
+  }
+  double Re = rho * eps * dp * slip / mu;
+  double cdre = (Re < 1000.0) ? 24.0 * (1.0 + 0.15 * pow(Re, 0.687)) : 0.44 * Re;
+  return 0.75 * cdre * mu * pow(eps, -2.65) / (dp * dp);
+}
+
+/* eq. e3-45; reading: a non-positive radicand means a perfectly inelastic parcel */
+double ora_e_cgp(double e_p, double k) {
+  double a = 1.0 + k * (e_p * e_p - 1.0);
+  return a > 0.0 ? sqrt(a) : 0.0;
+}
+
+/* eq. e3-44; e -> 0 gives critical damping */
+double ora_zeta(double e) {
+  if (e <= 0.0) return 1.0;
+  double l = log(e);
+  return -l / sqrt(PI * PI + l * l);
+}
+
+/* ------------------------------------------------------------ parcel / cell helpers */
+static int cell_of(const ora_sys *s, int i) {
+  const ora_bed *b = &s->beds[s->bed[i]];
+  int c[3];
+  for (int a = 0; a < 3; a++) {
+    double f = floor((s->pos[3 * i + a] - b->origin[a]) / b->h);
+    if (f < 0) f = 0;
+    if (f > b->n[a] - 1) f = b->n[a] - 1;
+    c[a] = (int)f;
+  }
+  return b->cell_off + c[0] + b->n[0] * (c[1] + b->n[1] * c[2]);
+}
+static double radius(const ora_sys *s, int i) { return 0.5 * s->d[i]; }
+static double volume(const ora_sys *s, int i) { return PI / 6.0 * s->d[i] * s->d[i] * s->d[i]; }
+static double inertia(const ora_sys *s, int i) {
+  double r = radius(s, i);
+  return 0.4 * s->mass[i] * r * r; /* eq. e3-7 */
+}
+/* eq. e3-4 with eq. e3-52: parcel mass = k^3 x real-particle mass */
+static double parcel_mass(const ora_sys *s, int i) {
+  const double *n = &s->sp[4 * i];
+  double mp = (n[0] * MS[0] + n[1] * MS[1] + n[2] * MS[2] + n[3] * MS[3]) * 1e-3;
+  double k = s->k[i];
+  return k * k * k * mp;
+}
+
+/* ------------------------------------------------------------ construction */
+static void deposit(ora_sys *s, const ora_gas *g, double *np_, double *sumK, double *sumKu,
+                    double *sumKv, double *sumKw, double *sumKs);
+
+ora_sys *ora_new(const ora_params *P, const ora_bed *beds, const ora_ore *ores, int n,
+                 const double *x, const double *y, const double *z, const double *vx,
+                 const double *vy, const double *vz, const double *wx, const double *wy,
+                 const double *wz, const double *d, const double *k, const int *ore,
+                 const int *bed, const double *nh, const double *nm, const double *nw,
+                 const double *nfe) {
+  ora_sys *s = (ora_sys *)calloc(1, sizeof *s);
+  s->P = *P;
+  s->beds = (ora_bed *)malloc(sizeof(ora_bed) * P->n_beds);
+  memcpy(s->beds, beds, sizeof(ora_bed) * P->n_beds);
+  s->ores = (ora_ore *)malloc(sizeof(ora_ore) * P->n_ores);
+  memcpy(s->ores, ores, sizeof(ora_ore) * P->n_ores);
+  s->n = n;
+  int nc = 0;
+  for (int b = 0; b < P->n_beds; b++) {
+    int e = beds[b].cell_off + beds[b].n[0] * beds[b].n[1] * beds[b].n[2];
+    if (e > nc) nc = e;
+  }
+  s->n_cells = nc;
+  s->pos = (double *)malloc(sizeof(double) * 3 * n);
+  s->vel = (double *)malloc(sizeof(double) * 3 * n);
+  s->omg = (double *)malloc(sizeof(double) * 3 * n);
+  s->d = (double *)malloc(sizeof(double) * n);
+  s->k = (double *)malloc(sizeof(double) * n);
+  s->mass = (double *)malloc(sizeof(double) * n);
+  s->sp = (double *)malloc(sizeof(double) * 4 * n);
+  s->ore = (int *)malloc(sizeof(int) * n);
+  s->bed = (int *)malloc(sizeof(int) * n);
+  s->hcnt = (int *)calloc(n, sizeof(int));
+  s->hist = (hist_t *)malloc(sizeof(hist_t) * (size_t)HCAP * n);
+  s->wxi = (double *)calloc((size_t)18 * n, sizeof(double));
+  s->won = (unsigned char *)calloc((size_t)6 * n, 1);
+  s->eps = (double *)malloc(sizeof(double) * (nc > 0 ? nc : 1));
+  for (int i = 0; i < n; i++) {
+    s->pos[3 * i] = x[i];
+    s->pos[3 * i + 1] = y[i];
+    s->pos[3 * i + 2] = z[i];
+    s->vel[3 * i] = vx[i];
+    s->vel[3 * i + 1] = vy[i];
+    s->vel[3 * i + 2] = vz[i];
+    s->omg[3 * i] = wx[i];
+    s->omg[3 * i + 1] = wy[i];
+    s->omg[3 * i + 2] = wz[i];
+    s->d[i] = d[i];
+    s->k[i] = k[i];
+    s->ore[i] = ore[i];
+    s->bed[i] = bed[i];
+    s->sp[4 * i] = nh[i];
+    s->sp[4 * i + 1] = nm[i];
+    s->sp[4 * i + 2] = nw[i];
+    s->sp[4 * i + 3] = nfe[i];
+    s->mass[i] = parcel_mass(s, i);
+  }
+  deposit(s, NULL, NULL, NULL, NULL, NULL, NULL, NULL); /* voidage at t = 0 */
+  return s;
+}
+
+void ora_free(ora_sys *s) {
+  if (!s) return;
+  free(s->beds); free(s->ores); free(s->pos); free(s->vel); free(s->omg); free(s->d);
+  free(s->k); free(s->mass); free(s->sp); free(s->ore); free(s->bed); free(s->hcnt);
+  free(s->hist); free(s->wxi); free(s->won); free(s->eps); free(s);
+}
+
+int ora_n_cells(const ora_sys *s) { return s->n_cells; }
+
+/* ------------------------------------------------------------ contact detection */
+static int in_contact(const ora_sys *s, int a, int b) {
+  double dx = s->pos[3 * b] - s->pos[3 * a];
+  double dy = s->pos[3 * b + 1] - s->pos[3 * a + 1];
+  double dz = s->pos[3 * b + 2] - s->pos[3 * a + 2];
+  double sr = radius(s, a) + radius(s, b);
+  return ((dx * dx + dy * dy) + dz * dz) < sr * sr;
+}
+
+static int cmp_pair(const void *p, const void *q) {
+  const int *a = (const int *)p, *b = (const int *)q;
+  if (a[0] != b[0]) return a[0] < b[0] ? -1 : 1;
+  if (a[1] != b[1]) return a[1] < b[1] ? -1 : 1;
+  return 0;
+}
+
+/* All contacting pairs a < b (same bed), sorted.  *out is malloc'ed. */
+static long find_pairs(ora_sys *s, int brute, int **out) {
+  long cap = 1024, cnt = 0;
+  int *pr = (int *)malloc(sizeof(int) * 2 * cap);
+  if (brute) {
+    for (int a = 0; a < s->n; a++)
+      for (int b = a + 1; b < s->n; b++)
+        if (s->bed[a] == s->bed[b] && in_contact(s, a, b)) {
+          if (cnt == cap) { cap *= 2; pr = (int *)realloc(pr, sizeof(int) * 2 * cap); }
+          pr[2 * cnt] = a; pr[2 * cnt + 1] = b; cnt++;
+        }
+  } else {
+    for (int bd = 0; bd < s->P.n_beds; bd++) {
+      const ora_bed *B = &s->beds[bd];
+      double hc = 0.0;
+      for (int i = 0; i < s->n; i++) if (s->bed[i] == bd && s->d[i] > hc) hc = s->d[i];
+      if (hc <= 0.0) continue;
+      int nc[3];
+      for (int a = 0; a < 3; a++) { nc[a] = (int)floor((B->hi[a] - B->lo[a]) / hc); if (nc[a] < 1) nc[a] = 1; }
+      double cs[3];
+      for (int a = 0; a < 3; a++) cs[a] = (B->hi[a] - B->lo[a]) / nc[a];
+      long ncell = (long)nc[0] * nc[1] * nc[2];
+      int *head = (int *)malloc(sizeof(int) * ncell);
+      int *next = (int *)malloc(sizeof(int) * s->n);
+      int *cid = (int *)malloc(sizeof(int) * 3 * s->n);
+      for (long c = 0; c < ncell; c++) head[c] = -1;
+      for (int i = s->n - 1; i >= 0; i--) {
+        if (s->bed[i] != bd) continue;
+        for (int a = 0; a < 3; a++) {
+          double f = floor((s->pos[3 * i + a] - B->lo[a]) / cs[a]);
+          if (f < 0) f = 0;
+          if (f > nc[a] - 1) f = nc[a] - 1;
+          cid[3 * i + a] = (int)f;
+        }
+        long c = cid[3 * i] + (long)nc[0] * (cid[3 * i + 1] + (long)nc[1] * cid[3 * i + 2]);
+        next[i] = head[c];
+        head[c] = i;
+      }
+      for (int a = 0; a < s->n; a++) {
+        if (s->bed[a] != bd) continue;
+        for (int oz = -1; oz <= 1; oz++)
+          for (int oy = -1; oy <= 1; oy++)
+            for (int ox = -1; ox <= 1; ox++) {
+              int cx = cid[3 * a] + ox, cy = cid[3 * a + 1] + oy, cz = cid[3 * a + 2] + oz;
+              if (cx < 0 || cy < 0 || cz < 0 || cx >= nc[0] || cy >= nc[1] || cz >= nc[2]) continue;
+              for (int b = head[cx + (long)nc[0] * (cy + (long)nc[1] * cz)]; b >= 0; b = next[b]) {
+                if (b <= a || !in_contact(s, a, b)) continue;
+                if (cnt == cap) { cap *= 2; pr = (int *)realloc(pr, sizeof(int) * 2 * cap); }
+                pr[2 * cnt] = a; pr[2 * cnt + 1] = b; cnt++;
+              }
+            }
+      }
+      free(head); free(next); free(cid);
+    }
+  }
+  qsort(pr, cnt, 2 * sizeof(int), cmp_pair);
+  *out = pr;
+  return cnt;
+}
+
+long ora_pairs(ora_sys *s, int brute, int *ij, long cap) {
+  int *pr;
+  long cnt = find_pairs(s, brute, &pr);
+  for (long q = 0; q < cnt && q < cap; q++) { ij[2 * q] = pr[2 * q]; ij[2 * q + 1] = pr[2 * q + 1]; }
+  free(pr);
+  return cnt;
+}
+
+/* ------------------------------------------------------------ contact law
+ * reading (the paper defers the contact model to another work): linear
+ * spring-dashpot in the normal direction with damping ratio zeta from the
+ * coarse-grained restitution (eqs. e3-44, e3-45), no tensile clamp; Cundall
+ * tangential spring k_t with Coulomb cap mu_s |F_n|; the spring is projected
+ * onto the current tangent plane before the increment v_t dt.  F (on the
+ * first body), the tangential part Ft, the new history and |F_n| are returned. */
+static void contact_law(const ora_params *P, double mstar, double zeta, double delta,
+                        const double n[3], const double vrel[3], const double xi_in[3],
+                        double F[3], double Ft[3], double xi_out[3], double *fn_abs) {
+  double gn = 2.0 * zeta * sqrt(mstar * P->kn);
+  double vn = dot3(vrel, n);
+  double fn = -(P->kn * delta + gn * vn);
+  double vt[3], xi[3];
+  for (int a = 0; a < 3; a++) vt[a] = vrel[a] - vn * n[a];
+  double xn = dot3(xi_in, n);
+  for (int a = 0; a < 3; a++) xi[a] = (xi_in[a] - xn * n[a]) + vt[a] * P->dt;
+  double kt = P->kt_over_kn * P->kn, gt = P->gt_over_gn * gn;
+  for (int a = 0; a < 3; a++) Ft[a] = -kt * xi[a] - gt * vt[a];
+  double ftm = norm3(Ft), cap = P->mu_s * fabs(fn);
+  if (ftm > cap) {
+    for (int a = 0; a < 3; a++) {
+      Ft[a] = cap * Ft[a] / ftm;
+      xi[a] = -(Ft[a] + gt * vt[a]) / kt;
+    }
+  }
+  for (int a = 0; a < 3; a++) {
+    F[a] = fn * n[a] + Ft[a];
+    xi_out[a] = xi[a];
+  }
+  *fn_abs = fabs(fn);
+}
+
+static void rolling(const ora_sys *s, int i, double fn_abs, double T[3]) {
+  if (s->P.mu_r <= 0.0) return;
+  double w = norm3(&s->omg[3 * i]);
+  if (w <= 0.0) return;
+  for (int a = 0; a < 3; a++) T[a] -= s->P.mu_r * fn_abs * s->omg[3 * i + a] / w;
+}
+
+static int n_walls(const ora_bed *b) { return b->wall_kind == 0 ? 6 : 3; }
+
+/* signed distance from the wall surface into the domain and the unit vector
+ * from the parcel centre towards the wall */
+static double wall_geom(const ora_bed *b, int w, const double x[3], double nvec[3]) {
+  nvec[0] = nvec[1] = nvec[2] = 0.0;
+  if (b->wall_kind == 0) {
+    int ax = w / 2;
+    if (w % 2 == 0) { nvec[ax] = -1.0; return x[ax] - b->lo[ax]; }
+    nvec[ax] = 1.0;
+    return b->hi[ax] - x[ax];
+  }
+  if (w == 0) {
+    double cx = 0.5 * (b->lo[0] + b->hi[0]), cy = 0.5 * (b->lo[1] + b->hi[1]);
+    double rx = x[0] - cx, ry = x[1] - cy;
+    double rho = sqrt(rx * rx + ry * ry);
+    if (rho <= 0.0) return b->R;
+    nvec[0] = rx / rho;
+    nvec[1] = ry / rho;
+    return b->R - rho;
+  }
+  if (w == 1) { nvec[2] = -1.0; return x[2] - b->lo[2]; }
+  nvec[2] = 1.0;
+  return b->hi[2] - x[2];
+}
+
+/* eq. e3-5 with e3-5-1 plus body forces of eq. e3-3 (gravity, -V grad p) */
+static void gas_force(const ora_sys *s, const ora_gas *g, int i, double F[3]) {
+  double m = s->mass[i];
+  for (int a = 0; a < 3; a++) F[a] += m * s->P.g[a];
+  if (!s->P.drag_on) return;
+  int c = cell_of(s, i);
+  const ora_bed *B = &s->beds[s->bed[i]];
+  double V = volume(s, i);
+  F[0] -= V * g->dpdx[c];
+  F[1] -= V * g->dpdy[c];
+  F[2] -= V * g->dpdz[c];
+  double rho, mu;
+  ora_gas_props(g->T[c], g->p[c], g->xH2[c], g->xH2O[c], g->xN2[c], B->mu_override, &rho, &mu);
+  double sl[3] = {g->ug[c] - s->vel[3 * i], g->vg[c] - s->vel[3 * i + 1], g->wg[c] - s->vel[3 * i + 2]};
+  double dp = s->d[i] / s->k[i]; /* reading: drag uses the real-particle diameter */
+  double be = ora_beta_over_epsp(s->eps[c], rho, mu, norm3(sl), dp, s->P.ergun_printed);
+  for (int a = 0; a < 3; a++) F[a] += be * V * sl[a];
+}
+
+static const double *hist_lookup(const ora_sys *s, int a, int b) {
+  for (int q = 0; q < s->hcnt[a]; q++)
+    if (s->hist[(size_t)a * HCAP + q].partner == b) return s->hist[(size_t)a * HCAP + q].xi;
+  return NULL;
+}
+
+/* Forces and torques of one DEM step from the step-start state; with commit,
+ * the tangential histories are replaced by the new ones. */
+static void compute_forces(ora_sys *s, const ora_gas *g, double *F, double *T, int commit) {
+  int n = s->n;
+  static const double zero3[3] = {0, 0, 0};
+  memset(F, 0, sizeof(double) * 3 * n);
+  memset(T, 0, sizeof(double) * 3 * n);
+  int *pr;
+  long np_ = find_pairs(s, 0, &pr);
+  int *ncnt = (int *)calloc(n, sizeof(int));
+  hist_t *nh = (hist_t *)malloc(sizeof(hist_t) * (size_t)HCAP * n);
+  for (long q = 0; q < np_; q++) {
+    int a = pr[2 * q], b = pr[2 * q + 1];
+    double dx[3], nv[3];
+    for (int c = 0; c < 3; c++) dx[c] = s->pos[3 * b + c] - s->pos[3 * a + c];
+    double dist = sqrt((dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2]);
+    double ra = radius(s, a), rb = radius(s, b);
+    for (int c = 0; c < 3; c++) nv[c] = dx[c] / dist;
+    double delta = (ra + rb) - dist;
+    double ma = s->mass[a], mb = s->mass[b];
+    double mstar = ma * mb / (ma + mb);
+    double kk = s->k[a] > s->k[b] ? s->k[a] : s->k[b];
+    double zeta = ora_zeta(ora_e_cgp(s->P.e_p, kk));
+    double wsum[3], cr[3], vrel[3];
+    for (int c = 0; c < 3; c++) wsum[c] = ra * s->omg[3 * a + c] + rb * s->omg[3 * b + c];
+    cross3(wsum, nv, cr);
+    for (int c = 0; c < 3; c++) vrel[c] = s->vel[3 * a + c] - s->vel[3 * b + c] + cr[c];
+    const double *xo = hist_lookup(s, a, b);
+    double Fa[3], Ft[3], xin[3], fnabs, tq[3];
+    contact_law(&s->P, mstar, zeta, delta, nv, vrel, xo ? xo : zero3, Fa, Ft, xin, &fnabs);
+    cross3(nv, Ft, tq);
+    for (int c = 0; c < 3; c++) {
+      F[3 * a + c] += Fa[c];
+      F[3 * b + c] -= Fa[c];
+      T[3 * a + c] += ra * tq[c];
+      T[3 * b + c] += rb * tq[c];
+    }
+    rolling(s, a, fnabs, &T[3 * a]);
+    rolling(s, b, fnabs, &T[3 * b]);
+    if (ncnt[a] >= HCAP) abort();
+    nh[(size_t)a * HCAP + ncnt[a]].partner = b;
+    memcpy(nh[(size_t)a * HCAP + ncnt[a]].xi, xin, sizeof xin);
+    ncnt[a]++;
+  }
+  free(pr);
+  /* walls: same law with m* = m, infinite radius and zero velocity */
+  for (int i = 0; i < n; i++) {
+    const ora_bed *B = &s->beds[s->bed[i]];
+    double r = radius(s, i);
+    for (int w = 0; w < n_walls(B); w++) {
+      double nv[3];
+      double phi = wall_geom(B, w, &s->pos[3 * i], nv);
+      double delta = r - phi;
+      if (!(delta > 0.0)) {
+        if (commit) s->won[6 * i + w] = 0;
+        continue;
+      }
+      double zeta = ora_zeta(ora_e_cgp(s->P.e_p, s->k[i]));
+      double wr[3], cr[3], vrel[3];
+      for (int c = 0; c < 3; c++) wr[c] = r * s->omg[3 * i + c];
+      cross3(wr, nv, cr);
+      for (int c = 0; c < 3; c++) vrel[c] = s->vel[3 * i + c] + cr[c];
+      const double *xo = s->won[6 * i + w] ? &s->wxi[18 * i + 3 * w] : zero3;
+      double Fa[3], Ft[3], xin[3], fnabs, tq[3];
+      contact_law(&s->P, s->mass[i], zeta, delta, nv, vrel, xo, Fa, Ft, xin, &fnabs);
+      cross3(nv, Ft, tq);
+      for (int c = 0; c < 3; c++) {
+        F[3 * i + c] += Fa[c];
+        T[3 * i + c] += r * tq[c];
+      }
+      rolling(s, i, fnabs, &T[3 * i]);
+      if (commit) {
+        memcpy(&s->wxi[18 * i + 3 * w], xin, sizeof xin);
+        s->won[6 * i + w] = 1;
+      }
+    }
+  }
+  for (int i = 0; i < n; i++) gas_force(s, g, i, &F[3 * i]);
+  if (commit) {
+    free(s->hist);
+    free(s->hcnt);
+    s->hist = nh;
+    s->hcnt = ncnt;
+  } else {
+    free(nh);
+    free(ncnt);
+  }
+}
+
+void ora_forces(ora_sys *s, const ora_gas *g, double *F, double *T) { compute_forces(s, g, F, T, 0); }
+
+/* eq. e3-3 and e3-6 advanced by semi-implicit Euler (reading: the paper does
+ * not name its integrator): v += dt F/m, w += dt T/I, x += dt v_new. */
+void ora_step(ora_sys *s, int nsteps, const ora_gas *g) {
+  int n = s->n;
+  double *F = (double *)malloc(sizeof(double) * 3 * n);
+  double *T = (double *)malloc(sizeof(double) * 3 * n);
+  for (int st = 0; st < nsteps; st++) {
+    compute_forces(s, g, F, T, 1);
+    double dt = s->P.dt;
+    for (int i = 0; i < n; i++) {
+      double m = s->mass[i], I = inertia(s, i);
+      for (int c = 0; c < 3; c++) {
+        s->vel[3 * i + c] += dt * F[3 * i + c] / m;
+        s->omg[3 * i + c] += dt * T[3 * i + c] / I;
+        s->pos[3 * i + c] += dt * s->vel[3 * i + c];
+      }
+    }
+  }
+  free(F);
+  free(T);
+}
+
+/* ------------------------------------------------------------ deposition
+ * eq. e3-25 / e3-27a summed over the parcels whose centre lies in the cell
+ * (reading: nearest-grid-point both ways, V_cell = h^3, eps_g clamped below
+ * by eps_min).  K_p = beta V_p / (1 - eps_g) uses the newly deposited eps_g. */
+static void deposit(ora_sys *s, const ora_gas *g, double *np_, double *sumK, double *sumKu,
+                    double *sumKv, double *sumKw, double *sumKs) {
+  int nc = s->n_cells;
+  double *sv = (double *)calloc(nc > 0 ? nc : 1, sizeof(double));
+  double *cnt = (double *)calloc(nc > 0 ? nc : 1, sizeof(double));
+  for (int i = 0; i < s->n; i++) {
+    int c = cell_of(s, i);
+    sv[c] += volume(s, i);
+    cnt[c] += 1.0;
+  }
+  for (int b = 0; b < s->P.n_beds; b++) {
+    const ora_bed *B = &s->beds[b];
+    int ncb = B->n[0] * B->n[1] * B->n[2];
+    double vc = B->h * B->h * B->h;
+    for (int q = 0; q < ncb; q++) {
+      int c = B->cell_off + q;
+      double e = 1.0 - sv[c] / vc;
+      if (e < s->P.eps_min) e = s->P.eps_min;
+      if (e > 1.0) e = 1.0;
+      s->eps[c] = e;
+    }
+  }
+  if (np_) memcpy(np_, cnt, sizeof(double) * nc);
+  if (g && (sumK || sumKu || sumKv || sumKw || sumKs)) {
+    double *a[5] = {sumK, sumKu, sumKv, sumKw, sumKs};
+    for (int j = 0; j < 5; j++) if (a[j]) memset(a[j], 0, sizeof(double) * nc);
+    for (int i = 0; i < s->n; i++) {
+      int c = cell_of(s, i);
+      const ora_bed *B = &s->beds[s->bed[i]];
+      double rho, mu;
+      ora_gas_props(g->T[c], g->p[c], g->xH2[c], g->xH2O[c], g->xN2[c], B->mu_override, &rho, &mu);
+      double sl[3] = {g->ug[c] - s->vel[3 * i], g->vg[c] - s->vel[3 * i + 1], g->wg[c] - s->vel[3 * i + 2]};
+      double slip = norm3(sl);
+      double K = ora_beta_over_epsp(s->eps[c], rho, mu, slip, s->d[i] / s->k[i], s->P.ergun_printed) * volume(s, i);
+      if (sumK) sumK[c] += K;
+      if (sumKu) sumKu[c] += K * s->vel[3 * i];
+      if (sumKv) sumKv[c] += K * s->vel[3 * i + 1];
+      if (sumKw) sumKw[c] += K * s->vel[3 * i + 2];
+      if (sumKs) sumKs[c] += K * slip;
+    }
+  }
+  free(sv);
+  free(cnt);
+}
+
+void ora_couple(ora_sys *s, const ora_gas *g, double *eps, double *np_, double *sumK,
+                double *sumKu, double *sumKv, double *sumKw, double *sumKs) {
+  deposit(s, g, np_, sumK, sumKu, sumKv, sumKw, sumKs);
+  if (eps) memcpy(eps, s->eps, sizeof(double) * s->n_cells);
+}
+
+/* ------------------------------------------------------------ reaction (USCM) */
+
+/* Kirchhoff solution of the resistance network of Fig. 2 / Fig. 4 for any set
+ * of active interfaces, as a ladder from the innermost active interface
+ * outwards (each stage a Thevenin pair (Phi, R)), then back-substitution
+ * inwards.  It reproduces the paper's closed forms e2-2..e2-10 (with the
+ * determinant corrected), eb1..eb3 and ea1..ea2.  A[i], B[] and x_eq[i] of
+ * layers inside the innermost active interface are never used. */
+static void ladder_dual(const int act[3], const dual A[3], const dual B[3], double F, double x,
+                        const double xeq[3], dual r[3], dual *Q, dual *S) {
+  int i0 = -1;
+  for (int i = 0; i < 3; i++) { r[i] = D(0.0); if (act[i] && i0 < 0) i0 = i; }
+  if (i0 < 0) { *Q = D(0.0); *S = D(0.0); return; }
+  dual R = A[i0], Phi = D(xeq[i0]);
+  for (int i = i0 + 1; i < 3; i++) {
+    R = dadd(R, B[i - 1]);
+    if (act[i]) {
+      dual g1 = dinv(R), g2 = dinv(A[i]);
+      Phi = ddiv(dadd(dmul(Phi, g1), dscale(g2, xeq[i])), dadd(g1, g2));
+      R = dinv(dadd(g1, g2));
+    }
+  }
+  dual Rt = dadd(dadd(R, B[2]), D(F));
+  dual N = ddiv(dsub(D(x), Phi), Rt);
+  *Q = dinv(Rt);
+  *S = ddiv(Phi, Rt);
+  dual phi = dsub(D(x), dmul(N, dadd(D(F), B[2])));
+  dual flow = N;
+  for (int i = 2; i >= i0; i--) {
+    if (act[i]) {
+      r[i] = ddiv(dsub(phi, D(xeq[i])), A[i]);
+      flow = dsub(flow, r[i]);
+    }
+    if (i > i0) phi = dsub(phi, dmul(flow, B[i - 1]));
+  }
+}
+
+void ora_ladder(const int active[3], const double A[3], const double B[3], double F, double x,
+                const double xeq[3], double r[3], double *Q, double *S) {
+  dual Ad[3], Bd[3], rd[3], q, sv;
+  for (int i = 0; i < 3; i++) { Ad[i] = D(A[i]); Bd[i] = D(B[i]); }
+  ladder_dual(active, Ad, Bd, F, x, xeq, rd, &q, &sv);
+  for (int i = 0; i < 3; i++) r[i] = rd[i].v;
+  *Q = q.v;
+  *S = sv.v;
+}
+
+/* Per-parcel environment of one reaction update.  kr carries the kinetic
+ * parameters' tangents. */
+typedef struct {
+  double x, xeq[3], kappa[3], c_mol, Ap, rp, Deff[3], F, dt;
+  dual kr[3];
+} renv;
+
+/* One explicit reaction update of a parcel (eqs. e2-1..e2-19, e2-25, e3-1,
+ * e3-2): shell geometry from the remaining fractions u = 1 - f (eqs.
+ * e2-15..e2-17), interface resistances (eq. e2-12), layer diffusion
+ * resistances (eq. e2-14; reading: layer m spans the h and m interfaces, layer
+ * w the m and w interfaces, layer Fe the w interface and the surface), the
+ * network solve, then H2 extents xi_i = A_p c r_i dt (moles per real particle;
+ * reading: negative rates clamp to zero, the reactions being irreversible,
+ * assumption (i), and each extent is capped by its reactant at the step start)
+ * and the stoichiometry of Table 1.  Returns the number of clamped rates. */
+static int react_core(const renv *e, dual sp[4], dual *Q, dual *S, dual xi[3]) {
+  dual N = dadd(dadd(dscale(sp[0], 2.0), dscale(sp[1], 3.0)), dadd(sp[2], sp[3]));
+  dual u[3];
+  u[0] = ddiv(dscale(sp[0], 2.0), N);
+  u[1] = ddiv(dadd(dscale(sp[0], 2.0), dscale(sp[1], 3.0)), N);
+  u[2] = ddiv(dadd(dadd(dscale(sp[0], 2.0), dscale(sp[1], 3.0)), sp[2]), N);
+  int act[3];
+  for (int i = 0; i < 3; i++) act[i] = (sp[i].v > 1e-12 * N.v) && (e->x > e->xeq[i]);
+  int i0 = -1;
+  for (int i = 0; i < 3; i++) if (act[i] && i0 < 0) i0 = i;
+  dual A[3], B[3], r[3];
+  for (int i = 0; i < 3; i++) { A[i] = D(1.0); B[i] = D(0.0); }
+  int clamps = 0;
+  if (i0 < 0) {
+    *Q = D(0.0);
+    *S = D(0.0);
+    for (int i = 0; i < 3; i++) xi[i] = D(0.0);
+    return 0;
+  }
+  for (int i = i0; i < 3; i++)
+    if (act[i]) A[i] = ddiv(dscale(dpowc(u[i], -2.0 / 3.0), e->kappa[i]), e->kr[i]);
+  /* layers outside i0: m (between interfaces 0 and 1), w (1..2), Fe (2..surface) */
+  if (i0 <= 0) B[0] = dscale(dsub(dpowc(u[0], -1.0 / 3.0), dpowc(u[1], -1.0 / 3.0)), e->rp / e->Deff[0]);
+  if (i0 <= 1) B[1] = dscale(dsub(dpowc(u[1], -1.0 / 3.0), dpowc(u[2], -1.0 / 3.0)), e->rp / e->Deff[1]);
+  B[2] = dscale(dsub(dpowc(u[2], -1.0 / 3.0), D(1.0)), e->rp / e->Deff[2]);
+  ladder_dual(act, A, B, e->F, e->x, e->xeq, r, Q, S);
+  double cad = e->Ap * e->c_mol * e->dt;
+  static const double nu[3] = {3.0, 1.0, 1.0};
+  for (int i = 0; i < 3; i++) {
+    if (r[i].v < 0.0) { r[i] = D(0.0); clamps++; }
+    xi[i] = dscale(r[i], cad);
+    dual lim = dscale(sp[i], 1.0 / nu[i]);
+    if (xi[i].v > lim.v) xi[i] = lim;
+  }
+  dual n0 = dsub(sp[0], dscale(xi[0], 3.0));
+  dual n1 = dsub(dadd(sp[1], dscale(xi[0], 2.0)), xi[1]);
+  dual n2 = dsub(dadd(sp[2], dscale(xi[1], 3.0)), xi[2]);
+  dual n3 = dadd(sp[3], xi[2]);
+  sp[0] = n0; sp[1] = n1; sp[2] = n2; sp[3] = n3;
+  return clamps;
+}
+
+int ora_react_point(const double env[18], double sp[4]) {
+  renv e;
+  e.x = env[0];
+  for (int i = 0; i < 3; i++) { e.xeq[i] = env[1 + i]; e.kappa[i] = env[4 + i]; e.kr[i] = D(env[7 + i]); }
+  e.c_mol = env[10];
+  e.Ap = env[11];
+  e.rp = env[12];
+  for (int i = 0; i < 3; i++) e.Deff[i] = env[13 + i];
+  e.F = env[16];
+  e.dt = env[17];
+  dual d[4], Q, S, xi[3];
+  for (int q = 0; q < 4; q++) d[q] = D(sp[q]);
+  int c = react_core(&e, d, &Q, &S, xi);
+  for (int q = 0; q < 4; q++) sp[q] = d[q].v;
+  return c;
+}
+
+/* eqs. e2-18 / e2-19 from the remaining fractions */
+static dual fov_of(const dual sp[4], int kind) {
+  dual N = dadd(dadd(dscale(sp[0], 2.0), dscale(sp[1], 3.0)), dadd(sp[2], sp[3]));
+  dual fh = dsub(D(1.0), ddiv(dscale(sp[0], 2.0), N));
+  dual fm = dsub(D(1.0), ddiv(dadd(dscale(sp[0], 2.0), dscale(sp[1], 3.0)), N));
+  dual fw = dsub(D(1.0), ddiv(dadd(dadd(dscale(sp[0], 2.0), dscale(sp[1], 3.0)), sp[2]), N));
+  if (kind == 1) return dadd(dscale(fm, 0.25), dscale(fw, 0.75));
+  return dadd(dadd(dscale(fh, 1.0 / 9.0), dscale(fm, 2.0 / 9.0)), dscale(fw, 6.0 / 9.0));
+}
+
+/* Environment of parcel i from its cell (NGP) and its slip. */
+static void make_env(const ora_sys *s, const ora_gas *g, int i, double dt, const double *theta,
+                     int tangents, renv *e) {
+  int c = cell_of(s, i);
+  const ora_bed *B = &s->beds[s->bed[i]];
+  const ora_ore *o = &s->ores[s->ore[i]];
+  double T = g->T[c], p = g->p[c], xh2 = g->xH2[c], xh2o = g->xH2O[c], xn2 = g->xN2[c];
+  /* Section 2.1: H2 fraction of the N2-free gas */
+  if (xh2o <= 0.0) e->x = xh2 > 0.0 ? 1.0 : 0.0;
+  else e->x = xh2 / (xh2 + xh2o);
+  for (int q = 0; q < 3; q++) {
+    double K = ora_keq(q, T);
+    e->xeq[q] = 1.0 / (K + 1.0);   /* eq. e2-1-3 */
+    e->kappa[q] = K / (1.0 + K);   /* eq. e2-12 factor */
+    const double *th = theta ? theta : B->theta;
+    double kr = exp(th[2 * q] - th[2 * q + 1] / (RG * T)); /* eq. e2-13 */
+    e->kr[q] = D(kr);
+    if (tangents) {
+      e->kr[q].d[2 * q] = kr;
+      e->kr[q].d[2 * q + 1] = -kr / (RG * T);
+    }
+  }
+  e->c_mol = p / (RG * T);
+  double dp = s->d[i] / s->k[i];
+  e->Ap = PI * dp * dp;
+  e->rp = 0.5 * dp;
+  double xi[4];
+  ora_layer_porosity(o, xi);
+  double Dp = ora_pore_diff(T, p, xh2, xh2o, xn2, o->d_pore_cm);
+  for (int q = 0; q < 3; q++) e->Deff[q] = Dp * xi[q + 1] / o->tau; /* eq. e2-30 */
+  double sl[3] = {g->ug[c] - s->vel[3 * i], g->vg[c] - s->vel[3 * i + 1], g->wg[c] - s->vel[3 * i + 2]};
+  e->F = ora_film(T, p, xh2, xh2o, xn2, B->mu_override, s->eps[c], norm3(sl), dp);
+  e->dt = dt;
+}
+
+long ora_react(ora_sys *s, double dt, const ora_gas *g, int update_mass, double *mdotH2,
+               double *mdotH2O, double *sumEQ, double *sumES, double *fov, double *bed_fov) {
+  int nc = s->n_cells;
+  double *outs[4] = {mdotH2, mdotH2O, sumEQ, sumES};
+  for (int j = 0; j < 4; j++) if (outs[j]) memset(outs[j], 0, sizeof(double) * nc);
+  double *bw = (double *)calloc(s->P.n_beds, sizeof(double));
+  double *bf = (double *)calloc(s->P.n_beds, sizeof(double));
+  long clamps = 0;
+  for (int i = 0; i < s->n; i++) {
+    renv e;
+    make_env(s, g, i, dt, NULL, 0, &e);
+    int c = cell_of(s, i);
+    dual sp[4], Q, S, xi[3];
+    for (int q = 0; q < 4; q++) sp[q] = D(s->sp[4 * i + q]);
+    clamps += react_core(&e, sp, &Q, &S, xi);
+    for (int q = 0; q < 4; q++) s->sp[4 * i + q] = sp[q].v;
+    double k3 = s->k[i] * s->k[i] * s->k[i];
+    double xs = xi[0].v + xi[1].v + xi[2].v;
+    /* eqs. e2-1, e2-25, e3-25, e3-52: kg/s per parcel, summed per cell */
+    if (mdotH2) mdotH2[c] += -k3 * MG[0] * 1e-3 * xs / dt;
+    if (mdotH2O) mdotH2O[c] += k3 * MG[1] * 1e-3 * xs / dt;
+    /* eqs. e4-7..e4-11 with E = eta A_p / T, eta_H2 = -1 */
+    double E = -e.Ap / g->T[c];
+    if (sumEQ) sumEQ[c] += k3 * E * Q.v;
+    if (sumES) sumES[c] += k3 * E * S.v;
+    double f = fov_of(sp, s->ores[s->ore[i]].kind).v;
+    if (fov) fov[i] = f;
+    double w = k3 * (2.0 * sp[0].v + 3.0 * sp[1].v + sp[2].v + sp[3].v);
+    bw[s->bed[i]] += w;
+    bf[s->bed[i]] += w * f;
+    if (update_mass) s->mass[i] = parcel_mass(s, i);
+  }
+  if (bed_fov)
+    for (int b = 0; b < s->P.n_beds; b++) bed_fov[b] = bw[b] > 0 ? bf[b] / bw[b] : 0.0;
+  free(bw);
+  free(bf);
+  return clamps;
+}
+
+void ora_grad(ora_sys *s, const ora_gas *g, int n_sub, double dt_react, int dyn_every,
+              const double theta[6], double *J, double grad[6]) {
+  int n = s->n;
+  dual *sp = (dual *)malloc(sizeof(dual) * 4 * n);
+  for (int i = 0; i < 4 * n; i++) sp[i] = D(s->sp[i]);
+  for (int st = 0; st < n_sub; st++) {
+    if (st % dyn_every == 0) {
+      ora_step(s, 1, g);
+      deposit(s, NULL, NULL, NULL, NULL, NULL, NULL, NULL);
+    }
+    for (int i = 0; i < n; i++) {
+      renv e;
+      make_env(s, g, i, dt_react, theta, 1, &e);
+      dual Q, S, xi[3];
+      react_core(&e, &sp[4 * i], &Q, &S, xi);
+    }
+  }
+  dual num = D(0.0);
+  double den = 0.0;
+  for (int i = 0; i < n; i++) {
+    double k3 = s->k[i] * s->k[i] * s->k[i];
+    double w = k3 * (2.0 * sp[4 * i].v + 3.0 * sp[4 * i + 1].v + sp[4 * i + 2].v + sp[4 * i + 3].v);
+    num = dadd(num, dscale(fov_of(&sp[4 * i], s->ores[s->ore[i]].kind), w));
+    den += w;
+  }
+  *J = num.v / den;
+  for (int q = 0; q < 6; q++) grad[q] = num.d[q] / den;
+  for (int i = 0; i < 4 * n; i++) s->sp[i] = sp[i].v;
+  free(sp);
+}
+
+void ora_get(const ora_sys *s, double *x, double *y, double *z, double *vx, double *vy,
+             double *vz, double *wx, double *wy, double *wz, double *nh, double *nm,
+             double *nw, double *nfe, double *mass, double *eps) {
+  for (int i = 0; i < s->n; i++) {
+    if (x) x[i] = s->pos[3 * i];
+    if (y) y[i] = s->pos[3 * i + 1];
+    if (z) z[i] = s->pos[3 * i + 2];
+    if (vx) vx[i] = s->vel[3 * i];
+    if (vy) vy[i] = s->vel[3 * i + 1];
+    if (vz) vz[i] = s->vel[3 * i + 2];
+    if (wx) wx[i] = s->omg[3 * i];
+    if (wy) wy[i] = s->omg[3 * i + 1];
+    if (wz) wz[i] = s->omg[3 * i + 2];
+    if (nh) nh[i] = s->sp[4 * i];
+    if (nm) nm[i] = s->sp[4 * i + 1];
+    if (nw) nw[i] = s->sp[4 * i + 2];
+    if (nfe) nfe[i] = s->sp[4 * i + 3];
+    if (mass) mass[i] = s->mass[i];
+  }
+  if (eps) memcpy(eps, s->eps, sizeof(double) * s->n_cells);
+}

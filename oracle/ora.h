@@ -1,0 +1,114 @@
+/*
+ * Oracle: a plain, slow, FP64 CPU implementation of the particle side of the
+ * coarse-grained CFD-DEM reduction model (arxiv 2311.03908).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link or
+ * call this code; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, constant or table
+ * with the GPU library.
+ *
+ * Every quantity is SI and double precision.  Parcels are kept in original id
+ * order; every loop visits parcels, pairs and cells in ascending id order.
+ */
+#ifndef ORA_H
+#define ORA_H
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int wall_kind;          /* 0 = box (six planes), 1 = cylinder (side, floor, lid) */
+  double lo[3], hi[3];    /* box; for a cylinder: floor lo[2], lid hi[2], axis at xy centre */
+  double R;               /* cylinder radius */
+  double origin[3];       /* gas grid origin */
+  double h;               /* gas cell edge */
+  int n[3];               /* gas cells per axis */
+  int cell_off;           /* first cell of this bed in the concatenated gas arrays */
+  double theta[6];        /* ln k0_i, Ea_i (J/mol) for R1..R3 */
+  double mu_override;     /* > 0: gas viscosity fixed */
+} ora_bed;
+
+typedef struct {
+  double xi0;             /* initial porosity */
+  double d_pore_cm;       /* pore diameter d_a in cm */
+  double tau;             /* tortuosity */
+  double rho_true[4];     /* true densities of Fe2O3, Fe3O4, FeO, Fe */
+  int kind;               /* 0 hematite ore (eq. e2-18), 1 magnetite ore (eq. e2-19) */
+} ora_ore;
+
+typedef struct {
+  double kn, e_p, mu_s, mu_r, kt_over_kn, gt_over_gn, eps_min, dt;
+  double g[3];
+  int ergun_printed;      /* 1: inertial Ergun term with eps_g as printed */
+  int drag_on;            /* 0: no gas-side forces (test switch) */
+  int n_beds, n_ores;
+} ora_params;
+
+typedef struct {
+  const double *ug, *vg, *wg, *p, *dpdx, *dpdy, *dpdz, *T, *xH2, *xH2O, *xN2;
+} ora_gas;
+
+typedef struct ora_sys ora_sys;
+
+ora_sys *ora_new(const ora_params *P, const ora_bed *beds, const ora_ore *ores, int n,
+                 const double *x, const double *y, const double *z,
+                 const double *vx, const double *vy, const double *vz,
+                 const double *wx, const double *wy, const double *wz,
+                 const double *d, const double *k, const int *ore, const int *bed,
+                 const double *nh, const double *nm, const double *nw, const double *nfe);
+void ora_free(ora_sys *s);
+int ora_n_cells(const ora_sys *s);
+
+/* canonical contact pairs (a < b by id) at the current positions, sorted;
+ * brute = 1 uses the O(N^2) scan instead of the cell list.  Returns the count
+ * (may exceed cap; only cap pairs are written). */
+long ora_pairs(ora_sys *s, int brute, int *ij, long cap);
+/* total force and torque the next step would apply (state is not changed) */
+void ora_forces(ora_sys *s, const ora_gas *g, double *F, double *T);
+void ora_step(ora_sys *s, int nsteps, const ora_gas *g);
+/* voidage + drag deposition; outputs may be NULL */
+void ora_couple(ora_sys *s, const ora_gas *g, double *eps, double *np_, double *sumK,
+                double *sumKu, double *sumKv, double *sumKw, double *sumKs);
+/* USCM update over dt; per-cell sources and per-parcel / per-bed f_ov (may be NULL);
+ * update_mass = 0 keeps the DEM mass frozen.  Returns the number of clamped rates. */
+long ora_react(ora_sys *s, double dt, const ora_gas *g, int update_mass, double *mdotH2,
+               double *mdotH2O, double *sumEQ, double *sumES, double *fov, double *bed_fov);
+void ora_get(const ora_sys *s, double *x, double *y, double *z, double *vx, double *vy,
+             double *vz, double *wx, double *wy, double *wz, double *nh, double *nm,
+             double *nw, double *nfe, double *mass, double *eps);
+/* kinetic gradient by forward-mode dual numbers: n_sub reaction substeps of
+ * dt_react with one DEM step (and a voidage deposit) before every dyn_every-th;
+ * the DEM mass stays frozen.  Writes J (bed-mean f_ov of bed 0 weighted by
+ * k^3 N_Fe over all parcels) and dJ/dtheta (6).  theta replaces every bed's
+ * kinetic parameters. The system state is advanced. */
+void ora_grad(ora_sys *s, const ora_gas *g, int n_sub, double dt_react, int dyn_every,
+              const double theta[6], double *J, double grad[6]);
+
+/* ---- point functions, exported for the pins ---- */
+double ora_e_cgp(double e_p, double k);
+double ora_zeta(double e);
+void ora_gas_props(double T, double p, double xh2, double xh2o, double xn2, double mu_override,
+                   double *rho, double *mu);
+double ora_fuller(double T, double p, int i, int j);   /* 0 H2, 1 H2O, 2 N2 */
+double ora_wilke_h2(double T, double p, double xh2, double xh2o, double xn2);
+double ora_knudsen_h2(double T, double d_pore_cm);
+double ora_pore_diff(double T, double p, double xh2, double xh2o, double xn2, double d_pore_cm);
+void ora_layer_porosity(const ora_ore *o, double xi[4]);
+double ora_sherwood(double eps, double Re, double Sc);
+double ora_film(double T, double p, double xh2, double xh2o, double xn2, double mu_override,
+                double eps, double slip, double dp);
+double ora_keq(int i, double T);
+double ora_beta_over_epsp(double eps, double rho, double mu, double slip, double dp, int printed);
+/* resistance ladder: active[3] (hm, mw, wFe), A[3], B[3] = (B_m, B_w, B_Fe), F,
+ * x, xeq[3] -> rates r[3] (unclamped) and the network's Q = 1/R, S = Phi/R */
+void ora_ladder(const int active[3], const double A[3], const double B[3], double F, double x,
+                const double xeq[3], double r[3], double *Q, double *S);
+/* one parcel, explicit environment:
+ *   env = {x, xeq0..2, kappa0..2, kr0..2, c_mol, Ap, rp, Deff_m, Deff_w, Deff_Fe, F, dt}
+ * sp[4] (nh, nm, nw, nfe) updated in place; returns the number of clamped rates */
+int ora_react_point(const double env[18], double sp[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
