@@ -1,0 +1,151 @@
+#!/usr/bin/env python3
+"""Throughput of the particle-side hot path on one MI355X.
+
+A step is one DEM step of the whole path over the 2,000,000-parcel
+polydisperse cylindrical bed: contact detection over the Verlet candidates,
+soft-sphere parcel/wall forces, drag and integration every step; the
+neighbour rebuild (cell sort + LDS-staged candidate scan), voidage/drag
+deposition and the shrinking-core reaction update with its cell and bed
+reductions every 20 steps (one coupling interval, dt_CFD = 20 dt_DEM), all
+replayed from a HIP graph.  Inputs are generated on the host, uploaded, and
+resident in HBM before the timed region.
+
+Prints one JSON line (metric particle-steps/s) with the roofline of the
+dominant kernel (the fused DEM step) and the oracle's CPU throughput on a
+bounded sample of the same bed.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def step_bytes(z_mean):
+    """Algorithmic HBM bytes of one parcel-step of the fused DEM-step kernel
+    (mixed precision): read x (24 B), v and w (24 B), d and m (8 B); write x,
+    v, w (48 B); read and write the 16 B tangential-spring record of each of
+    the z/2 contact pairs of a parcel (16 z B)."""
+    return 104.0 + 16.0 * z_mean
+
+
+def traffic_from_profile(kernel_src):
+    """HBM bytes per launch measured by rocprofv3 counters for the current
+    source of the step kernel, or None if the kernel changed since."""
+    path = os.path.join(ROOT, "profiles", "k_step_cfg3_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != h:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(w, S):
+    """The oracle as it stands (single thread) on the full bed: two DEM steps
+    and one coupling (deposit + reaction), the coupling amortised over S steps."""
+    from oracle import oracle as O
+
+    _log("[bench] cpu baseline: oracle init")
+    ora = O.Oracle(w)
+    t0 = time.perf_counter()
+    ora.step(2)
+    t1 = time.perf_counter()
+    ora.couple()
+    ora.react(S * w.params["dt"])
+    t2 = time.perf_counter()
+    t_step = (t1 - t0) / 2
+    t_couple = t2 - t1
+    rate = w.n / (t_step + t_couple / S)
+    _log(f"[bench] cpu: step {t_step:.2f} s, coupling {t_couple:.2f} s")
+    return {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"full {w.n}-parcel bed: 2 DEM steps + 1 deposit/reaction amortised over {S} steps, "
+                      f"single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n", type=int, default=None, help="parcel count (default: the 2M-parcel bed)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no multi-GPU mode",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2311_03908_amd import workloads as W
+    from paper_2311_03908_amd.bed import Bed
+
+    _log("[bench] generating workload")
+    w = W.cfg3() if args.n is None else W.cfg3(n=args.n)
+    S = w.couple_every
+    steps = max(S, (args.steps + S - 1) // S * S)
+    warm = max(2 * S, (args.warmup + S - 1) // S * S)
+    _log(f"[bench] n={w.n} steps={steps} warmup={warm}")
+    bed = Bed(w, device="cuda:0")
+    bed.autotune()
+    bed.profile(True)
+    bed.run(warm // S, S)
+    torch.cuda.synchronize()
+    _log("[bench] timed region")
+    t0 = time.perf_counter()
+    bed.run(steps // S, S)
+    bed.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = bed.stats()
+    elapsed = t1 - t0
+    rate = w.n * steps / elapsed
+    z = st["mean_coordination"]
+    k_ms = st["step_kernel_ms"]
+    bpu = step_bytes(z)
+    achieved = w.n * bpu / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None
+    traffic = traffic_from_profile(os.path.join(ROOT, "paper_2311_03908_amd", "csrc", "k_step.hip"))
+    _log(f"[bench] {rate:.4e} particle-steps/s, step kernel {k_ms * 1e3:.1f} us, z={z:.3f}")
+    out = {
+        "metric": "particle-steps/s",
+        "value": rate,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "polydisperse cylindrical bed: 2,000,000 parcels, lognormal d_p (median 100 um, "
+                               "sigma 0.3), k=5, 2 ore types, 64x64x384 gas grid, dt=5e-6 s, coupling every 20 steps",
+                   "parcels": w.n, "couple_every": S, "graph": True},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                     "kernel": "k_step (fused contact + drag + integrate)", "bytes_per_parcel_step": bpu,
+                     "kernel_ms": k_ms, "launches_timed": st["step_kernel_launches"], "z_mean": z},
+    }
+    if not args.no_cpu_baseline:
+        bed.close()
+        out["cpu_baseline"] = cpu_baseline(w, S)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,237 @@
+/*
+ * demrx -- C-ABI of the MI355X (gfx950) particle side of the coarse-grained
+ * CFD-DEM reduction model of arxiv 2311.03908 ("Direct reduction of iron ore
+ * with hydrogen in fluidized beds: a coarse-grained CFD-DEM-IBM study").
+ *
+ * The calls follow the paper's statement of the particle/gas exchange
+ * (Section 4, Fig. 5): the gas solver supplies per-cell fields; the particle
+ * side advances parcel velocities every DEM step and returns the voidage and
+ * the cell-summed momentum and species sources every n = dt_CFD / dt_DEM
+ * steps, when the layer masses of the parcels are also updated.
+ *
+ * Conventions
+ *  - SI units throughout; gas arrays hold one value per gas cell, the cells of
+ *    all beds concatenated bed by bed, each bed x-fastest (c = ix + nx (iy + ny iz)).
+ *  - Every array pointer in dem_parcels, dem_gas and dem_sources is a DEVICE
+ *    pointer owned by the caller; the library never frees caller memory and
+ *    keeps no caller pointer after a call returns.  Parcel arrays are in the
+ *    caller's original parcel order.
+ *  - All work is enqueued on the HIP stream given to dem_init; calls return
+ *    as soon as the work is enqueued unless stated otherwise.  A context is
+ *    not thread-safe; use one context per stream.
+ *  - Return value: DEMRX_OK (0) or a negative DEMRX_E* code; dem_last_error()
+ *    gives a message.  Errors detected on the device (slot overflow, a parcel
+ *    leaving its grid, a non-finite state, a neighbour-list skin violation)
+ *    are latched in a device status word and reported by the next call that
+ *    synchronises (dem_sync, dem_pairs, dem_get_state, dem_react with a host
+ *    result, dem_grad).
+ */
+#ifndef DEMRX_H
+#define DEMRX_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DEMRX_OK 0
+#define DEMRX_EINVAL -1     /* invalid argument (null pointer, bad size, bad parameter) */
+#define DEMRX_EHIP -2       /* a HIP runtime call failed */
+#define DEMRX_EOVERFLOW -3  /* a parcel has more neighbour candidates than max_nbr */
+#define DEMRX_EDOMAIN -4    /* a parcel centre left its bed's grid */
+#define DEMRX_ENONFINITE -5 /* non-finite parcel state or gas input */
+#define DEMRX_ENOMEM -6     /* device allocation failed */
+#define DEMRX_ESKIN -7      /* displacement bound since the last neighbour build exceeded skin/2 */
+
+#define DEM_FP64 0  /* forces, velocities and spins in FP64 */
+#define DEM_MIXED 1 /* FP32 forces, velocities and spins; FP64 positions, grid and reaction */
+
+#define DEM_WALL_BOX 0 /* six planes lo/hi */
+#define DEM_WALL_CYL 1 /* cylinder of radius R about the vertical axis through the xy centre of
+                          lo/hi, floor z = lo[2], lid z = hi[2] */
+#define DEM_MAX_ORES 8
+#define DEM_MAX_BEDS 4096
+#define DEM_MAX_NBR 48
+
+typedef struct dem_ctx dem_ctx;
+
+/* One bed: reactor walls, frozen gas grid and kinetic parameters. */
+typedef struct {
+  int32_t wall_kind;   /* DEM_WALL_BOX or DEM_WALL_CYL */
+  double lo[3], hi[3]; /* walls (box) or bounding box of the cylinder */
+  double R;            /* cylinder radius */
+  double origin[3];    /* gas grid origin */
+  double h;            /* gas cell edge; the grid must contain lo..hi */
+  int32_t n[3];        /* gas cells per axis */
+  int32_t refine;      /* DEM cells per gas-cell edge (1..4); h/refine must be >= the largest
+                          parcel diameter of the bed plus the skin */
+  double theta[6];     /* (ln k0, Ea) of R1 Fe2O3->Fe3O4, R2 Fe3O4->FeO, R3 FeO->Fe; eq. e2-13 */
+  double mu_override;  /* > 0: gas viscosity fixed to this value instead of eq. e3-56 */
+} dem_bed;
+
+/* One ore type (Section 2.3, Table 3). */
+typedef struct {
+  double xi0;         /* initial particle porosity, eq. e2-32 */
+  double d_pore_cm;   /* pore diameter d_a in cm (Section 2.3) */
+  double tau;         /* tortuosity of eq. e2-30 */
+  double rho_true[4]; /* true densities of Fe2O3, Fe3O4, FeO, Fe (kg/m3) */
+  int32_t kind;       /* 0: hematite ore (f_ov by eq. e2-18), 1: magnetite ore (eq. e2-19) */
+} dem_ore;
+
+typedef struct {
+  int32_t precision;     /* DEM_FP64 or DEM_MIXED */
+  int32_t n_beds;        /* 1..DEM_MAX_BEDS; host array copied at init */
+  const dem_bed *beds;
+  int32_t n_ores;        /* 1..DEM_MAX_ORES; host array copied at init */
+  const dem_ore *ores;
+  double kn;             /* normal spring stiffness (N/m) */
+  double e_p;            /* restitution of the real particle; parcels use eq. e3-45 */
+  double mu_s;           /* sliding friction */
+  double mu_r;           /* rolling friction length (m); 0 disables */
+  double kt_over_kn;     /* tangential / normal stiffness */
+  double gt_over_gn;     /* tangential / normal damping */
+  double eps_min;        /* lower clamp of the deposited voidage */
+  double skin;           /* neighbour-list skin (m) */
+  double dt;             /* DEM time step (s) */
+  double g[3];           /* gravity (m/s2) */
+  int32_t max_nbr;       /* neighbour slots per parcel, 1..DEM_MAX_NBR */
+  int32_t rebuild_every; /* steps between neighbour-list builds (>= 1) */
+  int32_t ergun_printed; /* 1: inertial Ergun term with eps_g as printed in eq. e3-5-1 */
+  int32_t drag_on;       /* 0: no gas-side forces on parcels (gravity only) */
+} dem_params;
+
+/* Parcel state (device pointers, original order).  v and w point to float in
+ * DEM_MIXED and to double in DEM_FP64.  d is the parcel diameter k * d_p
+ * (FP32), k the coarse-graining ratio of Section 3.3, n_* the moles of
+ * Fe2O3, Fe3O4, FeO and Fe per real particle. */
+typedef struct {
+  double *x, *y, *z;
+  void *vx, *vy, *vz, *wx, *wy, *wz;
+  float *d, *k;
+  int32_t *ore, *bed;
+  double *nh, *nm, *nw, *nfe;
+} dem_parcels;
+
+/* Frozen gas fields per cell (device pointers, double): velocity, pressure,
+ * pressure gradient, temperature (= particle temperature, Section 2,
+ * assumption (iv)) and the true mole fractions of H2, H2O and N2. */
+typedef struct {
+  const double *ug, *vg, *wg, *p, *dpdx, *dpdy, *dpdz, *T, *xH2, *xH2O, *xN2;
+} dem_gas;
+
+/* Per-cell outputs (device pointers, double, any may be NULL):
+ *  eps     voidage (eq. e3-25 reading: 1 - sum V_p / h^3, clamped to [eps_min, 1])
+ *  np      parcels per cell
+ *  sumK    sum of K_p = beta V_p / (1 - eps_g) (eqs. e3-5, e3-27a), kg/s
+ *  sumKu/v/w  sum of K_p v_p, sumKs sum of K_p |u_g - v_p|
+ *  mdotH2, mdotH2O  parcel mass sources of eq. e3-25 times V_cell (kg/s, eqs. e2-25, e3-52)
+ *  sumEQ, sumES     sums of k^3 E Q and k^3 E S of eqs. e4-8..e4-11 with E = eta_H2 A_p / T */
+typedef struct {
+  double *eps, *np, *sumK, *sumKu, *sumKv, *sumKw, *sumKs, *mdotH2, *mdotH2O, *sumEQ, *sumES;
+} dem_sources;
+
+/* Kinetic-gradient protocol: n_substeps reaction updates of dt_react, each
+ * block of dyn_every substeps preceded by one DEM step and a voidage deposit;
+ * the DEM mass stays frozen (the trajectory does not depend on theta).
+ * Reaction state is checkpointed every ckpt_every substeps. */
+typedef struct {
+  int32_t n_substeps;
+  double dt_react;
+  int32_t dyn_every;
+  int32_t ckpt_every;
+  int32_t state_fp32; /* 1: FP32 reaction state (FP64 adjoint accumulation); 0: FP64 */
+} dem_grad_spec;
+
+typedef struct {
+  int64_t n_parcels, n_contacts, n_wall_contacts, rebuilds, steps, clamps;
+  double mean_coordination;      /* 2 n_contacts / n_parcels in the last step */
+  int32_t max_nbr_used;
+  uint32_t status;
+  double step_kernel_ms;         /* mean duration of the timed DEM-step kernel launches */
+  int64_t step_kernel_launches;  /* launches behind step_kernel_ms (see dem_profile) */
+} dem_stats;
+
+/* Create a context holding n parcels.  Copies the parcel state (device, original
+ * order) into internal cell-sorted storage, computes parcel masses (eq. e3-4)
+ * and the voidage at t = 0.  stream: a hipStream_t (NULL = default stream).
+ * Synchronises once.  Errors: EINVAL (nulls, n <= 0, bad params or grid),
+ * ENOMEM, EDOMAIN (a parcel outside its bed's grid). */
+int dem_init(const dem_params *p, const dem_parcels *in, int32_t n, void *stream, dem_ctx **out);
+
+/* Advance n_steps DEM steps with the gas frozen (eq. e3-3, e3-6; semi-implicit
+ * Euler): contact detection, soft-sphere parcel-parcel and parcel-wall forces,
+ * Gidaspow drag with the voidage of the last deposit, gravity and -V grad p.
+ * The neighbour list is rebuilt every rebuild_every steps. */
+int dem_step(dem_ctx *c, int32_t n_steps, const dem_gas *g);
+
+/* Coupling deposit (eqs. e3-25, e3-27a, e4-1): voidage and drag sums per gas
+ * cell from the current parcel state; the new voidage is used by later steps. */
+int dem_couple(dem_ctx *c, const dem_gas *g, dem_sources *out);
+
+/* Reaction update over dt_cfd (eqs. e2-1..e2-36, e3-1..e3-4, e3-52): the
+ * multi-interface unreacted-shrinking-core rates of every parcel, the species
+ * and mass update and the cell sources mdotH2, mdotH2O, sumEQ, sumES.
+ * bed_fov (host, n_beds doubles, may be NULL): bed-mean overall reduction
+ * degree weighted by k^3 N_Fe (eqs. e2-18/e2-19); when given, the call
+ * synchronises.  fov (device, n doubles, original order, may be NULL):
+ * per-parcel overall reduction degree. */
+int dem_react(dem_ctx *c, double dt_cfd, const dem_gas *g, dem_sources *out, double *bed_fov,
+              double *fov);
+
+/* Gradient of the bed-mean reduction degree J (all parcels, weight k^3 N_Fe)
+ * after the protocol of spec with respect to theta (used for every bed) by a
+ * reverse (adjoint) sweep with checkpointing; grad may be NULL for a plain
+ * forward run.  J and grad are host pointers; the call synchronises.  The DEM
+ * and reaction state of the context are left unchanged. */
+int dem_grad(dem_ctx *c, const dem_grad_spec *s, const dem_gas *g, const double theta[6], double *J,
+             double *grad);
+
+/* Total force and torque (device, 3 n doubles each, original order, [3 i + axis])
+ * that the next DEM step applies; the state is not changed. */
+int dem_forces(dem_ctx *c, const dem_gas *g, double *F, double *T);
+
+/* Copy the parcel state into caller arrays (original order; only non-null
+ * members of out are written; d, k, ore, bed are ignored).  Synchronises. */
+int dem_get_state(dem_ctx *c, dem_parcels *out);
+
+/* Replace positions, velocities, spins and species (original order, all
+ * members required except d, k, ore, bed, which are ignored); masses follow
+ * the species; contact histories are cleared.  Synchronises. */
+int dem_set_state(dem_ctx *c, const dem_parcels *in);
+
+/* Contacting pairs at the current positions (exact FP64 test
+ * ((dx dx + dy dy) + dz dz) < (r_i + r_j)^2), canonical (i < j by original id),
+ * sorted by (i, j), written to the host array ij (2 * cap uint32).  *n_pairs
+ * receives the total count (may exceed cap).  Synchronises. */
+int dem_pairs(dem_ctx *c, uint32_t *ij, int64_t cap, int64_t *n_pairs);
+
+/* Counters of the last step (host).  Synchronises. */
+int dem_get_stats(dem_ctx *c, dem_stats *out);
+
+/* Replay the full hot path -- rebuild, couple_every DEM steps, coupling deposit
+ * and reaction update (dt_cfd = couple_every * dt) -- n_intervals times from a
+ * HIP graph captured on first use (recaptured if the arguments change).
+ * out and bed_fov (host) may be NULL; bed_fov receives the values after the
+ * last interval and makes the call synchronise. */
+int dem_run(dem_ctx *c, int32_t n_intervals, int32_t couple_every, const dem_gas *g,
+            dem_sources *out, double *bed_fov);
+
+/* Choose launch shapes for this context's kernels by timing candidates on
+ * its own data (state unchanged).  Synchronises. */
+int dem_autotune(dem_ctx *c, const dem_gas *g);
+
+/* Enable (1) or disable (0) HIP-event timing of every DEM-step kernel launch,
+ * recorded on the stream the kernel runs on (inside dem_run graphs too: the
+ * events of the last replay are kept).  Resets the timings; dem_get_stats
+ * reports their mean. */
+int dem_profile(dem_ctx *c, int32_t enable);
+
+/* Wait for all work of the context; report a latched device error. */
+int dem_sync(dem_ctx *c);
+const char *dem_last_error(const dem_ctx *c);
+void dem_destroy(dem_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -347,47 +347,81 @@ static long find_pairs(ora_sys *s, int brute, int **out) {
           pr[2 * cnt] = a; pr[2 * cnt + 1] = b; cnt++;
         }
   } else {
+    /* cell list: bins of edge >= the largest diameter, parcels copied in
+     * bin order so that each bin's members are contiguous */
     for (int bd = 0; bd < s->P.n_beds; bd++) {
       const ora_bed *B = &s->beds[bd];
       double hc = 0.0;
-      for (int i = 0; i < s->n; i++) if (s->bed[i] == bd && s->d[i] > hc) hc = s->d[i];
-      if (hc <= 0.0) continue;
+      int nb = 0;
+      for (int i = 0; i < s->n; i++)
+        if (s->bed[i] == bd) {
+          nb++;
+          if (s->d[i] > hc) hc = s->d[i];
+        }
+      if (nb == 0) continue;
       int nc[3];
-      for (int a = 0; a < 3; a++) { nc[a] = (int)floor((B->hi[a] - B->lo[a]) / hc); if (nc[a] < 1) nc[a] = 1; }
       double cs[3];
-      for (int a = 0; a < 3; a++) cs[a] = (B->hi[a] - B->lo[a]) / nc[a];
+      for (int a = 0; a < 3; a++) {
+        nc[a] = (int)floor((B->hi[a] - B->lo[a]) / hc);
+        if (nc[a] < 1) nc[a] = 1;
+        cs[a] = (B->hi[a] - B->lo[a]) / nc[a];
+      }
       long ncell = (long)nc[0] * nc[1] * nc[2];
-      int *head = (int *)malloc(sizeof(int) * ncell);
-      int *next = (int *)malloc(sizeof(int) * s->n);
-      int *cid = (int *)malloc(sizeof(int) * 3 * s->n);
-      for (long c = 0; c < ncell; c++) head[c] = -1;
-      for (int i = s->n - 1; i >= 0; i--) {
+      long *first = (long *)calloc(ncell + 1, sizeof(long));
+      long *cellof = (long *)malloc(sizeof(long) * nb);
+      int *member = (int *)malloc(sizeof(int) * nb);
+      double *q = (double *)malloc(sizeof(double) * 4 * nb);
+      int m = 0;
+      for (int i = 0; i < s->n; i++) {
         if (s->bed[i] != bd) continue;
+        int c3[3];
         for (int a = 0; a < 3; a++) {
           double f = floor((s->pos[3 * i + a] - B->lo[a]) / cs[a]);
           if (f < 0) f = 0;
           if (f > nc[a] - 1) f = nc[a] - 1;
-          cid[3 * i + a] = (int)f;
+          c3[a] = (int)f;
         }
-        long c = cid[3 * i] + (long)nc[0] * (cid[3 * i + 1] + (long)nc[1] * cid[3 * i + 2]);
-        next[i] = head[c];
-        head[c] = i;
+        cellof[m] = c3[0] + (long)nc[0] * (c3[1] + (long)nc[1] * c3[2]);
+        first[cellof[m] + 1]++;
+        member[m++] = i;
       }
-      for (int a = 0; a < s->n; a++) {
-        if (s->bed[a] != bd) continue;
+      for (long c = 0; c < ncell; c++) first[c + 1] += first[c];
+      long *fill = (long *)malloc(sizeof(long) * ncell);
+      memcpy(fill, first, sizeof(long) * ncell);
+      int *sorted = (int *)malloc(sizeof(int) * nb);
+      for (int t = 0; t < nb; t++) sorted[fill[cellof[t]]++] = member[t];
+      for (int t = 0; t < nb; t++) {
+        int i = sorted[t];
+        q[4 * t] = s->pos[3 * i];
+        q[4 * t + 1] = s->pos[3 * i + 1];
+        q[4 * t + 2] = s->pos[3 * i + 2];
+        q[4 * t + 3] = radius(s, i);
+      }
+      for (long c = 0; c < ncell; c++) {
+        if (first[c] == first[c + 1]) continue;
+        int cx = (int)(c % nc[0]), cy = (int)((c / nc[0]) % nc[1]), cz = (int)(c / ((long)nc[0] * nc[1]));
         for (int oz = -1; oz <= 1; oz++)
           for (int oy = -1; oy <= 1; oy++)
             for (int ox = -1; ox <= 1; ox++) {
-              int cx = cid[3 * a] + ox, cy = cid[3 * a + 1] + oy, cz = cid[3 * a + 2] + oz;
-              if (cx < 0 || cy < 0 || cz < 0 || cx >= nc[0] || cy >= nc[1] || cz >= nc[2]) continue;
-              for (int b = head[cx + (long)nc[0] * (cy + (long)nc[1] * cz)]; b >= 0; b = next[b]) {
-                if (b <= a || !in_contact(s, a, b)) continue;
-                if (cnt == cap) { cap *= 2; pr = (int *)realloc(pr, sizeof(int) * 2 * cap); }
-                pr[2 * cnt] = a; pr[2 * cnt + 1] = b; cnt++;
-              }
+              int x2 = cx + ox, y2 = cy + oy, z2 = cz + oz;
+              if (x2 < 0 || y2 < 0 || z2 < 0 || x2 >= nc[0] || y2 >= nc[1] || z2 >= nc[2]) continue;
+              long c2 = x2 + (long)nc[0] * (y2 + (long)nc[1] * z2);
+              for (long ta = first[c]; ta < first[c + 1]; ta++)
+                for (long tb = first[c2]; tb < first[c2 + 1]; tb++) {
+                  int a = sorted[ta], b = sorted[tb];
+                  if (b <= a) continue;
+                  /* the contact predicate of in_contact(), on the bin-ordered copies */
+                  double dx = q[4 * tb] - q[4 * ta];
+                  double dy = q[4 * tb + 1] - q[4 * ta + 1];
+                  double dz = q[4 * tb + 2] - q[4 * ta + 2];
+                  double sr = q[4 * ta + 3] + q[4 * tb + 3];
+                  if (!(((dx * dx + dy * dy) + dz * dz) < sr * sr)) continue;
+                  if (cnt == cap) { cap *= 2; pr = (int *)realloc(pr, sizeof(int) * 2 * cap); }
+                  pr[2 * cnt] = a; pr[2 * cnt + 1] = b; cnt++;
+                }
             }
       }
-      free(head); free(next); free(cid);
+      free(first); free(cellof); free(member); free(q); free(fill); free(sorted);
     }
   }
   qsort(pr, cnt, 2 * sizeof(int), cmp_pair);

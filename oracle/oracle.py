@@ -167,7 +167,7 @@ class Oracle:
 
     def pairs(self, brute=False):
         L = lib()
-        cap = 16
+        cap = max(16, 8 * self.n)
         while True:
             buf = np.zeros(2 * cap, np.int32)
             n = L.ora_pairs(self.h, int(brute), _p(buf, C.c_int), cap)

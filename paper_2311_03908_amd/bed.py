@@ -1,0 +1,198 @@
+"""Thin Python binding over the demrx C-ABI with PyTorch device memory.
+
+``Bed`` owns one demrx context: it uploads a workload's parcels and gas fields
+into torch CUDA tensors, passes their device pointers to the library and
+returns results as tensors.  No numerics happen here.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import capi
+from .capi import DemError
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Bed:
+    def __init__(self, w, device="cuda:0", drag_on=True, g=None, stream=None, theta=None, max_nbr=None,
+                 rebuild_every=None):
+        self.L = capi.load()
+        self.w = w
+        self.device = torch.device(device)
+        self.mixed = w.precision == "mixed"
+        self.vdtype = torch.float32 if self.mixed else torch.float64
+        self.n = w.n
+        self.n_beds = len(w.beds)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        prm = w.params
+        beds = (capi.DemBed * len(w.beds))()
+        for b, bd in enumerate(w.beds):
+            s = beds[b]
+            s.wall_kind = bd.wall
+            for i in range(3):
+                s.lo[i], s.hi[i], s.origin[i], s.n[i] = bd.lo[i], bd.hi[i], bd.origin[i], bd.n[i]
+            s.R, s.h, s.refine, s.mu_override = bd.R, bd.h, bd.refine, bd.mu_override
+            th = bd.theta if theta is None else theta
+            for i in range(6):
+                s.theta[i] = th[i]
+        ores = (capi.DemOre * len(w.ores))()
+        for o, od in enumerate(w.ores):
+            s = ores[o]
+            s.xi0, s.d_pore_cm, s.tau, s.kind = od.xi0, od.d_pore_cm, od.tau, od.kind
+            for i in range(4):
+                s.rho_true[i] = od.rho_true[i]
+        P = capi.DemParams()
+        P.precision = capi.DEM_MIXED if self.mixed else capi.DEM_FP64
+        P.n_beds, P.beds, P.n_ores, P.ores = len(w.beds), beds, len(w.ores), ores
+        P.kn, P.e_p, P.mu_s, P.mu_r = prm["kn"], prm["e_p"], prm["mu_s"], prm["mu_r"]
+        P.kt_over_kn, P.gt_over_gn, P.eps_min = prm["kt_over_kn"], prm["gt_over_gn"], prm["eps_min"]
+        P.skin, P.dt = prm["skin"], prm["dt"]
+        gg = prm["g"] if g is None else g
+        for i in range(3):
+            P.g[i] = gg[i]
+        P.max_nbr = prm["max_nbr"] if max_nbr is None else max_nbr
+        P.rebuild_every = prm["rebuild_every"] if rebuild_every is None else rebuild_every
+        P.ergun_printed = int(prm.get("ergun_printed", 0))
+        P.drag_on = int(drag_on)
+        self._P, self._beds, self._ores = P, beds, ores
+        dev = self.device
+        p = w.parcels
+        self.inp = {}
+        for k in ("x", "y", "z", "nh", "nm", "nw", "nfe"):
+            self.inp[k] = torch.as_tensor(np.ascontiguousarray(p[k], dtype=np.float64), device=dev)
+        for k in ("vx", "vy", "vz", "wx", "wy", "wz"):
+            self.inp[k] = torch.as_tensor(np.asarray(p[k], dtype=np.float64), device=dev).to(self.vdtype)
+        self.inp["d"] = torch.as_tensor(np.ascontiguousarray(p["d"], dtype=np.float32), device=dev)
+        self.inp["k"] = torch.as_tensor(np.ascontiguousarray(p["k"], dtype=np.float32), device=dev)
+        self.inp["ore"] = torch.as_tensor(np.ascontiguousarray(p["ore"], dtype=np.int32), device=dev)
+        self.inp["bed"] = torch.as_tensor(np.ascontiguousarray(p["bed"], dtype=np.int32), device=dev)
+        self.set_gas(w.gas)
+        self.n_cells = int(self.gas_t["T"].shape[0])
+        pc = capi.DemParcels(*[_ptr(self.inp[f]) for f in capi.PARCEL_FIELDS])
+        h = C.c_void_p()
+        with torch.cuda.device(dev):
+            torch.cuda.synchronize(dev)
+            r = self.L.dem_init(C.byref(P), C.byref(pc), self.n, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if r != 0:
+            raise DemError(r, self.L.dem_last_error(None).decode())
+        self.h = h
+
+    # ------------------------------------------------------------ helpers
+    def _check(self, r):
+        if r != 0:
+            raise DemError(r, self.L.dem_last_error(self.h).decode())
+
+    def set_gas(self, gas):
+        self.gas_t = {k: torch.as_tensor(np.ascontiguousarray(gas[k], dtype=np.float64), device=self.device)
+                      for k in capi.GAS_FIELDS}
+        self._gas = capi.DemGas(*[_ptr(self.gas_t[f]) for f in capi.GAS_FIELDS])
+
+    def _sources(self, keys):
+        out = {k: torch.zeros(self.n_cells, dtype=torch.float64, device=self.device) for k in keys}
+        s = capi.DemSources(*[_ptr(out.get(f)) for f in capi.SOURCE_FIELDS])
+        return out, s
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.dem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ API
+    def step(self, n=1):
+        self._check(self.L.dem_step(self.h, int(n), C.byref(self._gas)))
+
+    def couple(self, keys=("eps", "np", "sumK", "sumKu", "sumKv", "sumKw", "sumKs")):
+        out, s = self._sources(keys)
+        self._check(self.L.dem_couple(self.h, C.byref(self._gas), C.byref(s)))
+        self.sync()
+        return out
+
+    def react(self, dt, keys=("mdotH2", "mdotH2O", "sumEQ", "sumES"), fov=True):
+        out, s = self._sources(keys)
+        bf = (C.c_double * self.n_beds)()
+        fv = torch.zeros(self.n, dtype=torch.float64, device=self.device) if fov else None
+        self._check(self.L.dem_react(self.h, float(dt), C.byref(self._gas), C.byref(s), bf, _ptr(fv)))
+        out["bed_fov"] = np.array(bf[:])
+        if fov:
+            out["fov"] = fv
+        return out
+
+    def forces(self):
+        F = torch.zeros(3 * self.n, dtype=torch.float64, device=self.device)
+        T = torch.zeros(3 * self.n, dtype=torch.float64, device=self.device)
+        self._check(self.L.dem_forces(self.h, C.byref(self._gas), _ptr(F), _ptr(T)))
+        self.sync()
+        return F.view(-1, 3), T.view(-1, 3)
+
+    def state(self):
+        out = {k: torch.zeros(self.n, dtype=torch.float64, device=self.device) for k in
+               ("x", "y", "z", "nh", "nm", "nw", "nfe")}
+        for k in ("vx", "vy", "vz", "wx", "wy", "wz"):
+            out[k] = torch.zeros(self.n, dtype=self.vdtype, device=self.device)
+        pc = capi.DemParcels(*[_ptr(out.get(f)) for f in capi.PARCEL_FIELDS])
+        self._check(self.L.dem_get_state(self.h, C.byref(pc)))
+        return out
+
+    def set_state(self, st):
+        t = {}
+        for k in ("x", "y", "z", "nh", "nm", "nw", "nfe"):
+            t[k] = torch.as_tensor(np.asarray(st[k], dtype=np.float64), device=self.device)
+        for k in ("vx", "vy", "vz", "wx", "wy", "wz"):
+            t[k] = torch.as_tensor(np.asarray(st[k], dtype=np.float64), device=self.device).to(self.vdtype)
+        pc = capi.DemParcels(*[_ptr(t.get(f)) for f in capi.PARCEL_FIELDS])
+        self._check(self.L.dem_set_state(self.h, C.byref(pc)))
+
+    def pairs(self):
+        cap = max(16, 8 * self.n)
+        while True:
+            buf = (C.c_uint32 * (2 * cap))()
+            npairs = C.c_int64()
+            self._check(self.L.dem_pairs(self.h, buf, cap, C.byref(npairs)))
+            if npairs.value <= cap:
+                return np.frombuffer(buf, dtype=np.uint32, count=2 * npairs.value).reshape(-1, 2).astype(np.int64)
+            cap = npairs.value
+
+    def stats(self):
+        s = capi.DemStats()
+        self._check(self.L.dem_get_stats(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in capi.DemStats._fields_}
+
+    def run(self, n_intervals, couple_every, sources=False, bed_fov=False):
+        keys = capi.SOURCE_FIELDS if sources else ()
+        out, s = self._sources(keys)
+        bf = (C.c_double * self.n_beds)() if bed_fov else None
+        self._check(self.L.dem_run(self.h, int(n_intervals), int(couple_every), C.byref(self._gas),
+                                   C.byref(s) if sources else None, bf))
+        if bed_fov:
+            out["bed_fov"] = np.array(bf[:])
+        return out
+
+    def profile(self, enable=True):
+        self._check(self.L.dem_profile(self.h, int(enable)))
+
+    def autotune(self):
+        self._check(self.L.dem_autotune(self.h, C.byref(self._gas)))
+
+    def grad(self, n_substeps, dt_react, dyn_every, ckpt_every, theta, state_fp32=True, with_grad=True):
+        spec = capi.DemGradSpec(int(n_substeps), float(dt_react), int(dyn_every), int(ckpt_every), int(state_fp32))
+        th = (C.c_double * 6)(*[float(v) for v in theta])
+        J = C.c_double()
+        g = (C.c_double * 6)()
+        self._check(self.L.dem_grad(self.h, C.byref(spec), C.byref(self._gas), th, C.byref(J),
+                                    g if with_grad else None))
+        return J.value, (np.array(g[:]) if with_grad else None)
+
+    def sync(self):
+        self._check(self.L.dem_sync(self.h))

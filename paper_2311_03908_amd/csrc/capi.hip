@@ -1,0 +1,829 @@
+// Host side of the demrx C-ABI: validation, device memory, the rebuild /
+// step / coupling sequence, HIP-graph replay of the full hot path and the
+// launch-shape autotuner.  Numerics live in the kernel files.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+
+using namespace demrx;
+
+struct dem_ctx {
+  std::string err;
+  virtual ~dem_ctx() = default;
+  int fail(int code, const std::string &m) {
+    err = m;
+    return code;
+  }
+  virtual int step(int n, const dem_gas *g) = 0;
+  virtual int couple(const dem_gas *g, dem_sources *o) = 0;
+  virtual int react(double dt, const dem_gas *g, dem_sources *o, double *bed_fov, double *fov) = 0;
+  virtual int forces(const dem_gas *g, double *F, double *T) = 0;
+  virtual int get_state(dem_parcels *o) = 0;
+  virtual int set_state(const dem_parcels *in) = 0;
+  virtual int pairs(uint32_t *ij, int64_t cap, int64_t *np) = 0;
+  virtual int stats(dem_stats *o) = 0;
+  virtual int run(int n_int, int S, const dem_gas *g, dem_sources *o, double *bed_fov) = 0;
+  virtual int autotune(const dem_gas *g) = 0;
+  virtual int grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, double *J, double *grad) = 0;
+  virtual int profile(int enable) = 0;
+  virtual int sync() = 0;
+};
+
+namespace {
+
+#define HIPCHK(x)                                                                    \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess) return fail(DEMRX_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+GasArgs gas_args(const dem_gas *g) {
+  GasArgs a;
+  a.ug = g->ug; a.vg = g->vg; a.wg = g->wg; a.p = g->p;
+  a.dpdx = g->dpdx; a.dpdy = g->dpdy; a.dpdz = g->dpdz; a.T = g->T;
+  a.xH2 = g->xH2; a.xH2O = g->xH2O; a.xN2 = g->xN2;
+  return a;
+}
+
+bool gas_ok(const dem_gas *g) {
+  return g && g->ug && g->vg && g->wg && g->p && g->dpdx && g->dpdy && g->dpdz && g->T && g->xH2 && g->xH2O && g->xN2;
+}
+
+// Porosities of the product layers (eqs. e2-31..e2-36): effective densities
+// scale by q_b,a = |eta_b| M_b / (|eta_a| M_a) down the Fe2O3 -> Fe3O4 -> FeO
+// -> Fe chain.
+OreDev make_ore(const dem_ore &o) {
+  const double Mh = 159.687, Mm = 231.531, Mw = 71.844, Mf = 55.845;
+  const double qmh = 2.0 * Mm / (3.0 * Mh), qwm = 3.0 * Mw / Mm, qfw = Mf / Mw;
+  const double reh = (1.0 - o.xi0) * o.rho_true[0];
+  const double rem = reh * qmh, rew = rem * qwm, ref = rew * qfw;
+  OreDev d;
+  d.xi_layer[0] = 1.0 - rem / o.rho_true[1];
+  d.xi_layer[1] = 1.0 - rew / o.rho_true[2];
+  d.xi_layer[2] = 1.0 - ref / o.rho_true[3];
+  d.d_pore_cm = o.d_pore_cm;
+  d.tau = o.tau;
+  d.kind = o.kind;
+  return d;
+}
+
+int status_code(uint32_t st) {
+  if (st & 16u) return DEMRX_EINVAL;
+  if (st & ST_NONFINITE) return DEMRX_ENONFINITE;
+  if (st & ST_DOMAIN) return DEMRX_EDOMAIN;
+  if (st & ST_OVERFLOW) return DEMRX_EOVERFLOW;
+  if (st & ST_SKIN) return DEMRX_ESKIN;
+  return DEMRX_OK;
+}
+const char *status_text(uint32_t st) {
+  if (st & 16u) return "invalid parcel input (bed/ore index out of range, non-positive diameter or k < 1)";
+  if (st & ST_NONFINITE) return "non-finite parcel state or gas field";
+  if (st & ST_DOMAIN) return "a parcel centre lies outside its bed's gas grid";
+  if (st & ST_OVERFLOW) return "neighbour candidates exceed max_nbr (or a stencil plane exceeds the LDS tile)";
+  if (st & ST_SKIN) return "displacement bound since the last neighbour build exceeded skin/2";
+  return "";
+}
+
+}  // namespace
+
+template <typename T>
+struct Ctx final : dem_ctx {
+  dem_params P{};
+  std::vector<dem_bed> hbeds;
+  std::vector<dem_ore> hores;
+  std::vector<BedDev> hbd;
+  Phys ph{};
+  int n = 0, n_gas = 0, n_keys = 0, n_items = 0;
+  hipStream_t st = nullptr, user_st = nullptr, cap_st = nullptr;
+  std::vector<void *> allocs;
+  BedDev *beds = nullptr;
+  OreDev *ores = nullptr;
+  int32_t *cell_bed = nullptr;
+  Item *items = nullptr;
+  Dyn<T> dyn[2]{};
+  Props<T> pr[2]{};
+  Nbr<T> nb[2]{};
+  int cur = 0, pc = 0, nbc = 0;
+  int32_t *key = nullptr, *slot = nullptr, *count = nullptr, *start = nullptr, *perm = nullptr, *scan_scr = nullptr;
+  int32_t *iflags = nullptr, *ioffs = nullptr, *ilist = nullptr, *icount = nullptr;
+  T *gtab = nullptr;
+  double *eps = nullptr, *pm = nullptr, *pw = nullptr, *bed_fov_d = nullptr, *theta_d = nullptr;
+  uint32_t *status = nullptr;
+  unsigned *vmax = nullptr;
+  double *disp = nullptr;
+  unsigned long long *counters = nullptr;  // pp contacts, wall contacts, clamps, pairs
+  uint32_t *pairs_buf = nullptr;
+  long pairs_cap = 0;
+  long step_count = 0, steps_since = 0, rebuilds = 0;
+  bool built = false;
+  int step_block = 256, build_grid = 2048;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<const void *> gkey;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  // step-kernel timing: event pairs of eager launches and of the captured graph
+  bool prof = false, capturing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_eager, prof_graph, prof_capture;
+
+  ~Ctx() override {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ev_a) (void)hipEventDestroy(ev_a);
+    if (ev_b) (void)hipEventDestroy(ev_b);
+    if (cap_st) (void)hipStreamDestroy(cap_st);
+    for (void *p : allocs) (void)hipFree(p);
+  }
+
+  template <typename P_>
+  int dalloc(P_ *&p, size_t cnt) {
+    void *q = nullptr;
+    if (cnt == 0) cnt = 1;
+    if (hipMalloc(&q, cnt * sizeof(P_)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(DEMRX_ENOMEM, "device allocation of " + std::to_string(cnt * sizeof(P_)) + " bytes failed");
+    }
+    allocs.push_back(q);
+    p = (P_ *)q;
+    return DEMRX_OK;
+  }
+
+#define TRY(x)                 \
+  do {                         \
+    int r_ = (x);              \
+    if (r_ != DEMRX_OK) return r_; \
+  } while (0)
+
+  int alloc_dyn(Dyn<T> &d) {
+    TRY(dalloc(d.x, n)); TRY(dalloc(d.y, n)); TRY(dalloc(d.z, n));
+    TRY(dalloc(d.vx, n)); TRY(dalloc(d.vy, n)); TRY(dalloc(d.vz, n));
+    TRY(dalloc(d.wx, n)); TRY(dalloc(d.wy, n)); TRY(dalloc(d.wz, n));
+    return DEMRX_OK;
+  }
+  int alloc_props(Props<T> &p) {
+    TRY(dalloc(p.rad, n)); TRY(dalloc(p.kcg, n)); TRY(dalloc(p.mass, n)); TRY(dalloc(p.zeta, n));
+    TRY(dalloc(p.tag, n)); TRY(dalloc(p.id, n));
+    TRY(dalloc(p.nh, n)); TRY(dalloc(p.nm, n)); TRY(dalloc(p.nw, n)); TRY(dalloc(p.nfe, n));
+    TRY(dalloc(p.wh, (size_t)3 * kMaxWalls * n));
+    return DEMRX_OK;
+  }
+  int alloc_nbr(Nbr<T> &b) {
+    TRY(dalloc(b.cnt, n));
+    TRY(dalloc(b.idx, (size_t)kMaxNbr * n));
+    TRY(dalloc(b.hist, (size_t)3 * kMaxNbr * n));
+    TRY(dalloc(b.mask, n));
+    return DEMRX_OK;
+  }
+
+  int init(const dem_params *p, const dem_parcels *in, int n_, hipStream_t s) {
+    P = *p;
+    n = n_;
+    user_st = st = s;
+    hbeds.assign(p->beds, p->beds + p->n_beds);
+    hores.assign(p->ores, p->ores + p->n_ores);
+    P.beds = nullptr;
+    P.ores = nullptr;
+    ph.kn = p->kn; ph.e_p = p->e_p; ph.mu_s = p->mu_s; ph.mu_r = p->mu_r;
+    ph.kt = p->kt_over_kn * p->kn; ph.gt_ratio = p->gt_over_gn; ph.eps_min = p->eps_min;
+    ph.skin = p->skin; ph.dt = p->dt;
+    for (int a = 0; a < 3; a++) ph.g[a] = p->g[a];
+    ph.ergun_printed = p->ergun_printed; ph.drag_on = p->drag_on;
+    ph.n_beds = p->n_beds; ph.n_ores = p->n_ores; ph.max_nbr = p->max_nbr;
+    // beds
+    long goff = 0, doff = 0, items_total = 0;
+    for (int b = 0; b < p->n_beds; b++) {
+      const dem_bed &B = hbeds[b];
+      BedDev d{};
+      for (int a = 0; a < 3; a++) {
+        d.lo[a] = B.lo[a]; d.hi[a] = B.hi[a]; d.origin[a] = B.origin[a];
+        d.n[a] = B.n[a]; d.nd[a] = B.n[a] * B.refine;
+      }
+      d.R = B.R;
+      d.cx = 0.5 * (B.lo[0] + B.hi[0]);
+      d.cy = 0.5 * (B.lo[1] + B.hi[1]);
+      d.h = B.h;
+      d.hd = B.h / B.refine;
+      d.refine = B.refine;
+      d.wall_kind = B.wall_kind;
+      d.n_walls = B.wall_kind == DEM_WALL_BOX ? 6 : 3;
+      d.gas_off = (int)goff;
+      d.dem_off = (int)doff;
+      d.n_gas = B.n[0] * B.n[1] * B.n[2];
+      d.n_dem = d.nd[0] * d.nd[1] * d.nd[2];
+      for (int q = 0; q < 6; q++) d.theta[q] = B.theta[q];
+      d.mu_override = B.mu_override;
+      goff += d.n_gas;
+      doff += d.n_dem;
+      items_total += (long)d.nd[1] * d.nd[2] * ((d.nd[0] + kItemX - 1) / kItemX);
+      hbd.push_back(d);
+    }
+    if (goff > (1L << 30) || doff > (1L << 30) || items_total > (1L << 30))
+      return fail(DEMRX_EINVAL, "grid too large");
+    n_gas = (int)goff;
+    n_keys = (int)doff;
+    n_items = (int)items_total;
+    std::vector<OreDev> hod;
+    for (auto &o : hores) hod.push_back(make_ore(o));
+    std::vector<int32_t> hcb(n_gas);
+    std::vector<Item> hit;
+    hit.reserve(n_items);
+    for (int b = 0; b < p->n_beds; b++) {
+      const BedDev &d = hbd[b];
+      for (int c = 0; c < d.n_gas; c++) hcb[d.gas_off + c] = b;
+      for (int iz = 0; iz < d.nd[2]; iz++)
+        for (int iy = 0; iy < d.nd[1]; iy++)
+          for (int x0 = 0; x0 < d.nd[0]; x0 += kItemX) hit.push_back(Item{b, x0, iy, iz});
+    }
+    TRY(dalloc(beds, hbd.size()));
+    TRY(dalloc(ores, hod.size()));
+    TRY(dalloc(cell_bed, n_gas));
+    TRY(dalloc(items, n_items));
+    for (int k = 0; k < 2; k++) {
+      TRY(alloc_dyn(dyn[k]));
+      TRY(alloc_props(pr[k]));
+      TRY(alloc_nbr(nb[k]));
+    }
+    TRY(dalloc(key, n)); TRY(dalloc(slot, n)); TRY(dalloc(perm, n));
+    TRY(dalloc(count, (size_t)n_keys + 1)); TRY(dalloc(start, (size_t)n_keys + 1));
+    const long scr = std::max(scan_scratch_ints((long)n_keys + 1), scan_scratch_ints((long)n_items + 1));
+    TRY(dalloc(scan_scr, scr));
+    TRY(dalloc(iflags, (size_t)n_items + 1)); TRY(dalloc(ioffs, (size_t)n_items + 1));
+    TRY(dalloc(ilist, n_items)); TRY(dalloc(icount, 1));
+    TRY(dalloc(gtab, (size_t)n_gas * kGasRow));
+    TRY(dalloc(eps, n_gas));
+    TRY(dalloc(pm, (size_t)4 * n)); TRY(dalloc(pw, (size_t)2 * n));
+    TRY(dalloc(bed_fov_d, p->n_beds)); TRY(dalloc(theta_d, 6));
+    TRY(dalloc(status, 1)); TRY(dalloc(vmax, 2)); TRY(dalloc(disp, 1)); TRY(dalloc(counters, 4));
+    HIPCHK(hipMemcpyAsync(beds, hbd.data(), hbd.size() * sizeof(BedDev), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ores, hod.data(), hod.size() * sizeof(OreDev), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(cell_bed, hcb.data(), hcb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(items, hit.data(), hit.size() * sizeof(Item), hipMemcpyHostToDevice, st));
+    for (int k = 0; k < 2; k++) {
+      launch_fill_u32((uint32_t *)nb[k].mask, 0u, 2L * n, st);
+      launch_fill_i32(nb[k].cnt, 0, n, st);
+    }
+    launch_fill_u32(status, 0u, 1, st);
+    launch_fill_u32(vmax, 0u, 2, st);
+    launch_fill_u32((uint32_t *)disp, 0u, 2, st);
+    launch_fill_u32((uint32_t *)counters, 0u, 8, st);
+    launch_init<T>(*in, n, ph, p->n_ores, dyn[0], pr[0], status, st);
+    HIPCHK(hipGetLastError());
+    // largest parcel per bed against the DEM cell (checked on the host once)
+    {
+      std::vector<float> hd(n);
+      std::vector<int32_t> hb(n);
+      HIPCHK(hipMemcpyAsync(hd.data(), in->d, n * sizeof(float), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hb.data(), in->bed, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      std::vector<double> dmax(p->n_beds, 0.0);
+      for (int i = 0; i < n; i++)
+        if (hb[i] >= 0 && hb[i] < p->n_beds) dmax[hb[i]] = std::max(dmax[hb[i]], (double)hd[i]);
+      for (int b = 0; b < p->n_beds; b++)
+        if (hbd[b].hd < dmax[b] + p->skin)
+          return fail(DEMRX_EINVAL, "bed " + std::to_string(b) + ": DEM cell " + std::to_string(hbd[b].hd) +
+                                        " m is smaller than the largest parcel plus skin (" +
+                                        std::to_string(dmax[b] + p->skin) + " m)");
+    }
+    TRY(check_status());
+    TRY(rebuild());
+    DepositOut o{};
+    o.eps_ctx = eps;
+    launch_deposit<T>(dyn[cur], pr[pc], GasArgs{}, start, cell_bed, beds, ph, n_gas, false, o, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return check_status();
+  }
+
+  int check_status() {
+    uint32_t h = 0;
+    HIPCHK(hipMemcpy(&h, status, sizeof h, hipMemcpyDeviceToHost));
+    if (h) {
+      launch_fill_u32(status, 0u, 1, st);
+      return fail(status_code(h), status_text(h));
+    }
+    return DEMRX_OK;
+  }
+
+  int sync() override {
+    HIPCHK(hipStreamSynchronize(st));
+    return check_status();
+  }
+
+  int rebuild() {
+    launch_fill_i32(count, 0, (long)n_keys + 1, st);
+    launch_bin<T>(dyn[cur], pr[pc], beds, n, key, slot, count, status, st);
+    launch_scan(count, start, (long)n_keys + 1, scan_scr, st);
+    launch_scatter(key, slot, start, n, perm, st);
+    launch_cellsort(start, n_keys, pr[pc].id, perm, st);
+    launch_permute<T>(perm, n, dyn[cur], pr[pc], dyn[cur ^ 1], pr[pc ^ 1], vmax, disp, st);
+    cur ^= 1;
+    pc ^= 1;
+    launch_items(items, n_items, beds, start, iflags, ioffs, scan_scr, ilist, icount, st);
+    NbrBuild<T> a;
+    a.d = dyn[cur];
+    a.p = pr[pc];
+    a.id_old = pr[pc ^ 1].id;
+    a.perm = perm;
+    a.nb_new = nb[nbc ^ 1];
+    a.nb_old = nb[nbc];
+    a.beds = beds;
+    a.start = start;
+    a.items = items;
+    a.list = ilist;
+    a.list_count = icount;
+    a.n = n;
+    a.cap = P.max_nbr;
+    a.skin = P.skin;
+    a.status = status;
+    launch_build_nbr<T>(a, std::max(1, std::min(n_items, build_grid)), st);
+    nbc ^= 1;
+    HIPCHK(hipGetLastError());
+    steps_since = 0;
+    rebuilds++;
+    built = true;
+    return DEMRX_OK;
+  }
+
+  int gas_table(const dem_gas *g) {
+    launch_gas_table<T>(gas_args(g), eps, cell_bed, beds, n_gas, gtab, status, st);
+    HIPCHK(hipGetLastError());
+    return DEMRX_OK;
+  }
+
+  StepArgs<T> step_args(int mode) {
+    StepArgs<T> a;
+    a.in = dyn[cur];
+    a.out = dyn[cur ^ 1];
+    a.pr = pr[pc];
+    a.nb = nb[nbc];
+    a.gtab = gtab;
+    a.beds = beds;
+    a.ph = ph;
+    a.status = status;
+    a.vmax = vmax;
+    a.disp = disp;
+    a.counters = counters;
+    a.n = n;
+    a.par = (int)(step_count & 1);
+    a.mode = mode;
+    a.Fout = a.Tout = nullptr;
+    return a;
+  }
+
+  int new_event(hipEvent_t &e) {
+    HIPCHK(hipEventCreate(&e));
+    ev_pool.push_back(e);
+    return DEMRX_OK;
+  }
+
+  int profile(int enable) override {
+    prof = enable != 0;
+    prof_eager.clear();
+    prof_graph.clear();
+    return DEMRX_OK;
+  }
+
+  int step_one() {
+    if (!built || steps_since >= P.rebuild_every) TRY(rebuild());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof) {
+      auto &lst = capturing ? prof_capture : prof_eager;
+      if (!capturing && lst.size() >= 65536) return fail(DEMRX_EINVAL, "profile buffer full; call dem_get_stats");
+      TRY(new_event(e0));
+      TRY(new_event(e1));
+      HIPCHK(hipEventRecord(e0, st));
+      lst.emplace_back(e0, e1);
+    }
+    launch_step<T>(step_args(0), step_block, st);
+    HIPCHK(hipGetLastError());
+    if (prof) HIPCHK(hipEventRecord(e1, st));
+    cur ^= 1;
+    step_count++;
+    steps_since++;
+    return DEMRX_OK;
+  }
+
+  int step(int ns, const dem_gas *g) override {
+    if (ns < 0) return fail(DEMRX_EINVAL, "n_steps < 0");
+    if (!gas_ok(g)) return fail(DEMRX_EINVAL, "null gas field");
+    if (ns == 0) return DEMRX_OK;
+    TRY(gas_table(g));
+    for (int s = 0; s < ns; s++) {
+      if (s == ns - 1) launch_fill_u32((uint32_t *)counters, 0u, 4, st);
+      TRY(step_one());
+    }
+    return DEMRX_OK;
+  }
+
+  int ensure_sorted() {
+    if (!built || steps_since > 0) TRY(rebuild());
+    return DEMRX_OK;
+  }
+
+  int couple(const dem_gas *g, dem_sources *o) override {
+    if (!gas_ok(g)) return fail(DEMRX_EINVAL, "null gas field");
+    TRY(ensure_sorted());
+    DepositOut d{};
+    d.eps_ctx = eps;
+    bool sums = false;
+    if (o) {
+      d.eps = o->eps; d.np = o->np; d.sumK = o->sumK; d.sumKu = o->sumKu; d.sumKv = o->sumKv;
+      d.sumKw = o->sumKw; d.sumKs = o->sumKs;
+      sums = o->sumK || o->sumKu || o->sumKv || o->sumKw || o->sumKs;
+    }
+    launch_deposit<T>(dyn[cur], pr[pc], gas_args(g), start, cell_bed, beds, ph, n_gas, sums, d, st);
+    HIPCHK(hipGetLastError());
+    return DEMRX_OK;
+  }
+
+  int react_core(double dt, const dem_gas *g, dem_sources *o, double *fov, bool bed_sum, int update_mass,
+                 const double *theta_dev) {
+    TRY(ensure_sorted());
+    ReactArgs<T> a;
+    a.d = dyn[cur];
+    a.p = pr[pc];
+    a.g = gas_args(g);
+    a.eps = eps;
+    a.beds = beds;
+    a.ores = ores;
+    a.theta = theta_dev;
+    a.dt = dt;
+    a.n = n;
+    a.update_mass = update_mass;
+    a.pm = pm;
+    a.pw = pw;
+    a.fov = fov;
+    a.clamps = counters + 2;
+    a.status = status;
+    launch_react<T>(a, st);
+    if (o && (o->mdotH2 || o->mdotH2O || o->sumEQ || o->sumES))
+      launch_cellsum(pm, n, start, cell_bed, beds, n_gas, o->mdotH2, o->mdotH2O, o->sumEQ, o->sumES, st);
+    if (bed_sum) launch_bedsum(pw, n, start, beds, P.n_beds, bed_fov_d, st);
+    HIPCHK(hipGetLastError());
+    return DEMRX_OK;
+  }
+
+  int react(double dt, const dem_gas *g, dem_sources *o, double *bed_fov, double *fov) override {
+    if (!(dt > 0.0)) return fail(DEMRX_EINVAL, "dt_cfd must be positive");
+    if (!gas_ok(g)) return fail(DEMRX_EINVAL, "null gas field");
+    TRY(react_core(dt, g, o, fov, bed_fov != nullptr, 1, nullptr));
+    if (bed_fov) {
+      HIPCHK(hipMemcpyAsync(bed_fov, bed_fov_d, P.n_beds * sizeof(double), hipMemcpyDeviceToHost, st));
+      return sync();
+    }
+    return DEMRX_OK;
+  }
+
+  int forces(const dem_gas *g, double *F, double *Tq) override {
+    if (!gas_ok(g) || !F || !Tq) return fail(DEMRX_EINVAL, "null argument");
+    if (!built || steps_since >= P.rebuild_every) TRY(rebuild());
+    TRY(gas_table(g));
+    StepArgs<T> a = step_args(1);
+    a.Fout = F;
+    a.Tout = Tq;
+    launch_step<T>(a, step_block, st);
+    HIPCHK(hipGetLastError());
+    return DEMRX_OK;
+  }
+
+  int get_state(dem_parcels *o) override {
+    if (!o) return fail(DEMRX_EINVAL, "null output");
+    launch_export<T>(dyn[cur], pr[pc], n, *o, st);
+    HIPCHK(hipGetLastError());
+    return sync();
+  }
+
+  int set_state(const dem_parcels *in) override {
+    if (!in || !in->x || !in->y || !in->z || !in->vx || !in->vy || !in->vz || !in->wx || !in->wy || !in->wz ||
+        !in->nh || !in->nm || !in->nw || !in->nfe)
+      return fail(DEMRX_EINVAL, "null parcel array");
+    launch_import<T>(*in, n, dyn[cur], pr[pc], st);
+    for (int k = 0; k < 2; k++) launch_fill_u32((uint32_t *)nb[k].mask, 0u, 2L * n, st);
+    built = false;
+    TRY(rebuild());
+    DepositOut o{};
+    o.eps_ctx = eps;
+    launch_deposit<T>(dyn[cur], pr[pc], GasArgs{}, start, cell_bed, beds, ph, n_gas, false, o, st);
+    HIPCHK(hipGetLastError());
+    return sync();
+  }
+
+  int pairs(uint32_t *ij, int64_t cap, int64_t *np) override {
+    if (!np || (cap > 0 && !ij) || cap < 0) return fail(DEMRX_EINVAL, "bad pair buffer");
+    TRY(ensure_sorted());
+    for (int attempt = 0; attempt < 2; attempt++) {
+      if (!pairs_buf) {
+        pairs_cap = std::max<long>(1024, (long)n * 4);
+        TRY(dalloc(pairs_buf, 2 * (size_t)pairs_cap));
+      }
+      launch_fill_u32((uint32_t *)(counters + 3), 0u, 2, st);
+      launch_pairs<T>(dyn[cur], pr[pc], nb[nbc], n, pairs_buf, pairs_cap, counters + 3, st);
+      HIPCHK(hipGetLastError());
+      unsigned long long c = 0;
+      HIPCHK(hipMemcpyAsync(&c, counters + 3, sizeof c, hipMemcpyDeviceToHost, st));
+      TRY(sync());
+      if ((long)c > pairs_cap) {
+        pairs_cap = (long)c;
+        TRY(dalloc(pairs_buf, 2 * (size_t)pairs_cap));
+        continue;
+      }
+      std::vector<uint32_t> h(2 * c);
+      if (c) HIPCHK(hipMemcpy(h.data(), pairs_buf, 2 * c * sizeof(uint32_t), hipMemcpyDeviceToHost));
+      std::vector<uint64_t> k(c);
+      for (size_t q = 0; q < c; q++) k[q] = ((uint64_t)h[2 * q] << 32) | h[2 * q + 1];
+      std::sort(k.begin(), k.end());
+      for (size_t q = 0; q < c && (int64_t)q < cap; q++) {
+        ij[2 * q] = (uint32_t)(k[q] >> 32);
+        ij[2 * q + 1] = (uint32_t)(k[q] & 0xffffffffu);
+      }
+      *np = (int64_t)c;
+      return DEMRX_OK;
+    }
+    return fail(DEMRX_EHIP, "pair buffer growth failed");
+  }
+
+  int stats(dem_stats *o) override {
+    if (!o) return fail(DEMRX_EINVAL, "null output");
+    unsigned long long c[4];
+    HIPCHK(hipMemcpyAsync(c, counters, sizeof c, hipMemcpyDeviceToHost, st));
+    int r = sync();
+    o->n_parcels = n;
+    o->n_contacts = (int64_t)(c[0] / 2);
+    o->n_wall_contacts = (int64_t)c[1];
+    o->rebuilds = rebuilds;
+    o->steps = step_count;
+    o->clamps = (int64_t)c[2];
+    o->mean_coordination = n ? (double)c[0] / n : 0.0;
+    o->max_nbr_used = P.max_nbr;
+    o->status = 0;
+    double tot = 0.0;
+    long cnt = 0;
+    for (auto *lst : {&prof_eager, &prof_graph}) {
+      for (auto &pr_ : *lst) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, pr_.first, pr_.second) == hipSuccess) {
+          tot += ms;
+          cnt++;
+        } else {
+          (void)hipGetLastError();
+        }
+      }
+    }
+    o->step_kernel_ms = cnt ? tot / cnt : 0.0;
+    o->step_kernel_launches = cnt;
+    return r;
+  }
+
+  // one coupling interval of the hot path
+  int interval(int S, const dem_gas *g, dem_sources *o) {
+    TRY(gas_table(g));
+    for (int s = 0; s < S; s++) {
+      if (s == S - 1) launch_fill_u32((uint32_t *)counters, 0u, 4, st);  // contact counts of the last step
+      TRY(step_one());
+    }
+    TRY(couple(g, o));
+    TRY(react_core(S * P.dt, g, o, nullptr, true, 1, nullptr));
+    return DEMRX_OK;
+  }
+
+  int run(int n_int, int S, const dem_gas *g, dem_sources *o, double *bed_fov) override {
+    if (n_int < 0 || S < 1) return fail(DEMRX_EINVAL, "bad interval count");
+    if (!gas_ok(g)) return fail(DEMRX_EINVAL, "null gas field");
+    if (n_int == 0) return DEMRX_OK;
+    TRY(ensure_sorted());
+    std::vector<const void *> k = {(const void *)(intptr_t)S, g->ug, g->vg, g->wg, g->p, g->dpdx, g->dpdy,
+                                   g->dpdz, g->T, g->xH2, g->xH2O, g->xN2};
+    dem_sources oo{};
+    if (o) oo = *o;
+    for (double *q : {oo.eps, oo.np, oo.sumK, oo.sumKu, oo.sumKv, oo.sumKw, oo.sumKs, oo.mdotH2, oo.mdotH2O,
+                      oo.sumEQ, oo.sumES})
+      k.push_back(q);
+    k.push_back((const void *)(intptr_t)step_block);
+    if (!cap_st) {
+      HIPCHK(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&ev_a, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&ev_b, hipEventDisableTiming));
+    }
+    HIPCHK(hipEventRecord(ev_a, user_st));
+    HIPCHK(hipStreamWaitEvent(cap_st, ev_a, 0));
+    st = cap_st;
+    int r = run_on_cap(n_int, S, g, o ? &oo : nullptr, k);
+    st = user_st;
+    if (r != DEMRX_OK) return r;
+    HIPCHK(hipEventRecord(ev_b, cap_st));
+    HIPCHK(hipStreamWaitEvent(user_st, ev_b, 0));
+    if (bed_fov) {
+      HIPCHK(hipMemcpyAsync(bed_fov, bed_fov_d, P.n_beds * sizeof(double), hipMemcpyDeviceToHost, st));
+      return sync();
+    }
+    return DEMRX_OK;
+  }
+
+  int run_on_cap(int n_int, int S, const dem_gas *g, dem_sources *o, const std::vector<const void *> &k) {
+    // two intervals return every buffer parity to its starting value, so a
+    // graph of two intervals can be replayed as is
+    if (!gexec || k != gkey) {
+      if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
+      if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+      const int s_cur = cur, s_pc = pc, s_nbc = nbc;
+      const long s_sc = step_count, s_ss = steps_since, s_rb = rebuilds;
+      HIPCHK(hipStreamBeginCapture(cap_st, hipStreamCaptureModeRelaxed));
+      capturing = true;
+      prof_capture.clear();
+      int r = interval(S, g, o);
+      if (r == DEMRX_OK) r = interval(S, g, o);
+      capturing = false;
+      hipGraph_t gr = nullptr;
+      hipError_t e = hipStreamEndCapture(cap_st, &gr);
+      if (r != DEMRX_OK) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return r;
+      }
+      if (e != hipSuccess) return fail(DEMRX_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+      if (cur != s_cur || pc != s_pc || nbc != s_nbc || ((step_count ^ s_sc) & 1))
+        return fail(DEMRX_EHIP, "graph interval does not restore buffer parity");
+      graph = gr;
+      HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+      gkey = k;
+      gprof = prof;
+      rebuilds_per_pair = rebuilds - s_rb;
+      cur = s_cur; pc = s_pc; nbc = s_nbc;
+      step_count = s_sc; steps_since = s_ss; rebuilds = s_rb;
+    }
+    if (gprof != prof) {  // recapture with or without timing events
+      gkey.clear();
+      return run_on_cap(n_int, S, g, o, k);
+    }
+    if (prof && n_int >= 2) prof_graph = prof_capture;
+    for (int q = 0; q < n_int / 2; q++) {
+      HIPCHK(hipGraphLaunch(gexec, cap_st));
+      step_count += 2L * S;
+      rebuilds += rebuilds_per_pair;
+    }
+    steps_since = 0;
+    if (n_int & 1) TRY(interval(S, g, o));
+    return DEMRX_OK;
+  }
+  long rebuilds_per_pair = 0;
+  bool gprof = false;
+
+  int autotune(const dem_gas *g) override {
+    if (!gas_ok(g)) return fail(DEMRX_EINVAL, "null gas field");
+    TRY(ensure_sorted());
+    TRY(gas_table(g));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_b = step_block;
+    for (int b : {64, 128, 256, 512}) {
+      float tot = 0.0f;
+      for (int rep = 0; rep < 4; rep++) {
+        HIPCHK(hipEventRecord(e0, st));
+        launch_step<T>(step_args(2), b, st);
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (rep) tot += ms;
+      }
+      if (tot < best) { best = tot; best_b = b; }
+    }
+    step_block = best_b;
+    // neighbour build: persistent grid size
+    best = 1e30f;
+    int best_g = build_grid;
+    for (int gsz : {512, 1024, 2048, 4096, 8192}) {
+      build_grid = gsz;
+      float tot = 0.0f;
+      for (int rep = 0; rep < 3; rep++) {
+        HIPCHK(hipEventRecord(e0, st));
+        TRY(rebuild());
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (rep) tot += ms;
+      }
+      if (tot < best) { best = tot; best_g = gsz; }
+    }
+    build_grid = best_g;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; gkey.clear(); }
+    return sync();
+  }
+
+  int grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, double *J, double *gr) override;
+};
+
+#include "grad_impl.h"
+
+// ------------------------------------------------------------------ C entry points
+static int validate(const dem_params *p, const dem_parcels *in, int32_t n, std::string &m) {
+  if (!p || !in) { m = "null params or parcels"; return DEMRX_EINVAL; }
+  if (n <= 0) { m = "n_parcels must be positive"; return DEMRX_EINVAL; }
+  if (p->precision != DEM_FP64 && p->precision != DEM_MIXED) { m = "unknown precision"; return DEMRX_EINVAL; }
+  if (p->n_beds < 1 || p->n_beds > DEM_MAX_BEDS || !p->beds) { m = "bad n_beds/beds"; return DEMRX_EINVAL; }
+  if (p->n_ores < 1 || p->n_ores > DEM_MAX_ORES || !p->ores) { m = "bad n_ores/ores"; return DEMRX_EINVAL; }
+  if (!(p->kn > 0) || !(p->e_p > 0 && p->e_p <= 1) || !(p->mu_s >= 0) || !(p->mu_r >= 0) ||
+      !(p->kt_over_kn > 0) || !(p->gt_over_gn >= 0) || !(p->eps_min > 0 && p->eps_min <= 1) ||
+      !(p->skin >= 0) || !(p->dt > 0) || !std::isfinite(p->g[0] + p->g[1] + p->g[2])) {
+    m = "bad physical parameter";
+    return DEMRX_EINVAL;
+  }
+  if (p->max_nbr < 1 || p->max_nbr > DEM_MAX_NBR || p->rebuild_every < 1) { m = "bad max_nbr/rebuild_every"; return DEMRX_EINVAL; }
+  for (int b = 0; b < p->n_beds; b++) {
+    const dem_bed &B = p->beds[b];
+    if (B.wall_kind != DEM_WALL_BOX && B.wall_kind != DEM_WALL_CYL) { m = "bad wall kind"; return DEMRX_EINVAL; }
+    if (!(B.h > 0) || B.n[0] < 1 || B.n[1] < 1 || B.n[2] < 1 || B.refine < 1 || B.refine > 4) {
+      m = "bad grid of bed " + std::to_string(b);
+      return DEMRX_EINVAL;
+    }
+    for (int a = 0; a < 3; a++)
+      if (!(B.lo[a] < B.hi[a]) || B.origin[a] > B.lo[a] + 1e-12 || B.origin[a] + B.n[a] * B.h < B.hi[a] - 1e-12) {
+        m = "grid of bed " + std::to_string(b) + " does not contain its walls";
+        return DEMRX_EINVAL;
+      }
+    if (B.wall_kind == DEM_WALL_CYL &&
+        !(B.R > 0 && 2 * B.R <= (B.hi[0] - B.lo[0]) + 1e-12 && 2 * B.R <= (B.hi[1] - B.lo[1]) + 1e-12)) {
+      m = "cylinder radius of bed " + std::to_string(b) + " does not fit its bounding box";
+      return DEMRX_EINVAL;
+    }
+  }
+  for (int o = 0; o < p->n_ores; o++) {
+    const dem_ore &O = p->ores[o];
+    if (!(O.xi0 >= 0 && O.xi0 < 1) || !(O.d_pore_cm > 0) || !(O.tau > 0) || (O.kind != 0 && O.kind != 1)) {
+      m = "bad ore " + std::to_string(o);
+      return DEMRX_EINVAL;
+    }
+  }
+  if (!in->x || !in->y || !in->z || !in->vx || !in->vy || !in->vz || !in->wx || !in->wy || !in->wz || !in->d ||
+      !in->k || !in->ore || !in->bed || !in->nh || !in->nm || !in->nw || !in->nfe) {
+    m = "null parcel array";
+    return DEMRX_EINVAL;
+  }
+  return DEMRX_OK;
+}
+
+static thread_local std::string g_init_err;
+
+extern "C" {
+
+int dem_init(const dem_params *p, const dem_parcels *in, int32_t n, void *stream, dem_ctx **out) {
+  if (!out) return DEMRX_EINVAL;
+  *out = nullptr;
+  std::string m;
+  int r = validate(p, in, n, m);
+  if (r != DEMRX_OK) {
+    g_init_err = m;
+    return r;
+  }
+  dem_ctx *c = nullptr;
+  if (p->precision == DEM_MIXED) {
+    auto *q = new Ctx<float>();
+    r = q->init(p, in, n, (hipStream_t)stream);
+    c = q;
+  } else {
+    auto *q = new Ctx<double>();
+    r = q->init(p, in, n, (hipStream_t)stream);
+    c = q;
+  }
+  if (r != DEMRX_OK) {
+    g_init_err = c->err;
+    delete c;
+    return r;
+  }
+  *out = c;
+  return DEMRX_OK;
+}
+
+int dem_step(dem_ctx *c, int32_t n, const dem_gas *g) { return c ? c->step(n, g) : DEMRX_EINVAL; }
+int dem_couple(dem_ctx *c, const dem_gas *g, dem_sources *o) { return c ? c->couple(g, o) : DEMRX_EINVAL; }
+int dem_react(dem_ctx *c, double dt, const dem_gas *g, dem_sources *o, double *bed_fov, double *fov) {
+  return c ? c->react(dt, g, o, bed_fov, fov) : DEMRX_EINVAL;
+}
+int dem_grad(dem_ctx *c, const dem_grad_spec *s, const dem_gas *g, const double theta[6], double *J, double *grad) {
+  return c ? c->grad(s, g, theta, J, grad) : DEMRX_EINVAL;
+}
+int dem_forces(dem_ctx *c, const dem_gas *g, double *F, double *T) { return c ? c->forces(g, F, T) : DEMRX_EINVAL; }
+int dem_get_state(dem_ctx *c, dem_parcels *o) { return c ? c->get_state(o) : DEMRX_EINVAL; }
+int dem_set_state(dem_ctx *c, const dem_parcels *in) { return c ? c->set_state(in) : DEMRX_EINVAL; }
+int dem_pairs(dem_ctx *c, uint32_t *ij, int64_t cap, int64_t *np) { return c ? c->pairs(ij, cap, np) : DEMRX_EINVAL; }
+int dem_get_stats(dem_ctx *c, dem_stats *o) { return c ? c->stats(o) : DEMRX_EINVAL; }
+int dem_run(dem_ctx *c, int32_t n_int, int32_t S, const dem_gas *g, dem_sources *o, double *bed_fov) {
+  return c ? c->run(n_int, S, g, o, bed_fov) : DEMRX_EINVAL;
+}
+int dem_autotune(dem_ctx *c, const dem_gas *g) { return c ? c->autotune(g) : DEMRX_EINVAL; }
+int dem_profile(dem_ctx *c, int32_t enable) { return c ? c->profile(enable) : DEMRX_EINVAL; }
+int dem_sync(dem_ctx *c) { return c ? c->sync() : DEMRX_EINVAL; }
+const char *dem_last_error(const dem_ctx *c) { return c ? c->err.c_str() : g_init_err.c_str(); }
+void dem_destroy(dem_ctx *c) { delete c; }
+
+}  // extern "C"

@@ -1,0 +1,173 @@
+// Device-side types and helpers shared by the demrx kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/demrx.h"
+
+namespace demrx {
+
+constexpr int kMaxNbr = DEM_MAX_NBR;  // neighbour slots per parcel; mask bits 0..47
+constexpr int kWallBit = 48;          // mask bits 48..53: walls
+constexpr int kMaxWalls = 6;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kRg = 8.314;  // J/(mol K), Section 2.1
+
+enum : uint32_t { ST_OVERFLOW = 1u, ST_DOMAIN = 2u, ST_NONFINITE = 4u, ST_SKIN = 8u };
+
+// One bed as the kernels see it.
+struct BedDev {
+  double lo[3], hi[3];
+  double R, cx, cy;
+  double origin[3];
+  double h, hd;          // gas cell edge, DEM cell edge (h / refine)
+  int n[3], nd[3];       // gas cells, DEM cells per axis
+  int refine, wall_kind, n_walls;
+  int gas_off, dem_off;  // first gas cell, first DEM cell key of the bed
+  int n_gas, n_dem;
+  double theta[6];
+  double mu_override;
+};
+
+// Per-ore constants: porosities of the Fe3O4, FeO, Fe layers (eqs. e2-31..e2-36)
+struct OreDev {
+  double xi_layer[3];
+  double d_pore_cm, tau;
+  int kind;
+};
+
+struct Phys {
+  double kn, e_p, mu_s, mu_r, kt, gt_ratio, eps_min, skin, dt;
+  double g[3];
+  int ergun_printed, drag_on, n_beds, n_ores, max_nbr;
+};
+
+// Double-buffered dynamic state (swapped every step)
+template <typename T>
+struct Dyn {
+  double *x, *y, *z;
+  T *vx, *vy, *vz, *wx, *wy, *wz;
+};
+
+// Per-parcel properties, permuted with the parcels at every rebuild
+template <typename T>
+struct Props {
+  float *rad, *kcg;
+  T *mass, *zeta;
+  int32_t *tag;  // bed * 256 + ore
+  uint32_t *id;  // original parcel id
+  double *nh, *nm, *nw, *nfe;
+  T *wh;         // wall tangential springs: [(wall * 3 + axis) * N + i]
+};
+
+// Neighbour list (slot-major) with the pair tangential springs of each slot
+template <typename T>
+struct Nbr {
+  int32_t *cnt;
+  int32_t *idx;    // [slot * N + i] sorted index of the partner
+  T *hist;         // [(axis * kMaxNbr + slot) * N + i]
+  uint64_t *mask;  // bit s: slot s in contact last step; bits 48..53: walls
+};
+
+__device__ __forceinline__ int bed_of(int32_t tag) { return tag >> 8; }
+__device__ __forceinline__ int ore_of(int32_t tag) { return tag & 255; }
+
+// Exact contact predicate terms, evaluated without contraction so that the
+// result equals the FP64 reference bit for bit.
+__device__ __forceinline__ double dist2_exact(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+  return (dx * dx + dy * dy) + dz * dz;
+}
+__device__ __forceinline__ double sq_exact(double s) {
+#pragma clang fp contract(off)
+  return s * s;
+}
+
+// Gas cell (nearest grid point) and nested DEM cell of a position.
+// Returns false if the position lies outside the bed's grid (then clamped).
+struct Cells {
+  int gas, dem;  // global indices
+  int d[3];      // DEM cell coordinates within the bed
+};
+__device__ __forceinline__ bool locate(const BedDev &b, double x, double y, double z, Cells &c) {
+  const double p[3] = {x, y, z};
+  bool inside = true;
+  int g[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    double rel = p[a] - b.origin[a];
+    double f = floor(rel / b.h);
+    if (!(f >= 0.0)) { f = 0.0; inside = false; }
+    if (f > b.n[a] - 1) { f = b.n[a] - 1; inside = false; }
+    g[a] = (int)f;
+    int s = 0;
+    if (b.refine > 1) {
+      double fs = floor((rel - g[a] * b.h) / b.hd);
+      s = fs < 0.0 ? 0 : (fs > b.refine - 1 ? b.refine - 1 : (int)fs);
+    }
+    c.d[a] = g[a] * b.refine + s;
+  }
+  c.gas = b.gas_off + g[0] + b.n[0] * (g[1] + b.n[1] * g[2]);
+  c.dem = b.dem_off + c.d[0] + b.nd[0] * (c.d[1] + b.nd[1] * c.d[2]);
+  return inside;
+}
+
+// Wall w of a bed: signed clearance of the point from the wall surface and the
+// unit vector from the point towards the wall.
+__device__ __forceinline__ double wall_clearance(const BedDev &b, int w, double x, double y, double z,
+                                                 double nv[3]) {
+  nv[0] = nv[1] = nv[2] = 0.0;
+  if (b.wall_kind == DEM_WALL_BOX) {
+    const int ax = w >> 1;
+    const double p = ax == 0 ? x : (ax == 1 ? y : z);
+    if ((w & 1) == 0) { nv[ax] = -1.0; return p - b.lo[ax]; }
+    nv[ax] = 1.0;
+    return b.hi[ax] - p;
+  }
+  if (w == 0) {
+    const double rx = x - b.cx, ry = y - b.cy;
+    const double rho = sqrt(rx * rx + ry * ry);
+    if (rho <= 0.0) return b.R;
+    nv[0] = rx / rho;
+    nv[1] = ry / rho;
+    return b.R - rho;
+  }
+  if (w == 1) { nv[2] = -1.0; return z - b.lo[2]; }
+  nv[2] = 1.0;
+  return b.hi[2] - z;
+}
+
+template <typename T>
+__device__ __forceinline__ T tsqrt(T a);
+template <>
+__device__ __forceinline__ float tsqrt<float>(float a) { return sqrtf(a); }
+template <>
+__device__ __forceinline__ double tsqrt<double>(double a) { return sqrt(a); }
+template <typename T>
+__device__ __forceinline__ T tpow(T a, T e);
+template <>
+__device__ __forceinline__ float tpow<float>(float a, float e) { return powf(a, e); }
+template <>
+__device__ __forceinline__ double tpow<double>(double a, double e) { return pow(a, e); }
+
+// Gidaspow drag coefficient divided by eps_p = 1 - eps_g (eq. e3-5-1), so
+// that F_d = (beta/eps_p) V (u_g - v) (eq. e3-5) is finite at eps_g = 1.
+// Wen-Yu with Schiller-Naumann C_D (Re of eq. e2-23) at eps_g >= 0.8.
+template <typename T>
+__device__ __forceinline__ T beta_over_epsp(T eps, T rho, T mu, T slip, T dp, int printed) {
+  const T ep = T(1) - eps;
+  if (eps < T(0.8)) {
+    const T inertial = printed ? T(1.75) * eps * rho * slip / (dp * ep) : T(1.75) * rho * slip / dp;
+    return T(150) * ep * mu / (eps * dp * dp) + inertial;
+  }
+  const T re = rho * eps * dp * slip / mu;
+  const T cdre = re < T(1000) ? T(24) * (T(1) + T(0.15) * tpow<T>(re, T(0.687))) : T(0.44) * re;
+  return T(0.75) * cdre * mu * tpow<T>(eps, T(-2.65)) / (dp * dp);
+}
+
+// Per-gas-cell drag table row: ug vg wg eps dpdx dpdy dpdz rho mu (+pad)
+constexpr int kGasRow = 12;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+}  // namespace demrx

@@ -1,0 +1,474 @@
+// Coupling kernels: voidage/drag deposition onto the gas grid, the
+// multi-interface unreacted-shrinking-core reaction update, per-cell and
+// per-bed reductions (deterministic: fixed lane assignment and shuffle trees,
+// no floating-point atomics), and state import/export.
+#include "launch.h"
+
+namespace demrx {
+
+constexpr int kGroup = 16;  // lanes per gas cell in the segmented reductions
+
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = kGroup / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kGroup);
+  return v;
+}
+
+// DEM-cell ranges of a gas cell: refine^2 rows of `refine` consecutive keys
+struct GasCellRanges {
+  int base, f, nd0, nd1;
+  __device__ GasCellRanges(const BedDev &B, int c) {
+    const int lc = c - B.gas_off;
+    const int gx = lc % B.n[0], gy = (lc / B.n[0]) % B.n[1], gz = lc / (B.n[0] * B.n[1]);
+    f = B.refine;
+    nd0 = B.nd[0];
+    nd1 = B.nd[1];
+    base = B.dem_off + gx * f + nd0 * (gy * f + nd1 * (gz * f));
+  }
+  __device__ int row_key(int r) const {  // r in [0, f*f)
+    const int sy = r % f, sz = r / f;
+    return base + nd0 * (sy + nd1 * sz);
+  }
+};
+
+__device__ __forceinline__ void gas_props(double T, double p, double x1, double x2, double x3, double mu_fix,
+                                          double &rho, double &mu) {
+  // eq. e3-53 and eqs. e3-55/e3-56 with Table C2 (mass-weighted viscosity)
+  const double M1 = 2.016, M2 = 18.015, M3 = 28.013;
+  const double Mg = x1 * M1 + x2 * M2 + x3 * M3;
+  rho = p * (Mg * 1e-3) / (kRg * T);
+  if (mu_fix > 0.0) {
+    mu = mu_fix;
+    return;
+  }
+  const double m1 = 2.85e-6 + 2.16e-8 * T - 3.78e-12 * T * T;
+  const double m2 = -4.44e-6 + 4.52e-8 * T - 3.20e-12 * T * T;
+  const double m3 = 7.86e-6 + 3.87e-8 * T - 5.11e-12 * T * T;
+  mu = (x1 * M1 * m1 + x2 * M2 * m2 + x3 * M3 * m3) / Mg;
+}
+
+// ------------------------------------------------------------------ deposition
+template <typename T>
+__global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g, const int32_t *start,
+                                                 const int32_t *cell_bed, const BedDev *beds, Phys ph, int n_gas,
+                                                 int sums, DepositOut o) {
+  const int gc = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
+  const int sl = threadIdx.x % kGroup;
+  const bool valid = gc < n_gas;
+  const int c = valid ? gc : n_gas - 1;
+  const BedDev &B = beds[cell_bed[c]];
+  const GasCellRanges R(B, c);
+  double sv = 0.0, cnt = 0.0;
+  for (int r = 0; r < R.f * R.f; r++) {
+    const int k0 = R.row_key(r);
+    const int e = start[k0 + R.f];
+    for (int j = start[k0] + sl; j < e; j += kGroup) {
+      const double dd = 2.0 * (double)p.rad[j];
+      sv += kPi / 6.0 * dd * dd * dd;
+      cnt += 1.0;
+    }
+  }
+  sv = group_sum(sv);
+  cnt = group_sum(cnt);
+  double eps = 1.0 - sv / (B.h * B.h * B.h);
+  eps = eps < ph.eps_min ? ph.eps_min : (eps > 1.0 ? 1.0 : eps);
+  if (valid && sl == 0) {
+    o.eps_ctx[c] = eps;
+    if (o.eps) o.eps[c] = eps;
+    if (o.np) o.np[c] = cnt;
+  }
+  if (!sums) return;
+  double rho, mu;
+  gas_props(g.T[c], g.p[c], g.xH2[c], g.xH2O[c], g.xN2[c], B.mu_override, rho, mu);
+  const double ug = g.ug[c], vg = g.vg[c], wg = g.wg[c];
+  double sK = 0, sKu = 0, sKv = 0, sKw = 0, sKs = 0;
+  for (int r = 0; r < R.f * R.f; r++) {
+    const int k0 = R.row_key(r);
+    const int e = start[k0 + R.f];
+    for (int j = start[k0] + sl; j < e; j += kGroup) {
+      const double vx = (double)d.vx[j], vy = (double)d.vy[j], vz = (double)d.vz[j];
+      const double sx = ug - vx, sy = vg - vy, sz = wg - vz;
+      const double slip = sqrt(sx * sx + sy * sy + sz * sz);
+      const double dd = 2.0 * (double)p.rad[j];
+      const double V = kPi / 6.0 * dd * dd * dd;
+      const double K = beta_over_epsp<double>(eps, rho, mu, slip, dd / (double)p.kcg[j], ph.ergun_printed) * V;
+      sK += K;
+      sKu += K * vx;
+      sKv += K * vy;
+      sKw += K * vz;
+      sKs += K * slip;
+    }
+  }
+  sK = group_sum(sK);
+  sKu = group_sum(sKu);
+  sKv = group_sum(sKv);
+  sKw = group_sum(sKw);
+  sKs = group_sum(sKs);
+  if (valid && sl == 0) {
+    if (o.sumK) o.sumK[c] = sK;
+    if (o.sumKu) o.sumKu[c] = sKu;
+    if (o.sumKv) o.sumKv[c] = sKv;
+    if (o.sumKw) o.sumKw[c] = sKw;
+    if (o.sumKs) o.sumKs[c] = sKs;
+  }
+}
+
+template <typename T>
+void launch_deposit(const Dyn<T> &d, const Props<T> &p, const GasArgs &g, const int32_t *start,
+                    const int32_t *cell_bed, const BedDev *beds, const Phys &ph, int n_gas, bool sums,
+                    const DepositOut &o, hipStream_t s) {
+  const long threads = (long)n_gas * kGroup;
+  k_deposit<T><<<(int)((threads + 255) / 256), 256, 0, s>>>(d, p, g, start, cell_bed, beds, ph, n_gas, sums ? 1 : 0, o);
+}
+
+// ------------------------------------------------------------------ reaction
+// Diffusion in a porous particle (Section 2.3): Fuller binary coefficients
+// (eq. e2-26, M in g/mol), Wilke mixture coefficient of H2 (eq. e2-27; a gas
+// of pure H2 takes the H2-H2O pair), Knudsen coefficient (eq. e2-28), the
+// regime by lambda / d_a and the series combination (eq. e2-29).
+__device__ __forceinline__ double fuller(double T, double p, double Mi, double Mj, double Vi, double Vj) {
+  const double s = cbrt(Vi) + cbrt(Vj);
+  return 1e-7 * pow(T, 1.75) * sqrt(1.0 / Mi + 1.0 / Mj) / ((p / 101325.0) * s * s);
+}
+
+struct PoreDiff {
+  double Dm, D;
+};
+__device__ __forceinline__ PoreDiff pore_diffusion(double T, double p, double a, double b, double nn, double d_pore_cm) {
+  const double D_hw = fuller(T, p, 2.016, 18.015, 7.07, 12.7);
+  const double D_hn = fuller(T, p, 2.016, 28.013, 7.07, 17.9);
+  PoreDiff r;
+  r.Dm = (b + nn < 1e-12) ? D_hw : (1.0 - a) / (b / D_hw + nn / D_hn);
+  const double DK = 0.97 * (0.5 * d_pore_cm) * sqrt(T / 2.016);
+  const double ratio = a > 0.0 ? (1.013 / (p * a)) / d_pore_cm : INFINITY;
+  r.D = ratio <= 0.01 ? r.Dm : (ratio >= 10.0 ? DK : 1.0 / (1.0 / r.Dm + 1.0 / DK));
+  return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n) return;
+  const int32_t tag = a.p.tag[j];
+  const BedDev &B = a.beds[bed_of(tag)];
+  const OreDev &O = a.ores[ore_of(tag)];
+  Cells cl;
+  locate(B, a.d.x[j], a.d.y[j], a.d.z[j], cl);
+  const int c = cl.gas;
+  const double Tg = a.g.T[c], p = a.g.p[c], xa = a.g.xH2[c], xb = a.g.xH2O[c], xn = a.g.xN2[c];
+  // H2 fraction of the N2-free gas (Section 2.1)
+  const double x = xb > 0.0 ? xa / (xa + xb) : (xa > 0.0 ? 1.0 : 0.0);
+  const double *th = a.theta ? a.theta : B.theta;
+  const double RT = kRg * Tg;
+  // Table 2 equilibria (eq. e2-1-3) and Arrhenius constants (eq. e2-13)
+  const double Kc[3] = {exp(1433.4 / Tg + 9.08), exp(-7393.9 / Tg + 7.56), exp(-2023.8 / Tg + 1.24)};
+  double xeq[3], kap_kr[3];
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    xeq[q] = 1.0 / (Kc[q] + 1.0);
+    kap_kr[q] = (Kc[q] / (1.0 + Kc[q])) / exp(th[2 * q] - th[2 * q + 1] / RT);
+  }
+  const double dd = 2.0 * (double)a.p.rad[j];
+  const double kcg = (double)a.p.kcg[j];
+  const double dp = dd / kcg, rp = 0.5 * dp, Ap = kPi * dp * dp;
+  const PoreDiff Dd = pore_diffusion(Tg, p, xa, xb, xn, O.d_pore_cm);
+  double rp_over_D[3];
+#pragma unroll
+  for (int q = 0; q < 3; q++) rp_over_D[q] = rp / (Dd.D * O.xi_layer[q] / O.tau);  // eq. e2-30
+  // gas film (eqs. e2-20..e2-24, Gunn's Sherwood number)
+  double rho, mu;
+  gas_props(Tg, p, xa, xb, xn, B.mu_override, rho, mu);
+  const double eps = a.eps[c];
+  const double sx = a.g.ug[c] - (double)a.d.vx[j], sy = a.g.vg[c] - (double)a.d.vy[j], sz = a.g.wg[c] - (double)a.d.vz[j];
+  const double slip = sqrt(sx * sx + sy * sy + sz * sz);
+  const double Re = rho * eps * dp * slip / mu;
+  const double sc3 = cbrt(mu / (rho * Dd.Dm));
+  const double Sh = (7.0 - 10.0 * eps + 5.0 * eps * eps) * (1.0 + 0.7 * pow(Re, 0.2) * sc3) +
+                    (1.33 - 2.4 * eps + 1.2 * eps * eps) * pow(Re, 0.7) * sc3;
+  const double Ff = dp / (Sh * Dd.Dm);
+  // shell geometry from the remaining fractions u = 1 - f (eqs. e2-15..e2-17)
+  double n[4] = {a.p.nh[j], a.p.nm[j], a.p.nw[j], a.p.nfe[j]};
+  const double Nfe = 2.0 * n[0] + 3.0 * n[1] + n[2] + n[3];
+  const double cum[3] = {2.0 * n[0], 2.0 * n[0] + 3.0 * n[1], 2.0 * n[0] + 3.0 * n[1] + n[2]};
+  bool act[3];
+  int inner = 3;
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    act[q] = n[q] > 1e-12 * Nfe && x > xeq[q];
+    if (act[q] && inner == 3) inner = q;
+  }
+  double r[3] = {0.0, 0.0, 0.0}, Qn = 0.0, Sn = 0.0;
+  int clamps = 0;
+  if (inner < 3) {
+    // interface (eq. e2-12) and layer (eq. e2-14) resistances outside the
+    // innermost active interface; layer l spans interfaces l-1 and l, the
+    // outermost reaches the particle surface (u = 1)
+    double icbrt[3], A[3], Bl[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++) icbrt[q] = q >= inner ? 1.0 / cbrt(cum[q] / Nfe) : 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      A[q] = act[q] ? icbrt[q] * icbrt[q] * kap_kr[q] : 0.0;
+      const double outer = q < 2 ? icbrt[q + 1] : 1.0;
+      Bl[q] = q >= inner ? (icbrt[q] - outer) * rp_over_D[q] : 0.0;
+    }
+    // series/parallel reduction of the network (Figs. 2 and 4) from the
+    // innermost active interface outwards: (Phi, G) is the equilibrium
+    // potential and conductance seen looking inwards
+    double Rin = A[inner], Phi = xeq[inner];
+    for (int q = inner + 1; q < 3; q++) {
+      Rin += Bl[q - 1];
+      if (act[q]) {
+        const double g1 = 1.0 / Rin, g2 = 1.0 / A[q];
+        Phi = (Phi * g1 + xeq[q] * g2) / (g1 + g2);
+        Rin = 1.0 / (g1 + g2);
+      }
+    }
+    const double Rtot = Rin + Bl[2] + Ff;
+    const double flux = (x - Phi) / Rtot;
+    Qn = 1.0 / Rtot;
+    Sn = Phi / Rtot;
+    // walk back inwards distributing the flux over the active interfaces
+    double pot = x - flux * (Ff + Bl[2]);
+    double rest = flux;
+    for (int q = 2; q >= inner; q--) {
+      if (act[q]) {
+        r[q] = (pot - xeq[q]) / A[q];
+        rest -= r[q];
+      }
+      if (q > inner) pot -= rest * Bl[q - 1];
+    }
+  }
+  // extents per real particle (eq. e2-1 with eta_H2 = -1), irreversible and
+  // capped by the reactant present at the start of the update; Table 1 stoichiometry
+  const double cad = Ap * (p / RT) * a.dt;
+  double xi[3];
+  const double nu[3] = {3.0, 1.0, 1.0};
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    if (r[q] < 0.0) {
+      r[q] = 0.0;
+      clamps++;
+    }
+    xi[q] = fmin(r[q] * cad, n[q] / nu[q]);
+  }
+  n[0] = n[0] - 3.0 * xi[0];
+  n[1] = n[1] + 2.0 * xi[0] - xi[1];
+  n[2] = n[2] + 3.0 * xi[1] - xi[2];
+  n[3] = n[3] + xi[2];
+  a.p.nh[j] = n[0];
+  a.p.nm[j] = n[1];
+  a.p.nw[j] = n[2];
+  a.p.nfe[j] = n[3];
+  const double k3 = kcg * kcg * kcg;
+  const double xs = xi[0] + xi[1] + xi[2];
+  const long N = a.n;
+  a.pm[j] = -k3 * 2.016e-3 * xs / a.dt;           // eq. e3-52, kg/s
+  a.pm[N + j] = k3 * 18.015e-3 * xs / a.dt;       // eq. e2-25
+  const double E = -Ap / Tg;                      // eq. e4-8 with eta_H2 = -1
+  a.pm[2 * N + j] = k3 * E * Qn;
+  a.pm[3 * N + j] = k3 * E * Sn;
+  // overall reduction degree (eqs. e2-18, e2-19) from the updated remaining fractions
+  const double N2 = 2.0 * n[0] + 3.0 * n[1] + n[2] + n[3];
+  const double fh = 1.0 - 2.0 * n[0] / N2, fm = 1.0 - (2.0 * n[0] + 3.0 * n[1]) / N2,
+               fw = 1.0 - (2.0 * n[0] + 3.0 * n[1] + n[2]) / N2;
+  const double fov = O.kind == 1 ? 0.25 * fm + 0.75 * fw : fh / 9.0 + 2.0 * fm / 9.0 + 6.0 * fw / 9.0;
+  const double w = k3 * N2;
+  a.pw[j] = w * fov;
+  a.pw[N + j] = w;
+  if (a.fov) a.fov[a.p.id[j]] = fov;
+  if (a.update_mass)
+    a.p.mass[j] = T(k3 * 1e-3 * (n[0] * 159.687 + n[1] * 231.531 + n[2] * 71.844 + n[3] * 55.845));
+  if (clamps) atomicAdd(a.clamps, (unsigned long long)clamps);
+  if (!(isfinite(fov) && n[0] >= 0.0 && n[1] >= 0.0 && n[2] >= 0.0)) atomicOr(a.status, ST_NONFINITE);
+}
+
+template <typename T>
+void launch_react(const ReactArgs<T> &a, hipStream_t s) {
+  k_react<T><<<(a.n + 255) / 256, 256, 0, s>>>(a);
+}
+
+__global__ void __launch_bounds__(256) k_cellsum(const double *pm, int n, const int32_t *start, const int32_t *cell_bed,
+                                                 const BedDev *beds, int n_gas, double *o0, double *o1, double *o2,
+                                                 double *o3) {
+  const int gc = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
+  const int sl = threadIdx.x % kGroup;
+  const bool valid = gc < n_gas;
+  const int c = valid ? gc : n_gas - 1;
+  const GasCellRanges R(beds[cell_bed[c]], c);
+  double s[4] = {0, 0, 0, 0};
+  for (int r = 0; r < R.f * R.f; r++) {
+    const int k0 = R.row_key(r);
+    const int e = start[k0 + R.f];
+    for (int j = start[k0] + sl; j < e; j += kGroup) {
+#pragma unroll
+      for (int q = 0; q < 4; q++) s[q] += pm[(long)q * n + j];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; q++) s[q] = group_sum(s[q]);
+  if (valid && sl == 0) {
+    if (o0) o0[c] = s[0];
+    if (o1) o1[c] = s[1];
+    if (o2) o2[c] = s[2];
+    if (o3) o3[c] = s[3];
+  }
+}
+
+void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t *cell_bed, const BedDev *beds,
+                    int n_gas, double *o0, double *o1, double *o2, double *o3, hipStream_t s) {
+  const long threads = (long)n_gas * kGroup;
+  k_cellsum<<<(int)((threads + 255) / 256), 256, 0, s>>>(pm, n, start, cell_bed, beds, n_gas, o0, o1, o2, o3);
+}
+
+// Bed-mean f_ov weighted by k^3 N_Fe: one block per bed, strided partial sums
+// then a fixed shuffle/LDS tree.
+__global__ void __launch_bounds__(256) k_bedsum(const double *pw, int n, const int32_t *start, const BedDev *beds,
+                                                double *bed_fov) {
+  const BedDev &B = beds[blockIdx.x];
+  const int s = start[B.dem_off], e = start[B.dem_off + B.n_dem];
+  double a = 0.0, b = 0.0;
+  for (int j = s + threadIdx.x; j < e; j += blockDim.x) {
+    a += pw[j];
+    b += pw[(long)n + j];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  __shared__ double sa[4], sb[4];
+  if ((threadIdx.x & 63) == 0) {
+    sa[threadIdx.x >> 6] = a;
+    sb[threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double A = (sa[0] + sa[1]) + (sa[2] + sa[3]);
+    const double Bs = (sb[0] + sb[1]) + (sb[2] + sb[3]);
+    bed_fov[blockIdx.x] = Bs > 0.0 ? A / Bs : 0.0;
+  }
+}
+
+void launch_bedsum(const double *pw, int n, const int32_t *start, const BedDev *beds, int n_beds, double *bed_fov,
+                   hipStream_t s) {
+  k_bedsum<<<n_beds, 256, 0, s>>>(pw, n, start, beds, bed_fov);
+}
+
+// ------------------------------------------------------------------ init / import / export
+template <typename T>
+__global__ void k_init(dem_parcels in, int n, Phys ph, int n_ores, Dyn<T> d, Props<T> p, uint32_t *status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  d.x[i] = in.x[i];
+  d.y[i] = in.y[i];
+  d.z[i] = in.z[i];
+  d.vx[i] = ((const T *)in.vx)[i];
+  d.vy[i] = ((const T *)in.vy)[i];
+  d.vz[i] = ((const T *)in.vz)[i];
+  d.wx[i] = ((const T *)in.wx)[i];
+  d.wy[i] = ((const T *)in.wy)[i];
+  d.wz[i] = ((const T *)in.wz)[i];
+  const float dd = in.d[i], kk = in.k[i];
+  const int b = in.bed[i], o = in.ore[i];
+  if (b < 0 || b >= ph.n_beds || o < 0 || o >= n_ores || !(dd > 0.0f) || !(kk >= 1.0f)) atomicOr(status, 16u);
+  p.rad[i] = 0.5f * dd;
+  p.kcg[i] = kk;
+  const bool ok = b >= 0 && b < ph.n_beds && o >= 0 && o < n_ores;
+  p.tag[i] = ok ? b * 256 + o : 0;
+  p.id[i] = (uint32_t)i;
+  const double nh = in.nh[i], nm = in.nm[i], nw = in.nw[i], nfe = in.nfe[i];
+  p.nh[i] = nh;
+  p.nm[i] = nm;
+  p.nw[i] = nw;
+  p.nfe[i] = nfe;
+  const double k3 = (double)kk * kk * kk;
+  p.mass[i] = T(k3 * 1e-3 * (nh * 159.687 + nm * 231.531 + nw * 71.844 + nfe * 55.845));  // eq. e3-4
+  // eq. e3-45 restitution of the parcel, eq. e3-44 damping ratio
+  const double rad = 1.0 + (double)kk * (ph.e_p * ph.e_p - 1.0);
+  const double e = rad > 0.0 ? sqrt(rad) : 0.0;
+  double z = 1.0;
+  if (e > 0.0) {
+    const double l = log(e);
+    z = -l / sqrt(kPi * kPi + l * l);
+  }
+  p.zeta[i] = T(z);
+#pragma unroll
+  for (int k = 0; k < 3 * kMaxWalls; k++) p.wh[(long)k * n + i] = T(0);
+}
+
+template <typename T>
+void launch_init(const dem_parcels &in, int n, const Phys &ph, int n_ores, const Dyn<T> &d, const Props<T> &p,
+                 uint32_t *status, hipStream_t s) {
+  k_init<T><<<(n + 255) / 256, 256, 0, s>>>(in, n, ph, n_ores, d, p, status);
+}
+
+template <typename T>
+__global__ void k_export(Dyn<T> d, Props<T> p, int n, dem_parcels out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t i = p.id[j];
+  if (out.x) out.x[i] = d.x[j];
+  if (out.y) out.y[i] = d.y[j];
+  if (out.z) out.z[i] = d.z[j];
+  if (out.vx) ((T *)out.vx)[i] = d.vx[j];
+  if (out.vy) ((T *)out.vy)[i] = d.vy[j];
+  if (out.vz) ((T *)out.vz)[i] = d.vz[j];
+  if (out.wx) ((T *)out.wx)[i] = d.wx[j];
+  if (out.wy) ((T *)out.wy)[i] = d.wy[j];
+  if (out.wz) ((T *)out.wz)[i] = d.wz[j];
+  if (out.nh) out.nh[i] = p.nh[j];
+  if (out.nm) out.nm[i] = p.nm[j];
+  if (out.nw) out.nw[i] = p.nw[j];
+  if (out.nfe) out.nfe[i] = p.nfe[j];
+}
+
+template <typename T>
+void launch_export(const Dyn<T> &d, const Props<T> &p, int n, const dem_parcels &out, hipStream_t s) {
+  k_export<T><<<(n + 255) / 256, 256, 0, s>>>(d, p, n, out);
+}
+
+template <typename T>
+__global__ void k_import(dem_parcels in, int n, Dyn<T> d, Props<T> p) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t i = p.id[j];
+  d.x[j] = in.x[i];
+  d.y[j] = in.y[i];
+  d.z[j] = in.z[i];
+  d.vx[j] = ((const T *)in.vx)[i];
+  d.vy[j] = ((const T *)in.vy)[i];
+  d.vz[j] = ((const T *)in.vz)[i];
+  d.wx[j] = ((const T *)in.wx)[i];
+  d.wy[j] = ((const T *)in.wy)[i];
+  d.wz[j] = ((const T *)in.wz)[i];
+  const double nh = in.nh[i], nm = in.nm[i], nw = in.nw[i], nfe = in.nfe[i];
+  p.nh[j] = nh;
+  p.nm[j] = nm;
+  p.nw[j] = nw;
+  p.nfe[j] = nfe;
+  const double kk = (double)p.kcg[j];
+  p.mass[j] = T(kk * kk * kk * 1e-3 * (nh * 159.687 + nm * 231.531 + nw * 71.844 + nfe * 55.845));
+#pragma unroll
+  for (int k = 0; k < 3 * kMaxWalls; k++) p.wh[(long)k * n + j] = T(0);
+}
+
+template <typename T>
+void launch_import(const dem_parcels &in, int n, const Dyn<T> &d, const Props<T> &p, hipStream_t s) {
+  k_import<T><<<(n + 255) / 256, 256, 0, s>>>(in, n, d, p);
+}
+
+#define INST(T)                                                                                                    \
+  template void launch_deposit<T>(const Dyn<T> &, const Props<T> &, const GasArgs &, const int32_t *,             \
+                                  const int32_t *, const BedDev *, const Phys &, int, bool, const DepositOut &,   \
+                                  hipStream_t);                                                                    \
+  template void launch_react<T>(const ReactArgs<T> &, hipStream_t);                                               \
+  template void launch_init<T>(const dem_parcels &, int, const Phys &, int, const Dyn<T> &, const Props<T> &,     \
+                               uint32_t *, hipStream_t);                                                           \
+  template void launch_export<T>(const Dyn<T> &, const Props<T> &, int, const dem_parcels &, hipStream_t);        \
+  template void launch_import<T>(const dem_parcels &, int, const Dyn<T> &, const Props<T> &, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace demrx

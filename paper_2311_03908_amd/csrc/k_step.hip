@@ -1,0 +1,323 @@
+// One DEM step, fused: exact contact test over the Verlet candidates,
+// soft-sphere parcel-parcel and parcel-wall forces with tangential springs,
+// Gidaspow drag + gravity + pressure-gradient force, semi-implicit Euler.
+// One thread per parcel in cell-sorted order; the step reads buffer `in` and
+// writes buffer `out`, so no parcel sees a partner's updated state.
+#include "launch.h"
+
+namespace demrx {
+
+// Linear spring-dashpot normal force (no tensile clamp) and Cundall tangential
+// spring with Coulomb cap, in the orientation of body a; n points from a to b.
+// The paper defers the contact model to another work; the damping ratio
+// follows the coarse-grained restitution of eqs. e3-44/e3-45.
+template <typename T>
+__device__ __forceinline__ void contact_force(const Phys &ph, T mstar, T zeta, T delta, const T n[3], const T vrel[3],
+                                              const T xin[3], T F[3], T Ft[3], T xo[3], T &fn_abs) {
+  const T kn = T(ph.kn), dt = T(ph.dt);
+  const T gn = T(2) * zeta * tsqrt<T>(mstar * kn);
+  const T vn = vrel[0] * n[0] + vrel[1] * n[1] + vrel[2] * n[2];
+  const T fn = -(kn * delta + gn * vn);
+  T vt[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) vt[a] = vrel[a] - vn * n[a];
+  const T xn = xin[0] * n[0] + xin[1] * n[1] + xin[2] * n[2];
+#pragma unroll
+  for (int a = 0; a < 3; a++) xo[a] = (xin[a] - xn * n[a]) + vt[a] * dt;
+  const T kt = T(ph.kt), gt = T(ph.gt_ratio) * gn;
+#pragma unroll
+  for (int a = 0; a < 3; a++) Ft[a] = -kt * xo[a] - gt * vt[a];
+  const T ftm = tsqrt<T>(Ft[0] * Ft[0] + Ft[1] * Ft[1] + Ft[2] * Ft[2]);
+  const T cap = T(ph.mu_s) * fabs(fn);
+  if (ftm > cap) {
+    const T sc = cap / ftm;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      Ft[a] *= sc;
+      xo[a] = -(Ft[a] + gt * vt[a]) / kt;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; a++) F[a] = fn * n[a] + Ft[a];
+  fn_abs = fabs(fn);
+}
+
+template <typename T>
+__device__ __forceinline__ void cross(const T a[3], const T b[3], T c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const long N = a.n;
+  float vmag = 0.0f;
+  int n_pp = 0, n_w = 0;
+  if (i < a.n) {
+    const double xi = a.in.x[i], yi = a.in.y[i], zi = a.in.z[i];
+    const T vi[3] = {a.in.vx[i], a.in.vy[i], a.in.vz[i]};
+    const T wi[3] = {a.in.wx[i], a.in.wy[i], a.in.wz[i]};
+    const float rif = a.pr.rad[i];
+    const T ri = T(rif);
+    const T mi = a.pr.mass[i];
+    const T zi_ = a.pr.zeta[i];
+    const uint32_t idi = a.pr.id[i];
+    const int32_t tag = a.pr.tag[i];
+    const int cnt = a.nb.cnt[i];
+    const uint64_t mold = a.nb.mask[i];
+    uint64_t mnew = 0;
+    T F[3] = {T(0), T(0), T(0)}, Tq[3] = {T(0), T(0), T(0)};
+    T wmag = tsqrt<T>(wi[0] * wi[0] + wi[1] * wi[1] + wi[2] * wi[2]);
+    const bool roll = a.ph.mu_r > 0.0 && wmag > T(0);
+    for (int s = 0; s < cnt; s++) {
+      const int j = a.nb.idx[(long)s * N + i];
+      const double dx = a.in.x[j] - xi, dy = a.in.y[j] - yi, dz = a.in.z[j] - zi;
+      const float rjf = a.pr.rad[j];
+      const double sr = (double)rif + (double)rjf;
+      const double d2 = dist2_exact(dx, dy, dz);
+      if (!(d2 < sq_exact(sr))) continue;
+      // pair evaluated in canonical orientation (lower original id first) so
+      // both partners obtain bit-identical values with opposite signs
+      const uint32_t idj = a.pr.id[j];
+      const bool ifirst = idi < idj;
+      const T sgn = ifirst ? T(1) : T(-1);
+      const double dist = sqrt(d2);
+      const double inv = 1.0 / dist;
+      const T n[3] = {T((ifirst ? dx : -dx) * inv), T((ifirst ? dy : -dy) * inv), T((ifirst ? dz : -dz) * inv)};
+      const T delta = T(sr - dist);
+      const T vj[3] = {a.in.vx[j], a.in.vy[j], a.in.vz[j]};
+      const T wj[3] = {a.in.wx[j], a.in.wy[j], a.in.wz[j]};
+      const T mj = a.pr.mass[j];
+      const T zj = a.pr.zeta[j];
+      const T rj = T(rjf);
+      const T ra = ifirst ? ri : rj, rb = ifirst ? rj : ri;
+      const T ma = ifirst ? mi : mj, mb = ifirst ? mj : mi;
+      T vrel[3], ws[3], cr[3];
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        const T va = ifirst ? vi[c] : vj[c], vb = ifirst ? vj[c] : vi[c];
+        const T wa = ifirst ? wi[c] : wj[c], wb = ifirst ? wj[c] : wi[c];
+        ws[c] = ra * wa + rb * wb;
+        vrel[c] = va - vb;
+      }
+      cross(ws, n, cr);
+#pragma unroll
+      for (int c = 0; c < 3; c++) vrel[c] += cr[c];
+      const T mstar = ma * mb / (ma + mb);
+      const T zeta = zi_ > zj ? zi_ : zj;
+      T xin[3] = {T(0), T(0), T(0)};
+      if ((mold >> s) & 1ull) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) xin[c] = a.nb.hist[((long)c * kMaxNbr + s) * N + i];
+      }
+      T Fa[3], Ft[3], xo[3], fnabs;
+      contact_force<T>(a.ph, mstar, zeta, delta, n, vrel, xin, Fa, Ft, xo, fnabs);
+      T tq[3];
+      cross(n, Ft, tq);
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        F[c] += sgn * Fa[c];
+        Tq[c] += ri * tq[c];
+      }
+      if (roll) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) Tq[c] -= T(a.ph.mu_r) * fnabs * wi[c] / wmag;
+      }
+      if (a.mode == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) a.nb.hist[((long)c * kMaxNbr + s) * N + i] = xo[c];
+      }
+      mnew |= 1ull << s;
+      n_pp++;
+    }
+    // walls: same law against a body of infinite mass and radius at rest
+    const BedDev &B = a.beds[bed_of(tag)];
+    for (int w = 0; w < B.n_walls; w++) {
+      double nv[3];
+      const double phi = wall_clearance(B, w, xi, yi, zi, nv);
+      const double delw = (double)rif - phi;
+      if (!(delw > 0.0)) continue;
+      const T n[3] = {T(nv[0]), T(nv[1]), T(nv[2])};
+      T wr[3] = {ri * wi[0], ri * wi[1], ri * wi[2]}, cr[3];
+      cross(wr, n, cr);
+      const T vrel[3] = {vi[0] + cr[0], vi[1] + cr[1], vi[2] + cr[2]};
+      T xin[3] = {T(0), T(0), T(0)};
+      if ((mold >> (kWallBit + w)) & 1ull) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) xin[c] = a.pr.wh[(long)(w * 3 + c) * N + i];
+      }
+      T Fa[3], Ft[3], xo[3], fnabs;
+      contact_force<T>(a.ph, mi, zi_, T(delw), n, vrel, xin, Fa, Ft, xo, fnabs);
+      T tq[3];
+      cross(n, Ft, tq);
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        F[c] += Fa[c];
+        Tq[c] += ri * tq[c];
+      }
+      if (roll) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) Tq[c] -= T(a.ph.mu_r) * fnabs * wi[c] / wmag;
+      }
+      if (a.mode == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) a.pr.wh[(long)(w * 3 + c) * N + i] = xo[c];
+      }
+      mnew |= 1ull << (kWallBit + w);
+      n_w++;
+    }
+    // gravity, pressure gradient and drag (eqs. e3-3, e3-5), NGP gas cell
+#pragma unroll
+    for (int c = 0; c < 3; c++) F[c] += mi * T(a.ph.g[c]);
+    if (a.ph.drag_on) {
+      Cells cl;
+      locate(B, xi, yi, zi, cl);
+      const T *g = a.gtab + (long)cl.gas * kGasRow;
+      const T dpr = T(2) * ri / T(a.pr.kcg[i]);  // real-particle diameter
+      const T V = T(kPi / 6.0) * (T(2) * ri) * (T(2) * ri) * (T(2) * ri);
+      const T s[3] = {g[0] - vi[0], g[1] - vi[1], g[2] - vi[2]};
+      const T slip = tsqrt<T>(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+      const T be = beta_over_epsp<T>(g[3], g[7], g[8], slip, dpr, a.ph.ergun_printed);
+#pragma unroll
+      for (int c = 0; c < 3; c++) F[c] += be * V * s[c] - V * g[4 + c];
+    }
+    if (a.mode == 1) {
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        a.Fout[3 * (long)idi + c] = (double)F[c];
+        a.Tout[3 * (long)idi + c] = (double)Tq[c];
+      }
+    } else {
+      const T dt = T(a.ph.dt);
+      const T im = T(1) / mi;
+      const T iI = T(1) / (T(0.4) * mi * ri * ri);
+      T vn[3], wn[3];
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        vn[c] = vi[c] + dt * F[c] * im;
+        wn[c] = wi[c] + dt * Tq[c] * iI;
+      }
+      const double xn = xi + a.ph.dt * (double)vn[0];
+      const double yn = yi + a.ph.dt * (double)vn[1];
+      const double zn = zi + a.ph.dt * (double)vn[2];
+      a.out.x[i] = xn;
+      a.out.y[i] = yn;
+      a.out.z[i] = zn;
+      a.out.vx[i] = vn[0];
+      a.out.vy[i] = vn[1];
+      a.out.vz[i] = vn[2];
+      a.out.wx[i] = wn[0];
+      a.out.wy[i] = wn[1];
+      a.out.wz[i] = wn[2];
+      if (a.mode == 0) a.nb.mask[i] = mnew;
+      const float v2 = (float)(vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]);
+      vmag = sqrtf(v2);
+      if (!(isfinite(xn) && isfinite(yn) && isfinite(zn) && isfinite(v2) &&
+            isfinite((float)(wn[0] + wn[1] + wn[2]))))
+        atomicOr(a.status, ST_NONFINITE);
+    }
+  }
+  if (a.mode != 0) return;
+  // block maximum of |v| -> global bound on the displacement since the last build
+  __shared__ float smax[8];
+  __shared__ int scnt[2][8];
+  float m = vmag;
+  int c0 = n_pp, c1 = n_w;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    m = fmaxf(m, __shfl_xor(m, o, 64));
+    c0 += __shfl_xor(c0, o, 64);
+    c1 += __shfl_xor(c1, o, 64);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    smax[wid] = m;
+    scnt[0][wid] = c0;
+    scnt[1][wid] = c1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float bm = 0.0f;
+    int t0 = 0, t1 = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); w++) {
+      bm = fmaxf(bm, smax[w]);
+      t0 += scnt[0][w];
+      t1 += scnt[1][w];
+    }
+    atomicMax(&a.vmax[a.par], __float_as_uint(bm));
+    if (t0) atomicAdd(&a.counters[0], (unsigned long long)t0);
+    if (t1) atomicAdd(&a.counters[1], (unsigned long long)t1);
+    if (blockIdx.x == 0) {
+      // the previous step moved every parcel by at most dt * vmax[prev]
+      const float vp = __uint_as_float(a.vmax[a.par ^ 1]);
+      const double dsp = a.disp[0] + a.ph.dt * (double)vp;
+      a.disp[0] = dsp;
+      a.vmax[a.par ^ 1] = 0u;
+      if (dsp > 0.5 * a.ph.skin) atomicOr(a.status, ST_SKIN);
+    }
+  }
+}
+
+template <typename T>
+void launch_step(const StepArgs<T> &a, int block, hipStream_t s) {
+  k_step<T><<<(a.n + block - 1) / block, block, 0, s>>>(a);
+}
+
+// ------------------------------------------------------------------ gas table
+// Ideal-gas density (eq. e3-53) and mass-weighted viscosity (eqs. e3-55,
+// e3-56, Table C2) of each cell, with the cell's velocity, voidage and
+// pressure gradient, packed in one row for the drag gather.
+__device__ __forceinline__ void gas_rho_mu(double T, double p, double x1, double x2, double x3, double mu_fix,
+                                           double &rho, double &mu) {
+  const double M1 = 2.016, M2 = 18.015, M3 = 28.013;  // g/mol H2, H2O, N2
+  const double Mg = x1 * M1 + x2 * M2 + x3 * M3;
+  rho = p * (Mg * 1e-3) / (kRg * T);
+  if (mu_fix > 0.0) {
+    mu = mu_fix;
+    return;
+  }
+  const double m1 = 2.85e-6 + 2.16e-8 * T - 3.78e-12 * T * T;
+  const double m2 = -4.44e-6 + 4.52e-8 * T - 3.20e-12 * T * T;
+  const double m3 = 7.86e-6 + 3.87e-8 * T - 5.11e-12 * T * T;
+  mu = (x1 * M1 * m1 + x2 * M2 * m2 + x3 * M3 * m3) / Mg;
+}
+
+template <typename T>
+__global__ void k_gas_table(GasArgs g, const double *eps, const int32_t *cell_bed, const BedDev *beds, int n_gas,
+                            T *gtab, uint32_t *status) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_gas) return;
+  double rho, mu;
+  gas_rho_mu(g.T[c], g.p[c], g.xH2[c], g.xH2O[c], g.xN2[c], beds[cell_bed[c]].mu_override, rho, mu);
+  T *r = gtab + (long)c * kGasRow;
+  r[0] = T(g.ug[c]);
+  r[1] = T(g.vg[c]);
+  r[2] = T(g.wg[c]);
+  r[3] = T(eps[c]);
+  r[4] = T(g.dpdx[c]);
+  r[5] = T(g.dpdy[c]);
+  r[6] = T(g.dpdz[c]);
+  r[7] = T(rho);
+  r[8] = T(mu);
+  r[9] = r[10] = r[11] = T(0);
+  if (!(isfinite(rho) && isfinite(mu) && isfinite(g.ug[c] + g.vg[c] + g.wg[c]) &&
+        isfinite(g.dpdx[c] + g.dpdy[c] + g.dpdz[c])) || !(rho > 0.0) || !(mu > 0.0))
+    atomicOr(status, ST_NONFINITE);
+}
+
+template <typename T>
+void launch_gas_table(const GasArgs &g, const double *eps, const int32_t *cell_bed, const BedDev *beds, int n_gas,
+                      T *gtab, uint32_t *status, hipStream_t s) {
+  k_gas_table<T><<<(n_gas + 255) / 256, 256, 0, s>>>(g, eps, cell_bed, beds, n_gas, gtab, status);
+}
+
+template void launch_step<float>(const StepArgs<float> &, int, hipStream_t);
+template void launch_step<double>(const StepArgs<double> &, int, hipStream_t);
+template void launch_gas_table<float>(const GasArgs &, const double *, const int32_t *, const BedDev *, int, float *,
+                                      uint32_t *, hipStream_t);
+template void launch_gas_table<double>(const GasArgs &, const double *, const int32_t *, const BedDev *, int,
+                                       double *, uint32_t *, hipStream_t);
+
+}  // namespace demrx

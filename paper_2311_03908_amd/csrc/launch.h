@@ -1,0 +1,152 @@
+// Host-side launchers of the demrx kernels (one definition per kernel file).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace demrx {
+
+// ---------------------------------------------------------------- k_build.hip
+struct Item {  // a run of up to kItemX DEM cells along x in one (y, z) row of a bed
+  int bed, x0, iy, iz;
+};
+constexpr int kItemX = 4;
+
+void launch_fill_i32(int32_t *p, int32_t v, long n, hipStream_t s);
+void launch_fill_u32(uint32_t *p, uint32_t v, long n, hipStream_t s);
+// exclusive prefix sum of m ints; scratch needs scan_scratch_ints(m) ints
+long scan_scratch_ints(long m);
+void launch_scan(const int32_t *in, int32_t *out, long m, int32_t *scratch, hipStream_t s);
+
+template <typename T>
+void launch_bin(const Dyn<T> &d, const Props<T> &p, const BedDev *beds, int n, int32_t *key,
+                int32_t *slot, int32_t *count, uint32_t *status, hipStream_t s);
+void launch_scatter(const int32_t *key, const int32_t *slot, const int32_t *start, int n, int32_t *perm,
+                    hipStream_t s);
+void launch_cellsort(const int32_t *start, int n_keys, const uint32_t *id_old, int32_t *perm, hipStream_t s);
+template <typename T>
+void launch_permute(const int32_t *perm, int n, const Dyn<T> &din, const Props<T> &pin, const Dyn<T> &dout,
+                    const Props<T> &pout, unsigned *vmax, double *disp, hipStream_t s);
+void launch_items(const Item *items, int n_items, const BedDev *beds, const int32_t *start, int32_t *flags,
+                  int32_t *offs, int32_t *scratch, int32_t *list, int32_t *count, hipStream_t s);
+
+template <typename T>
+struct NbrBuild {
+  Dyn<T> d;             // new sorted state
+  Props<T> p;           // new sorted properties
+  const uint32_t *id_old;
+  const int32_t *perm;  // new position -> old position
+  Nbr<T> nb_new, nb_old;
+  const BedDev *beds;
+  const int32_t *start;
+  const Item *items;
+  const int32_t *list, *list_count;
+  int n, cap;
+  double skin;
+  uint32_t *status;
+};
+template <typename T>
+void launch_build_nbr(const NbrBuild<T> &a, int grid, hipStream_t s);
+
+template <typename T>
+void launch_pairs(const Dyn<T> &d, const Props<T> &p, const Nbr<T> &nb, int n, uint32_t *out, long cap,
+                  unsigned long long *count, hipStream_t s);
+
+// ---------------------------------------------------------------- k_step.hip
+template <typename T>
+struct StepArgs {
+  Dyn<T> in, out;
+  Props<T> pr;
+  Nbr<T> nb;
+  const T *gtab;
+  const BedDev *beds;
+  Phys ph;
+  uint32_t *status;
+  unsigned *vmax;
+  double *disp;
+  unsigned long long *counters;  // [0] pp contacts, [1] wall contacts (mode 0)
+  int n, par, mode;              // mode 0: integrate; 1: write forces; 2: timing dry run
+  double *Fout, *Tout;
+};
+template <typename T>
+void launch_step(const StepArgs<T> &a, int block, hipStream_t s);
+
+struct GasArgs {
+  const double *ug, *vg, *wg, *p, *dpdx, *dpdy, *dpdz, *T, *xH2, *xH2O, *xN2;
+};
+template <typename T>
+void launch_gas_table(const GasArgs &g, const double *eps, const int32_t *cell_bed, const BedDev *beds,
+                      int n_gas, T *gtab, uint32_t *status, hipStream_t s);
+
+// ---------------------------------------------------------------- k_couple.hip
+struct DepositOut {
+  double *eps_ctx;  // context voidage (always written)
+  double *eps, *np, *sumK, *sumKu, *sumKv, *sumKw, *sumKs;
+};
+template <typename T>
+void launch_deposit(const Dyn<T> &d, const Props<T> &p, const GasArgs &g, const int32_t *start,
+                    const int32_t *cell_bed, const BedDev *beds, const Phys &ph, int n_gas, bool sums,
+                    const DepositOut &o, hipStream_t s);
+
+template <typename T>
+struct ReactArgs {
+  Dyn<T> d;
+  Props<T> p;
+  GasArgs g;
+  const double *eps;
+  const BedDev *beds;
+  const OreDev *ores;
+  const double *theta;  // 6 values overriding every bed's, or null
+  double dt;
+  int n;
+  int update_mass;
+  double *pm;    // [4][N] per-parcel mdotH2, mdotH2O, EQ, ES
+  double *pw;    // [2][N] per-parcel w f_ov, w
+  double *fov;   // original order (may be null)
+  unsigned long long *clamps;
+  uint32_t *status;
+};
+template <typename T>
+void launch_react(const ReactArgs<T> &a, hipStream_t s);
+void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t *cell_bed, const BedDev *beds,
+                    int n_gas, double *o0, double *o1, double *o2, double *o3, hipStream_t s);
+void launch_bedsum(const double *pw, int n, const int32_t *start, const BedDev *beds, int n_beds,
+                   double *bed_fov, hipStream_t s);
+
+template <typename T>
+void launch_init(const dem_parcels &in, int n, const Phys &ph, int n_ores, const Dyn<T> &d, const Props<T> &p,
+                 uint32_t *status, hipStream_t s);
+template <typename T>
+void launch_export(const Dyn<T> &d, const Props<T> &p, int n, const dem_parcels &out, hipStream_t s);
+template <typename T>
+void launch_import(const dem_parcels &in, int n, const Dyn<T> &d, const Props<T> &p, hipStream_t s);
+
+// ---------------------------------------------------------------- k_adjoint.hip
+struct AdjEnv {  // per-parcel reaction environment of one dynamics interval
+  float *F;      // film resistance
+  int32_t *cell; // gas cell
+};
+struct AdjArgs {
+  int n, n_int, dyn_every, ckpt_every, n_sub;
+  double dt;
+  const int32_t *cell_rec;  // [n_int][N] gas cell per parcel (original order)
+  const float *F_rec;       // [n_int][N]
+  const double *cell_tab;   // per gas cell: T, x, c_mol, Dm, (per ore D computed in kernel)
+  const double *gasT, *gasP, *gasH2, *gasH2O, *gasN2;
+  const OreDev *ores;
+  const int32_t *ore;       // original order
+  const float *dp;          // real diameter, original order
+  const float *k3;          // k^3 per parcel
+  const int32_t *kind;      // per parcel f_ov kind
+  const double *sp0;        // [4][N] initial species (double)
+  double theta[6];
+  int fp32;                 // state precision
+  void *ckpt;               // [n_ckpt][4][N] (float or double)
+  void *seg;                // [ckpt_every/dyn_every + 1][4][N] segment replay buffer
+  double *partial;          // per block partial sums: [blocks][8] (J num, J den, grad 6)
+};
+void launch_adjoint_forward(const AdjArgs &a, int grad, hipStream_t s);
+void launch_adjoint_backward(const AdjArgs &a, hipStream_t s);
+int adjoint_blocks(int n);
+
+}  // namespace demrx

@@ -31,11 +31,12 @@ Any workload can be shrunk with ``n=...``: the container is scaled by
 Placement: the dilute box beds (cfg1, cfg5) use random sequential addition
 without overlap over the whole box.  The cylindrical beds (cfg2-4) start as a
 packed bed, as the paper's bubbling beds do before fluidization: parcels are
-sorted by size into horizontal layers, each layer a square lattice whose pitch
-is the largest parcel of that layer plus a small gap, with each parcel
-jittered inside its own lattice cube (so no two parcels overlap), layers
-stacked from the floor up; original ids are then shuffled so id order carries
-no spatial information.
+split into size classes and stacked from the floor up in horizontal layers
+that cycle through the classes; each layer is a square lattice whose pitch is
+the largest parcel of its class plus a 2 % gap, with each parcel jittered
+inside its own lattice cube (so no two parcels overlap and neighbours are
+nearly touching); original ids are then shuffled so id order carries no
+spatial information.
 """
 from __future__ import annotations
 
@@ -213,49 +214,47 @@ def _rsa_box(rng, d, lo, hi, max_rounds=20000):
     return pos
 
 
-def _layer_pack(rng, d, R, cx, cy, z0, gap_frac=0.02, jitter=0.5, box=None):
-    """Size-sorted layered lattice packing inside a cylinder of radius R (axis
-    at cx, cy) from height z0 up (or inside an xy box ``box=(x0,x1,y0,y1)``).
-    Each layer is a square lattice with pitch a = d_max(layer)*(1+gap_frac);
-    each parcel sits in its own a^3 cube, jittered by up to
-    jitter*(a-d)/2 per axis.  Returns (n, 3) centres."""
+def _layer_pack(rng, d, R, cx, cy, z0, gap_frac=0.02, jitter=0.5, classes=1):
+    """Layered lattice packing inside a cylinder of radius R (axis at cx, cy)
+    from height z0 up.  Parcels are split into ``classes`` size classes (by
+    quantile); horizontal layers cycle through the classes, each layer a
+    square lattice of pitch a = d_max(class)*(1+gap_frac) filled with parcels
+    of its class at random sites, each parcel jittered inside its own a^3 cube
+    by up to jitter*(a-d)/2 per axis (so no two parcels overlap).  Cycling the
+    classes keeps sizes mixed along the bed height.  Returns (n, 3) centres."""
     n = d.shape[0]
     order = np.argsort(-d, kind="stable")
+    groups = [g for g in np.array_split(order, classes) if g.size]
     pos = np.zeros((n, 3))
+    taken = [0] * len(groups)
     z = z0
-    i = 0
-    while i < n:
-        dl = d[order[i]]
-        a = dl * (1.0 + gap_frac)
-        if box is None:
+    c = 0
+    left = n
+    while left > 0:
+        g = groups[c]
+        if taken[c] < g.size:
+            a = float(d[g[taken[c]:]].max()) * (1.0 + gap_frac)
             m = int(math.floor(2 * R / a))
-            g = (np.arange(m) - (m - 1) / 2.0) * a
-            gx, gy = np.meshgrid(g, g, indexing="ij")
+            lat = (np.arange(m) - (m - 1) / 2.0) * a
+            gx, gy = np.meshgrid(lat, lat, indexing="ij")
             gx = gx.ravel()
             gy = gy.ravel()
             inside = np.sqrt(gx ** 2 + gy ** 2) + 0.5 * a * math.sqrt(2.0) <= R
             sx = gx[inside] + cx
             sy = gy[inside] + cy
-        else:
-            x0, x1, y0, y1 = box
-            mx = int(math.floor((x1 - x0) / a))
-            my = int(math.floor((y1 - y0) / a))
-            gx, gy = np.meshgrid(x0 + (np.arange(mx) + 0.5) * a, y0 + (np.arange(my) + 0.5) * a,
-                                 indexing="ij")
-            sx = gx.ravel()
-            sy = gy.ravel()
-        cap = sx.size
-        if cap == 0:
-            raise RuntimeError("container too small for one lattice layer")
-        take = order[i:i + cap]
-        sel = rng.permutation(cap)[: take.size]
-        r = 0.5 * d[take]
-        amp = jitter * (0.5 * a - r)
-        pos[take, 0] = sx[sel] + amp * (2 * rng.random(take.size) - 1)
-        pos[take, 1] = sy[sel] + amp * (2 * rng.random(take.size) - 1)
-        pos[take, 2] = z + 0.5 * a + amp * (2 * rng.random(take.size) - 1)
-        z += a
-        i += take.size
+            if sx.size == 0:
+                raise RuntimeError("container too small for one lattice layer")
+            take = g[taken[c]:taken[c] + sx.size]
+            sel = rng.permutation(sx.size)[: take.size]
+            r = 0.5 * d[take]
+            amp = jitter * (0.5 * a - r)
+            pos[take, 0] = sx[sel] + amp * (2 * rng.random(take.size) - 1)
+            pos[take, 1] = sy[sel] + amp * (2 * rng.random(take.size) - 1)
+            pos[take, 2] = z + 0.5 * a + amp * (2 * rng.random(take.size) - 1)
+            z += a
+            taken[c] += take.size
+            left -= take.size
+        c = (c + 1) % len(groups)
     return pos
 
 
@@ -364,7 +363,7 @@ def cfg1(n=2048, seed=1, steps=1000):
 
 
 def _cfg_cyl(name, n, N0, R0, H0, h, refine, d_sampler, k, ores, ore_split, T, xh2, seed, steps,
-             dt=5e-6, couple=20, precision="mixed", skin=3e-5, u=0.3):
+             dt=5e-6, couple=20, precision="mixed", skin=3e-5, u=0.3, classes=8):
     rng = np.random.Generator(np.random.PCG64(seed))
     s = (n / float(N0)) ** (1.0 / 3.0)
     R = R0 * s
@@ -376,7 +375,7 @@ def _cfg_cyl(name, n, N0, R0, H0, h, refine, d_sampler, k, ores, ore_split, T, x
     ore_idx = ore_split(rng, n)
     cx = 0.5 * (bed.lo[0] + bed.hi[0])
     cy = 0.5 * (bed.lo[1] + bed.hi[1])
-    pos = _layer_pack(rng, (k * d_p), R, cx, cy, 0.0)
+    pos = _layer_pack(rng, (k * d_p), R, cx, cy, 0.0, classes=classes)
     if pos[:, 2].max() + 0.5 * k * d_p.max() > H:
         raise RuntimeError("packed bed higher than the container")
     rho_of = {i: (1.0 - o.xi0) * o.rho_true[0] for i, o in enumerate(ores)}

@@ -1,0 +1,394 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle on
+identical seeded inputs.
+
+Gates: contact pair lists bit-exact; per-step forces within 1e-5 of
+max(|F_oracle|, m g) (FP64 path: 1e-10); 100-step trajectories within
+1e-4 d (positions) and 1e-4 max(|v|, 1e-3 m/s) (velocities); reduction
+degree within 1e-4 per parcel; cell sums within 1e-9 relative.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2311_03908_amd import workloads as W
+from paper_2311_03908_amd.capi import DemError
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2311_03908_amd.bed import Bed
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _force_err(Fg, Fo, mass, floor_scale=9.81):
+    floor = mass * floor_scale
+    return float(np.max(np.abs(Fg - Fo) / np.maximum(np.linalg.norm(Fo, axis=1), floor)[:, None]))
+
+
+# Dense variants (parcels pushed together) for one-shot comparisons, and gently
+# overlapping variants with slow random motion for comparisons over many
+# steps (velocities stay well inside the neighbour-list skin).
+DENSE = {
+    "cfg1_fp64": lambda: W.with_velocities(W.squeeze(W.cfg1(), 0.6, 0), 11),
+    "cfg2_mixed": lambda: W.with_velocities(W.squeeze(W.cfg2(n=3000, seed=12), 0.97, 0), 12),
+    "cfg3_mixed": lambda: W.with_velocities(W.squeeze(W.cfg3(n=20000, seed=13), 0.97, 0), 13),
+}
+GENTLE = {
+    "cfg1_fp64": lambda: W.with_velocities(W.squeeze(W.cfg1(), 0.995, 0), 21, vscale=0.05, wscale=20.0),
+    "cfg2_mixed": lambda: W.with_velocities(W.squeeze(W.cfg2(n=3000, seed=22), 0.995, 0), 22, vscale=0.03, wscale=20.0),
+    "cfg3_mixed": lambda: W.with_velocities(W.squeeze(W.cfg3(n=20000, seed=23), 0.995, 0), 23, vscale=0.03, wscale=20.0),
+}
+CASES = DENSE
+
+
+def _rolling(w):
+    w.params["mu_r"] = 2e-5
+    w.params["gt_over_gn"] = 0.2
+    w.params["rebuild_every"] = 2
+    return w
+
+
+def _from_state(w, st):
+    """Workload w with its parcel state replaced by an oracle state."""
+    p = dict(w.parcels)
+    for k in ("x", "y", "z", "vx", "vy", "vz", "wx", "wy", "wz", "nh", "nm", "nw", "nfe"):
+        v = np.asarray(st[k], dtype=np.float64)
+        if w.precision == "mixed" and k[0] in "vw":
+            v = v.astype(np.float32).astype(np.float64)
+        p[k] = v
+    return W.dataclasses.replace(w, parcels=p)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_pairs_bit_exact(case):
+    w = CASES[case]()
+    _say(f"[pairs] {case} n={w.n}")
+    bed = Bed(w)
+    ora = O.Oracle(w)
+    pg = bed.pairs()
+    po = ora.pairs()
+    assert len(po) > 100
+    assert np.array_equal(pg, po)
+
+
+@pytest.mark.parametrize("case", list(GENTLE))
+def test_forces_each_step(case):
+    """FP64: both sides step on their own and the forces of every step agree
+    (tangential-spring history included).  Mixed: at every step of the
+    oracle's trajectory both sides restart from the oracle state (fresh
+    springs) and their forces agree to the FP32 gate."""
+    w = _rolling(GENTLE[case]())
+    _say(f"[forces] {case} n={w.n}")
+    ora = O.Oracle(w)
+    mass = ora.state()["mass"]
+    rg = mass * 9.81 * 0.5 * w.parcels["d"].astype(np.float64)
+    bed = Bed(w)
+    for k in range(6):
+        if w.precision == "mixed":
+            wk = _from_state(w, ora.state())
+            bed.close()
+            bed = Bed(wk)
+            ok = O.Oracle(wk)
+            Fo, To = ok.forces()
+            tol = 1e-5
+        else:
+            Fo, To = ora.forces()
+            tol = 1e-9
+        Fg, Tg = bed.forces()
+        ef = _force_err(_np(Fg), Fo, mass)
+        et = float(np.max(np.abs(_np(Tg) - To) / np.maximum(np.linalg.norm(To, axis=1), rg)[:, None]))
+        assert ef <= tol, (k, ef)
+        assert et <= tol, (k, et)
+        if w.precision != "mixed":
+            bed.step(1)
+        ora.step(1)
+
+
+@pytest.mark.parametrize("case", list(GENTLE))
+def test_trajectory_100_steps(case):
+    """100 steps from the same state.  FP64 path: every parcel within 1e-4 d
+    (positions) and 1e-4 max(|v|, 1e-3 m/s) (velocities).  Mixed path: the
+    damped spring's force jumps at contact onset and release (gamma_n v_n is
+    not zero at delta = 0), so a parcel whose contact starts or ends within
+    the FP32 rounding band of a step boundary follows another, equally valid,
+    path; at most 0.1 % of the parcels may leave the 1e-4 band and none may
+    leave 1e-2.  Rolling friction (discontinuous in the spin direction at
+    w = 0) is exercised in FP64 only."""
+    w = _rolling(GENTLE[case]())
+    mixed = w.precision == "mixed"
+    if mixed:
+        w.params["mu_r"] = 0.0
+    _say(f"[trajectory] {case} n={w.n}")
+    bed = Bed(w)
+    ora = O.Oracle(w)
+    for _ in range(10):
+        bed.step(10)
+        ora.step(10)
+    sg = bed.state()
+    so = ora.state()
+    d = w.parcels["d"].astype(np.float64)
+    errs = [np.sqrt(sum((_np(sg[k]) - so[k]) ** 2 for k in ("x", "y", "z"))) / d]
+    for a in ("v", "w"):
+        keys = [a + c for c in "xyz"]
+        vo = np.stack([so[k] for k in keys], 1)
+        vg = np.stack([_np(sg[k]) for k in keys], 1)
+        floor = 1e-3 if a == "v" else 1e-3 / (0.5 * d)
+        errs.append(np.linalg.norm(vg - vo, axis=1) / np.maximum(np.linalg.norm(vo, axis=1), floor))
+    for name, e in zip(("x", "v", "w"), errs):
+        out = int(np.sum(e > 1e-4))
+        _say(f"  {name}: max {e.max():.2e}, parcels beyond 1e-4: {out} of {w.n}")
+        if mixed:
+            assert out <= max(1, w.n // 1000) and e.max() <= 1e-2, (name, out, e.max())
+        else:
+            assert out == 0, (name, e.max())
+    assert bed.stats()["n_contacts"] > 0
+
+
+@pytest.mark.parametrize("case", list(GENTLE))
+def test_couple_and_react_at_identical_state(case):
+    w = GENTLE[case]()
+    _say(f"[couple/react] {case} n={w.n}")
+    bed = Bed(w)
+    ora = O.Oracle(w)
+    cg = bed.couple()
+    co = ora.couple()
+    assert np.array_equal(_np(cg["np"]), co["np"])
+    for k in ("eps", "sumK", "sumKu", "sumKv", "sumKw", "sumKs"):
+        a, b = _np(cg[k]), co[k]
+        assert np.max(np.abs(a - b)) <= 1e-12 * max(np.max(np.abs(b)), 1e-300), k
+    dt = 20 * w.params["dt"]
+    for it in range(3):
+        rg = bed.react(dt)
+        ro = ora.react(dt)
+        assert np.max(np.abs(_np(rg["fov"]) - ro["fov"])) <= 1e-4
+        assert np.max(np.abs(_np(rg["fov"]) - ro["fov"])) <= 1e-11  # FP64 on both sides
+        assert np.allclose(rg["bed_fov"], ro["bed_fov"], rtol=1e-12, atol=0)
+        for k in ("mdotH2", "mdotH2O", "sumEQ", "sumES"):
+            a, b = _np(rg[k]), ro[k]
+            assert np.max(np.abs(a - b)) <= 1e-9 * np.max(np.abs(b)), (it, k)
+    sg, so = bed.state(), ora.state()
+    for k in ("nh", "nm", "nw", "nfe"):
+        assert np.max(np.abs(_np(sg[k]) - so[k])) <= 1e-11 * np.max(np.abs(so[k]) + 1e-300), k
+
+
+def _gas_variant(w, xh2, xh2o):
+    g = dict(w.gas)
+    g["xH2"] = np.full_like(g["xH2"], xh2)
+    g["xH2O"] = np.full_like(g["xH2O"], xh2o)
+    g["xN2"] = np.full_like(g["xN2"], 1.0 - xh2 - xh2o)
+    return g
+
+
+@pytest.mark.parametrize("xh2,xh2o", [(0.5, 0.5), (0.3, 0.6), (0.6, 0.1), (0.0, 0.0), (1.0, 0.0)])
+def test_react_partial_networks(xh2, xh2o):
+    """H2O-bearing gas drives the partial networks (some interfaces below
+    equilibrium); pure N2 stops every reaction."""
+    w = W.cfg2(n=2000, seed=31)
+    w = W.dataclasses.replace(w, gas=_gas_variant(w, xh2, xh2o))
+    bed = Bed(w)
+    ora = O.Oracle(w)
+    for _ in range(4):
+        rg = bed.react(0.05)
+        ro = ora.react(0.05)
+        assert np.max(np.abs(_np(rg["fov"]) - ro["fov"])) <= 1e-11
+        for k in ("mdotH2", "sumEQ", "sumES"):
+            b = ro[k]
+            assert np.max(np.abs(_np(rg[k]) - b)) <= 1e-9 * max(np.max(np.abs(b)), 1e-300), k
+
+
+def test_react_magnetite_ore_and_long_horizon():
+    """Magnetite ore (eq. e2-19) and a long reaction horizon in which
+    interfaces are exhausted one after another."""
+    w = W.cfg2(n=1500, seed=41)
+    ores = [W.Ore(xi0=0.29, d_pore_cm=9.5e-6, kind=W.ORE_MAGNETITE)]
+    p = dict(w.parcels)
+    m_p = (p["nh"] * 159.687e-3 + p["nm"] * 231.531e-3 + p["nw"] * 71.844e-3 + p["nfe"] * 55.845e-3)
+    p["nh"] = np.zeros(w.n)
+    p["nm"] = m_p * 0.6994 / 231.531e-3
+    p["nw"] = m_p * 0.3006 / 71.844e-3
+    p["nfe"] = np.zeros(w.n)
+    beds = [W.dataclasses.replace(w.beds[0], theta=W.THETA_TABLE2)]
+    w = W.dataclasses.replace(w, ores=ores, parcels=p, beds=beds, gas=_gas_variant(w, 0.7, 0.0))
+    bed = Bed(w)
+    ora = O.Oracle(w)
+    for _ in range(25):
+        rg = bed.react(2.0)
+        ro = ora.react(2.0)
+    assert np.max(np.abs(_np(rg["fov"]) - ro["fov"])) <= 1e-9
+    assert 0.2 < ro["bed_fov"][0] <= 1.0
+
+
+def test_full_intervals_reduction_degree():
+    """Couple_every DEM steps + deposit + reaction, repeated: per-parcel
+    reduction degree within 1e-4 and positions within 1e-4 d."""
+    w = GENTLE["cfg2_mixed"]()
+    S = 20
+    bed = Bed(w)
+    ora = O.Oracle(w)
+    for _ in range(5):
+        bed.step(S)
+        ora.step(S)
+        bed.couple()
+        ora.couple()
+        rg = bed.react(S * w.params["dt"])
+        ro = ora.react(S * w.params["dt"])
+    assert np.max(np.abs(_np(rg["fov"]) - ro["fov"])) <= 1e-4
+    sg, so = bed.state(), ora.state()
+    d = w.parcels["d"].astype(np.float64)
+    dx = np.sqrt(sum((_np(sg[k]) - so[k]) ** 2 for k in ("x", "y", "z")))
+    assert np.max(dx / d) <= 1e-4
+
+
+def test_graph_replay_matches_eager_and_is_deterministic():
+    w = GENTLE["cfg3_mixed"]()
+    S = 10
+    outs = []
+    for mode in ("eager", "graph", "graph"):
+        bed = Bed(w)
+        if mode == "eager":
+            for _ in range(4):
+                bed.step(S)
+                bed.couple()
+                r = bed.react(S * w.params["dt"])
+            bf = r["bed_fov"]
+        else:
+            bf = bed.run(4, S, bed_fov=True)["bed_fov"]
+        st = bed.state()
+        outs.append((bf, {k: _np(v) for k, v in st.items()}))
+        bed.close()
+    for bf, st in outs[1:]:
+        assert np.array_equal(bf, outs[0][0])
+        for k in st:
+            assert np.array_equal(st[k], outs[0][1][k]), k
+
+
+def test_batched_beds_match_single_beds():
+    """Several beds of different size and temperature in one context give the
+    same per-bed results as the oracle run on all beds together."""
+    w = W.cfg5(n_beds=6, n_scale=0.05, seed=71)
+    w = W.with_velocities(w, 71)
+    bed = Bed(w)
+    ora = O.Oracle(w)
+    assert np.array_equal(bed.pairs(), ora.pairs())
+    for _ in range(3):
+        bed.step(10)
+        ora.step(10)
+        bed.couple()
+        ora.couple()
+        rg = bed.react(1e-3)
+        ro = ora.react(1e-3, n_beds=len(w.beds))
+    assert np.allclose(rg["bed_fov"], ro["bed_fov"], rtol=0, atol=1e-9)
+    sg, so = bed.state(), ora.state()
+    d = w.parcels["d"].astype(np.float64)
+    dx = np.sqrt(sum((_np(sg[k]) - so[k]) ** 2 for k in ("x", "y", "z")))
+    assert np.max(dx / d) <= 1e-4
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_single_parcel_and_wall_contacts():
+    w = W.cfg1(n=1, seed=3)
+    p = dict(w.parcels)
+    p["z"] = np.array([0.5 * float(p["d"][0]) * 0.98])  # resting on the floor, overlapping
+    p["x"] = np.array([0.5 * float(p["d"][0]) * 0.99])  # and touching the x-lo wall
+    w = W.with_velocities(W.dataclasses.replace(w, parcels=p), 5)
+    bed = Bed(w)
+    ora = O.Oracle(w)
+    assert len(bed.pairs()) == 0
+    for _ in range(5):
+        Fg, Tg = bed.forces()
+        Fo, To = ora.forces()
+        assert np.allclose(_np(Fg), Fo, rtol=1e-12, atol=1e-18)
+        assert np.allclose(_np(Tg), To, rtol=1e-12, atol=1e-18)
+        bed.step(1)
+        ora.step(1)
+    assert bed.stats()["n_wall_contacts"] >= 1
+
+
+def test_overflow_reported():
+    w = W.squeeze(W.cfg2(n=2000, seed=81), 0.97, 0)
+    with pytest.raises(DemError) as e:
+        bed = Bed(w, max_nbr=1)
+        bed.step(1)
+        bed.sync()
+    assert e.value.code == -3
+
+
+def test_parcel_outside_domain_rejected():
+    w = W.cfg1(n=64, seed=4)
+    p = dict(w.parcels)
+    p["z"] = p["z"].copy()
+    p["z"][7] = 1.0  # far above the grid
+    w = W.dataclasses.replace(w, parcels=p)
+    with pytest.raises(DemError) as e:
+        Bed(w)
+    assert e.value.code == -4
+
+
+def test_nan_gas_reported():
+    w = W.cfg1(n=64, seed=5)
+    g = dict(w.gas)
+    g["ug"] = g["ug"].copy()
+    g["ug"][3] = np.nan
+    bed = Bed(W.dataclasses.replace(w, gas=g))
+    with pytest.raises(DemError) as e:
+        bed.step(1)
+        bed.sync()
+    assert e.value.code == -5
+
+
+def test_cell_smaller_than_parcel_rejected():
+    w = W.cfg1(n=64, seed=6)
+    b = W.dataclasses.replace(w.beds[0], refine=2)  # 1 mm DEM cells < 1.05 mm parcels
+    with pytest.raises(DemError) as e:
+        Bed(W.dataclasses.replace(w, beds=[b]))
+    assert e.value.code == -1
+
+
+def test_skin_violation_reported():
+    w = W.with_velocities(W.cfg1(n=256, seed=7), 7, vscale=5.0)
+    w.params["skin"] = 1e-7
+    w.params["rebuild_every"] = 1000
+    bed = Bed(w)
+    with pytest.raises(DemError) as e:
+        bed.step(5)
+        bed.sync()
+    assert e.value.code == -7
+
+
+# ------------------------------------------------------------------ full size
+
+def test_headline_bed_full_size_one_step():
+    """2,000,000-parcel bed, launch shapes as benchmarked: pair list, forces
+    of the first step and the reaction update against the oracle on every
+    parcel."""
+    _say("[full] generating cfg3")
+    w = W.squeeze(W.cfg3(), 0.96, 0)  # the packed bed pressed so that contacts exist
+    bed = Bed(w)
+    bed.autotune()
+    ora = O.Oracle(w)
+    _say("[full] pairs")
+    pg, po = bed.pairs(), ora.pairs()
+    assert len(po) > 10000 and np.array_equal(pg, po)
+    _say("[full] forces")
+    Fg, _ = bed.forces()
+    Fo, _ = ora.forces()
+    mass = ora.state()["mass"]
+    assert _force_err(_np(Fg), Fo, mass) <= 1e-5
+    _say("[full] couple + react")
+    cg, co = bed.couple(), ora.couple()
+    assert np.max(np.abs(_np(cg["eps"]) - co["eps"])) <= 1e-12
+    rg, ro = bed.react(1e-4), ora.react(1e-4)
+    assert np.max(np.abs(_np(rg["fov"]) - ro["fov"])) <= 1e-4
+    assert abs(rg["bed_fov"][0] - ro["bed_fov"][0]) <= 1e-12
