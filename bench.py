@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=None, help="parcel count (default: the 2M-parcel bed)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain device copy of 512 MiB three times (for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no multi-GPU mode",
@@ -94,6 +96,14 @@ def main():
     from paper_2311_03908_amd import workloads as W
     from paper_2311_03908_amd.bed import Bed
 
+    if args.copy_calibration:
+        src = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        _log("[bench] copy calibration: 3 x 512 MiB read + 512 MiB write")
+        del src, dst
     _log("[bench] generating workload")
     w = W.cfg3() if args.n is None else W.cfg3(n=args.n)
     S = w.couple_every

@@ -110,6 +110,10 @@ struct Ctx final : dem_ctx {
   Nbr<T> nb[2]{};
   int cur = 0, pc = 0, nbc = 0;
   int32_t *key = nullptr, *slot = nullptr, *count = nullptr, *start = nullptr, *perm = nullptr, *scan_scr = nullptr;
+  int32_t *perm2 = nullptr;
+  int4 *bchunks = nullptr;
+  double *bpartial = nullptr;
+  int max_chunks = 0;
   int32_t *iflags = nullptr, *ioffs = nullptr, *ilist = nullptr, *icount = nullptr;
   T *gtab = nullptr;
   double *eps = nullptr, *pm = nullptr, *pw = nullptr, *bed_fov_d = nullptr, *theta_d = nullptr;
@@ -121,7 +125,7 @@ struct Ctx final : dem_ctx {
   long pairs_cap = 0;
   long step_count = 0, steps_since = 0, rebuilds = 0;
   bool built = false;
-  int step_block = 256, build_grid = 2048;
+  int step_block = 256, build_grid = 1024;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<const void *> gkey;
@@ -161,15 +165,17 @@ struct Ctx final : dem_ctx {
   } while (0)
 
   int alloc_dyn(Dyn<T> &d) {
-    TRY(dalloc(d.x, n)); TRY(dalloc(d.y, n)); TRY(dalloc(d.z, n));
-    TRY(dalloc(d.vx, n)); TRY(dalloc(d.vy, n)); TRY(dalloc(d.vz, n));
-    TRY(dalloc(d.wx, n)); TRY(dalloc(d.wy, n)); TRY(dalloc(d.wz, n));
+    TRY(dalloc(d.pos, n));
+    TRY(dalloc(d.vel, n));
     return DEMRX_OK;
   }
-  int alloc_props(Props<T> &p) {
-    TRY(dalloc(p.rad, n)); TRY(dalloc(p.kcg, n)); TRY(dalloc(p.mass, n)); TRY(dalloc(p.zeta, n));
-    TRY(dalloc(p.tag, n)); TRY(dalloc(p.id, n));
+  int alloc_props(Props<T> &p, const Props<T> *shared) {
+    TRY(dalloc(p.kcg, n)); TRY(dalloc(p.tag, n));
     TRY(dalloc(p.nh, n)); TRY(dalloc(p.nm, n)); TRY(dalloc(p.nw, n)); TRY(dalloc(p.nfe, n));
+    if (shared) {  // wall springs are indexed by original id: one copy
+      p.wh = shared->wh;
+      return DEMRX_OK;
+    }
     TRY(dalloc(p.wh, (size_t)3 * kMaxWalls * n));
     return DEMRX_OK;
   }
@@ -240,16 +246,37 @@ struct Ctx final : dem_ctx {
         for (int iy = 0; iy < d.nd[1]; iy++)
           for (int x0 = 0; x0 < d.nd[0]; x0 += kItemX) hit.push_back(Item{b, x0, iy, iz});
     }
+    // largest parcel per bed against the DEM cell (checked on the host once)
+    {
+      std::vector<float> hd(n);
+      std::vector<int32_t> hb(n);
+      HIPCHK(hipMemcpyAsync(hd.data(), in->d, n * sizeof(float), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hb.data(), in->bed, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      std::vector<double> dmax(p->n_beds, 0.0);
+      for (int i = 0; i < n; i++)
+        if (hb[i] >= 0 && hb[i] < p->n_beds) dmax[hb[i]] = std::max(dmax[hb[i]], (double)hd[i]);
+      for (int b = 0; b < p->n_beds; b++) {
+        if (hbd[b].hd < dmax[b] + p->skin)
+          return fail(DEMRX_EINVAL, "bed " + std::to_string(b) + ": DEM cell " + std::to_string(hbd[b].hd) +
+                                        " m is smaller than the largest parcel plus skin (" +
+                                        std::to_string(dmax[b] + p->skin) + " m)");
+        hbd[b].rmax = 0.5 * dmax[b];
+      }
+    }
     TRY(dalloc(beds, hbd.size()));
     TRY(dalloc(ores, hod.size()));
     TRY(dalloc(cell_bed, n_gas));
     TRY(dalloc(items, n_items));
     for (int k = 0; k < 2; k++) {
       TRY(alloc_dyn(dyn[k]));
-      TRY(alloc_props(pr[k]));
+      TRY(alloc_props(pr[k], k ? &pr[0] : nullptr));
       TRY(alloc_nbr(nb[k]));
     }
-    TRY(dalloc(key, n)); TRY(dalloc(slot, n)); TRY(dalloc(perm, n));
+    TRY(dalloc(key, n)); TRY(dalloc(slot, n)); TRY(dalloc(perm, n)); TRY(dalloc(perm2, n));
+    max_chunks = n / kBedChunk + p->n_beds + 2;
+    TRY(dalloc(bchunks, max_chunks));
+    TRY(dalloc(bpartial, 2 * (size_t)max_chunks));
     TRY(dalloc(count, (size_t)n_keys + 1)); TRY(dalloc(start, (size_t)n_keys + 1));
     const long scr = std::max(scan_scratch_ints((long)n_keys + 1), scan_scratch_ints((long)n_items + 1));
     TRY(dalloc(scan_scr, scr));
@@ -274,22 +301,6 @@ struct Ctx final : dem_ctx {
     launch_fill_u32((uint32_t *)counters, 0u, 8, st);
     launch_init<T>(*in, n, ph, p->n_ores, dyn[0], pr[0], status, st);
     HIPCHK(hipGetLastError());
-    // largest parcel per bed against the DEM cell (checked on the host once)
-    {
-      std::vector<float> hd(n);
-      std::vector<int32_t> hb(n);
-      HIPCHK(hipMemcpyAsync(hd.data(), in->d, n * sizeof(float), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(hb.data(), in->bed, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      std::vector<double> dmax(p->n_beds, 0.0);
-      for (int i = 0; i < n; i++)
-        if (hb[i] >= 0 && hb[i] < p->n_beds) dmax[hb[i]] = std::max(dmax[hb[i]], (double)hd[i]);
-      for (int b = 0; b < p->n_beds; b++)
-        if (hbd[b].hd < dmax[b] + p->skin)
-          return fail(DEMRX_EINVAL, "bed " + std::to_string(b) + ": DEM cell " + std::to_string(hbd[b].hd) +
-                                        " m is smaller than the largest parcel plus skin (" +
-                                        std::to_string(dmax[b] + p->skin) + " m)");
-    }
     TRY(check_status());
     TRY(rebuild());
     DepositOut o{};
@@ -319,8 +330,8 @@ struct Ctx final : dem_ctx {
     launch_fill_i32(count, 0, (long)n_keys + 1, st);
     launch_bin<T>(dyn[cur], pr[pc], beds, n, key, slot, count, status, st);
     launch_scan(count, start, (long)n_keys + 1, scan_scr, st);
-    launch_scatter(key, slot, start, n, perm, st);
-    launch_cellsort(start, n_keys, pr[pc].id, perm, st);
+    launch_scatter(key, slot, start, n, perm2, st);
+    launch_cellrank(start, key, dyn[cur].pos, perm2, n, perm, st);
     launch_permute<T>(perm, n, dyn[cur], pr[pc], dyn[cur ^ 1], pr[pc ^ 1], vmax, disp, st);
     cur ^= 1;
     pc ^= 1;
@@ -328,7 +339,7 @@ struct Ctx final : dem_ctx {
     NbrBuild<T> a;
     a.d = dyn[cur];
     a.p = pr[pc];
-    a.id_old = pr[pc ^ 1].id;
+    a.pos_old = dyn[cur ^ 1].pos;
     a.perm = perm;
     a.nb_new = nb[nbc ^ 1];
     a.nb_old = nb[nbc];
@@ -464,7 +475,7 @@ struct Ctx final : dem_ctx {
     launch_react<T>(a, st);
     if (o && (o->mdotH2 || o->mdotH2O || o->sumEQ || o->sumES))
       launch_cellsum(pm, n, start, cell_bed, beds, n_gas, o->mdotH2, o->mdotH2O, o->sumEQ, o->sumES, st);
-    if (bed_sum) launch_bedsum(pw, n, start, beds, P.n_beds, bed_fov_d, st);
+    if (bed_sum) launch_bedsum(pw, n, start, beds, P.n_beds, bchunks, max_chunks, bpartial, bed_fov_d, st);
     HIPCHK(hipGetLastError());
     return DEMRX_OK;
   }
@@ -699,7 +710,7 @@ struct Ctx final : dem_ctx {
     // neighbour build: persistent grid size
     best = 1e30f;
     int best_g = build_grid;
-    for (int gsz : {512, 1024, 2048, 4096, 8192}) {
+    for (int gsz : {256, 512, 1024, 2048, 4096}) {
       build_grid = gsz;
       float tot = 0.0f;
       for (int rep = 0; rep < 3; rep++) {

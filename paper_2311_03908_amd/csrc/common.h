@@ -27,6 +27,7 @@ struct BedDev {
   int n_gas, n_dem;
   double theta[6];
   double mu_override;
+  double rmax;           // largest parcel radius in the bed
 };
 
 // Per-ore constants: porosities of the Fe3O4, FeO, Fe layers (eqs. e2-31..e2-36)
@@ -42,22 +43,36 @@ struct Phys {
   int ergun_printed, drag_on, n_beds, n_ores, max_nbr;
 };
 
-// Double-buffered dynamic state (swapped every step)
+// Parcel records, double-buffered (the step reads one buffer and writes the
+// other).  One 32-byte position record per parcel, so that a neighbour's
+// position, radius and id arrive in one memory transaction; the velocity
+// record holds what is only read for parcels in contact.
+struct alignas(32) PosRec {
+  double x, y, z;
+  float r;      // parcel radius d/2 (FP32-representable)
+  uint32_t id;  // original parcel id
+};
+template <typename T>
+struct alignas(sizeof(T) * 8) VelRec {
+  T v[3], w[3];
+  T m;     // parcel mass
+  T zeta;  // damping ratio of the parcel's coarse-grained restitution
+};
 template <typename T>
 struct Dyn {
-  double *x, *y, *z;
-  T *vx, *vy, *vz, *wx, *wy, *wz;
+  PosRec *pos;
+  VelRec<T> *vel;
 };
 
-// Per-parcel properties, permuted with the parcels at every rebuild
+// Per-parcel properties.  kcg, tag and the species are permuted with the
+// parcels at every rebuild; the wall springs, touched only in wall contact,
+// stay in original-id order.
 template <typename T>
 struct Props {
-  float *rad, *kcg;
-  T *mass, *zeta;
+  float *kcg;
   int32_t *tag;  // bed * 256 + ore
-  uint32_t *id;  // original parcel id
   double *nh, *nm, *nw, *nfe;
-  T *wh;         // wall tangential springs: [(wall * 3 + axis) * N + i]
+  T *wh;         // wall tangential springs by original id: [(wall * 3 + axis) * N + id]
 };
 
 // Neighbour list (slot-major) with the pair tangential springs of each slot
@@ -68,6 +83,31 @@ struct Nbr {
   T *hist;         // [(axis * kMaxNbr + slot) * N + i]
   uint64_t *mask;  // bit s: slot s in contact last step; bits 48..53: walls
 };
+
+// Vector loads of the records (one 16-byte transaction per half)
+__device__ __forceinline__ PosRec load_pos(const PosRec *p, long i) {
+  const double4 a = *reinterpret_cast<const double4 *>(p + i);
+  PosRec r;
+  r.x = a.x;
+  r.y = a.y;
+  r.z = a.z;
+  const uint64_t bits = (uint64_t)__double_as_longlong(a.w);
+  r.r = __uint_as_float((uint32_t)bits);
+  r.id = (uint32_t)(bits >> 32);
+  return r;
+}
+__device__ __forceinline__ void store_pos(PosRec *p, long i, const PosRec &r) {
+  const uint64_t bits = ((uint64_t)r.id << 32) | (uint64_t)__float_as_uint(r.r);
+  *reinterpret_cast<double4 *>(p + i) = make_double4(r.x, r.y, r.z, __longlong_as_double((long long)bits));
+}
+
+// Block index remapped so that the 8 XCDs, which receive workgroups in turn,
+// each work on one contiguous eighth of the grid and keep their neighbours'
+// records in their own L2.  The grid is a multiple of 8.
+__device__ __forceinline__ int xcd_block() {
+  const int per = gridDim.x >> 3;
+  return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+}
 
 __device__ __forceinline__ int bed_of(int32_t tag) { return tag >> 8; }
 __device__ __forceinline__ int ore_of(int32_t tag) { return tag & 255; }

@@ -117,18 +117,40 @@ void launch_scan(const int32_t *in, int32_t *out, long m, int32_t *scratch, hipS
 }
 
 // ------------------------------------------------------------------ binning
+// Bin parcels by DEM cell.  Parcels arrive in the order of the last sort, so
+// runs of equal keys are common inside a wave: one atomic per run reserves
+// the run's slots.
 template <typename T>
 __global__ void k_bin(Dyn<T> d, Props<T> p, const BedDev *beds, int n, int32_t *key, int32_t *slot,
                       int32_t *count, uint32_t *status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double x = d.x[i], y = d.y[i], z = d.z[i];
-  const BedDev &B = beds[bed_of(p.tag[i])];
-  Cells c;
-  if (!(isfinite(x) && isfinite(y) && isfinite(z))) atomicOr(status, ST_NONFINITE);
-  if (!locate(B, x, y, z, c)) atomicOr(status, ST_DOMAIN);
-  key[i] = c.dem;
-  slot[i] = atomicAdd(&count[c.dem], 1);
+  const int lane = threadIdx.x & 63;
+  int k = -1;
+  if (i < n) {
+    const PosRec q = load_pos(d.pos, i);
+    const BedDev &B = beds[bed_of(p.tag[i])];
+    Cells c;
+    if (!(isfinite(q.x) && isfinite(q.y) && isfinite(q.z))) atomicOr(status, ST_NONFINITE);
+    if (!locate(B, q.x, q.y, q.z, c)) atomicOr(status, ST_DOMAIN);
+    k = c.dem;
+  }
+  const int prev = __shfl_up(k, 1, 64);
+  const bool head = (i < n) && (lane == 0 || prev != k);
+  const uint64_t heads = __ballot(head);
+  const uint64_t below = heads & ((2ull << lane) - 1ull);      // heads at or below this lane
+  const int my_head = 63 - __clzll((long long)below);
+  const uint64_t above = heads & ~((2ull << lane) - 1ull);     // heads after this lane
+  const int next_head = above ? __ffsll((unsigned long long)above) - 1 : 64;
+  int base = 0;
+  if (head) {
+    const int len = min(next_head, (int)((n - (i - lane)) < 64 ? (n - (i - lane)) : 64)) - lane;
+    base = atomicAdd(&count[k], len);
+  }
+  base = __shfl(base, my_head, 64);
+  if (i < n) {
+    key[i] = k;
+    slot[i] = base + (lane - my_head);
+  }
 }
 
 template <typename T>
@@ -146,26 +168,28 @@ void launch_scatter(const int32_t *key, const int32_t *slot, const int32_t *star
   k_scatter<<<(n + 255) / 256, 256, 0, s>>>(key, slot, start, n, perm);
 }
 
-// Order the parcels of each cell by original id (the atomic slot order is not
-// reproducible); cells hold tens of parcels, so one thread per cell sorts by
-// insertion.
-__global__ void k_cellsort(const int32_t *start, int n_keys, const uint32_t *id_old, int32_t *perm) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_keys) return;
+// Order the parcels of each cell by x, ties by original id (the atomic slot
+// order is not reproducible; x order makes every row of cells x-sorted for the
+// candidate search): every parcel counts the members of its cell that precede
+// it and moves to that rank.
+__global__ void k_cellrank(const int32_t *start, const int32_t *key, const PosRec *pos_old, const int32_t *perm,
+                           int n, int32_t *perm_out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int v = perm[p];
+  const int c = key[v];
   const int s = start[c], e = start[c + 1];
-  for (int a = s + 1; a < e; a++) {
-    const int v = perm[a];
-    const uint32_t key = id_old[v];
-    int b = a - 1;
-    while (b >= s && id_old[perm[b]] > key) {
-      perm[b + 1] = perm[b];
-      b--;
-    }
-    perm[b + 1] = v;
+  const PosRec me = load_pos(pos_old, v);
+  int rank = 0;
+  for (int q = s; q < e; q++) {
+    const PosRec o = load_pos(pos_old, perm[q]);
+    rank += (o.x < me.x || (o.x == me.x && o.id < me.id)) ? 1 : 0;
   }
+  perm_out[s + rank] = v;
 }
-void launch_cellsort(const int32_t *start, int n_keys, const uint32_t *id_old, int32_t *perm, hipStream_t s) {
-  k_cellsort<<<(n_keys + 255) / 256, 256, 0, s>>>(start, n_keys, id_old, perm);
+void launch_cellrank(const int32_t *start, const int32_t *key, const PosRec *pos_old, const int32_t *perm, int n,
+                     int32_t *perm_out, hipStream_t s) {
+  k_cellrank<<<(n + 255) / 256, 256, 0, s>>>(start, key, pos_old, perm, n, perm_out);
 }
 
 template <typename T>
@@ -179,27 +203,14 @@ __global__ void k_permute(const int32_t *perm, int n, Dyn<T> din, Props<T> pin, 
   }
   if (j >= n) return;
   const int i = perm[j];
-  dout.x[j] = din.x[i];
-  dout.y[j] = din.y[i];
-  dout.z[j] = din.z[i];
-  dout.vx[j] = din.vx[i];
-  dout.vy[j] = din.vy[i];
-  dout.vz[j] = din.vz[i];
-  dout.wx[j] = din.wx[i];
-  dout.wy[j] = din.wy[i];
-  dout.wz[j] = din.wz[i];
-  pout.rad[j] = pin.rad[i];
+  store_pos(dout.pos, j, load_pos(din.pos, i));
+  dout.vel[j] = din.vel[i];
   pout.kcg[j] = pin.kcg[i];
-  pout.mass[j] = pin.mass[i];
-  pout.zeta[j] = pin.zeta[i];
   pout.tag[j] = pin.tag[i];
-  pout.id[j] = pin.id[i];
   pout.nh[j] = pin.nh[i];
   pout.nm[j] = pin.nm[i];
   pout.nw[j] = pin.nw[i];
   pout.nfe[j] = pin.nfe[i];
-#pragma unroll
-  for (int k = 0; k < 3 * kMaxWalls; k++) pout.wh[(long)k * n + j] = pin.wh[(long)k * n + i];
 }
 
 template <typename T>
@@ -248,151 +259,158 @@ void launch_items(const Item *items, int n_items, const BedDev *beds, const int3
 }
 
 // ------------------------------------------------------------------ neighbour build
-// Work item: kItemX consecutive DEM cells of one row.  For each of the three
-// z-planes of the stencil, the three rows (dy = -1..1) spanning x0-1 .. x0+kItemX
-// are staged in LDS (relative FP32 positions and radii, one coalesced pass);
-// each wave then takes centre parcels one at a time and its 64 lanes test the
-// centre's own 3x3 candidate cells of that plane, compacting hits with a
-// ballot.  Candidates are pairs closer than r_i + r_j + skin (conservative
-// FP32 test); exact contact is decided each step.
-constexpr int kCandMax = 3072;  // staged candidates per plane
-constexpr int kCentMax = 512;   // centres per pass
-constexpr int kBuildThreads = 256;
+// Work item: kItemX consecutive DEM cells of one row of a bed.  The nine rows
+// of its 3x3 (y, z) stencil, each spanning x0-1 .. x0+kItemX, are staged in
+// LDS (FP32 positions relative to the item corner, radii, sorted indices) as
+// many rows at a time as fit; every thread owns one centre parcel of the item
+// and tests the 3 cells of each staged row around its own cell, appending the
+// candidates closer than r_i + r_j + skin (conservative FP32 test; the exact
+// contact test runs every step) to its slot-major list.  The tangential
+// springs of partners already in contact are then carried over from the
+// previous list.
+constexpr int kCandMax = 2048;
+constexpr int kBuildThreads = 512;
 
 template <typename T>
 __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
   __shared__ float4 cpos[kCandMax];
   __shared__ int cidx[kCandMax];
-  __shared__ int ccnt[kCentMax];
-  __shared__ int rstart[3][kItemX + 3];  // global start of each staged cell (+ end)
-  __shared__ int roff[4];                // LDS offset of each staged row
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  __shared__ int rstart[9][kItemX + 3];  // global start of each staged cell of each row (+ end)
+  __shared__ int roff[10];
   const int n_list = *a.list_count;
   const long N = a.n;
   const float cut_scale = 1.0f + 1e-5f;
+  const int tid = threadIdx.x;
   for (int w = blockIdx.x; w < n_list; w += gridDim.x) {
     const Item it = a.items[a.list[w]];
     const BedDev &B = a.beds[it.bed];
     const int xc = min(kItemX, B.nd[0] - it.x0);
-    const int c0 = a.start[item_key(B, it.x0, it.iy, it.iz)];
-    const int c1 = a.start[item_key(B, it.x0 + xc - 1, it.iy, it.iz) + 1];
     const int xa = max(it.x0 - 1, 0), xb = min(it.x0 + xc, B.nd[0] - 1);
-    const int nx = xb - xa + 1;  // staged cells per row
+    const int nx = xb - xa + 1;
+    __syncthreads();
+    for (int t = tid; t < 9 * (nx + 1); t += blockDim.x) {
+      const int r = t / (nx + 1), q = t % (nx + 1);
+      const int iy2 = it.iy + (r % 3) - 1, iz2 = it.iz + (r / 3) - 1;
+      int v = 0;
+      if (iy2 >= 0 && iy2 < B.nd[1] && iz2 >= 0 && iz2 < B.nd[2]) v = a.start[item_key(B, xa + q, iy2, iz2)];
+      rstart[r][q] = v;
+    }
+    __syncthreads();
+    const int c0 = rstart[4][it.x0 - xa], c1 = rstart[4][it.x0 + xc - xa];
     const double xr = B.origin[0] + it.x0 * B.hd, yr = B.origin[1] + it.iy * B.hd, zr = B.origin[2] + it.iz * B.hd;
-    for (int cb = c0; cb < c1; cb += kCentMax) {
-      const int nc = min(kCentMax, c1 - cb);
-      for (int t = threadIdx.x; t < nc; t += blockDim.x) ccnt[t] = 0;
-      for (int dz = -1; dz <= 1; dz++) {
-        const int iz2 = it.iz + dz;
-        if (iz2 < 0 || iz2 >= B.nd[2]) continue;
-        __syncthreads();
-        if (threadIdx.x < 3 * (nx + 1)) {
-          const int r = threadIdx.x / (nx + 1), q = threadIdx.x % (nx + 1);
-          const int iy2 = it.iy + r - 1;
-          int v = 0;
-          if (iy2 >= 0 && iy2 < B.nd[1]) v = a.start[item_key(B, xa + q, iy2, iz2)];
-          rstart[r][q] = v;
+    for (int cb = c0; cb < c1; cb += blockDim.x) {
+      const int i = cb + tid;
+      const bool mine = i < c1;
+      float xi = 0.f, yi = 0.f, zi = 0.f, rs = 0.f;
+      int cnt = 0;
+      float cut_hi = 0.f;
+      if (mine) {
+        const PosRec pi = load_pos(a.d.pos, i);
+        xi = (float)(pi.x - xr);
+        yi = (float)(pi.y - yr);
+        zi = (float)(pi.z - zr);
+        rs = pi.r + (float)a.skin;
+        // widest candidate distance along x for this centre
+        cut_hi = (rs + (float)B.rmax) * cut_scale + 1e-9f;
+      }
+      int row = 0;
+      while (row < 9) {
+        // as many consecutive rows as fit in LDS
+        int re = row, tot = 0;
+        while (re < 9) {
+          const int len = rstart[re][nx] - rstart[re][0];
+          if (tot + len > kCandMax) break;
+          tot += len;
+          re++;
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-          int o = 0;
-          for (int r = 0; r < 3; r++) {
-            roff[r] = o;
-            const int iy2 = it.iy + r - 1;
-            if (iy2 >= 0 && iy2 < B.nd[1]) o += rstart[r][nx] - rstart[r][0];
-          }
-          roff[3] = o;
-        }
-        __syncthreads();
-        const int tot = roff[3];
-        if (tot > kCandMax) {
-          if (threadIdx.x == 0) atomicOr(a.status, ST_OVERFLOW);
+        if (re == row) {  // one row alone exceeds the tile
+          if (tid == 0) atomicOr(a.status, ST_OVERFLOW);
+          row++;
           continue;
         }
-        for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-          const int r = t >= roff[2] ? 2 : (t >= roff[1] ? 1 : 0);
+        __syncthreads();
+        if (tid == 0) {
+          int o = 0;
+          for (int r = row; r < re; r++) {
+            roff[r] = o;
+            o += rstart[r][nx] - rstart[r][0];
+          }
+          roff[re] = o;
+        }
+        __syncthreads();
+        for (int t = tid; t < tot; t += blockDim.x) {
+          int r = row;
+          while (r + 1 < re && roff[r + 1] <= t) r++;
           const int j = rstart[r][0] + (t - roff[r]);
-          cpos[t] = make_float4((float)(a.d.x[j] - xr), (float)(a.d.y[j] - yr), (float)(a.d.z[j] - zr), a.p.rad[j]);
+          const PosRec pj = load_pos(a.d.pos, j);
+          cpos[t] = make_float4((float)(pj.x - xr), (float)(pj.y - yr), (float)(pj.z - zr), pj.r);
           cidx[t] = j;
         }
         __syncthreads();
-        for (int ci = wid; ci < nc; ci += nwave) {
-          const int i = cb + ci;
-          // x cell of the centre: first staged x whose cell range ends beyond i
-          int cx = it.x0;
-          while (cx < it.x0 + xc - 1 && a.start[item_key(B, cx, it.iy, it.iz) + 1] <= i) cx++;
-          const float xi = (float)(a.d.x[i] - xr), yi = (float)(a.d.y[i] - yr), zi = (float)(a.d.z[i] - zr);
-          const float ri = a.p.rad[i];
-          const float rs = ri + (float)a.skin;
-          const int qa = max(cx - 1, xa) - xa, qb = min(cx + 1, xb) - xa + 1;
-          int seg_lo[3], pre[4];
-          pre[0] = 0;
-#pragma unroll
-          for (int r = 0; r < 3; r++) {
-            const int iy2 = it.iy + r - 1;
-            int len = 0;
-            seg_lo[r] = 0;
-            if (iy2 >= 0 && iy2 < B.nd[1]) {
-              seg_lo[r] = roff[r] + (rstart[r][qa] - rstart[r][0]);
-              len = rstart[r][qb] - rstart[r][qa];
+        if (mine) {
+          for (int r = row; r < re; r++) {
+            // the staged row is sorted by x: bisect the window |x_j - x_i| < cut_hi
+            int lo = roff[r], hi = roff[r + 1];
+            {
+              int a0 = lo, a1 = hi;
+              const float xl = xi - cut_hi;
+              while (a0 < a1) {
+                const int mid = (a0 + a1) >> 1;
+                if (cpos[mid].x < xl) a0 = mid + 1; else a1 = mid;
+              }
+              lo = a0;
+              a1 = hi;
+              const float xh = xi + cut_hi;
+              while (a0 < a1) {
+                const int mid = (a0 + a1) >> 1;
+                if (cpos[mid].x <= xh) a0 = mid + 1; else a1 = mid;
+              }
+              hi = a0;
             }
-            pre[r + 1] = pre[r] + len;
-          }
-          int cnt = ccnt[ci];
-          for (int base = 0; base < pre[3]; base += 64) {
-            const int t = base + lane;
-            bool hit = false;
-            int j = -1;
-            if (t < pre[3]) {
-              const int r = t >= pre[2] ? 2 : (t >= pre[1] ? 1 : 0);
-              const int q = seg_lo[r] + (t - pre[r]);
+            for (int q = lo; q < hi; q++) {
               const float4 c = cpos[q];
-              j = cidx[q];
-              const float dx = c.x - xi, dy = c.y - yi, dz2 = c.z - zi;
+              const float dx = c.x - xi, dy = c.y - yi, dz = c.z - zi;
               const float cut = (rs + c.w) * cut_scale;
-              hit = (j != i) && (dx * dx + dy * dy + dz2 * dz2 < cut * cut);
+              const int j = cidx[q];
+              if (j != i && dx * dx + dy * dy + dz * dz < cut * cut) {
+                if (cnt < a.cap) a.nb_new.idx[(long)cnt * N + i] = j;
+                cnt++;
+              }
             }
-            const uint64_t bal = __ballot(hit);
-            const int pos = cnt + __popcll(bal & ((1ull << lane) - 1ull));
-            if (hit && pos < a.cap) a.nb_new.idx[(long)pos * N + i] = j;
-            cnt += __popcll(bal);
           }
-          if (lane == 0) ccnt[ci] = cnt;
         }
+        row = re;
       }
-      __syncthreads();
-      // finalise: counts, overflow, spring carry-over from the old list
-      for (int ci = wid; ci < nc; ci += nwave) {
-        const int i = cb + ci;
-        int cnt = ccnt[ci];
+      if (mine) {
         if (cnt > a.cap) {
-          if (lane == 0) atomicOr(a.status, ST_OVERFLOW);
+          atomicOr(a.status, ST_OVERFLOW);
           cnt = a.cap;
         }
+        // carry over the springs of partners that were in contact
         const int po = a.perm[i];
         const uint64_t mo = a.nb_old.mask[po];
-        uint32_t my_id = 0xffffffffu;
-        if (lane < cnt) my_id = a.p.id[a.nb_new.idx[(long)lane * N + i]];
-        uint64_t bits = mo & ((1ull << kWallBit) - 1ull);
         uint64_t newbits = 0;
-        while (bits) {
-          const int q = __ffsll((unsigned long long)bits) - 1;
-          bits &= bits - 1;
-          const uint32_t oid = a.id_old[a.nb_old.idx[(long)q * N + po]];
-          const bool m = (lane < cnt) && (my_id == oid);
-          if (m) {
+        const uint64_t obits = mo & ((1ull << kWallBit) - 1ull);
+        if (obits) {
+          for (int s = 0; s < cnt; s++) {
+            const uint32_t idn = a.d.pos[a.nb_new.idx[(long)s * N + i]].id;
+            uint64_t b = obits;
+            while (b) {
+              const int q = __ffsll((unsigned long long)b) - 1;
+              b &= b - 1;
+              if (a.pos_old[a.nb_old.idx[(long)q * N + po]].id == idn) {
 #pragma unroll
-            for (int ax = 0; ax < 3; ax++)
-              a.nb_new.hist[((long)ax * kMaxNbr + lane) * N + i] = a.nb_old.hist[((long)ax * kMaxNbr + q) * N + po];
+                for (int ax = 0; ax < 3; ax++)
+                  a.nb_new.hist[((long)ax * kMaxNbr + s) * N + i] = a.nb_old.hist[((long)ax * kMaxNbr + q) * N + po];
+                newbits |= 1ull << s;
+                break;
+              }
+            }
           }
-          newbits |= __ballot(m);
         }
-        if (lane == 0) {
-          a.nb_new.cnt[i] = cnt;
-          a.nb_new.mask[i] = newbits | (mo & ~((1ull << kWallBit) - 1ull));
-        }
+        a.nb_new.cnt[i] = cnt;
+        a.nb_new.mask[i] = newbits | (mo & ~((1ull << kWallBit) - 1ull));
       }
-      __syncthreads();
     }
   }
 }
@@ -407,21 +425,19 @@ template <typename T>
 __global__ void k_pairs(Dyn<T> d, Props<T> p, Nbr<T> nb, int n, uint32_t *out, long cap, unsigned long long *count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double xi = d.x[i], yi = d.y[i], zi = d.z[i];
-  const double ri = p.rad[i];
-  const uint32_t idi = p.id[i];
+  const PosRec a = load_pos(d.pos, i);
   const int c = nb.cnt[i];
   for (int s = 0; s < c; s++) {
     const int j = nb.idx[(long)s * n + i];
-    const uint32_t idj = p.id[j];
-    if (idj <= idi) continue;
-    const double d2 = dist2_exact(d.x[j] - xi, d.y[j] - yi, d.z[j] - zi);
-    const double sr = ri + (double)p.rad[j];
+    const PosRec b = load_pos(d.pos, j);
+    if (b.id <= a.id) continue;
+    const double d2 = dist2_exact(b.x - a.x, b.y - a.y, b.z - a.z);
+    const double sr = (double)a.r + (double)b.r;
     if (d2 < sq_exact(sr)) {
       const unsigned long long k = atomicAdd(count, 1ull);
       if ((long)k < cap) {
-        out[2 * k] = idi;
-        out[2 * k + 1] = idj;
+        out[2 * k] = a.id;
+        out[2 * k + 1] = b.id;
       }
     }
   }

@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g
     const int k0 = R.row_key(r);
     const int e = start[k0 + R.f];
     for (int j = start[k0] + sl; j < e; j += kGroup) {
-      const double dd = 2.0 * (double)p.rad[j];
+      const double dd = 2.0 * (double)d.pos[j].r;
       sv += kPi / 6.0 * dd * dd * dd;
       cnt += 1.0;
     }
@@ -86,10 +86,11 @@ __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g
     const int k0 = R.row_key(r);
     const int e = start[k0 + R.f];
     for (int j = start[k0] + sl; j < e; j += kGroup) {
-      const double vx = (double)d.vx[j], vy = (double)d.vy[j], vz = (double)d.vz[j];
+      const VelRec<T> vr = d.vel[j];
+      const double vx = (double)vr.v[0], vy = (double)vr.v[1], vz = (double)vr.v[2];
       const double sx = ug - vx, sy = vg - vy, sz = wg - vz;
       const double slip = sqrt(sx * sx + sy * sy + sz * sz);
-      const double dd = 2.0 * (double)p.rad[j];
+      const double dd = 2.0 * (double)d.pos[j].r;
       const double V = kPi / 6.0 * dd * dd * dd;
       const double K = beta_over_epsp<double>(eps, rho, mu, slip, dd / (double)p.kcg[j], ph.ergun_printed) * V;
       sK += K;
@@ -152,8 +153,10 @@ __global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
   const int32_t tag = a.p.tag[j];
   const BedDev &B = a.beds[bed_of(tag)];
   const OreDev &O = a.ores[ore_of(tag)];
+  const PosRec P = load_pos(a.d.pos, j);
+  const VelRec<T> Vr = a.d.vel[j];
   Cells cl;
-  locate(B, a.d.x[j], a.d.y[j], a.d.z[j], cl);
+  locate(B, P.x, P.y, P.z, cl);
   const int c = cl.gas;
   const double Tg = a.g.T[c], p = a.g.p[c], xa = a.g.xH2[c], xb = a.g.xH2O[c], xn = a.g.xN2[c];
   // H2 fraction of the N2-free gas (Section 2.1)
@@ -168,7 +171,7 @@ __global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
     xeq[q] = 1.0 / (Kc[q] + 1.0);
     kap_kr[q] = (Kc[q] / (1.0 + Kc[q])) / exp(th[2 * q] - th[2 * q + 1] / RT);
   }
-  const double dd = 2.0 * (double)a.p.rad[j];
+  const double dd = 2.0 * (double)P.r;
   const double kcg = (double)a.p.kcg[j];
   const double dp = dd / kcg, rp = 0.5 * dp, Ap = kPi * dp * dp;
   const PoreDiff Dd = pore_diffusion(Tg, p, xa, xb, xn, O.d_pore_cm);
@@ -179,7 +182,7 @@ __global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
   double rho, mu;
   gas_props(Tg, p, xa, xb, xn, B.mu_override, rho, mu);
   const double eps = a.eps[c];
-  const double sx = a.g.ug[c] - (double)a.d.vx[j], sy = a.g.vg[c] - (double)a.d.vy[j], sz = a.g.wg[c] - (double)a.d.vz[j];
+  const double sx = a.g.ug[c] - (double)Vr.v[0], sy = a.g.vg[c] - (double)Vr.v[1], sz = a.g.wg[c] - (double)Vr.v[2];
   const double slip = sqrt(sx * sx + sy * sy + sz * sz);
   const double Re = rho * eps * dp * slip / mu;
   const double sc3 = cbrt(mu / (rho * Dd.Dm));
@@ -276,9 +279,9 @@ __global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
   const double w = k3 * N2;
   a.pw[j] = w * fov;
   a.pw[N + j] = w;
-  if (a.fov) a.fov[a.p.id[j]] = fov;
+  if (a.fov) a.fov[P.id] = fov;
   if (a.update_mass)
-    a.p.mass[j] = T(k3 * 1e-3 * (n[0] * 159.687 + n[1] * 231.531 + n[2] * 71.844 + n[3] * 55.845));
+    a.d.vel[j].m = T(k3 * 1e-3 * (n[0] * 159.687 + n[1] * 231.531 + n[2] * 71.844 + n[3] * 55.845));
   if (clamps) atomicAdd(a.clamps, (unsigned long long)clamps);
   if (!(isfinite(fov) && n[0] >= 0.0 && n[1] >= 0.0 && n[2] >= 0.0)) atomicOr(a.status, ST_NONFINITE);
 }
@@ -321,14 +324,27 @@ void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t
   k_cellsum<<<(int)((threads + 255) / 256), 256, 0, s>>>(pm, n, start, cell_bed, beds, n_gas, o0, o1, o2, o3);
 }
 
-// Bed-mean f_ov weighted by k^3 N_Fe: one block per bed, strided partial sums
-// then a fixed shuffle/LDS tree.
-__global__ void __launch_bounds__(256) k_bedsum(const double *pw, int n, const int32_t *start, const BedDev *beds,
-                                                double *bed_fov) {
-  const BedDev &B = beds[blockIdx.x];
-  const int s = start[B.dem_off], e = start[B.dem_off + B.n_dem];
+// Bed-mean f_ov weighted by k^3 N_Fe: every bed's parcel range (contiguous,
+// keys are bed-major) is cut into chunks of kBedChunk parcels; one block sums
+// each chunk with a fixed shuffle/LDS tree, then one thread per bed adds its
+// chunks in order.  Deterministic, and parallel for a single large bed.
+__global__ void k_bed_chunks(const int32_t *start, const BedDev *beds, int n_beds, int4 *chunks, int max_chunks) {
+  if (threadIdx.x != 0) return;
+  int c = 0;
+  for (int b = 0; b < n_beds; b++) {
+    const int s = start[beds[b].dem_off], e = start[beds[b].dem_off + beds[b].n_dem];
+    for (int q = s; q < e && c < max_chunks - 1; q += kBedChunk) chunks[c++] = make_int4(b, q, min(q + kBedChunk, e), 0);
+  }
+  chunks[max_chunks - 1] = make_int4(c, 0, 0, 0);  // chunk count
+}
+
+__global__ void __launch_bounds__(256) k_chunk_sum(const double *pw, int n, const int4 *chunks, int max_chunks,
+                                                    double *partial) {
+  const int nch = chunks[max_chunks - 1].x;
+  if ((int)blockIdx.x >= nch) return;
+  const int4 ch = chunks[blockIdx.x];
   double a = 0.0, b = 0.0;
-  for (int j = s + threadIdx.x; j < e; j += blockDim.x) {
+  for (int j = ch.y + threadIdx.x; j < ch.z; j += blockDim.x) {
     a += pw[j];
     b += pw[(long)n + j];
   }
@@ -344,15 +360,54 @@ __global__ void __launch_bounds__(256) k_bedsum(const double *pw, int n, const i
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double A = (sa[0] + sa[1]) + (sa[2] + sa[3]);
-    const double Bs = (sb[0] + sb[1]) + (sb[2] + sb[3]);
-    bed_fov[blockIdx.x] = Bs > 0.0 ? A / Bs : 0.0;
+    partial[2 * blockIdx.x] = (sa[0] + sa[1]) + (sa[2] + sa[3]);
+    partial[2 * blockIdx.x + 1] = (sb[0] + sb[1]) + (sb[2] + sb[3]);
   }
 }
 
-void launch_bedsum(const double *pw, int n, const int32_t *start, const BedDev *beds, int n_beds, double *bed_fov,
-                   hipStream_t s) {
-  k_bedsum<<<n_beds, 256, 0, s>>>(pw, n, start, beds, bed_fov);
+__global__ void __launch_bounds__(256) k_bed_final(const int4 *chunks, int max_chunks, const double *partial,
+                                                  double *bed_fov) {
+  const int b = blockIdx.x;
+  const int nch = chunks[max_chunks - 1].x;
+  // chunks are ordered by bed: bisect for this bed's first and last chunk
+  int lo = 0, hi = nch;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (chunks[mid].x < b) lo = mid + 1; else hi = mid;
+  }
+  int e0 = lo, e1 = nch;
+  while (e0 < e1) {
+    const int mid = (e0 + e1) >> 1;
+    if (chunks[mid].x <= b) e0 = mid + 1; else e1 = mid;
+  }
+  double A = 0.0, Bs = 0.0;
+  for (int c = lo + threadIdx.x; c < e0; c += blockDim.x) {
+    A += partial[2 * c];
+    Bs += partial[2 * c + 1];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    A += __shfl_xor(A, o, 64);
+    Bs += __shfl_xor(Bs, o, 64);
+  }
+  __shared__ double sa[4], sb[4];
+  if ((threadIdx.x & 63) == 0) {
+    sa[threadIdx.x >> 6] = A;
+    sb[threadIdx.x >> 6] = Bs;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double a2 = (sa[0] + sa[1]) + (sa[2] + sa[3]);
+    const double b2 = (sb[0] + sb[1]) + (sb[2] + sb[3]);
+    bed_fov[b] = b2 > 0.0 ? a2 / b2 : 0.0;
+  }
+}
+
+void launch_bedsum(const double *pw, int n, const int32_t *start, const BedDev *beds, int n_beds, int4 *chunks,
+                   int max_chunks, double *partial, double *bed_fov, hipStream_t s) {
+  k_bed_chunks<<<1, 64, 0, s>>>(start, beds, n_beds, chunks, max_chunks);
+  k_chunk_sum<<<max_chunks - 1, 256, 0, s>>>(pw, n, chunks, max_chunks, partial);
+  k_bed_final<<<n_beds, 256, 0, s>>>(chunks, max_chunks, partial, bed_fov);
 }
 
 // ------------------------------------------------------------------ init / import / export
@@ -360,30 +415,33 @@ template <typename T>
 __global__ void k_init(dem_parcels in, int n, Phys ph, int n_ores, Dyn<T> d, Props<T> p, uint32_t *status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  d.x[i] = in.x[i];
-  d.y[i] = in.y[i];
-  d.z[i] = in.z[i];
-  d.vx[i] = ((const T *)in.vx)[i];
-  d.vy[i] = ((const T *)in.vy)[i];
-  d.vz[i] = ((const T *)in.vz)[i];
-  d.wx[i] = ((const T *)in.wx)[i];
-  d.wy[i] = ((const T *)in.wy)[i];
-  d.wz[i] = ((const T *)in.wz)[i];
   const float dd = in.d[i], kk = in.k[i];
+  PosRec P;
+  P.x = in.x[i];
+  P.y = in.y[i];
+  P.z = in.z[i];
+  P.r = 0.5f * dd;
+  P.id = (uint32_t)i;
+  store_pos(d.pos, i, P);
+  VelRec<T> V;
+  V.v[0] = ((const T *)in.vx)[i];
+  V.v[1] = ((const T *)in.vy)[i];
+  V.v[2] = ((const T *)in.vz)[i];
+  V.w[0] = ((const T *)in.wx)[i];
+  V.w[1] = ((const T *)in.wy)[i];
+  V.w[2] = ((const T *)in.wz)[i];
   const int b = in.bed[i], o = in.ore[i];
   if (b < 0 || b >= ph.n_beds || o < 0 || o >= n_ores || !(dd > 0.0f) || !(kk >= 1.0f)) atomicOr(status, 16u);
-  p.rad[i] = 0.5f * dd;
   p.kcg[i] = kk;
   const bool ok = b >= 0 && b < ph.n_beds && o >= 0 && o < n_ores;
   p.tag[i] = ok ? b * 256 + o : 0;
-  p.id[i] = (uint32_t)i;
   const double nh = in.nh[i], nm = in.nm[i], nw = in.nw[i], nfe = in.nfe[i];
   p.nh[i] = nh;
   p.nm[i] = nm;
   p.nw[i] = nw;
   p.nfe[i] = nfe;
   const double k3 = (double)kk * kk * kk;
-  p.mass[i] = T(k3 * 1e-3 * (nh * 159.687 + nm * 231.531 + nw * 71.844 + nfe * 55.845));  // eq. e3-4
+  V.m = T(k3 * 1e-3 * (nh * 159.687 + nm * 231.531 + nw * 71.844 + nfe * 55.845));  // eq. e3-4
   // eq. e3-45 restitution of the parcel, eq. e3-44 damping ratio
   const double rad = 1.0 + (double)kk * (ph.e_p * ph.e_p - 1.0);
   const double e = rad > 0.0 ? sqrt(rad) : 0.0;
@@ -392,7 +450,8 @@ __global__ void k_init(dem_parcels in, int n, Phys ph, int n_ores, Dyn<T> d, Pro
     const double l = log(e);
     z = -l / sqrt(kPi * kPi + l * l);
   }
-  p.zeta[i] = T(z);
+  V.zeta = T(z);
+  d.vel[i] = V;
 #pragma unroll
   for (int k = 0; k < 3 * kMaxWalls; k++) p.wh[(long)k * n + i] = T(0);
 }
@@ -407,16 +466,18 @@ template <typename T>
 __global__ void k_export(Dyn<T> d, Props<T> p, int n, dem_parcels out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  const uint32_t i = p.id[j];
-  if (out.x) out.x[i] = d.x[j];
-  if (out.y) out.y[i] = d.y[j];
-  if (out.z) out.z[i] = d.z[j];
-  if (out.vx) ((T *)out.vx)[i] = d.vx[j];
-  if (out.vy) ((T *)out.vy)[i] = d.vy[j];
-  if (out.vz) ((T *)out.vz)[i] = d.vz[j];
-  if (out.wx) ((T *)out.wx)[i] = d.wx[j];
-  if (out.wy) ((T *)out.wy)[i] = d.wy[j];
-  if (out.wz) ((T *)out.wz)[i] = d.wz[j];
+  const PosRec P = load_pos(d.pos, j);
+  const VelRec<T> V = d.vel[j];
+  const uint32_t i = P.id;
+  if (out.x) out.x[i] = P.x;
+  if (out.y) out.y[i] = P.y;
+  if (out.z) out.z[i] = P.z;
+  if (out.vx) ((T *)out.vx)[i] = V.v[0];
+  if (out.vy) ((T *)out.vy)[i] = V.v[1];
+  if (out.vz) ((T *)out.vz)[i] = V.v[2];
+  if (out.wx) ((T *)out.wx)[i] = V.w[0];
+  if (out.wy) ((T *)out.wy)[i] = V.w[1];
+  if (out.wz) ((T *)out.wz)[i] = V.w[2];
   if (out.nh) out.nh[i] = p.nh[j];
   if (out.nm) out.nm[i] = p.nm[j];
   if (out.nw) out.nw[i] = p.nw[j];
@@ -432,25 +493,29 @@ template <typename T>
 __global__ void k_import(dem_parcels in, int n, Dyn<T> d, Props<T> p) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  const uint32_t i = p.id[j];
-  d.x[j] = in.x[i];
-  d.y[j] = in.y[i];
-  d.z[j] = in.z[i];
-  d.vx[j] = ((const T *)in.vx)[i];
-  d.vy[j] = ((const T *)in.vy)[i];
-  d.vz[j] = ((const T *)in.vz)[i];
-  d.wx[j] = ((const T *)in.wx)[i];
-  d.wy[j] = ((const T *)in.wy)[i];
-  d.wz[j] = ((const T *)in.wz)[i];
+  PosRec P = load_pos(d.pos, j);
+  const uint32_t i = P.id;
+  P.x = in.x[i];
+  P.y = in.y[i];
+  P.z = in.z[i];
+  store_pos(d.pos, j, P);
+  VelRec<T> V = d.vel[j];
+  V.v[0] = ((const T *)in.vx)[i];
+  V.v[1] = ((const T *)in.vy)[i];
+  V.v[2] = ((const T *)in.vz)[i];
+  V.w[0] = ((const T *)in.wx)[i];
+  V.w[1] = ((const T *)in.wy)[i];
+  V.w[2] = ((const T *)in.wz)[i];
   const double nh = in.nh[i], nm = in.nm[i], nw = in.nw[i], nfe = in.nfe[i];
   p.nh[j] = nh;
   p.nm[j] = nm;
   p.nw[j] = nw;
   p.nfe[j] = nfe;
   const double kk = (double)p.kcg[j];
-  p.mass[j] = T(kk * kk * kk * 1e-3 * (nh * 159.687 + nm * 231.531 + nw * 71.844 + nfe * 55.845));
+  V.m = T(kk * kk * kk * 1e-3 * (nh * 159.687 + nm * 231.531 + nw * 71.844 + nfe * 55.845));
+  d.vel[j] = V;
 #pragma unroll
-  for (int k = 0; k < 3 * kMaxWalls; k++) p.wh[(long)k * n + j] = T(0);
+  for (int k = 0; k < 3 * kMaxWalls; k++) p.wh[(long)k * n + i] = T(0);
 }
 
 template <typename T>

@@ -51,54 +51,64 @@ __device__ __forceinline__ void cross(const T a[3], const T b[3], T c[3]) {
 
 template <typename T>
 __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block() * blockDim.x + threadIdx.x;
   const long N = a.n;
   float vmag = 0.0f;
   int n_pp = 0, n_w = 0;
   if (i < a.n) {
-    const double xi = a.in.x[i], yi = a.in.y[i], zi = a.in.z[i];
-    const T vi[3] = {a.in.vx[i], a.in.vy[i], a.in.vz[i]};
-    const T wi[3] = {a.in.wx[i], a.in.wy[i], a.in.wz[i]};
-    const float rif = a.pr.rad[i];
+    const PosRec P = load_pos(a.in.pos, i);
+    const VelRec<T> Vi = a.in.vel[i];
+    const double xi = P.x, yi = P.y, zi = P.z;
+    const float rif = P.r;
     const T ri = T(rif);
-    const T mi = a.pr.mass[i];
-    const T zi_ = a.pr.zeta[i];
-    const uint32_t idi = a.pr.id[i];
+    const T mi = Vi.m;
+    const T zi_ = Vi.zeta;
+    const uint32_t idi = P.id;
     const int32_t tag = a.pr.tag[i];
     const int cnt = a.nb.cnt[i];
     const uint64_t mold = a.nb.mask[i];
     uint64_t mnew = 0;
     T F[3] = {T(0), T(0), T(0)}, Tq[3] = {T(0), T(0), T(0)};
-    T wmag = tsqrt<T>(wi[0] * wi[0] + wi[1] * wi[1] + wi[2] * wi[2]);
+    const T wmag = tsqrt<T>(Vi.w[0] * Vi.w[0] + Vi.w[1] * Vi.w[1] + Vi.w[2] * Vi.w[2]);
     const bool roll = a.ph.mu_r > 0.0 && wmag > T(0);
-    for (int s = 0; s < cnt; s++) {
-      const int j = a.nb.idx[(long)s * N + i];
-      const double dx = a.in.x[j] - xi, dy = a.in.y[j] - yi, dz = a.in.z[j] - zi;
-      const float rjf = a.pr.rad[j];
-      const double sr = (double)rif + (double)rjf;
+    // candidates in groups of kPre: their indices, then their position
+    // records, are requested together so the gathers overlap
+    constexpr int kPre = 4;
+    for (int s0 = 0; s0 < cnt; s0 += kPre) {
+      int jj[kPre];
+      PosRec Qs[kPre];
+#pragma unroll
+      for (int k = 0; k < kPre; k++) jj[k] = (s0 + k < cnt) ? a.nb.idx[(long)(s0 + k) * N + i] : -1;
+#pragma unroll
+      for (int k = 0; k < kPre; k++)
+        if (jj[k] >= 0) Qs[k] = load_pos(a.in.pos, jj[k]);
+#pragma unroll
+      for (int k = 0; k < kPre; k++) {
+      if (jj[k] < 0) continue;
+      const int s = s0 + k;
+      const int j = jj[k];
+      const PosRec Q = Qs[k];
+      const double dx = Q.x - xi, dy = Q.y - yi, dz = Q.z - zi;
+      const double sr = (double)rif + (double)Q.r;
       const double d2 = dist2_exact(dx, dy, dz);
       if (!(d2 < sq_exact(sr))) continue;
       // pair evaluated in canonical orientation (lower original id first) so
       // both partners obtain bit-identical values with opposite signs
-      const uint32_t idj = a.pr.id[j];
-      const bool ifirst = idi < idj;
+      const bool ifirst = idi < Q.id;
       const T sgn = ifirst ? T(1) : T(-1);
       const double dist = sqrt(d2);
       const double inv = 1.0 / dist;
       const T n[3] = {T((ifirst ? dx : -dx) * inv), T((ifirst ? dy : -dy) * inv), T((ifirst ? dz : -dz) * inv)};
       const T delta = T(sr - dist);
-      const T vj[3] = {a.in.vx[j], a.in.vy[j], a.in.vz[j]};
-      const T wj[3] = {a.in.wx[j], a.in.wy[j], a.in.wz[j]};
-      const T mj = a.pr.mass[j];
-      const T zj = a.pr.zeta[j];
-      const T rj = T(rjf);
+      const VelRec<T> Vj = a.in.vel[j];
+      const T rj = T(Q.r);
       const T ra = ifirst ? ri : rj, rb = ifirst ? rj : ri;
-      const T ma = ifirst ? mi : mj, mb = ifirst ? mj : mi;
+      const T ma = ifirst ? mi : Vj.m, mb = ifirst ? Vj.m : mi;
       T vrel[3], ws[3], cr[3];
 #pragma unroll
       for (int c = 0; c < 3; c++) {
-        const T va = ifirst ? vi[c] : vj[c], vb = ifirst ? vj[c] : vi[c];
-        const T wa = ifirst ? wi[c] : wj[c], wb = ifirst ? wj[c] : wi[c];
+        const T va = ifirst ? Vi.v[c] : Vj.v[c], vb = ifirst ? Vj.v[c] : Vi.v[c];
+        const T wa = ifirst ? Vi.w[c] : Vj.w[c], wb = ifirst ? Vj.w[c] : Vi.w[c];
         ws[c] = ra * wa + rb * wb;
         vrel[c] = va - vb;
       }
@@ -106,7 +116,7 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
 #pragma unroll
       for (int c = 0; c < 3; c++) vrel[c] += cr[c];
       const T mstar = ma * mb / (ma + mb);
-      const T zeta = zi_ > zj ? zi_ : zj;
+      const T zeta = zi_ > Vj.zeta ? zi_ : Vj.zeta;
       T xin[3] = {T(0), T(0), T(0)};
       if ((mold >> s) & 1ull) {
 #pragma unroll
@@ -123,7 +133,7 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
       }
       if (roll) {
 #pragma unroll
-        for (int c = 0; c < 3; c++) Tq[c] -= T(a.ph.mu_r) * fnabs * wi[c] / wmag;
+        for (int c = 0; c < 3; c++) Tq[c] -= T(a.ph.mu_r) * fnabs * Vi.w[c] / wmag;
       }
       if (a.mode == 0) {
 #pragma unroll
@@ -131,6 +141,7 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
       }
       mnew |= 1ull << s;
       n_pp++;
+      }
     }
     // walls: same law against a body of infinite mass and radius at rest
     const BedDev &B = a.beds[bed_of(tag)];
@@ -140,13 +151,13 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
       const double delw = (double)rif - phi;
       if (!(delw > 0.0)) continue;
       const T n[3] = {T(nv[0]), T(nv[1]), T(nv[2])};
-      T wr[3] = {ri * wi[0], ri * wi[1], ri * wi[2]}, cr[3];
+      T wr[3] = {ri * Vi.w[0], ri * Vi.w[1], ri * Vi.w[2]}, cr[3];
       cross(wr, n, cr);
-      const T vrel[3] = {vi[0] + cr[0], vi[1] + cr[1], vi[2] + cr[2]};
+      const T vrel[3] = {Vi.v[0] + cr[0], Vi.v[1] + cr[1], Vi.v[2] + cr[2]};
       T xin[3] = {T(0), T(0), T(0)};
       if ((mold >> (kWallBit + w)) & 1ull) {
 #pragma unroll
-        for (int c = 0; c < 3; c++) xin[c] = a.pr.wh[(long)(w * 3 + c) * N + i];
+        for (int c = 0; c < 3; c++) xin[c] = a.pr.wh[(long)(w * 3 + c) * N + idi];
       }
       T Fa[3], Ft[3], xo[3], fnabs;
       contact_force<T>(a.ph, mi, zi_, T(delw), n, vrel, xin, Fa, Ft, xo, fnabs);
@@ -159,11 +170,11 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
       }
       if (roll) {
 #pragma unroll
-        for (int c = 0; c < 3; c++) Tq[c] -= T(a.ph.mu_r) * fnabs * wi[c] / wmag;
+        for (int c = 0; c < 3; c++) Tq[c] -= T(a.ph.mu_r) * fnabs * Vi.w[c] / wmag;
       }
       if (a.mode == 0) {
 #pragma unroll
-        for (int c = 0; c < 3; c++) a.pr.wh[(long)(w * 3 + c) * N + i] = xo[c];
+        for (int c = 0; c < 3; c++) a.pr.wh[(long)(w * 3 + c) * N + idi] = xo[c];
       }
       mnew |= 1ull << (kWallBit + w);
       n_w++;
@@ -177,7 +188,7 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
       const T *g = a.gtab + (long)cl.gas * kGasRow;
       const T dpr = T(2) * ri / T(a.pr.kcg[i]);  // real-particle diameter
       const T V = T(kPi / 6.0) * (T(2) * ri) * (T(2) * ri) * (T(2) * ri);
-      const T s[3] = {g[0] - vi[0], g[1] - vi[1], g[2] - vi[2]};
+      const T s[3] = {g[0] - Vi.v[0], g[1] - Vi.v[1], g[2] - Vi.v[2]};
       const T slip = tsqrt<T>(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
       const T be = beta_over_epsp<T>(g[3], g[7], g[8], slip, dpr, a.ph.ergun_printed);
 #pragma unroll
@@ -193,29 +204,23 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
       const T dt = T(a.ph.dt);
       const T im = T(1) / mi;
       const T iI = T(1) / (T(0.4) * mi * ri * ri);
-      T vn[3], wn[3];
+      VelRec<T> Vo = Vi;
 #pragma unroll
       for (int c = 0; c < 3; c++) {
-        vn[c] = vi[c] + dt * F[c] * im;
-        wn[c] = wi[c] + dt * Tq[c] * iI;
+        Vo.v[c] = Vi.v[c] + dt * F[c] * im;
+        Vo.w[c] = Vi.w[c] + dt * Tq[c] * iI;
       }
-      const double xn = xi + a.ph.dt * (double)vn[0];
-      const double yn = yi + a.ph.dt * (double)vn[1];
-      const double zn = zi + a.ph.dt * (double)vn[2];
-      a.out.x[i] = xn;
-      a.out.y[i] = yn;
-      a.out.z[i] = zn;
-      a.out.vx[i] = vn[0];
-      a.out.vy[i] = vn[1];
-      a.out.vz[i] = vn[2];
-      a.out.wx[i] = wn[0];
-      a.out.wy[i] = wn[1];
-      a.out.wz[i] = wn[2];
+      PosRec Po = P;
+      Po.x = xi + a.ph.dt * (double)Vo.v[0];
+      Po.y = yi + a.ph.dt * (double)Vo.v[1];
+      Po.z = zi + a.ph.dt * (double)Vo.v[2];
+      store_pos(a.out.pos, i, Po);
+      a.out.vel[i] = Vo;
       if (a.mode == 0) a.nb.mask[i] = mnew;
-      const float v2 = (float)(vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2]);
+      const float v2 = (float)(Vo.v[0] * Vo.v[0] + Vo.v[1] * Vo.v[1] + Vo.v[2] * Vo.v[2]);
       vmag = sqrtf(v2);
-      if (!(isfinite(xn) && isfinite(yn) && isfinite(zn) && isfinite(v2) &&
-            isfinite((float)(wn[0] + wn[1] + wn[2]))))
+      if (!(isfinite(Po.x) && isfinite(Po.y) && isfinite(Po.z) && isfinite(v2) &&
+            isfinite((float)(Vo.w[0] + Vo.w[1] + Vo.w[2]))))
         atomicOr(a.status, ST_NONFINITE);
     }
   }
@@ -262,7 +267,8 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
 
 template <typename T>
 void launch_step(const StepArgs<T> &a, int block, hipStream_t s) {
-  k_step<T><<<(a.n + block - 1) / block, block, 0, s>>>(a);
+  const int g = ((a.n + block - 1) / block + 7) & ~7;  // multiple of 8 for the XCD remap
+  k_step<T><<<g, block, 0, s>>>(a);
 }
 
 // ------------------------------------------------------------------ gas table

@@ -10,7 +10,7 @@ namespace demrx {
 struct Item {  // a run of up to kItemX DEM cells along x in one (y, z) row of a bed
   int bed, x0, iy, iz;
 };
-constexpr int kItemX = 4;
+constexpr int kItemX = 16;
 
 void launch_fill_i32(int32_t *p, int32_t v, long n, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, long n, hipStream_t s);
@@ -23,7 +23,8 @@ void launch_bin(const Dyn<T> &d, const Props<T> &p, const BedDev *beds, int n, i
                 int32_t *slot, int32_t *count, uint32_t *status, hipStream_t s);
 void launch_scatter(const int32_t *key, const int32_t *slot, const int32_t *start, int n, int32_t *perm,
                     hipStream_t s);
-void launch_cellsort(const int32_t *start, int n_keys, const uint32_t *id_old, int32_t *perm, hipStream_t s);
+void launch_cellrank(const int32_t *start, const int32_t *key, const PosRec *pos_old, const int32_t *perm, int n,
+                     int32_t *perm_out, hipStream_t s);
 template <typename T>
 void launch_permute(const int32_t *perm, int n, const Dyn<T> &din, const Props<T> &pin, const Dyn<T> &dout,
                     const Props<T> &pout, unsigned *vmax, double *disp, hipStream_t s);
@@ -34,7 +35,7 @@ template <typename T>
 struct NbrBuild {
   Dyn<T> d;             // new sorted state
   Props<T> p;           // new sorted properties
-  const uint32_t *id_old;
+  const PosRec *pos_old;  // position records before the permutation (partner ids)
   const int32_t *perm;  // new position -> old position
   Nbr<T> nb_new, nb_old;
   const BedDev *beds;
@@ -110,8 +111,9 @@ template <typename T>
 void launch_react(const ReactArgs<T> &a, hipStream_t s);
 void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t *cell_bed, const BedDev *beds,
                     int n_gas, double *o0, double *o1, double *o2, double *o3, hipStream_t s);
-void launch_bedsum(const double *pw, int n, const int32_t *start, const BedDev *beds, int n_beds,
-                   double *bed_fov, hipStream_t s);
+constexpr int kBedChunk = 4096;  // parcels per partial sum of the bed means
+void launch_bedsum(const double *pw, int n, const int32_t *start, const BedDev *beds, int n_beds, int4 *chunks,
+                   int max_chunks, double *partial, double *bed_fov, hipStream_t s);
 
 template <typename T>
 void launch_init(const dem_parcels &in, int n, const Phys &ph, int n_ores, const Dyn<T> &d, const Props<T> &p,

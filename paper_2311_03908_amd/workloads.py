@@ -115,6 +115,9 @@ class Workload:
         return int(self.gas["T"].shape[0])
 
 
+# Neighbour-list skins: a parcel may move skin/2 between builds; the fine
+# parcels are carried at up to the gas speed (0.3-0.5 m/s), so skin/2 must
+# exceed rebuild_every * dt * 0.4 m/s.
 def base_params(**kw) -> dict:
     p = dict(kn=1000.0, e_p=0.9, mu_s=0.3, mu_r=0.0, kt_over_kn=2.0 / 7.0, gt_over_gn=0.0,
              eps_min=0.35, skin=5e-5, g=(0.0, 0.0, -9.81), dt=1e-5, rebuild_every=10,
@@ -358,12 +361,12 @@ def cfg1(n=2048, seed=1, steps=1000):
     ore = Ore(xi0=1.0 - rho / RHO_TRUE[0], d_pore_cm=3.3e-6)
     parcels = _parcels(pos, d_p, 1.0, np.zeros(n), np.zeros(n), {0: rho}, {0: HEMATITE_WT})
     gas = _gas(rng, [bed], 1073.0, 1.0, 0.0, (0.0, 0.0, 0.5), 0.0, False)
-    params = base_params(dt=1e-5, skin=5e-5, rebuild_every=10)
+    params = base_params(dt=1e-5, skin=1e-4, rebuild_every=10)
     return Workload("cfg1", "fp64", params, [bed], [ore], parcels, gas, np.array([0]), steps, 10)
 
 
 def _cfg_cyl(name, n, N0, R0, H0, h, refine, d_sampler, k, ores, ore_split, T, xh2, seed, steps,
-             dt=5e-6, couple=20, precision="mixed", skin=3e-5, u=0.3, classes=8):
+             dt=5e-6, couple=20, precision="mixed", skin=6e-5, u=0.3, classes=8, rebuild=10):
     rng = np.random.Generator(np.random.PCG64(seed))
     s = (n / float(N0)) ** (1.0 / 3.0)
     R = R0 * s
@@ -383,7 +386,7 @@ def _cfg_cyl(name, n, N0, R0, H0, h, refine, d_sampler, k, ores, ore_split, T, x
     parcels = _parcels(pos, d_p, k, ore_idx, np.zeros(n), rho_of, wt_of)
     parcels = _shuffle_ids(rng, parcels)
     gas = _gas(rng, [bed], T, xh2, 0.0, (0.0, 0.0, u), 0.1 * u, True)
-    params = base_params(dt=dt, skin=skin, rebuild_every=couple)
+    params = base_params(dt=dt, skin=skin, rebuild_every=rebuild)
     return Workload(name, precision, params, [bed], ores, parcels, gas, np.array([0]), steps, couple)
 
 
@@ -407,7 +410,7 @@ def cfg3(n=2_000_000, seed=3, steps=500):
     ores = [Ore(xi0=0.05, d_pore_cm=3.3e-6), Ore(xi0=0.25, d_pore_cm=9.5e-6)]
     return _cfg_cyl("cfg3", n, 2_000_000, 50e-3, 600e-3, 1.5625e-3, 1, _lognormal_dp, 5.0, ores,
                     lambda rng, m: (rng.random(m) < 0.5).astype(np.int32), 1073.0, 1.0, seed, steps,
-                    skin=5e-5)
+                    skin=1e-4, rebuild=20)
 
 
 def cfg4(n=500_000, seed=4, steps=20_000):
@@ -454,7 +457,7 @@ def cfg5(n_beds=64, seed=5, steps=1000, n_scale=1.0):
     rng = np.random.Generator(np.random.PCG64(ss.spawn(1)[0]))
     gas = _gas(rng, beds, Ts, xs, 0.0, (0.0, 0.0, 0.5), 0.0, False)
     offs = np.concatenate([[0], np.cumsum([bd.n_cells for bd in beds])[:-1]])
-    params = base_params(dt=5e-6, skin=5e-5, rebuild_every=20)
+    params = base_params(dt=5e-6, skin=2e-4, rebuild_every=20)
     return Workload("cfg5", "mixed", params, beds, [ore], parcels, gas, offs, steps, 20)
 
 
