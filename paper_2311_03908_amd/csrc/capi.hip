@@ -125,7 +125,7 @@ struct Ctx final : dem_ctx {
   long pairs_cap = 0;
   long step_count = 0, steps_since = 0, rebuilds = 0;
   bool built = false;
-  int step_block = 256, build_grid = 1024;
+  int step_block = 256, build_grid = 1024, step_xcd = 1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<const void *> gkey;
@@ -143,6 +143,7 @@ struct Ctx final : dem_ctx {
     if (ev_b) (void)hipEventDestroy(ev_b);
     if (cap_st) (void)hipStreamDestroy(cap_st);
     for (void *p : allocs) (void)hipFree(p);
+    if (gscr.base) (void)hipFree(gscr.base);
   }
 
   template <typename P_>
@@ -383,6 +384,7 @@ struct Ctx final : dem_ctx {
     a.n = n;
     a.par = (int)(step_count & 1);
     a.mode = mode;
+    a.xcd = step_xcd;
     a.Fout = a.Tout = nullptr;
     return a;
   }
@@ -616,6 +618,9 @@ struct Ctx final : dem_ctx {
                       oo.sumEQ, oo.sumES})
       k.push_back(q);
     k.push_back((const void *)(intptr_t)step_block);
+    k.push_back((const void *)(intptr_t)step_xcd);
+    // the graph bakes in the buffer parities it was captured at
+    k.push_back((const void *)(intptr_t)(cur | (pc << 1) | (nbc << 2) | (int)((step_count & 1) << 3)));
     if (!cap_st) {
       HIPCHK(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking));
       HIPCHK(hipEventCreateWithFlags(&ev_a, hipEventDisableTiming));
@@ -692,8 +697,10 @@ struct Ctx final : dem_ctx {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     float best = 1e30f;
-    int best_b = step_block;
-    for (int b : {64, 128, 256, 512}) {
+    int best_b = step_block, best_x = step_xcd;
+    for (int cand = 0; cand < 8; cand++) {
+      const int b = 64 << (cand % 4);
+      step_xcd = cand / 4;
       float tot = 0.0f;
       for (int rep = 0; rep < 4; rep++) {
         HIPCHK(hipEventRecord(e0, st));
@@ -704,9 +711,10 @@ struct Ctx final : dem_ctx {
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         if (rep) tot += ms;
       }
-      if (tot < best) { best = tot; best_b = b; }
+      if (tot < best) { best = tot; best_b = b; best_x = step_xcd; }
     }
     step_block = best_b;
+    step_xcd = best_x;
     // neighbour build: persistent grid size
     best = 1e30f;
     int best_g = build_grid;
@@ -732,6 +740,10 @@ struct Ctx final : dem_ctx {
   }
 
   int grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, double *J, double *gr) override;
+  struct {
+    void *base = nullptr;
+    size_t cap = 0;
+  } gscr;
 };
 
 #include "grad_impl.h"

@@ -3,6 +3,7 @@
 // per-bed reductions (deterministic: fixed lane assignment and shuffle trees,
 // no floating-point atomics), and state import/export.
 #include "launch.h"
+#include "uscm.h"
 
 namespace demrx {
 
@@ -30,22 +31,6 @@ struct GasCellRanges {
     return base + nd0 * (sy + nd1 * sz);
   }
 };
-
-__device__ __forceinline__ void gas_props(double T, double p, double x1, double x2, double x3, double mu_fix,
-                                          double &rho, double &mu) {
-  // eq. e3-53 and eqs. e3-55/e3-56 with Table C2 (mass-weighted viscosity)
-  const double M1 = 2.016, M2 = 18.015, M3 = 28.013;
-  const double Mg = x1 * M1 + x2 * M2 + x3 * M3;
-  rho = p * (Mg * 1e-3) / (kRg * T);
-  if (mu_fix > 0.0) {
-    mu = mu_fix;
-    return;
-  }
-  const double m1 = 2.85e-6 + 2.16e-8 * T - 3.78e-12 * T * T;
-  const double m2 = -4.44e-6 + 4.52e-8 * T - 3.20e-12 * T * T;
-  const double m3 = 7.86e-6 + 3.87e-8 * T - 5.11e-12 * T * T;
-  mu = (x1 * M1 * m1 + x2 * M2 * m2 + x3 * M3 * m3) / Mg;
-}
 
 // ------------------------------------------------------------------ deposition
 template <typename T>
@@ -79,7 +64,7 @@ __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g
   }
   if (!sums) return;
   double rho, mu;
-  gas_props(g.T[c], g.p[c], g.xH2[c], g.xH2O[c], g.xN2[c], B.mu_override, rho, mu);
+  gas_props_h2(g.T[c], g.p[c], g.xH2[c], g.xH2O[c], g.xN2[c], B.mu_override, rho, mu);
   const double ug = g.ug[c], vg = g.vg[c], wg = g.wg[c];
   double sK = 0, sKu = 0, sKv = 0, sKw = 0, sKs = 0;
   for (int r = 0; r < R.f * R.f; r++) {
@@ -123,29 +108,9 @@ void launch_deposit(const Dyn<T> &d, const Props<T> &p, const GasArgs &g, const 
 }
 
 // ------------------------------------------------------------------ reaction
-// Diffusion in a porous particle (Section 2.3): Fuller binary coefficients
-// (eq. e2-26, M in g/mol), Wilke mixture coefficient of H2 (eq. e2-27; a gas
-// of pure H2 takes the H2-H2O pair), Knudsen coefficient (eq. e2-28), the
-// regime by lambda / d_a and the series combination (eq. e2-29).
-__device__ __forceinline__ double fuller(double T, double p, double Mi, double Mj, double Vi, double Vj) {
-  const double s = cbrt(Vi) + cbrt(Vj);
-  return 1e-7 * pow(T, 1.75) * sqrt(1.0 / Mi + 1.0 / Mj) / ((p / 101325.0) * s * s);
-}
-
-struct PoreDiff {
-  double Dm, D;
-};
-__device__ __forceinline__ PoreDiff pore_diffusion(double T, double p, double a, double b, double nn, double d_pore_cm) {
-  const double D_hw = fuller(T, p, 2.016, 18.015, 7.07, 12.7);
-  const double D_hn = fuller(T, p, 2.016, 28.013, 7.07, 17.9);
-  PoreDiff r;
-  r.Dm = (b + nn < 1e-12) ? D_hw : (1.0 - a) / (b / D_hw + nn / D_hn);
-  const double DK = 0.97 * (0.5 * d_pore_cm) * sqrt(T / 2.016);
-  const double ratio = a > 0.0 ? (1.013 / (p * a)) / d_pore_cm : INFINITY;
-  r.D = ratio <= 0.01 ? r.Dm : (ratio >= 10.0 ? DK : 1.0 / (1.0 / r.Dm + 1.0 / DK));
-  return r;
-}
-
+// Environment of a parcel from its gas cell (NGP) and slip, then the update of
+// its species (uscm_step), its mass (eq. e3-4), its cell sources (eqs. e2-25,
+// e3-52, e4-8) and its weighted reduction degree.
 template <typename T>
 __global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -159,106 +124,30 @@ __global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
   locate(B, P.x, P.y, P.z, cl);
   const int c = cl.gas;
   const double Tg = a.g.T[c], p = a.g.p[c], xa = a.g.xH2[c], xb = a.g.xH2O[c], xn = a.g.xN2[c];
-  // H2 fraction of the N2-free gas (Section 2.1)
-  const double x = xb > 0.0 ? xa / (xa + xb) : (xa > 0.0 ? 1.0 : 0.0);
   const double *th = a.theta ? a.theta : B.theta;
   const double RT = kRg * Tg;
+  UscmEnv<double> e;
+  e.x = xb > 0.0 ? xa / (xa + xb) : (xa > 0.0 ? 1.0 : 0.0);
   // Table 2 equilibria (eq. e2-1-3) and Arrhenius constants (eq. e2-13)
   const double Kc[3] = {exp(1433.4 / Tg + 9.08), exp(-7393.9 / Tg + 7.56), exp(-2023.8 / Tg + 1.24)};
-  double xeq[3], kap_kr[3];
 #pragma unroll
   for (int q = 0; q < 3; q++) {
-    xeq[q] = 1.0 / (Kc[q] + 1.0);
-    kap_kr[q] = (Kc[q] / (1.0 + Kc[q])) / exp(th[2 * q] - th[2 * q + 1] / RT);
+    e.xeq[q] = 1.0 / (Kc[q] + 1.0);
+    e.kk[q] = (Kc[q] / (1.0 + Kc[q])) / exp(th[2 * q] - th[2 * q + 1] / RT);
   }
-  const double dd = 2.0 * (double)P.r;
   const double kcg = (double)a.p.kcg[j];
-  const double dp = dd / kcg, rp = 0.5 * dp, Ap = kPi * dp * dp;
+  const double dp = 2.0 * (double)P.r / kcg, rp = 0.5 * dp, Ap = kPi * dp * dp;
   const PoreDiff Dd = pore_diffusion(Tg, p, xa, xb, xn, O.d_pore_cm);
-  double rp_over_D[3];
 #pragma unroll
-  for (int q = 0; q < 3; q++) rp_over_D[q] = rp / (Dd.D * O.xi_layer[q] / O.tau);  // eq. e2-30
-  // gas film (eqs. e2-20..e2-24, Gunn's Sherwood number)
+  for (int q = 0; q < 3; q++) e.rpD[q] = rp / (Dd.D * O.xi_layer[q] / O.tau);
   double rho, mu;
-  gas_props(Tg, p, xa, xb, xn, B.mu_override, rho, mu);
-  const double eps = a.eps[c];
+  gas_props_h2(Tg, p, xa, xb, xn, B.mu_override, rho, mu);
   const double sx = a.g.ug[c] - (double)Vr.v[0], sy = a.g.vg[c] - (double)Vr.v[1], sz = a.g.wg[c] - (double)Vr.v[2];
-  const double slip = sqrt(sx * sx + sy * sy + sz * sz);
-  const double Re = rho * eps * dp * slip / mu;
-  const double sc3 = cbrt(mu / (rho * Dd.Dm));
-  const double Sh = (7.0 - 10.0 * eps + 5.0 * eps * eps) * (1.0 + 0.7 * pow(Re, 0.2) * sc3) +
-                    (1.33 - 2.4 * eps + 1.2 * eps * eps) * pow(Re, 0.7) * sc3;
-  const double Ff = dp / (Sh * Dd.Dm);
-  // shell geometry from the remaining fractions u = 1 - f (eqs. e2-15..e2-17)
+  e.F = film_resistance(rho, mu, Dd.Dm, a.eps[c], dp, sqrt(sx * sx + sy * sy + sz * sz));
+  e.cad = Ap * (p / RT) * a.dt;
   double n[4] = {a.p.nh[j], a.p.nm[j], a.p.nw[j], a.p.nfe[j]};
-  const double Nfe = 2.0 * n[0] + 3.0 * n[1] + n[2] + n[3];
-  const double cum[3] = {2.0 * n[0], 2.0 * n[0] + 3.0 * n[1], 2.0 * n[0] + 3.0 * n[1] + n[2]};
-  bool act[3];
-  int inner = 3;
-#pragma unroll
-  for (int q = 0; q < 3; q++) {
-    act[q] = n[q] > 1e-12 * Nfe && x > xeq[q];
-    if (act[q] && inner == 3) inner = q;
-  }
-  double r[3] = {0.0, 0.0, 0.0}, Qn = 0.0, Sn = 0.0;
-  int clamps = 0;
-  if (inner < 3) {
-    // interface (eq. e2-12) and layer (eq. e2-14) resistances outside the
-    // innermost active interface; layer l spans interfaces l-1 and l, the
-    // outermost reaches the particle surface (u = 1)
-    double icbrt[3], A[3], Bl[3];
-#pragma unroll
-    for (int q = 0; q < 3; q++) icbrt[q] = q >= inner ? 1.0 / cbrt(cum[q] / Nfe) : 0.0;
-#pragma unroll
-    for (int q = 0; q < 3; q++) {
-      A[q] = act[q] ? icbrt[q] * icbrt[q] * kap_kr[q] : 0.0;
-      const double outer = q < 2 ? icbrt[q + 1] : 1.0;
-      Bl[q] = q >= inner ? (icbrt[q] - outer) * rp_over_D[q] : 0.0;
-    }
-    // series/parallel reduction of the network (Figs. 2 and 4) from the
-    // innermost active interface outwards: (Phi, G) is the equilibrium
-    // potential and conductance seen looking inwards
-    double Rin = A[inner], Phi = xeq[inner];
-    for (int q = inner + 1; q < 3; q++) {
-      Rin += Bl[q - 1];
-      if (act[q]) {
-        const double g1 = 1.0 / Rin, g2 = 1.0 / A[q];
-        Phi = (Phi * g1 + xeq[q] * g2) / (g1 + g2);
-        Rin = 1.0 / (g1 + g2);
-      }
-    }
-    const double Rtot = Rin + Bl[2] + Ff;
-    const double flux = (x - Phi) / Rtot;
-    Qn = 1.0 / Rtot;
-    Sn = Phi / Rtot;
-    // walk back inwards distributing the flux over the active interfaces
-    double pot = x - flux * (Ff + Bl[2]);
-    double rest = flux;
-    for (int q = 2; q >= inner; q--) {
-      if (act[q]) {
-        r[q] = (pot - xeq[q]) / A[q];
-        rest -= r[q];
-      }
-      if (q > inner) pot -= rest * Bl[q - 1];
-    }
-  }
-  // extents per real particle (eq. e2-1 with eta_H2 = -1), irreversible and
-  // capped by the reactant present at the start of the update; Table 1 stoichiometry
-  const double cad = Ap * (p / RT) * a.dt;
-  double xi[3];
-  const double nu[3] = {3.0, 1.0, 1.0};
-#pragma unroll
-  for (int q = 0; q < 3; q++) {
-    if (r[q] < 0.0) {
-      r[q] = 0.0;
-      clamps++;
-    }
-    xi[q] = fmin(r[q] * cad, n[q] / nu[q]);
-  }
-  n[0] = n[0] - 3.0 * xi[0];
-  n[1] = n[1] + 2.0 * xi[0] - xi[1];
-  n[2] = n[2] + 3.0 * xi[1] - xi[2];
-  n[3] = n[3] + xi[2];
+  double xi[3], Qn, Sn;
+  const int clamps = uscm_step<double>(n, e, xi, Qn, Sn);
   a.p.nh[j] = n[0];
   a.p.nm[j] = n[1];
   a.p.nw[j] = n[2];
@@ -266,17 +155,13 @@ __global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
   const double k3 = kcg * kcg * kcg;
   const double xs = xi[0] + xi[1] + xi[2];
   const long N = a.n;
-  a.pm[j] = -k3 * 2.016e-3 * xs / a.dt;           // eq. e3-52, kg/s
-  a.pm[N + j] = k3 * 18.015e-3 * xs / a.dt;       // eq. e2-25
-  const double E = -Ap / Tg;                      // eq. e4-8 with eta_H2 = -1
+  a.pm[j] = -k3 * 2.016e-3 * xs / a.dt;      // eq. e3-52, kg/s
+  a.pm[N + j] = k3 * 18.015e-3 * xs / a.dt;  // eq. e2-25
+  const double E = -Ap / Tg;                 // eq. e4-8 with eta_H2 = -1
   a.pm[2 * N + j] = k3 * E * Qn;
   a.pm[3 * N + j] = k3 * E * Sn;
-  // overall reduction degree (eqs. e2-18, e2-19) from the updated remaining fractions
-  const double N2 = 2.0 * n[0] + 3.0 * n[1] + n[2] + n[3];
-  const double fh = 1.0 - 2.0 * n[0] / N2, fm = 1.0 - (2.0 * n[0] + 3.0 * n[1]) / N2,
-               fw = 1.0 - (2.0 * n[0] + 3.0 * n[1] + n[2]) / N2;
-  const double fov = O.kind == 1 ? 0.25 * fm + 0.75 * fw : fh / 9.0 + 2.0 * fm / 9.0 + 6.0 * fw / 9.0;
-  const double w = k3 * N2;
+  const double fov = fov_of<double>(n, O.kind);
+  const double w = k3 * (2.0 * n[0] + 3.0 * n[1] + n[2] + n[3]);
   a.pw[j] = w * fov;
   a.pw[N + j] = w;
   if (a.fov) a.fov[P.id] = fov;

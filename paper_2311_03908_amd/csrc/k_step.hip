@@ -51,7 +51,7 @@ __device__ __forceinline__ void cross(const T a[3], const T b[3], T c[3]) {
 
 template <typename T>
 __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
-  const int i = xcd_block() * blockDim.x + threadIdx.x;
+  const int i = (a.xcd ? xcd_block() : (int)blockIdx.x) * blockDim.x + threadIdx.x;
   const long N = a.n;
   float vmag = 0.0f;
   int n_pp = 0, n_w = 0;
@@ -71,9 +71,11 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
     T F[3] = {T(0), T(0), T(0)}, Tq[3] = {T(0), T(0), T(0)};
     const T wmag = tsqrt<T>(Vi.w[0] * Vi.w[0] + Vi.w[1] * Vi.w[1] + Vi.w[2] * Vi.w[2]);
     const bool roll = a.ph.mu_r > 0.0 && wmag > T(0);
-    // candidates in groups of kPre: their indices, then their position
-    // records, are requested together so the gathers overlap
+    // phase 1: exact contact test over the candidates, in groups of kPre whose
+    // indices and position records are requested together so the gathers
+    // overlap; contacting slots are collected in a bit set
     constexpr int kPre = 4;
+    uint64_t cbits = 0;
     for (int s0 = 0; s0 < cnt; s0 += kPre) {
       int jj[kPre];
       PosRec Qs[kPre];
@@ -84,14 +86,20 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
         if (jj[k] >= 0) Qs[k] = load_pos(a.in.pos, jj[k]);
 #pragma unroll
       for (int k = 0; k < kPre; k++) {
-      if (jj[k] < 0) continue;
-      const int s = s0 + k;
-      const int j = jj[k];
-      const PosRec Q = Qs[k];
+        if (jj[k] < 0) continue;
+        const double d2 = dist2_exact(Qs[k].x - xi, Qs[k].y - yi, Qs[k].z - zi);
+        const double sr = (double)rif + (double)Qs[k].r;
+        if (d2 < sq_exact(sr)) cbits |= 1ull << (s0 + k);
+      }
+    }
+    // phase 2: forces of the contacting pairs (records re-read from cache)
+    for (uint64_t cb = cbits; cb; cb &= cb - 1) {
+      const int s = __ffsll((unsigned long long)cb) - 1;
+      const int j = a.nb.idx[(long)s * N + i];
+      const PosRec Q = load_pos(a.in.pos, j);
       const double dx = Q.x - xi, dy = Q.y - yi, dz = Q.z - zi;
       const double sr = (double)rif + (double)Q.r;
       const double d2 = dist2_exact(dx, dy, dz);
-      if (!(d2 < sq_exact(sr))) continue;
       // pair evaluated in canonical orientation (lower original id first) so
       // both partners obtain bit-identical values with opposite signs
       const bool ifirst = idi < Q.id;
@@ -139,10 +147,9 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < 3; c++) a.nb.hist[((long)c * kMaxNbr + s) * N + i] = xo[c];
       }
-      mnew |= 1ull << s;
       n_pp++;
-      }
     }
+    mnew = cbits;
     // walls: same law against a body of infinite mass and radius at rest
     const BedDev &B = a.beds[bed_of(tag)];
     for (int w = 0; w < B.n_walls; w++) {
@@ -216,7 +223,7 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
       Po.z = zi + a.ph.dt * (double)Vo.v[2];
       store_pos(a.out.pos, i, Po);
       a.out.vel[i] = Vo;
-      if (a.mode == 0) a.nb.mask[i] = mnew;
+      if (a.mode == 0 && mnew != mold) a.nb.mask[i] = mnew;
       const float v2 = (float)(Vo.v[0] * Vo.v[0] + Vo.v[1] * Vo.v[1] + Vo.v[2] * Vo.v[2]);
       vmag = sqrtf(v2);
       if (!(isfinite(Po.x) && isfinite(Po.y) && isfinite(Po.z) && isfinite(v2) &&

@@ -67,6 +67,7 @@ struct StepArgs {
   double *disp;
   unsigned long long *counters;  // [0] pp contacts, [1] wall contacts (mode 0)
   int n, par, mode;              // mode 0: integrate; 1: write forces; 2: timing dry run
+  int xcd;                       // 1: remap blocks so each XCD takes a contiguous range
   double *Fout, *Tout;
 };
 template <typename T>
@@ -124,31 +125,35 @@ template <typename T>
 void launch_import(const dem_parcels &in, int n, const Dyn<T> &d, const Props<T> &p, hipStream_t s);
 
 // ---------------------------------------------------------------- k_adjoint.hip
-struct AdjEnv {  // per-parcel reaction environment of one dynamics interval
-  float *F;      // film resistance
-  int32_t *cell; // gas cell
-};
 struct AdjArgs {
-  int n, n_int, dyn_every, ckpt_every, n_sub;
-  double dt;
-  const int32_t *cell_rec;  // [n_int][N] gas cell per parcel (original order)
-  const float *F_rec;       // [n_int][N]
-  const double *cell_tab;   // per gas cell: T, x, c_mol, Dm, (per ore D computed in kernel)
-  const double *gasT, *gasP, *gasH2, *gasH2O, *gasN2;
-  const OreDev *ores;
-  const int32_t *ore;       // original order
-  const float *dp;          // real diameter, original order
-  const float *k3;          // k^3 per parcel
-  const int32_t *kind;      // per parcel f_ov kind
-  const double *sp0;        // [4][N] initial species (double)
-  double theta[6];
-  int fp32;                 // state precision
-  void *ckpt;               // [n_ckpt][4][N] (float or double)
-  void *seg;                // [ckpt_every/dyn_every + 1][4][N] segment replay buffer
-  double *partial;          // per block partial sums: [blocks][8] (J num, J den, grad 6)
+  int n;                     // parcels (state in original-id order)
+  int n_sub, dyn_every, ckpt_every;
+  int k_base;                // interval held by record slot 0
+  int s_begin, s_end;        // substeps run by a forward launch
+  double dt;                 // reaction substep
+  const int32_t *rec_cell;   // [slot][N] gas cell of every parcel
+  const double *rec_F;       // [slot][N] film resistance
+  const double *ctab;        // per gas cell reaction table (kCtab doubles)
+  const double *dtab;        // per (gas cell, ore): tau / (D xi_l) of the three layers
+  int n_ores;
+  const double *dp, *k3;     // real diameter and k^3 by id
+  const int32_t *ore, *kind; // ore index and f_ov kind by id
+  void *state;               // [4][N] (float or double)
+  void *ckpt;                // [n_ckpt][4][N] or null
+  void *seg;                 // [ckpt_every + 1][4][N]
+  double *part;              // [blocks][8]: J numerator, sum w, dJ/dtheta numerators
+  double inv_W;
 };
-void launch_adjoint_forward(const AdjArgs &a, int grad, hipStream_t s);
-void launch_adjoint_backward(const AdjArgs &a, hipStream_t s);
 int adjoint_blocks(int n);
+void launch_adj_cells(const GasArgs &g, const int32_t *cell_bed, const BedDev *beds, const OreDev *ores, int n_ores,
+                      int n_gas, const double *theta, double *ctab, double *dtab, hipStream_t s);
+template <typename T, typename S>
+void launch_adj_static(const Dyn<T> &d, const Props<T> &p, const OreDev *ores, int n, double *dp, double *k3,
+                       int32_t *ore, int32_t *kind, S *state, hipStream_t s);
+template <typename T>
+void launch_adj_record(const Dyn<T> &d, const Props<T> &p, const GasArgs &g, const double *eps, const BedDev *beds,
+                       int n, int32_t *rec_cell, double *rec_F, hipStream_t s);
+void launch_adjoint_forward(const AdjArgs &a, int fp32, hipStream_t s);
+void launch_adjoint_backward(const AdjArgs &a, int fp32, hipStream_t s);
 
 }  // namespace demrx
