@@ -2,13 +2,20 @@
 """Throughput of the particle-side hot path on one MI355X.
 
 A step is one DEM step of the whole path over the 2,000,000-parcel
-polydisperse cylindrical bed: contact detection over the Verlet candidates,
+polydisperse cylindrical fixed bed: contact detection over the Verlet candidates,
 soft-sphere parcel/wall forces, drag and integration every step; the
 neighbour rebuild (cell sort + LDS-staged candidate scan), voidage/drag
 deposition and the shrinking-core reaction update with its cell and bed
 reductions every 20 steps (one coupling interval, dt_CFD = 20 dt_DEM), all
 replayed from a HIP graph.  Inputs are generated on the host, uploaded, and
 resident in HBM before the timed region.
+
+The generated bed starts as loose lattice layers without contacts; before
+anything is timed it is settled under gravity for 20,000 DEM steps (0.1 s of
+bed time, neighbour lists rebuilt every 10 steps during the settling) into a
+packed bed with about five contacts per parcel, whose state then seeds the
+timed run.  --save-settled / --settled keep that state in a file so that a
+profiled run can skip the settling.
 
 Prints one JSON line (metric particle-steps/s) with the roofline of the
 dominant kernel (the fused DEM step) and the oracle's CPU throughput on a
@@ -53,6 +60,57 @@ def traffic_from_profile(kernel_src):
     return rec.get("bytes_per_launch")
 
 
+SETTLE_STEPS = 20_000
+
+
+def settle(w, steps, log=True):
+    """The bed after `steps` DEM steps under gravity (coupling every
+    couple_every steps), as a new workload with the same parameters."""
+    import dataclasses
+
+    from paper_2311_03908_amd.bed import Bed
+
+    S = w.couple_every
+    ws = dataclasses.replace(w, params={**w.params, "rebuild_every": 10})
+    bed = Bed(ws, device="cuda:0")
+    t0 = time.perf_counter()
+    bed.run(steps // S, S)
+    bed.sync()
+    st = bed.stats()
+    s = bed.state()
+    if log:
+        _log(f"[bench] settled {steps} steps in {time.perf_counter() - t0:.1f} s: "
+             f"{st['mean_coordination']:.2f} contacts per parcel")
+    p = dict(w.parcels)
+    for k in ("x", "y", "z", "vx", "vy", "vz", "wx", "wy", "wz", "nh", "nm", "nw", "nfe"):
+        p[k] = s[k].double().cpu().numpy()
+    bed.close()
+    return dataclasses.replace(w, parcels=p)
+
+
+STATE_KEYS = ("x", "y", "z", "vx", "vy", "vz", "wx", "wy", "wz", "nh", "nm", "nw", "nfe")
+
+
+def save_state(w, path):
+    import numpy as np
+
+    np.savez(path, **{k: w.parcels[k] for k in STATE_KEYS})
+
+
+def load_state(w, path):
+    import dataclasses
+
+    import numpy as np
+
+    z = np.load(path)
+    p = dict(w.parcels)
+    for k in STATE_KEYS:
+        if z[k].shape != p[k].shape:
+            raise ValueError(f"{path}: state of {z[k].shape[0]} parcels, workload has {p[k].shape[0]}")
+        p[k] = np.ascontiguousarray(z[k], dtype=np.float64)
+    return dataclasses.replace(w, parcels=p)
+
+
 def cpu_baseline(w, S):
     """The oracle as it stands (single thread) on the full bed: two DEM steps
     and one coupling (deposit + reaction), the coupling amortised over S steps."""
@@ -84,6 +142,9 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="parcel count (default: the 2M-parcel bed)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of 512 MiB three times (for counter scaling)")
+    ap.add_argument("--settle-steps", type=int, default=SETTLE_STEPS)
+    ap.add_argument("--save-settled", default=None, help="settle the bed, save its state (.npz) and exit")
+    ap.add_argument("--settled", default=None, help="start from a state saved by --save-settled")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no multi-GPU mode",
@@ -106,6 +167,15 @@ def main():
         del src, dst
     _log("[bench] generating workload")
     w = W.cfg3() if args.n is None else W.cfg3(n=args.n)
+    if args.settled:
+        w = load_state(w, args.settled)
+        _log(f"[bench] state from {args.settled}")
+    elif args.settle_steps > 0:
+        w = settle(w, args.settle_steps)
+    if args.save_settled:
+        save_state(w, args.save_settled)
+        _log(f"[bench] saved settled state to {args.save_settled}")
+        return
     S = w.couple_every
     steps = max(S, (args.steps + S - 1) // S * S)
     warm = max(2 * S, (args.warmup + S - 1) // S * S)
@@ -143,9 +213,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "polydisperse cylindrical bed: 2,000,000 parcels, lognormal d_p (median 100 um, "
-                               "sigma 0.3), k=5, 2 ore types, 64x64x384 gas grid, dt=5e-6 s, coupling every 20 steps",
-                   "parcels": w.n, "couple_every": S, "graph": True},
+        "config": {"workload": "polydisperse cylindrical fixed bed: 2,000,000 parcels, lognormal d_p (median "
+                               "100 um, sigma 0.3), k=5, 2 ore types, 100x600 mm cylinder, 64x64x384 gas grid, "
+                               "H2 at 1073 K, dt=5e-6 s, coupling every 20 steps, settled under gravity",
+                   "parcels": w.n, "couple_every": S, "graph": True,
+                   "settle_steps": 0 if args.settled else args.settle_steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                      "kernel": "k_step (fused contact + drag + integrate)", "bytes_per_parcel_step": bpu,

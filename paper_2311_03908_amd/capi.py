@@ -93,6 +93,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} not built; run __graft_entry__.build() (hipcc, gfx950)")
+    # PyTorch brings its own HIP runtime; loading it first makes the library
+    # bind to that same runtime, so that device pointers and streams are shared.
+    import torch  # noqa: F401
+
     L = C.CDLL(path)
     vp = C.c_void_p
     L.dem_init.argtypes = [C.POINTER(DemParams), C.POINTER(DemParcels), C.c_int32, vp, C.POINTER(vp)]

@@ -536,7 +536,7 @@ struct Ctx final : dem_ctx {
         TRY(dalloc(pairs_buf, 2 * (size_t)pairs_cap));
       }
       launch_fill_u32((uint32_t *)(counters + 3), 0u, 2, st);
-      launch_pairs<T>(dyn[cur], pr[pc], nb[nbc], n, pairs_buf, pairs_cap, counters + 3, st);
+      launch_pairs<T>(dyn[cur], pr[pc], nb[nbc], n, P.max_nbr, pairs_buf, pairs_cap, counters + 3, st);
       HIPCHK(hipGetLastError());
       unsigned long long c = 0;
       HIPCHK(hipMemcpyAsync(&c, counters + 3, sizeof c, hipMemcpyDeviceToHost, st));

@@ -261,20 +261,29 @@ void launch_items(const Item *items, int n_items, const BedDev *beds, const int3
 // ------------------------------------------------------------------ neighbour build
 // Work item: kItemX consecutive DEM cells of one row of a bed.  The nine rows
 // of its 3x3 (y, z) stencil, each spanning x0-1 .. x0+kItemX, are staged in
-// LDS (FP32 positions relative to the item corner, radii, sorted indices) as
-// many rows at a time as fit; every thread owns one centre parcel of the item
-// and tests the 3 cells of each staged row around its own cell, appending the
-// candidates closer than r_i + r_j + skin (conservative FP32 test; the exact
-// contact test runs every step) to its slot-major list.  The tangential
-// springs of partners already in contact are then carried over from the
-// previous list.
+// LDS (FP32 positions relative to the item corner, radii, sorted indices,
+// original ids) as many rows at a time as fit; every thread owns one centre
+// parcel of the item and tests the 3 cells of each staged row around its own
+// cell, keeping the candidates closer than r_i + r_j + skin (conservative FP32
+// test; the exact contact test runs every step).
+//
+// The list has two regions so that the step visits contacts in lockstep rows:
+// candidates that touch now (FP32 test with a 1e-4 margin, a superset of the
+// exact contacts) fill slots cap-1, cap-2, ... downwards, the others fill
+// slots 0, 1, ... upwards; cnt packs (near << 16) | far.  The tangential
+// springs of partners in contact before the rebuild are carried over to the
+// near slots by matching original ids (held in registers for up to kCarry
+// old contacts; more fall back to a gather loop).
 constexpr int kCandMax = 2048;
 constexpr int kBuildThreads = 512;
+constexpr int kCarry = 12;
+constexpr float kNear = 1.0f + 1e-4f;
 
 template <typename T>
 __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
   __shared__ float4 cpos[kCandMax];
   __shared__ int cidx[kCandMax];
+  __shared__ uint32_t cid[kCandMax];
   __shared__ int rstart[9][kItemX + 3];  // global start of each staged cell of each row (+ end)
   __shared__ int roff[10];
   const int n_list = *a.list_count;
@@ -301,17 +310,42 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
     for (int cb = c0; cb < c1; cb += blockDim.x) {
       const int i = cb + tid;
       const bool mine = i < c1;
-      float xi = 0.f, yi = 0.f, zi = 0.f, rs = 0.f;
-      int cnt = 0;
+      float xi = 0.f, yi = 0.f, zi = 0.f, rs = 0.f, ri = 0.f;
+      int nn = 0, nf = 0;  // near / far candidates written
+      bool over = false;
       float cut_hi = 0.f;
+      // partners in contact before the rebuild: original ids and old slots
+      uint32_t oid[kCarry];
+      int oslot[kCarry];
+      int po = 0;
+      uint64_t mo = 0, orest = 0, newbits = 0;
+#pragma unroll
+      for (int k = 0; k < kCarry; k++) {
+        oid[k] = 0xffffffffu;
+        oslot[k] = 0;
+      }
       if (mine) {
         const PosRec pi = load_pos(a.d.pos, i);
         xi = (float)(pi.x - xr);
         yi = (float)(pi.y - yr);
         zi = (float)(pi.z - zr);
+        ri = pi.r;
         rs = pi.r + (float)a.skin;
         // widest candidate distance along x for this centre
         cut_hi = (rs + (float)B.rmax) * cut_scale + 1e-9f;
+        po = a.perm[i];
+        mo = a.nb_old.mask[po];
+        uint64_t b = mo & ((1ull << kWallBit) - 1ull);
+#pragma unroll
+        for (int k = 0; k < kCarry; k++) {
+          if (b) {
+            const int q = __ffsll((unsigned long long)b) - 1;
+            b &= b - 1;
+            oslot[k] = q;
+            oid[k] = a.pos_old[a.nb_old.idx[(long)q * N + po]].id;
+          }
+        }
+        orest = b;
       }
       int row = 0;
       while (row < 9) {
@@ -345,6 +379,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
           const PosRec pj = load_pos(a.d.pos, j);
           cpos[t] = make_float4((float)(pj.x - xr), (float)(pj.y - yr), (float)(pj.z - zr), pj.r);
           cidx[t] = j;
+          cid[t] = pj.id;
         }
         __syncthreads();
         if (mine) {
@@ -372,9 +407,36 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
               const float dx = c.x - xi, dy = c.y - yi, dz = c.z - zi;
               const float cut = (rs + c.w) * cut_scale;
               const int j = cidx[q];
-              if (j != i && dx * dx + dy * dy + dz * dz < cut * cut) {
-                if (cnt < a.cap) a.nb_new.idx[(long)cnt * N + i] = j;
-                cnt++;
+              const float d2 = dx * dx + dy * dy + dz * dz;
+              if (j == i || !(d2 < cut * cut)) continue;
+              const float sn = (ri + c.w) * kNear;
+              if (nn + nf >= a.cap) {
+                over = true;
+              } else if (d2 < sn * sn) {
+                {
+                  const int sl = a.cap - 1 - nn;
+                  a.nb_new.idx[(long)sl * N + i] = j;
+                  const uint32_t idn = cid[q];
+                  int qo = -1;
+#pragma unroll
+                  for (int k = 0; k < kCarry; k++)
+                    if (oid[k] == idn) qo = oslot[k];
+                  for (uint64_t b = orest; b && qo < 0; b &= b - 1) {
+                    const int q2 = __ffsll((unsigned long long)b) - 1;
+                    if (a.pos_old[a.nb_old.idx[(long)q2 * N + po]].id == idn) qo = q2;
+                  }
+                  if (qo >= 0) {
+#pragma unroll
+                    for (int ax = 0; ax < 3; ax++)
+                      a.nb_new.hist[((long)ax * kMaxNbr + sl) * N + i] =
+                          a.nb_old.hist[((long)ax * kMaxNbr + qo) * N + po];
+                    newbits |= 1ull << sl;
+                  }
+                }
+                nn++;
+              } else {
+                a.nb_new.idx[(long)nf * N + i] = j;
+                nf++;
               }
             }
           }
@@ -382,33 +444,8 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
         row = re;
       }
       if (mine) {
-        if (cnt > a.cap) {
-          atomicOr(a.status, ST_OVERFLOW);
-          cnt = a.cap;
-        }
-        // carry over the springs of partners that were in contact
-        const int po = a.perm[i];
-        const uint64_t mo = a.nb_old.mask[po];
-        uint64_t newbits = 0;
-        const uint64_t obits = mo & ((1ull << kWallBit) - 1ull);
-        if (obits) {
-          for (int s = 0; s < cnt; s++) {
-            const uint32_t idn = a.d.pos[a.nb_new.idx[(long)s * N + i]].id;
-            uint64_t b = obits;
-            while (b) {
-              const int q = __ffsll((unsigned long long)b) - 1;
-              b &= b - 1;
-              if (a.pos_old[a.nb_old.idx[(long)q * N + po]].id == idn) {
-#pragma unroll
-                for (int ax = 0; ax < 3; ax++)
-                  a.nb_new.hist[((long)ax * kMaxNbr + s) * N + i] = a.nb_old.hist[((long)ax * kMaxNbr + q) * N + po];
-                newbits |= 1ull << s;
-                break;
-              }
-            }
-          }
-        }
-        a.nb_new.cnt[i] = cnt;
+        if (over) atomicOr(a.status, ST_OVERFLOW);
+        a.nb_new.cnt[i] = (nn << 16) | nf;
         a.nb_new.mask[i] = newbits | (mo & ~((1ull << kWallBit) - 1ull));
       }
     }
@@ -422,12 +459,14 @@ void launch_build_nbr(const NbrBuild<T> &a, int grid, hipStream_t s) {
 
 // ------------------------------------------------------------------ pairs
 template <typename T>
-__global__ void k_pairs(Dyn<T> d, Props<T> p, Nbr<T> nb, int n, uint32_t *out, long cap, unsigned long long *count) {
+__global__ void k_pairs(Dyn<T> d, Props<T> p, Nbr<T> nb, int n, int cap_slots, uint32_t *out, long cap,
+                        unsigned long long *count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const PosRec a = load_pos(d.pos, i);
-  const int c = nb.cnt[i];
-  for (int s = 0; s < c; s++) {
+  const int cw = nb.cnt[i], c_near = cw >> 16, c_far = cw & 0xffff;
+  for (int v = 0; v < c_near + c_far; v++) {
+    const int s = v < c_near ? cap_slots - 1 - v : v - c_near;
     const int j = nb.idx[(long)s * n + i];
     const PosRec b = load_pos(d.pos, j);
     if (b.id <= a.id) continue;
@@ -443,9 +482,9 @@ __global__ void k_pairs(Dyn<T> d, Props<T> p, Nbr<T> nb, int n, uint32_t *out, l
   }
 }
 template <typename T>
-void launch_pairs(const Dyn<T> &d, const Props<T> &p, const Nbr<T> &nb, int n, uint32_t *out, long cap,
+void launch_pairs(const Dyn<T> &d, const Props<T> &p, const Nbr<T> &nb, int n, int cap_slots, uint32_t *out, long cap,
                   unsigned long long *count, hipStream_t s) {
-  k_pairs<T><<<(n + 255) / 256, 256, 0, s>>>(d, p, nb, n, out, cap, count);
+  k_pairs<T><<<(n + 255) / 256, 256, 0, s>>>(d, p, nb, n, cap_slots, out, cap, count);
 }
 
 #define INST(T)                                                                                                   \
@@ -454,7 +493,7 @@ void launch_pairs(const Dyn<T> &d, const Props<T> &p, const Nbr<T> &nb, int n, u
   template void launch_permute<T>(const int32_t *, int, const Dyn<T> &, const Props<T> &, const Dyn<T> &,        \
                                   const Props<T> &, unsigned *, double *, hipStream_t);                          \
   template void launch_build_nbr<T>(const NbrBuild<T> &, int, hipStream_t);                                      \
-  template void launch_pairs<T>(const Dyn<T> &, const Props<T> &, const Nbr<T> &, int, uint32_t *, long,         \
+  template void launch_pairs<T>(const Dyn<T> &, const Props<T> &, const Nbr<T> &, int, int, uint32_t *, long,         \
                                 unsigned long long *, hipStream_t);
 INST(float)
 INST(double)

@@ -71,42 +71,29 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
     T F[3] = {T(0), T(0), T(0)}, Tq[3] = {T(0), T(0), T(0)};
     const T wmag = tsqrt<T>(Vi.w[0] * Vi.w[0] + Vi.w[1] * Vi.w[1] + Vi.w[2] * Vi.w[2]);
     const bool roll = a.ph.mu_r > 0.0 && wmag > T(0);
-    // phase 1: exact contact test over the candidates, in groups of kPre whose
-    // indices and position records are requested together so the gathers
-    // overlap; contacting slots are collected in a bit set
-    constexpr int kPre = 4;
+    // The list holds the candidates touching at the last rebuild in slots
+    // cap-1, cap-2, ... ("near") and the others in slots 0, 1, ... ("far").
+    // Each region is visited in lockstep across the wave (near first, where
+    // nearly every lane has a contact), so neighbour indices and the
+    // slot-major tangential springs of one visit are contiguous rows.
+    // Indices and position records are requested kPre slots at a time so
+    // that the gathers overlap.
+    const int c_near = cnt >> 16, c_far = cnt & 0xffff;
+    const int cap = a.ph.max_nbr;
     uint64_t cbits = 0;
-    for (int s0 = 0; s0 < cnt; s0 += kPre) {
-      int jj[kPre];
-      PosRec Qs[kPre];
-#pragma unroll
-      for (int k = 0; k < kPre; k++) jj[k] = (s0 + k < cnt) ? a.nb.idx[(long)(s0 + k) * N + i] : -1;
-#pragma unroll
-      for (int k = 0; k < kPre; k++)
-        if (jj[k] >= 0) Qs[k] = load_pos(a.in.pos, jj[k]);
-#pragma unroll
-      for (int k = 0; k < kPre; k++) {
-        if (jj[k] < 0) continue;
-        const double d2 = dist2_exact(Qs[k].x - xi, Qs[k].y - yi, Qs[k].z - zi);
-        const double sr = (double)rif + (double)Qs[k].r;
-        if (d2 < sq_exact(sr)) cbits |= 1ull << (s0 + k);
-      }
-    }
-    // phase 2: forces of the contacting pairs (records re-read from cache)
-    for (uint64_t cb = cbits; cb; cb &= cb - 1) {
-      const int s = __ffsll((unsigned long long)cb) - 1;
-      const int j = a.nb.idx[(long)s * N + i];
-      const PosRec Q = load_pos(a.in.pos, j);
+    auto pair = [&](int s, int j, const PosRec &Q) {
       const double dx = Q.x - xi, dy = Q.y - yi, dz = Q.z - zi;
-      const double sr = (double)rif + (double)Q.r;
       const double d2 = dist2_exact(dx, dy, dz);
+      const double sr = (double)rif + (double)Q.r;
+      if (!(d2 < sq_exact(sr))) return;
+      cbits |= 1ull << s;
       // pair evaluated in canonical orientation (lower original id first) so
       // both partners obtain bit-identical values with opposite signs
       const bool ifirst = idi < Q.id;
       const T sgn = ifirst ? T(1) : T(-1);
       const double dist = sqrt(d2);
-      const double inv = 1.0 / dist;
-      const T n[3] = {T((ifirst ? dx : -dx) * inv), T((ifirst ? dy : -dy) * inv), T((ifirst ? dz : -dz) * inv)};
+      const T inv = T(1) / T(dist);
+      const T n[3] = {T(ifirst ? dx : -dx) * inv, T(ifirst ? dy : -dy) * inv, T(ifirst ? dz : -dz) * inv};
       const T delta = T(sr - dist);
       const VelRec<T> Vj = a.in.vel[j];
       const T rj = T(Q.r);
@@ -148,6 +135,31 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
         for (int c = 0; c < 3; c++) a.nb.hist[((long)c * kMaxNbr + s) * N + i] = xo[c];
       }
       n_pp++;
+    };
+    constexpr int kPre = 4;
+    for (int t0 = 0; t0 < c_near; t0 += kPre) {
+      int jj[kPre];
+      PosRec Qs[kPre];
+#pragma unroll
+      for (int k = 0; k < kPre; k++) jj[k] = (t0 + k < c_near) ? a.nb.idx[(long)(cap - 1 - t0 - k) * N + i] : -1;
+#pragma unroll
+      for (int k = 0; k < kPre; k++)
+        if (jj[k] >= 0) Qs[k] = load_pos(a.in.pos, jj[k]);
+#pragma unroll
+      for (int k = 0; k < kPre; k++)
+        if (jj[k] >= 0) pair(cap - 1 - t0 - k, jj[k], Qs[k]);
+    }
+    for (int t0 = 0; t0 < c_far; t0 += kPre) {
+      int jj[kPre];
+      PosRec Qs[kPre];
+#pragma unroll
+      for (int k = 0; k < kPre; k++) jj[k] = (t0 + k < c_far) ? a.nb.idx[(long)(t0 + k) * N + i] : -1;
+#pragma unroll
+      for (int k = 0; k < kPre; k++)
+        if (jj[k] >= 0) Qs[k] = load_pos(a.in.pos, jj[k]);
+#pragma unroll
+      for (int k = 0; k < kPre; k++)
+        if (jj[k] >= 0) pair(t0 + k, jj[k], Qs[k]);
     }
     mnew = cbits;
     // walls: same law against a body of infinite mass and radius at rest

@@ -50,7 +50,7 @@ template <typename T>
 void launch_build_nbr(const NbrBuild<T> &a, int grid, hipStream_t s);
 
 template <typename T>
-void launch_pairs(const Dyn<T> &d, const Props<T> &p, const Nbr<T> &nb, int n, uint32_t *out, long cap,
+void launch_pairs(const Dyn<T> &d, const Props<T> &p, const Nbr<T> &nb, int n, int cap_slots, uint32_t *out, long cap,
                   unsigned long long *count, hipStream_t s);
 
 // ---------------------------------------------------------------- k_step.hip
