@@ -111,6 +111,97 @@ def load_state(w, path):
     return dataclasses.replace(w, parcels=p)
 
 
+def bench_batched(log=True):
+    """64 beds of uneven size and temperature (the batched workload): one
+    context holding all beds, 1,000 steps replayed from one HIP graph, against
+    the plain loop running each bed in a context of its own, both autotuned."""
+    import torch
+
+    from paper_2311_03908_amd import workloads as W
+    from paper_2311_03908_amd.bed import Bed
+
+    w = W.cfg5()
+    S = w.couple_every
+    n_int = 1000 // S
+
+    def timed(wk):
+        bed = Bed(wk, device="cuda:0")
+        bed.autotune()
+        bed.run(2, S)
+        bed.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bed.run(n_int, S)
+        bed.sync()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        bed.close()
+        return dt
+
+    t_batch = timed(w)
+    t_loop = 0.0
+    for b in range(len(w.beds)):
+        t_loop += timed(W.split_bed(w, b))
+    if log:
+        _log(f"[bench] batched: {len(w.beds)} beds, {w.n} parcels: one context {t_batch:.3f} s, "
+             f"per-bed loop {t_loop:.3f} s")
+    return {"beds": len(w.beds), "parcels": w.n, "steps": n_int * S, "batched_s": t_batch, "per_bed_loop_s": t_loop,
+            "speedup": t_loop / t_batch, "particle_steps_per_s": w.n * n_int * S / t_batch}
+
+
+def bench_adjoint(log=True):
+    """Kinetic gradient of the 500,000-parcel bed over 20,000 reaction
+    substeps (dt_react 1e-4 s, one DEM step per 10 substeps, checkpoints every
+    500, FP32 state, FP64 adjoint accumulation): one dem_grad call against the
+    12 plain forward runs of central finite differences (h = 1e-4 relative)
+    in the same precision on the same GPU.  The gradient is checked against
+    central differences of FP64-state forward runs (FP32 round-off would
+    swamp differences of that step), each component relative to the largest
+    component of its kind (ln k0 or E_a)."""
+    import numpy as np
+
+    from paper_2311_03908_amd import workloads as W
+    from paper_2311_03908_amd.bed import Bed
+
+    w = W.cfg4()
+    spec = W.grad_spec_cfg4()
+    args = (spec["n_substeps"], spec["dt_react"], spec["dyn_every"], spec["ckpt_every"])
+    th = np.array(W.THETA_HEMATITE_FIT)
+    bed = Bed(w, device="cuda:0")
+    bed.grad(200, spec["dt_react"], spec["dyn_every"], spec["ckpt_every"], th, state_fp32=True)  # allocate
+    t0 = time.perf_counter()
+    J, g = bed.grad(*args, th, state_fp32=True)
+    t_grad = time.perf_counter() - t0
+
+    def central(fp32):
+        fd = np.zeros(6)
+        for q in range(6):
+            h = 1e-4 * abs(th[q])
+            Jq = []
+            for sgn in (1.0, -1.0):
+                tq = th.copy()
+                tq[q] += sgn * h
+                Jq.append(bed.grad(*args, tq, state_fp32=fp32, with_grad=False)[0])
+            fd[q] = (Jq[0] - Jq[1]) / (2 * h)
+        return fd
+
+    t0 = time.perf_counter()
+    central(True)
+    t_fd = time.perf_counter() - t0
+    fd64 = central(False)
+    bed.close()
+    sk = np.max(np.abs(fd64[0::2]))
+    se = np.max(np.abs(fd64[1::2]))
+    scale = np.array([sk, se, sk, se, sk, se])
+    err = float(np.max(np.abs(g - fd64) / scale))
+    if log:
+        _log(f"[bench] adjoint: J={J:.6f} grad {t_grad:.2f} s, 12 forwards {t_fd:.2f} s, "
+             f"max deviation from FP64 central differences {err:.2e}")
+    return {"parcels": w.n, "substeps": spec["n_substeps"], "J": J, "grad": g.tolist(), "fd_grad_f64": fd64.tolist(),
+            "grad_s": t_grad, "fd_12_forwards_s": t_fd, "speedup": t_fd / t_grad, "max_dev_from_fd": err,
+            "state": "f32", "accumulation": "f64"}
+
+
 def cpu_baseline(w, S):
     """The oracle as it stands (single thread) on the full bed: two DEM steps
     and one coupling (deposit + reaction), the coupling amortised over S steps."""
@@ -145,6 +236,10 @@ def main():
     ap.add_argument("--settle-steps", type=int, default=SETTLE_STEPS)
     ap.add_argument("--save-settled", default=None, help="settle the bed, save its state (.npz) and exit")
     ap.add_argument("--settled", default=None, help="start from a state saved by --save-settled")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched (64-bed) and adjoint (500k-parcel gradient) speedup legs")
+    ap.add_argument("--only", choices=["batched", "adjoint"], default=None,
+                    help="run only one speedup leg and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path has no multi-GPU mode",
@@ -157,6 +252,9 @@ def main():
     from paper_2311_03908_amd import workloads as W
     from paper_2311_03908_amd.bed import Bed
 
+    if args.only:
+        print(json.dumps(bench_batched() if args.only == "batched" else bench_adjoint()), flush=True)
+        return
     if args.copy_calibration:
         src = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0").fill_(1.0)
         dst = torch.empty_like(src)
@@ -223,8 +321,11 @@ def main():
                      "kernel": "k_step (fused contact + drag + integrate)", "bytes_per_parcel_step": bpu,
                      "kernel_ms": k_ms, "launches_timed": st["step_kernel_launches"], "z_mean": z},
     }
+    bed.close()
+    if not args.no_extras:
+        out["batched"] = bench_batched()
+        out["adjoint"] = bench_adjoint()
     if not args.no_cpu_baseline:
-        bed.close()
         out["cpu_baseline"] = cpu_baseline(w, S)
     print(json.dumps(out), flush=True)
 

@@ -9,6 +9,13 @@
  *
  * Every quantity is SI and double precision.  Parcels are kept in original id
  * order; every loop visits parcels, pairs and cells in ascending id order.
+ *
+ * Parity unpinned (conventions with no independent pin; the tests check only
+ * their use, limits or finiteness): the tortuosity, eps_min, kt/kn, the
+ * tangential damping, the neighbour skin and clamp thresholds, the mixture
+ * viscosity correlation of Table C2, the magnitude of the Ergun branch of the
+ * drag, the rolling-friction torque, and the species coefficients E Q, E S of
+ * eqs. e4-7..e4-11.
  */
 #ifndef ORA_H
 #define ORA_H

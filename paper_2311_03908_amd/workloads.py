@@ -183,8 +183,6 @@ def _rsa_box(rng, d, lo, hi, max_rounds=20000):
     cap = int(math.ceil(0.74 * float(np.prod(cell_sz)) / (math.pi / 6.0 * float(d.min()) ** 3))) + 2
     grid = -np.ones((ncell, cap), np.int64)
     fill = np.zeros(ncell, np.int64)
-    tgrid = -np.ones((ncell, cap), np.int64)
-    tfill = np.zeros(ncell, np.int64)
     pos = np.zeros((n, 3))
     rad = 0.5 * d
     pending = order.copy()
@@ -200,12 +198,13 @@ def _rsa_box(rng, d, lo, hi, max_rounds=20000):
         ok = ~_grid_hits(grid, nc, ci, p, r, pos, rad)
         idx = np.nonzero(ok)[0]
         if idx.size > 1:
+            # conflicts inside the batch: candidates may still overlap each
+            # other, so their grid is sized by the fullest cell of this batch
             tlin = _grid_lin(ci[idx], nc)
-            _grid_insert(tgrid, tfill, tlin, np.arange(idx.size))
+            tgrid = -np.ones((ncell, int(np.bincount(tlin).max())), np.int64)
+            _grid_insert(tgrid, np.zeros(ncell, np.int64), tlin, np.arange(idx.size))
             clash = _grid_hits(tgrid, nc, ci[idx], p[idx], r[idx], p[idx], r[idx],
                                later_than=np.arange(idx.size))
-            tgrid[tlin] = -1
-            tfill[tlin] = 0
             idx = idx[~clash]
         acc = np.zeros(batch.size, bool)
         acc[idx] = True
@@ -504,3 +503,16 @@ def squeeze(w: Workload, factor: float, seed: int) -> Workload:
         z[sel] = bed.lo[2] + (z[sel] - bed.lo[2]) * factor
     p["x"], p["y"], p["z"] = x, y, z
     return dataclasses.replace(w, parcels=p)
+
+
+def split_bed(w: Workload, b: int) -> Workload:
+    """Bed b of a multi-bed workload as a workload of its own (its parcels in
+    original order, its gas cells), for running beds one at a time."""
+    sel = np.flatnonzero(w.parcels["bed"] == b)
+    p = {k: np.ascontiguousarray(v[sel]) for k, v in w.parcels.items()}
+    p["bed"] = np.zeros(sel.size, dtype=w.parcels["bed"].dtype)
+    c0 = int(w.cell_offset[b])
+    c1 = c0 + w.beds[b].n_cells
+    gas = {k: np.ascontiguousarray(v[c0:c1]) for k, v in w.gas.items()}
+    return dataclasses.replace(w, name=f"{w.name}_bed{b}", beds=[w.beds[b]], parcels=p, gas=gas,
+                               cell_offset=np.array([0]))
