@@ -120,6 +120,8 @@ struct Ctx final : dem_ctx {
   uint32_t *status = nullptr;
   unsigned *vmax = nullptr;
   double *disp = nullptr;
+  float *wmax = nullptr;
+  int32_t *wcnt = nullptr;
   unsigned long long *counters = nullptr;  // pp contacts, wall contacts, clamps, pairs
   uint32_t *pairs_buf = nullptr;
   long pairs_cap = 0;
@@ -222,7 +224,14 @@ struct Ctx final : dem_ctx {
       d.gas_off = (int)goff;
       d.dem_off = (int)doff;
       d.n_gas = B.n[0] * B.n[1] * B.n[2];
-      d.n_dem = d.nd[0] * d.nd[1] * d.nd[2];
+      // key tiles (see dem_key): items of kItemX cells never straddle a tile
+      d.tx = std::min(kItemX, d.nd[0]);
+      d.ty = std::min(kTileY, d.nd[1]);
+      d.ntx = (d.nd[0] + d.tx - 1) / d.tx;
+      const long nty = (d.nd[1] + d.ty - 1) / d.ty;
+      const long n_dem = (long)d.ntx * d.tx * nty * d.ty * d.nd[2];
+      if (n_dem > (1L << 30)) return fail(DEMRX_EINVAL, "grid too large");
+      d.n_dem = (int)n_dem;
       for (int q = 0; q < 6; q++) d.theta[q] = B.theta[q];
       d.mu_override = B.mu_override;
       goff += d.n_gas;
@@ -243,9 +252,15 @@ struct Ctx final : dem_ctx {
     for (int b = 0; b < p->n_beds; b++) {
       const BedDev &d = hbd[b];
       for (int c = 0; c < d.n_gas; c++) hcb[d.gas_off + c] = b;
-      for (int iz = 0; iz < d.nd[2]; iz++)
-        for (int iy = 0; iy < d.nd[1]; iy++)
-          for (int x0 = 0; x0 < d.nd[0]; x0 += kItemX) hit.push_back(Item{b, x0, iy, iz});
+      // items in key order (tile column by column), so that the rebuild's
+      // persistent blocks work on neighbouring cells at the same time
+      const int nty = (d.nd[1] + d.ty - 1) / d.ty;
+      for (int cy = 0; cy < nty; cy++)
+        for (int cx = 0; cx < d.ntx; cx++)
+          for (int iz = 0; iz < d.nd[2]; iz++)
+            for (int iy = cy * d.ty; iy < std::min((cy + 1) * d.ty, d.nd[1]); iy++)
+              for (int x0 = cx * d.tx; x0 < std::min((cx + 1) * d.tx, d.nd[0]); x0 += kItemX)
+                hit.push_back(Item{b, x0, iy, iz});
     }
     // largest parcel per bed against the DEM cell (checked on the host once)
     {
@@ -288,9 +303,11 @@ struct Ctx final : dem_ctx {
     TRY(dalloc(pm, (size_t)4 * n)); TRY(dalloc(pw, (size_t)2 * n));
     TRY(dalloc(bed_fov_d, p->n_beds)); TRY(dalloc(theta_d, 6));
     TRY(dalloc(status, 1)); TRY(dalloc(vmax, 2)); TRY(dalloc(disp, 1)); TRY(dalloc(counters, 4));
+    TRY(dalloc(wmax, step_waves_max(n))); TRY(dalloc(wcnt, 2 * step_waves_max(n)));
     HIPCHK(hipMemcpyAsync(beds, hbd.data(), hbd.size() * sizeof(BedDev), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ores, hod.data(), hod.size() * sizeof(OreDev), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(cell_bed, hcb.data(), hcb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    if ((long)hit.size() != n_items) return fail(DEMRX_EINVAL, "internal: work-item count mismatch");
     HIPCHK(hipMemcpyAsync(items, hit.data(), hit.size() * sizeof(Item), hipMemcpyHostToDevice, st));
     for (int k = 0; k < 2; k++) {
       launch_fill_u32((uint32_t *)nb[k].mask, 0u, 2L * n, st);
@@ -378,8 +395,9 @@ struct Ctx final : dem_ctx {
     a.beds = beds;
     a.ph = ph;
     a.status = status;
-    a.vmax = vmax;
     a.disp = disp;
+    a.wmax = wmax;
+    a.wcnt = wcnt;
     a.counters = counters;
     a.n = n;
     a.par = (int)(step_count & 1);
@@ -413,9 +431,11 @@ struct Ctx final : dem_ctx {
       HIPCHK(hipEventRecord(e0, st));
       lst.emplace_back(e0, e1);
     }
-    launch_step<T>(step_args(0), step_block, st);
+    const StepArgs<T> sa = step_args(0);
+    launch_step<T>(sa, step_block, st);
     HIPCHK(hipGetLastError());
     if (prof) HIPCHK(hipEventRecord(e1, st));
+    launch_step_fin<T>(sa, step_block, st);
     cur ^= 1;
     step_count++;
     steps_since++;

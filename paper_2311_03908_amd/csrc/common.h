@@ -28,7 +28,21 @@ struct BedDev {
   double theta[6];
   double mu_override;
   double rmax;           // largest parcel radius in the bed
+  int tx, ty, ntx;       // key tiles: tx x ty DEM cells in x, y; tiles per x row
 };
+
+// Sort key of a DEM cell.  Cells are grouped in columns of tx x ty cells that
+// run through the whole bed height; columns follow each other x-fastest, and
+// inside a column the order is z, then y, then x.  A run of neighbouring
+// cells, and the parcels in them, then stays within a small window of
+// memory: one z-plane of a column is tx * ty cells, so the planes above and
+// below a cell (its contact neighbours) sit close to it in the sorted arrays.
+// Keys of a bed span [dem_off, dem_off + n_dem) with n_dem counting padded
+// columns; padding cells stay empty.
+__host__ __device__ __forceinline__ int dem_key(const BedDev &b, int x, int y, int z) {
+  const int cx = x / b.tx, cy = y / b.ty;
+  return b.dem_off + (((cy * b.ntx + cx) * b.nd[2] + z) * b.ty + (y - cy * b.ty)) * b.tx + (x - cx * b.tx);
+}
 
 // Per-ore constants: porosities of the Fe3O4, FeO, Fe layers (eqs. e2-31..e2-36)
 struct OreDev {
@@ -148,7 +162,7 @@ __device__ __forceinline__ bool locate(const BedDev &b, double x, double y, doub
     c.d[a] = g[a] * b.refine + s;
   }
   c.gas = b.gas_off + g[0] + b.n[0] * (g[1] + b.n[1] * g[2]);
-  c.dem = b.dem_off + c.d[0] + b.nd[0] * (c.d[1] + b.nd[1] * c.d[2]);
+  c.dem = dem_key(b, c.d[0], c.d[1], c.d[2]);
   return inside;
 }
 

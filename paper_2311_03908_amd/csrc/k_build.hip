@@ -220,10 +220,6 @@ void launch_permute(const int32_t *perm, int n, const Dyn<T> &din, const Props<T
 }
 
 // ------------------------------------------------------------------ work items
-__device__ __forceinline__ int item_key(const BedDev &B, int x, int y, int z) {
-  return B.dem_off + x + B.nd[0] * (y + B.nd[1] * z);
-}
-
 __global__ void k_item_flags(const Item *items, int n_items, const BedDev *beds, const int32_t *start,
                              int32_t *flags) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -235,8 +231,8 @@ __global__ void k_item_flags(const Item *items, int n_items, const BedDev *beds,
   const Item it = items[t];
   const BedDev &B = beds[it.bed];
   const int xe = min(it.x0 + kItemX, B.nd[0]);
-  const int k0 = item_key(B, it.x0, it.iy, it.iz);
-  const int k1 = item_key(B, xe - 1, it.iy, it.iz) + 1;
+  const int k0 = dem_key(B, it.x0, it.iy, it.iz);
+  const int k1 = dem_key(B, xe - 1, it.iy, it.iz) + 1;
   flags[t] = start[k1] > start[k0] ? 1 : 0;
 }
 
@@ -284,7 +280,9 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
   __shared__ float4 cpos[kCandMax];
   __shared__ int cidx[kCandMax];
   __shared__ uint32_t cid[kCandMax];
-  __shared__ int rstart[9][kItemX + 3];  // global start of each staged cell of each row (+ end)
+  // each stencil row is staged from up to three runs of keys: the halo cell
+  // left of the item, the item's own cells, the halo cell right of it
+  __shared__ int sst[9][3], sln[9][3];
   __shared__ int roff[10];
   const int n_list = *a.list_count;
   const long N = a.n;
@@ -294,18 +292,22 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
     const Item it = a.items[a.list[w]];
     const BedDev &B = a.beds[it.bed];
     const int xc = min(kItemX, B.nd[0] - it.x0);
-    const int xa = max(it.x0 - 1, 0), xb = min(it.x0 + xc, B.nd[0] - 1);
-    const int nx = xb - xa + 1;
     __syncthreads();
-    for (int t = tid; t < 9 * (nx + 1); t += blockDim.x) {
-      const int r = t / (nx + 1), q = t % (nx + 1);
+    if (tid < 27) {
+      const int r = tid / 3, k = tid % 3;
       const int iy2 = it.iy + (r % 3) - 1, iz2 = it.iz + (r / 3) - 1;
-      int v = 0;
-      if (iy2 >= 0 && iy2 < B.nd[1] && iz2 >= 0 && iz2 < B.nd[2]) v = a.start[item_key(B, xa + q, iy2, iz2)];
-      rstart[r][q] = v;
+      const int xl = k == 0 ? it.x0 - 1 : (k == 1 ? it.x0 : it.x0 + xc);
+      const int xh = k == 1 ? it.x0 + xc - 1 : xl;
+      int s0 = 0, ln = 0;
+      if (iy2 >= 0 && iy2 < B.nd[1] && iz2 >= 0 && iz2 < B.nd[2] && xl >= 0 && xh < B.nd[0]) {
+        s0 = a.start[dem_key(B, xl, iy2, iz2)];
+        ln = a.start[dem_key(B, xh, iy2, iz2) + 1] - s0;
+      }
+      sst[r][k] = s0;
+      sln[r][k] = ln;
     }
     __syncthreads();
-    const int c0 = rstart[4][it.x0 - xa], c1 = rstart[4][it.x0 + xc - xa];
+    const int c0 = sst[4][1], c1 = c0 + sln[4][1];
     const double xr = B.origin[0] + it.x0 * B.hd, yr = B.origin[1] + it.iy * B.hd, zr = B.origin[2] + it.iz * B.hd;
     for (int cb = c0; cb < c1; cb += blockDim.x) {
       const int i = cb + tid;
@@ -352,7 +354,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
         // as many consecutive rows as fit in LDS
         int re = row, tot = 0;
         while (re < 9) {
-          const int len = rstart[re][nx] - rstart[re][0];
+          const int len = sln[re][0] + sln[re][1] + sln[re][2];
           if (tot + len > kCandMax) break;
           tot += len;
           re++;
@@ -367,7 +369,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
           int o = 0;
           for (int r = row; r < re; r++) {
             roff[r] = o;
-            o += rstart[r][nx] - rstart[r][0];
+            o += sln[r][0] + sln[r][1] + sln[r][2];
           }
           roff[re] = o;
         }
@@ -375,7 +377,10 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
         for (int t = tid; t < tot; t += blockDim.x) {
           int r = row;
           while (r + 1 < re && roff[r + 1] <= t) r++;
-          const int j = rstart[r][0] + (t - roff[r]);
+          const int o = t - roff[r];
+          const int j = o < sln[r][0] ? sst[r][0] + o
+                                      : (o < sln[r][0] + sln[r][1] ? sst[r][1] + (o - sln[r][0])
+                                                                   : sst[r][2] + (o - sln[r][0] - sln[r][1]));
           const PosRec pj = load_pos(a.d.pos, j);
           cpos[t] = make_float4((float)(pj.x - xr), (float)(pj.y - yr), (float)(pj.z - zr), pj.r);
           cidx[t] = j;

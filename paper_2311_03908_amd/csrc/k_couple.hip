@@ -16,19 +16,20 @@ __device__ __forceinline__ double group_sum(double v) {
 }
 
 // DEM-cell ranges of a gas cell: refine^2 rows of `refine` consecutive keys
+// (key tiles hold a multiple of `refine` cells along x)
 struct GasCellRanges {
-  int base, f, nd0, nd1;
-  __device__ GasCellRanges(const BedDev &B, int c) {
+  const BedDev &B;
+  int gx, gy, gz, f;
+  __device__ GasCellRanges(const BedDev &B_, int c) : B(B_) {
     const int lc = c - B.gas_off;
-    const int gx = lc % B.n[0], gy = (lc / B.n[0]) % B.n[1], gz = lc / (B.n[0] * B.n[1]);
+    gx = lc % B.n[0];
+    gy = (lc / B.n[0]) % B.n[1];
+    gz = lc / (B.n[0] * B.n[1]);
     f = B.refine;
-    nd0 = B.nd[0];
-    nd1 = B.nd[1];
-    base = B.dem_off + gx * f + nd0 * (gy * f + nd1 * (gz * f));
   }
   __device__ int row_key(int r) const {  // r in [0, f*f)
     const int sy = r % f, sz = r / f;
-    return base + nd0 * (sy + nd1 * sz);
+    return dem_key(B, gx * f, gy * f + sy, gz * f + sz);
   }
 };
 

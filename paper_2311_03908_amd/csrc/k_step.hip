@@ -244,9 +244,8 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
     }
   }
   if (a.mode != 0) return;
-  // block maximum of |v| -> global bound on the displacement since the last build
-  __shared__ float smax[8];
-  __shared__ int scnt[2][8];
+  // per-wave partials (no block barrier, so waves retire independently);
+  // k_step_fin folds them into the displacement bound and the counters
   float m = vmag;
   int c0 = n_pp, c1 = n_w;
 #pragma unroll
@@ -255,32 +254,54 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
     c0 += __shfl_xor(c0, o, 64);
     c1 += __shfl_xor(c1, o, 64);
   }
+  if ((threadIdx.x & 63) == 0) {
+    const long wv = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    a.wmax[wv] = m;
+    a.wcnt[2 * wv] = c0;
+    a.wcnt[2 * wv + 1] = c1;
+  }
+}
+
+// Every parcel moved by at most dt max|v| in this step: add that to the bound
+// on the displacement since the last rebuild and flag a skin violation.
+__global__ void __launch_bounds__(1024) k_step_fin(const float *wmax, const int32_t *wcnt, long n_waves, double dt,
+                                                   double skin, double *disp, unsigned long long *counters,
+                                                   uint32_t *status) {
+  __shared__ float sm[16];
+  __shared__ long sc[2][16];
+  float m = 0.0f;
+  long c0 = 0, c1 = 0;
+  for (long w = threadIdx.x; w < n_waves; w += blockDim.x) {
+    m = fmaxf(m, wmax[w]);
+    c0 += wcnt[2 * w];
+    c1 += wcnt[2 * w + 1];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    m = fmaxf(m, __shfl_xor(m, o, 64));
+    c0 += __shfl_xor(c0, o, 64);
+    c1 += __shfl_xor(c1, o, 64);
+  }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) {
-    smax[wid] = m;
-    scnt[0][wid] = c0;
-    scnt[1][wid] = c1;
+    sm[wid] = m;
+    sc[0][wid] = c0;
+    sc[1][wid] = c1;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     float bm = 0.0f;
-    int t0 = 0, t1 = 0;
+    long t0 = 0, t1 = 0;
     for (int w = 0; w < (int)(blockDim.x >> 6); w++) {
-      bm = fmaxf(bm, smax[w]);
-      t0 += scnt[0][w];
-      t1 += scnt[1][w];
+      bm = fmaxf(bm, sm[w]);
+      t0 += sc[0][w];
+      t1 += sc[1][w];
     }
-    atomicMax(&a.vmax[a.par], __float_as_uint(bm));
-    if (t0) atomicAdd(&a.counters[0], (unsigned long long)t0);
-    if (t1) atomicAdd(&a.counters[1], (unsigned long long)t1);
-    if (blockIdx.x == 0) {
-      // the previous step moved every parcel by at most dt * vmax[prev]
-      const float vp = __uint_as_float(a.vmax[a.par ^ 1]);
-      const double dsp = a.disp[0] + a.ph.dt * (double)vp;
-      a.disp[0] = dsp;
-      a.vmax[a.par ^ 1] = 0u;
-      if (dsp > 0.5 * a.ph.skin) atomicOr(a.status, ST_SKIN);
-    }
+    const double d = disp[0] + dt * (double)bm;
+    disp[0] = d;
+    if (d > 0.5 * skin) atomicOr(status, ST_SKIN);
+    counters[0] += (unsigned long long)t0;
+    counters[1] += (unsigned long long)t1;
   }
 }
 
@@ -288,6 +309,13 @@ template <typename T>
 void launch_step(const StepArgs<T> &a, int block, hipStream_t s) {
   const int g = ((a.n + block - 1) / block + 7) & ~7;  // multiple of 8 for the XCD remap
   k_step<T><<<g, block, 0, s>>>(a);
+}
+
+template <typename T>
+void launch_step_fin(const StepArgs<T> &a, int block, hipStream_t s) {
+  const int g = ((a.n + block - 1) / block + 7) & ~7;
+  k_step_fin<<<1, 1024, 0, s>>>(a.wmax, a.wcnt, (long)g * (block / 64), a.ph.dt, a.ph.skin, a.disp, a.counters,
+                                a.status);
 }
 
 // ------------------------------------------------------------------ gas table
@@ -340,6 +368,8 @@ void launch_gas_table(const GasArgs &g, const double *eps, const int32_t *cell_b
 
 template void launch_step<float>(const StepArgs<float> &, int, hipStream_t);
 template void launch_step<double>(const StepArgs<double> &, int, hipStream_t);
+template void launch_step_fin<float>(const StepArgs<float> &, int, hipStream_t);
+template void launch_step_fin<double>(const StepArgs<double> &, int, hipStream_t);
 template void launch_gas_table<float>(const GasArgs &, const double *, const int32_t *, const BedDev *, int, float *,
                                       uint32_t *, hipStream_t);
 template void launch_gas_table<double>(const GasArgs &, const double *, const int32_t *, const BedDev *, int,

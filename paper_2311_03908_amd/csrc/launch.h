@@ -11,6 +11,7 @@ struct Item {  // a run of up to kItemX DEM cells along x in one (y, z) row of a
   int bed, x0, iy, iz;
 };
 constexpr int kItemX = 16;
+constexpr int kTileY = 16;  // key tile height in DEM cells (see dem_key)
 
 void launch_fill_i32(int32_t *p, int32_t v, long n, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, long n, hipStream_t s);
@@ -63,8 +64,9 @@ struct StepArgs {
   const BedDev *beds;
   Phys ph;
   uint32_t *status;
-  unsigned *vmax;
-  double *disp;
+  double *disp;                  // displacement bound since the last rebuild
+  float *wmax;                   // per-wave max |v| (mode 0)
+  int32_t *wcnt;                 // per-wave pp and wall contact counts (mode 0)
   unsigned long long *counters;  // [0] pp contacts, [1] wall contacts (mode 0)
   int n, par, mode;              // mode 0: integrate; 1: write forces; 2: timing dry run
   int xcd;                       // 1: remap blocks so each XCD takes a contiguous range
@@ -72,6 +74,10 @@ struct StepArgs {
 };
 template <typename T>
 void launch_step(const StepArgs<T> &a, int block, hipStream_t s);
+template <typename T>
+void launch_step_fin(const StepArgs<T> &a, int block, hipStream_t s);
+// per-wave partial sums of the step kernel: at most this many waves
+inline long step_waves_max(long n) { return n / 64 + 128; }
 
 struct GasArgs {
   const double *ug, *vg, *wg, *p, *dpdx, *dpdy, *dpdz, *T, *xH2, *xH2O, *xN2;
