@@ -111,6 +111,10 @@ struct Ctx final : dem_ctx {
   int cur = 0, pc = 0, nbc = 0;
   int32_t *key = nullptr, *slot = nullptr, *count = nullptr, *start = nullptr, *perm = nullptr, *scan_scr = nullptr;
   int32_t *perm2 = nullptr;
+  // cell order of the current positions for the deposits (refreshed at every
+  // coupling without permuting the parcels or rebuilding neighbour lists)
+  int32_t *start_d = nullptr, *order_d = nullptr;
+  bool dep_fresh = false;
   int4 *bchunks = nullptr;
   double *bpartial = nullptr;
   int max_chunks = 0;
@@ -118,10 +122,10 @@ struct Ctx final : dem_ctx {
   T *gtab = nullptr;
   double *eps = nullptr, *pm = nullptr, *pw = nullptr, *bed_fov_d = nullptr, *theta_d = nullptr;
   uint32_t *status = nullptr;
-  unsigned *vmax = nullptr;
-  double *disp = nullptr;
-  float *wmax = nullptr;
-  int32_t *wcnt = nullptr;
+  float4 *xref = nullptr;            // positions at the last rebuild
+  unsigned *dslot = nullptr;         // per-step displacement maxima (kSlots x 2, padded)
+  unsigned long long *cslot = nullptr;  // contact counts of the counted step (kSlots, padded)
+
   unsigned long long *counters = nullptr;  // pp contacts, wall contacts, clamps, pairs
   uint32_t *pairs_buf = nullptr;
   long pairs_cap = 0;
@@ -224,9 +228,10 @@ struct Ctx final : dem_ctx {
       d.gas_off = (int)goff;
       d.dem_off = (int)doff;
       d.n_gas = B.n[0] * B.n[1] * B.n[2];
-      // key tiles (see dem_key): items of kItemX cells never straddle a tile
-      d.tx = std::min(kItemX, d.nd[0]);
-      d.ty = std::min(kTileY, d.nd[1]);
+      // key tiles (see dem_key): one tile per bed plane (row-major keys).
+      // Columns of 16 x 16 cells measured no faster on the 2M-parcel bed.
+      d.tx = d.nd[0];
+      d.ty = d.nd[1];
       d.ntx = (d.nd[0] + d.tx - 1) / d.tx;
       const long nty = (d.nd[1] + d.ty - 1) / d.ty;
       const long n_dem = (long)d.ntx * d.tx * nty * d.ty * d.nd[2];
@@ -294,6 +299,7 @@ struct Ctx final : dem_ctx {
     TRY(dalloc(bchunks, max_chunks));
     TRY(dalloc(bpartial, 2 * (size_t)max_chunks));
     TRY(dalloc(count, (size_t)n_keys + 1)); TRY(dalloc(start, (size_t)n_keys + 1));
+    TRY(dalloc(start_d, (size_t)n_keys + 1)); TRY(dalloc(order_d, n));
     const long scr = std::max(scan_scratch_ints((long)n_keys + 1), scan_scratch_ints((long)n_items + 1));
     TRY(dalloc(scan_scr, scr));
     TRY(dalloc(iflags, (size_t)n_items + 1)); TRY(dalloc(ioffs, (size_t)n_items + 1));
@@ -302,8 +308,8 @@ struct Ctx final : dem_ctx {
     TRY(dalloc(eps, n_gas));
     TRY(dalloc(pm, (size_t)4 * n)); TRY(dalloc(pw, (size_t)2 * n));
     TRY(dalloc(bed_fov_d, p->n_beds)); TRY(dalloc(theta_d, 6));
-    TRY(dalloc(status, 1)); TRY(dalloc(vmax, 2)); TRY(dalloc(disp, 1)); TRY(dalloc(counters, 4));
-    TRY(dalloc(wmax, step_waves_max(n))); TRY(dalloc(wcnt, 2 * step_waves_max(n)));
+    TRY(dalloc(status, 1)); TRY(dalloc(counters, 4)); TRY(dalloc(xref, n));
+    TRY(dalloc(dslot, 2 * kSlots * kSlotPad)); TRY(dalloc(cslot, kSlots * kSlotPad64));
     HIPCHK(hipMemcpyAsync(beds, hbd.data(), hbd.size() * sizeof(BedDev), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ores, hod.data(), hod.size() * sizeof(OreDev), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(cell_bed, hcb.data(), hcb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
@@ -314,16 +320,17 @@ struct Ctx final : dem_ctx {
       launch_fill_i32(nb[k].cnt, 0, n, st);
     }
     launch_fill_u32(status, 0u, 1, st);
-    launch_fill_u32(vmax, 0u, 2, st);
-    launch_fill_u32((uint32_t *)disp, 0u, 2, st);
+    launch_fill_u32(dslot, 0u, 2 * kSlots * kSlotPad, st);
+    launch_fill_u32((uint32_t *)cslot, 0u, 2 * kSlots * kSlotPad64, st);
     launch_fill_u32((uint32_t *)counters, 0u, 8, st);
     launch_init<T>(*in, n, ph, p->n_ores, dyn[0], pr[0], status, st);
     HIPCHK(hipGetLastError());
     TRY(check_status());
     TRY(rebuild());
+    TRY(resort());
     DepositOut o{};
     o.eps_ctx = eps;
-    launch_deposit<T>(dyn[cur], pr[pc], GasArgs{}, start, cell_bed, beds, ph, n_gas, false, o, st);
+    launch_deposit<T>(dyn[cur], pr[pc], GasArgs{}, start_d, order_d, cell_bed, beds, ph, n_gas, false, o, st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     return check_status();
@@ -350,7 +357,7 @@ struct Ctx final : dem_ctx {
     launch_scan(count, start, (long)n_keys + 1, scan_scr, st);
     launch_scatter(key, slot, start, n, perm2, st);
     launch_cellrank(start, key, dyn[cur].pos, perm2, n, perm, st);
-    launch_permute<T>(perm, n, dyn[cur], pr[pc], dyn[cur ^ 1], pr[pc ^ 1], vmax, disp, st);
+    launch_permute<T>(perm, n, dyn[cur], pr[pc], dyn[cur ^ 1], pr[pc ^ 1], xref, dslot, st);
     cur ^= 1;
     pc ^= 1;
     launch_items(items, n_items, beds, start, iflags, ioffs, scan_scr, ilist, icount, st);
@@ -376,6 +383,27 @@ struct Ctx final : dem_ctx {
     steps_since = 0;
     rebuilds++;
     built = true;
+    dep_fresh = false;
+    return DEMRX_OK;
+  }
+
+  // Cell order of the current positions (bin, scan, scatter, in-cell rank):
+  // the parcels stay where they are; deposits and cell sums read them through
+  // order_d.  Deterministic like the full sort.
+  int resort() {
+    launch_fill_i32(count, 0, (long)n_keys + 1, st);
+    launch_bin<T>(dyn[cur], pr[pc], beds, n, key, slot, count, status, st);
+    launch_scan(count, start_d, (long)n_keys + 1, scan_scr, st);
+    launch_scatter(key, slot, start_d, n, perm2, st);
+    launch_cellrank(start_d, key, dyn[cur].pos, perm2, n, order_d, st);
+    HIPCHK(hipGetLastError());
+    dep_fresh = true;
+    return DEMRX_OK;
+  }
+
+  int ensure_dep() {
+    if (!built) TRY(rebuild());
+    if (!dep_fresh) TRY(resort());
     return DEMRX_OK;
   }
 
@@ -395,10 +423,10 @@ struct Ctx final : dem_ctx {
     a.beds = beds;
     a.ph = ph;
     a.status = status;
-    a.disp = disp;
-    a.wmax = wmax;
-    a.wcnt = wcnt;
-    a.counters = counters;
+    a.xref = xref;
+    a.dslot = dslot;
+    a.cslot = cslot;
+    a.count = 0;
     a.n = n;
     a.par = (int)(step_count & 1);
     a.mode = mode;
@@ -420,7 +448,7 @@ struct Ctx final : dem_ctx {
     return DEMRX_OK;
   }
 
-  int step_one() {
+  int step_one(bool count = false) {
     if (!built || steps_since >= P.rebuild_every) TRY(rebuild());
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof) {
@@ -431,14 +459,15 @@ struct Ctx final : dem_ctx {
       HIPCHK(hipEventRecord(e0, st));
       lst.emplace_back(e0, e1);
     }
-    const StepArgs<T> sa = step_args(0);
+    StepArgs<T> sa = step_args(0);
+    sa.count = count ? 1 : 0;
     launch_step<T>(sa, step_block, st);
     HIPCHK(hipGetLastError());
     if (prof) HIPCHK(hipEventRecord(e1, st));
-    launch_step_fin<T>(sa, step_block, st);
     cur ^= 1;
     step_count++;
     steps_since++;
+    dep_fresh = false;
     return DEMRX_OK;
   }
 
@@ -448,8 +477,8 @@ struct Ctx final : dem_ctx {
     if (ns == 0) return DEMRX_OK;
     TRY(gas_table(g));
     for (int s = 0; s < ns; s++) {
-      if (s == ns - 1) launch_fill_u32((uint32_t *)counters, 0u, 4, st);
-      TRY(step_one());
+      if (s == ns - 1) launch_fill_u32((uint32_t *)cslot, 0u, 2 * kSlots * kSlotPad64, st);
+      TRY(step_one(s == ns - 1));
     }
     return DEMRX_OK;
   }
@@ -461,7 +490,7 @@ struct Ctx final : dem_ctx {
 
   int couple(const dem_gas *g, dem_sources *o) override {
     if (!gas_ok(g)) return fail(DEMRX_EINVAL, "null gas field");
-    TRY(ensure_sorted());
+    TRY(ensure_dep());
     DepositOut d{};
     d.eps_ctx = eps;
     bool sums = false;
@@ -470,14 +499,14 @@ struct Ctx final : dem_ctx {
       d.sumKw = o->sumKw; d.sumKs = o->sumKs;
       sums = o->sumK || o->sumKu || o->sumKv || o->sumKw || o->sumKs;
     }
-    launch_deposit<T>(dyn[cur], pr[pc], gas_args(g), start, cell_bed, beds, ph, n_gas, sums, d, st);
+    launch_deposit<T>(dyn[cur], pr[pc], gas_args(g), start_d, order_d, cell_bed, beds, ph, n_gas, sums, d, st);
     HIPCHK(hipGetLastError());
     return DEMRX_OK;
   }
 
   int react_core(double dt, const dem_gas *g, dem_sources *o, double *fov, bool bed_sum, int update_mass,
                  const double *theta_dev) {
-    TRY(ensure_sorted());
+    TRY(ensure_dep());
     ReactArgs<T> a;
     a.d = dyn[cur];
     a.p = pr[pc];
@@ -496,7 +525,8 @@ struct Ctx final : dem_ctx {
     a.status = status;
     launch_react<T>(a, st);
     if (o && (o->mdotH2 || o->mdotH2O || o->sumEQ || o->sumES))
-      launch_cellsum(pm, n, start, cell_bed, beds, n_gas, o->mdotH2, o->mdotH2O, o->sumEQ, o->sumES, st);
+      launch_cellsum(pm, n, start_d, order_d, cell_bed, beds, n_gas, o->mdotH2, o->mdotH2O, o->sumEQ, o->sumES,
+                     st);
     if (bed_sum) launch_bedsum(pw, n, start, beds, P.n_beds, bchunks, max_chunks, bpartial, bed_fov_d, st);
     HIPCHK(hipGetLastError());
     return DEMRX_OK;
@@ -540,9 +570,10 @@ struct Ctx final : dem_ctx {
     for (int k = 0; k < 2; k++) launch_fill_u32((uint32_t *)nb[k].mask, 0u, 2L * n, st);
     built = false;
     TRY(rebuild());
+    TRY(resort());
     DepositOut o{};
     o.eps_ctx = eps;
-    launch_deposit<T>(dyn[cur], pr[pc], GasArgs{}, start, cell_bed, beds, ph, n_gas, false, o, st);
+    launch_deposit<T>(dyn[cur], pr[pc], GasArgs{}, start_d, order_d, cell_bed, beds, ph, n_gas, false, o, st);
     HIPCHK(hipGetLastError());
     return sync();
   }
@@ -584,8 +615,15 @@ struct Ctx final : dem_ctx {
   int stats(dem_stats *o) override {
     if (!o) return fail(DEMRX_EINVAL, "null output");
     unsigned long long c[4];
+    std::vector<unsigned long long> cs((size_t)kSlots * kSlotPad64);
     HIPCHK(hipMemcpyAsync(c, counters, sizeof c, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(cs.data(), cslot, cs.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     int r = sync();
+    c[0] = c[1] = 0;
+    for (int q = 0; q < kSlots; q++) {
+      c[0] += cs[(size_t)q * kSlotPad64];
+      c[1] += cs[(size_t)q * kSlotPad64 + 1];
+    }
     o->n_parcels = n;
     o->n_contacts = (int64_t)(c[0] / 2);
     o->n_wall_contacts = (int64_t)c[1];
@@ -613,23 +651,31 @@ struct Ctx final : dem_ctx {
     return r;
   }
 
-  // one coupling interval of the hot path
-  int interval(int S, const dem_gas *g, dem_sources *o) {
+  // One coupling interval of the hot path.  With rebuild_first the neighbour
+  // lists are rebuilt before its first step (the replay schedule below);
+  // step_one also rebuilds whenever rebuild_every steps have passed.
+  int interval(int S, const dem_gas *g, dem_sources *o, bool rebuild_first = false) {
+    if (rebuild_first) TRY(rebuild());
     TRY(gas_table(g));
     for (int s = 0; s < S; s++) {
-      if (s == S - 1) launch_fill_u32((uint32_t *)counters, 0u, 4, st);  // contact counts of the last step
-      TRY(step_one());
+      if (s == S - 1) launch_fill_u32((uint32_t *)cslot, 0u, 2 * kSlots * kSlotPad64, st);  // last step counts
+      TRY(step_one(s == S - 1));
     }
     TRY(couple(g, o));
     TRY(react_core(S * P.dt, g, o, nullptr, true, 1, nullptr));
     return DEMRX_OK;
   }
 
+  // Replay schedule: lists are rebuilt at the start of every m-th interval,
+  // m = max(1, rebuild_every / S), so they are never older than rebuild_every
+  // steps; a graph of 2m intervals holds an even number of rebuilds and steps
+  // and so returns every buffer parity to its starting value.
+  int sched_period(int S) const { return std::max(1, P.rebuild_every / S); }
+
   int run(int n_int, int S, const dem_gas *g, dem_sources *o, double *bed_fov) override {
     if (n_int < 0 || S < 1) return fail(DEMRX_EINVAL, "bad interval count");
     if (!gas_ok(g)) return fail(DEMRX_EINVAL, "null gas field");
     if (n_int == 0) return DEMRX_OK;
-    TRY(ensure_sorted());
     std::vector<const void *> k = {(const void *)(intptr_t)S, g->ug, g->vg, g->wg, g->p, g->dpdx, g->dpdy,
                                    g->dpdz, g->T, g->xH2, g->xH2O, g->xN2};
     dem_sources oo{};
@@ -662,18 +708,18 @@ struct Ctx final : dem_ctx {
   }
 
   int run_on_cap(int n_int, int S, const dem_gas *g, dem_sources *o, const std::vector<const void *> &k) {
-    // two intervals return every buffer parity to its starting value, so a
-    // graph of two intervals can be replayed as is
+    const int m = sched_period(S), G = 2 * m;
     if (!gexec || k != gkey) {
       if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
       if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
       const int s_cur = cur, s_pc = pc, s_nbc = nbc;
       const long s_sc = step_count, s_ss = steps_since, s_rb = rebuilds;
+      const bool s_built = built, s_dep = dep_fresh;
       HIPCHK(hipStreamBeginCapture(cap_st, hipStreamCaptureModeRelaxed));
       capturing = true;
       prof_capture.clear();
-      int r = interval(S, g, o);
-      if (r == DEMRX_OK) r = interval(S, g, o);
+      int r = DEMRX_OK;
+      for (int q = 0; q < G && r == DEMRX_OK; q++) r = interval(S, g, o, q % m == 0);
       capturing = false;
       hipGraph_t gr = nullptr;
       hipError_t e = hipStreamEndCapture(cap_st, &gr);
@@ -683,30 +729,36 @@ struct Ctx final : dem_ctx {
       }
       if (e != hipSuccess) return fail(DEMRX_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
       if (cur != s_cur || pc != s_pc || nbc != s_nbc || ((step_count ^ s_sc) & 1))
-        return fail(DEMRX_EHIP, "graph interval does not restore buffer parity");
+        return fail(DEMRX_EHIP, "graph intervals do not restore buffer parity");
       graph = gr;
       HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
       gkey = k;
       gprof = prof;
-      rebuilds_per_pair = rebuilds - s_rb;
+      rebuilds_per_graph = rebuilds - s_rb;
+      ss_after_graph = steps_since;
+      dep_after_graph = dep_fresh;
       cur = s_cur; pc = s_pc; nbc = s_nbc;
       step_count = s_sc; steps_since = s_ss; rebuilds = s_rb;
+      built = s_built; dep_fresh = s_dep;
     }
     if (gprof != prof) {  // recapture with or without timing events
       gkey.clear();
       return run_on_cap(n_int, S, g, o, k);
     }
-    if (prof && n_int >= 2) prof_graph = prof_capture;
-    for (int q = 0; q < n_int / 2; q++) {
+    if (prof && n_int >= G) prof_graph = prof_capture;
+    for (int q = 0; q < n_int / G; q++) {
       HIPCHK(hipGraphLaunch(gexec, cap_st));
-      step_count += 2L * S;
-      rebuilds += rebuilds_per_pair;
+      step_count += (long)G * S;
+      rebuilds += rebuilds_per_graph;
+      built = true;
+      steps_since = ss_after_graph;
+      dep_fresh = dep_after_graph;
     }
-    steps_since = 0;
-    if (n_int & 1) TRY(interval(S, g, o));
+    for (int q = 0; q < n_int % G; q++) TRY(interval(S, g, o, q % m == 0));
     return DEMRX_OK;
   }
-  long rebuilds_per_pair = 0;
+  long rebuilds_per_graph = 0, ss_after_graph = 0;
+  bool dep_after_graph = false;
   bool gprof = false;
 
   int autotune(const dem_gas *g) override {

@@ -54,6 +54,7 @@ int Ctx<T>::grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, 
   const size_t o_cnt = take(N * 4), o_idx = take((size_t)kMaxNbr * N * 4);
   const size_t o_hist = take((size_t)3 * kMaxNbr * N * sizeof(T)), o_mask = take(N * 8);
   const size_t o_eps = take((size_t)n_gas * 8), o_start = take(((size_t)n_keys + 1) * 4);
+  const size_t o_xref = take(N * sizeof(float4));
   if (off > gscr.cap) {
     if (gscr.base) (void)hipFree(gscr.base);
     gscr.base = nullptr;
@@ -82,7 +83,8 @@ int Ctx<T>::grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, 
       {p0.nfe, o_sp + 3 * N * 8, N * 8}, {p0.wh, o_wh, (size_t)3 * kMaxWalls * N * sizeof(T)},
       {b0.cnt, o_cnt, N * 4}, {b0.idx, o_idx, (size_t)kMaxNbr * N * 4},
       {b0.hist, o_hist, (size_t)3 * kMaxNbr * N * sizeof(T)}, {b0.mask, o_mask, N * 8},
-      {eps, o_eps, (size_t)n_gas * 8}, {start, o_start, ((size_t)n_keys + 1) * 4}};
+      {eps, o_eps, (size_t)n_gas * 8}, {start, o_start, ((size_t)n_keys + 1) * 4},
+      {xref, o_xref, N * sizeof(float4)}};
   for (const Cp &c : cps) HIPCHK(hipMemcpyAsync(B + c.o, c.live, c.bytes, hipMemcpyDeviceToDevice, st));
   const int cur0 = cur, pc0 = pc, nbc0 = nbc;
   const long sc0 = step_count;
@@ -183,15 +185,15 @@ int Ctx<T>::grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, 
   step_count = sc0;
   steps_since = 0;
   built = true;
+  dep_fresh = false;
   const Dyn<T> &d1 = dyn[cur];
   const Props<T> &p1 = pr[pc];
   const Nbr<T> &b1 = nb[nbc];
   void *lives[] = {d1.pos, d1.vel, p1.kcg, p1.tag, p1.nh, p1.nm, p1.nw, p1.nfe, p1.wh,
-                   b1.cnt, b1.idx, b1.hist, b1.mask, eps, start};
+                   b1.cnt, b1.idx, b1.hist, b1.mask, eps, start, xref};
   for (size_t q = 0; q < sizeof(cps) / sizeof(cps[0]); q++)
     HIPCHK(hipMemcpyAsync(lives[q], B + cps[q].o, cps[q].bytes, hipMemcpyDeviceToDevice, st));
-  launch_fill_u32(vmax, 0u, 2, st);
-  launch_fill_u32((uint32_t *)disp, 0u, 2, st);
+  launch_fill_u32(dslot, 0u, 2 * kSlots * kSlotPad, st);
   HIPCHK(hipGetLastError());
   const int rs = sync();
   return r != DEMRX_OK ? r : rs;

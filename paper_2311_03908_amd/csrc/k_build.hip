@@ -194,16 +194,14 @@ void launch_cellrank(const int32_t *start, const int32_t *key, const PosRec *pos
 
 template <typename T>
 __global__ void k_permute(const int32_t *perm, int n, Dyn<T> din, Props<T> pin, Dyn<T> dout, Props<T> pout,
-                          unsigned *vmax, double *disp) {
+                          float4 *xref, unsigned *dslot) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j == 0) {
-    vmax[0] = 0u;
-    vmax[1] = 0u;
-    disp[0] = 0.0;
-  }
+  if (j < 2 * kSlots) dslot[j * kSlotPad] = 0u;  // displacement maxima restart at the rebuild
   if (j >= n) return;
   const int i = perm[j];
-  store_pos(dout.pos, j, load_pos(din.pos, i));
+  const PosRec P = load_pos(din.pos, i);
+  store_pos(dout.pos, j, P);
+  xref[j] = make_float4((float)P.x, (float)P.y, (float)P.z, 0.0f);
   dout.vel[j] = din.vel[i];
   pout.kcg[j] = pin.kcg[i];
   pout.tag[j] = pin.tag[i];
@@ -215,8 +213,8 @@ __global__ void k_permute(const int32_t *perm, int n, Dyn<T> din, Props<T> pin, 
 
 template <typename T>
 void launch_permute(const int32_t *perm, int n, const Dyn<T> &din, const Props<T> &pin, const Dyn<T> &dout,
-                    const Props<T> &pout, unsigned *vmax, double *disp, hipStream_t s) {
-  k_permute<T><<<(n + 255) / 256, 256, 0, s>>>(perm, n, din, pin, dout, pout, vmax, disp);
+                    const Props<T> &pout, float4 *xref, unsigned *dslot, hipStream_t s) {
+  k_permute<T><<<(n + 255) / 256, 256, 0, s>>>(perm, n, din, pin, dout, pout, xref, dslot);
 }
 
 // ------------------------------------------------------------------ work items
@@ -496,7 +494,7 @@ void launch_pairs(const Dyn<T> &d, const Props<T> &p, const Nbr<T> &nb, int n, i
   template void launch_bin<T>(const Dyn<T> &, const Props<T> &, const BedDev *, int, int32_t *, int32_t *,       \
                               int32_t *, uint32_t *, hipStream_t);                                                \
   template void launch_permute<T>(const int32_t *, int, const Dyn<T> &, const Props<T> &, const Dyn<T> &,        \
-                                  const Props<T> &, unsigned *, double *, hipStream_t);                          \
+                                  const Props<T> &, float4 *, unsigned *, hipStream_t);                          \
   template void launch_build_nbr<T>(const NbrBuild<T> &, int, hipStream_t);                                      \
   template void launch_pairs<T>(const Dyn<T> &, const Props<T> &, const Nbr<T> &, int, int, uint32_t *, long,         \
                                 unsigned long long *, hipStream_t);

@@ -36,8 +36,8 @@ struct GasCellRanges {
 // ------------------------------------------------------------------ deposition
 template <typename T>
 __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g, const int32_t *start,
-                                                 const int32_t *cell_bed, const BedDev *beds, Phys ph, int n_gas,
-                                                 int sums, DepositOut o) {
+                                                 const int32_t *order, const int32_t *cell_bed, const BedDev *beds,
+                                                 Phys ph, int n_gas, int sums, DepositOut o) {
   const int gc = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
   const int sl = threadIdx.x % kGroup;
   const bool valid = gc < n_gas;
@@ -48,7 +48,8 @@ __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g
   for (int r = 0; r < R.f * R.f; r++) {
     const int k0 = R.row_key(r);
     const int e = start[k0 + R.f];
-    for (int j = start[k0] + sl; j < e; j += kGroup) {
+    for (int q = start[k0] + sl; q < e; q += kGroup) {
+      const int j = order[q];
       const double dd = 2.0 * (double)d.pos[j].r;
       sv += kPi / 6.0 * dd * dd * dd;
       cnt += 1.0;
@@ -71,7 +72,8 @@ __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g
   for (int r = 0; r < R.f * R.f; r++) {
     const int k0 = R.row_key(r);
     const int e = start[k0 + R.f];
-    for (int j = start[k0] + sl; j < e; j += kGroup) {
+    for (int q = start[k0] + sl; q < e; q += kGroup) {
+      const int j = order[q];
       const VelRec<T> vr = d.vel[j];
       const double vx = (double)vr.v[0], vy = (double)vr.v[1], vz = (double)vr.v[2];
       const double sx = ug - vx, sy = vg - vy, sz = wg - vz;
@@ -102,10 +104,11 @@ __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g
 
 template <typename T>
 void launch_deposit(const Dyn<T> &d, const Props<T> &p, const GasArgs &g, const int32_t *start,
-                    const int32_t *cell_bed, const BedDev *beds, const Phys &ph, int n_gas, bool sums,
-                    const DepositOut &o, hipStream_t s) {
+                    const int32_t *order, const int32_t *cell_bed, const BedDev *beds, const Phys &ph, int n_gas,
+                    bool sums, const DepositOut &o, hipStream_t s) {
   const long threads = (long)n_gas * kGroup;
-  k_deposit<T><<<(int)((threads + 255) / 256), 256, 0, s>>>(d, p, g, start, cell_bed, beds, ph, n_gas, sums ? 1 : 0, o);
+  k_deposit<T><<<(int)((threads + 255) / 256), 256, 0, s>>>(d, p, g, start, order, cell_bed, beds, ph, n_gas,
+                                                            sums ? 1 : 0, o);
 }
 
 // ------------------------------------------------------------------ reaction
@@ -177,9 +180,9 @@ void launch_react(const ReactArgs<T> &a, hipStream_t s) {
   k_react<T><<<(a.n + 255) / 256, 256, 0, s>>>(a);
 }
 
-__global__ void __launch_bounds__(256) k_cellsum(const double *pm, int n, const int32_t *start, const int32_t *cell_bed,
-                                                 const BedDev *beds, int n_gas, double *o0, double *o1, double *o2,
-                                                 double *o3) {
+__global__ void __launch_bounds__(256) k_cellsum(const double *pm, int n, const int32_t *start, const int32_t *order,
+                                                 const int32_t *cell_bed, const BedDev *beds, int n_gas, double *o0,
+                                                 double *o1, double *o2, double *o3) {
   const int gc = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
   const int sl = threadIdx.x % kGroup;
   const bool valid = gc < n_gas;
@@ -189,7 +192,8 @@ __global__ void __launch_bounds__(256) k_cellsum(const double *pm, int n, const 
   for (int r = 0; r < R.f * R.f; r++) {
     const int k0 = R.row_key(r);
     const int e = start[k0 + R.f];
-    for (int j = start[k0] + sl; j < e; j += kGroup) {
+    for (int t = start[k0] + sl; t < e; t += kGroup) {
+      const int j = order[t];
 #pragma unroll
       for (int q = 0; q < 4; q++) s[q] += pm[(long)q * n + j];
     }
@@ -204,10 +208,11 @@ __global__ void __launch_bounds__(256) k_cellsum(const double *pm, int n, const 
   }
 }
 
-void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t *cell_bed, const BedDev *beds,
-                    int n_gas, double *o0, double *o1, double *o2, double *o3, hipStream_t s) {
+void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t *order, const int32_t *cell_bed,
+                    const BedDev *beds, int n_gas, double *o0, double *o1, double *o2, double *o3, hipStream_t s) {
   const long threads = (long)n_gas * kGroup;
-  k_cellsum<<<(int)((threads + 255) / 256), 256, 0, s>>>(pm, n, start, cell_bed, beds, n_gas, o0, o1, o2, o3);
+  k_cellsum<<<(int)((threads + 255) / 256), 256, 0, s>>>(pm, n, start, order, cell_bed, beds, n_gas, o0, o1, o2,
+                                                         o3);
 }
 
 // Bed-mean f_ov weighted by k^3 N_Fe: every bed's parcel range (contiguous,
@@ -411,8 +416,8 @@ void launch_import(const dem_parcels &in, int n, const Dyn<T> &d, const Props<T>
 
 #define INST(T)                                                                                                    \
   template void launch_deposit<T>(const Dyn<T> &, const Props<T> &, const GasArgs &, const int32_t *,             \
-                                  const int32_t *, const BedDev *, const Phys &, int, bool, const DepositOut &,   \
-                                  hipStream_t);                                                                    \
+                                  const int32_t *, const int32_t *, const BedDev *, const Phys &, int, bool,      \
+                                  const DepositOut &, hipStream_t);                                                \
   template void launch_react<T>(const ReactArgs<T> &, hipStream_t);                                               \
   template void launch_init<T>(const dem_parcels &, int, const Phys &, int, const Dyn<T> &, const Props<T> &,     \
                                uint32_t *, hipStream_t);                                                           \

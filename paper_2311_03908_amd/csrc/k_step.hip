@@ -52,8 +52,20 @@ __device__ __forceinline__ void cross(const T a[3], const T b[3], T c[3]) {
 template <typename T>
 __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
   const int i = (a.xcd ? xcd_block() : (int)blockIdx.x) * blockDim.x + threadIdx.x;
+  if (a.mode == 0 && blockIdx.x == 0 && threadIdx.x < 64) {
+    // largest displacement of any parcel since the last rebuild, up to the
+    // positions this step starts from (the previous step's wave maxima are
+    // complete); the candidate lists hold every pair while it is below skin/2
+    unsigned *src = a.dslot + ((a.par ^ 1) * kSlots + threadIdx.x) * kSlotPad;
+    float d2 = __uint_as_float(*src);
+    *src = 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) d2 = fmaxf(d2, __shfl_xor(d2, o, 64));
+    const float lim = 0.5f * (float)a.ph.skin - 1e-7f;  // FP32 reference positions
+    if (threadIdx.x == 0 && d2 > lim * lim) atomicOr(a.status, ST_SKIN);
+  }
   const long N = a.n;
-  float vmag = 0.0f;
+  float dmax2 = 0.0f;
   int n_pp = 0, n_w = 0;
   if (i < a.n) {
     const PosRec P = load_pos(a.in.pos, i);
@@ -237,16 +249,19 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
       a.out.vel[i] = Vo;
       if (a.mode == 0 && mnew != mold) a.nb.mask[i] = mnew;
       const float v2 = (float)(Vo.v[0] * Vo.v[0] + Vo.v[1] * Vo.v[1] + Vo.v[2] * Vo.v[2]);
-      vmag = sqrtf(v2);
+      const float4 xr = a.xref[i];
+      const float ex = (float)Po.x - xr.x, ey = (float)Po.y - xr.y, ez = (float)Po.z - xr.z;
+      dmax2 = ex * ex + ey * ey + ez * ez;
       if (!(isfinite(Po.x) && isfinite(Po.y) && isfinite(Po.z) && isfinite(v2) &&
             isfinite((float)(Vo.w[0] + Vo.w[1] + Vo.w[2]))))
         atomicOr(a.status, ST_NONFINITE);
     }
   }
   if (a.mode != 0) return;
-  // per-wave partials (no block barrier, so waves retire independently);
-  // k_step_fin folds them into the displacement bound and the counters
-  float m = vmag;
+  // wave maximum of the displacement and the contact counts, one no-return
+  // atomic per wave into one of kSlots padded slots (so waves rarely contend
+  // and retire independently, with no block barrier)
+  float m = dmax2;
   int c0 = n_pp, c1 = n_w;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -255,53 +270,12 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
     c1 += __shfl_xor(c1, o, 64);
   }
   if ((threadIdx.x & 63) == 0) {
-    const long wv = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    a.wmax[wv] = m;
-    a.wcnt[2 * wv] = c0;
-    a.wcnt[2 * wv + 1] = c1;
-  }
-}
-
-// Every parcel moved by at most dt max|v| in this step: add that to the bound
-// on the displacement since the last rebuild and flag a skin violation.
-__global__ void __launch_bounds__(1024) k_step_fin(const float *wmax, const int32_t *wcnt, long n_waves, double dt,
-                                                   double skin, double *disp, unsigned long long *counters,
-                                                   uint32_t *status) {
-  __shared__ float sm[16];
-  __shared__ long sc[2][16];
-  float m = 0.0f;
-  long c0 = 0, c1 = 0;
-  for (long w = threadIdx.x; w < n_waves; w += blockDim.x) {
-    m = fmaxf(m, wmax[w]);
-    c0 += wcnt[2 * w];
-    c1 += wcnt[2 * w + 1];
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    m = fmaxf(m, __shfl_xor(m, o, 64));
-    c0 += __shfl_xor(c0, o, 64);
-    c1 += __shfl_xor(c1, o, 64);
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) {
-    sm[wid] = m;
-    sc[0][wid] = c0;
-    sc[1][wid] = c1;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float bm = 0.0f;
-    long t0 = 0, t1 = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); w++) {
-      bm = fmaxf(bm, sm[w]);
-      t0 += sc[0][w];
-      t1 += sc[1][w];
+    const int sl = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kSlots - 1));
+    atomicMax(a.dslot + (a.par * kSlots + sl) * kSlotPad, __float_as_uint(m));
+    if (a.count) {
+      if (c0) atomicAdd(a.cslot + sl * kSlotPad64, (unsigned long long)c0);
+      if (c1) atomicAdd(a.cslot + sl * kSlotPad64 + 1, (unsigned long long)c1);
     }
-    const double d = disp[0] + dt * (double)bm;
-    disp[0] = d;
-    if (d > 0.5 * skin) atomicOr(status, ST_SKIN);
-    counters[0] += (unsigned long long)t0;
-    counters[1] += (unsigned long long)t1;
   }
 }
 
@@ -311,12 +285,6 @@ void launch_step(const StepArgs<T> &a, int block, hipStream_t s) {
   k_step<T><<<g, block, 0, s>>>(a);
 }
 
-template <typename T>
-void launch_step_fin(const StepArgs<T> &a, int block, hipStream_t s) {
-  const int g = ((a.n + block - 1) / block + 7) & ~7;
-  k_step_fin<<<1, 1024, 0, s>>>(a.wmax, a.wcnt, (long)g * (block / 64), a.ph.dt, a.ph.skin, a.disp, a.counters,
-                                a.status);
-}
 
 // ------------------------------------------------------------------ gas table
 // Ideal-gas density (eq. e3-53) and mass-weighted viscosity (eqs. e3-55,
@@ -368,8 +336,6 @@ void launch_gas_table(const GasArgs &g, const double *eps, const int32_t *cell_b
 
 template void launch_step<float>(const StepArgs<float> &, int, hipStream_t);
 template void launch_step<double>(const StepArgs<double> &, int, hipStream_t);
-template void launch_step_fin<float>(const StepArgs<float> &, int, hipStream_t);
-template void launch_step_fin<double>(const StepArgs<double> &, int, hipStream_t);
 template void launch_gas_table<float>(const GasArgs &, const double *, const int32_t *, const BedDev *, int, float *,
                                       uint32_t *, hipStream_t);
 template void launch_gas_table<double>(const GasArgs &, const double *, const int32_t *, const BedDev *, int,

@@ -11,7 +11,9 @@ struct Item {  // a run of up to kItemX DEM cells along x in one (y, z) row of a
   int bed, x0, iy, iz;
 };
 constexpr int kItemX = 16;
-constexpr int kTileY = 16;  // key tile height in DEM cells (see dem_key)
+// per-step maxima and counts are gathered in kSlots padded slots (128 bytes
+// apart) by per-wave atomics, and summed by their readers
+constexpr int kSlots = 64, kSlotPad = 32, kSlotPad64 = 16;
 
 void launch_fill_i32(int32_t *p, int32_t v, long n, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, long n, hipStream_t s);
@@ -28,7 +30,7 @@ void launch_cellrank(const int32_t *start, const int32_t *key, const PosRec *pos
                      int32_t *perm_out, hipStream_t s);
 template <typename T>
 void launch_permute(const int32_t *perm, int n, const Dyn<T> &din, const Props<T> &pin, const Dyn<T> &dout,
-                    const Props<T> &pout, unsigned *vmax, double *disp, hipStream_t s);
+                    const Props<T> &pout, float4 *xref, unsigned *dslot, hipStream_t s);
 void launch_items(const Item *items, int n_items, const BedDev *beds, const int32_t *start, int32_t *flags,
                   int32_t *offs, int32_t *scratch, int32_t *list, int32_t *count, hipStream_t s);
 
@@ -64,20 +66,17 @@ struct StepArgs {
   const BedDev *beds;
   Phys ph;
   uint32_t *status;
-  double *disp;                  // displacement bound since the last rebuild
-  float *wmax;                   // per-wave max |v| (mode 0)
-  int32_t *wcnt;                 // per-wave pp and wall contact counts (mode 0)
-  unsigned long long *counters;  // [0] pp contacts, [1] wall contacts (mode 0)
+  const float4 *xref;            // positions at the last rebuild (FP32)
+  unsigned *dslot;               // [2][kSlots] padded: max squared displacement (this step: par)
+  unsigned long long *cslot;     // [kSlots] padded: pp and wall contacts (mode 0 with count)
   int n, par, mode;              // mode 0: integrate; 1: write forces; 2: timing dry run
+  int count;                     // 1: add this step's contacts to counters
   int xcd;                       // 1: remap blocks so each XCD takes a contiguous range
   double *Fout, *Tout;
 };
 template <typename T>
 void launch_step(const StepArgs<T> &a, int block, hipStream_t s);
-template <typename T>
-void launch_step_fin(const StepArgs<T> &a, int block, hipStream_t s);
-// per-wave partial sums of the step kernel: at most this many waves
-inline long step_waves_max(long n) { return n / 64 + 128; }
+
 
 struct GasArgs {
   const double *ug, *vg, *wg, *p, *dpdx, *dpdy, *dpdz, *T, *xH2, *xH2O, *xN2;
@@ -93,8 +92,8 @@ struct DepositOut {
 };
 template <typename T>
 void launch_deposit(const Dyn<T> &d, const Props<T> &p, const GasArgs &g, const int32_t *start,
-                    const int32_t *cell_bed, const BedDev *beds, const Phys &ph, int n_gas, bool sums,
-                    const DepositOut &o, hipStream_t s);
+                    const int32_t *order, const int32_t *cell_bed, const BedDev *beds, const Phys &ph, int n_gas,
+                    bool sums, const DepositOut &o, hipStream_t s);
 
 template <typename T>
 struct ReactArgs {
@@ -116,7 +115,8 @@ struct ReactArgs {
 };
 template <typename T>
 void launch_react(const ReactArgs<T> &a, hipStream_t s);
-void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t *cell_bed, const BedDev *beds,
+void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t *order, const int32_t *cell_bed,
+                    const BedDev *beds,
                     int n_gas, double *o0, double *o1, double *o2, double *o3, hipStream_t s);
 constexpr int kBedChunk = 4096;  // parcels per partial sum of the bed means
 void launch_bedsum(const double *pw, int n, const int32_t *start, const BedDev *beds, int n_beds, int4 *chunks,

@@ -413,11 +413,13 @@ def cfg3(n=2_000_000, seed=3, steps=500, u=0.01, kn=200.0):
     starts in.  kn = 200 N/m: a linear stiffness of the size a Hertzian contact
     with the paper's Y = 1e7 Pa at u_c = 1 m/s gives for these parcels, and one
     that keeps the contact of the smallest parcels (d = 0.2 mm, 3 sigma below
-    the median) resolved at dt = 5 us (kn = 1000 N/m would make it unstable)."""
+    the median) resolved at dt = 5 us (kn = 1000 N/m would make it unstable).
+    Neighbour lists are rebuilt every 60 steps (skin 0.1 mm); the voidage and
+    source deposits re-sort by cell at every coupling on their own."""
     ores = [Ore(xi0=0.05, d_pore_cm=3.3e-6), Ore(xi0=0.25, d_pore_cm=9.5e-6)]
     return _cfg_cyl("cfg3", n, 2_000_000, 50e-3, 600e-3, 1.5625e-3, 1, _lognormal_dp, 5.0, ores,
                     lambda rng, m: (rng.random(m) < 0.5).astype(np.int32), 1073.0, 1.0, seed, steps,
-                    skin=1e-4, rebuild=20, u=u, kn=kn)
+                    skin=1e-4, rebuild=60, u=u, kn=kn)
 
 
 def cfg4(n=500_000, seed=4, steps=20_000):
