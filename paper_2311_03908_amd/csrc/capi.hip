@@ -189,7 +189,7 @@ struct Ctx final : dem_ctx {
   int alloc_nbr(Nbr<T> &b) {
     TRY(dalloc(b.cnt, n));
     TRY(dalloc(b.idx, (size_t)kMaxNbr * n));
-    TRY(dalloc(b.hist, (size_t)3 * kMaxNbr * n));
+    TRY(dalloc(b.hist, (size_t)kMaxNbr * n));
     TRY(dalloc(b.mask, n));
     return DEMRX_OK;
   }

@@ -89,13 +89,22 @@ struct Props {
   T *wh;         // wall tangential springs by original id: [(wall * 3 + axis) * N + id]
 };
 
+// Four values loaded and stored as one vector record
+template <typename T>
+struct alignas(sizeof(T) * 4) Quad {
+  T x, y, z, w;
+};
+// Tangential spring of one contact slot (w unused)
+template <typename T>
+using Spring = Quad<T>;
+
 // Neighbour list (slot-major) with the pair tangential springs of each slot
 template <typename T>
 struct Nbr {
   int32_t *cnt;
-  int32_t *idx;    // [slot * N + i] sorted index of the partner
-  T *hist;         // [(axis * kMaxNbr + slot) * N + i]
-  uint64_t *mask;  // bit s: slot s in contact last step; bits 48..53: walls
+  int32_t *idx;       // [slot * N + i] sorted index of the partner
+  Spring<T> *hist;    // [slot * N + i]
+  uint64_t *mask;     // bit s: slot s in contact last step; bits 48..53: walls
 };
 
 // Vector loads of the records (one 16-byte transaction per half)
@@ -219,7 +228,7 @@ __device__ __forceinline__ T beta_over_epsp(T eps, T rho, T mu, T slip, T dp, in
   return T(0.75) * cdre * mu * tpow<T>(eps, T(-2.65)) / (dp * dp);
 }
 
-// Per-gas-cell drag table row: ug vg wg eps dpdx dpdy dpdz rho mu (+pad)
+// Per-gas-cell drag table row, three quads: (ug vg wg eps) (dpdx dpdy dpdz rho) (mu - - -)
 constexpr int kGasRow = 12;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

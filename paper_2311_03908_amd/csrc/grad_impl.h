@@ -52,7 +52,7 @@ int Ctx<T>::grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, 
   const size_t o_kcg = take(N * 4), o_tag = take(N * 4), o_sp = take(4 * N * 8);
   const size_t o_wh = take((size_t)3 * kMaxWalls * N * sizeof(T));
   const size_t o_cnt = take(N * 4), o_idx = take((size_t)kMaxNbr * N * 4);
-  const size_t o_hist = take((size_t)3 * kMaxNbr * N * sizeof(T)), o_mask = take(N * 8);
+  const size_t o_hist = take((size_t)kMaxNbr * N * sizeof(Spring<T>)), o_mask = take(N * 8);
   const size_t o_eps = take((size_t)n_gas * 8), o_start = take(((size_t)n_keys + 1) * 4);
   const size_t o_xref = take(N * sizeof(float4));
   if (off > gscr.cap) {
@@ -82,7 +82,7 @@ int Ctx<T>::grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, 
       {p0.nh, o_sp, N * 8}, {p0.nm, o_sp + N * 8, N * 8}, {p0.nw, o_sp + 2 * N * 8, N * 8},
       {p0.nfe, o_sp + 3 * N * 8, N * 8}, {p0.wh, o_wh, (size_t)3 * kMaxWalls * N * sizeof(T)},
       {b0.cnt, o_cnt, N * 4}, {b0.idx, o_idx, (size_t)kMaxNbr * N * 4},
-      {b0.hist, o_hist, (size_t)3 * kMaxNbr * N * sizeof(T)}, {b0.mask, o_mask, N * 8},
+      {b0.hist, o_hist, (size_t)kMaxNbr * N * sizeof(Spring<T>)}, {b0.mask, o_mask, N * 8},
       {eps, o_eps, (size_t)n_gas * 8}, {start, o_start, ((size_t)n_keys + 1) * 4},
       {xref, o_xref, N * sizeof(float4)}};
   for (const Cp &c : cps) HIPCHK(hipMemcpyAsync(B + c.o, c.live, c.bytes, hipMemcpyDeviceToDevice, st));

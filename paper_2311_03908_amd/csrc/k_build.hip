@@ -429,10 +429,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
                     if (a.pos_old[a.nb_old.idx[(long)q2 * N + po]].id == idn) qo = q2;
                   }
                   if (qo >= 0) {
-#pragma unroll
-                    for (int ax = 0; ax < 3; ax++)
-                      a.nb_new.hist[((long)ax * kMaxNbr + sl) * N + i] =
-                          a.nb_old.hist[((long)ax * kMaxNbr + qo) * N + po];
+                    a.nb_new.hist[(long)sl * N + i] = a.nb_old.hist[(long)qo * N + po];
                     newbits |= 1ull << sl;
                   }
                 }

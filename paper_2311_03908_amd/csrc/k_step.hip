@@ -50,7 +50,7 @@ __device__ __forceinline__ void cross(const T a[3], const T b[3], T c[3]) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
+__global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 1) k_step(StepArgs<T> a) {
   const int i = (a.xcd ? xcd_block() : (int)blockIdx.x) * blockDim.x + threadIdx.x;
   if (a.mode == 0 && blockIdx.x == 0 && threadIdx.x < 64) {
     // largest displacement of any parcel since the last rebuild, up to the
@@ -126,8 +126,10 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
       const T zeta = zi_ > Vj.zeta ? zi_ : Vj.zeta;
       T xin[3] = {T(0), T(0), T(0)};
       if ((mold >> s) & 1ull) {
-#pragma unroll
-        for (int c = 0; c < 3; c++) xin[c] = a.nb.hist[((long)c * kMaxNbr + s) * N + i];
+        const Spring<T> h = a.nb.hist[(long)s * N + i];
+        xin[0] = h.x;
+        xin[1] = h.y;
+        xin[2] = h.z;
       }
       T Fa[3], Ft[3], xo[3], fnabs;
       contact_force<T>(a.ph, mstar, zeta, delta, n, vrel, xin, Fa, Ft, xo, fnabs);
@@ -143,8 +145,7 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
         for (int c = 0; c < 3; c++) Tq[c] -= T(a.ph.mu_r) * fnabs * Vi.w[c] / wmag;
       }
       if (a.mode == 0) {
-#pragma unroll
-        for (int c = 0; c < 3; c++) a.nb.hist[((long)c * kMaxNbr + s) * N + i] = xo[c];
+        a.nb.hist[(long)s * N + i] = Spring<T>{xo[0], xo[1], xo[2], T(0)};
       }
       n_pp++;
     };
@@ -174,57 +175,67 @@ __global__ void __launch_bounds__(512) k_step(StepArgs<T> a) {
         if (jj[k] >= 0) pair(t0 + k, jj[k], Qs[k]);
     }
     mnew = cbits;
-    // walls: same law against a body of infinite mass and radius at rest
-    const BedDev &B = a.beds[bed_of(tag)];
-    for (int w = 0; w < B.n_walls; w++) {
-      double nv[3];
-      const double phi = wall_clearance(B, w, xi, yi, zi, nv);
-      const double delw = (double)rif - phi;
-      if (!(delw > 0.0)) continue;
-      const T n[3] = {T(nv[0]), T(nv[1]), T(nv[2])};
-      T wr[3] = {ri * Vi.w[0], ri * Vi.w[1], ri * Vi.w[2]}, cr[3];
-      cross(wr, n, cr);
-      const T vrel[3] = {Vi.v[0] + cr[0], Vi.v[1] + cr[1], Vi.v[2] + cr[2]};
-      T xin[3] = {T(0), T(0), T(0)};
-      if ((mold >> (kWallBit + w)) & 1ull) {
+    // walls, gravity, pressure gradient and drag, against the parcel's bed
+    auto bed_terms = [&](const BedDev &B) {
+      // walls: same law against a body of infinite mass and radius at rest
+      for (int w = 0; w < B.n_walls; w++) {
+        double nv[3];
+        const double phi = wall_clearance(B, w, xi, yi, zi, nv);
+        const double delw = (double)rif - phi;
+        if (!(delw > 0.0)) continue;
+        const T n[3] = {T(nv[0]), T(nv[1]), T(nv[2])};
+        T wr[3] = {ri * Vi.w[0], ri * Vi.w[1], ri * Vi.w[2]}, cr[3];
+        cross(wr, n, cr);
+        const T vrel[3] = {Vi.v[0] + cr[0], Vi.v[1] + cr[1], Vi.v[2] + cr[2]};
+        T xin[3] = {T(0), T(0), T(0)};
+        if ((mold >> (kWallBit + w)) & 1ull) {
 #pragma unroll
-        for (int c = 0; c < 3; c++) xin[c] = a.pr.wh[(long)(w * 3 + c) * N + idi];
+          for (int c = 0; c < 3; c++) xin[c] = a.pr.wh[(long)(w * 3 + c) * N + idi];
+        }
+        T Fa[3], Ft[3], xo[3], fnabs;
+        contact_force<T>(a.ph, mi, zi_, T(delw), n, vrel, xin, Fa, Ft, xo, fnabs);
+        T tq[3];
+        cross(n, Ft, tq);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          F[c] += Fa[c];
+          Tq[c] += ri * tq[c];
+        }
+        if (roll) {
+#pragma unroll
+          for (int c = 0; c < 3; c++) Tq[c] -= T(a.ph.mu_r) * fnabs * Vi.w[c] / wmag;
+        }
+        if (a.mode == 0) {
+#pragma unroll
+          for (int c = 0; c < 3; c++) a.pr.wh[(long)(w * 3 + c) * N + idi] = xo[c];
+        }
+        mnew |= 1ull << (kWallBit + w);
+        n_w++;
       }
-      T Fa[3], Ft[3], xo[3], fnabs;
-      contact_force<T>(a.ph, mi, zi_, T(delw), n, vrel, xin, Fa, Ft, xo, fnabs);
-      T tq[3];
-      cross(n, Ft, tq);
+      // gravity, pressure gradient and drag (eqs. e3-3, e3-5), NGP gas cell
 #pragma unroll
-      for (int c = 0; c < 3; c++) {
-        F[c] += Fa[c];
-        Tq[c] += ri * tq[c];
+      for (int c = 0; c < 3; c++) F[c] += mi * T(a.ph.g[c]);
+      if (a.ph.drag_on) {
+        Cells cl;
+        locate(B, xi, yi, zi, cl);
+        const Quad<T> *gq = reinterpret_cast<const Quad<T> *>(a.gtab + (long)cl.gas * kGasRow);
+        const Quad<T> g0 = gq[0], g1 = gq[1];
+        const T mu = gq[2].x;
+        const T dpr = T(2) * ri / T(a.pr.kcg[i]);  // real-particle diameter
+        const T V = T(kPi / 6.0) * (T(2) * ri) * (T(2) * ri) * (T(2) * ri);
+        const T s[3] = {g0.x - Vi.v[0], g0.y - Vi.v[1], g0.z - Vi.v[2]};
+        const T slip = tsqrt<T>(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+        const T be = beta_over_epsp<T>(g0.w, g1.w, mu, slip, dpr, a.ph.ergun_printed);
+        F[0] += be * V * s[0] - V * g1.x;
+        F[1] += be * V * s[1] - V * g1.y;
+        F[2] += be * V * s[2] - V * g1.z;
       }
-      if (roll) {
-#pragma unroll
-        for (int c = 0; c < 3; c++) Tq[c] -= T(a.ph.mu_r) * fnabs * Vi.w[c] / wmag;
-      }
-      if (a.mode == 0) {
-#pragma unroll
-        for (int c = 0; c < 3; c++) a.pr.wh[(long)(w * 3 + c) * N + idi] = xo[c];
-      }
-      mnew |= 1ull << (kWallBit + w);
-      n_w++;
-    }
-    // gravity, pressure gradient and drag (eqs. e3-3, e3-5), NGP gas cell
-#pragma unroll
-    for (int c = 0; c < 3; c++) F[c] += mi * T(a.ph.g[c]);
-    if (a.ph.drag_on) {
-      Cells cl;
-      locate(B, xi, yi, zi, cl);
-      const T *g = a.gtab + (long)cl.gas * kGasRow;
-      const T dpr = T(2) * ri / T(a.pr.kcg[i]);  // real-particle diameter
-      const T V = T(kPi / 6.0) * (T(2) * ri) * (T(2) * ri) * (T(2) * ri);
-      const T s[3] = {g[0] - Vi.v[0], g[1] - Vi.v[1], g[2] - Vi.v[2]};
-      const T slip = tsqrt<T>(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
-      const T be = beta_over_epsp<T>(g[3], g[7], g[8], slip, dpr, a.ph.ergun_printed);
-#pragma unroll
-      for (int c = 0; c < 3; c++) F[c] += be * V * s[c] - V * g[4 + c];
-    }
+    };
+    // with a single bed its record is read through uniform (scalar) loads
+    if (a.ph.n_beds == 1)
+      bed_terms(a.beds[0]);
+    else
+      bed_terms(a.beds[bed_of(tag)]);
     if (a.mode == 1) {
 #pragma unroll
       for (int c = 0; c < 3; c++) {
