@@ -149,6 +149,10 @@ typedef struct {
   uint32_t status;
   double step_kernel_ms;         /* mean duration of the timed DEM-step kernel launches */
   int64_t step_kernel_launches;  /* launches behind step_kernel_ms (see dem_profile) */
+  int32_t step_block;            /* launch shape in use (dem_autotune): step-kernel block size, */
+  int32_t step_xcd;              /* blocks per XCD chunk (1: plain round-robin), */
+  int32_t build_grid;            /* persistent grid of the neighbour build */
+  int32_t rebuild_period;        /* steps between neighbour-list rebuilds in dem_run */
 } dem_stats;
 
 /* Create a context holding n parcels.  Copies the parcel state (device, original

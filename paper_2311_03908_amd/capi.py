@@ -70,7 +70,9 @@ class DemStats(C.Structure):
     _fields_ = [("n_parcels", C.c_int64), ("n_contacts", C.c_int64), ("n_wall_contacts", C.c_int64),
                 ("rebuilds", C.c_int64), ("steps", C.c_int64), ("clamps", C.c_int64),
                 ("mean_coordination", C.c_double), ("max_nbr_used", C.c_int32), ("status", C.c_uint32),
-                ("step_kernel_ms", C.c_double), ("step_kernel_launches", C.c_int64)]
+                ("step_kernel_ms", C.c_double), ("step_kernel_launches", C.c_int64),
+                ("step_block", C.c_int32), ("step_xcd", C.c_int32), ("build_grid", C.c_int32),
+                ("rebuild_period", C.c_int32)]
 
 
 EXPORTS = ("dem_init", "dem_step", "dem_couple", "dem_react", "dem_grad", "dem_forces", "dem_get_state",

@@ -131,7 +131,7 @@ struct Ctx final : dem_ctx {
   long pairs_cap = 0;
   long step_count = 0, steps_since = 0, rebuilds = 0;
   bool built = false;
-  int step_block = 256, build_grid = 1024, step_xcd = 1;
+  int step_block = 64, build_grid = 1024, step_xcd = 1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<const void *> gkey;
@@ -648,6 +648,10 @@ struct Ctx final : dem_ctx {
     }
     o->step_kernel_ms = cnt ? tot / cnt : 0.0;
     o->step_kernel_launches = cnt;
+    o->step_block = step_block;
+    o->step_xcd = step_xcd;
+    o->build_grid = build_grid;
+    o->rebuild_period = P.rebuild_every;
     return r;
   }
 
@@ -770,20 +774,21 @@ struct Ctx final : dem_ctx {
     HIPCHK(hipEventCreate(&e1));
     float best = 1e30f;
     int best_b = step_block, best_x = step_xcd;
-    for (int cand = 0; cand < 8; cand++) {
-      const int b = 64 << (cand % 4);
-      step_xcd = cand / 4;
-      float tot = 0.0f;
-      for (int rep = 0; rep < 4; rep++) {
-        HIPCHK(hipEventRecord(e0, st));
-        launch_step<T>(step_args(2), b, st);
-        HIPCHK(hipEventRecord(e1, st));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (rep) tot += ms;
+    for (int b : {64, 128, 256, 512}) {
+      for (int x : {1, 4, 16, 64}) {
+        step_xcd = x;
+        float tot = 0.0f;
+        for (int rep = 0; rep < 4; rep++) {
+          HIPCHK(hipEventRecord(e0, st));
+          launch_step<T>(step_args(2), b, st);
+          HIPCHK(hipEventRecord(e1, st));
+          HIPCHK(hipEventSynchronize(e1));
+          float ms = 0.0f;
+          HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+          if (rep) tot += ms;
+        }
+        if (tot < best) { best = tot; best_b = b; best_x = x; }
       }
-      if (tot < best) { best = tot; best_b = b; best_x = step_xcd; }
     }
     step_block = best_b;
     step_xcd = best_x;

@@ -124,12 +124,15 @@ __device__ __forceinline__ void store_pos(PosRec *p, long i, const PosRec &r) {
   *reinterpret_cast<double4 *>(p + i) = make_double4(r.x, r.y, r.z, __longlong_as_double((long long)bits));
 }
 
-// Block index remapped so that the 8 XCDs, which receive workgroups in turn,
-// each work on one contiguous eighth of the grid and keep their neighbours'
-// records in their own L2.  The grid is a multiple of 8.
-__device__ __forceinline__ int xcd_block() {
-  const int per = gridDim.x >> 3;
-  return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+// Block index remapped for the 8 XCDs, which receive workgroups in turn:
+// each XCD takes chunks of `chunk` consecutive blocks (chunk 1: no remap;
+// chunk grid/8: one contiguous range per XCD).  Larger chunks keep a
+// neighbourhood's records in one XCD's L2; smaller ones spread the requests
+// over more L2 channels and balance the XCDs.  The grid is a multiple of
+// 8 * chunk.
+__device__ __forceinline__ int xcd_block(int chunk) {
+  const int j = (int)(blockIdx.x >> 3), x = (int)(blockIdx.x & 7);
+  return (j / chunk) * (8 * chunk) + x * chunk + (j % chunk);
 }
 
 __device__ __forceinline__ int bed_of(int32_t tag) { return tag >> 8; }

@@ -51,7 +51,7 @@ __device__ __forceinline__ void cross(const T a[3], const T b[3], T c[3]) {
 
 template <typename T>
 __global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 1) k_step(StepArgs<T> a) {
-  const int i = (a.xcd ? xcd_block() : (int)blockIdx.x) * blockDim.x + threadIdx.x;
+  const int i = (a.xcd > 1 ? xcd_block(a.xcd) : (int)blockIdx.x) * blockDim.x + threadIdx.x;
   if (a.mode == 0 && blockIdx.x == 0 && threadIdx.x < 64) {
     // largest displacement of any parcel since the last rebuild, up to the
     // positions this step starts from (the previous step's wave maxima are
@@ -292,7 +292,8 @@ __global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 1) k_step(StepArgs<T
 
 template <typename T>
 void launch_step(const StepArgs<T> &a, int block, hipStream_t s) {
-  const int g = ((a.n + block - 1) / block + 7) & ~7;  // multiple of 8 for the XCD remap
+  const int q = 8 * (a.xcd > 1 ? a.xcd : 1);  // grid: a multiple of 8 chunks for the XCD remap
+  const int g = ((a.n + block - 1) / block + q - 1) / q * q;
   k_step<T><<<g, block, 0, s>>>(a);
 }
 

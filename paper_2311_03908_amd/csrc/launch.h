@@ -71,7 +71,7 @@ struct StepArgs {
   unsigned long long *cslot;     // [kSlots] padded: pp and wall contacts (mode 0 with count)
   int n, par, mode;              // mode 0: integrate; 1: write forces; 2: timing dry run
   int count;                     // 1: add this step's contacts to counters
-  int xcd;                       // 1: remap blocks so each XCD takes a contiguous range
+  int xcd;                       // >1: XCD chunk of consecutive blocks (see xcd_block)
   double *Fout, *Tout;
 };
 template <typename T>

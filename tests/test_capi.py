@@ -37,6 +37,7 @@ def test_struct_layouts_match_header_sizes():
     assert C.sizeof(capi.DemParcels) == 17 * 8
     assert C.sizeof(capi.DemGas) == 11 * 8
     assert C.sizeof(capi.DemSources) == 11 * 8
+    assert C.sizeof(capi.DemStats) == 6 * 8 + 8 + 4 + 4 + 8 + 8 + 4 * 4
 
 
 def test_host_validation_rejects_null_and_bad_arguments():
