@@ -160,96 +160,125 @@ __global__ void __launch_bounds__(256) k_adj_forward(AdjArgs a) {
 }
 
 // ------------------------------------------------------------------ backward
+template <typename C>
 struct D6 {  // value and tangents w.r.t. (A0, A1, A2, B0, B1, B2)
-  double v, d[6];
+  C v, d[6];
 };
-__device__ __forceinline__ D6 dc(double v) {
-  D6 r;
+template <typename C>
+__device__ __forceinline__ D6<C> dc(C v) {
+  D6<C> r;
   r.v = v;
 #pragma unroll
-  for (int t = 0; t < 6; t++) r.d[t] = 0.0;
+  for (int t = 0; t < 6; t++) r.d[t] = C(0);
   return r;
 }
-__device__ __forceinline__ D6 dvar(double v, int t) {
-  D6 r = dc(v);
-  r.d[t] = 1.0;
+template <typename C>
+__device__ __forceinline__ D6<C> dvar(C v, int t) {
+  D6<C> r = dc<C>(v);
+  r.d[t] = C(1);
   return r;
 }
-__device__ __forceinline__ D6 operator+(const D6 &a, const D6 &b) {
-  D6 r;
+template <typename C>
+__device__ __forceinline__ D6<C> operator+(const D6<C> &a, const D6<C> &b) {
+  D6<C> r;
   r.v = a.v + b.v;
 #pragma unroll
   for (int t = 0; t < 6; t++) r.d[t] = a.d[t] + b.d[t];
   return r;
 }
-__device__ __forceinline__ D6 operator-(const D6 &a, const D6 &b) {
-  D6 r;
+template <typename C>
+__device__ __forceinline__ D6<C> operator-(const D6<C> &a, const D6<C> &b) {
+  D6<C> r;
   r.v = a.v - b.v;
 #pragma unroll
   for (int t = 0; t < 6; t++) r.d[t] = a.d[t] - b.d[t];
   return r;
 }
-__device__ __forceinline__ D6 operator*(const D6 &a, const D6 &b) {
-  D6 r;
+template <typename C>
+__device__ __forceinline__ D6<C> operator*(const D6<C> &a, const D6<C> &b) {
+  D6<C> r;
   r.v = a.v * b.v;
 #pragma unroll
   for (int t = 0; t < 6; t++) r.d[t] = a.d[t] * b.v + a.v * b.d[t];
   return r;
 }
-__device__ __forceinline__ D6 operator/(const D6 &a, const D6 &b) {
-  D6 r;
-  r.v = a.v / b.v;
-  const double ib = 1.0 / b.v;
+template <typename C>
+__device__ __forceinline__ D6<C> operator/(const D6<C> &a, const D6<C> &b) {
+  D6<C> r;
+  const C ib = C(1) / b.v;
+  r.v = a.v * ib;
 #pragma unroll
   for (int t = 0; t < 6; t++) r.d[t] = (a.d[t] - r.v * b.d[t]) * ib;
   return r;
 }
 
-// lam <- lam dg/dn, tb += lam dg/dtheta at state n (vector-Jacobian product of uscm_step)
-__device__ void uscm_vjp(const double n[4], const UscmEnv<double> &e, double irt, double lam[4], double tb[6]) {
+template <typename C>
+__device__ __forceinline__ C icbrt_c(C u);
+template <>
+__device__ __forceinline__ float icbrt_c<float>(float u) { return 1.0f / cbrtf(u); }
+template <>
+__device__ __forceinline__ double icbrt_c<double>(double u) { return 1.0 / cbrt(u); }
+
+// lam <- lam dg/dn, tb += lam dg/dtheta at state n (vector-Jacobian product of
+// uscm_step).  The partial derivatives are formed in C (float for an FP32
+// reaction state: their rounding is far below the state's own); lam and the
+// theta accumulators stay in FP64.
+template <typename C>
+__device__ __forceinline__ void uscm_vjp(const double n[4], const UscmEnv<double> &e, double irt, double lam[4], double tb[6]) {
   const double Nfe = 2.0 * n[0] + 3.0 * n[1] + n[2] + n[3];
   const double cum[3] = {2.0 * n[0], 2.0 * n[0] + 3.0 * n[1], 2.0 * n[0] + 3.0 * n[1] + n[2]};
   bool act[3];
   int inner = 3;
+#pragma unroll
   for (int q = 0; q < 3; q++) {
     act[q] = n[q] > 1e-12 * Nfe && e.x > e.xeq[q];
     if (act[q] && inner == 3) inner = q;
   }
   if (inner == 3) return;
-  double u[3], ic[3], A[3], Bv[3];
+  C u[3], ic[3], A[3], Bv[3];
+#pragma unroll
   for (int q = 0; q < 3; q++) {
-    u[q] = cum[q] / Nfe;
-    ic[q] = q >= inner ? 1.0 / cbrt(u[q]) : 0.0;
+    u[q] = C(cum[q] / Nfe);
+    ic[q] = q >= inner ? icbrt_c<C>(u[q]) : C(0);
   }
+#pragma unroll
   for (int q = 0; q < 3; q++) {
-    A[q] = act[q] ? ic[q] * ic[q] * e.kk[q] : 1.0;
-    const double outer = q < 2 ? ic[q + 1] : 1.0;
-    Bv[q] = q >= inner ? (ic[q] - outer) * e.rpD[q] : 0.0;
+    A[q] = act[q] ? ic[q] * ic[q] * C(e.kk[q]) : C(1);
+    const C outer = q < 2 ? ic[q + 1] : C(1);
+    Bv[q] = q >= inner ? (ic[q] - outer) * C(e.rpD[q]) : C(0);
   }
-  // network solve with tangents over (A, B)
-  D6 Ad[3], Bd[3];
+  // network solve with tangents over (A, B); loops unrolled over the three
+  // interfaces so that every array index is static (no scratch)
+  D6<C> Ad[3], Bd[3];
+#pragma unroll
   for (int q = 0; q < 3; q++) {
-    Ad[q] = dvar(A[q], q);
-    Bd[q] = dvar(Bv[q], 3 + q);
+    Ad[q] = dvar<C>(A[q], q);
+    Bd[q] = dvar<C>(Bv[q], 3 + q);
   }
-  D6 R = Ad[inner], Phi = dc(e.xeq[inner]);
-  for (int q = inner + 1; q < 3; q++) {
+  const C ex = C(e.x), eF = C(e.F);
+  D6<C> R = inner == 0 ? Ad[0] : (inner == 1 ? Ad[1] : Ad[2]);
+  D6<C> Phi = dc<C>(C(inner == 0 ? e.xeq[0] : (inner == 1 ? e.xeq[1] : e.xeq[2])));
+#pragma unroll
+  for (int q = 1; q < 3; q++) {
+    if (q <= inner) continue;
     R = R + Bd[q - 1];
     if (act[q]) {
-      const D6 one = dc(1.0);
-      const D6 g1 = one / R, g2 = one / Ad[q];
-      Phi = (Phi * g1 + dc(e.xeq[q]) * g2) / (g1 + g2);
+      const D6<C> one = dc<C>(C(1));
+      const D6<C> g1 = one / R, g2 = one / Ad[q];
+      Phi = (Phi * g1 + dc<C>(C(e.xeq[q])) * g2) / (g1 + g2);
       R = one / (g1 + g2);
     }
   }
-  const D6 Rt = R + Bd[2] + dc(e.F);
-  const D6 flux = (dc(e.x) - Phi) / Rt;
-  D6 pot = dc(e.x) - flux * (dc(e.F) + Bd[2]);
-  D6 rest = flux;
-  D6 r[3] = {dc(0.0), dc(0.0), dc(0.0)};
-  for (int q = 2; q >= inner; q--) {
+  const D6<C> Rt = R + Bd[2] + dc<C>(eF);
+  const D6<C> flux = (dc<C>(ex) - Phi) / Rt;
+  D6<C> pot = dc<C>(ex) - flux * (dc<C>(eF) + Bd[2]);
+  D6<C> rest = flux;
+  D6<C> r[3] = {dc<C>(C(0)), dc<C>(C(0)), dc<C>(C(0))};
+#pragma unroll
+  for (int q = 2; q >= 0; q--) {
+    if (q < inner) continue;
     if (act[q]) {
-      r[q] = (pot - dc(e.xeq[q])) / Ad[q];
+      r[q] = (pot - dc<C>(C(e.xeq[q]))) / Ad[q];
       rest = rest - r[q];
     }
     if (q > inner) pot = pot - rest * Bd[q - 1];
@@ -259,25 +288,28 @@ __device__ void uscm_vjp(const double n[4], const UscmEnv<double> &e, double irt
   const double nu[3] = {3.0, 1.0, 1.0};
   double nl[4] = {lam[0], lam[1], lam[2], lam[3]};
   double Ab[3] = {0, 0, 0}, Bb[3] = {0, 0, 0};
+#pragma unroll
   for (int q = 0; q < 3; q++) {
-    if (r[q].v < 0.0) continue;                 // clamped: no dependence
-    if (r[q].v * e.cad > n[q] / nu[q]) {        // capped by the reactant
+    if (r[q].v < C(0)) continue;                         // clamped: no dependence
+    if ((double)r[q].v * e.cad > n[q] / nu[q]) {         // capped by the reactant
       nl[q] += xb[q] / nu[q];
       continue;
     }
     const double rb = e.cad * xb[q];
+#pragma unroll
     for (int t = 0; t < 3; t++) {
-      Ab[t] += rb * r[q].d[t];
-      Bb[t] += rb * r[q].d[3 + t];
+      Ab[t] += rb * (double)r[q].d[t];
+      Bb[t] += rb * (double)r[q].d[3 + t];
     }
   }
   // resistances -> theta and remaining fractions
   double ab[3] = {0, 0, 0};
+#pragma unroll
   for (int q = 0; q < 3; q++) {
     if (act[q]) {
-      tb[2 * q] += -Ab[q] * A[q];
-      tb[2 * q + 1] += Ab[q] * A[q] * irt;
-      ab[q] += Ab[q] * 2.0 * ic[q] * e.kk[q];
+      tb[2 * q] += -Ab[q] * (double)A[q];
+      tb[2 * q + 1] += Ab[q] * (double)A[q] * irt;
+      ab[q] += Ab[q] * 2.0 * (double)ic[q] * e.kk[q];
     }
     if (q >= inner) {
       ab[q] += Bb[q] * e.rpD[q];
@@ -287,9 +319,13 @@ __device__ void uscm_vjp(const double n[4], const UscmEnv<double> &e, double irt
   // u_q = cum_q / N with dcum/dn = (2,0,0,0), (2,3,0,0), (2,3,1,0) and dN/dn = (2,3,1,1)
   const double dcum[3][4] = {{2, 0, 0, 0}, {2, 3, 0, 0}, {2, 3, 1, 0}};
   const double dN[4] = {2, 3, 1, 1};
-  for (int q = inner; q < 3; q++) {
-    const double ub = ab[q] * (-ic[q] / (3.0 * u[q]));
-    for (int z = 0; z < 4; z++) nl[z] += ub * (dcum[q][z] - u[q] * dN[z]) / Nfe;
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    if (q < inner) continue;
+    const double uq = cum[q] / Nfe;
+    const double ub = ab[q] * (-(double)ic[q] / (3.0 * uq));
+#pragma unroll
+    for (int z = 0; z < 4; z++) nl[z] += ub * (dcum[q][z] - uq * dN[z]) / Nfe;
   }
   for (int z = 0; z < 4; z++) lam[z] = nl[z];
 }
@@ -348,17 +384,19 @@ __global__ void __launch_bounds__(256) k_adj_backward(AdjArgs a) {
         const double w = a.k3[i] * (2.0 * nf[0] + 3.0 * nf[1] + nf[2] + nf[3]);
         for (int z = 0; z < 4; z++) lam[z] = a.inv_W * w * g[z];
       }
-      kcur = -1;
-      UscmEnv<double> ed;
-      for (int s = s1 - 1; s >= s0; s--) {
+      // substeps of the segment, last first, grouped by dynamics interval so
+      // that each interval's environment is loaded once
+      for (int s = s1 - 1; s >= s0;) {
         const int k = s / a.dyn_every;
-        if (k != kcur) {
-          load_env<double>(a, i, k, ed, irt);
-          kcur = k;
+        const int s_lo = max(s0, k * a.dyn_every);
+        UscmEnv<double> ed;
+        double irt_k;
+        load_env<double>(a, i, k, ed, irt_k);
+        for (; s >= s_lo; s--) {
+          const S *src = seg + (long)(s - s0) * 4 * N;
+          const double ns[4] = {(double)src[i], (double)src[N + i], (double)src[2 * N + i], (double)src[3 * N + i]};
+          uscm_vjp<S>(ns, ed, irt_k, lam, tb);
         }
-        const S *src = seg + (long)(s - s0) * 4 * N;
-        const double ns[4] = {(double)src[i], (double)src[N + i], (double)src[2 * N + i], (double)src[3 * N + i]};
-        uscm_vjp(ns, ed, irt, lam, tb);
       }
     }
     for (int t = 0; t < 6; t++) v[2 + t] = tb[t];

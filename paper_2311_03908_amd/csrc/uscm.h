@@ -57,8 +57,12 @@ __device__ __forceinline__ int uscm_step(S n[4], const UscmEnv<S> &e, S xi[3], S
       const S outer = q < 2 ? ic[q + 1] : S(1);
       Bl[q] = q >= inner ? (ic[q] - outer) * e.rpD[q] : S(0);
     }
-    S Rin = A[inner], Phi = e.xeq[inner];
-    for (int q = inner + 1; q < 3; q++) {
+    // loops over the three interfaces are unrolled with static indices
+    S Rin = inner == 0 ? A[0] : (inner == 1 ? A[1] : A[2]);
+    S Phi = inner == 0 ? e.xeq[0] : (inner == 1 ? e.xeq[1] : e.xeq[2]);
+#pragma unroll
+    for (int q = 1; q < 3; q++) {
+      if (q <= inner) continue;
       Rin += Bl[q - 1];
       if (act[q]) {
         const S g1 = S(1) / Rin, g2 = S(1) / A[q];
@@ -72,7 +76,9 @@ __device__ __forceinline__ int uscm_step(S n[4], const UscmEnv<S> &e, S xi[3], S
     Sn = Phi / Rtot;
     S pot = e.x - flux * (e.F + Bl[2]);
     S rest = flux;
-    for (int q = 2; q >= inner; q--) {
+#pragma unroll
+    for (int q = 2; q >= 0; q--) {
+      if (q < inner) continue;
       if (act[q]) {
         r[q] = (pot - e.xeq[q]) / A[q];
         rest -= r[q];
