@@ -115,6 +115,7 @@ struct Ctx final : dem_ctx {
   // coupling without permuting the parcels or rebuilding neighbour lists)
   int32_t *start_d = nullptr, *order_d = nullptr;
   bool dep_fresh = false;
+  int32_t *occ_flags = nullptr, *occ_offs = nullptr, *occ_list = nullptr, *occ_count = nullptr;
   int4 *bchunks = nullptr;
   double *bpartial = nullptr;
   int max_chunks = 0;
@@ -300,6 +301,8 @@ struct Ctx final : dem_ctx {
     TRY(dalloc(bpartial, 2 * (size_t)max_chunks));
     TRY(dalloc(count, (size_t)n_keys + 1)); TRY(dalloc(start, (size_t)n_keys + 1));
     TRY(dalloc(start_d, (size_t)n_keys + 1)); TRY(dalloc(order_d, n));
+    TRY(dalloc(occ_flags, (size_t)n_gas + 1)); TRY(dalloc(occ_offs, (size_t)n_gas + 1));
+    TRY(dalloc(occ_list, n_gas)); TRY(dalloc(occ_count, 1));
     const long scr = std::max(scan_scratch_ints((long)n_keys + 1), scan_scratch_ints((long)n_items + 1));
     TRY(dalloc(scan_scr, scr));
     TRY(dalloc(iflags, (size_t)n_items + 1)); TRY(dalloc(ioffs, (size_t)n_items + 1));
@@ -330,7 +333,7 @@ struct Ctx final : dem_ctx {
     TRY(resort());
     DepositOut o{};
     o.eps_ctx = eps;
-    launch_deposit<T>(dyn[cur], pr[pc], GasArgs{}, start_d, order_d, cell_bed, beds, ph, n_gas, false, o, st);
+    TRY(deposit(GasArgs{}, false, o));
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     return check_status();
@@ -404,6 +407,16 @@ struct Ctx final : dem_ctx {
   int ensure_dep() {
     if (!built) TRY(rebuild());
     if (!dep_fresh) TRY(resort());
+    return DEMRX_OK;
+  }
+
+  // voidage (and drag sums) of every gas cell from the current cell order:
+  // empty cells directly, occupied cells through their compacted list
+  int deposit(const GasArgs &g, bool sums, const DepositOut &o) {
+    launch_occupied(start_d, cell_bed, beds, n_gas, sums, o, occ_flags, occ_offs, scan_scr, occ_list, occ_count, st);
+    launch_deposit<T>(dyn[cur], pr[pc], g, start_d, order_d, cell_bed, beds, ph, occ_list, occ_count, n_gas, sums, o,
+                      st);
+    HIPCHK(hipGetLastError());
     return DEMRX_OK;
   }
 
@@ -499,7 +512,7 @@ struct Ctx final : dem_ctx {
       d.sumKw = o->sumKw; d.sumKs = o->sumKs;
       sums = o->sumK || o->sumKu || o->sumKv || o->sumKw || o->sumKs;
     }
-    launch_deposit<T>(dyn[cur], pr[pc], gas_args(g), start_d, order_d, cell_bed, beds, ph, n_gas, sums, d, st);
+    TRY(deposit(gas_args(g), sums, d));
     HIPCHK(hipGetLastError());
     return DEMRX_OK;
   }
@@ -573,7 +586,7 @@ struct Ctx final : dem_ctx {
     TRY(resort());
     DepositOut o{};
     o.eps_ctx = eps;
-    launch_deposit<T>(dyn[cur], pr[pc], GasArgs{}, start_d, order_d, cell_bed, beds, ph, n_gas, false, o, st);
+    TRY(deposit(GasArgs{}, false, o));
     HIPCHK(hipGetLastError());
     return sync();
   }

@@ -2,6 +2,8 @@
 // multi-interface unreacted-shrinking-core reaction update, per-cell and
 // per-bed reductions (deterministic: fixed lane assignment and shuffle trees,
 // no floating-point atomics), and state import/export.
+#include <algorithm>
+
 #include "launch.h"
 #include "uscm.h"
 
@@ -34,81 +36,134 @@ struct GasCellRanges {
 };
 
 // ------------------------------------------------------------------ deposition
+// Occupied gas cells: most cells of a tall reactor grid hold no parcel.  One
+// thread per cell writes the outputs of an empty cell (voidage 1, zero sums)
+// and flags the others, which are compacted (scan) into a list; the deposit
+// then runs one 16-lane group per listed cell.
+__global__ void k_occ_flags(const int32_t *start, const int32_t *cell_bed, const BedDev *beds, int n_gas, int sums,
+                            DepositOut o, int32_t *flags) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > n_gas) return;
+  if (c == n_gas) {
+    flags[c] = 0;
+    return;
+  }
+  const GasCellRanges R(beds[cell_bed[c]], c);
+  bool any = false;
+  for (int r = 0; r < R.f * R.f && !any; r++) {
+    const int k0 = R.row_key(r);
+    any = start[k0 + R.f] > start[k0];
+  }
+  flags[c] = any ? 1 : 0;
+  if (any) return;
+  o.eps_ctx[c] = 1.0;
+  if (o.eps) o.eps[c] = 1.0;
+  if (o.np) o.np[c] = 0.0;
+  if (!sums) return;
+  if (o.sumK) o.sumK[c] = 0.0;
+  if (o.sumKu) o.sumKu[c] = 0.0;
+  if (o.sumKv) o.sumKv[c] = 0.0;
+  if (o.sumKw) o.sumKw[c] = 0.0;
+  if (o.sumKs) o.sumKs[c] = 0.0;
+}
+
+__global__ void k_occ_compact(const int32_t *flags, const int32_t *offs, int n_gas, int32_t *list, int32_t *count) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > n_gas) return;
+  if (c == n_gas) {
+    *count = offs[n_gas];
+    return;
+  }
+  if (flags[c]) list[offs[c]] = c;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g, const int32_t *start,
                                                  const int32_t *order, const int32_t *cell_bed, const BedDev *beds,
-                                                 Phys ph, int n_gas, int sums, DepositOut o) {
-  const int gc = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
+                                                 Phys ph, const int32_t *list, const int32_t *list_count, int sums,
+                                                 DepositOut o) {
   const int sl = threadIdx.x % kGroup;
-  const bool valid = gc < n_gas;
-  const int c = valid ? gc : n_gas - 1;
-  const BedDev &B = beds[cell_bed[c]];
-  const GasCellRanges R(B, c);
-  double sv = 0.0, cnt = 0.0;
-  for (int r = 0; r < R.f * R.f; r++) {
-    const int k0 = R.row_key(r);
-    const int e = start[k0 + R.f];
-    for (int q = start[k0] + sl; q < e; q += kGroup) {
-      const int j = order[q];
-      const double dd = 2.0 * (double)d.pos[j].r;
-      sv += kPi / 6.0 * dd * dd * dd;
-      cnt += 1.0;
+  const int n_list = *list_count;
+  const int groups = gridDim.x * (blockDim.x / kGroup);
+  for (int gi = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup; gi < n_list; gi += groups) {
+    const int c = list[gi];
+    const BedDev &B = beds[cell_bed[c]];
+    const GasCellRanges R(B, c);
+    double sv = 0.0, cnt = 0.0;
+    for (int r = 0; r < R.f * R.f; r++) {
+      const int k0 = R.row_key(r);
+      const int e = start[k0 + R.f];
+      for (int q = start[k0] + sl; q < e; q += kGroup) {
+        const int j = order[q];
+        const double dd = 2.0 * (double)d.pos[j].r;
+        sv += kPi / 6.0 * dd * dd * dd;
+        cnt += 1.0;
+      }
+    }
+    sv = group_sum(sv);
+    cnt = group_sum(cnt);
+    double eps = 1.0 - sv / (B.h * B.h * B.h);
+    eps = eps < ph.eps_min ? ph.eps_min : (eps > 1.0 ? 1.0 : eps);
+    if (sl == 0) {
+      o.eps_ctx[c] = eps;
+      if (o.eps) o.eps[c] = eps;
+      if (o.np) o.np[c] = cnt;
+    }
+    if (!sums) continue;
+    double rho, mu;
+    gas_props_h2(g.T[c], g.p[c], g.xH2[c], g.xH2O[c], g.xN2[c], B.mu_override, rho, mu);
+    const double ug = g.ug[c], vg = g.vg[c], wg = g.wg[c];
+    double sK = 0, sKu = 0, sKv = 0, sKw = 0, sKs = 0;
+    for (int r = 0; r < R.f * R.f; r++) {
+      const int k0 = R.row_key(r);
+      const int e = start[k0 + R.f];
+      for (int q = start[k0] + sl; q < e; q += kGroup) {
+        const int j = order[q];
+        const VelRec<T> vr = d.vel[j];
+        const double vx = (double)vr.v[0], vy = (double)vr.v[1], vz = (double)vr.v[2];
+        const double sx = ug - vx, sy = vg - vy, sz = wg - vz;
+        const double slip = sqrt(sx * sx + sy * sy + sz * sz);
+        const double dd = 2.0 * (double)d.pos[j].r;
+        const double V = kPi / 6.0 * dd * dd * dd;
+        const double K = beta_over_epsp<double>(eps, rho, mu, slip, dd / (double)p.kcg[j], ph.ergun_printed) * V;
+        sK += K;
+        sKu += K * vx;
+        sKv += K * vy;
+        sKw += K * vz;
+        sKs += K * slip;
+      }
+    }
+    sK = group_sum(sK);
+    sKu = group_sum(sKu);
+    sKv = group_sum(sKv);
+    sKw = group_sum(sKw);
+    sKs = group_sum(sKs);
+    if (sl == 0) {
+      if (o.sumK) o.sumK[c] = sK;
+      if (o.sumKu) o.sumKu[c] = sKu;
+      if (o.sumKv) o.sumKv[c] = sKv;
+      if (o.sumKw) o.sumKw[c] = sKw;
+      if (o.sumKs) o.sumKs[c] = sKs;
     }
   }
-  sv = group_sum(sv);
-  cnt = group_sum(cnt);
-  double eps = 1.0 - sv / (B.h * B.h * B.h);
-  eps = eps < ph.eps_min ? ph.eps_min : (eps > 1.0 ? 1.0 : eps);
-  if (valid && sl == 0) {
-    o.eps_ctx[c] = eps;
-    if (o.eps) o.eps[c] = eps;
-    if (o.np) o.np[c] = cnt;
-  }
-  if (!sums) return;
-  double rho, mu;
-  gas_props_h2(g.T[c], g.p[c], g.xH2[c], g.xH2O[c], g.xN2[c], B.mu_override, rho, mu);
-  const double ug = g.ug[c], vg = g.vg[c], wg = g.wg[c];
-  double sK = 0, sKu = 0, sKv = 0, sKw = 0, sKs = 0;
-  for (int r = 0; r < R.f * R.f; r++) {
-    const int k0 = R.row_key(r);
-    const int e = start[k0 + R.f];
-    for (int q = start[k0] + sl; q < e; q += kGroup) {
-      const int j = order[q];
-      const VelRec<T> vr = d.vel[j];
-      const double vx = (double)vr.v[0], vy = (double)vr.v[1], vz = (double)vr.v[2];
-      const double sx = ug - vx, sy = vg - vy, sz = wg - vz;
-      const double slip = sqrt(sx * sx + sy * sy + sz * sz);
-      const double dd = 2.0 * (double)d.pos[j].r;
-      const double V = kPi / 6.0 * dd * dd * dd;
-      const double K = beta_over_epsp<double>(eps, rho, mu, slip, dd / (double)p.kcg[j], ph.ergun_printed) * V;
-      sK += K;
-      sKu += K * vx;
-      sKv += K * vy;
-      sKw += K * vz;
-      sKs += K * slip;
-    }
-  }
-  sK = group_sum(sK);
-  sKu = group_sum(sKu);
-  sKv = group_sum(sKv);
-  sKw = group_sum(sKw);
-  sKs = group_sum(sKs);
-  if (valid && sl == 0) {
-    if (o.sumK) o.sumK[c] = sK;
-    if (o.sumKu) o.sumKu[c] = sKu;
-    if (o.sumKv) o.sumKv[c] = sKv;
-    if (o.sumKw) o.sumKw[c] = sKw;
-    if (o.sumKs) o.sumKs[c] = sKs;
-  }
+}
+
+void launch_occupied(const int32_t *start, const int32_t *cell_bed, const BedDev *beds, int n_gas, bool sums,
+                     const DepositOut &o, int32_t *flags, int32_t *offs, int32_t *scratch, int32_t *list,
+                     int32_t *count, hipStream_t s) {
+  k_occ_flags<<<(n_gas + 256) / 256, 256, 0, s>>>(start, cell_bed, beds, n_gas, sums ? 1 : 0, o, flags);
+  launch_scan(flags, offs, n_gas + 1, scratch, s);
+  k_occ_compact<<<(n_gas + 256) / 256, 256, 0, s>>>(flags, offs, n_gas, list, count);
 }
 
 template <typename T>
 void launch_deposit(const Dyn<T> &d, const Props<T> &p, const GasArgs &g, const int32_t *start,
-                    const int32_t *order, const int32_t *cell_bed, const BedDev *beds, const Phys &ph, int n_gas,
-                    bool sums, const DepositOut &o, hipStream_t s) {
-  const long threads = (long)n_gas * kGroup;
-  k_deposit<T><<<(int)((threads + 255) / 256), 256, 0, s>>>(d, p, g, start, order, cell_bed, beds, ph, n_gas,
-                                                            sums ? 1 : 0, o);
+                    const int32_t *order, const int32_t *cell_bed, const BedDev *beds, const Phys &ph,
+                    const int32_t *list, const int32_t *list_count, int max_list, bool sums, const DepositOut &o,
+                    hipStream_t s) {
+  const int groups_per_block = 256 / kGroup;
+  const int blocks = std::max(1, std::min((max_list + groups_per_block - 1) / groups_per_block, 8192));
+  k_deposit<T><<<blocks, 256, 0, s>>>(d, p, g, start, order, cell_bed, beds, ph, list, list_count, sums ? 1 : 0, o);
 }
 
 // ------------------------------------------------------------------ reaction
@@ -416,8 +471,8 @@ void launch_import(const dem_parcels &in, int n, const Dyn<T> &d, const Props<T>
 
 #define INST(T)                                                                                                    \
   template void launch_deposit<T>(const Dyn<T> &, const Props<T> &, const GasArgs &, const int32_t *,             \
-                                  const int32_t *, const int32_t *, const BedDev *, const Phys &, int, bool,      \
-                                  const DepositOut &, hipStream_t);                                                \
+                                  const int32_t *, const int32_t *, const BedDev *, const Phys &,                 \
+                                  const int32_t *, const int32_t *, int, bool, const DepositOut &, hipStream_t);  \
   template void launch_react<T>(const ReactArgs<T> &, hipStream_t);                                               \
   template void launch_init<T>(const dem_parcels &, int, const Phys &, int, const Dyn<T> &, const Props<T> &,     \
                                uint32_t *, hipStream_t);                                                           \

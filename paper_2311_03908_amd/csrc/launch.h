@@ -90,10 +90,14 @@ struct DepositOut {
   double *eps_ctx;  // context voidage (always written)
   double *eps, *np, *sumK, *sumKu, *sumKv, *sumKw, *sumKs;
 };
+void launch_occupied(const int32_t *start, const int32_t *cell_bed, const BedDev *beds, int n_gas, bool sums,
+                     const DepositOut &o, int32_t *flags, int32_t *offs, int32_t *scratch, int32_t *list,
+                     int32_t *count, hipStream_t s);
 template <typename T>
 void launch_deposit(const Dyn<T> &d, const Props<T> &p, const GasArgs &g, const int32_t *start,
-                    const int32_t *order, const int32_t *cell_bed, const BedDev *beds, const Phys &ph, int n_gas,
-                    bool sums, const DepositOut &o, hipStream_t s);
+                    const int32_t *order, const int32_t *cell_bed, const BedDev *beds, const Phys &ph,
+                    const int32_t *list, const int32_t *list_count, int max_list, bool sums, const DepositOut &o,
+                    hipStream_t s);
 
 template <typename T>
 struct ReactArgs {
