@@ -306,7 +306,7 @@ struct Ctx final : dem_ctx {
     const long scr = std::max(scan_scratch_ints((long)n_keys + 1), scan_scratch_ints((long)n_items + 1));
     TRY(dalloc(scan_scr, scr));
     TRY(dalloc(iflags, (size_t)n_items + 1)); TRY(dalloc(ioffs, (size_t)n_items + 1));
-    TRY(dalloc(ilist, n_items)); TRY(dalloc(icount, 1));
+    TRY(dalloc(ilist, n_items)); TRY(dalloc(icount, 2));
     TRY(dalloc(gtab, (size_t)n_gas * kGasRow));
     TRY(dalloc(eps, n_gas));
     TRY(dalloc(pm, (size_t)4 * n)); TRY(dalloc(pw, (size_t)2 * n));
@@ -380,6 +380,8 @@ struct Ctx final : dem_ctx {
     a.cap = P.max_nbr;
     a.skin = P.skin;
     a.status = status;
+    a.queue = icount + 1;
+    launch_fill_i32(a.queue, 0, 1, st);
     launch_build_nbr<T>(a, std::max(1, std::min(n_items, build_grid)), st);
     nbc ^= 1;
     HIPCHK(hipGetLastError());
@@ -808,7 +810,7 @@ struct Ctx final : dem_ctx {
     // neighbour build: persistent grid size
     best = 1e30f;
     int best_g = build_grid;
-    for (int gsz : {256, 512, 1024, 2048, 4096}) {
+    for (int gsz : {256, 512, 768, 1024, 2048}) {
       build_grid = gsz;
       float tot = 0.0f;
       for (int rep = 0; rep < 3; rep++) {

@@ -286,7 +286,15 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
   const long N = a.n;
   const float cut_scale = 1.0f + 1e-5f;
   const int tid = threadIdx.x;
-  for (int w = blockIdx.x; w < n_list; w += gridDim.x) {
+  __shared__ int w_next;
+  // blocks take work items from a queue (counter zeroed before the launch),
+  // so that items of uneven cost balance over the persistent grid
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) w_next = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int w = w_next;
+    if (w >= n_list) break;
     const Item it = a.items[a.list[w]];
     const BedDev &B = a.beds[it.bed];
     const int xc = min(kItemX, B.nd[0] - it.x0);

@@ -45,6 +45,7 @@ struct NbrBuild {
   const int32_t *start;
   const Item *items;
   const int32_t *list, *list_count;
+  int32_t *queue;  // work-item counter, zero at launch
   int n, cap;
   double skin;
   uint32_t *status;
