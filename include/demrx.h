@@ -76,6 +76,9 @@ typedef struct {
   double tau;         /* tortuosity of eq. e2-30 */
   double rho_true[4]; /* true densities of Fe2O3, Fe3O4, FeO, Fe (kg/m3) */
   int32_t kind;       /* 0: hematite ore (f_ov by eq. e2-18), 1: magnetite ore (eq. e2-19) */
+  double psi;         /* sphericity: 0 spheres (Gidaspow, eq. e3-5-1); in (0, 1]: Gidaspow-Ganser
+                         drag of non-spherical particles (eqs. e3-5-2..e3-5-5, Table 3: 0.85, 0.86),
+                         with the bed's equivalent-area diameter (2R, or sqrt(4 A / pi) for a box) */
 } dem_ore;
 
 typedef struct {

@@ -210,6 +210,46 @@ double ora_beta_over_epsp(double eps, double rho, double mu, double slip, double
   return 0.75 * cdre * mu * pow(eps, -2.65) / (dp * dp);
 }
 
+/* Gidaspow-Ganser drag of non-spherical particles (eqs. e3-5-2..e3-5-5),
+ * divided by eps_p like ora_beta_over_epsp, for sphericity psi in (0, 1] and
+ * equivalent-area bed diameter Dbed.  The Ergun branch divides the viscous
+ * term by psi^2 and the inertial one by psi (same eps reading as above); the
+ * Wen-Yu branch takes Ganser's single-particle C_D with
+ *   K1 = 1 / (1/3 + 2/3 psi^-1/2) - 2.25 dp / Dbed,
+ *   K2 = 10^(1.8148 (-log10 psi)^0.5743),
+ *   C_D Re = 24/K1 (1 + 0.1118 (Re K1 K2)^0.6567) + 0.4305 K2 Re / (1 + 3305 / (Re K1 K2)). */
+double ora_beta_ganser_over_epsp(double eps, double rho, double mu, double slip, double dp, double psi,
+                                 double Dbed, int printed) {
+  double ep = 1.0 - eps;
+  if (eps < 0.8) {
+    double inertial = printed ? 1.75 * eps * rho * slip / (dp * psi * ep) : 1.75 * rho * slip / (dp * psi);
+    return 150.0 * ep * mu / (eps * dp * dp * psi * psi) + inertial;
+  }
+  double Re = rho * eps * dp * slip / mu;
+  double K1 = 1.0 / (1.0 / 3.0 + 2.0 / 3.0 / sqrt(psi)) - 2.25 * dp / Dbed;
+  double K2 = pow(10.0, 1.8148 * pow(-log10(psi), 0.5743));
+  double x = Re * K1 * K2;
+  double cdre = 24.0 / K1 * (1.0 + 0.1118 * pow(x, 0.6567)) + (x > 0.0 ? 0.4305 * K2 * Re / (1.0 + 3305.0 / x) : 0.0);
+  return 0.75 * cdre * mu * pow(eps, -2.65) / (dp * dp);
+}
+
+/* reading: the "equivalent-area bed diameter" of eq. e3-5-4 is that of the
+ * bed's horizontal cross-section: 2R for a cylinder, sqrt(4 A / pi) for a box */
+static double bed_diameter(const ora_bed *b) {
+  if (b->wall_kind == 1) return 2.0 * b->R;
+  return sqrt(4.0 * (b->hi[0] - b->lo[0]) * (b->hi[1] - b->lo[1]) / PI);
+}
+
+/* drag coefficient of parcel i (spheres: eq. e3-5-1; psi in (0, 1]: eq. e3-5-2) */
+static double beta_of(const ora_sys *s, int i, double eps, double rho, double mu, double slip) {
+  const ora_ore *o = &s->ores[s->ore[i]];
+  double dp = s->d[i] / s->k[i]; /* reading: drag uses the real-particle diameter */
+  if (o->psi > 0.0)
+    return ora_beta_ganser_over_epsp(eps, rho, mu, slip, dp, o->psi, bed_diameter(&s->beds[s->bed[i]]),
+                                     s->P.ergun_printed);
+  return ora_beta_over_epsp(eps, rho, mu, slip, dp, s->P.ergun_printed);
+}
+
 /* eq. e3-45; reading: a non-positive radicand means a perfectly inelastic parcel */
 double ora_e_cgp(double e_p, double k) {
   double a = 1.0 + k * (e_p * e_p - 1.0);
@@ -517,8 +557,7 @@ static void gas_force(const ora_sys *s, const ora_gas *g, int i, double F[3]) {
   double rho, mu;
   ora_gas_props(g->T[c], g->p[c], g->xH2[c], g->xH2O[c], g->xN2[c], B->mu_override, &rho, &mu);
   double sl[3] = {g->ug[c] - s->vel[3 * i], g->vg[c] - s->vel[3 * i + 1], g->wg[c] - s->vel[3 * i + 2]};
-  double dp = s->d[i] / s->k[i]; /* reading: drag uses the real-particle diameter */
-  double be = ora_beta_over_epsp(s->eps[c], rho, mu, norm3(sl), dp, s->P.ergun_printed);
+  double be = beta_of(s, i, s->eps[c], rho, mu, norm3(sl));
   for (int a = 0; a < 3; a++) F[a] += be * V * sl[a];
 }
 
@@ -678,7 +717,7 @@ static void deposit(ora_sys *s, const ora_gas *g, double *np_, double *sumK, dou
       ora_gas_props(g->T[c], g->p[c], g->xH2[c], g->xH2O[c], g->xN2[c], B->mu_override, &rho, &mu);
       double sl[3] = {g->ug[c] - s->vel[3 * i], g->vg[c] - s->vel[3 * i + 1], g->wg[c] - s->vel[3 * i + 2]};
       double slip = norm3(sl);
-      double K = ora_beta_over_epsp(s->eps[c], rho, mu, slip, s->d[i] / s->k[i], s->P.ergun_printed) * volume(s, i);
+      double K = beta_of(s, i, s->eps[c], rho, mu, slip) * volume(s, i);
       if (sumK) sumK[c] += K;
       if (sumKu) sumKu[c] += K * s->vel[3 * i];
       if (sumKv) sumKv[c] += K * s->vel[3 * i + 1];

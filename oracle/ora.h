@@ -41,6 +41,7 @@ typedef struct {
   double tau;             /* tortuosity */
   double rho_true[4];     /* true densities of Fe2O3, Fe3O4, FeO, Fe */
   int kind;               /* 0 hematite ore (eq. e2-18), 1 magnetite ore (eq. e2-19) */
+  double psi;             /* sphericity: 0 spheres (eq. e3-5-1), (0, 1] Gidaspow-Ganser (eq. e3-5-2) */
 } ora_ore;
 
 typedef struct {
@@ -106,6 +107,8 @@ double ora_film(double T, double p, double xh2, double xh2o, double xn2, double 
                 double eps, double slip, double dp);
 double ora_keq(int i, double T);
 double ora_beta_over_epsp(double eps, double rho, double mu, double slip, double dp, int printed);
+double ora_beta_ganser_over_epsp(double eps, double rho, double mu, double slip, double dp, double psi,
+                                 double Dbed, int printed);
 /* resistance ladder: active[3] (hm, mw, wFe), A[3], B[3] = (B_m, B_w, B_Fe), F,
  * x, xeq[3] -> rates r[3] (unclamped) and the network's Q = 1/R, S = Phi/R */
 void ora_ladder(const int active[3], const double A[3], const double B[3], double F, double x,

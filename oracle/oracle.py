@@ -36,7 +36,7 @@ class OraBed(C.Structure):
 
 class OraOre(C.Structure):
     _fields_ = [("xi0", C.c_double), ("d_pore_cm", C.c_double), ("tau", C.c_double),
-                ("rho_true", C.c_double * 4), ("kind", C.c_int)]
+                ("rho_true", C.c_double * 4), ("kind", C.c_int), ("psi", C.c_double)]
 
 
 class OraParams(C.Structure):
@@ -97,6 +97,8 @@ def lib():
         L.ora_film.argtypes = [C.c_double] * 9
         L.ora_beta_over_epsp.restype = C.c_double
         L.ora_beta_over_epsp.argtypes = [C.c_double] * 5 + [C.c_int]
+        L.ora_beta_ganser_over_epsp.restype = C.c_double
+        L.ora_beta_ganser_over_epsp.argtypes = [C.c_double] * 7 + [C.c_int]
         L.ora_ladder.argtypes = [_ip, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp, _dp]
         L.ora_react_point.restype = C.c_int
         L.ora_react_point.argtypes = [_dp, _dp]
@@ -111,6 +113,7 @@ def _p(a, ct=C.c_double):
 def ore_struct(o) -> OraOre:
     s = OraOre()
     s.xi0, s.d_pore_cm, s.tau, s.kind = o.xi0, o.d_pore_cm, o.tau, o.kind
+    s.psi = getattr(o, "psi", 0.0)
     for i in range(4):
         s.rho_true[i] = o.rho_true[i]
     return s
@@ -268,6 +271,10 @@ def film(T, p, xh2, xh2o, xn2, mu_override, eps, slip, dp):
 
 def beta_over_epsp(eps, rho, mu, slip, dp, printed=0):
     return lib().ora_beta_over_epsp(eps, rho, mu, slip, dp, int(printed))
+
+
+def beta_ganser_over_epsp(eps, rho, mu, slip, dp, psi, Dbed, printed=False):
+    return lib().ora_beta_ganser_over_epsp(eps, rho, mu, slip, dp, psi, Dbed, int(printed))
 
 
 def ladder(active, A, B, F, x, xeq):

@@ -45,6 +45,7 @@ class Bed:
         for o, od in enumerate(w.ores):
             s = ores[o]
             s.xi0, s.d_pore_cm, s.tau, s.kind = od.xi0, od.d_pore_cm, od.tau, od.kind
+            s.psi = getattr(od, "psi", 0.0)
             for i in range(4):
                 s.rho_true[i] = od.rho_true[i]
         P = capi.DemParams()

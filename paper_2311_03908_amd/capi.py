@@ -27,7 +27,7 @@ class DemBed(C.Structure):
 
 class DemOre(C.Structure):
     _fields_ = [("xi0", C.c_double), ("d_pore_cm", C.c_double), ("tau", C.c_double),
-                ("rho_true", C.c_double * 4), ("kind", C.c_int32)]
+                ("rho_true", C.c_double * 4), ("kind", C.c_int32), ("psi", C.c_double)]
 
 
 class DemParams(C.Structure):

@@ -69,6 +69,9 @@ OreDev make_ore(const dem_ore &o) {
   d.d_pore_cm = o.d_pore_cm;
   d.tau = o.tau;
   d.kind = o.kind;
+  d.psi = o.psi;
+  d.k1_shape = o.psi > 0.0 ? 1.0 / (1.0 / 3.0 + 2.0 / 3.0 / std::sqrt(o.psi)) : 0.0;
+  d.k2 = o.psi > 0.0 ? std::pow(10.0, 1.8148 * std::pow(-std::log10(o.psi), 0.5743)) : 0.0;
   return d;
 }
 
@@ -209,6 +212,8 @@ struct Ctx final : dem_ctx {
     for (int a = 0; a < 3; a++) ph.g[a] = p->g[a];
     ph.ergun_printed = p->ergun_printed; ph.drag_on = p->drag_on;
     ph.n_beds = p->n_beds; ph.n_ores = p->n_ores; ph.max_nbr = p->max_nbr;
+    ph.ganser = 0;
+    for (int o = 0; o < p->n_ores; o++) ph.ganser |= p->ores[o].psi > 0.0;
     // beds
     long goff = 0, doff = 0, items_total = 0;
     for (int b = 0; b < p->n_beds; b++) {
@@ -219,6 +224,8 @@ struct Ctx final : dem_ctx {
         d.n[a] = B.n[a]; d.nd[a] = B.n[a] * B.refine;
       }
       d.R = B.R;
+      d.dbed = B.wall_kind == DEM_WALL_CYL ? 2.0 * B.R
+                                           : std::sqrt(4.0 * (B.hi[0] - B.lo[0]) * (B.hi[1] - B.lo[1]) / M_PI);
       d.cx = 0.5 * (B.lo[0] + B.hi[0]);
       d.cy = 0.5 * (B.lo[1] + B.hi[1]);
       d.h = B.h;
@@ -416,8 +423,8 @@ struct Ctx final : dem_ctx {
   // empty cells directly, occupied cells through their compacted list
   int deposit(const GasArgs &g, bool sums, const DepositOut &o) {
     launch_occupied(start_d, cell_bed, beds, n_gas, sums, o, occ_flags, occ_offs, scan_scr, occ_list, occ_count, st);
-    launch_deposit<T>(dyn[cur], pr[pc], g, start_d, order_d, cell_bed, beds, ph, occ_list, occ_count, n_gas, sums, o,
-                      st);
+    launch_deposit<T>(dyn[cur], pr[pc], g, start_d, order_d, cell_bed, beds, ores, ph, occ_list, occ_count, n_gas,
+                      sums, o, st);
     HIPCHK(hipGetLastError());
     return DEMRX_OK;
   }
@@ -436,6 +443,7 @@ struct Ctx final : dem_ctx {
     a.nb = nb[nbc];
     a.gtab = gtab;
     a.beds = beds;
+    a.ores = ores;
     a.ph = ph;
     a.status = status;
     a.xref = xref;

@@ -28,6 +28,7 @@ struct BedDev {
   double theta[6];
   double mu_override;
   double rmax;           // largest parcel radius in the bed
+  double dbed;           // equivalent-area diameter of the horizontal cross-section
   int tx, ty, ntx;       // key tiles: tx x ty DEM cells in x, y; tiles per x row
 };
 
@@ -48,6 +49,9 @@ __host__ __device__ __forceinline__ int dem_key(const BedDev &b, int x, int y, i
 struct OreDev {
   double xi_layer[3];
   double d_pore_cm, tau;
+  double psi;       // sphericity (0: spheres)
+  double k1_shape;  // Ganser's Stokes shape factor before the wall correction
+  double k2;        // Ganser's Newton shape factor
   int kind;
 };
 
@@ -55,6 +59,7 @@ struct Phys {
   double kn, e_p, mu_s, mu_r, kt, gt_ratio, eps_min, skin, dt;
   double g[3];
   int ergun_printed, drag_on, n_beds, n_ores, max_nbr;
+  int ganser;  // some ore has a sphericity in (0, 1]
 };
 
 // Parcel records, double-buffered (the step reads one buffer and writes the
@@ -229,6 +234,39 @@ __device__ __forceinline__ T beta_over_epsp(T eps, T rho, T mu, T slip, T dp, in
   const T re = rho * eps * dp * slip / mu;
   const T cdre = re < T(1000) ? T(24) * (T(1) + T(0.15) * tpow<T>(re, T(0.687))) : T(0.44) * re;
   return T(0.75) * cdre * mu * tpow<T>(eps, T(-2.65)) / (dp * dp);
+}
+
+// Gidaspow-Ganser drag of particles of sphericity psi (eqs. e3-5-2..e3-5-5),
+// divided by eps_p like beta_over_epsp: the dense branch divides the viscous
+// term by psi^2 and the inertial one by psi; the dilute branch takes Ganser's
+// single-particle C_D with K1 = 1/(1/3 + 2/3 psi^-1/2) - 2.25 dp / Dbed and
+// K2 = 10^(1.8148 (-log10 psi)^0.5743) (K1, K2 passed in, per parcel).
+template <typename T>
+__device__ __forceinline__ T beta_ganser_over_epsp(T eps, T rho, T mu, T slip, T dp, T psi, T K1, T K2,
+                                                   int printed) {
+  const T ep = T(1) - eps;
+  if (eps < T(0.8)) {
+    const T inertial =
+        printed ? T(1.75) * eps * rho * slip / (dp * psi * ep) : T(1.75) * rho * slip / (dp * psi);
+    return T(150) * ep * mu / (eps * dp * dp * psi * psi) + inertial;
+  }
+  const T re = rho * eps * dp * slip / mu;
+  const T x = re * K1 * K2;
+  const T cdre = T(24) / K1 * (T(1) + T(0.1118) * tpow<T>(x, T(0.6567))) +
+                 (x > T(0) ? T(0.4305) * K2 * re / (T(1) + T(3305) / x) : T(0));
+  return T(0.75) * cdre * mu * tpow<T>(eps, T(-2.65)) / (dp * dp);
+}
+
+// drag coefficient over eps_p of one parcel of ore O in bed B: Gidaspow for
+// spheres, Gidaspow-Ganser for a sphericity in (0, 1]
+template <typename T>
+__device__ __forceinline__ T drag_beta(const Phys &ph, const OreDev &O, const BedDev &B, T eps, T rho, T mu, T slip,
+                                       T dp) {
+  if (ph.ganser && O.psi > 0.0) {
+    const T K1 = T(O.k1_shape) - T(2.25) * dp / T(B.dbed);
+    return beta_ganser_over_epsp<T>(eps, rho, mu, slip, dp, T(O.psi), K1, T(O.k2), ph.ergun_printed);
+  }
+  return beta_over_epsp<T>(eps, rho, mu, slip, dp, ph.ergun_printed);
 }
 
 // Per-gas-cell drag table row, three quads: (ug vg wg eps) (dpdx dpdy dpdz rho) (mu - - -)

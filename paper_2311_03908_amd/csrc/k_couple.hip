@@ -80,7 +80,7 @@ __global__ void k_occ_compact(const int32_t *flags, const int32_t *offs, int n_g
 template <typename T>
 __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g, const int32_t *start,
                                                  const int32_t *order, const int32_t *cell_bed, const BedDev *beds,
-                                                 Phys ph, const int32_t *list, const int32_t *list_count, int sums,
+                                                 const OreDev *ores, Phys ph, const int32_t *list, const int32_t *list_count, int sums,
                                                  DepositOut o) {
   const int sl = threadIdx.x % kGroup;
   const int n_list = *list_count;
@@ -125,7 +125,10 @@ __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g
         const double slip = sqrt(sx * sx + sy * sy + sz * sz);
         const double dd = 2.0 * (double)d.pos[j].r;
         const double V = kPi / 6.0 * dd * dd * dd;
-        const double K = beta_over_epsp<double>(eps, rho, mu, slip, dd / (double)p.kcg[j], ph.ergun_printed) * V;
+        const double dpj = dd / (double)p.kcg[j];  // real-particle diameter
+        const double K = (ph.ganser ? drag_beta<double>(ph, ores[ore_of(p.tag[j])], B, eps, rho, mu, slip, dpj)
+                                    : beta_over_epsp<double>(eps, rho, mu, slip, dpj, ph.ergun_printed)) *
+                         V;
         sK += K;
         sKu += K * vx;
         sKv += K * vy;
@@ -158,12 +161,13 @@ void launch_occupied(const int32_t *start, const int32_t *cell_bed, const BedDev
 
 template <typename T>
 void launch_deposit(const Dyn<T> &d, const Props<T> &p, const GasArgs &g, const int32_t *start,
-                    const int32_t *order, const int32_t *cell_bed, const BedDev *beds, const Phys &ph,
-                    const int32_t *list, const int32_t *list_count, int max_list, bool sums, const DepositOut &o,
-                    hipStream_t s) {
+                    const int32_t *order, const int32_t *cell_bed, const BedDev *beds, const OreDev *ores,
+                    const Phys &ph, const int32_t *list, const int32_t *list_count, int max_list, bool sums,
+                    const DepositOut &o, hipStream_t s) {
   const int groups_per_block = 256 / kGroup;
   const int blocks = std::max(1, std::min((max_list + groups_per_block - 1) / groups_per_block, 8192));
-  k_deposit<T><<<blocks, 256, 0, s>>>(d, p, g, start, order, cell_bed, beds, ph, list, list_count, sums ? 1 : 0, o);
+  k_deposit<T><<<blocks, 256, 0, s>>>(d, p, g, start, order, cell_bed, beds, ores, ph, list, list_count, sums ? 1 : 0,
+                                      o);
 }
 
 // ------------------------------------------------------------------ reaction
@@ -471,7 +475,7 @@ void launch_import(const dem_parcels &in, int n, const Dyn<T> &d, const Props<T>
 
 #define INST(T)                                                                                                    \
   template void launch_deposit<T>(const Dyn<T> &, const Props<T> &, const GasArgs &, const int32_t *,             \
-                                  const int32_t *, const int32_t *, const BedDev *, const Phys &,                 \
+                                  const int32_t *, const int32_t *, const BedDev *, const OreDev *, const Phys &, \
                                   const int32_t *, const int32_t *, int, bool, const DepositOut &, hipStream_t);  \
   template void launch_react<T>(const ReactArgs<T> &, hipStream_t);                                               \
   template void launch_init<T>(const dem_parcels &, int, const Phys &, int, const Dyn<T> &, const Props<T> &,     \

@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 1) k_step(StepArgs<T
         const T V = T(kPi / 6.0) * (T(2) * ri) * (T(2) * ri) * (T(2) * ri);
         const T s[3] = {g0.x - Vi.v[0], g0.y - Vi.v[1], g0.z - Vi.v[2]};
         const T slip = tsqrt<T>(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
-        const T be = beta_over_epsp<T>(g0.w, g1.w, mu, slip, dpr, a.ph.ergun_printed);
+        const T be = drag_beta<T>(a.ph, a.ores[ore_of(tag)], B, g0.w, g1.w, mu, slip, dpr);
         F[0] += be * V * s[0] - V * g1.x;
         F[1] += be * V * s[1] - V * g1.y;
         F[2] += be * V * s[2] - V * g1.z;

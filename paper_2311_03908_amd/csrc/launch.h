@@ -65,6 +65,7 @@ struct StepArgs {
   Nbr<T> nb;
   const T *gtab;
   const BedDev *beds;
+  const OreDev *ores;
   Phys ph;
   uint32_t *status;
   const float4 *xref;            // positions at the last rebuild (FP32)
@@ -96,8 +97,8 @@ void launch_occupied(const int32_t *start, const int32_t *cell_bed, const BedDev
                      int32_t *count, hipStream_t s);
 template <typename T>
 void launch_deposit(const Dyn<T> &d, const Props<T> &p, const GasArgs &g, const int32_t *start,
-                    const int32_t *order, const int32_t *cell_bed, const BedDev *beds, const Phys &ph,
-                    const int32_t *list, const int32_t *list_count, int max_list, bool sums, const DepositOut &o,
+                    const int32_t *order, const int32_t *cell_bed, const BedDev *beds, const OreDev *ores,
+                    const Phys &ph, const int32_t *list, const int32_t *list_count, int max_list, bool sums, const DepositOut &o,
                     hipStream_t s);
 
 template <typename T>

@@ -92,6 +92,7 @@ class Ore:
     tau: float = 2.0           # tortuosity
     kind: int = ORE_HEMATITE
     rho_true: tuple = RHO_TRUE
+    psi: float = 0.0           # sphericity: 0 spheres, (0, 1] Gidaspow-Ganser drag (Table 3: 0.85 / 0.86)
 
 
 @dataclasses.dataclass

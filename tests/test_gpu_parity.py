@@ -403,3 +403,37 @@ def test_headline_bed_full_size_one_step():
     rg, ro = bed.react(1e-4), ora.react(1e-4)
     assert np.max(np.abs(_np(rg["fov"]) - ro["fov"])) <= 1e-4
     assert abs(rg["bed_fov"][0] - ro["bed_fov"][0]) <= 1e-12
+
+
+def _nonspherical(w, psi=0.86):
+    return W.dataclasses.replace(w, ores=[W.dataclasses.replace(o, psi=psi) for o in w.ores])
+
+
+@pytest.mark.parametrize("case", ["cfg1_fp64", "cfg2_mixed"])
+def test_ganser_drag_forces_and_sums(case):
+    """Gidaspow-Ganser drag (eqs. e3-5-2..e3-5-5) of ore of sphericity 0.86:
+    per-parcel forces to the force gate (box bed and cylinder bed, both drag
+    branches) and the per-cell drag sums of the deposit within 1e-12."""
+    w = _nonspherical(GENTLE[case]())
+    _say(f"[ganser] {case} n={w.n}")
+    ora = O.Oracle(w)
+    co = ora.couple()
+    eps = co["eps"]
+    _say(f"  voidage range {eps.min():.3f}..{eps.max():.3f}")
+    assert eps.min() < 0.8 < eps.max()  # both branches in play
+    bed = Bed(w)
+    cg = bed.couple()
+    for k in ("eps", "sumK", "sumKu", "sumKv", "sumKw", "sumKs"):
+        a, b = _np(cg[k]), co[k]
+        assert np.max(np.abs(a - b)) <= 1e-12 * max(np.max(np.abs(b)), 1e-300), k
+    # the shape changes the sums: not the spherical law
+    sph = O.Oracle(GENTLE[case]()).couple()["sumK"]
+    assert np.max(np.abs(co["sumK"] - sph)) > 1e-3 * np.max(np.abs(sph))
+    mass = ora.state()["mass"]
+    Fo, _ = ora.forces()
+    Fg, _ = bed.forces()
+    tol = 1e-5 if w.precision == "mixed" else 1e-9
+    ef = _force_err(_np(Fg), Fo, mass)
+    _say(f"  force err {ef:.2e}")
+    assert ef <= tol
+    bed.close()

@@ -182,3 +182,74 @@ def test_force_output_matches_step_velocity_change():
     st1 = ora.state()
     dv = np.stack([st1[k] - st0[k] for k in ("vx", "vy", "vz")], 1)
     assert np.allclose(dv * st0["mass"][:, None] / w.params["dt"], F, rtol=1e-9, atol=1e-18)
+
+
+# ------------------------------------------------------------- Gidaspow-Ganser
+def _cd_from_beta(be, eps, rho, mu, slip, dp):
+    """Single-particle C_D recovered from the Wen-Yu branch:
+    beta/eps_p = 3/4 C_D Re mu eps^-2.65 / dp^2 with Re = rho eps dp slip / mu."""
+    Re = rho * eps * dp * slip / mu
+    return be * dp * dp / (0.75 * Re * mu * eps ** -2.65), Re
+
+
+def test_ganser_stokes_limit_is_stokes_law():
+    """eq. e3-5-3 at Re -> 0 gives C_D Re -> 24 / K1; for spheres in an unbounded
+    bed (K1 = 1) that is Stokes drag, the same limit as the spherical branch."""
+    eps, rho, mu, dp = 0.9, 0.03, 4e-5, 1e-4
+    for slip in (1e-9, 1e-8):
+        g = O.beta_ganser_over_epsp(eps, rho, mu, slip, dp, 1.0, 1e12)
+        s = O.beta_over_epsp(eps, rho, mu, slip, dp)
+        assert g == pytest.approx(s, rel=1e-5)
+    # a finite bed raises the drag through K1 = 1 - 2.25 dp / D
+    g_wall = O.beta_ganser_over_epsp(eps, rho, mu, 1e-9, dp, 1.0, 100 * dp)
+    g_free = O.beta_ganser_over_epsp(eps, rho, mu, 1e-9, dp, 1.0, 1e12)
+    assert g_wall / g_free == pytest.approx(1.0 / (1.0 - 2.25 / 100.0), rel=1e-6)
+
+
+def test_ganser_newton_limit_for_spheres():
+    """At large Re Ganser's sphere C_D tends to 0.4305 K2 = 0.4305, the Newton
+    regime value of a sphere (about 0.43-0.44)."""
+    eps, rho, mu, dp = 0.95, 1.0, 1e-5, 1e-3
+    be = O.beta_ganser_over_epsp(eps, rho, mu, 1e9, dp, 1.0, 1e12)
+    cd, Re = _cd_from_beta(be, eps, rho, mu, 1e9, dp)
+    assert Re > 1e10
+    assert cd == pytest.approx(0.4305, rel=2e-3)
+    assert 0.42 < cd < 0.45
+
+
+def test_ganser_less_spherical_drags_more_at_high_re():
+    eps, rho, mu, dp, slip = 0.95, 1.0, 1e-5, 1e-3, 10.0
+    cds = [_cd_from_beta(O.beta_ganser_over_epsp(eps, rho, mu, slip, dp, psi, 1e12), eps, rho, mu, slip, dp)[0]
+           for psi in (1.0, 0.9, 0.8, 0.6)]
+    assert all(a < b for a, b in zip(cds, cds[1:]))
+
+
+def test_ganser_ergun_branch_sphericity_scaling():
+    """Dense branch of eq. e3-5-2: the viscous term scales as 1/psi^2 (slip -> 0)
+    and the inertial term as 1/psi (slip -> infinity)."""
+    eps, rho, mu, dp, psi = 0.5, 0.03, 4e-5, 1e-4, 0.86
+    lo = O.beta_ganser_over_epsp(eps, rho, mu, 1e-12, dp, psi, 1e12) / O.beta_over_epsp(eps, rho, mu, 1e-12, dp)
+    hi = O.beta_ganser_over_epsp(eps, rho, mu, 1e9, dp, psi, 1e12) / O.beta_over_epsp(eps, rho, mu, 1e9, dp)
+    assert lo == pytest.approx(1.0 / psi ** 2, rel=1e-9)
+    assert hi == pytest.approx(1.0 / psi, rel=1e-6)
+
+
+@pytest.mark.parametrize("psi", [0.0, 0.86])
+def test_drag_on_lone_parcel_uses_real_diameter_and_bed_width(psi):
+    """One parcel at rest in slow uniform upflow (dilute cell, Re -> 0): the
+    force is the Stokes limit of eq. e3-5-1 (psi = 0) or of eq. e3-5-3 with
+    K1 = 1/(1/3 + 2/3 psi^-1/2) - 2.25 d_p / D, D the equivalent-area
+    diameter of the 20 mm x 20 mm box, on the real-particle diameter d/k."""
+    k, dp, u, mu, h = 2.0, 1e-4, 1e-7, 4e-5, 2e-3
+    ore = W.Ore(xi0=1.0 - 4500.0 / W.RHO_TRUE[0], d_pore_cm=3.3e-6, psi=psi)
+    w = box_workload([(0.011, 0.011, 0.011)], k * dp, k=k, ore=ore, u=(0.0, 0.0, u), mu_override=mu)
+    F, _ = O.Oracle(w, g=(0.0, 0.0, 0.0)).forces()
+    d = float(w.parcels["d"][0])
+    dpr = d / k
+    V = math.pi / 6 * d ** 3
+    eps = 1.0 - V / h ** 3
+    K1 = 1.0 / (1.0 / 3.0 + 2.0 / 3.0 / math.sqrt(psi)) - 2.25 * dpr / math.sqrt(4 * 0.02 * 0.02 / math.pi) \
+        if psi > 0 else 1.0
+    expect = 0.75 * 24.0 / K1 * mu * eps ** -2.65 / dpr ** 2 * V * u
+    assert F[0, 2] == pytest.approx(expect, rel=1e-5)
+    assert abs(F[0, 0]) < 1e-12 * expect and abs(F[0, 1]) < 1e-12 * expect
