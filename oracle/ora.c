@@ -47,6 +47,9 @@ struct ora_sys {
   double *wxi;          /* 6 walls x 3 per parcel */
   unsigned char *won;   /* 6 per parcel */
   double *eps;          /* gas voidage per cell from the last deposit */
+  double *Tp;           /* particle temperature (K) */
+  double *qrx;          /* k^3 (Q_r + Q_rm) of the last reaction update (W) */
+  double *mcp;          /* m C_p,p of the parcel at the last reaction update (J/K) */
 };
 
 /* ------------------------------------------------------------ vectors */
@@ -194,6 +197,109 @@ double ora_film(double T, double p, double xh2, double xh2o, double xn2, double 
 /* Table 2 equilibrium constants and eq. e2-1-3 */
 double ora_keq(int i, double T) { return exp(KEQ[i][0] / T + KEQ[i][1]); }
 
+/* ------------------------------------------------------------ thermochemistry */
+
+/* Table C1: a1..a6 of eqs. e3-22 / e3-23 per temperature range (K), molar
+ * form; species 0 H2, 1 H2O, 2 N2, 3 Fe2O3, 4 Fe3O4, 5 FeO, 6 Fe */
+typedef struct {
+  double lo, hi, a[6];
+} c1_range;
+static const int C1N[7] = {2, 2, 2, 2, 2, 2, 4};
+static const c1_range C1[7][4] = {
+    {{298, 1000, {2.3443, 7.98e-3, -1.95e-5, 2.02e-8, -7.38e-12, -9.179e2}},
+     {1000, 6000, {2.9328, 8.27e-4, -1.46e-7, 1.54e-11, -6.89e-16, -8.131e2}}},
+    {{373, 1000, {4.1986, -2.04e-3, 6.52e-6, -5.49e-9, 1.77e-12, -3.03e4}},
+     {1000, 6000, {2.677, 2.97e-3, -7.74e-7, 9.44e-11, -4.27e-15, -2.989e4}}},
+    {{298, 1000, {3.531, -1.24e-4, -5.03e-7, 2.44e-9, -1.41e-12, -1.047e3}},
+     {1000, 6000, {2.9526, 1.40e-3, -4.93e-7, 7.86e-11, -4.61e-15, -9.239e2}}},
+    {{298, 960, {0.1522, 6.71e-2, -1.13e-4, 9.93e-8, -3.28e-11, -1.013e5}},
+     {960, 1700, {353.05, -0.9728, 1.05e-3, -4.96e-7, 8.74e-11, -1.96e5}}},
+    {{298, 850, {4.8445, 4.39e-2, 5.25e-5, -2.21e-7, 1.75e-10, -1.38e5}},
+     {850, 1870, {88.431, -0.149, 1.26e-4, -4.7e-8, 6.79e-12, -1.621e5}}},
+    {{298, 1000, {5.3195, 2.21e-3, 1.07e-6, -2.79e-9, 1.33e-12, -3.441e4}},
+     {1000, 1650, {5.8316, 1.43e-3, -9.32e-8, -6.6e-12, -2.25e-14, -3.457e4}}},
+    {{298, 1000, {2.4134, -1.58e-3, 2.15e-5, -3.8e-8, 2.20e-11, -774.38}},
+     {1000, 1042, {4690.8, -9.91, 2.69e-3, 5.54e-6, -3.02e-9, -1.415e6}},
+     {1042, 1184, {659.68, -1.14, 4.96e-4, 0, 0, -2.52e5}},
+     {1184, 1665, {61.011, -0.161, 1.68e-4, -7.75e-8, 1.33e-11, -1.65e4}}}};
+
+/* eq. e3-23 times M: R (a1 + a2 T + a3 T^2 + a4 T^3 + a5 T^4), J/(mol K) */
+static double c1_cp(const double *a, double T) {
+  return RG * (a[0] + a[1] * T + a[2] * T * T + a[3] * T * T * T + a[4] * T * T * T * T);
+}
+/* eq. e3-22 times M: R (a1 T + a2 T^2/2 + a3 T^3/3 + a4 T^4/4 + a5 T^5/5 + a6), J/mol */
+static double c1_h(const double *a, double T) {
+  double T2 = T * T, T3 = T2 * T, T4 = T3 * T, T5 = T4 * T;
+  return RG * (a[0] * T + a[1] * T2 / 2.0 + a[2] * T3 / 3.0 + a[3] * T4 / 4.0 + a[4] * T5 / 5.0 + a[5]);
+}
+/* reading: Fe's 1000-1042 K coefficients give a negative heat capacity as
+ * printed; there C_p is linear between the neighbouring ranges' values at
+ * 1000 K and 1042 K */
+static double fe_gap_cp(double T) {
+  double c0 = c1_cp(C1[6][0].a, 1000.0), c1 = c1_cp(C1[6][2].a, 1042.0);
+  return c0 + (c1 - c0) * (T - 1000.0) / 42.0;
+}
+static double fe_gap_h(double t) { /* integral of fe_gap_cp from 1000 K to t */
+  double c0 = c1_cp(C1[6][0].a, 1000.0), c1 = c1_cp(C1[6][2].a, 1042.0);
+  return c0 * (t - 1000.0) + (c1 - c0) * (t - 1000.0) * (t - 1000.0) / (2.0 * 42.0);
+}
+
+/* molar heat capacity of species sp (eq. e3-23) in the range holding T (the
+ * nearest range outside the table) */
+double ora_cp_mol(int sp, double T) {
+  int r = 0;
+  while (r < C1N[sp] - 1 && T > C1[sp][r].hi) r++;
+  if (sp == 6 && r == 1) return fe_gap_cp(T);
+  return c1_cp(C1[sp][r].a, T);
+}
+
+/* molar enthalpy of species sp (eq. e3-22).  reading: the printed
+ * coefficients are rounded to about three figures, which leaves steps in H at
+ * the range bounds (9 kJ/mol for Fe2O3 at 960 K); H is the first range's
+ * eq. e3-22 (its a6 reproduces the formation enthalpy at 298.15 K) continued
+ * upward by integrating each later range's heat capacity, i.e. each later
+ * range's a6 is the one that makes H continuous at its lower bound */
+double ora_h_mol(int sp, double T) {
+  const c1_range *R = C1[sp];
+  int nr = C1N[sp];
+  double H = c1_h(R[0].a, (T <= R[0].hi || nr == 1) ? T : R[0].hi);
+  for (int r = 1; r < nr && T > R[r].lo; r++) {
+    double t1 = (T <= R[r].hi || r == nr - 1) ? T : R[r].hi;
+    if (sp == 6 && r == 1)
+      H += fe_gap_h(t1);
+    else
+      H += c1_h(R[r].a, t1) - c1_h(R[r].a, R[r].lo);
+  }
+  return H;
+}
+
+/* Table C3: thermal conductivity a1 + a2 T + ... + a5 T^4 (W/(m K)) of H2, H2O, N2 */
+static const double LAMC[3][5] = {{3.07e-3, 8.09e-4, -8.52e-7, 7.2e-10, -2.21e-13},
+                                  {6.84e-3, 6.25e-6, 1.31e-7, -5.99e-11, 1.12e-14},
+                                  {2.51e-3, 8.92e-5, -4.00e-8, 1.62e-11, -2.61e-15}};
+
+/* eqs. e3-58, e3-59: mass-weighted thermal conductivity of the gas */
+double ora_lambda_g(double T, double xh2, double xh2o, double xn2) {
+  double xs[3] = {xh2, xh2o, xn2}, Mg = 0.0, l = 0.0;
+  for (int j = 0; j < 3; j++) Mg += xs[j] * MG[j];
+  for (int j = 0; j < 3; j++) {
+    const double *a = LAMC[j];
+    l += xs[j] * MG[j] / Mg * (a[0] + a[1] * T + a[2] * T * T + a[3] * T * T * T + a[4] * T * T * T * T);
+  }
+  return l;
+}
+
+/* eqs. e3-23, e3-57: mass-weighted specific heat of the gas, J/(kg K) */
+double ora_cp_g(double T, double xh2, double xh2o, double xn2) {
+  double xs[3] = {xh2, xh2o, xn2}, Mg = 0.0, c = 0.0;
+  for (int j = 0; j < 3; j++) Mg += xs[j] * MG[j];
+  for (int j = 0; j < 3; j++) c += xs[j] * MG[j] / Mg * ora_cp_mol(j, T) / (MG[j] * 1e-3);
+  return c;
+}
+
+/* eq. e3-12: Gunn's correlation, the form of eq. e2-22 with Pr in place of Sc */
+double ora_nusselt(double eps, double Re, double Pr) { return ora_sherwood(eps, Re, Pr); }
+
 /* eq. e3-5-1 divided by eps_p = 1 - eps_g, so that F_d = (beta/eps_p) V (u_g - v)
  * (eq. e3-5) stays finite in a cell of unit voidage.  reading: Gidaspow's
  * inertial Ergun term carries eps_p (printed: eps_g, selectable); C_D is
@@ -289,6 +395,34 @@ static double parcel_mass(const ora_sys *s, int i) {
   return k * k * k * mp;
 }
 
+/* eq. e3-9 times the parcel mass: m C_p,p = k^3 sum_z n_z C_p,z(T_p) (J/K) */
+static double parcel_mcp(const ora_sys *s, int i) {
+  const double *n = &s->sp[4 * i];
+  double c = 0.0;
+  for (int z = 0; z < 4; z++) c += n[z] * ora_cp_mol(3 + z, s->Tp[i]);
+  double k = s->k[i];
+  return k * k * k * c;
+}
+
+/* eqs. e3-10, e3-11, e3-12, e3-13 and e3-41: k^3 h_p A_p of parcel i (W/K)
+ * from the gas of its cell, the voidage of the last deposit and its slip;
+ * Re_p as in eq. e2-23, on the real-particle diameter */
+static double parcel_hA(const ora_sys *s, const ora_gas *g, int i) {
+  int c = cell_of(s, i);
+  const ora_bed *B = &s->beds[s->bed[i]];
+  double T = g->T[c], rho, mu;
+  ora_gas_props(T, g->p[c], g->xH2[c], g->xH2O[c], g->xN2[c], B->mu_override, &rho, &mu);
+  double lam = ora_lambda_g(T, g->xH2[c], g->xH2O[c], g->xN2[c]);
+  double cp = ora_cp_g(T, g->xH2[c], g->xH2O[c], g->xN2[c]);
+  double sl[3] = {g->ug[c] - s->vel[3 * i], g->vg[c] - s->vel[3 * i + 1], g->wg[c] - s->vel[3 * i + 2]};
+  double slip = sqrt((sl[0] * sl[0] + sl[1] * sl[1]) + sl[2] * sl[2]);
+  double k = s->k[i], dp = s->d[i] / k;
+  double Re = rho * s->eps[c] * dp * slip / mu;
+  double Nu = ora_nusselt(s->eps[c], Re, cp * mu / lam);
+  double h = Nu * lam / dp;
+  return k * k * k * h * PI * dp * dp;
+}
+
 /* ------------------------------------------------------------ construction */
 static void deposit(ora_sys *s, const ora_gas *g, double *np_, double *sumK, double *sumKu,
                     double *sumKv, double *sumKw, double *sumKs);
@@ -326,6 +460,9 @@ ora_sys *ora_new(const ora_params *P, const ora_bed *beds, const ora_ore *ores, 
   s->wxi = (double *)calloc((size_t)18 * n, sizeof(double));
   s->won = (unsigned char *)calloc((size_t)6 * n, 1);
   s->eps = (double *)malloc(sizeof(double) * (nc > 0 ? nc : 1));
+  s->Tp = (double *)calloc(n > 0 ? n : 1, sizeof(double));
+  s->qrx = (double *)calloc(n > 0 ? n : 1, sizeof(double));
+  s->mcp = (double *)calloc(n > 0 ? n : 1, sizeof(double));
   for (int i = 0; i < n; i++) {
     s->pos[3 * i] = x[i];
     s->pos[3 * i + 1] = y[i];
@@ -354,7 +491,8 @@ void ora_free(ora_sys *s) {
   if (!s) return;
   free(s->beds); free(s->ores); free(s->pos); free(s->vel); free(s->omg); free(s->d);
   free(s->k); free(s->mass); free(s->sp); free(s->ore); free(s->bed); free(s->hcnt);
-  free(s->hist); free(s->wxi); free(s->won); free(s->eps); free(s);
+  free(s->hist); free(s->wxi); free(s->won); free(s->eps); free(s->Tp); free(s->qrx); free(s->mcp);
+  free(s);
 }
 
 int ora_n_cells(const ora_sys *s) { return s->n_cells; }
@@ -667,6 +805,16 @@ void ora_step(ora_sys *s, int nsteps, const ora_gas *g) {
   for (int st = 0; st < nsteps; st++) {
     compute_forces(s, g, F, T, 1);
     double dt = s->P.dt;
+    /* eq. e3-8 with conduction and radiation left out: m C_p dT_p/dt =
+     * k^3 (Q_conv + Q_r + Q_rm) (eqs. e3-41, e3-49, e3-50), explicit in the
+     * step-start state; reading: m C_p,p and Q_r + Q_rm are those of the last
+     * reaction update (masses change only at coupling, Section 4) */
+    if (s->P.energy_on)
+      for (int i = 0; i < n; i++) {
+        int c = cell_of(s, i);
+        double q = parcel_hA(s, g, i) * (g->T[c] - s->Tp[i]) + s->qrx[i];
+        s->Tp[i] += dt * q / s->mcp[i];
+      }
     for (int i = 0; i < n; i++) {
       double m = s->mass[i], I = inertia(s, i);
       for (int c = 0; c < 3; c++) {
@@ -874,19 +1022,23 @@ static void make_env(const ora_sys *s, const ora_gas *g, int i, double dt, const
   const ora_bed *B = &s->beds[s->bed[i]];
   const ora_ore *o = &s->ores[s->ore[i]];
   double T = g->T[c], p = g->p[c], xh2 = g->xH2[c], xh2o = g->xH2O[c], xn2 = g->xN2[c];
+  /* reading: with the energy equation, equilibria, rate constants and pore
+   * diffusion take the particle temperature; the film, the gas density and
+   * the molar concentration stay at the gas temperature */
+  double Tk = s->P.energy_on ? s->Tp[i] : T;
   /* Section 2.1: H2 fraction of the N2-free gas */
   if (xh2o <= 0.0) e->x = xh2 > 0.0 ? 1.0 : 0.0;
   else e->x = xh2 / (xh2 + xh2o);
   for (int q = 0; q < 3; q++) {
-    double K = ora_keq(q, T);
+    double K = ora_keq(q, Tk);
     e->xeq[q] = 1.0 / (K + 1.0);   /* eq. e2-1-3 */
     e->kappa[q] = K / (1.0 + K);   /* eq. e2-12 factor */
     const double *th = theta ? theta : B->theta;
-    double kr = exp(th[2 * q] - th[2 * q + 1] / (RG * T)); /* eq. e2-13 */
+    double kr = exp(th[2 * q] - th[2 * q + 1] / (RG * Tk)); /* eq. e2-13 */
     e->kr[q] = D(kr);
     if (tangents) {
       e->kr[q].d[2 * q] = kr;
-      e->kr[q].d[2 * q + 1] = -kr / (RG * T);
+      e->kr[q].d[2 * q + 1] = -kr / (RG * Tk);
     }
   }
   e->c_mol = p / (RG * T);
@@ -895,7 +1047,7 @@ static void make_env(const ora_sys *s, const ora_gas *g, int i, double dt, const
   e->rp = 0.5 * dp;
   double xi[4];
   ora_layer_porosity(o, xi);
-  double Dp = ora_pore_diff(T, p, xh2, xh2o, xn2, o->d_pore_cm);
+  double Dp = ora_pore_diff(Tk, p, xh2, xh2o, xn2, o->d_pore_cm);
   for (int q = 0; q < 3; q++) e->Deff[q] = Dp * xi[q + 1] / o->tau; /* eq. e2-30 */
   double sl[3] = {g->ug[c] - s->vel[3 * i], g->vg[c] - s->vel[3 * i + 1], g->wg[c] - s->vel[3 * i + 2]};
   e->F = ora_film(T, p, xh2, xh2o, xn2, B->mu_override, s->eps[c], norm3(sl), dp);
@@ -903,10 +1055,11 @@ static void make_env(const ora_sys *s, const ora_gas *g, int i, double dt, const
 }
 
 long ora_react(ora_sys *s, double dt, const ora_gas *g, int update_mass, double *mdotH2,
-               double *mdotH2O, double *sumEQ, double *sumES, double *fov, double *bed_fov) {
+               double *mdotH2O, double *sumEQ, double *sumES, double *fov, double *bed_fov,
+               double *hA, double *hAT, double *Qrm, double *Hr) {
   int nc = s->n_cells;
-  double *outs[4] = {mdotH2, mdotH2O, sumEQ, sumES};
-  for (int j = 0; j < 4; j++) if (outs[j]) memset(outs[j], 0, sizeof(double) * nc);
+  double *outs[8] = {mdotH2, mdotH2O, sumEQ, sumES, hA, hAT, Qrm, Hr};
+  for (int j = 0; j < 8; j++) if (outs[j]) memset(outs[j], 0, sizeof(double) * nc);
   double *bw = (double *)calloc(s->P.n_beds, sizeof(double));
   double *bf = (double *)calloc(s->P.n_beds, sizeof(double));
   long clamps = 0;
@@ -917,9 +1070,30 @@ long ora_react(ora_sys *s, double dt, const ora_gas *g, int update_mass, double 
     dual sp[4], Q, S, xi[3];
     for (int q = 0; q < 4; q++) sp[q] = D(s->sp[4 * i + q]);
     clamps += react_core(&e, sp, &Q, &S, xi);
-    for (int q = 0; q < 4; q++) s->sp[4 * i + q] = sp[q].v;
+    double dn[4];
+    for (int q = 0; q < 4; q++) {
+      dn[q] = sp[q].v - s->sp[4 * i + q];
+      s->sp[4 * i + q] = sp[q].v;
+    }
     double k3 = s->k[i] * s->k[i] * s->k[i];
     double xs = xi[0].v + xi[1].v + xi[2].v;
+    if (s->P.energy_on) {
+      /* eqs. e3-18, e3-19 (solids) and e3-20, e3-21 (gases) at T_p, with the
+       * k^3 of eqs. e3-49, e3-50; the moles changed over dt per real
+       * particle; reading: the gas species of a reaction are the H2 it takes
+       * from and the H2O it gives to the gas */
+      double Tp = s->Tp[i], Qr = 0.0;
+      for (int z = 0; z < 4; z++) Qr -= ora_h_mol(3 + z, Tp) * dn[z] / dt;
+      double Qm = -(ora_h_mol(1, Tp) - ora_h_mol(0, Tp)) * xs / dt;
+      s->qrx[i] = k3 * (Qr + Qm);
+      s->mcp[i] = parcel_mcp(s, i);
+      /* eqs. e4-4, e4-5 (times V_cell), e3-38 and e3-39 (times -V_cell) */
+      double ha = parcel_hA(s, g, i);
+      if (hA) hA[c] += ha;
+      if (hAT) hAT[c] += ha * Tp;
+      if (Qrm) Qrm[c] += k3 * Qm;
+      if (Hr) Hr[c] += k3 * (ora_h_mol(1, g->T[c]) - ora_h_mol(0, g->T[c])) * xs / dt;
+    }
     /* eqs. e2-1, e2-25, e3-25, e3-52: kg/s per parcel, summed per cell */
     if (mdotH2) mdotH2[c] += -k3 * MG[0] * 1e-3 * xs / dt;
     if (mdotH2O) mdotH2O[c] += k3 * MG[1] * 1e-3 * xs / dt;
@@ -992,4 +1166,21 @@ void ora_get(const ora_sys *s, double *x, double *y, double *z, double *vx, doub
     if (mass) mass[i] = s->mass[i];
   }
   if (eps) memcpy(eps, s->eps, sizeof(double) * s->n_cells);
+}
+
+/* particle temperatures (K, by id); m C_p,p follows, Q_r + Q_rm restarts at 0 */
+void ora_set_temperature(ora_sys *s, const double *Tp) {
+  for (int i = 0; i < s->n; i++) {
+    s->Tp[i] = Tp[i];
+    s->qrx[i] = 0.0;
+    s->mcp[i] = parcel_mcp(s, i);
+  }
+}
+
+void ora_get_energy(const ora_sys *s, double *Tp, double *qrx, double *mcp) {
+  for (int i = 0; i < s->n; i++) {
+    if (Tp) Tp[i] = s->Tp[i];
+    if (qrx) qrx[i] = s->qrx[i];
+    if (mcp) mcp[i] = s->mcp[i];
+  }
 }

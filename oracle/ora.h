@@ -14,8 +14,9 @@
  * their use, limits or finiteness): the tortuosity, eps_min, kt/kn, the
  * tangential damping, the neighbour skin and clamp thresholds, the mixture
  * viscosity correlation of Table C2, the magnitude of the Ergun branch of the
- * drag, the rolling-friction torque, and the species coefficients E Q, E S of
- * eqs. e4-7..e4-11.
+ * drag, the rolling-friction torque, the species coefficients E Q, E S of
+ * eqs. e4-7..e4-11, and the gas conductivity correlation of Table C3 (pinned
+ * only to textbook values of the pure gases).
  */
 #ifndef ORA_H
 #define ORA_H
@@ -50,6 +51,7 @@ typedef struct {
   int ergun_printed;      /* 1: inertial Ergun term with eps_g as printed */
   int drag_on;            /* 0: no gas-side forces (test switch) */
   int n_beds, n_ores;
+  int energy_on;          /* 1: particle energy equation (set temperatures with ora_set_temperature) */
 } ora_params;
 
 typedef struct {
@@ -80,7 +82,12 @@ void ora_couple(ora_sys *s, const ora_gas *g, double *eps, double *np_, double *
 /* USCM update over dt; per-cell sources and per-parcel / per-bed f_ov (may be NULL);
  * update_mass = 0 keeps the DEM mass frozen.  Returns the number of clamped rates. */
 long ora_react(ora_sys *s, double dt, const ora_gas *g, int update_mass, double *mdotH2,
-               double *mdotH2O, double *sumEQ, double *sumES, double *fov, double *bed_fov);
+               double *mdotH2O, double *sumEQ, double *sumES, double *fov, double *bed_fov,
+               double *hA, double *hAT, double *Qrm, double *Hr);
+/* energy equation: per-parcel temperatures (K, by id; Q_r + Q_rm restarts at 0)
+ * and the current temperature, k^3 (Q_r + Q_rm) and m C_p,p of every parcel */
+void ora_set_temperature(ora_sys *s, const double *Tp);
+void ora_get_energy(const ora_sys *s, double *Tp, double *qrx, double *mcp);
 void ora_get(const ora_sys *s, double *x, double *y, double *z, double *vx, double *vy,
              double *vz, double *wx, double *wy, double *wz, double *nh, double *nm,
              double *nw, double *nfe, double *mass, double *eps);
@@ -106,6 +113,12 @@ double ora_sherwood(double eps, double Re, double Sc);
 double ora_film(double T, double p, double xh2, double xh2o, double xn2, double mu_override,
                 double eps, double slip, double dp);
 double ora_keq(int i, double T);
+/* species 0 H2, 1 H2O, 2 N2, 3 Fe2O3, 4 Fe3O4, 5 FeO, 6 Fe (Table C1) */
+double ora_h_mol(int sp, double T);    /* J/mol, eq. e3-22 times M */
+double ora_cp_mol(int sp, double T);   /* J/(mol K), eq. e3-23 times M */
+double ora_lambda_g(double T, double xh2, double xh2o, double xn2);  /* eqs. e3-58, e3-59 */
+double ora_cp_g(double T, double xh2, double xh2o, double xn2);      /* eq. e3-57, J/(kg K) */
+double ora_nusselt(double eps, double Re, double Pr);                /* eq. e3-12 */
 double ora_beta_over_epsp(double eps, double rho, double mu, double slip, double dp, int printed);
 double ora_beta_ganser_over_epsp(double eps, double rho, double mu, double slip, double dp, double psi,
                                  double Dbed, int printed);

@@ -43,7 +43,7 @@ class OraParams(C.Structure):
     _fields_ = [("kn", C.c_double), ("e_p", C.c_double), ("mu_s", C.c_double), ("mu_r", C.c_double),
                 ("kt_over_kn", C.c_double), ("gt_over_gn", C.c_double), ("eps_min", C.c_double),
                 ("dt", C.c_double), ("g", C.c_double * 3), ("ergun_printed", C.c_int),
-                ("drag_on", C.c_int), ("n_beds", C.c_int), ("n_ores", C.c_int)]
+                ("drag_on", C.c_int), ("n_beds", C.c_int), ("n_ores", C.c_int), ("energy_on", C.c_int)]
 
 
 _GAS_KEYS = ("ug", "vg", "wg", "p", "dpdx", "dpdy", "dpdz", "T", "xH2", "xH2O", "xN2")
@@ -74,7 +74,17 @@ def lib():
         L.ora_step.argtypes = [C.c_void_p, C.c_int, C.POINTER(OraGas)]
         L.ora_couple.argtypes = [C.c_void_p, C.POINTER(OraGas)] + [_dp] * 7
         L.ora_react.restype = C.c_long
-        L.ora_react.argtypes = [C.c_void_p, C.c_double, C.POINTER(OraGas), C.c_int] + [_dp] * 6
+        L.ora_react.argtypes = [C.c_void_p, C.c_double, C.POINTER(OraGas), C.c_int] + [_dp] * 10
+        L.ora_set_temperature.argtypes = [C.c_void_p, _dp]
+        L.ora_get_energy.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        for name in ("ora_h_mol", "ora_cp_mol"):
+            getattr(L, name).restype = C.c_double
+            getattr(L, name).argtypes = [C.c_int, C.c_double]
+        for name in ("ora_lambda_g", "ora_cp_g"):
+            getattr(L, name).restype = C.c_double
+            getattr(L, name).argtypes = [C.c_double] * 4
+        L.ora_nusselt.restype = C.c_double
+        L.ora_nusselt.argtypes = [C.c_double] * 3
         L.ora_get.argtypes = [C.c_void_p] + [_dp] * 15
         L.ora_grad.argtypes = [C.c_void_p, C.POINTER(OraGas), C.c_int, C.c_double, C.c_int, _dp, _dp, _dp]
         for name in ("ora_e_cgp", "ora_zeta", "ora_knudsen_h2", "ora_keq"):
@@ -134,6 +144,7 @@ class Oracle:
         P.ergun_printed = int(prm.get("ergun_printed", 0))
         P.drag_on = int(drag_on)
         P.n_beds, P.n_ores = len(w.beds), len(w.ores)
+        P.energy_on = int(prm.get("energy_on", 0))
         beds = (OraBed * len(w.beds))()
         for b, bd in enumerate(w.beds):
             s = beds[b]
@@ -157,6 +168,10 @@ class Oracle:
                            _p(kp["ore"], C.c_int), _p(kp["bed"], C.c_int),
                            *[_p(kp[k]) for k in ("nh", "nm", "nw", "nfe")])
         self.n_cells = L.ora_n_cells(self.h)
+        self.energy = bool(P.energy_on)
+        if self.energy:
+            self._keep["Tp"] = np.ascontiguousarray(p["Tp"], dtype=np.float64)
+            L.ora_set_temperature(self.h, _p(self._keep["Tp"]))
         self.set_gas(w.gas)
 
     def set_gas(self, gas):
@@ -194,17 +209,24 @@ class Oracle:
         return out
 
     def react(self, dt, update_mass=True, n_beds=1):
-        out = {k: np.zeros(self.n_cells) for k in ("mdotH2", "mdotH2O", "sumEQ", "sumES")}
+        keys = ("mdotH2", "mdotH2O", "sumEQ", "sumES")
+        heat = ("hA", "hAT", "Qrm", "Hr")
+        out = {k: np.zeros(self.n_cells) for k in keys + heat}
         fov = np.zeros(self.n)
         bf = np.zeros(n_beds)
         cl = lib().ora_react(self.h, float(dt), C.byref(self._gs), int(update_mass),
-                             *[_p(out[k]) for k in ("mdotH2", "mdotH2O", "sumEQ", "sumES")], _p(fov), _p(bf))
+                             *[_p(out[k]) for k in keys], _p(fov), _p(bf), *[_p(out[k]) for k in heat])
+        if not self.energy:
+            for k in heat:
+                del out[k]
         out["fov"] = fov
         out["bed_fov"] = bf
         out["clamps"] = int(cl)
         return out
 
     def grad(self, n_sub, dt_react, dyn_every, theta):
+        if self.energy:
+            raise ValueError("the gradient protocol is isothermal")
         th = np.ascontiguousarray(theta, dtype=np.float64)
         J = np.zeros(1)
         g = np.zeros(6)
@@ -216,6 +238,10 @@ class Oracle:
         out = {k: np.zeros(self.n) for k in keys}
         out["eps"] = np.zeros(self.n_cells)
         lib().ora_get(self.h, *[_p(out[k]) for k in keys], _p(out["eps"]))
+        if self.energy:
+            for k in ("Tp", "qrx", "mcp"):
+                out[k] = np.zeros(self.n)
+            lib().ora_get_energy(self.h, _p(out["Tp"]), _p(out["qrx"]), _p(out["mcp"]))
         return out
 
 
@@ -294,3 +320,24 @@ def react_point(env, sp):
     s = np.ascontiguousarray(sp, dtype=np.float64).copy()
     c = lib().ora_react_point(_p(e), _p(s))
     return s, c
+
+
+# species: 0 H2, 1 H2O, 2 N2, 3 Fe2O3, 4 Fe3O4, 5 FeO, 6 Fe (Table C1)
+def h_mol(sp, T):
+    return lib().ora_h_mol(int(sp), float(T))
+
+
+def cp_mol(sp, T):
+    return lib().ora_cp_mol(int(sp), float(T))
+
+
+def lambda_g(T, xh2, xh2o, xn2):
+    return lib().ora_lambda_g(T, xh2, xh2o, xn2)
+
+
+def cp_g(T, xh2, xh2o, xn2):
+    return lib().ora_cp_g(T, xh2, xh2o, xn2)
+
+
+def nusselt(eps, Re, Pr):
+    return lib().ora_nusselt(eps, Re, Pr)

@@ -123,7 +123,7 @@ class Workload:
 def base_params(**kw) -> dict:
     p = dict(kn=1000.0, e_p=0.9, mu_s=0.3, mu_r=0.0, kt_over_kn=2.0 / 7.0, gt_over_gn=0.0,
              eps_min=0.35, skin=5e-5, g=(0.0, 0.0, -9.81), dt=1e-5, rebuild_every=10,
-             max_nbr=48, ergun_printed=0)
+             max_nbr=48, ergun_printed=0, energy_on=0)
     p.update(kw)
     return p
 
@@ -489,6 +489,28 @@ def with_velocities(w: Workload, seed: int, vscale=0.05, wscale=50.0) -> Workloa
         for key in ("vx", "vy", "vz", "wx", "wy", "wz"):
             p[key] = p[key].astype(np.float32).astype(np.float64)
     return dataclasses.replace(w, parcels=p)
+
+
+def with_energy(w: Workload, dT: float = 0.0, seed: int = None, spread: float = 0.0) -> Workload:
+    """Copy of ``w`` with the particle energy equation on: every parcel starts
+    at the gas temperature of its cell plus ``dT`` (K), plus a seeded uniform
+    offset in [-spread, spread] when ``seed`` is given."""
+    p = dict(w.parcels)
+    Tp = np.zeros(w.n)
+    for b, bed in enumerate(w.beds):
+        sel = np.flatnonzero(p["bed"] == b)
+        q = [np.clip(np.floor((p[a][sel] - bed.origin[i]) / bed.h), 0, bed.n[i] - 1).astype(np.int64)
+             for i, a in enumerate(("x", "y", "z"))]
+        c = int(w.cell_offset[b]) + q[0] + bed.n[0] * (q[1] + bed.n[1] * q[2])
+        Tp[sel] = w.gas["T"][c]
+    Tp += dT
+    if seed is not None:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        Tp += spread * (2 * rng.random(w.n) - 1)
+    p["Tp"] = Tp
+    prm = dict(w.params)
+    prm["energy_on"] = 1
+    return dataclasses.replace(w, parcels=p, params=prm)
 
 
 def squeeze(w: Workload, factor: float, seed: int) -> Workload:
