@@ -101,23 +101,30 @@ typedef struct {
   int32_t rebuild_every; /* steps between neighbour-list builds (>= 1) */
   int32_t ergun_printed; /* 1: inertial Ergun term with eps_g as printed in eq. e3-5-1 */
   int32_t drag_on;       /* 0: no gas-side forces on parcels (gravity only) */
+  int32_t energy_on;     /* 1: particle energy equation (eqs. e3-8..e3-13, e3-18..e3-23, e3-41,
+                            e3-49, e3-50): each parcel carries T_p, heated by convection (Gunn Nu)
+                            and by the reaction heats of the last dem_react; equilibria, rate
+                            constants and pore diffusion then take T_p.  Conduction and
+                            radiation are not modelled.  dem_grad requires 0. */
 } dem_params;
 
 /* Parcel state (device pointers, original order).  v and w point to float in
  * DEM_MIXED and to double in DEM_FP64.  d is the parcel diameter k * d_p
  * (FP32), k the coarse-graining ratio of Section 3.3, n_* the moles of
- * Fe2O3, Fe3O4, FeO and Fe per real particle. */
+ * Fe2O3, Fe3O4, FeO and Fe per real particle, Tp the particle temperature
+ * (K, double; read and written only with energy_on, required then). */
 typedef struct {
   double *x, *y, *z;
   void *vx, *vy, *vz, *wx, *wy, *wz;
   float *d, *k;
   int32_t *ore, *bed;
   double *nh, *nm, *nw, *nfe;
+  double *Tp;
 } dem_parcels;
 
 /* Frozen gas fields per cell (device pointers, double): velocity, pressure,
- * pressure gradient, temperature (= particle temperature, Section 2,
- * assumption (iv)) and the true mole fractions of H2, H2O and N2. */
+ * pressure gradient, temperature (also the particle temperature unless
+ * energy_on) and the true mole fractions of H2, H2O and N2. */
 typedef struct {
   const double *ug, *vg, *wg, *p, *dpdx, *dpdy, *dpdz, *T, *xH2, *xH2O, *xN2;
 } dem_gas;
@@ -128,9 +135,15 @@ typedef struct {
  *  sumK    sum of K_p = beta V_p / (1 - eps_g) (eqs. e3-5, e3-27a), kg/s
  *  sumKu/v/w  sum of K_p v_p, sumKs sum of K_p |u_g - v_p|
  *  mdotH2, mdotH2O  parcel mass sources of eq. e3-25 times V_cell (kg/s, eqs. e2-25, e3-52)
- *  sumEQ, sumES     sums of k^3 E Q and k^3 E S of eqs. e4-8..e4-11 with E = eta_H2 A_p / T */
+ *  sumEQ, sumES     sums of k^3 E Q and k^3 E S of eqs. e4-8..e4-11 with E = eta_H2 A_p / T
+ * and, written by dem_react with energy_on only (W/K or W, at the reaction update):
+ *  hA      sum of k^3 h_p A_p = H0 V_cell (eqs. e3-10..e3-13, e3-41, e4-4)
+ *  hAT     sum of k^3 h_p A_p T_p = H1 V_cell (eq. e4-5)
+ *  Qrm     sum of k^3 Q_rm (eqs. e3-20, e3-21, e3-50); the gas takes -Qrm / V_cell in eq. e3-38
+ *  Hr      sum over gas species of H_j(T_g) times mdot_j, = -M_r V_cell of eq. e3-39 */
 typedef struct {
   double *eps, *np, *sumK, *sumKu, *sumKv, *sumKw, *sumKs, *mdotH2, *mdotH2O, *sumEQ, *sumES;
+  double *hA, *hAT, *Qrm, *Hr;
 } dem_sources;
 
 /* Kinetic-gradient protocol: n_substeps reaction updates of dt_react, each
@@ -177,7 +190,10 @@ int dem_couple(dem_ctx *c, const dem_gas *g, dem_sources *out);
 
 /* Reaction update over dt_cfd (eqs. e2-1..e2-36, e3-1..e3-4, e3-52): the
  * multi-interface unreacted-shrinking-core rates of every parcel, the species
- * and mass update and the cell sources mdotH2, mdotH2O, sumEQ, sumES.
+ * and mass update and the cell sources mdotH2, mdotH2O, sumEQ, sumES; with
+ * energy_on also each parcel's reaction heat k^3 (Q_r + Q_rm) and heat
+ * capacity m C_p,p (eq. e3-9), held by the DEM steps until the next update,
+ * and the heat sums hA, hAT, Qrm, Hr.
  * bed_fov (host, n_beds doubles, may be NULL): bed-mean overall reduction
  * degree weighted by k^3 N_Fe (eqs. e2-18/e2-19); when given, the call
  * synchronises.  fov (device, n doubles, original order, may be NULL):

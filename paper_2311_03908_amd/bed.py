@@ -61,6 +61,8 @@ class Bed:
         P.rebuild_every = prm["rebuild_every"] if rebuild_every is None else rebuild_every
         P.ergun_printed = int(prm.get("ergun_printed", 0))
         P.drag_on = int(drag_on)
+        P.energy_on = int(prm.get("energy_on", 0))
+        self.energy = bool(P.energy_on)
         self._P, self._beds, self._ores = P, beds, ores
         dev = self.device
         p = w.parcels
@@ -73,9 +75,11 @@ class Bed:
         self.inp["k"] = torch.as_tensor(np.ascontiguousarray(p["k"], dtype=np.float32), device=dev)
         self.inp["ore"] = torch.as_tensor(np.ascontiguousarray(p["ore"], dtype=np.int32), device=dev)
         self.inp["bed"] = torch.as_tensor(np.ascontiguousarray(p["bed"], dtype=np.int32), device=dev)
+        if self.energy:
+            self.inp["Tp"] = torch.as_tensor(np.ascontiguousarray(p["Tp"], dtype=np.float64), device=dev)
         self.set_gas(w.gas)
         self.n_cells = int(self.gas_t["T"].shape[0])
-        pc = capi.DemParcels(*[_ptr(self.inp[f]) for f in capi.PARCEL_FIELDS])
+        pc = capi.DemParcels(*[_ptr(self.inp.get(f)) for f in capi.PARCEL_FIELDS])
         h = C.c_void_p()
         with torch.cuda.device(dev):
             torch.cuda.synchronize(dev)
@@ -120,7 +124,9 @@ class Bed:
         self.sync()
         return out
 
-    def react(self, dt, keys=("mdotH2", "mdotH2O", "sumEQ", "sumES"), fov=True):
+    def react(self, dt, keys=None, fov=True):
+        if keys is None:
+            keys = ("mdotH2", "mdotH2O", "sumEQ", "sumES") + (("hA", "hAT", "Qrm", "Hr") if self.energy else ())
         out, s = self._sources(keys)
         bf = (C.c_double * self.n_beds)()
         fv = torch.zeros(self.n, dtype=torch.float64, device=self.device) if fov else None
@@ -142,6 +148,8 @@ class Bed:
                ("x", "y", "z", "nh", "nm", "nw", "nfe")}
         for k in ("vx", "vy", "vz", "wx", "wy", "wz"):
             out[k] = torch.zeros(self.n, dtype=self.vdtype, device=self.device)
+        if self.energy:
+            out["Tp"] = torch.zeros(self.n, dtype=torch.float64, device=self.device)
         pc = capi.DemParcels(*[_ptr(out.get(f)) for f in capi.PARCEL_FIELDS])
         self._check(self.L.dem_get_state(self.h, C.byref(pc)))
         return out
@@ -152,6 +160,8 @@ class Bed:
             t[k] = torch.as_tensor(np.asarray(st[k], dtype=np.float64), device=self.device)
         for k in ("vx", "vy", "vz", "wx", "wy", "wz"):
             t[k] = torch.as_tensor(np.asarray(st[k], dtype=np.float64), device=self.device).to(self.vdtype)
+        if self.energy and "Tp" in st:
+            t["Tp"] = torch.as_tensor(np.asarray(st["Tp"], dtype=np.float64), device=self.device)
         pc = capi.DemParcels(*[_ptr(t.get(f)) for f in capi.PARCEL_FIELDS])
         self._check(self.L.dem_set_state(self.h, C.byref(pc)))
 

@@ -37,10 +37,11 @@ class DemParams(C.Structure):
                 ("kt_over_kn", C.c_double), ("gt_over_gn", C.c_double), ("eps_min", C.c_double),
                 ("skin", C.c_double), ("dt", C.c_double), ("g", C.c_double * 3),
                 ("max_nbr", C.c_int32), ("rebuild_every", C.c_int32), ("ergun_printed", C.c_int32),
-                ("drag_on", C.c_int32)]
+                ("drag_on", C.c_int32), ("energy_on", C.c_int32)]
 
 
-PARCEL_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "wx", "wy", "wz", "d", "k", "ore", "bed", "nh", "nm", "nw", "nfe")
+PARCEL_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "wx", "wy", "wz", "d", "k", "ore", "bed", "nh", "nm", "nw", "nfe",
+                 "Tp")
 
 
 class DemParcels(C.Structure):
@@ -54,7 +55,8 @@ class DemGas(C.Structure):
     _fields_ = [(f, C.c_void_p) for f in GAS_FIELDS]
 
 
-SOURCE_FIELDS = ("eps", "np", "sumK", "sumKu", "sumKv", "sumKw", "sumKs", "mdotH2", "mdotH2O", "sumEQ", "sumES")
+SOURCE_FIELDS = ("eps", "np", "sumK", "sumKu", "sumKv", "sumKw", "sumKs", "mdotH2", "mdotH2O", "sumEQ", "sumES",
+                 "hA", "hAT", "Qrm", "Hr")
 
 
 class DemSources(C.Structure):

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -124,6 +125,8 @@ struct Ctx final : dem_ctx {
   int max_chunks = 0;
   int32_t *iflags = nullptr, *ioffs = nullptr, *ilist = nullptr, *icount = nullptr;
   T *gtab = nullptr;
+  ThermoTab *thermo = nullptr;    // energy equation only
+  const double *gas_T = nullptr;  // gas temperature of the last gas table (energy equation)
   double *eps = nullptr, *pm = nullptr, *pw = nullptr, *bed_fov_d = nullptr, *theta_d = nullptr;
   uint32_t *status = nullptr;
   float4 *xref = nullptr;            // positions at the last rebuild
@@ -183,6 +186,9 @@ struct Ctx final : dem_ctx {
   int alloc_props(Props<T> &p, const Props<T> *shared) {
     TRY(dalloc(p.kcg, n)); TRY(dalloc(p.tag, n));
     TRY(dalloc(p.nh, n)); TRY(dalloc(p.nm, n)); TRY(dalloc(p.nw, n)); TRY(dalloc(p.nfe, n));
+    if (P.energy_on) {
+      TRY(dalloc(p.Tp, n)); TRY(dalloc(p.qrx, n)); TRY(dalloc(p.mcp, n));
+    }
     if (shared) {  // wall springs are indexed by original id: one copy
       p.wh = shared->wh;
       return DEMRX_OK;
@@ -214,6 +220,8 @@ struct Ctx final : dem_ctx {
     ph.n_beds = p->n_beds; ph.n_ores = p->n_ores; ph.max_nbr = p->max_nbr;
     ph.ganser = 0;
     for (int o = 0; o < p->n_ores; o++) ph.ganser |= p->ores[o].psi > 0.0;
+    ph.energy = p->energy_on != 0;
+    if (p->energy_on && !in->Tp) return fail(DEMRX_EINVAL, "energy_on needs the particle temperatures Tp");
     // beds
     long goff = 0, doff = 0, items_total = 0;
     for (int b = 0; b < p->n_beds; b++) {
@@ -316,7 +324,12 @@ struct Ctx final : dem_ctx {
     TRY(dalloc(ilist, n_items)); TRY(dalloc(icount, 2));
     TRY(dalloc(gtab, (size_t)n_gas * kGasRow));
     TRY(dalloc(eps, n_gas));
-    TRY(dalloc(pm, (size_t)4 * n)); TRY(dalloc(pw, (size_t)2 * n));
+    TRY(dalloc(pm, (size_t)(P.energy_on ? 8 : 4) * n)); TRY(dalloc(pw, (size_t)2 * n));
+    if (P.energy_on) {
+      TRY(dalloc(thermo, 1));
+      static const ThermoTab tt = make_thermo();
+      HIPCHK(hipMemcpyAsync(thermo, &tt, sizeof(ThermoTab), hipMemcpyHostToDevice, st));
+    }
     TRY(dalloc(bed_fov_d, p->n_beds)); TRY(dalloc(theta_d, 6));
     TRY(dalloc(status, 1)); TRY(dalloc(counters, 4)); TRY(dalloc(xref, n));
     TRY(dalloc(dslot, 2 * kSlots * kSlotPad)); TRY(dalloc(cslot, kSlots * kSlotPad64));
@@ -333,7 +346,7 @@ struct Ctx final : dem_ctx {
     launch_fill_u32(dslot, 0u, 2 * kSlots * kSlotPad, st);
     launch_fill_u32((uint32_t *)cslot, 0u, 2 * kSlots * kSlotPad64, st);
     launch_fill_u32((uint32_t *)counters, 0u, 8, st);
-    launch_init<T>(*in, n, ph, p->n_ores, dyn[0], pr[0], status, st);
+    launch_init<T>(*in, n, ph, p->n_ores, thermo, dyn[0], pr[0], status, st);
     HIPCHK(hipGetLastError());
     TRY(check_status());
     TRY(rebuild());
@@ -430,7 +443,8 @@ struct Ctx final : dem_ctx {
   }
 
   int gas_table(const dem_gas *g) {
-    launch_gas_table<T>(gas_args(g), eps, cell_bed, beds, n_gas, gtab, status, st);
+    launch_gas_table<T>(gas_args(g), eps, cell_bed, beds, thermo, n_gas, gtab, status, st);
+    gas_T = g->T;
     HIPCHK(hipGetLastError());
     return DEMRX_OK;
   }
@@ -446,6 +460,7 @@ struct Ctx final : dem_ctx {
     a.ores = ores;
     a.ph = ph;
     a.status = status;
+    a.Tg = gas_T;
     a.xref = xref;
     a.dslot = dslot;
     a.cslot = cslot;
@@ -537,6 +552,7 @@ struct Ctx final : dem_ctx {
     a.eps = eps;
     a.beds = beds;
     a.ores = ores;
+    a.thermo = thermo;
     a.theta = theta_dev;
     a.dt = dt;
     a.n = n;
@@ -547,9 +563,12 @@ struct Ctx final : dem_ctx {
     a.clamps = counters + 2;
     a.status = status;
     launch_react<T>(a, st);
-    if (o && (o->mdotH2 || o->mdotH2O || o->sumEQ || o->sumES))
-      launch_cellsum(pm, n, start_d, order_d, cell_bed, beds, n_gas, o->mdotH2, o->mdotH2O, o->sumEQ, o->sumES,
-                     st);
+    if (o) {
+      CellSumOut cs{{o->mdotH2, o->mdotH2O, o->sumEQ, o->sumES, o->hA, o->hAT, o->Qrm, o->Hr}, thermo ? 8 : 4};
+      bool any = false;
+      for (int q = 0; q < cs.rows; q++) any |= cs.o[q] != nullptr;
+      if (any) launch_cellsum(pm, n, start_d, order_d, cell_bed, beds, n_gas, cs, st);
+    }
     if (bed_sum) launch_bedsum(pw, n, start, beds, P.n_beds, bchunks, max_chunks, bpartial, bed_fov_d, st);
     HIPCHK(hipGetLastError());
     return DEMRX_OK;
@@ -589,7 +608,7 @@ struct Ctx final : dem_ctx {
     if (!in || !in->x || !in->y || !in->z || !in->vx || !in->vy || !in->vz || !in->wx || !in->wy || !in->wz ||
         !in->nh || !in->nm || !in->nw || !in->nfe)
       return fail(DEMRX_EINVAL, "null parcel array");
-    launch_import<T>(*in, n, dyn[cur], pr[pc], st);
+    launch_import<T>(*in, n, thermo, dyn[cur], pr[pc], st);
     for (int k = 0; k < 2; k++) launch_fill_u32((uint32_t *)nb[k].mask, 0u, 2L * n, st);
     built = false;
     TRY(rebuild());
@@ -797,6 +816,7 @@ struct Ctx final : dem_ctx {
     HIPCHK(hipEventCreate(&e1));
     float best = 1e30f;
     int best_b = step_block, best_x = step_xcd;
+    const bool tune_log = std::getenv("DEMRX_TUNE_LOG") != nullptr;  // per-candidate timings on stderr
     for (int b : {64, 128, 256, 512}) {
       for (int x : {1, 4, 16, 64}) {
         step_xcd = x;
@@ -810,6 +830,7 @@ struct Ctx final : dem_ctx {
           HIPCHK(hipEventElapsedTime(&ms, e0, e1));
           if (rep) tot += ms;
         }
+        if (tune_log) std::fprintf(stderr, "[demrx] autotune step block %d xcd chunk %d: %.1f us\n", b, x, tot / 3 * 1e3f);
         if (tot < best) { best = tot; best_b = b; best_x = x; }
       }
     }
@@ -830,6 +851,7 @@ struct Ctx final : dem_ctx {
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         if (rep) tot += ms;
       }
+      if (tune_log) std::fprintf(stderr, "[demrx] autotune build grid %d: %.1f us\n", gsz, tot / 2 * 1e3f);
       if (tot < best) { best = tot; best_g = gsz; }
     }
     build_grid = best_g;

@@ -60,6 +60,7 @@ struct Phys {
   double g[3];
   int ergun_printed, drag_on, n_beds, n_ores, max_nbr;
   int ganser;  // some ore has a sphericity in (0, 1]
+  int energy;  // particle energy equation on
 };
 
 // Parcel records, double-buffered (the step reads one buffer and writes the
@@ -92,6 +93,9 @@ struct Props {
   int32_t *tag;  // bed * 256 + ore
   double *nh, *nm, *nw, *nfe;
   T *wh;         // wall tangential springs by original id: [(wall * 3 + axis) * N + id]
+  // energy equation only (null otherwise): temperature (K), k^3 (Q_r + Q_rm)
+  // of the last reaction update (W) and m C_p,p at that update (J/K)
+  double *Tp, *qrx, *mcp;
 };
 
 // Four values loaded and stored as one vector record

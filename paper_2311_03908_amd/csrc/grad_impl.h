@@ -15,6 +15,7 @@
 template <typename T>
 int Ctx<T>::grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, double *J, double *gr) {
   if (!s || !J) return fail(DEMRX_EINVAL, "null spec or J");
+  if (P.energy_on) return fail(DEMRX_EINVAL, "the gradient protocol is isothermal (energy_on must be 0)");
   if (!gas_ok(g)) return fail(DEMRX_EINVAL, "null gas field");
   if (s->n_substeps < 1 || s->dyn_every < 1 || s->ckpt_every < 1 || !(s->dt_react > 0.0) ||
       !std::isfinite(s->dt_react))

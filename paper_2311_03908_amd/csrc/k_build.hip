@@ -209,6 +209,11 @@ __global__ void k_permute(const int32_t *perm, int n, Dyn<T> din, Props<T> pin, 
   pout.nm[j] = pin.nm[i];
   pout.nw[j] = pin.nw[i];
   pout.nfe[j] = pin.nfe[i];
+  if (pin.Tp) {
+    pout.Tp[j] = pin.Tp[i];
+    pout.qrx[j] = pin.qrx[i];
+    pout.mcp[j] = pin.mcp[i];
+  }
 }
 
 template <typename T>

@@ -188,27 +188,33 @@ __global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
   const int c = cl.gas;
   const double Tg = a.g.T[c], p = a.g.p[c], xa = a.g.xH2[c], xb = a.g.xH2O[c], xn = a.g.xN2[c];
   const double *th = a.theta ? a.theta : B.theta;
-  const double RT = kRg * Tg;
+  // with the energy equation the interface reactions and the pore diffusion
+  // run at the particle temperature; film, density and concentration at T_g
+  const double Tk = a.thermo ? a.p.Tp[j] : Tg;
+  const double RT = kRg * Tg, RTk = kRg * Tk;
   UscmEnv<double> e;
   e.x = xb > 0.0 ? xa / (xa + xb) : (xa > 0.0 ? 1.0 : 0.0);
   // Table 2 equilibria (eq. e2-1-3) and Arrhenius constants (eq. e2-13)
-  const double Kc[3] = {exp(1433.4 / Tg + 9.08), exp(-7393.9 / Tg + 7.56), exp(-2023.8 / Tg + 1.24)};
+  const double Kc[3] = {exp(1433.4 / Tk + 9.08), exp(-7393.9 / Tk + 7.56), exp(-2023.8 / Tk + 1.24)};
 #pragma unroll
   for (int q = 0; q < 3; q++) {
     e.xeq[q] = 1.0 / (Kc[q] + 1.0);
-    e.kk[q] = (Kc[q] / (1.0 + Kc[q])) / exp(th[2 * q] - th[2 * q + 1] / RT);
+    e.kk[q] = (Kc[q] / (1.0 + Kc[q])) / exp(th[2 * q] - th[2 * q + 1] / RTk);
   }
   const double kcg = (double)a.p.kcg[j];
   const double dp = 2.0 * (double)P.r / kcg, rp = 0.5 * dp, Ap = kPi * dp * dp;
   const PoreDiff Dd = pore_diffusion(Tg, p, xa, xb, xn, O.d_pore_cm);
+  const double Dpore = a.thermo ? pore_diffusion(Tk, p, xa, xb, xn, O.d_pore_cm).D : Dd.D;
 #pragma unroll
-  for (int q = 0; q < 3; q++) e.rpD[q] = rp / (Dd.D * O.xi_layer[q] / O.tau);
+  for (int q = 0; q < 3; q++) e.rpD[q] = rp / (Dpore * O.xi_layer[q] / O.tau);
   double rho, mu;
   gas_props_h2(Tg, p, xa, xb, xn, B.mu_override, rho, mu);
   const double sx = a.g.ug[c] - (double)Vr.v[0], sy = a.g.vg[c] - (double)Vr.v[1], sz = a.g.wg[c] - (double)Vr.v[2];
-  e.F = film_resistance(rho, mu, Dd.Dm, a.eps[c], dp, sqrt(sx * sx + sy * sy + sz * sz));
+  const double slip = sqrt(sx * sx + sy * sy + sz * sz);
+  e.F = film_resistance(rho, mu, Dd.Dm, a.eps[c], dp, slip);
   e.cad = Ap * (p / RT) * a.dt;
   double n[4] = {a.p.nh[j], a.p.nm[j], a.p.nw[j], a.p.nfe[j]};
+  const double n0[4] = {n[0], n[1], n[2], n[3]};
   double xi[3], Qn, Sn;
   const int clamps = uscm_step<double>(n, e, xi, Qn, Sn);
   a.p.nh[j] = n[0];
@@ -223,6 +229,31 @@ __global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
   const double E = -Ap / Tg;                 // eq. e4-8 with eta_H2 = -1
   a.pm[2 * N + j] = k3 * E * Qn;
   a.pm[3 * N + j] = k3 * E * Sn;
+  if (a.thermo) {
+    const ThermoTab &tt = *a.thermo;
+    // eqs. e3-18..e3-21 with the k^3 of eqs. e3-49, e3-50: enthalpies at T_p
+    // of the solid species' mole changes and of the H2 taken / H2O given
+    double Qr = 0.0, cp = 0.0;
+#pragma unroll
+    for (int z = 0; z < 4; z++) {
+      Qr -= h_mol(tt, kFe2O3 + z, Tk) * (n[z] - n0[z]);
+      cp += n[z] * cp_mol(tt, kFe2O3 + z, Tk);
+    }
+    const double Qm = -(h_mol(tt, kH2O, Tk) - h_mol(tt, kH2, Tk)) * xs;
+    a.p.qrx[j] = k3 * (Qr + Qm) / a.dt;
+    a.p.mcp[j] = k3 * cp;  // eq. e3-9 times the parcel mass
+    // H0, H1 of eqs. e4-4, e4-5 (times V_cell), Q_rm of eq. e3-38 and the
+    // gas-species enthalpy flow of eq. e3-39 at T_g
+    double lam, cpg;
+    gas_heat_props(tt, Tg, xa, xb, xn, lam, cpg);
+    const double Re = rho * a.eps[c] * dp * slip / mu;
+    const double nu = gunn<double>(a.eps[c], pow(Re, 0.2), pow(Re, 0.7), cbrt(cpg * mu / lam));
+    const double hA = k3 * nu * lam * kPi * dp;
+    a.pm[4 * N + j] = hA;
+    a.pm[5 * N + j] = hA * Tk;
+    a.pm[6 * N + j] = k3 * Qm / a.dt;
+    a.pm[7 * N + j] = k3 * (h_mol(tt, kH2O, Tg) - h_mol(tt, kH2, Tg)) * xs / a.dt;
+  }
   const double fov = fov_of<double>(n, O.kind);
   const double w = k3 * (2.0 * n[0] + 3.0 * n[1] + n[2] + n[3]);
   a.pw[j] = w * fov;
@@ -240,38 +271,38 @@ void launch_react(const ReactArgs<T> &a, hipStream_t s) {
 }
 
 __global__ void __launch_bounds__(256) k_cellsum(const double *pm, int n, const int32_t *start, const int32_t *order,
-                                                 const int32_t *cell_bed, const BedDev *beds, int n_gas, double *o0,
-                                                 double *o1, double *o2, double *o3) {
+                                                 const int32_t *cell_bed, const BedDev *beds, int n_gas,
+                                                 CellSumOut o) {
   const int gc = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
   const int sl = threadIdx.x % kGroup;
   const bool valid = gc < n_gas;
   const int c = valid ? gc : n_gas - 1;
   const GasCellRanges R(beds[cell_bed[c]], c);
-  double s[4] = {0, 0, 0, 0};
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int r = 0; r < R.f * R.f; r++) {
     const int k0 = R.row_key(r);
     const int e = start[k0 + R.f];
     for (int t = start[k0] + sl; t < e; t += kGroup) {
       const int j = order[t];
 #pragma unroll
-      for (int q = 0; q < 4; q++) s[q] += pm[(long)q * n + j];
+      for (int q = 0; q < 8; q++)
+        if (q < o.rows) s[q] += pm[(long)q * n + j];
     }
   }
 #pragma unroll
-  for (int q = 0; q < 4; q++) s[q] = group_sum(s[q]);
+  for (int q = 0; q < 8; q++)
+    if (q < o.rows) s[q] = group_sum(s[q]);
   if (valid && sl == 0) {
-    if (o0) o0[c] = s[0];
-    if (o1) o1[c] = s[1];
-    if (o2) o2[c] = s[2];
-    if (o3) o3[c] = s[3];
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+      if (q < o.rows && o.o[q]) o.o[q][c] = s[q];
   }
 }
 
 void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t *order, const int32_t *cell_bed,
-                    const BedDev *beds, int n_gas, double *o0, double *o1, double *o2, double *o3, hipStream_t s) {
+                    const BedDev *beds, int n_gas, const CellSumOut &o, hipStream_t s) {
   const long threads = (long)n_gas * kGroup;
-  k_cellsum<<<(int)((threads + 255) / 256), 256, 0, s>>>(pm, n, start, order, cell_bed, beds, n_gas, o0, o1, o2,
-                                                         o3);
+  k_cellsum<<<(int)((threads + 255) / 256), 256, 0, s>>>(pm, n, start, order, cell_bed, beds, n_gas, o);
 }
 
 // Bed-mean f_ov weighted by k^3 N_Fe: every bed's parcel range (contiguous,
@@ -361,8 +392,17 @@ void launch_bedsum(const double *pw, int n, const int32_t *start, const BedDev *
 }
 
 // ------------------------------------------------------------------ init / import / export
+// heat capacity of a parcel, m C_p,p = k^3 sum_z n_z C_p,z(T_p) (eq. e3-9)
+__device__ __forceinline__ double parcel_mcp(const ThermoTab &t, double k, const double n[4], double Tp) {
+  double c = 0.0;
+#pragma unroll
+  for (int z = 0; z < 4; z++) c += n[z] * cp_mol(t, kFe2O3 + z, Tp);
+  return k * k * k * c;
+}
+
 template <typename T>
-__global__ void k_init(dem_parcels in, int n, Phys ph, int n_ores, Dyn<T> d, Props<T> p, uint32_t *status) {
+__global__ void k_init(dem_parcels in, int n, Phys ph, int n_ores, const ThermoTab *thermo, Dyn<T> d, Props<T> p,
+                       uint32_t *status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float dd = in.d[i], kk = in.k[i];
@@ -390,6 +430,14 @@ __global__ void k_init(dem_parcels in, int n, Phys ph, int n_ores, Dyn<T> d, Pro
   p.nm[i] = nm;
   p.nw[i] = nw;
   p.nfe[i] = nfe;
+  if (thermo) {
+    const double Tp = in.Tp[i];
+    if (!(Tp > 0.0 && Tp < 1e4)) atomicOr(status, 16u);
+    const double ns[4] = {nh, nm, nw, nfe};
+    p.Tp[i] = Tp;
+    p.qrx[i] = 0.0;
+    p.mcp[i] = parcel_mcp(*thermo, (double)kk, ns, Tp);
+  }
   const double k3 = (double)kk * kk * kk;
   V.m = T(k3 * 1e-3 * (nh * 159.687 + nm * 231.531 + nw * 71.844 + nfe * 55.845));  // eq. e3-4
   // eq. e3-45 restitution of the parcel, eq. e3-44 damping ratio
@@ -407,9 +455,9 @@ __global__ void k_init(dem_parcels in, int n, Phys ph, int n_ores, Dyn<T> d, Pro
 }
 
 template <typename T>
-void launch_init(const dem_parcels &in, int n, const Phys &ph, int n_ores, const Dyn<T> &d, const Props<T> &p,
-                 uint32_t *status, hipStream_t s) {
-  k_init<T><<<(n + 255) / 256, 256, 0, s>>>(in, n, ph, n_ores, d, p, status);
+void launch_init(const dem_parcels &in, int n, const Phys &ph, int n_ores, const ThermoTab *thermo, const Dyn<T> &d,
+                 const Props<T> &p, uint32_t *status, hipStream_t s) {
+  k_init<T><<<(n + 255) / 256, 256, 0, s>>>(in, n, ph, n_ores, thermo, d, p, status);
 }
 
 template <typename T>
@@ -432,6 +480,7 @@ __global__ void k_export(Dyn<T> d, Props<T> p, int n, dem_parcels out) {
   if (out.nm) out.nm[i] = p.nm[j];
   if (out.nw) out.nw[i] = p.nw[j];
   if (out.nfe) out.nfe[i] = p.nfe[j];
+  if (out.Tp && p.Tp) out.Tp[i] = p.Tp[j];
 }
 
 template <typename T>
@@ -440,7 +489,7 @@ void launch_export(const Dyn<T> &d, const Props<T> &p, int n, const dem_parcels 
 }
 
 template <typename T>
-__global__ void k_import(dem_parcels in, int n, Dyn<T> d, Props<T> p) {
+__global__ void k_import(dem_parcels in, int n, const ThermoTab *thermo, Dyn<T> d, Props<T> p) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   PosRec P = load_pos(d.pos, j);
@@ -463,14 +512,22 @@ __global__ void k_import(dem_parcels in, int n, Dyn<T> d, Props<T> p) {
   p.nfe[j] = nfe;
   const double kk = (double)p.kcg[j];
   V.m = T(kk * kk * kk * 1e-3 * (nh * 159.687 + nm * 231.531 + nw * 71.844 + nfe * 55.845));
+  if (thermo) {  // new temperature if given; the heat capacity follows, the reaction heat restarts
+    const double Tp = in.Tp ? in.Tp[i] : p.Tp[j];
+    const double ns[4] = {nh, nm, nw, nfe};
+    p.Tp[j] = Tp;
+    p.qrx[j] = 0.0;
+    p.mcp[j] = parcel_mcp(*thermo, kk, ns, Tp);
+  }
   d.vel[j] = V;
 #pragma unroll
   for (int k = 0; k < 3 * kMaxWalls; k++) p.wh[(long)k * n + i] = T(0);
 }
 
 template <typename T>
-void launch_import(const dem_parcels &in, int n, const Dyn<T> &d, const Props<T> &p, hipStream_t s) {
-  k_import<T><<<(n + 255) / 256, 256, 0, s>>>(in, n, d, p);
+void launch_import(const dem_parcels &in, int n, const ThermoTab *thermo, const Dyn<T> &d, const Props<T> &p,
+                   hipStream_t s) {
+  k_import<T><<<(n + 255) / 256, 256, 0, s>>>(in, n, thermo, d, p);
 }
 
 #define INST(T)                                                                                                    \
@@ -478,10 +535,11 @@ void launch_import(const dem_parcels &in, int n, const Dyn<T> &d, const Props<T>
                                   const int32_t *, const int32_t *, const BedDev *, const OreDev *, const Phys &, \
                                   const int32_t *, const int32_t *, int, bool, const DepositOut &, hipStream_t);  \
   template void launch_react<T>(const ReactArgs<T> &, hipStream_t);                                               \
-  template void launch_init<T>(const dem_parcels &, int, const Phys &, int, const Dyn<T> &, const Props<T> &,     \
-                               uint32_t *, hipStream_t);                                                           \
+  template void launch_init<T>(const dem_parcels &, int, const Phys &, int, const ThermoTab *, const Dyn<T> &,    \
+                               const Props<T> &, uint32_t *, hipStream_t);                                         \
   template void launch_export<T>(const Dyn<T> &, const Props<T> &, int, const dem_parcels &, hipStream_t);        \
-  template void launch_import<T>(const dem_parcels &, int, const Dyn<T> &, const Props<T> &, hipStream_t);
+  template void launch_import<T>(const dem_parcels &, int, const ThermoTab *, const Dyn<T> &, const Props<T> &,  \
+                                 hipStream_t);
 INST(float)
 INST(double)
 #undef INST

@@ -215,20 +215,33 @@ __global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 1) k_step(StepArgs<T
       // gravity, pressure gradient and drag (eqs. e3-3, e3-5), NGP gas cell
 #pragma unroll
       for (int c = 0; c < 3; c++) F[c] += mi * T(a.ph.g[c]);
-      if (a.ph.drag_on) {
+      if (a.ph.drag_on || a.ph.energy) {
         Cells cl;
         locate(B, xi, yi, zi, cl);
         const Quad<T> *gq = reinterpret_cast<const Quad<T> *>(a.gtab + (long)cl.gas * kGasRow);
-        const Quad<T> g0 = gq[0], g1 = gq[1];
-        const T mu = gq[2].x;
-        const T dpr = T(2) * ri / T(a.pr.kcg[i]);  // real-particle diameter
-        const T V = T(kPi / 6.0) * (T(2) * ri) * (T(2) * ri) * (T(2) * ri);
+        const Quad<T> g0 = gq[0], g1 = gq[1], g2 = gq[2];
+        const T mu = g2.x;
+        const T kcg = T(a.pr.kcg[i]);
+        const T dpr = T(2) * ri / kcg;  // real-particle diameter
         const T s[3] = {g0.x - Vi.v[0], g0.y - Vi.v[1], g0.z - Vi.v[2]};
         const T slip = tsqrt<T>(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
-        const T be = drag_beta<T>(a.ph, a.ores[ore_of(tag)], B, g0.w, g1.w, mu, slip, dpr);
-        F[0] += be * V * s[0] - V * g1.x;
-        F[1] += be * V * s[1] - V * g1.y;
-        F[2] += be * V * s[2] - V * g1.z;
+        if (a.ph.drag_on) {
+          const T V = T(kPi / 6.0) * (T(2) * ri) * (T(2) * ri) * (T(2) * ri);
+          const T be = drag_beta<T>(a.ph, a.ores[ore_of(tag)], B, g0.w, g1.w, mu, slip, dpr);
+          F[0] += be * V * s[0] - V * g1.x;
+          F[1] += be * V * s[1] - V * g1.y;
+          F[2] += be * V * s[2] - V * g1.z;
+        }
+        if (a.ph.energy && a.mode == 0) {
+          // eqs. e3-8, e3-10..e3-13, e3-41: k^3 h_p A_p = k^3 Nu lambda_g pi d_p,
+          // with the reaction heat and m C_p,p of the last reaction update
+          const T re = g1.w * g0.w * dpr * slip / mu;
+          const T nu = gunn<T>(g0.w, tpow<T>(re, T(0.2)), tpow<T>(re, T(0.7)), g2.z);
+          const T hA = kcg * kcg * kcg * nu * g2.y * T(kPi) * dpr;
+          const double Tp = a.pr.Tp[i];
+          const double q = (double)hA * (a.Tg[cl.gas] - Tp) + a.pr.qrx[i];
+          a.pr.Tp[i] = Tp + a.ph.dt * q / a.pr.mcp[i];
+        }
       }
     };
     // with a single bed its record is read through uniform (scalar) loads
@@ -301,7 +314,8 @@ void launch_step(const StepArgs<T> &a, int block, hipStream_t s) {
 // ------------------------------------------------------------------ gas table
 // Ideal-gas density (eq. e3-53) and mass-weighted viscosity (eqs. e3-55,
 // e3-56, Table C2) of each cell, with the cell's velocity, voidage and
-// pressure gradient, packed in one row for the drag gather.
+// pressure gradient, packed in one row for the drag gather; with the energy
+// equation also the conductivity and Pr^(1/3) (eqs. e3-13, e3-57..e3-59).
 __device__ __forceinline__ void gas_rho_mu(double T, double p, double x1, double x2, double x3, double mu_fix,
                                            double &rho, double &mu) {
   const double M1 = 2.016, M2 = 18.015, M3 = 28.013;  // g/mol H2, H2O, N2
@@ -318,8 +332,8 @@ __device__ __forceinline__ void gas_rho_mu(double T, double p, double x1, double
 }
 
 template <typename T>
-__global__ void k_gas_table(GasArgs g, const double *eps, const int32_t *cell_bed, const BedDev *beds, int n_gas,
-                            T *gtab, uint32_t *status) {
+__global__ void k_gas_table(GasArgs g, const double *eps, const int32_t *cell_bed, const BedDev *beds,
+                            const ThermoTab *thermo, int n_gas, T *gtab, uint32_t *status) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n_gas) return;
   double rho, mu;
@@ -335,22 +349,29 @@ __global__ void k_gas_table(GasArgs g, const double *eps, const int32_t *cell_be
   r[7] = T(rho);
   r[8] = T(mu);
   r[9] = r[10] = r[11] = T(0);
-  if (!(isfinite(rho) && isfinite(mu) && isfinite(g.ug[c] + g.vg[c] + g.wg[c]) &&
+  double lam = 1.0, cp = 1.0;
+  if (thermo) {
+    gas_heat_props(*thermo, g.T[c], g.xH2[c], g.xH2O[c], g.xN2[c], lam, cp);
+    r[9] = T(lam);
+    r[10] = T(cbrt(cp * mu / lam));
+  }
+  if (!(lam > 0.0 && cp > 0.0 && isfinite(g.T[c])) ||
+      !(isfinite(rho) && isfinite(mu) && isfinite(g.ug[c] + g.vg[c] + g.wg[c]) &&
         isfinite(g.dpdx[c] + g.dpdy[c] + g.dpdz[c])) || !(rho > 0.0) || !(mu > 0.0))
     atomicOr(status, ST_NONFINITE);
 }
 
 template <typename T>
-void launch_gas_table(const GasArgs &g, const double *eps, const int32_t *cell_bed, const BedDev *beds, int n_gas,
-                      T *gtab, uint32_t *status, hipStream_t s) {
-  k_gas_table<T><<<(n_gas + 255) / 256, 256, 0, s>>>(g, eps, cell_bed, beds, n_gas, gtab, status);
+void launch_gas_table(const GasArgs &g, const double *eps, const int32_t *cell_bed, const BedDev *beds,
+                      const ThermoTab *thermo, int n_gas, T *gtab, uint32_t *status, hipStream_t s) {
+  k_gas_table<T><<<(n_gas + 255) / 256, 256, 0, s>>>(g, eps, cell_bed, beds, thermo, n_gas, gtab, status);
 }
 
 template void launch_step<float>(const StepArgs<float> &, int, hipStream_t);
 template void launch_step<double>(const StepArgs<double> &, int, hipStream_t);
-template void launch_gas_table<float>(const GasArgs &, const double *, const int32_t *, const BedDev *, int, float *,
-                                      uint32_t *, hipStream_t);
-template void launch_gas_table<double>(const GasArgs &, const double *, const int32_t *, const BedDev *, int,
-                                       double *, uint32_t *, hipStream_t);
+template void launch_gas_table<float>(const GasArgs &, const double *, const int32_t *, const BedDev *,
+                                      const ThermoTab *, int, float *, uint32_t *, hipStream_t);
+template void launch_gas_table<double>(const GasArgs &, const double *, const int32_t *, const BedDev *,
+                                       const ThermoTab *, int, double *, uint32_t *, hipStream_t);
 
 }  // namespace demrx

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.h"
+#include "thermo.h"
 
 namespace demrx {
 
@@ -68,6 +69,7 @@ struct StepArgs {
   const OreDev *ores;
   Phys ph;
   uint32_t *status;
+  const double *Tg;              // gas temperature per cell (energy equation)
   const float4 *xref;            // positions at the last rebuild (FP32)
   unsigned *dslot;               // [2][kSlots] padded: max squared displacement (this step: par)
   unsigned long long *cslot;     // [kSlots] padded: pp and wall contacts (mode 0 with count)
@@ -85,7 +87,7 @@ struct GasArgs {
 };
 template <typename T>
 void launch_gas_table(const GasArgs &g, const double *eps, const int32_t *cell_bed, const BedDev *beds,
-                      int n_gas, T *gtab, uint32_t *status, hipStream_t s);
+                      const ThermoTab *thermo, int n_gas, T *gtab, uint32_t *status, hipStream_t s);
 
 // ---------------------------------------------------------------- k_couple.hip
 struct DepositOut {
@@ -109,11 +111,12 @@ struct ReactArgs {
   const double *eps;
   const BedDev *beds;
   const OreDev *ores;
+  const ThermoTab *thermo;  // energy equation on (null: isothermal at the gas temperature)
   const double *theta;  // 6 values overriding every bed's, or null
   double dt;
   int n;
   int update_mass;
-  double *pm;    // [4][N] per-parcel mdotH2, mdotH2O, EQ, ES
+  double *pm;    // [4][N] per-parcel mdotH2, mdotH2O, EQ, ES (+ [4][N] hA, hA Tp, Qrm, Hr with energy)
   double *pw;    // [2][N] per-parcel w f_ov, w
   double *fov;   // original order (may be null)
   unsigned long long *clamps;
@@ -121,20 +124,24 @@ struct ReactArgs {
 };
 template <typename T>
 void launch_react(const ReactArgs<T> &a, hipStream_t s);
+struct CellSumOut {
+  double *o[8];  // per-cell sums of the pm rows (null: not written)
+  int rows;      // 4, or 8 with the energy equation
+};
 void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t *order, const int32_t *cell_bed,
-                    const BedDev *beds,
-                    int n_gas, double *o0, double *o1, double *o2, double *o3, hipStream_t s);
+                    const BedDev *beds, int n_gas, const CellSumOut &o, hipStream_t s);
 constexpr int kBedChunk = 4096;  // parcels per partial sum of the bed means
 void launch_bedsum(const double *pw, int n, const int32_t *start, const BedDev *beds, int n_beds, int4 *chunks,
                    int max_chunks, double *partial, double *bed_fov, hipStream_t s);
 
 template <typename T>
-void launch_init(const dem_parcels &in, int n, const Phys &ph, int n_ores, const Dyn<T> &d, const Props<T> &p,
-                 uint32_t *status, hipStream_t s);
+void launch_init(const dem_parcels &in, int n, const Phys &ph, int n_ores, const ThermoTab *thermo, const Dyn<T> &d,
+                 const Props<T> &p, uint32_t *status, hipStream_t s);
 template <typename T>
 void launch_export(const Dyn<T> &d, const Props<T> &p, int n, const dem_parcels &out, hipStream_t s);
 template <typename T>
-void launch_import(const dem_parcels &in, int n, const Dyn<T> &d, const Props<T> &p, hipStream_t s);
+void launch_import(const dem_parcels &in, int n, const ThermoTab *thermo, const Dyn<T> &d, const Props<T> &p,
+                   hipStream_t s);
 
 // ---------------------------------------------------------------- k_adjoint.hip
 struct AdjArgs {

@@ -34,9 +34,9 @@ def test_struct_layouts_match_header_sizes():
     # sizes implied by the C declarations (x86-64 / gfx950 host ABI)
     assert C.sizeof(capi.DemBed) == 4 + 4 + 24 + 24 + 8 + 24 + 8 + 12 + 4 + 48 + 8
     assert C.sizeof(capi.DemOre) == 8 * 3 + 32 + 8 + 8
-    assert C.sizeof(capi.DemParcels) == 17 * 8
+    assert C.sizeof(capi.DemParcels) == 18 * 8
     assert C.sizeof(capi.DemGas) == 11 * 8
-    assert C.sizeof(capi.DemSources) == 11 * 8
+    assert C.sizeof(capi.DemSources) == 15 * 8
     assert C.sizeof(capi.DemStats) == 6 * 8 + 8 + 4 + 4 + 8 + 8 + 4 * 4
 
 
