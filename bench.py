@@ -202,6 +202,47 @@ def bench_adjoint(log=True):
             "state": "f32", "accumulation": "f64"}
 
 
+def bench_sweep(log=True):
+    """Kinetic sweep over Bed I / Bed II shaped beds (seven beds, 1.5 M
+    parcels, one context): 500 DEM steps replayed from the graph (coupling
+    every 20), then a 600 s fast-forward of the reaction in 1 s updates with
+    the bed frozen, recording each bed's reduction degree every second."""
+    import numpy as np
+    import torch
+
+    from paper_2311_03908_amd import workloads as W
+    from paper_2311_03908_amd.bed import Bed
+
+    w = W.sweep()
+    S = w.couple_every
+    bed = Bed(w, device="cuda:0")
+    bed.autotune()
+    bed.run(5, S)
+    bed.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bed.run(25, S)
+    bed.sync()
+    torch.cuda.synchronize()
+    t_dem = time.perf_counter() - t0
+    curves = []
+    t0 = time.perf_counter()
+    for _ in range(600):
+        curves.append(bed.react(1.0, keys=(), fov=False)["bed_fov"])
+    torch.cuda.synchronize()
+    t_react = time.perf_counter() - t0
+    bed.close()
+    c = np.array(curves)
+    t90 = [float(np.argmax(c[:, b] >= 0.9) + 1) if np.any(c[:, b] >= 0.9) else None for b in range(c.shape[1])]
+    labels = [f"Bed {k} {T:.0f} K k0=({np.exp(th[2]):.0f},{np.exp(th[4]):.0f})" for k, T, _, th in W.SWEEP_BEDS]
+    if log:
+        _log(f"[bench] sweep: {len(w.beds)} beds, {w.n} parcels: 500 DEM steps {t_dem:.3f} s, "
+             f"600 reaction updates {t_react:.3f} s; f_ov at 60 s {np.round(c[59], 3).tolist()}")
+    return {"beds": labels, "parcels": w.n, "dem_particle_steps_per_s": w.n * 25 * S / t_dem,
+            "react_parcel_updates_per_s": w.n * 600 / t_react, "fov_60s": c[59].tolist(),
+            "fov_300s": c[299].tolist(), "fov_600s": c[599].tolist(), "t90_s": t90}
+
+
 def cpu_baseline(w, S):
     """The oracle as it stands (single thread) on the full bed: two DEM steps
     and one coupling (deposit + reaction), the coupling amortised over S steps."""
@@ -237,8 +278,8 @@ def main():
     ap.add_argument("--save-settled", default=None, help="settle the bed, save its state (.npz) and exit")
     ap.add_argument("--settled", default=None, help="start from a state saved by --save-settled")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched (64-bed) and adjoint (500k-parcel gradient) speedup legs")
-    ap.add_argument("--only", choices=["batched", "adjoint"], default=None,
+                    help="skip the batched (64-bed), adjoint (500k-parcel gradient) and kinetic-sweep legs")
+    ap.add_argument("--only", choices=["batched", "adjoint", "sweep"], default=None,
                     help="run only one speedup leg and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -253,7 +294,8 @@ def main():
     from paper_2311_03908_amd.bed import Bed
 
     if args.only:
-        print(json.dumps(bench_batched() if args.only == "batched" else bench_adjoint()), flush=True)
+        leg = {"batched": bench_batched, "adjoint": bench_adjoint, "sweep": bench_sweep}[args.only]
+        print(json.dumps(leg()), flush=True)
         return
     if args.copy_calibration:
         src = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0").fill_(1.0)
@@ -334,6 +376,7 @@ def main():
     if not args.no_extras:
         out["batched"] = bench_batched()
         out["adjoint"] = bench_adjoint()
+        out["sweep"] = bench_sweep()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, S)
     print(json.dumps(out), flush=True)

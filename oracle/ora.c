@@ -981,6 +981,7 @@ static int react_core(const renv *e, dual sp[4], dual *Q, dual *S, dual xi[3]) {
     if (xi[i].v > lim.v) xi[i] = lim;
   }
   dual n0 = dsub(sp[0], dscale(xi[0], 3.0));
+  if (n0.v < 0.0) n0 = D(0.0); /* a capped extent exhausts Fe2O3; 3 (n/3) may round above n */
   dual n1 = dsub(dadd(sp[1], dscale(xi[0], 2.0)), xi[1]);
   dual n2 = dsub(dadd(sp[2], dscale(xi[1], 3.0)), xi[2]);
   dual n3 = dadd(sp[3], xi[2]);

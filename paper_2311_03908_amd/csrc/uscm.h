@@ -95,7 +95,9 @@ __device__ __forceinline__ int uscm_step(S n[4], const UscmEnv<S> &e, S xi[3], S
     }
     xi[q] = fmin(r[q] * e.cad, n[q] / nu[q]);
   }
+  // an extent at its cap exhausts the reactant: 3 (n/3) may round above n
   n[0] = n[0] - S(3) * xi[0];
+  if (n[0] < S(0)) n[0] = S(0);
   n[1] = n[1] + S(2) * xi[0] - xi[1];
   n[2] = n[2] + S(3) * xi[1] - xi[2];
   n[3] = n[3] + xi[2];

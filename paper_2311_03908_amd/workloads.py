@@ -471,8 +471,69 @@ def cfg5(n_beds=64, seed=5, steps=1000, n_scale=1.0):
     return Workload("cfg5", "mixed", params, beds, [ore], parcels, gas, offs, steps, 20)
 
 
+# Magnetite kinetics: Table 2 (Takenaka) for R1, and for R2 / R3 the
+# activation energies of Section 5.1 with the fitted pre-exponential factors
+# 8 and 6000 m/s (the starting guess 8 and 5000 in THETA_MAGNETITE_START).
+THETA_MAGNETITE_FIT = (math.log(29.17), 66974.0, math.log(8.0), 75345.0, math.log(6000.0), 117204.0)
+THETA_MAGNETITE_START = (math.log(29.17), 66974.0, math.log(8.0), 75345.0, math.log(5000.0), 117204.0)
+
+# (bed, T (K), superficial gas velocity (m/s), kinetic set) of the sweep: the
+# Bed I magnetite temperatures of Fig. 12 with the fitted set, the starting
+# set of Fig. 7 at 943 K, and the Bed II hematite temperatures of Fig. 13
+SWEEP_BEDS = (("I", 943.0, 0.183, THETA_MAGNETITE_FIT), ("I", 923.0, 0.179, THETA_MAGNETITE_FIT),
+              ("I", 903.0, 0.175, THETA_MAGNETITE_FIT), ("I", 943.0, 0.183, THETA_MAGNETITE_START),
+              ("II", 1073.0, 0.43, THETA_HEMATITE_FIT), ("II", 1023.0, 0.41, THETA_HEMATITE_FIT),
+              ("II", 973.0, 0.39, THETA_HEMATITE_FIT))
+
+
+def sweep(n_scale=1.0, seed=6, steps=500, beds=SWEEP_BEDS):
+    """Kinetic sweep over Bed I / Bed II shaped beds in one batched context
+    (Table 3).  Bed I: magnetite ore (69.94 % Fe3O4, 30.06 % FeO, rho_p0 3720,
+    porosity 0.29, pore 9.5e-6 cm, sphericity 0.85), real d_p 0.1 mm (+-10 %),
+    k = 2.8, 5,140,800 real particles in a 20 x 60 mm cylinder, 1.25 mm gas
+    cells, 70 % H2 in N2 at 101325 Pa.  Bed II: hematite ore (96.28 % Fe2O3,
+    3.72 % FeO, rho_p0 3500, porosity 0.34, pore 3.3e-6 cm, sphericity 0.86),
+    d_p 0.35 mm (+-10 %), k = 3, 5,095,837 real particles in a 68 x 200 mm
+    cylinder, 4.25 mm gas cells, 65 % H2 in N2 at 110000 Pa.  n_scale scales
+    the parcel counts (and the cylinders by its cube root).  One DEM step of
+    5 us for all beds (Bed I's), coupling every 20 steps; kn = 100 N/m, the
+    linear stiffness a Hertzian contact with Y = 1e7 Pa gives the Bed I
+    parcels at 1 % overlap."""
+    ss = np.random.SeedSequence(seed)
+    kids = ss.spawn(len(beds) + 1)
+    ores = [Ore(xi0=0.29, d_pore_cm=9.5e-6, kind=ORE_MAGNETITE, psi=0.85),
+            Ore(xi0=0.34, d_pore_cm=3.3e-6, kind=ORE_HEMATITE, psi=0.86)]
+    shape = {"I": dict(R=10e-3, H=60e-3, h=1.25e-3, dp=0.1e-3, k=2.8, real=5_140_800, ore=0, rho=3720.0,
+                       wt=MAGNETITE_WT, xh2=0.7, p=101325.0),
+             "II": dict(R=34e-3, H=200e-3, h=4.25e-3, dp=0.35e-3, k=3.0, real=5_095_837, ore=1, rho=3500.0,
+                        wt=HEMATITE_WT, xh2=0.65, p=110000.0)}
+    s = n_scale ** (1.0 / 3.0)
+    bl, parts, gases = [], [], []
+    for b, (kind, T, u, theta) in enumerate(beds):
+        sh = shape[kind]
+        rng = np.random.Generator(np.random.PCG64(kids[b]))
+        n = max(16, int(round(sh["real"] / sh["k"] ** 3 * n_scale)))
+        bed = _cyl_bed(sh["R"] * s, sh["H"] * s, sh["h"], 3, theta)
+        d_p = rng.uniform(0.9 * sh["dp"], 1.1 * sh["dp"], n).astype(np.float32).astype(np.float64)
+        cx = 0.5 * (bed.lo[0] + bed.hi[0])
+        cy = 0.5 * (bed.lo[1] + bed.hi[1])
+        pos = _layer_pack(rng, sh["k"] * d_p, bed.R, cx, cy, 0.0, classes=4)
+        if pos[:, 2].max() + 0.5 * sh["k"] * d_p.max() > bed.hi[2]:
+            raise RuntimeError("packed bed higher than the container")
+        pc = _parcels(pos, d_p, sh["k"], np.full(n, sh["ore"]), np.full(n, b), {sh["ore"]: sh["rho"]},
+                      {sh["ore"]: sh["wt"]})
+        bl.append(bed)
+        parts.append(_shuffle_ids(rng, pc))
+        gases.append(_gas(rng, [bed], T, sh["xh2"], 0.0, (0.0, 0.0, u), 0.1 * u, True, p=sh["p"]))
+    parcels = {k: np.ascontiguousarray(np.concatenate([p[k] for p in parts])) for k in parts[0]}
+    gas = {k: np.ascontiguousarray(np.concatenate([g[k] for g in gases])) for k in gases[0]}
+    offs = np.concatenate([[0], np.cumsum([bd.n_cells for bd in bl])[:-1]])
+    params = base_params(dt=5e-6, skin=1e-4, rebuild_every=10, kn=100.0)
+    return Workload("sweep", "mixed", params, bl, ores, parcels, gas, offs, steps, 20)
+
+
 def make(name: str, **kw) -> Workload:
-    return {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4, "cfg5": cfg5}[name](**kw)
+    return {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4, "cfg5": cfg5, "sweep": sweep}[name](**kw)
 
 
 def with_velocities(w: Workload, seed: int, vscale=0.05, wscale=50.0) -> Workload:
