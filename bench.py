@@ -234,7 +234,8 @@ def bench_sweep(log=True):
     bed.close()
     c = np.array(curves)
     t90 = [float(np.argmax(c[:, b] >= 0.9) + 1) if np.any(c[:, b] >= 0.9) else None for b in range(c.shape[1])]
-    labels = [f"Bed {k} {T:.0f} K k0=({np.exp(th[2]):.0f},{np.exp(th[4]):.0f})" for k, T, _, th in W.SWEEP_BEDS]
+    labels = [f"Bed {k} {T:.0f} K k0=({np.exp(th[0]):.4g},{np.exp(th[2]):.4g},{np.exp(th[4]):.4g})"
+              for k, T, _, th in W.SWEEP_BEDS]
     if log:
         _log(f"[bench] sweep: {len(w.beds)} beds, {w.n} parcels: 500 DEM steps {t_dem:.3f} s, "
              f"600 reaction updates {t_react:.3f} s; f_ov at 60 s {np.round(c[59], 3).tolist()}")

@@ -207,3 +207,25 @@ class Bed:
 
     def sync(self):
         self._check(self.L.dem_sync(self.h))
+
+
+class ReductionDegree(torch.autograd.Function):
+    """J(theta), the bed-mean reduction degree after the gradient protocol of
+    ``spec`` (n_substeps, dt_react, dyn_every, ckpt_every[, state_fp32]), as a
+    differentiable function of the six kinetic parameters theta = (ln k0_i,
+    E_a,i): forward runs dem_grad (forward sweep with checkpoints and the
+    adjoint sweep) and keeps the gradient; backward returns gJ * dJ/dtheta.
+    theta is a float64 tensor of 6 values; J is returned on its device."""
+
+    @staticmethod
+    def forward(ctx, theta, bed, spec):
+        th = theta.detach().to("cpu", torch.float64).numpy()
+        J, g = bed.grad(spec["n_substeps"], spec["dt_react"], spec["dyn_every"], spec["ckpt_every"], th,
+                        state_fp32=spec.get("state_fp32", True))
+        ctx.save_for_backward(torch.as_tensor(g, dtype=theta.dtype, device=theta.device))
+        return theta.new_tensor(J)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        (g,) = ctx.saved_tensors
+        return gJ * g, None, None

@@ -132,3 +132,37 @@ def test_grad_bad_spec():
     with pytest.raises(DemError):
         bed.grad(10, 0.1, 10, 10, [float("nan")] + list(TH[1:]))
     bed.close()
+
+
+def test_reduction_degree_autograd_function():
+    """torch.autograd.Function over dem_grad: J and dJ/dtheta through
+    backward() equal a direct dem_grad call; a few gradient steps on ln k0 of
+    R3 move J towards a target value."""
+    from paper_2311_03908_amd.bed import ReductionDegree
+
+    w = _w("cfg2", 1500, precision="mixed")
+    bed = Bed(w)
+    spec = dict(n_substeps=60, dt_react=0.2, dyn_every=10, ckpt_every=20, state_fp32=False)
+    theta = torch.tensor(TH, dtype=torch.float64, requires_grad=True)
+    J = ReductionDegree.apply(theta, bed, spec)
+    J.backward()
+    Jd, gd = bed.grad(60, 0.2, 10, 20, TH, state_fp32=False)
+    assert float(J.detach()) == Jd
+    assert np.array_equal(theta.grad.numpy(), gd)
+    # calibration as in Section 5.1.1, as gradient descent on (J - target)^2
+    target = Jd + 0.02
+    th = torch.tensor(TH, dtype=torch.float64, requires_grad=True)
+    mask = torch.zeros(6, dtype=torch.float64)
+    mask[4] = 1.0  # ln k0 of FeO -> Fe
+    loss0 = None
+    for _ in range(4):
+        Jt = ReductionDegree.apply(th, bed, spec)
+        loss = (Jt - target) ** 2
+        if loss0 is None:
+            loss0 = float(loss.detach())
+        th.grad = None
+        loss.backward()
+        with torch.no_grad():
+            th -= 0.5 * mask * th.grad / max(float(th.grad[4] ** 2), 1e-300) * float(loss.detach())
+    assert float(loss.detach()) < 0.5 * loss0
+    bed.close()
