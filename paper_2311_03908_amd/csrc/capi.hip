@@ -387,7 +387,6 @@ struct Ctx final : dem_ctx {
     NbrBuild<T> a;
     a.d = dyn[cur];
     a.p = pr[pc];
-    a.pos_old = dyn[cur ^ 1].pos;
     a.perm = perm;
     a.nb_new = nb[nbc ^ 1];
     a.nb_old = nb[nbc];

@@ -103,9 +103,18 @@ template <typename T>
 struct alignas(sizeof(T) * 4) Quad {
   T x, y, z, w;
 };
-// Tangential spring of one contact slot (w unused)
+// Tangential spring of one contact slot; w carries the partner's original id
+// (bit pattern in FP32, exact value in FP64) so that a rebuild can match it
 template <typename T>
 using Spring = Quad<T>;
+template <typename T>
+__device__ __forceinline__ T spring_tag(uint32_t id);
+template <>
+__device__ __forceinline__ float spring_tag<float>(uint32_t id) { return __uint_as_float(id); }
+template <>
+__device__ __forceinline__ double spring_tag<double>(uint32_t id) { return (double)id; }
+__device__ __forceinline__ uint32_t spring_partner(float w) { return __float_as_uint(w); }
+__device__ __forceinline__ uint32_t spring_partner(double w) { return (uint32_t)w; }
 
 // Neighbour list (slot-major) with the pair tangential springs of each slot
 template <typename T>

@@ -271,11 +271,12 @@ void launch_items(const Item *items, int n_items, const BedDev *beds, const int3
 // exact contacts) fill slots cap-1, cap-2, ... downwards, the others fill
 // slots 0, 1, ... upwards; cnt packs (near << 16) | far.  The tangential
 // springs of partners in contact before the rebuild are carried over to the
-// near slots by matching original ids (held in registers for up to kCarry
-// old contacts; more fall back to a gather loop).
+// near slots by matching original ids, which every spring record carries
+// (read into registers for up to kCarry old contacts; more fall back to a
+// gather loop).
 constexpr int kCandMax = 2048;
 constexpr int kBuildThreads = 512;
-constexpr int kCarry = 12;
+constexpr int kCarry = 8;  // 78 VGPRs: three 512-thread blocks per CU
 constexpr float kNear = 1.0f + 1e-4f;
 
 template <typename T>
@@ -355,7 +356,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
             const int q = __ffsll((unsigned long long)b) - 1;
             b &= b - 1;
             oslot[k] = q;
-            oid[k] = a.pos_old[a.nb_old.idx[(long)q * N + po]].id;
+            oid[k] = spring_partner(a.nb_old.hist[(long)q * N + po].w);
           }
         }
         orest = b;
@@ -439,7 +440,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
                     if (oid[k] == idn) qo = oslot[k];
                   for (uint64_t b = orest; b && qo < 0; b &= b - 1) {
                     const int q2 = __ffsll((unsigned long long)b) - 1;
-                    if (a.pos_old[a.nb_old.idx[(long)q2 * N + po]].id == idn) qo = q2;
+                    if (spring_partner(a.nb_old.hist[(long)q2 * N + po].w) == idn) qo = q2;
                   }
                   if (qo >= 0) {
                     a.nb_new.hist[(long)sl * N + i] = a.nb_old.hist[(long)qo * N + po];

@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 1) k_step(StepArgs<T
         for (int c = 0; c < 3; c++) Tq[c] -= T(a.ph.mu_r) * fnabs * Vi.w[c] / wmag;
       }
       if (a.mode == 0) {
-        a.nb.hist[(long)s * N + i] = Spring<T>{xo[0], xo[1], xo[2], T(0)};
+        a.nb.hist[(long)s * N + i] = Spring<T>{xo[0], xo[1], xo[2], spring_tag<T>(Q.id)};
       }
       n_pp++;
     };

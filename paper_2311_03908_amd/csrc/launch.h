@@ -39,7 +39,6 @@ template <typename T>
 struct NbrBuild {
   Dyn<T> d;             // new sorted state
   Props<T> p;           // new sorted properties
-  const PosRec *pos_old;  // position records before the permutation (partner ids)
   const int32_t *perm;  // new position -> old position
   Nbr<T> nb_new, nb_old;
   const BedDev *beds;
