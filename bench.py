@@ -371,7 +371,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                      "kernel": "k_step (fused contact + drag + integrate)", "bytes_per_parcel_step": bpu,
-                     "kernel_ms": k_ms, "launches_timed": st["step_kernel_launches"], "z_mean": z},
+                     "kernel_ms": k_ms, "launches_timed": st["step_kernel_launches"], "z_mean": z,
+                     "launch": {"step_block": st["step_block"], "step_xcd_chunk": st["step_xcd"],
+                                "build_grid": st["build_grid"], "rebuild_period": st["rebuild_period"]}},
     }
     bed.close()
     if not args.no_extras:

@@ -49,25 +49,13 @@ __device__ __forceinline__ void cross(const T a[3], const T b[3], T c[3]) {
   c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// The DEM step of parcel i (sorted index): contacts over its candidate list,
+// walls, body and gas forces, integration.  Accumulates the displacement
+// maximum and the contact counts of the calling thread.
 template <typename T>
-__global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 1) k_step(StepArgs<T> a) {
-  const int i = (a.xcd > 1 ? xcd_block(a.xcd) : (int)blockIdx.x) * blockDim.x + threadIdx.x;
-  if (a.mode == 0 && blockIdx.x == 0 && threadIdx.x < 64) {
-    // largest displacement of any parcel since the last rebuild, up to the
-    // positions this step starts from (the previous step's wave maxima are
-    // complete); the candidate lists hold every pair while it is below skin/2
-    unsigned *src = a.dslot + ((a.par ^ 1) * kSlots + threadIdx.x) * kSlotPad;
-    float d2 = __uint_as_float(*src);
-    *src = 0u;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) d2 = fmaxf(d2, __shfl_xor(d2, o, 64));
-    const float lim = 0.5f * (float)a.ph.skin - 1e-7f;  // FP32 reference positions
-    if (threadIdx.x == 0 && d2 > lim * lim) atomicOr(a.status, ST_SKIN);
-  }
+__device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, float &dmax2, int &n_pp, int &n_w) {
   const long N = a.n;
-  float dmax2 = 0.0f;
-  int n_pp = 0, n_w = 0;
-  if (i < a.n) {
+  {
     const PosRec P = load_pos(a.in.pos, i);
     const VelRec<T> Vi = a.in.vel[i];
     const double xi = P.x, yi = P.y, zi = P.z;
@@ -275,16 +263,20 @@ __global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 1) k_step(StepArgs<T
       const float v2 = (float)(Vo.v[0] * Vo.v[0] + Vo.v[1] * Vo.v[1] + Vo.v[2] * Vo.v[2]);
       const float4 xr = a.xref[i];
       const float ex = (float)Po.x - xr.x, ey = (float)Po.y - xr.y, ez = (float)Po.z - xr.z;
-      dmax2 = ex * ex + ey * ey + ez * ez;
+      dmax2 = fmaxf(dmax2, ex * ex + ey * ey + ez * ez);
       if (!(isfinite(Po.x) && isfinite(Po.y) && isfinite(Po.z) && isfinite(v2) &&
             isfinite((float)(Vo.w[0] + Vo.w[1] + Vo.w[2]))))
         atomicOr(a.status, ST_NONFINITE);
     }
   }
+}
+
+// Wave maximum of the displacement and the contact counts, one no-return
+// atomic per wave into one of kSlots padded slots (so waves rarely contend
+// and retire independently, with no block barrier)
+template <typename T>
+__device__ __forceinline__ void step_flush(const StepArgs<T> &a, float dmax2, int n_pp, int n_w) {
   if (a.mode != 0) return;
-  // wave maximum of the displacement and the contact counts, one no-return
-  // atomic per wave into one of kSlots padded slots (so waves rarely contend
-  // and retire independently, with no block barrier)
   float m = dmax2;
   int c0 = n_pp, c1 = n_w;
 #pragma unroll
@@ -301,6 +293,33 @@ __global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 1) k_step(StepArgs<T
       if (c1) atomicAdd(a.cslot + sl * kSlotPad64 + 1, (unsigned long long)c1);
     }
   }
+}
+
+// Largest displacement of any parcel since the last rebuild, up to the
+// positions this step starts from (the previous step's wave maxima are
+// complete): the candidate lists hold every pair while it is below skin/2
+template <typename T>
+__device__ __forceinline__ void step_skin_check(const StepArgs<T> &a) {
+  if (a.mode == 0 && blockIdx.x == 0 && threadIdx.x < 64) {
+    unsigned *src = a.dslot + ((a.par ^ 1) * kSlots + threadIdx.x) * kSlotPad;
+    float d2 = __uint_as_float(*src);
+    *src = 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) d2 = fmaxf(d2, __shfl_xor(d2, o, 64));
+    const float lim = 0.5f * (float)a.ph.skin - 1e-7f;  // FP32 reference positions
+    if (threadIdx.x == 0 && d2 > lim * lim) atomicOr(a.status, ST_SKIN);
+  }
+}
+
+// One thread per parcel over the sorted order.
+template <typename T>
+__global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 1) k_step(StepArgs<T> a) {
+  const int i = (a.xcd > 1 ? xcd_block(a.xcd) : (int)blockIdx.x) * blockDim.x + threadIdx.x;
+  step_skin_check(a);
+  float dmax2 = 0.0f;
+  int n_pp = 0, n_w = 0;
+  if (i < a.n) step_parcel(a, i, dmax2, n_pp, n_w);
+  step_flush(a, dmax2, n_pp, n_w);
 }
 
 template <typename T>
