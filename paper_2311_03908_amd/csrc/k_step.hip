@@ -150,17 +150,26 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
       for (int k = 0; k < kPre; k++)
         if (jj[k] >= 0) pair(cap - 1 - t0 - k, jj[k], Qs[k]);
     }
-    for (int t0 = 0; t0 < c_far; t0 += kPre) {
-      int jj[kPre];
-      PosRec Qs[kPre];
+    {
+      // far region: the next group's indices are requested while the
+      // current group's position records are in flight
+      int jn[kPre];
 #pragma unroll
-      for (int k = 0; k < kPre; k++) jj[k] = (t0 + k < c_far) ? a.nb.idx[(long)(t0 + k) * N + i] : -1;
+      for (int k = 0; k < kPre; k++) jn[k] = (k < c_far) ? a.nb.idx[(long)k * N + i] : -1;
+      for (int t0 = 0; t0 < c_far; t0 += kPre) {
+        int jj[kPre];
+        PosRec Qs[kPre];
 #pragma unroll
-      for (int k = 0; k < kPre; k++)
-        if (jj[k] >= 0) Qs[k] = load_pos(a.in.pos, jj[k]);
+        for (int k = 0; k < kPre; k++) jj[k] = jn[k];
 #pragma unroll
-      for (int k = 0; k < kPre; k++)
-        if (jj[k] >= 0) pair(t0 + k, jj[k], Qs[k]);
+        for (int k = 0; k < kPre; k++)
+          if (jj[k] >= 0) Qs[k] = load_pos(a.in.pos, jj[k]);
+#pragma unroll
+        for (int k = 0; k < kPre; k++) jn[k] = (t0 + kPre + k < c_far) ? a.nb.idx[(long)(t0 + kPre + k) * N + i] : -1;
+#pragma unroll
+        for (int k = 0; k < kPre; k++)
+          if (jj[k] >= 0) pair(t0 + k, jj[k], Qs[k]);
+      }
     }
     mnew = cbits;
     // walls, gravity, pressure gradient and drag, against the parcel's bed
