@@ -201,6 +201,25 @@ int dem_couple(dem_ctx *c, const dem_gas *g, dem_sources *out);
 int dem_react(dem_ctx *c, double dt_cfd, const dem_gas *g, dem_sources *out, double *bed_fov,
               double *fov);
 
+/* Gas-side step of the two-way coupling for species (eq. e3-40 with the
+ * semi-implicit sources of eqs. e4-9..e4-11), on the frozen flow of g: one
+ * explicit step dt of H2 and H2O by first-order upwind convection along z
+ * (face velocity the mean of the two cells' wg; xin = true mole fractions of
+ * H2 and H2O (host, 2 doubles) entering through each bed's floor; zero
+ * gradient at the lid), with the particle sources of the last dem_react:
+ * H2 semi-implicit through C0 = sumEQ / V_cell and C1 = -(M_H2 / R) sumES /
+ * V_cell, the H2 taken returned as H2O one to one in moles.  eps_g is the
+ * voidage of the last deposit; T and p stay frozen.  Molecular and
+ * pseudo-turbulent diffusion and the momentum and energy coupling belong to
+ * the gas solver and are not modelled.  sumEQ, sumES: device, one double per
+ * gas cell (as written by dem_react).  Writes the new true mole fractions to
+ * xH2, xH2O, xN2 (device, one double per cell, distinct from g's arrays; the
+ * caller copies them into its gas fields for the next interval).  A Courant
+ * number |w| dt / h above one is reported as EINVAL by the next
+ * synchronising call.  Errors: EINVAL (nulls, dt <= 0, xin outside [0, 1]). */
+int dem_gas_species(dem_ctx *c, double dt, const dem_gas *g, const double *sumEQ, const double *sumES,
+                    const double xin[2], double *xH2, double *xH2O, double *xN2);
+
 /* Gradient of the bed-mean reduction degree J (all parcels, weight k^3 N_Fe)
  * after the protocol of spec with respect to theta (used for every bed) by a
  * reverse (adjoint) sweep with checkpointing; grad may be NULL for a plain

@@ -1185,3 +1185,87 @@ void ora_get_energy(const ora_sys *s, double *Tp, double *qrx, double *mcp) {
     if (mcp) mcp[i] = s->mcp[i];
   }
 }
+
+/* ------------------------------------------------------------ gas species (two-way coupling)
+ * One explicit step dt of H2 and H2O transport (eq. e3-40 with eqs. e4-9..e4-11)
+ * on the frozen flow: reading: first-order upwind convection along z only (no
+ * molecular or pseudo-turbulent diffusion), face velocity the mean of the two
+ * cells' w, the inlet composition xin entering through each bed's bottom face,
+ * zero gradient at the top; the H2 source semi-implicit through
+ * C0 = sum(k^3 E Q)/V_cell and C1 = -(M_H2/R) sum(k^3 E S)/V_cell; the H2O
+ * source the H2 taken, converted 1:1 in moles (Table 1); eps_g the voidage of
+ * the last deposit, T and p frozen.  Outputs the new true mole fractions. */
+void ora_gas_species(const ora_sys *s, const ora_gas *g, double dt, const double *sumEQ,
+                     const double *sumES, const double xin[2], double *xh2_out, double *xh2o_out,
+                     double *xn2_out) {
+  for (int b = 0; b < s->P.n_beds; b++) {
+    const ora_bed *B = &s->beds[b];
+    int nx = B->n[0], ny = B->n[1], nz = B->n[2];
+    double V = B->h * B->h * B->h;
+    for (int iz = 0; iz < nz; iz++)
+      for (int iy = 0; iy < ny; iy++)
+        for (int ix = 0; ix < nx; ix++) {
+          int c = B->cell_off + ix + nx * (iy + ny * iz);
+          /* partial densities eps rho Y_j (kg/m3 of cell) of H2, H2O, N2 in a cell
+           * with composition x (true mole fractions), at the cell's T, p */
+          double u[3], flux_lo[3], flux_hi[3];
+          for (int side = 0; side < 3; side++) {
+            /* side 0: this cell; side 1: the cell below (or the inlet); side 2: above */
+            int cc = c;
+            double x[3];
+            if (side == 1) cc = iz > 0 ? c - nx * ny : -1;
+            if (side == 2) cc = iz < nz - 1 ? c + nx * ny : -1;
+            if (cc < 0 && side == 1) {
+              x[0] = xin[0]; x[1] = xin[1]; x[2] = 1.0 - xin[0] - xin[1];
+              cc = c;
+            } else {
+              if (cc < 0) cc = c; /* top: zero gradient */
+              x[0] = g->xH2[cc]; x[1] = g->xH2O[cc]; x[2] = g->xN2[cc];
+            }
+            double Mg = 0.0;
+            for (int j = 0; j < 3; j++) Mg += x[j] * MG[j];
+            double rho = g->p[cc] * Mg * 1e-3 / (RG * g->T[cc]); /* eq. e3-53 */
+            double e = s->eps[cc];
+            double pd[3];
+            for (int j = 0; j < 3; j++) pd[j] = e * rho * x[j] * MG[j] / Mg;
+            if (side == 0) for (int j = 0; j < 3; j++) u[j] = pd[j];
+            if (side == 1) {
+              double wf = iz > 0 ? 0.5 * (g->wg[c - nx * ny] + g->wg[c]) : g->wg[c];
+              for (int j = 0; j < 3; j++) flux_lo[j] = wf * (wf >= 0.0 ? pd[j] : 0.0);
+            }
+            if (side == 2) {
+              double wf = iz < nz - 1 ? 0.5 * (g->wg[c] + g->wg[c + nx * ny]) : g->wg[c];
+              for (int j = 0; j < 3; j++) flux_hi[j] = wf * (wf < 0.0 ? pd[j] : 0.0);
+            }
+          }
+          /* upwind: the lower face carries the lower state upwards (w >= 0) or
+           * this cell's state downwards; the upper face the reverse */
+          {
+            double wl = iz > 0 ? 0.5 * (g->wg[c - nx * ny] + g->wg[c]) : g->wg[c];
+            double wu = iz < nz - 1 ? 0.5 * (g->wg[c] + g->wg[c + nx * ny]) : g->wg[c];
+            for (int j = 0; j < 3; j++) {
+              if (wl < 0.0) flux_lo[j] = wl * u[j];
+              if (wu >= 0.0) flux_hi[j] = wu * u[j];
+            }
+          }
+          double rhs[3];
+          for (int j = 0; j < 3; j++) rhs[j] = u[j] - dt / B->h * (flux_hi[j] - flux_lo[j]);
+          /* H2 semi-implicit (eq. e4-9): u1' (1 - dt C0 T / (X eps)) = rhs1 + dt C1 p */
+          double x1 = g->xH2[c], x2 = g->xH2O[c];
+          double X = x1 + x2;
+          double C0 = sumEQ[c] / V, C1 = -(MG[0] * 1e-3 / RG) * sumES[c] / V;
+          double e = s->eps[c];
+          double u1 = rhs[0] + dt * C1 * g->p[c];
+          if (X > 0.0) u1 = u1 / (1.0 - dt * C0 * g->T[c] / (X * e));
+          if (u1 < 0.0) u1 = 0.0;
+          /* H2 taken by the particles over dt (kg/m3), returned as H2O */
+          double taken = rhs[0] - u1;
+          double u2 = rhs[1] + taken * MG[1] / MG[0];
+          double u3 = rhs[2];
+          double n1 = u1 / MG[0], n2 = u2 / MG[1], n3 = u3 / MG[2], nt = n1 + n2 + n3;
+          xh2_out[c] = n1 / nt;
+          xh2o_out[c] = n2 / nt;
+          xn2_out[c] = n3 / nt;
+        }
+  }
+}

@@ -99,6 +99,14 @@ void ora_get(const ora_sys *s, double *x, double *y, double *z, double *vx, doub
 void ora_grad(ora_sys *s, const ora_gas *g, int n_sub, double dt_react, int dyn_every,
               const double theta[6], double *J, double grad[6]);
 
+/* two-way coupling stand-in: one explicit step dt of H2 / H2O transport on the
+ * frozen flow (upwind along z, inlet composition xin = (x_H2, x_H2O) at each bed's
+ * floor) with the particle sources of the last ora_react (semi-implicit H2 through
+ * sums of k^3 E Q and k^3 E S, eqs. e4-9..e4-11); new true mole fractions out */
+void ora_gas_species(const ora_sys *s, const ora_gas *g, double dt, const double *sumEQ,
+                     const double *sumES, const double xin[2], double *xh2_out, double *xh2o_out,
+                     double *xn2_out);
+
 /* ---- point functions, exported for the pins ---- */
 double ora_e_cgp(double e_p, double k);
 double ora_zeta(double e);

@@ -83,6 +83,7 @@ def lib():
         for name in ("ora_lambda_g", "ora_cp_g"):
             getattr(L, name).restype = C.c_double
             getattr(L, name).argtypes = [C.c_double] * 4
+        L.ora_gas_species.argtypes = [C.c_void_p, C.POINTER(OraGas), C.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
         L.ora_nusselt.restype = C.c_double
         L.ora_nusselt.argtypes = [C.c_double] * 3
         L.ora_get.argtypes = [C.c_void_p] + [_dp] * 15
@@ -223,6 +224,15 @@ class Oracle:
         out["bed_fov"] = bf
         out["clamps"] = int(cl)
         return out
+
+    def gas_species(self, dt, sumEQ, sumES, xin):
+        """New (xH2, xH2O, xN2) per cell after one transport step (see ora_gas_species)."""
+        out = [np.zeros(self.n_cells) for _ in range(3)]
+        eq = np.ascontiguousarray(sumEQ, dtype=np.float64)
+        es = np.ascontiguousarray(sumES, dtype=np.float64)
+        xi = np.ascontiguousarray(xin, dtype=np.float64)
+        lib().ora_gas_species(self.h, C.byref(self._gs), float(dt), _p(eq), _p(es), _p(xi), *[_p(o) for o in out])
+        return {"xH2": out[0], "xH2O": out[1], "xN2": out[2]}
 
     def grad(self, n_sub, dt_react, dyn_every, theta):
         if self.energy:

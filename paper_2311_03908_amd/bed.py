@@ -136,6 +136,20 @@ class Bed:
             out["fov"] = fv
         return out
 
+    def gas_species(self, dt, sources, xin, update=True):
+        """One gas-side species step (dem_gas_species) from the sumEQ / sumES of
+        a previous react(); returns the new mole fractions and, with update,
+        copies them into this bed's gas fields."""
+        out = {k: torch.zeros(self.n_cells, dtype=torch.float64, device=self.device) for k in ("xH2", "xH2O", "xN2")}
+        xi = (C.c_double * 2)(float(xin[0]), float(xin[1]))
+        self._check(self.L.dem_gas_species(self.h, float(dt), C.byref(self._gas), _ptr(sources["sumEQ"]),
+                                           _ptr(sources["sumES"]), xi, _ptr(out["xH2"]), _ptr(out["xH2O"]),
+                                           _ptr(out["xN2"])))
+        if update:
+            for k in out:
+                self.gas_t[k].copy_(out[k])
+        return out
+
     def forces(self):
         F = torch.zeros(3 * self.n, dtype=torch.float64, device=self.device)
         T = torch.zeros(3 * self.n, dtype=torch.float64, device=self.device)

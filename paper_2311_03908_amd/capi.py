@@ -77,8 +77,8 @@ class DemStats(C.Structure):
                 ("rebuild_period", C.c_int32)]
 
 
-EXPORTS = ("dem_init", "dem_step", "dem_couple", "dem_react", "dem_grad", "dem_forces", "dem_get_state",
-           "dem_set_state", "dem_pairs", "dem_get_stats", "dem_run", "dem_autotune", "dem_profile", "dem_sync",
+EXPORTS = ("dem_init", "dem_step", "dem_couple", "dem_react", "dem_gas_species", "dem_grad", "dem_forces",
+           "dem_get_state", "dem_set_state", "dem_pairs", "dem_get_stats", "dem_run", "dem_autotune", "dem_profile", "dem_sync",
            "dem_last_error", "dem_destroy")
 
 _lib = None
@@ -107,6 +107,7 @@ def load(path: str = LIB_PATH):
     L.dem_step.argtypes = [vp, C.c_int32, C.POINTER(DemGas)]
     L.dem_couple.argtypes = [vp, C.POINTER(DemGas), C.POINTER(DemSources)]
     L.dem_react.argtypes = [vp, C.c_double, C.POINTER(DemGas), C.POINTER(DemSources), C.POINTER(C.c_double), vp]
+    L.dem_gas_species.argtypes = [vp, C.c_double, C.POINTER(DemGas), vp, vp, C.POINTER(C.c_double), vp, vp, vp]
     L.dem_grad.argtypes = [vp, C.POINTER(DemGradSpec), C.POINTER(DemGas), C.POINTER(C.c_double),
                            C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.dem_forces.argtypes = [vp, C.POINTER(DemGas), vp, vp]

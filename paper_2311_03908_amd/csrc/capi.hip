@@ -23,6 +23,8 @@ struct dem_ctx {
   virtual int step(int n, const dem_gas *g) = 0;
   virtual int couple(const dem_gas *g, dem_sources *o) = 0;
   virtual int react(double dt, const dem_gas *g, dem_sources *o, double *bed_fov, double *fov) = 0;
+  virtual int gas_species(double dt, const dem_gas *g, const double *eq, const double *es, const double *xin,
+                          double *x1, double *x2, double *x3) = 0;
   virtual int forces(const dem_gas *g, double *F, double *T) = 0;
   virtual int get_state(dem_parcels *o) = 0;
   virtual int set_state(const dem_parcels *in) = 0;
@@ -584,6 +586,17 @@ struct Ctx final : dem_ctx {
     return DEMRX_OK;
   }
 
+  int gas_species(double dt, const dem_gas *g, const double *eq, const double *es, const double *xin, double *x1,
+                  double *x2, double *x3) override {
+    if (!gas_ok(g) || !eq || !es || !xin || !x1 || !x2 || !x3) return fail(DEMRX_EINVAL, "null argument");
+    if (!(dt > 0.0) || !(xin[0] >= 0.0) || !(xin[1] >= 0.0) || !(xin[0] + xin[1] <= 1.0))
+      return fail(DEMRX_EINVAL, "dt must be positive and xin fractions in [0, 1] with sum <= 1");
+    TRY(ensure_dep());
+    launch_gas_species(gas_args(g), eps, cell_bed, beds, n_gas, dt, eq, es, xin[0], xin[1], x1, x2, x3, status, st);
+    HIPCHK(hipGetLastError());
+    return DEMRX_OK;
+  }
+
   int forces(const dem_gas *g, double *F, double *Tq) override {
     if (!gas_ok(g) || !F || !Tq) return fail(DEMRX_EINVAL, "null argument");
     if (!built || steps_since >= P.rebuild_every) TRY(rebuild());
@@ -952,6 +965,10 @@ int dem_step(dem_ctx *c, int32_t n, const dem_gas *g) { return c ? c->step(n, g)
 int dem_couple(dem_ctx *c, const dem_gas *g, dem_sources *o) { return c ? c->couple(g, o) : DEMRX_EINVAL; }
 int dem_react(dem_ctx *c, double dt, const dem_gas *g, dem_sources *o, double *bed_fov, double *fov) {
   return c ? c->react(dt, g, o, bed_fov, fov) : DEMRX_EINVAL;
+}
+int dem_gas_species(dem_ctx *c, double dt, const dem_gas *g, const double *sumEQ, const double *sumES,
+                    const double xin[2], double *xH2, double *xH2O, double *xN2) {
+  return c ? c->gas_species(dt, g, sumEQ, sumES, xin, xH2, xH2O, xN2) : DEMRX_EINVAL;
 }
 int dem_grad(dem_ctx *c, const dem_grad_spec *s, const dem_gas *g, const double theta[6], double *J, double *grad) {
   return c ? c->grad(s, g, theta, J, grad) : DEMRX_EINVAL;

@@ -530,6 +530,84 @@ void launch_import(const dem_parcels &in, int n, const ThermoTab *thermo, const 
   k_import<T><<<(n + 255) / 256, 256, 0, s>>>(in, n, thermo, d, p);
 }
 
+// ------------------------------------------------------------------ gas species
+// Gas-side step of the two-way coupling: H2 and H2O transported on the frozen
+// flow (eq. e3-40) by first-order upwind convection along z, with the
+// particle sources of the last reaction update: H2 semi-implicit through the
+// C0, C1 of eqs. e4-9..e4-11, the H2 taken returned as H2O one to one in
+// moles.  One thread per gas cell; reads the old fractions, writes new ones.
+struct GasPartial {
+  double v[3];  // eps_g rho_g Y_j of H2, H2O, N2 (kg per m3 of cell)
+};
+__device__ __forceinline__ GasPartial gas_partial(double eps, double T, double p, double x1, double x2, double x3) {
+  const double M[3] = {2.016e-3, 18.015e-3, 28.013e-3};  // kg/mol
+  GasPartial g;
+  // eps rho Y_j = eps p x_j M_j / (R T) (eq. e3-53 with Y_j = x_j M_j / M_g)
+  const double c = eps * p / (kRg * T);
+  g.v[0] = c * x1 * M[0];
+  g.v[1] = c * x2 * M[1];
+  g.v[2] = c * x3 * M[2];
+  return g;
+}
+
+__global__ void k_gas_species(GasArgs g, const double *eps, const int32_t *cell_bed, const BedDev *beds, int n_gas,
+                              double dt, const double *sumEQ, const double *sumES, double xin1, double xin2,
+                              double *o1, double *o2, double *o3, uint32_t *status) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_gas) return;
+  const BedDev &B = beds[cell_bed[c]];
+  const int q = c - B.gas_off;
+  const int layer = B.n[0] * B.n[1];
+  const int iz = q / layer;
+  const bool has_lo = iz > 0, has_hi = iz < B.n[2] - 1;
+  const GasPartial me = gas_partial(eps[c], g.T[c], g.p[c], g.xH2[c], g.xH2O[c], g.xN2[c]);
+  // lower face: the state below (or the inlet, at the cell's eps, T, p) moves up
+  const double wl = has_lo ? 0.5 * (g.wg[c - layer] + g.wg[c]) : g.wg[c];
+  GasPartial lo;
+  if (has_lo) {
+    const int d = c - layer;
+    lo = gas_partial(eps[d], g.T[d], g.p[d], g.xH2[d], g.xH2O[d], g.xN2[d]);
+  } else {
+    lo = gas_partial(eps[c], g.T[c], g.p[c], xin1, xin2, 1.0 - xin1 - xin2);
+  }
+  // upper face: this state moves up, or the state above (zero gradient at the top) down
+  const double wu = has_hi ? 0.5 * (g.wg[c] + g.wg[c + layer]) : g.wg[c];
+  GasPartial hi = me;
+  if (has_hi && wu < 0.0) {
+    const int d = c + layer;
+    hi = gas_partial(eps[d], g.T[d], g.p[d], g.xH2[d], g.xH2O[d], g.xN2[d]);
+  }
+  const double r = dt / B.h;
+  if (fabs(wl) * r > 1.0 || fabs(wu) * r > 1.0) atomicOr(status, 16u);  // Courant number above one
+  double rhs[3];
+#pragma unroll
+  for (int j = 0; j < 3; j++) {
+    const double f_lo = wl * (wl >= 0.0 ? lo.v[j] : me.v[j]);
+    const double f_hi = wu * (wu >= 0.0 ? me.v[j] : hi.v[j]);
+    rhs[j] = me.v[j] - r * (f_hi - f_lo);
+  }
+  // H2: u (1 - dt C0 T / (X eps)) = rhs + dt C1 p (eq. e4-9), C0 = sum E Q / V,
+  // C1 = -(M_H2 / R) sum E S / V
+  const double V = B.h * B.h * B.h;
+  const double X = g.xH2[c] + g.xH2O[c];
+  const double C0 = sumEQ[c] / V, C1 = -(2.016e-3 / kRg) * sumES[c] / V;
+  double u1 = rhs[0] + dt * C1 * g.p[c];
+  if (X > 0.0) u1 /= 1.0 - dt * C0 * g.T[c] / (X * eps[c]);
+  u1 = fmax(u1, 0.0);
+  const double u2 = rhs[1] + (rhs[0] - u1) * (18.015 / 2.016);
+  const double n1 = u1 / 2.016, n2 = u2 / 18.015, n3 = rhs[2] / 28.013, nt = n1 + n2 + n3;
+  o1[c] = n1 / nt;
+  o2[c] = n2 / nt;
+  o3[c] = n3 / nt;
+}
+
+void launch_gas_species(const GasArgs &g, const double *eps, const int32_t *cell_bed, const BedDev *beds, int n_gas,
+                        double dt, const double *sumEQ, const double *sumES, double xin1, double xin2, double *o1,
+                        double *o2, double *o3, uint32_t *status, hipStream_t s) {
+  k_gas_species<<<(n_gas + 255) / 256, 256, 0, s>>>(g, eps, cell_bed, beds, n_gas, dt, sumEQ, sumES, xin1, xin2, o1,
+                                                    o2, o3, status);
+}
+
 #define INST(T)                                                                                                    \
   template void launch_deposit<T>(const Dyn<T> &, const Props<T> &, const GasArgs &, const int32_t *,             \
                                   const int32_t *, const int32_t *, const BedDev *, const OreDev *, const Phys &, \

@@ -123,6 +123,9 @@ struct ReactArgs {
 };
 template <typename T>
 void launch_react(const ReactArgs<T> &a, hipStream_t s);
+void launch_gas_species(const GasArgs &g, const double *eps, const int32_t *cell_bed, const BedDev *beds, int n_gas,
+                        double dt, const double *sumEQ, const double *sumES, double xin1, double xin2, double *o1,
+                        double *o2, double *o3, uint32_t *status, hipStream_t s);
 struct CellSumOut {
   double *o[8];  // per-cell sums of the pm rows (null: not written)
   int rows;      // 4, or 8 with the energy equation

@@ -1,0 +1,87 @@
+"""Two-way coupling for species through the C-ABI against the FP64 oracle:
+the gas-side step (dem_gas_species) at identical state, and coupled intervals
+in which the particles react with the gas they change.
+
+Gates: new mole fractions within 1e-12 relative at identical state; after
+four coupled intervals (FP64 path) mole fractions within 1e-9 and reduction
+degrees within 1e-9."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2311_03908_amd import workloads as W
+from paper_2311_03908_amd.capi import DemError
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2311_03908_amd.bed import Bed
+
+XIN = (0.7, 0.0)
+SRC = ("mdotH2", "mdotH2O", "sumEQ", "sumES")
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("case", ["cfg1_fp64", "cfg2_mixed"])
+def test_gas_step_at_identical_state(case):
+    w = (W.with_velocities(W.squeeze(W.cfg1(), 0.995, 0), 41) if case == "cfg1_fp64"
+         else W.with_velocities(W.squeeze(W.cfg2(n=3000, seed=42), 0.995, 0), 42, vscale=0.03))
+    _say(f"[gas] {case} n={w.n}")
+    bed = Bed(w)
+    ora = O.Oracle(w)
+    bed.couple()
+    ora.couple()
+    dt = 20 * w.params["dt"]
+    rg = bed.react(dt, keys=SRC)
+    ro = ora.react(dt)
+    og = bed.gas_species(dt, rg, XIN, update=False)
+    oo = ora.gas_species(dt, ro["sumEQ"], ro["sumES"], XIN)
+    for k in ("xH2", "xH2O", "xN2"):
+        err = float(np.max(np.abs(_np(og[k]) - oo[k])))
+        _say(f"  {k}: {err:.2e}")
+        assert err <= 1e-12, k
+    assert np.max(np.abs(oo["xH2O"] - w.gas["xH2O"])) > 1e-9  # the particles changed the gas
+
+
+def test_coupled_intervals_fp64():
+    w = W.with_velocities(W.squeeze(W.cfg1(), 0.995, 0), 43)
+    bed = Bed(w)
+    ora = O.Oracle(w)
+    g = dict(w.gas)
+    dt = 20 * w.params["dt"]
+    for it in range(4):
+        bed.step(20)
+        ora.step(20)
+        bed.couple()
+        ora.couple()
+        rg = bed.react(dt, keys=SRC)
+        ro = ora.react(dt)
+        assert np.max(np.abs(_np(rg["fov"]) - ro["fov"])) <= 1e-9, it
+        bed.gas_species(dt, rg, XIN)
+        oo = ora.gas_species(dt, ro["sumEQ"], ro["sumES"], XIN)
+        g.update(oo)
+        ora.set_gas(g)
+    for k in ("xH2", "xH2O", "xN2"):
+        err = float(np.max(np.abs(_np(bed.gas_t[k]) - g[k])))
+        _say(f"[gas] coupled {k}: {err:.2e}")
+        assert err <= 1e-9, k
+
+
+def test_courant_number_above_one_is_reported():
+    w = W.cfg1(n=512)
+    bed = Bed(w)
+    r = bed.react(1e-4, keys=SRC)
+    bed.gas_species(1.0, r, XIN, update=False)  # 0.5 m/s x 1 s over 2 mm cells
+    with pytest.raises(DemError) as e:
+        bed.sync()
+    assert e.value.code == -1
