@@ -259,7 +259,8 @@ int dem_run(dem_ctx *c, int32_t n_intervals, int32_t couple_every, const dem_gas
             dem_sources *out, double *bed_fov);
 
 /* Choose launch shapes for this context's kernels by timing candidates on
- * its own data (state unchanged).  Synchronises. */
+ * its own data (state unchanged).  Synchronises.  With the environment
+ * variable DEMRX_TUNE_LOG set, every candidate's timing goes to stderr. */
 int dem_autotune(dem_ctx *c, const dem_gas *g);
 
 /* Enable (1) or disable (0) HIP-event timing of every DEM-step kernel launch,
