@@ -181,9 +181,19 @@ __global__ void k_cellrank(const int32_t *start, const int32_t *key, const PosRe
   const int s = start[c], e = start[c + 1];
   const PosRec me = load_pos(pos_old, v);
   int rank = 0;
-  for (int q = s; q < e; q++) {
-    const PosRec o = load_pos(pos_old, perm[q]);
-    rank += (o.x < me.x || (o.x == me.x && o.id < me.id)) ? 1 : 0;
+  // members requested eight at a time, so that their loads overlap
+  constexpr int kB = 8;
+  for (int q0 = s; q0 < e; q0 += kB) {
+    int u[kB];
+#pragma unroll
+    for (int k = 0; k < kB; k++) u[k] = q0 + k < e ? perm[q0 + k] : -1;
+    PosRec o[kB];
+#pragma unroll
+    for (int k = 0; k < kB; k++)
+      if (u[k] >= 0) o[k] = load_pos(pos_old, u[k]);
+#pragma unroll
+    for (int k = 0; k < kB; k++)
+      if (u[k] >= 0) rank += (o[k].x < me.x || (o[k].x == me.x && o[k].id < me.id)) ? 1 : 0;
   }
   perm_out[s + rank] = v;
 }

@@ -56,6 +56,9 @@ def test_host_validation_rejects_null_and_bad_arguments():
     assert L.dem_step(None, 1, None) == -1
     assert L.dem_sync(None) == -1
     assert L.dem_pairs(None, None, 0, None) == -1
+    xin = (C.c_double * 2)(0.7, 0.0)
+    assert L.dem_gas_species(None, 1e-4, None, None, None, xin, None, None, None) == -1
+    assert L.dem_react(None, 1e-4, None, None, None, None) == -1
 
 
 def test_bad_grid_rejected_on_host():

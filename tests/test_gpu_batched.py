@@ -44,3 +44,32 @@ def test_batched_equals_per_bed_contexts():
                 assert o1[k][0] == ob[k][b], b
             else:
                 assert torch.equal(o1[k], ob[k][c0:c1]), (b, k)
+
+
+def test_empty_bed_in_a_batch():
+    """A bed without parcels in a batched context: its cells stay at voidage 1
+    with no sources and its bed-mean reduction degree is 0 (the oracle's
+    convention); the other beds step exactly as in their own contexts."""
+    w = W.with_velocities(W.cfg5(n_beds=3, n_scale=0.05, seed=97), 97)
+    keep = w.parcels["bed"] != 1
+    p = {k: np.ascontiguousarray(v[keep]) for k, v in w.parcels.items()}
+    w = W.dataclasses.replace(w, parcels=p)
+    _say(f"[batched] empty middle bed, {w.n} parcels")
+    bed = Bed(w)
+    ob = bed.run(2, 20, sources=True, bed_fov=True)
+    assert ob["bed_fov"][1] == 0.0 and ob["bed_fov"][0] > 0.0 and ob["bed_fov"][2] > 0.0
+    c0 = int(w.cell_offset[1])
+    c1 = c0 + w.beds[1].n_cells
+    eps = bed.couple()["eps"]
+    assert torch.all(eps[c0:c1] == 1.0)
+    for k in ("mdotH2", "sumK", "np"):
+        assert torch.all(ob[k][c0:c1] == 0.0), k
+    sb = bed.state()
+    ids = w.parcels["bed"]
+    for b in (0, 2):
+        one = Bed(W.split_bed(w, b))
+        one.run(2, 20, sources=True, bed_fov=True)
+        s1 = one.state()
+        sel = torch.as_tensor(np.flatnonzero(ids == b), device=sb["x"].device)
+        for k in ("x", "z", "vz", "nh", "nfe"):
+            assert torch.equal(s1[k], sb[k][sel]), (b, k)
