@@ -237,10 +237,12 @@ __device__ __forceinline__ double tpow<double>(double a, double e) { return pow(
 // Gidaspow drag coefficient divided by eps_p = 1 - eps_g (eq. e3-5-1), so
 // that F_d = (beta/eps_p) V (u_g - v) (eq. e3-5) is finite at eps_g = 1.
 // Wen-Yu with Schiller-Naumann C_D (Re of eq. e2-23) at eps_g >= 0.8.
+// The branch is chosen by the caller (dense: eps_g < 0.8, decided on the
+// FP64 voidage, so that an FP32 evaluation takes the branch the FP64 one does).
 template <typename T>
-__device__ __forceinline__ T beta_over_epsp(T eps, T rho, T mu, T slip, T dp, int printed) {
+__device__ __forceinline__ T beta_over_epsp(bool dense, T eps, T rho, T mu, T slip, T dp, int printed) {
   const T ep = T(1) - eps;
-  if (eps < T(0.8)) {
+  if (dense) {
     const T inertial = printed ? T(1.75) * eps * rho * slip / (dp * ep) : T(1.75) * rho * slip / dp;
     return T(150) * ep * mu / (eps * dp * dp) + inertial;
   }
@@ -255,10 +257,10 @@ __device__ __forceinline__ T beta_over_epsp(T eps, T rho, T mu, T slip, T dp, in
 // single-particle C_D with K1 = 1/(1/3 + 2/3 psi^-1/2) - 2.25 dp / Dbed and
 // K2 = 10^(1.8148 (-log10 psi)^0.5743) (K1, K2 passed in, per parcel).
 template <typename T>
-__device__ __forceinline__ T beta_ganser_over_epsp(T eps, T rho, T mu, T slip, T dp, T psi, T K1, T K2,
+__device__ __forceinline__ T beta_ganser_over_epsp(bool dense, T eps, T rho, T mu, T slip, T dp, T psi, T K1, T K2,
                                                    int printed) {
   const T ep = T(1) - eps;
-  if (eps < T(0.8)) {
+  if (dense) {
     const T inertial =
         printed ? T(1.75) * eps * rho * slip / (dp * psi * ep) : T(1.75) * rho * slip / (dp * psi);
     return T(150) * ep * mu / (eps * dp * dp * psi * psi) + inertial;
@@ -273,16 +275,17 @@ __device__ __forceinline__ T beta_ganser_over_epsp(T eps, T rho, T mu, T slip, T
 // drag coefficient over eps_p of one parcel of ore O in bed B: Gidaspow for
 // spheres, Gidaspow-Ganser for a sphericity in (0, 1]
 template <typename T>
-__device__ __forceinline__ T drag_beta(const Phys &ph, const OreDev &O, const BedDev &B, T eps, T rho, T mu, T slip,
-                                       T dp) {
+__device__ __forceinline__ T drag_beta(const Phys &ph, const OreDev &O, const BedDev &B, bool dense, T eps, T rho,
+                                       T mu, T slip, T dp) {
   if (ph.ganser && O.psi > 0.0) {
     const T K1 = T(O.k1_shape) - T(2.25) * dp / T(B.dbed);
-    return beta_ganser_over_epsp<T>(eps, rho, mu, slip, dp, T(O.psi), K1, T(O.k2), ph.ergun_printed);
+    return beta_ganser_over_epsp<T>(dense, eps, rho, mu, slip, dp, T(O.psi), K1, T(O.k2), ph.ergun_printed);
   }
-  return beta_over_epsp<T>(eps, rho, mu, slip, dp, ph.ergun_printed);
+  return beta_over_epsp<T>(dense, eps, rho, mu, slip, dp, ph.ergun_printed);
 }
 
-// Per-gas-cell drag table row, three quads: (ug vg wg eps) (dpdx dpdy dpdz rho) (mu - - -)
+// Per-gas-cell drag table row, three quads: (ug vg wg eps) (dpdx dpdy dpdz rho)
+// (mu lambda Pr^1/3 dense), dense = 1 where the FP64 voidage is below 0.8
 constexpr int kGasRow = 12;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

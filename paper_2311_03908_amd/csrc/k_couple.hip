@@ -126,8 +126,9 @@ __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g
         const double dd = 2.0 * (double)d.pos[j].r;
         const double V = kPi / 6.0 * dd * dd * dd;
         const double dpj = dd / (double)p.kcg[j];  // real-particle diameter
-        const double K = (ph.ganser ? drag_beta<double>(ph, ores[ore_of(p.tag[j])], B, eps, rho, mu, slip, dpj)
-                                    : beta_over_epsp<double>(eps, rho, mu, slip, dpj, ph.ergun_printed)) *
+        const bool dense = eps < 0.8;
+        const double K = (ph.ganser ? drag_beta<double>(ph, ores[ore_of(p.tag[j])], B, dense, eps, rho, mu, slip, dpj)
+                                    : beta_over_epsp<double>(dense, eps, rho, mu, slip, dpj, ph.ergun_printed)) *
                          V;
         sK += K;
         sKu += K * vx;

@@ -224,7 +224,7 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
         const T slip = tsqrt<T>(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
         if (a.ph.drag_on) {
           const T V = T(kPi / 6.0) * (T(2) * ri) * (T(2) * ri) * (T(2) * ri);
-          const T be = drag_beta<T>(a.ph, a.ores[ore_of(tag)], B, g0.w, g1.w, mu, slip, dpr);
+          const T be = drag_beta<T>(a.ph, a.ores[ore_of(tag)], B, g2.w != T(0), g0.w, g1.w, mu, slip, dpr);
           F[0] += be * V * s[0] - V * g1.x;
           F[1] += be * V * s[1] - V * g1.y;
           F[2] += be * V * s[2] - V * g1.z;
@@ -376,7 +376,8 @@ __global__ void k_gas_table(GasArgs g, const double *eps, const int32_t *cell_be
   r[6] = T(g.dpdz[c]);
   r[7] = T(rho);
   r[8] = T(mu);
-  r[9] = r[10] = r[11] = T(0);
+  r[9] = r[10] = T(0);
+  r[11] = T(eps[c] < 0.8 ? 1 : 0);  // drag branch, decided in FP64
   double lam = 1.0, cp = 1.0;
   if (thermo) {
     gas_heat_props(*thermo, g.T[c], g.xH2[c], g.xH2O[c], g.xN2[c], lam, cp);
