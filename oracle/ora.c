@@ -624,7 +624,7 @@ long ora_pairs(ora_sys *s, int brute, int *ij, long cap) {
  * first body), the tangential part Ft, the new history and |F_n| are returned. */
 static void contact_law(const ora_params *P, double mstar, double zeta, double delta,
                         const double n[3], const double vrel[3], const double xi_in[3],
-                        double F[3], double Ft[3], double xi_out[3], double *fn_abs) {
+                        double F[3], double Ft[3], double xi_out[3], double *fn_abs, double scale[2]) {
   double gn = 2.0 * zeta * sqrt(mstar * P->kn);
   double vn = dot3(vrel, n);
   double fn = -(P->kn * delta + gn * vn);
@@ -646,6 +646,14 @@ static void contact_law(const ora_params *P, double mstar, double zeta, double d
     xi_out[a] = xi[a];
   }
   *fn_abs = fabs(fn);
+  if (scale) {
+    /* magnitudes of the products the normal and the tangential force are
+     * built from (|v_n|, |v_t| <= |v_rel|): the spring and the dashpot cancel
+     * as a contact ends, so |F| alone understates them */
+    double vr = norm3(vrel);
+    scale[0] = P->kn * fabs(delta) + gn * vr;
+    scale[1] = kt * (norm3(xi_in) + vr * P->dt) + gt * vr;
+  }
 }
 
 static void rolling(const ora_sys *s, int i, double fn_abs, double T[3]) {
@@ -681,10 +689,12 @@ static double wall_geom(const ora_bed *b, int w, const double x[3], double nvec[
   return b->hi[2] - x[2];
 }
 
-/* eq. e3-5 with e3-5-1 plus body forces of eq. e3-3 (gravity, -V grad p) */
-static void gas_force(const ora_sys *s, const ora_gas *g, int i, double F[3]) {
+/* eq. e3-5 with e3-5-1 plus body forces of eq. e3-3 (gravity, -V grad p);
+ * with scale, the magnitudes of the three terms are added to *scale */
+static void gas_force(const ora_sys *s, const ora_gas *g, int i, double F[3], double *scale) {
   double m = s->mass[i];
   for (int a = 0; a < 3; a++) F[a] += m * s->P.g[a];
+  if (scale) *scale += m * norm3(s->P.g);
   if (!s->P.drag_on) return;
   int c = cell_of(s, i);
   const ora_bed *B = &s->beds[s->bed[i]];
@@ -697,6 +707,10 @@ static void gas_force(const ora_sys *s, const ora_gas *g, int i, double F[3]) {
   double sl[3] = {g->ug[c] - s->vel[3 * i], g->vg[c] - s->vel[3 * i + 1], g->wg[c] - s->vel[3 * i + 2]};
   double be = beta_of(s, i, s->eps[c], rho, mu, norm3(sl));
   for (int a = 0; a < 3; a++) F[a] += be * V * sl[a];
+  if (scale) {
+    double gp[3] = {g->dpdx[c], g->dpdy[c], g->dpdz[c]};
+    *scale += V * norm3(gp) + be * V * norm3(sl);
+  }
 }
 
 static const double *hist_lookup(const ora_sys *s, int a, int b) {
@@ -706,12 +720,20 @@ static const double *hist_lookup(const ora_sys *s, int a, int b) {
 }
 
 /* Forces and torques of one DEM step from the step-start state; with commit,
- * the tangential histories are replaced by the new ones. */
-static void compute_forces(ora_sys *s, const ora_gas *g, double *F, double *T, int commit) {
+ * the tangential histories are replaced by the new ones.  Fs and Ts (may be
+ * NULL) receive per parcel the sum of the magnitudes of the products that
+ * make up F and T (per contact: k_n |delta| + gamma_n |v_rel| normal, and
+ * k_t (|xi| + |v_rel| dt) + gamma_t |v_rel| tangential; gravity, pressure
+ * gradient and drag): the scale of the rounding error of F and T when they
+ * are evaluated in a lower precision. */
+static void compute_forces(ora_sys *s, const ora_gas *g, double *F, double *T, double *Fs, double *Ts,
+                           int commit) {
   int n = s->n;
   static const double zero3[3] = {0, 0, 0};
   memset(F, 0, sizeof(double) * 3 * n);
   memset(T, 0, sizeof(double) * 3 * n);
+  if (Fs) memset(Fs, 0, sizeof(double) * n);
+  if (Ts) memset(Ts, 0, sizeof(double) * n);
   int *pr;
   long np_ = find_pairs(s, 0, &pr);
   int *ncnt = (int *)calloc(n, sizeof(int));
@@ -733,8 +755,8 @@ static void compute_forces(ora_sys *s, const ora_gas *g, double *F, double *T, i
     cross3(wsum, nv, cr);
     for (int c = 0; c < 3; c++) vrel[c] = s->vel[3 * a + c] - s->vel[3 * b + c] + cr[c];
     const double *xo = hist_lookup(s, a, b);
-    double Fa[3], Ft[3], xin[3], fnabs, tq[3];
-    contact_law(&s->P, mstar, zeta, delta, nv, vrel, xo ? xo : zero3, Fa, Ft, xin, &fnabs);
+    double Fa[3], Ft[3], xin[3], fnabs, tq[3], sc[2];
+    contact_law(&s->P, mstar, zeta, delta, nv, vrel, xo ? xo : zero3, Fa, Ft, xin, &fnabs, sc);
     cross3(nv, Ft, tq);
     for (int c = 0; c < 3; c++) {
       F[3 * a + c] += Fa[c];
@@ -744,6 +766,15 @@ static void compute_forces(ora_sys *s, const ora_gas *g, double *F, double *T, i
     }
     rolling(s, a, fnabs, &T[3 * a]);
     rolling(s, b, fnabs, &T[3 * b]);
+    if (Fs) {
+      Fs[a] += sc[0] + sc[1];
+      Fs[b] += sc[0] + sc[1];
+    }
+    if (Ts) {
+      double roll = s->P.mu_r > 0.0 ? s->P.mu_r * sc[0] : 0.0;
+      Ts[a] += ra * sc[1] + roll;
+      Ts[b] += rb * sc[1] + roll;
+    }
     if (ncnt[a] >= HCAP) abort();
     nh[(size_t)a * HCAP + ncnt[a]].partner = b;
     memcpy(nh[(size_t)a * HCAP + ncnt[a]].xi, xin, sizeof xin);
@@ -768,21 +799,23 @@ static void compute_forces(ora_sys *s, const ora_gas *g, double *F, double *T, i
       cross3(wr, nv, cr);
       for (int c = 0; c < 3; c++) vrel[c] = s->vel[3 * i + c] + cr[c];
       const double *xo = s->won[6 * i + w] ? &s->wxi[18 * i + 3 * w] : zero3;
-      double Fa[3], Ft[3], xin[3], fnabs, tq[3];
-      contact_law(&s->P, s->mass[i], zeta, delta, nv, vrel, xo, Fa, Ft, xin, &fnabs);
+      double Fa[3], Ft[3], xin[3], fnabs, tq[3], sc[2];
+      contact_law(&s->P, s->mass[i], zeta, delta, nv, vrel, xo, Fa, Ft, xin, &fnabs, sc);
       cross3(nv, Ft, tq);
       for (int c = 0; c < 3; c++) {
         F[3 * i + c] += Fa[c];
         T[3 * i + c] += r * tq[c];
       }
       rolling(s, i, fnabs, &T[3 * i]);
+      if (Fs) Fs[i] += sc[0] + sc[1];
+      if (Ts) Ts[i] += r * sc[1] + (s->P.mu_r > 0.0 ? s->P.mu_r * sc[0] : 0.0);
       if (commit) {
         memcpy(&s->wxi[18 * i + 3 * w], xin, sizeof xin);
         s->won[6 * i + w] = 1;
       }
     }
   }
-  for (int i = 0; i < n; i++) gas_force(s, g, i, &F[3 * i]);
+  for (int i = 0; i < n; i++) gas_force(s, g, i, &F[3 * i], Fs ? &Fs[i] : NULL);
   if (commit) {
     free(s->hist);
     free(s->hcnt);
@@ -794,7 +827,15 @@ static void compute_forces(ora_sys *s, const ora_gas *g, double *F, double *T, i
   }
 }
 
-void ora_forces(ora_sys *s, const ora_gas *g, double *F, double *T) { compute_forces(s, g, F, T, 0); }
+void ora_forces(ora_sys *s, const ora_gas *g, double *F, double *T) { compute_forces(s, g, F, T, NULL, NULL, 0); }
+
+void ora_force_scale(ora_sys *s, const ora_gas *g, double *Fs, double *Ts) {
+  double *F = (double *)malloc(sizeof(double) * 3 * (s->n > 0 ? s->n : 1));
+  double *T = (double *)malloc(sizeof(double) * 3 * (s->n > 0 ? s->n : 1));
+  compute_forces(s, g, F, T, Fs, Ts, 0);
+  free(F);
+  free(T);
+}
 
 /* eq. e3-3 and e3-6 advanced by semi-implicit Euler (reading: the paper does
  * not name its integrator): v += dt F/m, w += dt T/I, x += dt v_new. */
@@ -803,7 +844,7 @@ void ora_step(ora_sys *s, int nsteps, const ora_gas *g) {
   double *F = (double *)malloc(sizeof(double) * 3 * n);
   double *T = (double *)malloc(sizeof(double) * 3 * n);
   for (int st = 0; st < nsteps; st++) {
-    compute_forces(s, g, F, T, 1);
+    compute_forces(s, g, F, T, NULL, NULL, 1);
     double dt = s->P.dt;
     /* eq. e3-8 with conduction and radiation left out: m C_p dT_p/dt =
      * k^3 (Q_conv + Q_r + Q_rm) (eqs. e3-41, e3-49, e3-50), explicit in the

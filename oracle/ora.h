@@ -75,6 +75,12 @@ int ora_n_cells(const ora_sys *s);
 long ora_pairs(ora_sys *s, int brute, int *ij, long cap);
 /* total force and torque the next step would apply (state is not changed) */
 void ora_forces(ora_sys *s, const ora_gas *g, double *F, double *T);
+/* per parcel, the sums of the magnitudes of the products that ora_forces
+ * builds the force and the torque from (per contact and wall: spring,
+ * dashpot, tangential spring and dashpot, rolling; gravity, pressure
+ * gradient, drag): the scale of the rounding error of F and T when they are
+ * evaluated in a lower precision */
+void ora_force_scale(ora_sys *s, const ora_gas *g, double *Fs, double *Ts);
 void ora_step(ora_sys *s, int nsteps, const ora_gas *g);
 /* voidage + drag deposition; outputs may be NULL */
 void ora_couple(ora_sys *s, const ora_gas *g, double *eps, double *np_, double *sumK,

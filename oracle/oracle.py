@@ -71,6 +71,7 @@ def lib():
         L.ora_pairs.restype = C.c_long
         L.ora_pairs.argtypes = [C.c_void_p, C.c_int, _ip, C.c_long]
         L.ora_forces.argtypes = [C.c_void_p, C.POINTER(OraGas), _dp, _dp]
+        L.ora_force_scale.argtypes = [C.c_void_p, C.POINTER(OraGas), _dp, _dp]
         L.ora_step.argtypes = [C.c_void_p, C.c_int, C.POINTER(OraGas)]
         L.ora_couple.argtypes = [C.c_void_p, C.POINTER(OraGas)] + [_dp] * 7
         L.ora_react.restype = C.c_long
@@ -199,6 +200,16 @@ class Oracle:
         T = np.zeros(3 * self.n)
         lib().ora_forces(self.h, C.byref(self._gs), _p(F), _p(T))
         return F.reshape(-1, 3), T.reshape(-1, 3)
+
+    def force_scale(self):
+        """Per parcel, the sums of the magnitudes of the products that
+        forces() builds F and T from (ora_force_scale): F and T evaluated in
+        a lower precision carry a rounding error proportional to these
+        scales, not to |F| and |T|."""
+        Fs = np.zeros(self.n)
+        Ts = np.zeros(self.n)
+        lib().ora_force_scale(self.h, C.byref(self._gs), _p(Fs), _p(Ts))
+        return Fs, Ts
 
     def step(self, n=1):
         lib().ora_step(self.h, int(n), C.byref(self._gs))

@@ -2,7 +2,8 @@
 identical seeded inputs.
 
 Gates: contact pair lists bit-exact; per-step forces within 1e-5 of
-max(|F_oracle|, m g) (FP64 path: 1e-10); 100-step trajectories within
+max(|F_oracle|, m g, force-term scale) (FP64 path: 1e-9 of
+max(|F_oracle|, m g)); 100-step trajectories within
 1e-4 d (positions) and 1e-4 max(|v|, 1e-3 m/s) (velocities); reduction
 degree within 1e-4 per parcel; cell sums within 1e-9 relative.
 """
@@ -31,9 +32,23 @@ def _np(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-def _force_err(Fg, Fo, mass, floor_scale=9.81):
-    floor = mass * floor_scale
-    return float(np.max(np.abs(Fg - Fo) / np.maximum(np.linalg.norm(Fo, axis=1), floor)[:, None]))
+def _force_err(Fg, Fo, mass, scale=None, floor_scale=9.81):
+    """Largest component error relative to max(|F|, m g) and, for the mixed
+    path, to the parcel's force-term scale (Oracle.force_scale): an FP32
+    evaluation errs in proportion to the products it adds up, which exceed
+    |F| where they cancel (spring against dashpot as a contact ends, opposite
+    contacts)."""
+    den = np.maximum(np.linalg.norm(Fo, axis=1), mass * floor_scale)
+    if scale is not None:
+        den = np.maximum(den, scale)
+    return float(np.max(np.abs(Fg - Fo) / den[:, None]))
+
+
+def _torque_err(Tg, To, floor, scale=None):
+    den = np.maximum(np.linalg.norm(To, axis=1), floor)
+    if scale is not None:
+        den = np.maximum(den, scale)
+    return float(np.max(np.abs(Tg - To) / den[:, None]))
 
 
 # Dense variants (parcels pushed together) for one-shot comparisons, and gently
@@ -101,18 +116,113 @@ def test_forces_each_step(case):
             bed = Bed(wk)
             ok = O.Oracle(wk)
             Fo, To = ok.forces()
+            Fs, Ts = ok.force_scale()
             tol = 1e-5
         else:
             Fo, To = ora.forces()
+            Fs = Ts = None
             tol = 1e-9
         Fg, Tg = bed.forces()
-        ef = _force_err(_np(Fg), Fo, mass)
-        et = float(np.max(np.abs(_np(Tg) - To) / np.maximum(np.linalg.norm(To, axis=1), rg)[:, None]))
+        ef = _force_err(_np(Fg), Fo, mass, Fs)
+        et = _torque_err(_np(Tg), To, rg, Ts)
         assert ef <= tol, (k, ef)
         assert et <= tol, (k, et)
         if w.precision != "mixed":
             bed.step(1)
         ora.step(1)
+
+
+# Mixed-precision beds pressed until hundreds of pairs and wall contacts
+# touch (the gentle variants touch nowhere), light enough that single
+# contact forces stay within FP32's reach of the net force.
+TOUCHING = {
+    "cfg2_mixed": lambda: W.with_velocities(W.squeeze(W.cfg2(n=3000, seed=22), 0.98, 0), 31, vscale=0.03, wscale=20.0),
+    "cfg3_mixed": lambda: W.with_velocities(W.squeeze(W.cfg3(n=20000, seed=23), 0.98, 0), 32, vscale=0.03, wscale=20.0),
+    "cfg5_mixed": lambda: W.with_velocities(W.squeeze(W.cfg5(n_beds=6, n_scale=0.05, seed=5), 0.97, 0), 33,
+                                            vscale=0.03, wscale=20.0),
+}
+
+
+@pytest.mark.parametrize("case", list(TOUCHING))
+def test_forces_touching_mixed(case):
+    """Mixed precision with touching parcels: forces and torques of four
+    successive oracle states (rolling friction on, each side starting from
+    the oracle state with fresh springs) to the force gate."""
+    w = _rolling(TOUCHING[case]())
+    ora = O.Oracle(w)
+    n0 = len(ora.pairs())
+    _say(f"[touching] {case} n={w.n} contacts={n0}")
+    assert n0 >= 100
+    mass = ora.state()["mass"]
+    rg = mass * 9.81 * 0.5 * w.parcels["d"].astype(np.float64)
+    for k in range(4):
+        wk = _from_state(w, ora.state())
+        bed = Bed(wk)
+        ok = O.Oracle(wk)
+        Fo, To = ok.forces()
+        Fs, Ts = ok.force_scale()
+        Fg, Tg = bed.forces()
+        bed.close()
+        ef = _force_err(_np(Fg), Fo, mass, Fs)
+        et = _torque_err(_np(Tg), To, rg, Ts)
+        _say(f"  state {k}: force err {ef:.2e} torque err {et:.2e}")
+        assert ef <= 1e-5, (k, ef)
+        assert et <= 1e-5, (k, et)
+        ora.step(1)
+
+
+def _drag_branch_edge():
+    """A cfg5-type bed in which one gas cell's FP64 voidage lies just below
+    the 0.8 switch of the Gidaspow drag but rounds to 0.8 in FP32: one
+    parcel diameter of the cell is moved by FP32 ulps until the NGP voidage
+    lands in that window.  Returns the workload and the cell."""
+    w = W.with_velocities(W.cfg5(n_beds=1, n_scale=0.1, seed=41), 41, vscale=0.03, wscale=20.0)
+    bed = w.beds[0]
+    p = dict(w.parcels)
+    q = [np.clip(np.floor((p[a] - bed.origin[k]) / bed.h), 0, bed.n[k] - 1).astype(np.int64)
+         for k, a in enumerate(("x", "y", "z"))]
+    cell = q[0] + bed.n[0] * (q[1] + bed.n[1] * q[2])
+    vc = bed.h ** 3
+    vol = math.pi / 6.0 * p["d"].astype(np.float64) ** 3
+    sv = np.bincount(cell, weights=vol, minlength=bed.n_cells)
+    lo = float(np.float32(0.8)) - 0.5 * (float(np.float32(0.8)) - float(np.nextafter(np.float32(0.8), np.float32(0))))
+    for c in np.argsort(np.abs(1.0 - sv / vc - 0.8)):
+        members = np.flatnonzero(cell == c)
+        for i in members[np.argsort(p["d"][members])]:
+            others = sv[c] - vol[i]
+            d = np.float32(p["d"][i])
+            for direction in (1, -1):
+                dd = d
+                for _ in range(4000):
+                    e = 1.0 - (others + math.pi / 6.0 * float(dd) ** 3) / vc
+                    if lo + 1e-10 < e < 0.8 - 1e-10:
+                        p["d"] = p["d"].copy()
+                        p["d"][i] = dd
+                        return W.dataclasses.replace(w, parcels=p), int(c)
+                    if (e > 0.8) == (direction < 0):
+                        break  # moving away from the window
+                    dd = np.nextafter(dd, np.float32(direction * np.inf))
+    raise AssertionError("no cell reaches the voidage window")
+
+
+def test_drag_branch_decided_in_fp64():
+    """The dense/dilute switch of the drag law is a decision taken on the
+    voidage: the mixed path takes it on the FP64 voidage, as the oracle does,
+    so a cell whose voidage rounds across 0.8 in FP32 still gets the
+    oracle's branch (forces of its parcels to the force gate)."""
+    w, c = _drag_branch_edge()
+    ora = O.Oracle(w)
+    eps = ora.couple()["eps"]
+    assert eps[c] < 0.8 and np.float32(eps[c]) == np.float32(0.8)
+    bed = Bed(w)
+    eg = _np(bed.couple()["eps"])
+    assert eg[c] < 0.8 and abs(eg[c] - eps[c]) <= 1e-15
+    Fg, _ = bed.forces()
+    Fo, _ = ora.forces()
+    ef = _force_err(_np(Fg), Fo, ora.state()["mass"], ora.force_scale()[0])
+    _say(f"[drag edge] cell {c} eps {eps[c]!r}: force err {ef:.2e}")
+    assert ef <= 1e-5
+    bed.close()
 
 
 @pytest.mark.parametrize("case", list(GENTLE))
@@ -371,38 +481,39 @@ def test_skin_violation_reported():
 
 # ------------------------------------------------------------------ full size
 
-def test_headline_bed_full_size_one_step():
-    """2,000,000-parcel bed, launch shapes as benchmarked: pair list, forces
-    of the first step and the reaction update against the oracle on every
-    parcel."""
-    _say("[full] generating cfg3")
-    w = W.squeeze(W.cfg3(), 0.96, 0)  # the packed bed pressed so that contacts exist
+def _full_size_check(make, press, tag):
+    """One step's worth of parity at full size, launch shapes autotuned as
+    the benchmark runs them, on the bed pressed by ``press`` (many contacts)
+    with slow random motion: pair list bit-exact, forces to the force gate,
+    voidage deposit, reaction update and bed-mean reduction degrees."""
+    w = W.with_velocities(W.squeeze(make(), press, 0), 7, vscale=0.03, wscale=20.0)
+    _say(f"[full] {tag}: {w.n} parcels, {len(w.beds)} beds; pairs")
     bed = Bed(w)
     bed.autotune()
     ora = O.Oracle(w)
-    _say("[full] pairs")
     pg, po = bed.pairs(), ora.pairs()
     assert len(po) > 10000 and np.array_equal(pg, po)
-    _say("[full] forces")
-    # forces on a lightly pressed bed: with the 4 % overlaps above, single
-    # contact forces exceed the net force by orders of magnitude and FP32
-    # summation cannot resolve the net force to 1e-5
-    bed.close()
-    del ora
-    w = W.with_velocities(W.squeeze(W.cfg3(), 0.99, 0), 3, vscale=0.03, wscale=20.0)
-    bed = Bed(w)
-    bed.autotune()
-    ora = O.Oracle(w)
+    _say(f"[full] {tag}: forces ({len(po)} contacts)")
     Fg, _ = bed.forces()
     Fo, _ = ora.forces()
-    mass = ora.state()["mass"]
-    assert _force_err(_np(Fg), Fo, mass) <= 1e-5
-    _say("[full] couple + react")
+    ef = _force_err(_np(Fg), Fo, ora.state()["mass"], ora.force_scale()[0])
+    _say(f"  force err {ef:.2e}")
+    assert ef <= 1e-5
+    _say(f"[full] {tag}: couple + react")
     cg, co = bed.couple(), ora.couple()
     assert np.max(np.abs(_np(cg["eps"]) - co["eps"])) <= 1e-12
-    rg, ro = bed.react(1e-4), ora.react(1e-4)
+    rg, ro = bed.react(1e-4), ora.react(1e-4, n_beds=len(w.beds))
     assert np.max(np.abs(_np(rg["fov"]) - ro["fov"])) <= 1e-4
-    assert abs(rg["bed_fov"][0] - ro["bed_fov"][0]) <= 1e-12
+    assert np.max(np.abs(rg["bed_fov"] - ro["bed_fov"])) <= 1e-12
+    for k in ("mdotH2", "sumEQ", "sumES"):
+        a, b = _np(rg[k]), ro[k]
+        assert np.max(np.abs(a - b)) <= 1e-9 * np.max(np.abs(b)), k
+    bed.close()
+
+
+def test_headline_bed_full_size_one_step():
+    """The 2,000,000-parcel bed, pressed to 4 % overlaps."""
+    _full_size_check(W.cfg3, 0.96, "cfg3")
 
 
 def _nonspherical(w, psi=0.86):
@@ -432,8 +543,21 @@ def test_ganser_drag_forces_and_sums(case):
     mass = ora.state()["mass"]
     Fo, _ = ora.forces()
     Fg, _ = bed.forces()
-    tol = 1e-5 if w.precision == "mixed" else 1e-9
-    ef = _force_err(_np(Fg), Fo, mass)
+    mixed = w.precision == "mixed"
+    tol = 1e-5 if mixed else 1e-9
+    ef = _force_err(_np(Fg), Fo, mass, ora.force_scale()[0] if mixed else None)
     _say(f"  force err {ef:.2e}")
     assert ef <= tol
     bed.close()
+
+
+def test_batched_workload_full_size_one_step():
+    """The 64-bed workload at full size (1,757,123 parcels) in the autotuned
+    launch shapes the benchmark uses."""
+    _full_size_check(W.cfg5, 0.96, "batched")
+
+
+def test_sweep_workload_full_size_one_step():
+    """The kinetic sweep's Bed I / Bed II beds at full size (magnetite and
+    hematite ore, Ganser drag) in the autotuned launch shapes."""
+    _full_size_check(W.sweep, 0.98, "sweep")

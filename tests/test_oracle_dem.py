@@ -253,3 +253,93 @@ def test_drag_on_lone_parcel_uses_real_diameter_and_bed_width(psi):
     expect = 0.75 * 24.0 / K1 * mu * eps ** -2.65 / dpr ** 2 * V * u
     assert F[0, 2] == pytest.approx(expect, rel=1e-5)
     assert abs(F[0, 0]) < 1e-12 * expect and abs(F[0, 1]) < 1e-12 * expect
+
+
+# ------------------------------------------------------------- force-term scale
+def test_force_scale_of_a_parcel_squeezed_between_two():
+    """Three parcels on a line, the middle one pressed equally from both
+    sides, no gravity or gas: its net force vanishes while its force-term
+    scale is twice one contact's k_n delta; each outer parcel has one term,
+    so its scale equals |F|.  No tangential or rolling terms: torque scale 0."""
+    d = float(np.float32(1e-3))
+    x0, s = 0.0078125, 0.0009765625  # 2^-7 and 2^-10: the positions are exact
+    w = box_workload([(x0 - s, 0.01, 0.01), (x0, 0.01, 0.01), (x0 + s, 0.01, 0.01)], d)
+    ora = O.Oracle(w, drag_on=False, g=(0.0, 0.0, 0.0))
+    F, T = ora.forces()
+    Fs, Ts = ora.force_scale()
+    delta = d - s
+    assert F[1] == pytest.approx([0.0, 0.0, 0.0], abs=1e-18)
+    assert Fs[1] == pytest.approx(2 * 1000.0 * delta, rel=1e-12)
+    for i in (0, 2):
+        assert Fs[i] == pytest.approx(np.linalg.norm(F[i]), rel=1e-12)
+        assert Fs[i] == pytest.approx(1000.0 * delta, rel=1e-12)
+    assert np.all(Ts == 0.0) and np.all(T == 0.0)
+
+
+def test_force_scale_of_a_lone_parcel_is_gravity_plus_drag():
+    """A parcel at rest in upflow: the scale is m|g| plus the drag term, the
+    latter read off as the force difference with the drag switched off."""
+    w = box_workload([(0.01, 0.01, 0.01)], 1e-3, u=(0.0, 0.0, 0.5))
+    on = O.Oracle(w)
+    off = O.Oracle(w, drag_on=False)
+    F_on, _ = on.forces()
+    F_off, _ = off.forces()
+    m = on.state()["mass"][0]
+    Fs, _ = on.force_scale()
+    assert F_on[0, 2] > F_off[0, 2] and F_off[0, 2] < 0  # drag up, gravity down
+    assert Fs[0] == pytest.approx(m * 9.81 + (F_on[0, 2] - F_off[0, 2]), rel=1e-12)
+    Fs_off, _ = off.force_scale()
+    assert Fs_off[0] == pytest.approx(m * 9.81, rel=1e-15)
+
+
+def test_force_scale_of_a_contact_whose_dashpot_cancels_its_spring():
+    """Two parcels separating at exactly the speed at which the dashpot
+    cancels the spring (gamma_n v = k_n delta): no net force, while the
+    scale keeps both products, 2 k_n delta, plus the tangential spring's
+    k_t |v_rel| dt (no tangential dashpot here) per parcel, whose torque
+    scale is r k_t |v_rel| dt."""
+    d = float(np.float32(1e-3))
+    x0, s = 0.0078125, 0.0009765625
+    delta = d - s
+    kn, e_p = 1000.0, 0.9
+    w = box_workload([(x0, 0.01, 0.01), (x0 + s, 0.01, 0.01)], d, kn=kn, e_p=e_p)
+    m = O.Oracle(w).state()["mass"][0]
+    gn = 2.0 * O.zeta(O.e_cgp(e_p, 1.0)) * math.sqrt(0.5 * m * kn)
+    v = kn * delta / gn
+    w = box_workload([(x0, 0.01, 0.01), (x0 + s, 0.01, 0.01)], d, kn=kn, e_p=e_p,
+                     v=[(-0.5 * v, 0, 0), (0.5 * v, 0, 0)])
+    ora = O.Oracle(w, drag_on=False, g=(0.0, 0.0, 0.0))
+    F, _ = ora.forces()
+    Fs, Ts = ora.force_scale()
+    assert np.max(np.abs(F)) <= 1e-12 * kn * delta
+    kt = w.params["kt_over_kn"] * kn
+    assert w.params["gt_over_gn"] == 0.0
+    assert Fs == pytest.approx([2 * kn * delta + kt * v * w.params["dt"]] * 2, rel=1e-12)
+    assert Ts == pytest.approx([0.5 * d * kt * v * w.params["dt"]] * 2, rel=1e-12)
+
+
+def test_force_scale_bounds_the_net_force_and_torque():
+    """Triangle inequality on a moving, rubbing cluster pressed against the
+    floor: the scales bound |F| and |T| for every parcel.  At rest, with no
+    gravity or gas, a parcel touched by one contact alone has scale |F|."""
+    pos, d, v, om = _cluster()
+    low = np.argmin(pos[:, 2])
+    pos[:, 2] -= pos[low, 2] - 0.49 * d[low]  # lowest parcel pressed into the floor
+    w = box_workload(pos, d, v=v, w=om, mu_r=2e-5, gt_over_gn=0.3)
+    ora = O.Oracle(w)
+    F, T = ora.forces()
+    Fs, Ts = ora.force_scale()
+    assert len(ora.pairs()) > 20
+    assert np.all(Fs >= np.linalg.norm(F, axis=1) * (1 - 1e-12))
+    assert np.all(Ts >= np.linalg.norm(T, axis=1) * (1 - 1e-12))
+    assert np.any(Ts > 0)
+    rest = box_workload(pos, d, mu_r=2e-5, gt_over_gn=0.3)
+    bare = O.Oracle(rest, drag_on=False, g=(0.0, 0.0, 0.0))
+    Fb, _ = bare.forces()
+    Fsb, _ = bare.force_scale()
+    pr = bare.pairs()
+    ones = np.flatnonzero(np.bincount(pr.ravel(), minlength=w.n) == 1)
+    R = 0.5 * w.parcels["d"].astype(np.float64)
+    clear = ones[(pos[ones, 2] - R[ones] > 0.0)]
+    assert clear.size > 0
+    assert np.allclose(Fsb[clear], np.linalg.norm(Fb[clear], axis=1), rtol=1e-12)
