@@ -278,6 +278,8 @@ def main():
     ap.add_argument("--settle-steps", type=int, default=SETTLE_STEPS)
     ap.add_argument("--save-settled", default=None, help="settle the bed, save its state (.npz) and exit")
     ap.add_argument("--settled", default=None, help="start from a state saved by --save-settled")
+    ap.add_argument("--launch", default=None, metavar="B,X,G",
+                    help="fixed launch shapes (step block, XCD chunk, build grid) instead of autotuning")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (64-bed), adjoint (500k-parcel gradient) and kinetic-sweep legs")
     ap.add_argument("--only", choices=["batched", "adjoint", "sweep"], default=None,
@@ -329,7 +331,10 @@ def main():
     warm = max(G * S, (args.warmup + S - 1) // S * S)
     _log(f"[bench] n={w.n} steps={steps} warmup={warm}")
     bed = Bed(w, device="cuda:0")
-    bed.autotune()
+    if args.launch:
+        bed.set_launch(*[int(v) for v in args.launch.split(",")])
+    else:
+        bed.autotune()
     bed.profile(True)  # the replay graph is captured with the timing events
     bed.run(warm // S, S)
     bed.sync()

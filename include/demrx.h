@@ -263,6 +263,14 @@ int dem_run(dem_ctx *c, int32_t n_intervals, int32_t couple_every, const dem_gas
  * variable DEMRX_TUNE_LOG set, every candidate's timing goes to stderr. */
 int dem_autotune(dem_ctx *c, const dem_gas *g);
 
+/* Set the launch shapes directly (instead of dem_autotune), e.g. to repeat a
+ * measurement in a known shape: step_block threads per block of the DEM-step
+ * kernel (64, 128, 256 or 512), step_xcd_chunk consecutive blocks kept on one
+ * XCD by the block remap (1..64; 1 = no remap), build_grid blocks of the
+ * persistent neighbour build (1..65536).  Results do not depend on the shapes.
+ * DEMRX_EINVAL outside these ranges (nothing changed).  No device work. */
+int dem_set_launch(dem_ctx *c, int32_t step_block, int32_t step_xcd_chunk, int32_t build_grid);
+
 /* Enable (1) or disable (0) HIP-event timing of every DEM-step kernel launch,
  * recorded on the stream the kernel runs on (inside dem_run graphs too: the
  * events of the last replay are kept).  Resets the timings; dem_get_stats

@@ -210,6 +210,9 @@ class Bed:
     def autotune(self):
         self._check(self.L.dem_autotune(self.h, C.byref(self._gas)))
 
+    def set_launch(self, step_block, step_xcd_chunk, build_grid):
+        self._check(self.L.dem_set_launch(self.h, int(step_block), int(step_xcd_chunk), int(build_grid)))
+
     def grad(self, n_substeps, dt_react, dyn_every, ckpt_every, theta, state_fp32=True, with_grad=True):
         spec = capi.DemGradSpec(int(n_substeps), float(dt_react), int(dyn_every), int(ckpt_every), int(state_fp32))
         th = (C.c_double * 6)(*[float(v) for v in theta])

@@ -78,7 +78,8 @@ class DemStats(C.Structure):
 
 
 EXPORTS = ("dem_init", "dem_step", "dem_couple", "dem_react", "dem_gas_species", "dem_grad", "dem_forces",
-           "dem_get_state", "dem_set_state", "dem_pairs", "dem_get_stats", "dem_run", "dem_autotune", "dem_profile", "dem_sync",
+           "dem_get_state", "dem_set_state", "dem_pairs", "dem_get_stats", "dem_run", "dem_autotune", "dem_set_launch", "dem_profile",
+           "dem_sync",
            "dem_last_error", "dem_destroy")
 
 _lib = None
@@ -118,6 +119,7 @@ def load(path: str = LIB_PATH):
     L.dem_run.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(DemGas), C.POINTER(DemSources),
                           C.POINTER(C.c_double)]
     L.dem_autotune.argtypes = [vp, C.POINTER(DemGas)]
+    L.dem_set_launch.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
     L.dem_profile.argtypes = [vp, C.c_int32]
     L.dem_sync.argtypes = [vp]
     L.dem_last_error.argtypes = [vp]

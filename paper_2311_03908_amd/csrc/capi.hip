@@ -32,6 +32,7 @@ struct dem_ctx {
   virtual int stats(dem_stats *o) = 0;
   virtual int run(int n_int, int S, const dem_gas *g, dem_sources *o, double *bed_fov) = 0;
   virtual int autotune(const dem_gas *g) = 0;
+  virtual int set_launch(int step_block, int step_xcd_chunk, int build_grid) = 0;
   virtual int grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, double *J, double *grad) = 0;
   virtual int profile(int enable) = 0;
   virtual int sync() = 0;
@@ -873,6 +874,17 @@ struct Ctx final : dem_ctx {
     return sync();
   }
 
+  int set_launch(int b, int x, int gsz) override {
+    if (!(b == 64 || b == 128 || b == 256 || b == 512) || x < 1 || x > 64 || gsz < 1 || gsz > 65536)
+      return fail(DEMRX_EINVAL, "launch shape out of range (step block 64/128/256/512, XCD chunk 1..64, "
+                                "build grid 1..65536)");
+    step_block = b;
+    step_xcd = x;
+    build_grid = gsz;
+    if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; gkey.clear(); }
+    return DEMRX_OK;
+  }
+
   int grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, double *J, double *gr) override;
   struct {
     void *base = nullptr;
@@ -982,6 +994,9 @@ int dem_run(dem_ctx *c, int32_t n_int, int32_t S, const dem_gas *g, dem_sources 
   return c ? c->run(n_int, S, g, o, bed_fov) : DEMRX_EINVAL;
 }
 int dem_autotune(dem_ctx *c, const dem_gas *g) { return c ? c->autotune(g) : DEMRX_EINVAL; }
+int dem_set_launch(dem_ctx *c, int32_t step_block, int32_t step_xcd_chunk, int32_t build_grid) {
+  return c ? c->set_launch(step_block, step_xcd_chunk, build_grid) : DEMRX_EINVAL;
+}
 int dem_profile(dem_ctx *c, int32_t enable) { return c ? c->profile(enable) : DEMRX_EINVAL; }
 int dem_sync(dem_ctx *c) { return c ? c->sync() : DEMRX_EINVAL; }
 const char *dem_last_error(const dem_ctx *c) { return c ? c->err.c_str() : g_init_err.c_str(); }

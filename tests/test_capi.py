@@ -59,6 +59,7 @@ def test_host_validation_rejects_null_and_bad_arguments():
     xin = (C.c_double * 2)(0.7, 0.0)
     assert L.dem_gas_species(None, 1e-4, None, None, None, xin, None, None, None) == -1
     assert L.dem_react(None, 1e-4, None, None, None, None) == -1
+    assert L.dem_set_launch(None, 64, 1, 1024) == -1
 
 
 def test_bad_grid_rejected_on_host():

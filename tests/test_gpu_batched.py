@@ -73,3 +73,34 @@ def test_empty_bed_in_a_batch():
         sel = torch.as_tensor(np.flatnonzero(ids == b), device=sb["x"].device)
         for k in ("x", "z", "vz", "nh", "nfe"):
             assert torch.equal(s1[k], sb[k][sel]), (b, k)
+
+
+def test_results_do_not_depend_on_launch_shapes():
+    """Two contexts on the same beds, one in the smallest and one in the
+    largest launch shapes (dem_set_launch), step bit-identically through
+    graph-replayed coupling intervals with neighbour rebuilds; out-of-range
+    shapes are rejected and leave the context usable."""
+    w = W.with_velocities(W.squeeze(W.cfg5(n_beds=4, n_scale=0.05, seed=93), 0.97, 0), 93)
+    _say(f"[launch] {len(w.beds)} beds, {w.n} parcels")
+    out = []
+    for shape in ((64, 1, 1), (512, 64, 2048)):
+        bed = Bed(w)
+        bed.set_launch(*shape)
+        o = bed.run(3, 20, sources=True, bed_fov=True)
+        out.append((bed.state(), o, bed.pairs()))
+        bed.close()
+    (s0, o0, p0), (s1, o1, p1) = out
+    assert np.array_equal(p0, p1) and len(p0) > 0
+    for k in s0:
+        assert torch.equal(s0[k], s1[k]), k
+    for k in o0:
+        if k == "bed_fov":
+            assert np.array_equal(o0[k], o1[k])
+        else:
+            assert torch.equal(o0[k], o1[k]), k
+    bed = Bed(w)
+    for bad in ((96, 1, 1), (64, 0, 1), (64, 65, 1), (64, 1, 0)):
+        with pytest.raises(Exception):
+            bed.set_launch(*bad)
+    bed.run(1, 20)
+    bed.close()
