@@ -49,11 +49,44 @@ __device__ __forceinline__ void cross(const T a[3], const T b[3], T c[3]) {
   c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// Neighbour position records requested kLand at a time land in LDS
+// (global_load_lds: 16 B per lane and instruction, written lane-major as a
+// 1 KB row) instead of registers.  That frees the 32 VGPRs the records in
+// flight took, which brings the kernel to 5 waves per SIMD; each wave owns
+// kLand record rows of 2 KB (8 KB, so 20 waves fill a CU's 160 KB of LDS).
+// The rows are read back by the lane that requested them, after a wait on
+// the vector-memory counter, which the LDS writes of these loads decrement.
+constexpr int kLand = 4;
+constexpr int kLandWaveBytes = kLand * 2048;
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ void land_pos(const PosRec *p, int j, unsigned char *row) {
+  const unsigned char *g = reinterpret_cast<const unsigned char *>(p + j);
+  __builtin_amdgcn_global_load_lds((const void *)g, (lds_void *)row, 16, 0, 0);
+  __builtin_amdgcn_global_load_lds((const void *)(g + 16), (lds_void *)(row + 1024), 16, 0, 0);
+}
+__device__ __forceinline__ PosRec landed_pos(const unsigned char *row) {
+  const int l = (int)(threadIdx.x & 63) * 16;
+  const double2 a = *reinterpret_cast<const double2 *>(row + l);
+  const double2 b = *reinterpret_cast<const double2 *>(row + 1024 + l);
+  PosRec r;
+  r.x = a.x;
+  r.y = a.y;
+  r.z = b.x;
+  const uint64_t bits = (uint64_t)__double_as_longlong(b.y);
+  r.r = __uint_as_float((uint32_t)bits);
+  r.id = (uint32_t)(bits >> 32);
+  return r;
+}
+// wait for every outstanding vector-memory load (the landed rows included)
+__device__ __forceinline__ void land_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // The DEM step of parcel i (sorted index): contacts over its candidate list,
 // walls, body and gas forces, integration.  Accumulates the displacement
 // maximum and the contact counts of the calling thread.
 template <typename T>
-__device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, float &dmax2, int &n_pp, int &n_w) {
+__device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, float &dmax2, int &n_pp, int &n_w,
+                                            unsigned char *wl) {
   const long N = a.n;
   {
     const PosRec P = load_pos(a.in.pos, i);
@@ -137,18 +170,18 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
       }
       n_pp++;
     };
-    constexpr int kPre = 4;
+    constexpr int kPre = kLand;
     for (int t0 = 0; t0 < c_near; t0 += kPre) {
       int jj[kPre];
-      PosRec Qs[kPre];
 #pragma unroll
       for (int k = 0; k < kPre; k++) jj[k] = (t0 + k < c_near) ? a.nb.idx[(long)(cap - 1 - t0 - k) * N + i] : -1;
 #pragma unroll
       for (int k = 0; k < kPre; k++)
-        if (jj[k] >= 0) Qs[k] = load_pos(a.in.pos, jj[k]);
+        if (jj[k] >= 0) land_pos(a.in.pos, jj[k], wl + k * 2048);
+      land_wait();
 #pragma unroll
       for (int k = 0; k < kPre; k++)
-        if (jj[k] >= 0) pair(cap - 1 - t0 - k, jj[k], Qs[k]);
+        if (jj[k] >= 0) pair(cap - 1 - t0 - k, jj[k], landed_pos(wl + k * 2048));
     }
     {
       // far region: the next group's indices are requested while the
@@ -158,17 +191,17 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
       for (int k = 0; k < kPre; k++) jn[k] = (k < c_far) ? a.nb.idx[(long)k * N + i] : -1;
       for (int t0 = 0; t0 < c_far; t0 += kPre) {
         int jj[kPre];
-        PosRec Qs[kPre];
 #pragma unroll
         for (int k = 0; k < kPre; k++) jj[k] = jn[k];
 #pragma unroll
         for (int k = 0; k < kPre; k++)
-          if (jj[k] >= 0) Qs[k] = load_pos(a.in.pos, jj[k]);
+          if (jj[k] >= 0) land_pos(a.in.pos, jj[k], wl + k * 2048);
 #pragma unroll
         for (int k = 0; k < kPre; k++) jn[k] = (t0 + kPre + k < c_far) ? a.nb.idx[(long)(t0 + kPre + k) * N + i] : -1;
+        land_wait();
 #pragma unroll
         for (int k = 0; k < kPre; k++)
-          if (jj[k] >= 0) pair(t0 + k, jj[k], Qs[k]);
+          if (jj[k] >= 0) pair(t0 + k, jj[k], landed_pos(wl + k * 2048));
       }
     }
     mnew = cbits;
@@ -320,14 +353,17 @@ __device__ __forceinline__ void step_skin_check(const StepArgs<T> &a) {
   }
 }
 
-// One thread per parcel over the sorted order.
+// One thread per parcel over the sorted order; (block / 64) * 8 KB of dynamic
+// LDS for the landed neighbour records.
 template <typename T>
-__global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 1) k_step(StepArgs<T> a) {
+__global__ void __launch_bounds__(512, sizeof(T) == 4 ? 5 : 1) k_step(StepArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char lds[];
   const int i = (a.xcd > 1 ? xcd_block(a.xcd) : (int)blockIdx.x) * blockDim.x + threadIdx.x;
   step_skin_check(a);
   float dmax2 = 0.0f;
   int n_pp = 0, n_w = 0;
-  if (i < a.n) step_parcel(a, i, dmax2, n_pp, n_w);
+  unsigned char *wl = lds + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * kLandWaveBytes;
+  if (i < a.n) step_parcel(a, i, dmax2, n_pp, n_w, wl);
   step_flush(a, dmax2, n_pp, n_w);
 }
 
@@ -335,7 +371,7 @@ template <typename T>
 void launch_step(const StepArgs<T> &a, int block, hipStream_t s) {
   const int q = 8 * (a.xcd > 1 ? a.xcd : 1);  // grid: a multiple of 8 chunks for the XCD remap
   const int g = ((a.n + block - 1) / block + q - 1) / q * q;
-  k_step<T><<<g, block, 0, s>>>(a);
+  k_step<T><<<g, block, (size_t)(block / 64) * kLandWaveBytes, s>>>(a);
 }
 
 
