@@ -102,6 +102,35 @@ def test_grad_vs_finite_differences():
     bed.close()
 
 
+def test_grad_full_size_vs_finite_differences():
+    """The 500,000-parcel gradient workload over its whole protocol (20,000
+    substeps of 1e-4 s, one DEM step per 10, checkpoints every 500) as the
+    benchmark runs it: the FP32-state adjoint against central differences
+    (h = 1e-4 relative) of FP64-state forward runs, each component within
+    1e-3 of the largest of its kind; J of the FP32 state within 1e-5 of the
+    FP64 state's."""
+    w = W.cfg4()
+    spec = W.grad_spec_cfg4()
+    args = (spec["n_substeps"], spec["dt_react"], spec["dyn_every"], spec["ckpt_every"])
+    _say(f"[adjoint] full size: n={w.n} substeps={args[0]}")
+    bed = Bed(w)
+    J, g = bed.grad(*args, TH, state_fp32=True)
+    J64, _ = bed.grad(*args, TH, state_fp32=False, with_grad=False)
+    fd = np.zeros(6)
+    for q in range(6):
+        h = 1e-4 * abs(TH[q])
+        Jq = []
+        for sgn in (1.0, -1.0):
+            tq = TH.copy()
+            tq[q] += sgn * h
+            Jq.append(bed.grad(*args, tq, state_fp32=False, with_grad=False)[0])
+        fd[q] = (Jq[0] - Jq[1]) / (2 * h)
+    bed.close()
+    _say(f"  J {J:.9f} (FP64 state {J64:.9f}); grad err vs FP64 differences {_grad_err(g, fd):.3e}")
+    assert abs(J - J64) <= 1e-5
+    assert _grad_err(g, fd) <= 1e-3
+
+
 def test_grad_leaves_state_and_repeats():
     """dem_grad restores the DEM state; a plain forward gives the same J; a
     second call gives the same result bit for bit."""
