@@ -551,6 +551,11 @@ def test_ganser_drag_forces_and_sums(case):
     bed.close()
 
 
+def test_cylinder_bed_200k_full_size_one_step():
+    """The 200,000-parcel cylindrical bed (k = 3, FP32 forces) at full size."""
+    _full_size_check(W.cfg2, 0.97, "cfg2")
+
+
 def test_batched_workload_full_size_one_step():
     """The 64-bed workload at full size (1,757,123 parcels) in the autotuned
     launch shapes the benchmark uses."""
