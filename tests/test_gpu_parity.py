@@ -267,6 +267,35 @@ def test_trajectory_100_steps(case):
     assert bed.stats()["n_contacts"] > 0
 
 
+def test_trajectory_full_size_cylinder_bed():
+    """The 200,000-parcel cylindrical bed, lightly pressed (about 10,000
+    contacts) and in slow random motion, 100 steps in the autotuned launch
+    shapes with the workload's own skin and rebuild period: the mixed-path
+    trajectory bar of the test above."""
+    w = W.with_velocities(W.squeeze(W.cfg2(), 0.985, 0), 17, vscale=0.03, wscale=20.0)
+    _say(f"[trajectory] full size n={w.n}")
+    bed = Bed(w)
+    bed.autotune()
+    ora = O.Oracle(w)
+    assert len(ora.pairs()) > 5000
+    for _ in range(10):
+        bed.step(10)
+        ora.step(10)
+    sg, so = bed.state(), ora.state()
+    d = w.parcels["d"].astype(np.float64)
+    ex = np.sqrt(sum((_np(sg[k]) - so[k]) ** 2 for k in ("x", "y", "z"))) / d
+    vo = np.stack([so[k] for k in ("vx", "vy", "vz")], 1)
+    vg = np.stack([_np(sg[k]) for k in ("vx", "vy", "vz")], 1)
+    ev = np.linalg.norm(vg - vo, axis=1) / np.maximum(np.linalg.norm(vo, axis=1), 1e-3)
+    for name, e in (("x", ex), ("v", ev)):
+        out = int(np.sum(e > 1e-4))
+        _say(f"  {name}: max {e.max():.2e}, parcels beyond 1e-4: {out} of {w.n}")
+        assert out <= w.n // 1000, (name, out)
+    assert ex.max() <= 1e-2
+    assert bed.stats()["n_contacts"] > 5000
+    bed.close()
+
+
 @pytest.mark.parametrize("case", list(GENTLE))
 def test_couple_and_react_at_identical_state(case):
     w = GENTLE[case]()
