@@ -467,7 +467,9 @@ def cfg5(n_beds=64, seed=5, steps=1000, n_scale=1.0):
     rng = np.random.Generator(np.random.PCG64(ss.spawn(1)[0]))
     gas = _gas(rng, beds, Ts, xs, 0.0, (0.0, 0.0, 0.5), 0.0, False)
     offs = np.concatenate([[0], np.cumsum([bd.n_cells for bd in beds])[:-1]])
-    params = base_params(dt=5e-6, skin=2e-4, rebuild_every=20)
+    # lists rebuilt every 40 steps: the skin holds while no parcel moves more
+    # than skin/2 in 40 steps (0.5 m/s); the step reports a violation
+    params = base_params(dt=5e-6, skin=2e-4, rebuild_every=40)
     return Workload("cfg5", "mixed", params, beds, [ore], parcels, gas, offs, steps, 20)
 
 
@@ -496,9 +498,9 @@ def sweep(n_scale=1.0, seed=6, steps=500, beds=SWEEP_BEDS):
     d_p 0.35 mm (+-10 %), k = 3, 5,095,837 real particles in a 68 x 200 mm
     cylinder, 4.25 mm gas cells, 65 % H2 in N2 at 110000 Pa.  n_scale scales
     the parcel counts (and the cylinders by its cube root).  One DEM step of
-    5 us for all beds (Bed I's), coupling every 20 steps; kn = 100 N/m, the
-    linear stiffness a Hertzian contact with Y = 1e7 Pa gives the Bed I
-    parcels at 1 % overlap."""
+    5 us for all beds (Bed I's), coupling every 20 steps, lists rebuilt every
+    40; kn = 100 N/m, the linear stiffness a Hertzian contact with Y = 1e7 Pa
+    gives the Bed I parcels at 1 % overlap."""
     ss = np.random.SeedSequence(seed)
     kids = ss.spawn(len(beds) + 1)
     ores = [Ore(xi0=0.29, d_pore_cm=9.5e-6, kind=ORE_MAGNETITE, psi=0.85),
@@ -528,7 +530,8 @@ def sweep(n_scale=1.0, seed=6, steps=500, beds=SWEEP_BEDS):
     parcels = {k: np.ascontiguousarray(np.concatenate([p[k] for p in parts])) for k in parts[0]}
     gas = {k: np.ascontiguousarray(np.concatenate([g[k] for g in gases])) for k in gases[0]}
     offs = np.concatenate([[0], np.cumsum([bd.n_cells for bd in bl])[:-1]])
-    params = base_params(dt=5e-6, skin=1e-4, rebuild_every=10, kn=100.0)
+    # lists rebuilt every 40 steps: the skin holds up to 0.25 m/s
+    params = base_params(dt=5e-6, skin=1e-4, rebuild_every=40, kn=100.0)
     return Workload("sweep", "mixed", params, bl, ores, parcels, gas, offs, steps, 20)
 
 
