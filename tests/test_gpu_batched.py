@@ -75,13 +75,17 @@ def test_empty_bed_in_a_batch():
             assert torch.equal(s1[k], sb[k][sel]), (b, k)
 
 
-def test_results_do_not_depend_on_launch_shapes():
+@pytest.mark.parametrize("case", ["mixed_batch", "fp64_box"])
+def test_results_do_not_depend_on_launch_shapes(case):
     """Two contexts on the same beds, one in the smallest and one in the
     largest launch shapes (dem_set_launch), step bit-identically through
     graph-replayed coupling intervals with neighbour rebuilds; out-of-range
     shapes are rejected and leave the context usable."""
-    w = W.with_velocities(W.squeeze(W.cfg5(n_beds=4, n_scale=0.05, seed=93), 0.97, 0), 93)
-    _say(f"[launch] {len(w.beds)} beds, {w.n} parcels")
+    if case == "mixed_batch":
+        w = W.with_velocities(W.squeeze(W.cfg5(n_beds=4, n_scale=0.05, seed=93), 0.97, 0), 93)
+    else:
+        w = W.with_velocities(W.squeeze(W.cfg1(), 0.995, 0), 94, vscale=0.05, wscale=20.0)
+    _say(f"[launch] {case}: {len(w.beds)} beds, {w.n} parcels")
     out = []
     for shape in ((64, 1, 1), (512, 64, 2048)):
         bed = Bed(w)
