@@ -2,7 +2,10 @@
 // soft-sphere parcel-parcel and parcel-wall forces with tangential springs,
 // Gidaspow drag + gravity + pressure-gradient force, semi-implicit Euler.
 // One thread per parcel in cell-sorted order; the step reads buffer `in` and
-// writes buffer `out`, so no parcel sees a partner's updated state.
+// writes buffer `out`, so no parcel sees a partner's updated state.  Mode 0
+// integrates; mode 1 writes the forces and torques instead (state unchanged);
+// mode 2 is the autotuner's timing run, which skips the spring, mask and
+// reduction writes.
 #include "launch.h"
 
 namespace demrx {
@@ -110,7 +113,7 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
     // nearly every lane has a contact), so neighbour indices and the
     // slot-major tangential springs of one visit are contiguous rows.
     // Indices and position records are requested kPre slots at a time so
-    // that the gathers overlap.
+    // that the gathers overlap; the records land in the wave's LDS rows.
     const int c_near = cnt >> 16, c_far = cnt & 0xffff;
     const int cap = a.ph.max_nbr;
     uint64_t cbits = 0;
