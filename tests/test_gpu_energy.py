@@ -132,3 +132,36 @@ def test_set_state_temperature_and_isothermal_gradient_only():
     with pytest.raises(DemError) as e:
         bed.grad(10, 0.1, 10, 10, W.THETA_HEMATITE_FIT)
     assert e.value.code == -1
+
+
+def test_energy_full_size_cylinder_bed():
+    """The 200,000-parcel cylinder bed with the energy equation on, in the
+    autotuned launch shapes: heat sums at identical state within 1e-12
+    relative, then T_p after three intervals of 20 steps and a reaction
+    update within the mixed-path bar (1e-4 K)."""
+    w = W.with_energy(W.with_velocities(W.squeeze(W.cfg2(), 0.985, 0), 33, vscale=0.03, wscale=20.0),
+                      -40.0, seed=33, spread=15.0)
+    _say(f"[energy] full size n={w.n}")
+    bed = Bed(w)
+    bed.autotune()
+    ora = O.Oracle(w)
+    dt = 20 * w.params["dt"]
+    bed.couple()
+    ora.couple()
+    rg, ro = bed.react(dt), ora.react(dt)
+    for k in ("hA", "hAT", "Qrm", "Hr"):
+        assert _rel(_np(rg[k]), ro[k]) <= 1e-12, k
+    T0 = w.parcels["Tp"].copy()
+    for _ in range(3):
+        bed.step(20)
+        ora.step(20)
+        bed.couple()
+        ora.couple()
+        bed.react(dt)
+        ora.react(dt)
+    err = np.abs(_np(bed.state()["Tp"]) - ora.state()["Tp"])
+    moved = np.abs(ora.state()["Tp"] - T0)
+    _say(f"  max |dT| {moved.max():.3f} K, max err {err.max():.2e} K")
+    assert moved.max() > 0.02
+    assert err.max() <= 1e-4
+    bed.close()
