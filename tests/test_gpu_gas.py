@@ -32,10 +32,16 @@ def _np(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("case", ["cfg1_fp64", "cfg2_mixed"])
+@pytest.mark.parametrize("case", ["cfg1_fp64", "cfg2_mixed", "cfg2_full_size"])
 def test_gas_step_at_identical_state(case):
-    w = (W.with_velocities(W.squeeze(W.cfg1(), 0.995, 0), 41) if case == "cfg1_fp64"
-         else W.with_velocities(W.squeeze(W.cfg2(n=3000, seed=42), 0.995, 0), 42, vscale=0.03))
+    """The gas-side step from the particles' sources; cfg2_full_size is the
+    200,000-parcel bed on its 32 x 32 x 160 gas grid."""
+    if case == "cfg1_fp64":
+        w = W.with_velocities(W.squeeze(W.cfg1(), 0.995, 0), 41)
+    elif case == "cfg2_mixed":
+        w = W.with_velocities(W.squeeze(W.cfg2(n=3000, seed=42), 0.995, 0), 42, vscale=0.03)
+    else:
+        w = W.with_velocities(W.squeeze(W.cfg2(), 0.985, 0), 44, vscale=0.03)
     _say(f"[gas] {case} n={w.n}")
     bed = Bed(w)
     ora = O.Oracle(w)
