@@ -244,33 +244,70 @@ def bench_sweep(log=True):
             "fov_300s": c[299].tolist(), "fov_600s": c[599].tolist(), "t90_s": t90}
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, S):
-    """The oracle as it stands (single thread) on the full bed: two DEM steps
-    and one coupling (deposit + reaction), the coupling amortised over S steps."""
+    """The oracle as it stands, built -O3 -march=native for this host, on the
+    full bed: one DEM step plus one coupling (deposit with drag sums, reaction
+    with cell sources) amortised over S steps, first on one thread, then on
+    every thread OpenMP is given (OMP_NUM_THREADS, else all cores).  The two
+    runs start from the same state and must give bit-identical results."""
+    import tempfile
+
+    import numpy as np
+
     from oracle import oracle as O
 
-    _log("[bench] cpu baseline: oracle init")
-    ora = O.Oracle(w)
-    t0 = time.perf_counter()
-    ora.step(2)
-    t1 = time.perf_counter()
-    ora.couple()
-    ora.react(S * w.params["dt"])
-    t2 = time.perf_counter()
-    t_step = (t1 - t0) / 2
-    t_couple = t2 - t1
-    rate = w.n / (t_step + t_couple / S)
-    _log(f"[bench] cpu: step {t_step:.2f} s, coupling {t_couple:.2f} s")
-    return {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"full {w.n}-parcel bed: 2 DEM steps + 1 deposit/reaction amortised over {S} steps, "
-                      f"single thread"}
+    path = os.path.join(tempfile.mkdtemp(prefix="ora_native_"), "libora_native.so")
+    O.build_native(path)
+    O.use_library(path)
+    all_threads = O.host_threads()
+
+    def one(threads):
+        O.set_threads(threads)
+        ora = O.Oracle(w)
+        t0 = time.perf_counter()
+        ora.step(1)
+        t1 = time.perf_counter()
+        c = ora.couple()
+        r = ora.react(S * w.params["dt"])
+        t2 = time.perf_counter()
+        st = ora.state()
+        res = [st[k] for k in ("x", "y", "z", "vx", "vy", "vz", "nh")] + [c["sumK"], r["sumEQ"], r["fov"]]
+        del ora
+        return t1 - t0, t2 - t1, res
+
+    _log("[bench] cpu baseline: oracle, one thread")
+    s1, c1, r1 = one(1)
+    _log(f"[bench] cpu (1 thread): step {s1:.2f} s, coupling {c1:.2f} s")
+    _log(f"[bench] cpu baseline: oracle, {all_threads} threads")
+    sn, cn, rn = one(all_threads)
+    _log(f"[bench] cpu ({all_threads} threads): step {sn:.2f} s, coupling {cn:.2f} s")
+    same = all(np.array_equal(a, b) for a, b in zip(r1, rn))
+    rate1 = w.n / (s1 + c1 / S)
+    raten = w.n / (sn + cn / S)
+    return {"value": raten, "unit": "particle-steps/s", "cores": all_threads, "kind": "oracle",
+            "sample": f"full {w.n}-parcel bed: 1 DEM step + 1 coupling (deposit with drag sums, reaction with cell "
+                      f"sources) amortised over {S} steps; oracle built -O3 -march=native -ffp-contract=off",
+            "single_thread_value": rate1, "nproc": os.cpu_count(),
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS"), "cpu_model": _cpu_model(),
+            "identical_to_single_thread": bool(same)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=120)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=None, help="parcel count (default: the 2M-parcel bed)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -320,29 +357,26 @@ def main():
         _log(f"[bench] saved settled state to {args.save_settled}")
         return
     S = w.couple_every
-    # one graph replays G coupling intervals (rebuild schedule); the timed
-    # region ends with one interval launched eagerly, whose step-kernel
-    # launches carry the HIP events that time the kernel
-    G = 2 * max(1, w.params["rebuild_every"] // S)
-    n_int = max(G + 1, (args.steps + S - 1) // S)
-    if n_int % G == 0:
-        n_int += 1
+    # whole coupling intervals: the timed steps are the requested count rounded
+    # down to a multiple of the coupling interval (at least one interval), the
+    # warm-up rounded up
+    n_int = max(1, args.steps // S)
     steps = n_int * S
-    warm = max(G * S, (args.warmup + S - 1) // S * S)
+    warm_int = max(1, -(-args.warmup // S))
+    warm = warm_int * S
     _log(f"[bench] n={w.n} steps={steps} warmup={warm}")
     bed = Bed(w, device="cuda:0")
     if args.launch:
         bed.set_launch(*[int(v) for v in args.launch.split(",")])
     else:
         bed.autotune()
-    bed.profile(True)  # the replay graph is captured with the timing events
-    bed.run(warm // S, S)
+    bed.run(warm_int, S, sources=True)
     bed.sync()
-    bed.profile(True)  # keep only the timed region's step-kernel timings
     torch.cuda.synchronize()
+    st0 = bed.stats()
     _log("[bench] timed region")
     t0 = time.perf_counter()
-    bed.run(n_int, S)
+    bed.run(n_int, S, sources=True)
     bed.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -350,11 +384,21 @@ def main():
     elapsed = t1 - t0
     rate = w.n * steps / elapsed
     z = st["mean_coordination"]
-    k_ms = st["step_kernel_ms"]
+    rebuilds = st["rebuilds"] - st0["rebuilds"]
+    # the step kernel's duration: one more interval after the timed region,
+    # launched eagerly on the same stream with HIP events around each step
+    # kernel (events recorded inside replayed graphs report no time)
+    bed.profile(True)
+    bed.step(S)
+    bed.couple()
+    bed.react(S * w.params["dt"], fov=False)
+    k_ms = bed.stats()["step_kernel_ms"]
+    k_launches = bed.stats()["step_kernel_launches"]
+    bed.profile(False)
     bpu = step_bytes(z)
     achieved = w.n * bpu / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None
     traffic = traffic_from_profile(os.path.join(ROOT, "paper_2311_03908_amd", "csrc", "k_step.hip"))
-    _log(f"[bench] {rate:.4e} particle-steps/s, step kernel {k_ms * 1e3:.1f} us, z={z:.3f}")
+    _log(f"[bench] {rate:.4e} particle-steps/s, step kernel {k_ms * 1e3:.1f} us, z={z:.3f}, rebuilds {rebuilds}")
     out = {
         "metric": "particle-steps/s",
         "value": rate,
@@ -371,12 +415,13 @@ def main():
         "config": {"workload": "polydisperse cylindrical fixed bed: 2,000,000 parcels, lognormal d_p (median "
                                "100 um, sigma 0.3), k=5, 2 ore types, 100x600 mm cylinder, 64x64x384 gas grid, "
                                "H2 at 1073 K, dt=5e-6 s, coupling every 20 steps, settled under gravity",
-                   "parcels": w.n, "couple_every": S, "graph": True,
+                   "parcels": w.n, "couple_every": S, "graph": n_int >= 2, "sources": "all (eps, drag sums, "
+                   "species sources) every coupling", "rebuilds_timed": rebuilds,
                    "settle_steps": 0 if args.settled else args.settle_steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                      "kernel": "k_step (fused contact + drag + integrate)", "bytes_per_parcel_step": bpu,
-                     "kernel_ms": k_ms, "launches_timed": st["step_kernel_launches"], "z_mean": z,
+                     "kernel_ms": k_ms, "launches_timed": k_launches, "z_mean": z,
                      "launch": {"step_block": st["step_block"], "step_xcd_chunk": st["step_xcd"],
                                 "build_grid": st["build_grid"], "rebuild_period": st["rebuild_period"]}},
     }

@@ -2,9 +2,10 @@
  * Oracle for the particle side of the coarse-grained CFD-DEM reduction model
  * of arxiv 2311.03908.  TEST INFRASTRUCTURE ONLY (see ora.h).
  *
- * Plain FP64, single thread, ascending-id loops, built with
- * -ffp-contract=off so that the contact predicate is evaluated exactly as
- * written.  Function headers cite the paper's equations; readings of passages
+ * Plain FP64, ascending-id sums, built with -ffp-contract=off so that the
+ * contact predicate is evaluated exactly as written.  Loops over independent
+ * parcels or pairs may run on several threads (OpenMP); sums never do, so
+ * the results do not depend on the thread count.  Function headers cite the paper's equations; readings of passages
  * the paper leaves open are marked "reading:".
  */
 #include "ora.h"
@@ -12,6 +13,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define RG 8.314 /* gas constant, Section 2.1 */
 #define PI 3.14159265358979323846
@@ -497,6 +501,24 @@ void ora_free(ora_sys *s) {
 
 int ora_n_cells(const ora_sys *s) { return s->n_cells; }
 
+/* Threads of the parallel loops (builds with OpenMP; 1 otherwise).  Every
+ * result is the same for any thread count: loops run over independent
+ * parcels or pairs, and every sum runs in ascending id order. */
+void ora_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+int ora_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 /* ------------------------------------------------------------ contact detection */
 static int in_contact(const ora_sys *s, int a, int b) {
   double dx = s->pos[3 * b] - s->pos[3 * a];
@@ -513,96 +535,148 @@ static int cmp_pair(const void *p, const void *q) {
   return 0;
 }
 
-/* All contacting pairs a < b (same bed), sorted.  *out is malloc'ed. */
+/* Partners b > a of parcel a in contact, from the bins of a's bed (edge >=
+ * the bed's largest diameter, members contiguous in bin order); written to
+ * out (may be NULL) in the bins' order.  Returns the count. */
+typedef struct {
+  int nc[3];
+  double lo[3], cs[3];
+  long *first;   /* bin b holds sorted[first[b] .. first[b+1]) */
+  int *sorted;   /* parcel ids in bin order */
+  double *q;     /* x, y, z, r of sorted[t] */
+} bins_t;
+
+static int bin_partners(const ora_sys *s, const bins_t *B, int a, int *out) {
+  int c3[3], m = 0;
+  for (int k = 0; k < 3; k++) {
+    double f = floor((s->pos[3 * a + k] - B->lo[k]) / B->cs[k]);
+    if (f < 0) f = 0;
+    if (f > B->nc[k] - 1) f = B->nc[k] - 1;
+    c3[k] = (int)f;
+  }
+  double ra = radius(s, a);
+  for (int oz = -1; oz <= 1; oz++)
+    for (int oy = -1; oy <= 1; oy++)
+      for (int ox = -1; ox <= 1; ox++) {
+        int x2 = c3[0] + ox, y2 = c3[1] + oy, z2 = c3[2] + oz;
+        if (x2 < 0 || y2 < 0 || z2 < 0 || x2 >= B->nc[0] || y2 >= B->nc[1] || z2 >= B->nc[2]) continue;
+        long c2 = x2 + (long)B->nc[0] * (y2 + (long)B->nc[1] * z2);
+        for (long tb = B->first[c2]; tb < B->first[c2 + 1]; tb++) {
+          int b = B->sorted[tb];
+          if (b <= a) continue;
+          /* the contact predicate of in_contact(), on the bin-ordered copy */
+          double dx = B->q[4 * tb] - s->pos[3 * a];
+          double dy = B->q[4 * tb + 1] - s->pos[3 * a + 1];
+          double dz = B->q[4 * tb + 2] - s->pos[3 * a + 2];
+          double sr = ra + B->q[4 * tb + 3];
+          if (!(((dx * dx + dy * dy) + dz * dz) < sr * sr)) continue;
+          if (out) out[m] = b;
+          m++;
+        }
+      }
+  return m;
+}
+
+/* All contacting pairs a < b (same bed), sorted by (a, b).  *out is
+ * malloc'ed.  The cell list collects each parcel's partners on its own (in
+ * parallel when built with OpenMP: a count pass, offsets in id order, a fill
+ * pass, and each parcel's short list sorted), so the list does not depend on
+ * the thread count. */
 static long find_pairs(ora_sys *s, int brute, int **out) {
   long cap = 1024, cnt = 0;
-  int *pr = (int *)malloc(sizeof(int) * 2 * cap);
+  int *pr = NULL;
   if (brute) {
+    pr = (int *)malloc(sizeof(int) * 2 * cap);
     for (int a = 0; a < s->n; a++)
       for (int b = a + 1; b < s->n; b++)
         if (s->bed[a] == s->bed[b] && in_contact(s, a, b)) {
           if (cnt == cap) { cap *= 2; pr = (int *)realloc(pr, sizeof(int) * 2 * cap); }
           pr[2 * cnt] = a; pr[2 * cnt + 1] = b; cnt++;
         }
-  } else {
-    /* cell list: bins of edge >= the largest diameter, parcels copied in
-     * bin order so that each bin's members are contiguous */
-    for (int bd = 0; bd < s->P.n_beds; bd++) {
-      const ora_bed *B = &s->beds[bd];
-      double hc = 0.0;
-      int nb = 0;
-      for (int i = 0; i < s->n; i++)
-        if (s->bed[i] == bd) {
-          nb++;
-          if (s->d[i] > hc) hc = s->d[i];
-        }
-      if (nb == 0) continue;
-      int nc[3];
-      double cs[3];
+    qsort(pr, cnt, 2 * sizeof(int), cmp_pair);
+    *out = pr;
+    return cnt;
+  }
+  int n = s->n, nb_ = s->P.n_beds;
+  bins_t *bins = (bins_t *)calloc(nb_ > 0 ? nb_ : 1, sizeof(bins_t));
+  /* bins of edge >= the largest diameter of each bed */
+  for (int bd = 0; bd < nb_; bd++) {
+    const ora_bed *Bd = &s->beds[bd];
+    bins_t *B = &bins[bd];
+    double hc = 0.0;
+    int nb = 0;
+    for (int i = 0; i < n; i++)
+      if (s->bed[i] == bd) {
+        nb++;
+        if (s->d[i] > hc) hc = s->d[i];
+      }
+    if (nb == 0) continue;
+    for (int a = 0; a < 3; a++) {
+      B->nc[a] = (int)floor((Bd->hi[a] - Bd->lo[a]) / hc);
+      if (B->nc[a] < 1) B->nc[a] = 1;
+      B->lo[a] = Bd->lo[a];
+      B->cs[a] = (Bd->hi[a] - Bd->lo[a]) / B->nc[a];
+    }
+    long ncell = (long)B->nc[0] * B->nc[1] * B->nc[2];
+    B->first = (long *)calloc(ncell + 1, sizeof(long));
+    long *cellof = (long *)malloc(sizeof(long) * nb);
+    int *member = (int *)malloc(sizeof(int) * nb);
+    int m = 0;
+    for (int i = 0; i < n; i++) {
+      if (s->bed[i] != bd) continue;
+      int c3[3];
       for (int a = 0; a < 3; a++) {
-        nc[a] = (int)floor((B->hi[a] - B->lo[a]) / hc);
-        if (nc[a] < 1) nc[a] = 1;
-        cs[a] = (B->hi[a] - B->lo[a]) / nc[a];
+        double f = floor((s->pos[3 * i + a] - B->lo[a]) / B->cs[a]);
+        if (f < 0) f = 0;
+        if (f > B->nc[a] - 1) f = B->nc[a] - 1;
+        c3[a] = (int)f;
       }
-      long ncell = (long)nc[0] * nc[1] * nc[2];
-      long *first = (long *)calloc(ncell + 1, sizeof(long));
-      long *cellof = (long *)malloc(sizeof(long) * nb);
-      int *member = (int *)malloc(sizeof(int) * nb);
-      double *q = (double *)malloc(sizeof(double) * 4 * nb);
-      int m = 0;
-      for (int i = 0; i < s->n; i++) {
-        if (s->bed[i] != bd) continue;
-        int c3[3];
-        for (int a = 0; a < 3; a++) {
-          double f = floor((s->pos[3 * i + a] - B->lo[a]) / cs[a]);
-          if (f < 0) f = 0;
-          if (f > nc[a] - 1) f = nc[a] - 1;
-          c3[a] = (int)f;
-        }
-        cellof[m] = c3[0] + (long)nc[0] * (c3[1] + (long)nc[1] * c3[2]);
-        first[cellof[m] + 1]++;
-        member[m++] = i;
+      cellof[m] = c3[0] + (long)B->nc[0] * (c3[1] + (long)B->nc[1] * c3[2]);
+      B->first[cellof[m] + 1]++;
+      member[m++] = i;
+    }
+    for (long c = 0; c < ncell; c++) B->first[c + 1] += B->first[c];
+    long *fill = (long *)malloc(sizeof(long) * ncell);
+    memcpy(fill, B->first, sizeof(long) * ncell);
+    B->sorted = (int *)malloc(sizeof(int) * nb);
+    for (int t = 0; t < nb; t++) B->sorted[fill[cellof[t]]++] = member[t];
+    B->q = (double *)malloc(sizeof(double) * 4 * nb);
+    for (int t = 0; t < nb; t++) {
+      int i = B->sorted[t];
+      B->q[4 * t] = s->pos[3 * i];
+      B->q[4 * t + 1] = s->pos[3 * i + 1];
+      B->q[4 * t + 2] = s->pos[3 * i + 2];
+      B->q[4 * t + 3] = radius(s, i);
+    }
+    free(cellof); free(member); free(fill);
+  }
+  long *off = (long *)malloc(sizeof(long) * (n + 1));
+  off[0] = 0;
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int a = 0; a < n; a++) off[a + 1] = bins[s->bed[a]].first ? bin_partners(s, &bins[s->bed[a]], a, NULL) : 0;
+  for (int a = 0; a < n; a++) off[a + 1] += off[a];
+  cnt = off[n];
+  pr = (int *)malloc(sizeof(int) * 2 * (cnt > 0 ? cnt : 1));
+  int *part = (int *)malloc(sizeof(int) * (cnt > 0 ? cnt : 1));
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int a = 0; a < n; a++) {
+    if (off[a + 1] == off[a]) continue;
+    int *seg = part + off[a];
+    int m = bin_partners(s, &bins[s->bed[a]], a, seg);
+    for (int u = 1; u < m; u++) /* insertion sort of a's few partners */
+      for (int v = u; v > 0 && seg[v - 1] > seg[v]; v--) {
+        int t = seg[v]; seg[v] = seg[v - 1]; seg[v - 1] = t;
       }
-      for (long c = 0; c < ncell; c++) first[c + 1] += first[c];
-      long *fill = (long *)malloc(sizeof(long) * ncell);
-      memcpy(fill, first, sizeof(long) * ncell);
-      int *sorted = (int *)malloc(sizeof(int) * nb);
-      for (int t = 0; t < nb; t++) sorted[fill[cellof[t]]++] = member[t];
-      for (int t = 0; t < nb; t++) {
-        int i = sorted[t];
-        q[4 * t] = s->pos[3 * i];
-        q[4 * t + 1] = s->pos[3 * i + 1];
-        q[4 * t + 2] = s->pos[3 * i + 2];
-        q[4 * t + 3] = radius(s, i);
-      }
-      for (long c = 0; c < ncell; c++) {
-        if (first[c] == first[c + 1]) continue;
-        int cx = (int)(c % nc[0]), cy = (int)((c / nc[0]) % nc[1]), cz = (int)(c / ((long)nc[0] * nc[1]));
-        for (int oz = -1; oz <= 1; oz++)
-          for (int oy = -1; oy <= 1; oy++)
-            for (int ox = -1; ox <= 1; ox++) {
-              int x2 = cx + ox, y2 = cy + oy, z2 = cz + oz;
-              if (x2 < 0 || y2 < 0 || z2 < 0 || x2 >= nc[0] || y2 >= nc[1] || z2 >= nc[2]) continue;
-              long c2 = x2 + (long)nc[0] * (y2 + (long)nc[1] * z2);
-              for (long ta = first[c]; ta < first[c + 1]; ta++)
-                for (long tb = first[c2]; tb < first[c2 + 1]; tb++) {
-                  int a = sorted[ta], b = sorted[tb];
-                  if (b <= a) continue;
-                  /* the contact predicate of in_contact(), on the bin-ordered copies */
-                  double dx = q[4 * tb] - q[4 * ta];
-                  double dy = q[4 * tb + 1] - q[4 * ta + 1];
-                  double dz = q[4 * tb + 2] - q[4 * ta + 2];
-                  double sr = q[4 * ta + 3] + q[4 * tb + 3];
-                  if (!(((dx * dx + dy * dy) + dz * dz) < sr * sr)) continue;
-                  if (cnt == cap) { cap *= 2; pr = (int *)realloc(pr, sizeof(int) * 2 * cap); }
-                  pr[2 * cnt] = a; pr[2 * cnt + 1] = b; cnt++;
-                }
-            }
-      }
-      free(first); free(cellof); free(member); free(q); free(fill); free(sorted);
+    for (int u = 0; u < m; u++) {
+      pr[2 * (off[a] + u)] = a;
+      pr[2 * (off[a] + u) + 1] = seg[u];
     }
   }
-  qsort(pr, cnt, 2 * sizeof(int), cmp_pair);
+  free(part); free(off);
+  for (int bd = 0; bd < nb_; bd++) {
+    free(bins[bd].first); free(bins[bd].sorted); free(bins[bd].q);
+  }
+  free(bins);
   *out = pr;
   return cnt;
 }
@@ -719,72 +793,110 @@ static const double *hist_lookup(const ora_sys *s, int a, int b) {
   return NULL;
 }
 
+/* One contact pair's terms in canonical orientation (a < b): force on a,
+ * the cross product n x F_t (torques r_a n x F_t on a and r_b n x F_t on b),
+ * |F_n|, the new tangential history and the force-term scales. */
+typedef struct {
+  double Fa[3], tq[3], fnabs, xi[3], sc[2];
+} pair_t;
+
+static void pair_terms(const ora_sys *s, int a, int b, pair_t *o) {
+  static const double zero3[3] = {0, 0, 0};
+  double dx[3], nv[3];
+  for (int c = 0; c < 3; c++) dx[c] = s->pos[3 * b + c] - s->pos[3 * a + c];
+  double dist = sqrt((dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2]);
+  double ra = radius(s, a), rb = radius(s, b);
+  for (int c = 0; c < 3; c++) nv[c] = dx[c] / dist;
+  double delta = (ra + rb) - dist;
+  double ma = s->mass[a], mb = s->mass[b];
+  double mstar = ma * mb / (ma + mb);
+  double kk = s->k[a] > s->k[b] ? s->k[a] : s->k[b];
+  double zeta = ora_zeta(ora_e_cgp(s->P.e_p, kk));
+  double wsum[3], cr[3], vrel[3];
+  for (int c = 0; c < 3; c++) wsum[c] = ra * s->omg[3 * a + c] + rb * s->omg[3 * b + c];
+  cross3(wsum, nv, cr);
+  for (int c = 0; c < 3; c++) vrel[c] = s->vel[3 * a + c] - s->vel[3 * b + c] + cr[c];
+  const double *xo = hist_lookup(s, a, b);
+  double Ft[3];
+  contact_law(&s->P, mstar, zeta, delta, nv, vrel, xo ? xo : zero3, o->Fa, Ft, o->xi, &o->fnabs, o->sc);
+  cross3(nv, Ft, o->tq);
+}
+
 /* Forces and torques of one DEM step from the step-start state; with commit,
  * the tangential histories are replaced by the new ones.  Fs and Ts (may be
  * NULL) receive per parcel the sum of the magnitudes of the products that
  * make up F and T (per contact: k_n |delta| + gamma_n |v_rel| normal, and
  * k_t (|xi| + |v_rel| dt) + gamma_t |v_rel| tangential; gravity, pressure
  * gradient and drag): the scale of the rounding error of F and T when they
- * are evaluated in a lower precision. */
+ * are evaluated in a lower precision.
+ *
+ * Each pair is evaluated once (+F on a, -F on b); every parcel then adds its
+ * pairs in ascending partner id, then its walls, then the gas force, so the
+ * sums are the same for any thread count. */
 static void compute_forces(ora_sys *s, const ora_gas *g, double *F, double *T, double *Fs, double *Ts,
                            int commit) {
   int n = s->n;
   static const double zero3[3] = {0, 0, 0};
-  memset(F, 0, sizeof(double) * 3 * n);
-  memset(T, 0, sizeof(double) * 3 * n);
-  if (Fs) memset(Fs, 0, sizeof(double) * n);
-  if (Ts) memset(Ts, 0, sizeof(double) * n);
   int *pr;
   long np_ = find_pairs(s, 0, &pr);
+  pair_t *pt = (pair_t *)malloc(sizeof(pair_t) * (np_ > 0 ? np_ : 1));
+#pragma omp parallel for schedule(static)
+  for (long q = 0; q < np_; q++) pair_terms(s, pr[2 * q], pr[2 * q + 1], &pt[q]);
+  /* pairs of each parcel: as the first member (pair list sorted by (a, b):
+   * one run per a) and as the second (in ascending a) */
+  long *first = (long *)calloc((size_t)n + 1, sizeof(long));
+  long *sec_off = (long *)calloc((size_t)n + 1, sizeof(long));
+  for (long q = 0; q < np_; q++) {
+    first[pr[2 * q] + 1]++;
+    sec_off[pr[2 * q + 1] + 1]++;
+  }
+  for (int i = 0; i < n; i++) {
+    first[i + 1] += first[i];
+    sec_off[i + 1] += sec_off[i];
+  }
+  long *sec = (long *)malloc(sizeof(long) * (np_ > 0 ? np_ : 1));
+  long *fill = (long *)malloc(sizeof(long) * ((size_t)n + 1));
+  memcpy(fill, sec_off, sizeof(long) * ((size_t)n + 1));
+  for (long q = 0; q < np_; q++) sec[fill[pr[2 * q + 1]]++] = q;
+  free(fill);
   int *ncnt = (int *)calloc(n, sizeof(int));
   hist_t *nh = (hist_t *)malloc(sizeof(hist_t) * (size_t)HCAP * n);
-  for (long q = 0; q < np_; q++) {
-    int a = pr[2 * q], b = pr[2 * q + 1];
-    double dx[3], nv[3];
-    for (int c = 0; c < 3; c++) dx[c] = s->pos[3 * b + c] - s->pos[3 * a + c];
-    double dist = sqrt((dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2]);
-    double ra = radius(s, a), rb = radius(s, b);
-    for (int c = 0; c < 3; c++) nv[c] = dx[c] / dist;
-    double delta = (ra + rb) - dist;
-    double ma = s->mass[a], mb = s->mass[b];
-    double mstar = ma * mb / (ma + mb);
-    double kk = s->k[a] > s->k[b] ? s->k[a] : s->k[b];
-    double zeta = ora_zeta(ora_e_cgp(s->P.e_p, kk));
-    double wsum[3], cr[3], vrel[3];
-    for (int c = 0; c < 3; c++) wsum[c] = ra * s->omg[3 * a + c] + rb * s->omg[3 * b + c];
-    cross3(wsum, nv, cr);
-    for (int c = 0; c < 3; c++) vrel[c] = s->vel[3 * a + c] - s->vel[3 * b + c] + cr[c];
-    const double *xo = hist_lookup(s, a, b);
-    double Fa[3], Ft[3], xin[3], fnabs, tq[3], sc[2];
-    contact_law(&s->P, mstar, zeta, delta, nv, vrel, xo ? xo : zero3, Fa, Ft, xin, &fnabs, sc);
-    cross3(nv, Ft, tq);
-    for (int c = 0; c < 3; c++) {
-      F[3 * a + c] += Fa[c];
-      F[3 * b + c] -= Fa[c];
-      T[3 * a + c] += ra * tq[c];
-      T[3 * b + c] += rb * tq[c];
-    }
-    rolling(s, a, fnabs, &T[3 * a]);
-    rolling(s, b, fnabs, &T[3 * b]);
-    if (Fs) {
-      Fs[a] += sc[0] + sc[1];
-      Fs[b] += sc[0] + sc[1];
-    }
-    if (Ts) {
-      double roll = s->P.mu_r > 0.0 ? s->P.mu_r * sc[0] : 0.0;
-      Ts[a] += ra * sc[1] + roll;
-      Ts[b] += rb * sc[1] + roll;
-    }
-    if (ncnt[a] >= HCAP) abort();
-    nh[(size_t)a * HCAP + ncnt[a]].partner = b;
-    memcpy(nh[(size_t)a * HCAP + ncnt[a]].xi, xin, sizeof xin);
-    ncnt[a]++;
-  }
-  free(pr);
-  /* walls: same law with m* = m, infinite radius and zero velocity */
+  int overflow = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(| : overflow)
   for (int i = 0; i < n; i++) {
-    const ora_bed *B = &s->beds[s->bed[i]];
+    double Fi[3] = {0, 0, 0}, Ti[3] = {0, 0, 0}, fs = 0.0, ts = 0.0;
     double r = radius(s, i);
+    int roll_on = s->P.mu_r > 0.0;
+    /* partners with a smaller id (i second in their pair), then larger */
+    for (long u = sec_off[i]; u < sec_off[i + 1]; u++) {
+      const pair_t *p = &pt[sec[u]];
+      for (int c = 0; c < 3; c++) {
+        Fi[c] -= p->Fa[c];
+        Ti[c] += r * p->tq[c];
+      }
+      rolling(s, i, p->fnabs, Ti);
+      fs += p->sc[0] + p->sc[1];
+      ts += r * p->sc[1] + (roll_on ? s->P.mu_r * p->sc[0] : 0.0);
+    }
+    for (long q = first[i]; q < first[i + 1]; q++) {
+      const pair_t *p = &pt[q];
+      for (int c = 0; c < 3; c++) {
+        Fi[c] += p->Fa[c];
+        Ti[c] += r * p->tq[c];
+      }
+      rolling(s, i, p->fnabs, Ti);
+      fs += p->sc[0] + p->sc[1];
+      ts += r * p->sc[1] + (roll_on ? s->P.mu_r * p->sc[0] : 0.0);
+      if (ncnt[i] >= HCAP) {
+        overflow = 1;
+        continue;
+      }
+      nh[(size_t)i * HCAP + ncnt[i]].partner = pr[2 * q + 1];
+      memcpy(nh[(size_t)i * HCAP + ncnt[i]].xi, p->xi, sizeof p->xi);
+      ncnt[i]++;
+    }
+    /* walls: same law with m* = m, infinite radius and zero velocity */
+    const ora_bed *B = &s->beds[s->bed[i]];
     for (int w = 0; w < n_walls(B); w++) {
       double nv[3];
       double phi = wall_geom(B, w, &s->pos[3 * i], nv);
@@ -803,19 +915,31 @@ static void compute_forces(ora_sys *s, const ora_gas *g, double *F, double *T, d
       contact_law(&s->P, s->mass[i], zeta, delta, nv, vrel, xo, Fa, Ft, xin, &fnabs, sc);
       cross3(nv, Ft, tq);
       for (int c = 0; c < 3; c++) {
-        F[3 * i + c] += Fa[c];
-        T[3 * i + c] += r * tq[c];
+        Fi[c] += Fa[c];
+        Ti[c] += r * tq[c];
       }
-      rolling(s, i, fnabs, &T[3 * i]);
-      if (Fs) Fs[i] += sc[0] + sc[1];
-      if (Ts) Ts[i] += r * sc[1] + (s->P.mu_r > 0.0 ? s->P.mu_r * sc[0] : 0.0);
+      rolling(s, i, fnabs, Ti);
+      fs += sc[0] + sc[1];
+      ts += r * sc[1] + (roll_on ? s->P.mu_r * sc[0] : 0.0);
       if (commit) {
         memcpy(&s->wxi[18 * i + 3 * w], xin, sizeof xin);
         s->won[6 * i + w] = 1;
       }
     }
+    gas_force(s, g, i, Fi, Fs ? &fs : NULL);
+    for (int c = 0; c < 3; c++) {
+      F[3 * i + c] = Fi[c];
+      T[3 * i + c] = Ti[c];
+    }
+    if (Fs) Fs[i] = fs;
+    if (Ts) Ts[i] = ts;
   }
-  for (int i = 0; i < n; i++) gas_force(s, g, i, &F[3 * i], Fs ? &Fs[i] : NULL);
+  if (overflow) abort();
+  free(pr);
+  free(pt);
+  free(first);
+  free(sec_off);
+  free(sec);
   if (commit) {
     free(s->hist);
     free(s->hcnt);
@@ -851,11 +975,13 @@ void ora_step(ora_sys *s, int nsteps, const ora_gas *g) {
      * step-start state; reading: m C_p,p and Q_r + Q_rm are those of the last
      * reaction update (masses change only at coupling, Section 4) */
     if (s->P.energy_on)
+#pragma omp parallel for schedule(static)
       for (int i = 0; i < n; i++) {
         int c = cell_of(s, i);
         double q = parcel_hA(s, g, i) * (g->T[c] - s->Tp[i]) + s->qrx[i];
         s->Tp[i] += dt * q / s->mcp[i];
       }
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < n; i++) {
       double m = s->mass[i], I = inertia(s, i);
       for (int c = 0; c < 3; c++) {
@@ -899,6 +1025,10 @@ static void deposit(ora_sys *s, const ora_gas *g, double *np_, double *sumK, dou
   if (g && (sumK || sumKu || sumKv || sumKw || sumKs)) {
     double *a[5] = {sumK, sumKu, sumKv, sumKw, sumKs};
     for (int j = 0; j < 5; j++) if (a[j]) memset(a[j], 0, sizeof(double) * nc);
+    /* K_p and |u_g - v_p| per parcel (independent), then the cell sums in
+     * ascending id */
+    double *Kp = (double *)malloc(sizeof(double) * 2 * (s->n > 0 ? s->n : 1));
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < s->n; i++) {
       int c = cell_of(s, i);
       const ora_bed *B = &s->beds[s->bed[i]];
@@ -906,13 +1036,19 @@ static void deposit(ora_sys *s, const ora_gas *g, double *np_, double *sumK, dou
       ora_gas_props(g->T[c], g->p[c], g->xH2[c], g->xH2O[c], g->xN2[c], B->mu_override, &rho, &mu);
       double sl[3] = {g->ug[c] - s->vel[3 * i], g->vg[c] - s->vel[3 * i + 1], g->wg[c] - s->vel[3 * i + 2]};
       double slip = norm3(sl);
-      double K = beta_of(s, i, s->eps[c], rho, mu, slip) * volume(s, i);
+      Kp[2 * i] = beta_of(s, i, s->eps[c], rho, mu, slip) * volume(s, i);
+      Kp[2 * i + 1] = slip;
+    }
+    for (int i = 0; i < s->n; i++) {
+      int c = cell_of(s, i);
+      double K = Kp[2 * i], slip = Kp[2 * i + 1];
       if (sumK) sumK[c] += K;
       if (sumKu) sumKu[c] += K * s->vel[3 * i];
       if (sumKv) sumKv[c] += K * s->vel[3 * i + 1];
       if (sumKw) sumKw[c] += K * s->vel[3 * i + 2];
       if (sumKs) sumKs[c] += K * slip;
     }
+    free(Kp);
   }
   free(sv);
   free(cnt);
@@ -1057,6 +1193,13 @@ static dual fov_of(const dual sp[4], int kind) {
   return dadd(dadd(dscale(fh, 1.0 / 9.0), dscale(fm, 2.0 / 9.0)), dscale(fw, 6.0 / 9.0));
 }
 
+/* eqs. e2-18 / e2-19 for one state (nh, nm, nw, nfe); kind 0 hematite, 1 magnetite */
+double ora_fov(const double sp[4], int kind) {
+  dual d[4];
+  for (int q = 0; q < 4; q++) d[q] = D(sp[q]);
+  return fov_of(d, kind).v;
+}
+
 /* Environment of parcel i from its cell (NGP) and its slip. */
 static void make_env(const ora_sys *s, const ora_gas *g, int i, double dt, const double *theta,
                      int tangents, renv *e) {
@@ -1099,13 +1242,18 @@ static void make_env(const ora_sys *s, const ora_gas *g, int i, double dt, const
 long ora_react(ora_sys *s, double dt, const ora_gas *g, int update_mass, double *mdotH2,
                double *mdotH2O, double *sumEQ, double *sumES, double *fov, double *bed_fov,
                double *hA, double *hAT, double *Qrm, double *Hr) {
-  int nc = s->n_cells;
+  int nc = s->n_cells, n = s->n;
   double *outs[8] = {mdotH2, mdotH2O, sumEQ, sumES, hA, hAT, Qrm, Hr};
   for (int j = 0; j < 8; j++) if (outs[j]) memset(outs[j], 0, sizeof(double) * nc);
   double *bw = (double *)calloc(s->P.n_beds, sizeof(double));
   double *bf = (double *)calloc(s->P.n_beds, sizeof(double));
+  /* per parcel (independent): the update and its 8 cell terms, f_ov and the
+   * bed weight; then the cell and bed sums in ascending id */
+  double *pp = (double *)malloc(sizeof(double) * 10 * (n > 0 ? n : 1));
   long clamps = 0;
-  for (int i = 0; i < s->n; i++) {
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : clamps)
+  for (int i = 0; i < n; i++) {
+    double *o = &pp[10 * i];
     renv e;
     make_env(s, g, i, dt, NULL, 0, &e);
     int c = cell_of(s, i);
@@ -1119,6 +1267,7 @@ long ora_react(ora_sys *s, double dt, const ora_gas *g, int update_mass, double 
     }
     double k3 = s->k[i] * s->k[i] * s->k[i];
     double xs = xi[0].v + xi[1].v + xi[2].v;
+    for (int q = 4; q < 8; q++) o[q] = 0.0;
     if (s->P.energy_on) {
       /* eqs. e3-18, e3-19 (solids) and e3-20, e3-21 (gases) at T_p, with the
        * k^3 of eqs. e3-49, e3-50; the moles changed over dt per real
@@ -1131,25 +1280,32 @@ long ora_react(ora_sys *s, double dt, const ora_gas *g, int update_mass, double 
       s->mcp[i] = parcel_mcp(s, i);
       /* eqs. e4-4, e4-5 (times V_cell), e3-38 and e3-39 (times -V_cell) */
       double ha = parcel_hA(s, g, i);
-      if (hA) hA[c] += ha;
-      if (hAT) hAT[c] += ha * Tp;
-      if (Qrm) Qrm[c] += k3 * Qm;
-      if (Hr) Hr[c] += k3 * (ora_h_mol(1, g->T[c]) - ora_h_mol(0, g->T[c])) * xs / dt;
+      o[4] = ha;
+      o[5] = ha * Tp;
+      o[6] = k3 * Qm;
+      o[7] = k3 * (ora_h_mol(1, g->T[c]) - ora_h_mol(0, g->T[c])) * xs / dt;
     }
     /* eqs. e2-1, e2-25, e3-25, e3-52: kg/s per parcel, summed per cell */
-    if (mdotH2) mdotH2[c] += -k3 * MG[0] * 1e-3 * xs / dt;
-    if (mdotH2O) mdotH2O[c] += k3 * MG[1] * 1e-3 * xs / dt;
+    o[0] = -k3 * MG[0] * 1e-3 * xs / dt;
+    o[1] = k3 * MG[1] * 1e-3 * xs / dt;
     /* eqs. e4-7..e4-11 with E = eta A_p / T, eta_H2 = -1 */
     double E = -e.Ap / g->T[c];
-    if (sumEQ) sumEQ[c] += k3 * E * Q.v;
-    if (sumES) sumES[c] += k3 * E * S.v;
-    double f = fov_of(sp, s->ores[s->ore[i]].kind).v;
-    if (fov) fov[i] = f;
-    double w = k3 * (2.0 * sp[0].v + 3.0 * sp[1].v + sp[2].v + sp[3].v);
-    bw[s->bed[i]] += w;
-    bf[s->bed[i]] += w * f;
+    o[2] = k3 * E * Q.v;
+    o[3] = k3 * E * S.v;
+    o[8] = fov_of(sp, s->ores[s->ore[i]].kind).v;
+    o[9] = k3 * (2.0 * sp[0].v + 3.0 * sp[1].v + sp[2].v + sp[3].v);
     if (update_mass) s->mass[i] = parcel_mass(s, i);
   }
+  for (int i = 0; i < n; i++) {
+    const double *o = &pp[10 * i];
+    int c = cell_of(s, i);
+    for (int j = 0; j < 8; j++)
+      if (outs[j] && (j < 4 || s->P.energy_on)) outs[j][c] += o[j];
+    if (fov) fov[i] = o[8];
+    bw[s->bed[i]] += o[9];
+    bf[s->bed[i]] += o[9] * o[8];
+  }
+  free(pp);
   if (bed_fov)
     for (int b = 0; b < s->P.n_beds; b++) bed_fov[b] = bw[b] > 0 ? bf[b] / bw[b] : 0.0;
   free(bw);
@@ -1167,6 +1323,7 @@ void ora_grad(ora_sys *s, const ora_gas *g, int n_sub, double dt_react, int dyn_
       ora_step(s, 1, g);
       deposit(s, NULL, NULL, NULL, NULL, NULL, NULL, NULL);
     }
+#pragma omp parallel for schedule(dynamic, 256)
     for (int i = 0; i < n; i++) {
       renv e;
       make_env(s, g, i, dt_react, theta, 1, &e);

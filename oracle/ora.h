@@ -8,7 +8,9 @@
  * with the GPU library.
  *
  * Every quantity is SI and double precision.  Parcels are kept in original id
- * order; every loop visits parcels, pairs and cells in ascending id order.
+ * order; every sum over parcels, pairs or cells runs in ascending id order.
+ * Loops over independent parcels or pairs may run on several threads
+ * (OpenMP), which changes no result.
  *
  * Parity unpinned (conventions with no independent pin; the tests check only
  * their use, limits or finiteness): the tortuosity, eps_min, kt/kn, the
@@ -68,6 +70,9 @@ ora_sys *ora_new(const ora_params *P, const ora_bed *beds, const ora_ore *ores, 
                  const double *nh, const double *nm, const double *nw, const double *nfe);
 void ora_free(ora_sys *s);
 int ora_n_cells(const ora_sys *s);
+/* threads of the parallel loops; results are identical for any count */
+void ora_set_threads(int n);
+int ora_threads(void);
 
 /* canonical contact pairs (a < b by id) at the current positions, sorted;
  * brute = 1 uses the O(N^2) scan instead of the cell list.  Returns the count
@@ -144,6 +149,8 @@ void ora_ladder(const int active[3], const double A[3], const double B[3], doubl
  *   env = {x, xeq0..2, kappa0..2, kr0..2, c_mol, Ap, rp, Deff_m, Deff_w, Deff_Fe, F, dt}
  * sp[4] (nh, nm, nw, nfe) updated in place; returns the number of clamped rates */
 int ora_react_point(const double env[18], double sp[4]);
+/* overall reduction degree of one state (nh, nm, nw, nfe): eq. e2-18 (kind 0) or e2-19 (kind 1) */
+double ora_fov(const double sp[4], int kind);
 
 #ifdef __cplusplus
 }

@@ -16,15 +16,26 @@ LIB = os.path.join(HERE, "libora.so")
 SRC = os.path.join(HERE, "ora.c")
 
 
+FLAGS = ["-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c99"]
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle (plain C, -O2 -ffp-contract=off, no FMA)."""
+    """Compile the oracle (plain C, -O2 -ffp-contract=off, no FMA, OpenMP)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
             os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "ora.h"))):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                               "-std=c99", "-o", tmp, SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", *FLAGS, "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
+
+
+def build_native(path: str) -> str:
+    """The same source built -O3 -march=native for the host it runs on (the
+    CPU-baseline timing); contraction stays off, so results are unchanged."""
+    tmp = path + ".tmp"
+    subprocess.check_call(["gcc", "-O3", "-march=native", *FLAGS, "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, path)
+    return path
 
 
 class OraBed(C.Structure):
@@ -54,15 +65,47 @@ class OraGas(C.Structure):
 
 
 _lib = None
+_lib_path = None
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from another build of the same source (before first use)."""
+    global _lib_path
+    if _lib is not None:
+        raise RuntimeError("oracle library already loaded")
+    _lib_path = path
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (results do not depend on it)."""
+    lib().ora_set_threads(int(n))
+
+
+def threads() -> int:
+    return int(lib().ora_threads())
+
+
+def host_threads() -> int:
+    """Threads this host gives the process: OMP_NUM_THREADS if set, else the
+    cores in its affinity mask."""
+    env = os.environ.get("OMP_NUM_THREADS", "").split(",")[0].strip()
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
 
 
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(LIB)
+        if _lib_path is None:
+            build()
+        L = C.CDLL(_lib_path or LIB)
+        L.ora_set_threads.argtypes = [C.c_int]
+        L.ora_set_threads.restype = None
+        L.ora_threads.restype = C.c_int
+        L.ora_set_threads(1)  # one thread unless set_threads() asks for more
         L.ora_new.restype = C.c_void_p
         L.ora_new.argtypes = [C.POINTER(OraParams), C.POINTER(OraBed), C.POINTER(OraOre), C.c_int] + \
             [_dp] * 9 + [_dp, _dp, _ip, _ip] + [_dp] * 4
@@ -114,6 +157,8 @@ def lib():
         L.ora_ladder.argtypes = [_ip, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp, _dp]
         L.ora_react_point.restype = C.c_int
         L.ora_react_point.argtypes = [_dp, _dp]
+        L.ora_fov.restype = C.c_double
+        L.ora_fov.argtypes = [_dp, C.c_int]
         _lib = L
     return _lib
 
@@ -341,6 +386,13 @@ def react_point(env, sp):
     s = np.ascontiguousarray(sp, dtype=np.float64).copy()
     c = lib().ora_react_point(_p(e), _p(s))
     return s, c
+
+
+def fov(sp, kind):
+    """Overall reduction degree of one state (nh, nm, nw, nfe), eq. e2-18 / e2-19."""
+    s = np.ascontiguousarray(sp, dtype=np.float64)
+    assert s.shape == (4,)
+    return lib().ora_fov(_p(s), int(kind))
 
 
 # species: 0 H2, 1 H2O, 2 N2, 3 Fe2O3, 4 Fe3O4, 5 FeO, 6 Fe (Table C1)

@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdemrx.so")
 
 DEMRX_OK = 0
+DEMRX_EINVAL = -1
 ERRORS = {-1: "EINVAL", -2: "EHIP", -3: "EOVERFLOW", -4: "EDOMAIN", -5: "ENONFINITE", -6: "ENOMEM", -7: "ESKIN"}
 DEM_FP64, DEM_MIXED = 0, 1
 DEM_WALL_BOX, DEM_WALL_CYL = 0, 1

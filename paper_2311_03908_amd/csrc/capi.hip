@@ -590,6 +590,12 @@ struct Ctx final : dem_ctx {
   int gas_species(double dt, const dem_gas *g, const double *eq, const double *es, const double *xin, double *x1,
                   double *x2, double *x3) override {
     if (!gas_ok(g) || !eq || !es || !xin || !x1 || !x2 || !x3) return fail(DEMRX_EINVAL, "null argument");
+    // the step reads neighbouring cells of g's mole fractions while it writes
+    // the outputs, so an output that aliases an input would race
+    for (const double *o : {(const double *)x1, (const double *)x2, (const double *)x3})
+      if (o == g->xH2 || o == g->xH2O || o == g->xN2)
+        return fail(DEMRX_EINVAL, "species outputs must be distinct from the gas mole-fraction inputs");
+    if (x1 == x2 || x1 == x3 || x2 == x3) return fail(DEMRX_EINVAL, "species outputs must be distinct arrays");
     if (!(dt > 0.0) || !(xin[0] >= 0.0) || !(xin[1] >= 0.0) || !(xin[0] + xin[1] <= 1.0))
       return fail(DEMRX_EINVAL, "dt must be positive and xin fractions in [0, 1] with sum <= 1");
     TRY(ensure_dep());

@@ -91,3 +91,30 @@ def test_courant_number_above_one_is_reported():
     with pytest.raises(DemError) as e:
         bed.sync()
     assert e.value.code == -1
+
+
+def test_outputs_aliasing_the_gas_inputs_are_rejected():
+    """The gas step reads the neighbouring cells' mole fractions while it
+    writes its outputs: outputs that alias the inputs (or each other) are an
+    invalid argument, with nothing launched."""
+    import ctypes as C
+
+    from paper_2311_03908_amd import capi
+
+    w = W.cfg1(n=512)
+    bed = Bed(w)
+    r = bed.react(1e-4, keys=SRC)
+    x = {k: torch.zeros(bed.n_cells, dtype=torch.float64, device=bed.device) for k in ("a", "b", "c")}
+    xi = (C.c_double * 2)(*XIN)
+
+    def call(o1, o2, o3):
+        p = [C.c_void_p(t.data_ptr()) for t in (o1, o2, o3)]
+        return bed.L.dem_gas_species(bed.h, 1e-4, C.byref(bed._gas), C.c_void_p(r["sumEQ"].data_ptr()),
+                                     C.c_void_p(r["sumES"].data_ptr()), xi, *p)
+
+    for alias in ("xH2", "xH2O", "xN2"):
+        assert call(bed.gas_t[alias], x["b"], x["c"]) == capi.DEMRX_EINVAL
+        assert call(x["a"], x["b"], bed.gas_t[alias]) == capi.DEMRX_EINVAL
+    assert call(x["a"], x["a"], x["c"]) == capi.DEMRX_EINVAL
+    assert call(x["a"], x["b"], x["c"]) == 0
+    bed.sync()
