@@ -71,7 +71,7 @@ def settle(w, steps, log=True):
     from paper_2311_03908_amd.bed import Bed
 
     S = w.couple_every
-    ws = dataclasses.replace(w, params={**w.params, "rebuild_every": 10})
+    ws = dataclasses.replace(w, params={**w.params, "check_every": 10})
     bed = Bed(ws, device="cuda:0")
     t0 = time.perf_counter()
     bed.run(steps // S, S)
@@ -423,7 +423,7 @@ def main():
                      "kernel": "k_step (fused contact + drag + integrate)", "bytes_per_parcel_step": bpu,
                      "kernel_ms": k_ms, "launches_timed": k_launches, "z_mean": z,
                      "launch": {"step_block": st["step_block"], "step_xcd_chunk": st["step_xcd"],
-                                "build_grid": st["build_grid"], "rebuild_period": st["rebuild_period"]}},
+                                "build_grid": st["build_grid"], "check_period": st["check_period"]}},
     }
     bed.close()
     if not args.no_extras:

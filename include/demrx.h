@@ -98,7 +98,9 @@ typedef struct {
   double dt;             /* DEM time step (s) */
   double g[3];           /* gravity (m/s2) */
   int32_t max_nbr;       /* neighbour slots per parcel, 1..DEM_MAX_NBR */
-  int32_t rebuild_every; /* steps between neighbour-list builds (>= 1) */
+  int32_t check_every;   /* steps between neighbour-list checks (>= 1): at a check the lists are
+                            rebuilt if the largest displacement since the last build plus twice the
+                            largest speed times the steps to the next check could reach skin/2 */
   int32_t ergun_printed; /* 1: inertial Ergun term with eps_g as printed in eq. e3-5-1 */
   int32_t drag_on;       /* 0: no gas-side forces on parcels (gravity only) */
   int32_t energy_on;     /* 1: particle energy equation (eqs. e3-8..e3-13, e3-18..e3-23, e3-41,
@@ -168,7 +170,7 @@ typedef struct {
   int32_t step_block;            /* launch shape in use (dem_autotune): step-kernel block size, */
   int32_t step_xcd;              /* blocks per XCD chunk (1: plain round-robin), */
   int32_t build_grid;            /* persistent grid of the neighbour build */
-  int32_t rebuild_period;        /* steps between neighbour-list rebuilds in dem_run */
+  int32_t check_period;          /* steps between neighbour-list checks (check_every) */
 } dem_stats;
 
 /* Create a context holding n parcels.  Copies the parcel state (device, original
@@ -181,7 +183,10 @@ int dem_init(const dem_params *p, const dem_parcels *in, int32_t n, void *stream
 /* Advance n_steps DEM steps with the gas frozen (eq. e3-3, e3-6; semi-implicit
  * Euler): contact detection, soft-sphere parcel-parcel and parcel-wall forces,
  * Gidaspow drag with the voidage of the last deposit, gravity and -V grad p.
- * The neighbour list is rebuilt every rebuild_every steps. */
+ * The neighbour lists are checked every check_every steps and rebuilt on the
+ * device when the displacement bound requires it (no host synchronisation);
+ * a step that still finds a parcel moved by skin/2 since the last build
+ * latches DEMRX_ESKIN. */
 int dem_step(dem_ctx *c, int32_t n_steps, const dem_gas *g);
 
 /* Coupling deposit (eqs. e3-25, e3-27a, e4-1): voidage and drag sums per gas
@@ -220,6 +225,23 @@ int dem_react(dem_ctx *c, double dt_cfd, const dem_gas *g, dem_sources *out, dou
 int dem_gas_species(dem_ctx *c, double dt, const dem_gas *g, const double *sumEQ, const double *sumES,
                     const double xin[2], double *xH2, double *xH2O, double *xN2);
 
+/* Gas-side momentum step of the two-way coupling: one step dt of the gas
+ * velocity of every cell on the frozen pressure field (eqs. e4-1, e4-2 with
+ * the interphase source of eqs. e3-27, e3-27a),
+ *   eps rho (u' - u) / dt = -eps grad p + eps rho g + K_gp u' - K_gp u_p,
+ * the source K_gp u_g implicit and K_gp u_p explicit, where K_gp = -sumK /
+ * V_cell and K_gp u_p = -(sumKu, sumKv, sumKw) / V_cell are the drag sums of
+ * a dem_couple (device, one double per gas cell): the gas takes exactly the
+ * drag the parcels feel.  eps is the voidage of the last deposit, rho that of
+ * eq. e3-53 at the cell's T, p and composition, g the gravity of dem_params.
+ * Convection and the viscous and pseudo-turbulent stresses belong to the gas
+ * solver and are not modelled.  Writes the new velocities to ug, vg, wg
+ * (device, one double per cell; each cell reads only itself, so they may be
+ * g's own velocity arrays).  Errors: EINVAL (nulls, dt <= 0); a non-finite
+ * result is reported by the next synchronising call. */
+int dem_gas_momentum(dem_ctx *c, double dt, const dem_gas *g, const double *sumK, const double *sumKu,
+                     const double *sumKv, const double *sumKw, double *ug, double *vg, double *wg);
+
 /* Gradient of the bed-mean reduction degree J (all parcels, weight k^3 N_Fe)
  * after the protocol of spec with respect to theta (used for every bed) by a
  * reverse (adjoint) sweep with checkpointing; grad may be NULL for a plain
@@ -250,11 +272,15 @@ int dem_pairs(dem_ctx *c, uint32_t *ij, int64_t cap, int64_t *n_pairs);
 /* Counters of the last step (host).  Synchronises. */
 int dem_get_stats(dem_ctx *c, dem_stats *out);
 
-/* Replay the full hot path -- rebuild, couple_every DEM steps, coupling deposit
- * and reaction update (dt_cfd = couple_every * dt) -- n_intervals times from a
- * HIP graph captured on first use (recaptured if the arguments change).
- * out and bed_fov (host) may be NULL; bed_fov receives the values after the
- * last interval and makes the call synchronise. */
+/* Replay the full hot path -- couple_every DEM steps with the neighbour-list
+ * check (and, when the displacement bound requires it, the rebuild) at the
+ * first step of the interval and every check_every steps after it, the
+ * coupling deposit and the reaction update (dt_cfd = couple_every * dt) --
+ * n_intervals times from a HIP graph of two intervals captured on first use
+ * (recaptured if the arguments change).  Whether a check rebuilds is decided
+ * on the device, so the replays need no host synchronisation.  out and
+ * bed_fov (host) may be NULL; bed_fov receives the values after the last
+ * interval and makes the call synchronise. */
 int dem_run(dem_ctx *c, int32_t n_intervals, int32_t couple_every, const dem_gas *g,
             dem_sources *out, double *bed_fov);
 

@@ -535,9 +535,8 @@ static int cmp_pair(const void *p, const void *q) {
   return 0;
 }
 
-/* Partners b > a of parcel a in contact, from the bins of a's bed (edge >=
- * the bed's largest diameter, members contiguous in bin order); written to
- * out (may be NULL) in the bins' order.  Returns the count. */
+/* Bins of one bed: edge >= the bed's largest diameter, members contiguous in
+ * bin order, with bin-ordered copies of their positions and radii. */
 typedef struct {
   int nc[3];
   double lo[3], cs[3];
@@ -546,42 +545,11 @@ typedef struct {
   double *q;     /* x, y, z, r of sorted[t] */
 } bins_t;
 
-static int bin_partners(const ora_sys *s, const bins_t *B, int a, int *out) {
-  int c3[3], m = 0;
-  for (int k = 0; k < 3; k++) {
-    double f = floor((s->pos[3 * a + k] - B->lo[k]) / B->cs[k]);
-    if (f < 0) f = 0;
-    if (f > B->nc[k] - 1) f = B->nc[k] - 1;
-    c3[k] = (int)f;
-  }
-  double ra = radius(s, a);
-  for (int oz = -1; oz <= 1; oz++)
-    for (int oy = -1; oy <= 1; oy++)
-      for (int ox = -1; ox <= 1; ox++) {
-        int x2 = c3[0] + ox, y2 = c3[1] + oy, z2 = c3[2] + oz;
-        if (x2 < 0 || y2 < 0 || z2 < 0 || x2 >= B->nc[0] || y2 >= B->nc[1] || z2 >= B->nc[2]) continue;
-        long c2 = x2 + (long)B->nc[0] * (y2 + (long)B->nc[1] * z2);
-        for (long tb = B->first[c2]; tb < B->first[c2 + 1]; tb++) {
-          int b = B->sorted[tb];
-          if (b <= a) continue;
-          /* the contact predicate of in_contact(), on the bin-ordered copy */
-          double dx = B->q[4 * tb] - s->pos[3 * a];
-          double dy = B->q[4 * tb + 1] - s->pos[3 * a + 1];
-          double dz = B->q[4 * tb + 2] - s->pos[3 * a + 2];
-          double sr = ra + B->q[4 * tb + 3];
-          if (!(((dx * dx + dy * dy) + dz * dz) < sr * sr)) continue;
-          if (out) out[m] = b;
-          m++;
-        }
-      }
-  return m;
-}
-
 /* All contacting pairs a < b (same bed), sorted by (a, b).  *out is
  * malloc'ed.  The cell list collects each parcel's partners on its own (in
- * parallel when built with OpenMP: a count pass, offsets in id order, a fill
- * pass, and each parcel's short list sorted), so the list does not depend on
- * the thread count. */
+ * parallel when built with OpenMP: up to HCAP per parcel, each short list
+ * sorted, then concatenated in id order), so the list does not depend on the
+ * thread count. */
 static long find_pairs(ora_sys *s, int brute, int **out) {
   long cap = 1024, cnt = 0;
   int *pr = NULL;
@@ -651,27 +619,68 @@ static long find_pairs(ora_sys *s, int brute, int **out) {
     free(cellof); free(member); free(fill);
   }
   long *off = (long *)malloc(sizeof(long) * (n + 1));
+  int *part = (int *)malloc(sizeof(int) * (size_t)HCAP * (n > 0 ? n : 1));
+  int over = 0;
   off[0] = 0;
-#pragma omp parallel for schedule(dynamic, 1024)
-  for (int a = 0; a < n; a++) off[a + 1] = bins[s->bed[a]].first ? bin_partners(s, &bins[s->bed[a]], a, NULL) : 0;
+  for (int a = 0; a < n; a++) off[a + 1] = 0;
+  /* bin by bin: the members of a bin against those of its 27 neighbours,
+   * each member a keeping its partners b > a (a bin's members are written
+   * by one thread only) */
+  for (int bd = 0; bd < nb_; bd++) {
+    const bins_t *B = &bins[bd];
+    if (!B->first) continue;
+    long ncell = (long)B->nc[0] * B->nc[1] * B->nc[2];
+#pragma omp parallel for schedule(dynamic, 64) reduction(| : over)
+    for (long c = 0; c < ncell; c++) {
+      if (B->first[c] == B->first[c + 1]) continue;
+      int cx = (int)(c % B->nc[0]), cy = (int)((c / B->nc[0]) % B->nc[1]), cz = (int)(c / ((long)B->nc[0] * B->nc[1]));
+      for (long ta = B->first[c]; ta < B->first[c + 1]; ta++) off[B->sorted[ta] + 1] = 0;
+      for (int oz = -1; oz <= 1; oz++)
+        for (int oy = -1; oy <= 1; oy++)
+          for (int ox = -1; ox <= 1; ox++) {
+            int x2 = cx + ox, y2 = cy + oy, z2 = cz + oz;
+            if (x2 < 0 || y2 < 0 || z2 < 0 || x2 >= B->nc[0] || y2 >= B->nc[1] || z2 >= B->nc[2]) continue;
+            long c2 = x2 + (long)B->nc[0] * (y2 + (long)B->nc[1] * z2);
+            for (long ta = B->first[c]; ta < B->first[c + 1]; ta++) {
+              int a = B->sorted[ta];
+              long m = off[a + 1];
+              for (long tb = B->first[c2]; tb < B->first[c2 + 1]; tb++) {
+                int b = B->sorted[tb];
+                if (b <= a) continue;
+                /* the contact predicate of in_contact(), on the bin-ordered copies */
+                double dx = B->q[4 * tb] - B->q[4 * ta];
+                double dy = B->q[4 * tb + 1] - B->q[4 * ta + 1];
+                double dz = B->q[4 * tb + 2] - B->q[4 * ta + 2];
+                double sr = B->q[4 * ta + 3] + B->q[4 * tb + 3];
+                if (!(((dx * dx + dy * dy) + dz * dz) < sr * sr)) continue;
+                if (m < HCAP) part[(size_t)HCAP * a + m] = b;
+                m++;
+              }
+              off[a + 1] = m;
+            }
+          }
+      for (long ta = B->first[c]; ta < B->first[c + 1]; ta++) {
+        int a = B->sorted[ta];
+        long m = off[a + 1];
+        if (m > HCAP) over = 1;
+        int *seg = part + (size_t)HCAP * a;
+        for (long u = 1; u < m && u < HCAP; u++) /* insertion sort of a's few partners */
+          for (long v = u; v > 0 && seg[v - 1] > seg[v]; v--) {
+            int tmp = seg[v]; seg[v] = seg[v - 1]; seg[v - 1] = tmp;
+          }
+      }
+    }
+  }
+  if (over) abort(); /* more partners than the history holds */
   for (int a = 0; a < n; a++) off[a + 1] += off[a];
   cnt = off[n];
   pr = (int *)malloc(sizeof(int) * 2 * (cnt > 0 ? cnt : 1));
-  int *part = (int *)malloc(sizeof(int) * (cnt > 0 ? cnt : 1));
-#pragma omp parallel for schedule(dynamic, 1024)
-  for (int a = 0; a < n; a++) {
-    if (off[a + 1] == off[a]) continue;
-    int *seg = part + off[a];
-    int m = bin_partners(s, &bins[s->bed[a]], a, seg);
-    for (int u = 1; u < m; u++) /* insertion sort of a's few partners */
-      for (int v = u; v > 0 && seg[v - 1] > seg[v]; v--) {
-        int t = seg[v]; seg[v] = seg[v - 1]; seg[v - 1] = t;
-      }
-    for (int u = 0; u < m; u++) {
+#pragma omp parallel for schedule(static)
+  for (int a = 0; a < n; a++)
+    for (long u = 0; u < off[a + 1] - off[a]; u++) {
       pr[2 * (off[a] + u)] = a;
-      pr[2 * (off[a] + u) + 1] = seg[u];
+      pr[2 * (off[a] + u) + 1] = part[(size_t)HCAP * a + u];
     }
-  }
   free(part); free(off);
   for (int bd = 0; bd < nb_; bd++) {
     free(bins[bd].first); free(bins[bd].sorted); free(bins[bd].q);
@@ -961,14 +970,35 @@ void ora_force_scale(ora_sys *s, const ora_gas *g, double *Fs, double *Ts) {
   free(T);
 }
 
+/* Test harness: a fixed pseudo-random sign (+1 or -1) per parcel, component
+ * and seed (splitmix64 of the three), for ora_step_perturbed. */
+static double fixed_sign(unsigned long long seed, int i, int c) {
+  unsigned long long z = seed * 0x9E3779B97F4A7C15ull + (unsigned long long)i * 6 + (unsigned long long)c + 1;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (z & 1ull) ? 1.0 : -1.0;
+}
+
 /* eq. e3-3 and e3-6 advanced by semi-implicit Euler (reading: the paper does
- * not name its integrator): v += dt F/m, w += dt T/I, x += dt v_new. */
-void ora_step(ora_sys *s, int nsteps, const ora_gas *g) {
+ * not name its integrator): v += dt F/m, w += dt T/I, x += dt v_new.  With
+ * rel > 0 (test harness only: ora_step_perturbed) every force and torque
+ * component is biased by rel times the parcel's force-term scale, with a
+ * sign fixed per parcel and component, every step. */
+static void step_impl(ora_sys *s, int nsteps, const ora_gas *g, double rel, unsigned long long seed) {
   int n = s->n;
   double *F = (double *)malloc(sizeof(double) * 3 * n);
   double *T = (double *)malloc(sizeof(double) * 3 * n);
+  double *Fs = rel > 0.0 ? (double *)malloc(sizeof(double) * n) : NULL;
+  double *Ts = rel > 0.0 ? (double *)malloc(sizeof(double) * n) : NULL;
   for (int st = 0; st < nsteps; st++) {
-    compute_forces(s, g, F, T, NULL, NULL, 1);
+    compute_forces(s, g, F, T, Fs, Ts, 1);
+    if (rel > 0.0)
+      for (int i = 0; i < n; i++)
+        for (int c = 0; c < 3; c++) {
+          F[3 * i + c] += rel * Fs[i] * fixed_sign(seed, i, c);
+          T[3 * i + c] += rel * Ts[i] * fixed_sign(seed, i, 3 + c);
+        }
     double dt = s->P.dt;
     /* eq. e3-8 with conduction and radiation left out: m C_p dT_p/dt =
      * k^3 (Q_conv + Q_r + Q_rm) (eqs. e3-41, e3-49, e3-50), explicit in the
@@ -993,6 +1023,14 @@ void ora_step(ora_sys *s, int nsteps, const ora_gas *g) {
   }
   free(F);
   free(T);
+  free(Fs);
+  free(Ts);
+}
+
+void ora_step(ora_sys *s, int nsteps, const ora_gas *g) { step_impl(s, nsteps, g, 0.0, 0); }
+
+void ora_step_perturbed(ora_sys *s, int nsteps, const ora_gas *g, double rel, unsigned long long seed) {
+  step_impl(s, nsteps, g, rel, seed);
 }
 
 /* ------------------------------------------------------------ deposition
@@ -1465,5 +1503,39 @@ void ora_gas_species(const ora_sys *s, const ora_gas *g, double dt, const double
           xh2o_out[c] = n2 / nt;
           xn2_out[c] = n3 / nt;
         }
+  }
+}
+
+/* Gas-side momentum step of the two-way coupling (eqs. e4-1, e4-2 with the
+ * interphase source of eqs. e3-27, e3-27a), on the frozen pressure field:
+ *   eps rho (u' - u) / dt = -eps grad p + eps rho g + K_gp u' - K_gp u_p,
+ * the source K_gp u_g implicit and K_gp u_p explicit.  reading: K_gp =
+ * -sum_p K_p / V_cell and K_gp u_p = -sum_p K_p v_p / V_cell with K_p =
+ * beta V_p / (1 - eps) of the last deposit, so the gas takes exactly the
+ * drag the parcels feel (the printed form weights the sum by |u_g - v_p| /
+ * |u_g - u_p| and equals this one when the parcels of a cell move
+ * together).  eps is that of the last deposit, rho from eq. e3-53 at the
+ * cell's T, p and composition; convection, viscous and pseudo-turbulent
+ * stresses belong to the gas solver and are left out. */
+void ora_gas_momentum(const ora_sys *s, const ora_gas *g, double dt, const double *sumK, const double *sumKu,
+                      const double *sumKv, const double *sumKw, double *u_out, double *v_out, double *w_out) {
+  for (int b = 0; b < s->P.n_beds; b++) {
+    const ora_bed *B = &s->beds[b];
+    int ncb = B->n[0] * B->n[1] * B->n[2];
+    double V = B->h * B->h * B->h;
+    for (int q = 0; q < ncb; q++) {
+      int c = B->cell_off + q;
+      double rho, mu;
+      ora_gas_props(g->T[c], g->p[c], g->xH2[c], g->xH2O[c], g->xN2[c], 0.0, &rho, &mu);
+      double e = s->eps[c];
+      double u[3] = {g->ug[c], g->vg[c], g->wg[c]};
+      double gp[3] = {g->dpdx[c], g->dpdy[c], g->dpdz[c]};
+      double Kv[3] = {sumKu[c], sumKv[c], sumKw[c]};
+      double *out[3] = {u_out, v_out, w_out};
+      for (int a = 0; a < 3; a++) {
+        double num = e * rho * u[a] / dt - e * gp[a] + e * rho * s->P.g[a] + Kv[a] / V;
+        out[a][c] = num / (e * rho / dt + sumK[c] / V);
+      }
+    }
   }
 }

@@ -87,6 +87,11 @@ void ora_forces(ora_sys *s, const ora_gas *g, double *F, double *T);
  * evaluated in a lower precision */
 void ora_force_scale(ora_sys *s, const ora_gas *g, double *Fs, double *Ts);
 void ora_step(ora_sys *s, int nsteps, const ora_gas *g);
+/* test harness only: ora_step with every force and torque component biased by
+ * rel times the parcel's force-term scale (ora_force_scale), with a sign fixed
+ * per parcel, component and seed: a deterministic emulation of a lower-precision
+ * evaluation that errs by rel of the products the forces are built from */
+void ora_step_perturbed(ora_sys *s, int nsteps, const ora_gas *g, double rel, unsigned long long seed);
 /* voidage + drag deposition; outputs may be NULL */
 void ora_couple(ora_sys *s, const ora_gas *g, double *eps, double *np_, double *sumK,
                 double *sumKu, double *sumKv, double *sumKw, double *sumKs);
@@ -117,6 +122,12 @@ void ora_grad(ora_sys *s, const ora_gas *g, int n_sub, double dt_react, int dyn_
 void ora_gas_species(const ora_sys *s, const ora_gas *g, double dt, const double *sumEQ,
                      const double *sumES, const double xin[2], double *xh2_out, double *xh2o_out,
                      double *xn2_out);
+
+/* two-way coupling, momentum: one step dt of the gas velocity on the frozen
+ * pressure field with the interphase source of the last deposit's drag sums
+ * (eqs. e4-1, e4-2: K_gp u_g implicit, K_gp u_p explicit); new velocities out */
+void ora_gas_momentum(const ora_sys *s, const ora_gas *g, double dt, const double *sumK, const double *sumKu,
+                      const double *sumKv, const double *sumKw, double *u_out, double *v_out, double *w_out);
 
 /* ---- point functions, exported for the pins ---- */
 double ora_e_cgp(double e_p, double k);

@@ -116,6 +116,7 @@ def lib():
         L.ora_forces.argtypes = [C.c_void_p, C.POINTER(OraGas), _dp, _dp]
         L.ora_force_scale.argtypes = [C.c_void_p, C.POINTER(OraGas), _dp, _dp]
         L.ora_step.argtypes = [C.c_void_p, C.c_int, C.POINTER(OraGas)]
+        L.ora_step_perturbed.argtypes = [C.c_void_p, C.c_int, C.POINTER(OraGas), C.c_double, C.c_ulonglong]
         L.ora_couple.argtypes = [C.c_void_p, C.POINTER(OraGas)] + [_dp] * 7
         L.ora_react.restype = C.c_long
         L.ora_react.argtypes = [C.c_void_p, C.c_double, C.POINTER(OraGas), C.c_int] + [_dp] * 10
@@ -128,6 +129,7 @@ def lib():
             getattr(L, name).restype = C.c_double
             getattr(L, name).argtypes = [C.c_double] * 4
         L.ora_gas_species.argtypes = [C.c_void_p, C.POINTER(OraGas), C.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.ora_gas_momentum.argtypes = [C.c_void_p, C.POINTER(OraGas), C.c_double] + [_dp] * 7
         L.ora_nusselt.restype = C.c_double
         L.ora_nusselt.argtypes = [C.c_double] * 3
         L.ora_get.argtypes = [C.c_void_p] + [_dp] * 15
@@ -259,6 +261,12 @@ class Oracle:
     def step(self, n=1):
         lib().ora_step(self.h, int(n), C.byref(self._gs))
 
+    def step_perturbed(self, n, rel, seed=1):
+        """Test harness: steps with every force and torque component biased by
+        rel of the parcel's force-term scale, with a sign fixed per parcel,
+        component and seed (ora_step_perturbed)."""
+        lib().ora_step_perturbed(self.h, int(n), C.byref(self._gs), float(rel), int(seed))
+
     def couple(self):
         out = {k: np.zeros(self.n_cells) for k in ("eps", "np", "sumK", "sumKu", "sumKv", "sumKw", "sumKs")}
         lib().ora_couple(self.h, C.byref(self._gs), *[_p(out[k]) for k in
@@ -289,6 +297,15 @@ class Oracle:
         xi = np.ascontiguousarray(xin, dtype=np.float64)
         lib().ora_gas_species(self.h, C.byref(self._gs), float(dt), _p(eq), _p(es), _p(xi), *[_p(o) for o in out])
         return {"xH2": out[0], "xH2O": out[1], "xN2": out[2]}
+
+    def gas_momentum(self, dt, sums):
+        """New gas velocity (ug, vg, wg) per cell after one step dt of the
+        interphase momentum exchange with the drag sums of a deposit
+        (sumK, sumKu, sumKv, sumKw; see ora_gas_momentum)."""
+        out = [np.zeros(self.n_cells) for _ in range(3)]
+        ins = [np.ascontiguousarray(sums[k], dtype=np.float64) for k in ("sumK", "sumKu", "sumKv", "sumKw")]
+        lib().ora_gas_momentum(self.h, C.byref(self._gs), float(dt), *[_p(a) for a in ins], *[_p(o) for o in out])
+        return {"ug": out[0], "vg": out[1], "wg": out[2]}
 
     def grad(self, n_sub, dt_react, dyn_every, theta):
         if self.energy:

@@ -21,7 +21,7 @@ def _ptr(t):
 
 class Bed:
     def __init__(self, w, device="cuda:0", drag_on=True, g=None, stream=None, theta=None, max_nbr=None,
-                 rebuild_every=None):
+                 check_every=None):
         self.L = capi.load()
         self.w = w
         self.device = torch.device(device)
@@ -58,7 +58,7 @@ class Bed:
         for i in range(3):
             P.g[i] = gg[i]
         P.max_nbr = prm["max_nbr"] if max_nbr is None else max_nbr
-        P.rebuild_every = prm["rebuild_every"] if rebuild_every is None else rebuild_every
+        P.check_every = prm["check_every"] if check_every is None else check_every
         P.ergun_printed = int(prm.get("ergun_printed", 0))
         P.drag_on = int(drag_on)
         P.energy_on = int(prm.get("energy_on", 0))
@@ -145,6 +145,19 @@ class Bed:
         self._check(self.L.dem_gas_species(self.h, float(dt), C.byref(self._gas), _ptr(sources["sumEQ"]),
                                            _ptr(sources["sumES"]), xi, _ptr(out["xH2"]), _ptr(out["xH2O"]),
                                            _ptr(out["xN2"])))
+        if update:
+            for k in out:
+                self.gas_t[k].copy_(out[k])
+        return out
+
+    def gas_momentum(self, dt, sums, update=True):
+        """One gas-side momentum step (dem_gas_momentum) from the drag sums of
+        a previous couple(); returns the new (ug, vg, wg) and, with update,
+        copies them into this bed's gas fields."""
+        out = {k: torch.zeros(self.n_cells, dtype=torch.float64, device=self.device) for k in ("ug", "vg", "wg")}
+        self._check(self.L.dem_gas_momentum(self.h, float(dt), C.byref(self._gas),
+                                            *[_ptr(sums[k]) for k in ("sumK", "sumKu", "sumKv", "sumKw")],
+                                            *[_ptr(out[k]) for k in ("ug", "vg", "wg")]))
         if update:
             for k in out:
                 self.gas_t[k].copy_(out[k])

@@ -37,7 +37,7 @@ class DemParams(C.Structure):
                 ("kn", C.c_double), ("e_p", C.c_double), ("mu_s", C.c_double), ("mu_r", C.c_double),
                 ("kt_over_kn", C.c_double), ("gt_over_gn", C.c_double), ("eps_min", C.c_double),
                 ("skin", C.c_double), ("dt", C.c_double), ("g", C.c_double * 3),
-                ("max_nbr", C.c_int32), ("rebuild_every", C.c_int32), ("ergun_printed", C.c_int32),
+                ("max_nbr", C.c_int32), ("check_every", C.c_int32), ("ergun_printed", C.c_int32),
                 ("drag_on", C.c_int32), ("energy_on", C.c_int32)]
 
 
@@ -75,10 +75,11 @@ class DemStats(C.Structure):
                 ("mean_coordination", C.c_double), ("max_nbr_used", C.c_int32), ("status", C.c_uint32),
                 ("step_kernel_ms", C.c_double), ("step_kernel_launches", C.c_int64),
                 ("step_block", C.c_int32), ("step_xcd", C.c_int32), ("build_grid", C.c_int32),
-                ("rebuild_period", C.c_int32)]
+                ("check_period", C.c_int32)]
 
 
-EXPORTS = ("dem_init", "dem_step", "dem_couple", "dem_react", "dem_gas_species", "dem_grad", "dem_forces",
+EXPORTS = ("dem_init", "dem_step", "dem_couple", "dem_react", "dem_gas_species", "dem_gas_momentum", "dem_grad",
+           "dem_forces",
            "dem_get_state", "dem_set_state", "dem_pairs", "dem_get_stats", "dem_run", "dem_autotune", "dem_set_launch", "dem_profile",
            "dem_sync",
            "dem_last_error", "dem_destroy")
@@ -110,6 +111,7 @@ def load(path: str = LIB_PATH):
     L.dem_couple.argtypes = [vp, C.POINTER(DemGas), C.POINTER(DemSources)]
     L.dem_react.argtypes = [vp, C.c_double, C.POINTER(DemGas), C.POINTER(DemSources), C.POINTER(C.c_double), vp]
     L.dem_gas_species.argtypes = [vp, C.c_double, C.POINTER(DemGas), vp, vp, C.POINTER(C.c_double), vp, vp, vp]
+    L.dem_gas_momentum.argtypes = [vp, C.c_double, C.POINTER(DemGas)] + [vp] * 7
     L.dem_grad.argtypes = [vp, C.POINTER(DemGradSpec), C.POINTER(DemGas), C.POINTER(C.c_double),
                            C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.dem_forces.argtypes = [vp, C.POINTER(DemGas), vp, vp]

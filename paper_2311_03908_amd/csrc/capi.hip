@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -25,6 +26,8 @@ struct dem_ctx {
   virtual int react(double dt, const dem_gas *g, dem_sources *o, double *bed_fov, double *fov) = 0;
   virtual int gas_species(double dt, const dem_gas *g, const double *eq, const double *es, const double *xin,
                           double *x1, double *x2, double *x3) = 0;
+  virtual int gas_momentum(double dt, const dem_gas *g, const double *sK, const double *sKu, const double *sKv,
+                           const double *sKw, double *u, double *v, double *w) = 0;
   virtual int forces(const dem_gas *g, double *F, double *T) = 0;
   virtual int get_state(dem_parcels *o) = 0;
   virtual int set_state(const dem_parcels *in) = 0;
@@ -112,16 +115,22 @@ struct Ctx final : dem_ctx {
   OreDev *ores = nullptr;
   int32_t *cell_bed = nullptr;
   Item *items = nullptr;
-  Dyn<T> dyn[2]{};
-  Props<T> pr[2]{};
-  Nbr<T> nb[2]{};
-  int cur = 0, pc = 0, nbc = 0;
+  Dyn<T> dyn[2]{};  // step buffers: a step reads dyn[cur] and writes dyn[cur ^ 1]
+  Props<T> pr{}, pr_sp{};  // properties and the spare the rebuild permutes into
+  Nbr<T> nb{};
+  Spring<T> *carry = nullptr;      // springs carried across a rebuild (launch_carry)
+  uint32_t *carry_meta = nullptr;
+  uint32_t *rb_flag = nullptr;     // set by the rebuild check: rebuild at this check point
+  unsigned long long *rb_count = nullptr;  // rebuilds done (device counter)
+  int cur = 0;
   int32_t *key = nullptr, *slot = nullptr, *count = nullptr, *start = nullptr, *perm = nullptr, *scan_scr = nullptr;
   int32_t *perm2 = nullptr;
+  CellOrd cord{};  // cell-ordered x, id, key of the last scatter
   // cell order of the current positions for the deposits (refreshed at every
   // coupling without permuting the parcels or rebuilding neighbour lists)
   int32_t *start_d = nullptr, *order_d = nullptr;
   bool dep_fresh = false;
+  bool occ_fresh = false;  // occupied-cell list of the current cell order
   int32_t *occ_flags = nullptr, *occ_offs = nullptr, *occ_list = nullptr, *occ_count = nullptr;
   int4 *bchunks = nullptr;
   double *bpartial = nullptr;
@@ -139,7 +148,7 @@ struct Ctx final : dem_ctx {
   unsigned long long *counters = nullptr;  // pp contacts, wall contacts, clamps, pairs
   uint32_t *pairs_buf = nullptr;
   long pairs_cap = 0;
-  long step_count = 0, steps_since = 0, rebuilds = 0;
+  long step_count = 0;
   bool built = false;
   int step_block = 64, build_grid = 1024, step_xcd = 1;
   hipGraph_t graph = nullptr;
@@ -204,6 +213,8 @@ struct Ctx final : dem_ctx {
     TRY(dalloc(b.idx, (size_t)kMaxNbr * n));
     TRY(dalloc(b.hist, (size_t)kMaxNbr * n));
     TRY(dalloc(b.mask, n));
+    TRY(dalloc(carry, (size_t)kMaxNbr * n));
+    TRY(dalloc(carry_meta, n));
     return DEMRX_OK;
   }
 
@@ -308,12 +319,14 @@ struct Ctx final : dem_ctx {
     TRY(dalloc(ores, hod.size()));
     TRY(dalloc(cell_bed, n_gas));
     TRY(dalloc(items, n_items));
-    for (int k = 0; k < 2; k++) {
-      TRY(alloc_dyn(dyn[k]));
-      TRY(alloc_props(pr[k], k ? &pr[0] : nullptr));
-      TRY(alloc_nbr(nb[k]));
-    }
+    for (int k = 0; k < 2; k++) TRY(alloc_dyn(dyn[k]));
+    TRY(alloc_props(pr, nullptr));
+    TRY(alloc_props(pr_sp, &pr));
+    TRY(alloc_nbr(nb));
+    TRY(dalloc(rb_flag, 1));
+    TRY(dalloc(rb_count, 1));
     TRY(dalloc(key, n)); TRY(dalloc(slot, n)); TRY(dalloc(perm, n)); TRY(dalloc(perm2, n));
+    TRY(dalloc(cord.x, n)); TRY(dalloc(cord.id, n)); TRY(dalloc(cord.key, n));
     max_chunks = n / kBedChunk + p->n_beds + 2;
     TRY(dalloc(bchunks, max_chunks));
     TRY(dalloc(bpartial, 2 * (size_t)max_chunks));
@@ -341,18 +354,17 @@ struct Ctx final : dem_ctx {
     HIPCHK(hipMemcpyAsync(cell_bed, hcb.data(), hcb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     if ((long)hit.size() != n_items) return fail(DEMRX_EINVAL, "internal: work-item count mismatch");
     HIPCHK(hipMemcpyAsync(items, hit.data(), hit.size() * sizeof(Item), hipMemcpyHostToDevice, st));
-    for (int k = 0; k < 2; k++) {
-      launch_fill_u32((uint32_t *)nb[k].mask, 0u, 2L * n, st);
-      launch_fill_i32(nb[k].cnt, 0, n, st);
-    }
+    launch_fill_u32((uint32_t *)nb.mask, 0u, 2L * n, st);
+    launch_fill_i32(nb.cnt, 0, n, st);
+    launch_fill_u32((uint32_t *)rb_count, 0u, 2, st);
     launch_fill_u32(status, 0u, 1, st);
     launch_fill_u32(dslot, 0u, 2 * kSlots * kSlotPad, st);
     launch_fill_u32((uint32_t *)cslot, 0u, 2 * kSlots * kSlotPad64, st);
     launch_fill_u32((uint32_t *)counters, 0u, 8, st);
-    launch_init<T>(*in, n, ph, p->n_ores, thermo, dyn[0], pr[0], status, st);
+    launch_init<T>(*in, n, ph, p->n_ores, thermo, dyn[0], pr, status, st);
     HIPCHK(hipGetLastError());
     TRY(check_status());
-    TRY(rebuild());
+    TRY(rebuild_chain(1, true));
     TRY(resort());
     DepositOut o{};
     o.eps_ctx = eps;
@@ -377,22 +389,34 @@ struct Ctx final : dem_ctx {
     return check_status();
   }
 
-  int rebuild() {
-    launch_fill_i32(count, 0, (long)n_keys + 1, st);
-    launch_bin<T>(dyn[cur], pr[pc], beds, n, key, slot, count, status, st);
-    launch_scan(count, start, (long)n_keys + 1, scan_scr, st);
-    launch_scatter(key, slot, start, n, perm2, st);
-    launch_cellrank(start, key, dyn[cur].pos, perm2, n, perm, st);
-    launch_permute<T>(perm, n, dyn[cur], pr[pc], dyn[cur ^ 1], pr[pc ^ 1], xref, dslot, st);
-    cur ^= 1;
-    pc ^= 1;
-    launch_items(items, n_items, beds, start, iflags, ioffs, scan_scr, ilist, icount, st);
+  // Neighbour-list rebuild check and the rebuild chain behind it.  The check
+  // kernel sets rb_flag when the lists could go stale within `horizon` steps
+  // (or when forced); every kernel of the chain returns at once when it is
+  // clear, so the chain's place in a captured graph is fixed while whether it
+  // runs is decided on the device.  A rebuild sorts the parcels by DEM cell
+  // (bin, scan, scatter, in-cell rank), compacts the contact springs,
+  // permutes the state through the spare buffers back into dyn[cur] and pr,
+  // and builds the lists; no buffer parity changes.
+  int rebuild_chain(int horizon, bool force) {
+    const uint32_t *G = rb_flag;
+    launch_rebuild_check(dslot, (int)((step_count & 1) ^ 1), P.skin, P.dt, horizon, force ? 1 : 0, rb_flag,
+                         rb_count, st);
+    launch_fill_i32(count, 0, (long)n_keys + 1, st, G);
+    launch_bin<T>(dyn[cur], pr, beds, n, key, slot, count, status, st, G);
+    launch_scan(count, start, (long)n_keys + 1, scan_scr, st, G);
+    launch_scatter(key, slot, start, dyn[cur].pos, n, perm2, cord, st, G);
+    launch_cellrank(start, perm2, cord, n, perm, st, G);
+    launch_carry<T>(nb, n, carry, carry_meta, st, G);
+    launch_permute<T>(perm, n, dyn[cur], pr, dyn[cur ^ 1], pr_sp, xref, dslot, st, G);
+    launch_items(items, n_items, beds, start, iflags, ioffs, scan_scr, ilist, icount, st, G);
     NbrBuild<T> a;
     a.d = dyn[cur];
-    a.p = pr[pc];
+    a.p = pr;
     a.perm = perm;
-    a.nb_new = nb[nbc ^ 1];
-    a.nb_old = nb[nbc];
+    a.nb = nb;
+    a.carry = carry;
+    a.carry_meta = carry_meta;
+    a.gate = G;
     a.beds = beds;
     a.start = start;
     a.items = items;
@@ -403,14 +427,11 @@ struct Ctx final : dem_ctx {
     a.skin = P.skin;
     a.status = status;
     a.queue = icount + 1;
-    launch_fill_i32(a.queue, 0, 1, st);
+    launch_fill_i32(a.queue, 0, 1, st, G);
     launch_build_nbr<T>(a, std::max(1, std::min(n_items, build_grid)), st);
-    nbc ^= 1;
     HIPCHK(hipGetLastError());
-    steps_since = 0;
-    rebuilds++;
     built = true;
-    dep_fresh = false;
+    dep_fresh = false;  // the parcels may have moved in memory
     return DEMRX_OK;
   }
 
@@ -419,17 +440,18 @@ struct Ctx final : dem_ctx {
   // order_d.  Deterministic like the full sort.
   int resort() {
     launch_fill_i32(count, 0, (long)n_keys + 1, st);
-    launch_bin<T>(dyn[cur], pr[pc], beds, n, key, slot, count, status, st);
+    launch_bin<T>(dyn[cur], pr, beds, n, key, slot, count, status, st);
     launch_scan(count, start_d, (long)n_keys + 1, scan_scr, st);
-    launch_scatter(key, slot, start_d, n, perm2, st);
-    launch_cellrank(start_d, key, dyn[cur].pos, perm2, n, order_d, st);
+    launch_scatter(key, slot, start_d, dyn[cur].pos, n, perm2, cord, st);
+    launch_cellrank(start_d, perm2, cord, n, order_d, st);
     HIPCHK(hipGetLastError());
     dep_fresh = true;
+    occ_fresh = false;
     return DEMRX_OK;
   }
 
   int ensure_dep() {
-    if (!built) TRY(rebuild());
+    if (!built) TRY(rebuild_chain(1, true));
     if (!dep_fresh) TRY(resort());
     return DEMRX_OK;
   }
@@ -438,7 +460,8 @@ struct Ctx final : dem_ctx {
   // empty cells directly, occupied cells through their compacted list
   int deposit(const GasArgs &g, bool sums, const DepositOut &o) {
     launch_occupied(start_d, cell_bed, beds, n_gas, sums, o, occ_flags, occ_offs, scan_scr, occ_list, occ_count, st);
-    launch_deposit<T>(dyn[cur], pr[pc], g, start_d, order_d, cell_bed, beds, ores, ph, occ_list, occ_count, n_gas,
+    occ_fresh = true;
+    launch_deposit<T>(dyn[cur], pr, g, start_d, order_d, cell_bed, beds, ores, ph, occ_list, occ_count, n_gas,
                       sums, o, st);
     HIPCHK(hipGetLastError());
     return DEMRX_OK;
@@ -455,8 +478,8 @@ struct Ctx final : dem_ctx {
     StepArgs<T> a;
     a.in = dyn[cur];
     a.out = dyn[cur ^ 1];
-    a.pr = pr[pc];
-    a.nb = nb[nbc];
+    a.pr = pr;
+    a.nb = nb;
     a.gtab = gtab;
     a.beds = beds;
     a.ores = ores;
@@ -488,8 +511,15 @@ struct Ctx final : dem_ctx {
     return DEMRX_OK;
   }
 
+  // The lists are checked before every step whose index is a multiple of
+  // check_every, eagerly and in graphs alike, so both take the same decisions.
+  int check_period() const { return std::max(1, P.check_every); }
+  bool check_due() const { return !built || step_count % check_period() == 0; }
+  // steps from a due check to the next one
+  int check_horizon() const { return check_period() - (int)(step_count % check_period()); }
+
+  // One DEM step (the lists must be valid for it).
   int step_one(bool count = false) {
-    if (!built || steps_since >= P.rebuild_every) TRY(rebuild());
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof) {
       auto &lst = capturing ? prof_capture : prof_eager;
@@ -506,9 +536,14 @@ struct Ctx final : dem_ctx {
     if (prof) HIPCHK(hipEventRecord(e1, st));
     cur ^= 1;
     step_count++;
-    steps_since++;
     dep_fresh = false;
     return DEMRX_OK;
+  }
+
+  // One step with the list check in front of it when one is due.
+  int step_checked(bool count = false) {
+    if (check_due()) TRY(rebuild_chain(check_horizon(), !built));
+    return step_one(count);
   }
 
   int step(int ns, const dem_gas *g) override {
@@ -518,15 +553,13 @@ struct Ctx final : dem_ctx {
     TRY(gas_table(g));
     for (int s = 0; s < ns; s++) {
       if (s == ns - 1) launch_fill_u32((uint32_t *)cslot, 0u, 2 * kSlots * kSlotPad64, st);
-      TRY(step_one(s == ns - 1));
+      TRY(step_checked(s == ns - 1));
     }
     return DEMRX_OK;
   }
 
-  int ensure_sorted() {
-    if (!built || steps_since > 0) TRY(rebuild());
-    return DEMRX_OK;
-  }
+  // Lists valid for the current positions (check with a one-step horizon).
+  int ensure_lists() { return rebuild_chain(1, !built); }
 
   int couple(const dem_gas *g, dem_sources *o) override {
     if (!gas_ok(g)) return fail(DEMRX_EINVAL, "null gas field");
@@ -549,7 +582,7 @@ struct Ctx final : dem_ctx {
     TRY(ensure_dep());
     ReactArgs<T> a;
     a.d = dyn[cur];
-    a.p = pr[pc];
+    a.p = pr;
     a.g = gas_args(g);
     a.eps = eps;
     a.beds = beds;
@@ -569,7 +602,14 @@ struct Ctx final : dem_ctx {
       CellSumOut cs{{o->mdotH2, o->mdotH2O, o->sumEQ, o->sumES, o->hA, o->hAT, o->Qrm, o->Hr}, thermo ? 8 : 4};
       bool any = false;
       for (int q = 0; q < cs.rows; q++) any |= cs.o[q] != nullptr;
-      if (any) launch_cellsum(pm, n, start_d, order_d, cell_bed, beds, n_gas, cs, st);
+      if (any) {
+        if (!occ_fresh) {  // occupied cells of the current order, voidage untouched
+          launch_occupied(start_d, cell_bed, beds, n_gas, false, DepositOut{}, occ_flags, occ_offs, scan_scr, occ_list,
+                          occ_count, st);
+          occ_fresh = true;
+        }
+        launch_cellsum(pm, n, start_d, order_d, cell_bed, beds, n_gas, occ_flags, occ_list, occ_count, n_gas, cs, st);
+      }
     }
     if (bed_sum) launch_bedsum(pw, n, start, beds, P.n_beds, bchunks, max_chunks, bpartial, bed_fov_d, st);
     HIPCHK(hipGetLastError());
@@ -604,9 +644,19 @@ struct Ctx final : dem_ctx {
     return DEMRX_OK;
   }
 
+  int gas_momentum(double dt, const dem_gas *g, const double *sK, const double *sKu, const double *sKv,
+                   const double *sKw, double *u, double *v, double *w) override {
+    if (!gas_ok(g) || !sK || !sKu || !sKv || !sKw || !u || !v || !w) return fail(DEMRX_EINVAL, "null argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DEMRX_EINVAL, "dt must be positive");
+    TRY(ensure_dep());
+    launch_gas_momentum(gas_args(g), eps, cell_bed, beds, n_gas, dt, P.g, sK, sKu, sKv, sKw, u, v, w, status, st);
+    HIPCHK(hipGetLastError());
+    return DEMRX_OK;
+  }
+
   int forces(const dem_gas *g, double *F, double *Tq) override {
     if (!gas_ok(g) || !F || !Tq) return fail(DEMRX_EINVAL, "null argument");
-    if (!built || steps_since >= P.rebuild_every) TRY(rebuild());
+    TRY(ensure_lists());
     TRY(gas_table(g));
     StepArgs<T> a = step_args(1);
     a.Fout = F;
@@ -618,7 +668,7 @@ struct Ctx final : dem_ctx {
 
   int get_state(dem_parcels *o) override {
     if (!o) return fail(DEMRX_EINVAL, "null output");
-    launch_export<T>(dyn[cur], pr[pc], n, *o, st);
+    launch_export<T>(dyn[cur], pr, n, *o, st);
     HIPCHK(hipGetLastError());
     return sync();
   }
@@ -627,10 +677,10 @@ struct Ctx final : dem_ctx {
     if (!in || !in->x || !in->y || !in->z || !in->vx || !in->vy || !in->vz || !in->wx || !in->wy || !in->wz ||
         !in->nh || !in->nm || !in->nw || !in->nfe)
       return fail(DEMRX_EINVAL, "null parcel array");
-    launch_import<T>(*in, n, thermo, dyn[cur], pr[pc], st);
-    for (int k = 0; k < 2; k++) launch_fill_u32((uint32_t *)nb[k].mask, 0u, 2L * n, st);
+    launch_import<T>(*in, n, thermo, dyn[cur], pr, st);
+    launch_fill_u32((uint32_t *)nb.mask, 0u, 2L * n, st);
     built = false;
-    TRY(rebuild());
+    TRY(rebuild_chain(1, true));
     TRY(resort());
     DepositOut o{};
     o.eps_ctx = eps;
@@ -641,14 +691,14 @@ struct Ctx final : dem_ctx {
 
   int pairs(uint32_t *ij, int64_t cap, int64_t *np) override {
     if (!np || (cap > 0 && !ij) || cap < 0) return fail(DEMRX_EINVAL, "bad pair buffer");
-    TRY(ensure_sorted());
+    TRY(ensure_lists());
     for (int attempt = 0; attempt < 2; attempt++) {
       if (!pairs_buf) {
         pairs_cap = std::max<long>(1024, (long)n * 4);
         TRY(dalloc(pairs_buf, 2 * (size_t)pairs_cap));
       }
       launch_fill_u32((uint32_t *)(counters + 3), 0u, 2, st);
-      launch_pairs<T>(dyn[cur], pr[pc], nb[nbc], n, P.max_nbr, pairs_buf, pairs_cap, counters + 3, st);
+      launch_pairs<T>(dyn[cur], pr, nb, n, P.max_nbr, pairs_buf, pairs_cap, counters + 3, st);
       HIPCHK(hipGetLastError());
       unsigned long long c = 0;
       HIPCHK(hipMemcpyAsync(&c, counters + 3, sizeof c, hipMemcpyDeviceToHost, st));
@@ -675,9 +725,10 @@ struct Ctx final : dem_ctx {
 
   int stats(dem_stats *o) override {
     if (!o) return fail(DEMRX_EINVAL, "null output");
-    unsigned long long c[4];
+    unsigned long long c[4], rbc = 0;
     std::vector<unsigned long long> cs((size_t)kSlots * kSlotPad64);
     HIPCHK(hipMemcpyAsync(c, counters, sizeof c, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&rbc, rb_count, sizeof rbc, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(cs.data(), cslot, cs.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     int r = sync();
     c[0] = c[1] = 0;
@@ -688,7 +739,7 @@ struct Ctx final : dem_ctx {
     o->n_parcels = n;
     o->n_contacts = (int64_t)(c[0] / 2);
     o->n_wall_contacts = (int64_t)c[1];
-    o->rebuilds = rebuilds;
+    o->rebuilds = (int64_t)rbc;
     o->steps = step_count;
     o->clamps = (int64_t)c[2];
     o->mean_coordination = n ? (double)c[0] / n : 0.0;
@@ -712,30 +763,30 @@ struct Ctx final : dem_ctx {
     o->step_block = step_block;
     o->step_xcd = step_xcd;
     o->build_grid = build_grid;
-    o->rebuild_period = P.rebuild_every;
+    o->check_period = check_period();
     return r;
   }
 
-  // One coupling interval of the hot path.  With rebuild_first the neighbour
-  // lists are rebuilt before its first step (the replay schedule below);
-  // step_one also rebuilds whenever rebuild_every steps have passed.
-  int interval(int S, const dem_gas *g, dem_sources *o, bool rebuild_first = false) {
-    if (rebuild_first) TRY(rebuild());
+  // One coupling interval of the hot path: S DEM steps (each with the list
+  // check in front of it when one is due), the deposit and the reaction.
+  int interval(int S, const dem_gas *g, dem_sources *o) {
     TRY(gas_table(g));
     for (int s = 0; s < S; s++) {
       if (s == S - 1) launch_fill_u32((uint32_t *)cslot, 0u, 2 * kSlots * kSlotPad64, st);  // last step counts
-      TRY(step_one(s == S - 1));
+      TRY(step_checked(s == S - 1));
     }
     TRY(couple(g, o));
     TRY(react_core(S * P.dt, g, o, nullptr, true, 1, nullptr));
     return DEMRX_OK;
   }
 
-  // Replay schedule: lists are rebuilt at the start of every m-th interval,
-  // m = max(1, rebuild_every / S), so they are never older than rebuild_every
-  // steps; a graph of 2m intervals holds an even number of rebuilds and steps
-  // and so returns every buffer parity to its starting value.
-  int sched_period(int S) const { return std::max(1, P.rebuild_every / S); }
+  // Intervals per graph: the fewest whose steps are a multiple of 2 (the
+  // step buffers flip every step) and of the check period, so every replay
+  // starts at the same buffer parity and check phase as the capture.
+  long graph_intervals(int S) const {
+    const long a = std::lcm((long)S, 2L), b = std::lcm(a, (long)check_period());
+    return b / S;
+  }
 
   int run(int n_int, int S, const dem_gas *g, dem_sources *o, double *bed_fov) override {
     if (n_int < 0 || S < 1) return fail(DEMRX_EINVAL, "bad interval count");
@@ -751,12 +802,16 @@ struct Ctx final : dem_ctx {
     k.push_back((const void *)(intptr_t)step_block);
     k.push_back((const void *)(intptr_t)step_xcd);
     // the graph bakes in the buffer parities it was captured at
-    k.push_back((const void *)(intptr_t)(cur | (pc << 1) | (nbc << 2) | (int)((step_count & 1) << 3)));
+    k.push_back((const void *)(intptr_t)(cur | (int)((step_count & 1) << 1)));
+    k.push_back((const void *)(intptr_t)(step_count % check_period()));
+    if (graph_intervals(S) > 4096) return fail(DEMRX_EINVAL, "couple_every and check_every give a graph of more "
+                                                             "than 4096 intervals");
     if (!cap_st) {
       HIPCHK(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking));
       HIPCHK(hipEventCreateWithFlags(&ev_a, hipEventDisableTiming));
       HIPCHK(hipEventCreateWithFlags(&ev_b, hipEventDisableTiming));
     }
+    if (!built) TRY(rebuild_chain(1, true));  // a forced first build stays out of the graph
     HIPCHK(hipEventRecord(ev_a, user_st));
     HIPCHK(hipStreamWaitEvent(cap_st, ev_a, 0));
     st = cap_st;
@@ -773,18 +828,18 @@ struct Ctx final : dem_ctx {
   }
 
   int run_on_cap(int n_int, int S, const dem_gas *g, dem_sources *o, const std::vector<const void *> &k) {
-    const int m = sched_period(S), G = 2 * m;
+    const int G = (int)graph_intervals(S);
     if (!gexec || k != gkey) {
       if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
       if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
-      const int s_cur = cur, s_pc = pc, s_nbc = nbc;
-      const long s_sc = step_count, s_ss = steps_since, s_rb = rebuilds;
-      const bool s_built = built, s_dep = dep_fresh;
+      const int s_cur = cur;
+      const long s_sc = step_count;
+      const bool s_dep = dep_fresh, s_occ = occ_fresh;
       HIPCHK(hipStreamBeginCapture(cap_st, hipStreamCaptureModeRelaxed));
       capturing = true;
       prof_capture.clear();
       int r = DEMRX_OK;
-      for (int q = 0; q < G && r == DEMRX_OK; q++) r = interval(S, g, o, q % m == 0);
+      for (int q = 0; q < G && r == DEMRX_OK; q++) r = interval(S, g, o);
       capturing = false;
       hipGraph_t gr = nullptr;
       hipError_t e = hipStreamEndCapture(cap_st, &gr);
@@ -793,18 +848,18 @@ struct Ctx final : dem_ctx {
         return r;
       }
       if (e != hipSuccess) return fail(DEMRX_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
-      if (cur != s_cur || pc != s_pc || nbc != s_nbc || ((step_count ^ s_sc) & 1))
+      if (cur != s_cur || ((step_count ^ s_sc) & 1))
         return fail(DEMRX_EHIP, "graph intervals do not restore buffer parity");
       graph = gr;
       HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
       gkey = k;
       gprof = prof;
-      rebuilds_per_graph = rebuilds - s_rb;
-      ss_after_graph = steps_since;
       dep_after_graph = dep_fresh;
-      cur = s_cur; pc = s_pc; nbc = s_nbc;
-      step_count = s_sc; steps_since = s_ss; rebuilds = s_rb;
-      built = s_built; dep_fresh = s_dep;
+      occ_after_graph = occ_fresh;
+      cur = s_cur;
+      step_count = s_sc;
+      dep_fresh = s_dep;
+      occ_fresh = s_occ;
     }
     if (gprof != prof) {  // recapture with or without timing events
       gkey.clear();
@@ -814,21 +869,18 @@ struct Ctx final : dem_ctx {
     for (int q = 0; q < n_int / G; q++) {
       HIPCHK(hipGraphLaunch(gexec, cap_st));
       step_count += (long)G * S;
-      rebuilds += rebuilds_per_graph;
-      built = true;
-      steps_since = ss_after_graph;
       dep_fresh = dep_after_graph;
+      occ_fresh = occ_after_graph;
     }
-    for (int q = 0; q < n_int % G; q++) TRY(interval(S, g, o, q % m == 0));
+    for (int q = 0; q < n_int % G; q++) TRY(interval(S, g, o));
     return DEMRX_OK;
   }
-  long rebuilds_per_graph = 0, ss_after_graph = 0;
-  bool dep_after_graph = false;
+  bool dep_after_graph = false, occ_after_graph = false;
   bool gprof = false;
 
   int autotune(const dem_gas *g) override {
     if (!gas_ok(g)) return fail(DEMRX_EINVAL, "null gas field");
-    TRY(ensure_sorted());
+    TRY(ensure_lists());
     TRY(gas_table(g));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -863,7 +915,7 @@ struct Ctx final : dem_ctx {
       float tot = 0.0f;
       for (int rep = 0; rep < 3; rep++) {
         HIPCHK(hipEventRecord(e0, st));
-        TRY(rebuild());
+        TRY(rebuild_chain(1, true));
         HIPCHK(hipEventRecord(e1, st));
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0.0f;
@@ -913,7 +965,7 @@ static int validate(const dem_params *p, const dem_parcels *in, int32_t n, std::
     m = "bad physical parameter";
     return DEMRX_EINVAL;
   }
-  if (p->max_nbr < 1 || p->max_nbr > DEM_MAX_NBR || p->rebuild_every < 1) { m = "bad max_nbr/rebuild_every"; return DEMRX_EINVAL; }
+  if (p->max_nbr < 1 || p->max_nbr > DEM_MAX_NBR || p->check_every < 1) { m = "bad max_nbr/check_every"; return DEMRX_EINVAL; }
   for (int b = 0; b < p->n_beds; b++) {
     const dem_bed &B = p->beds[b];
     if (B.wall_kind != DEM_WALL_BOX && B.wall_kind != DEM_WALL_CYL) { m = "bad wall kind"; return DEMRX_EINVAL; }
@@ -987,6 +1039,10 @@ int dem_react(dem_ctx *c, double dt, const dem_gas *g, dem_sources *o, double *b
 int dem_gas_species(dem_ctx *c, double dt, const dem_gas *g, const double *sumEQ, const double *sumES,
                     const double xin[2], double *xH2, double *xH2O, double *xN2) {
   return c ? c->gas_species(dt, g, sumEQ, sumES, xin, xH2, xH2O, xN2) : DEMRX_EINVAL;
+}
+int dem_gas_momentum(dem_ctx *c, double dt, const dem_gas *g, const double *sumK, const double *sumKu,
+                     const double *sumKv, const double *sumKw, double *ug, double *vg, double *wg) {
+  return c ? c->gas_momentum(dt, g, sumK, sumKu, sumKv, sumKw, ug, vg, wg) : DEMRX_EINVAL;
 }
 int dem_grad(dem_ctx *c, const dem_grad_spec *s, const dem_gas *g, const double theta[6], double *J, double *grad) {
   return c ? c->grad(s, g, theta, J, grad) : DEMRX_EINVAL;

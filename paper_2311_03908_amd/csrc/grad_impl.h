@@ -9,8 +9,9 @@
 // interval and keeps only the current interval's record.
 //
 // The context's DEM state is snapshotted after a (physically neutral)
-// neighbour rebuild and restored at the end; the context's reaction state is
-// only read.
+// neighbour rebuild, so that the displacements since the rebuild restart
+// from zero with it, and restored at the end; the context's reaction state
+// is only read.
 
 template <typename T>
 int Ctx<T>::grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, double *J, double *gr) {
@@ -68,15 +69,15 @@ int Ctx<T>::grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, 
   }
   char *B = (char *)gscr.base;
 
-  TRY(ensure_sorted());
+  TRY(rebuild_chain(1, true));  // displacements since the rebuild start from zero
   // ---- snapshot
   struct Cp {
     void *live;
     size_t o, bytes;
   };
   const Dyn<T> &d0 = dyn[cur];
-  const Props<T> &p0 = pr[pc];
-  const Nbr<T> &b0 = nb[nbc];
+  const Props<T> &p0 = pr;
+  const Nbr<T> &b0 = nb;
   const Cp cps[] = {
       {d0.pos, o_pos, N * sizeof(PosRec)}, {d0.vel, o_vel, N * sizeof(VelRec<T>)},
       {p0.kcg, o_kcg, N * 4}, {p0.tag, o_tag, N * 4},
@@ -87,7 +88,7 @@ int Ctx<T>::grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, 
       {eps, o_eps, (size_t)n_gas * 8}, {start, o_start, ((size_t)n_keys + 1) * 4},
       {xref, o_xref, N * sizeof(float4)}};
   for (const Cp &c : cps) HIPCHK(hipMemcpyAsync(B + c.o, c.live, c.bytes, hipMemcpyDeviceToDevice, st));
-  const int cur0 = cur, pc0 = pc, nbc0 = nbc;
+  const int cur0 = cur;
   const long sc0 = step_count;
 
   // ---- static tables
@@ -115,10 +116,10 @@ int Ctx<T>::grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, 
   a.seg = want ? (void *)(B + o_seg) : nullptr;
   a.part = (double *)(B + o_part);
   if (fp32)
-    launch_adj_static<T, float>(dyn[cur], pr[pc], ores, n, (double *)(B + o_dp), (double *)(B + o_k3),
+    launch_adj_static<T, float>(dyn[cur], pr, ores, n, (double *)(B + o_dp), (double *)(B + o_k3),
                                 (int32_t *)(B + o_ore), (int32_t *)(B + o_kind), (float *)a.state, st);
   else
-    launch_adj_static<T, double>(dyn[cur], pr[pc], ores, n, (double *)(B + o_dp), (double *)(B + o_k3),
+    launch_adj_static<T, double>(dyn[cur], pr, ores, n, (double *)(B + o_dp), (double *)(B + o_k3),
                                  (int32_t *)(B + o_ore), (int32_t *)(B + o_kind), (double *)a.state, st);
   HIPCHK(hipGetLastError());
 
@@ -126,11 +127,11 @@ int Ctx<T>::grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, 
   int r = DEMRX_OK;
   for (int k = 0; k < n_int && r == DEMRX_OK; k++) {
     r = gas_table(g);
-    if (r == DEMRX_OK) r = step_one();
+    if (r == DEMRX_OK) r = step_checked();
     if (r == DEMRX_OK) r = couple(g, nullptr);
     if (r != DEMRX_OK) break;
     const size_t slot = want ? (size_t)k : 0;
-    launch_adj_record<T>(dyn[cur], pr[pc], ga, eps, beds, n, (int32_t *)(B + o_cell) + slot * N,
+    launch_adj_record<T>(dyn[cur], pr, ga, eps, beds, n, (int32_t *)(B + o_cell) + slot * N,
                          (double *)(B + o_F) + slot * N, st);
     if (!want) {  // plain forward: this interval's substeps now
       AdjArgs f = a;
@@ -181,15 +182,12 @@ int Ctx<T>::grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, 
 
   // ---- restore the DEM state
   cur = cur0;
-  pc = pc0;
-  nbc = nbc0;
   step_count = sc0;
-  steps_since = 0;
   built = true;
   dep_fresh = false;
   const Dyn<T> &d1 = dyn[cur];
-  const Props<T> &p1 = pr[pc];
-  const Nbr<T> &b1 = nb[nbc];
+  const Props<T> &p1 = pr;
+  const Nbr<T> &b1 = nb;
   void *lives[] = {d1.pos, d1.vel, p1.kcg, p1.tag, p1.nh, p1.nm, p1.nw, p1.nfe, p1.wh,
                    b1.cnt, b1.idx, b1.hist, b1.mask, eps, start, xref};
   for (size_t q = 0; q < sizeof(cps) / sizeof(cps[0]); q++)

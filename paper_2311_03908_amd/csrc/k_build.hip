@@ -2,12 +2,20 @@
 // inside gas cells, bed-major keys), deterministic in-cell order by original
 // id, permutation of the parcel state, and the LDS-staged 27-cell candidate
 // scan with wave64 ballot compaction and tangential-spring carry-over.
+#include <algorithm>
+
 #include "launch.h"
 
 namespace demrx {
 
 // ------------------------------------------------------------------ fills
-__global__ void k_fill_i32(int32_t *p, int32_t v, long n) {
+// Kernels of the neighbour rebuild take a gate: a device word that the
+// rebuild check sets; with a non-null gate holding 0 they return at once, so
+// a captured graph holds the rebuild chain and runs it only when needed.
+__device__ __forceinline__ bool gated_off(const uint32_t *gate) { return gate && *gate == 0u; }
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, long n, const uint32_t *gate) {
+  if (gated_off(gate)) return;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
 }
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, long n) {
@@ -17,8 +25,8 @@ static int grid_for(long n, int block, int cap = 65536) {
   long g = (n + block - 1) / block;
   return (int)(g < 1 ? 1 : (g > cap ? cap : g));
 }
-void launch_fill_i32(int32_t *p, int32_t v, long n, hipStream_t s) {
-  if (n > 0) k_fill_i32<<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
+void launch_fill_i32(int32_t *p, int32_t v, long n, hipStream_t s, const uint32_t *gate) {
+  if (n > 0) k_fill_i32<<<grid_for(n, 256), 256, 0, s>>>(p, v, n, gate);
 }
 void launch_fill_u32(uint32_t *p, uint32_t v, long n, hipStream_t s) {
   if (n > 0) k_fill_u32<<<grid_for(n, 256), 256, 0, s>>>(p, v, n);
@@ -55,7 +63,9 @@ __device__ int block_exclusive_scan(int v, int *lds, int &total) {
   return r;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const int32_t *in, int32_t *out, int32_t *bsum, long m) {
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const int32_t *in, int32_t *out, int32_t *bsum, long m,
+                                                              const uint32_t *gate) {
+  if (gated_off(gate)) return;
   __shared__ int lds[16];
   const long base = (long)blockIdx.x * kScanTile + (long)threadIdx.x * kScanItems;
   int v[kScanItems];
@@ -75,7 +85,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const int32_t *in, 
   if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_sums(int32_t *bsum, int nb) {
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(int32_t *bsum, int nb, const uint32_t *gate) {
+  if (gated_off(gate)) return;
   __shared__ int lds[16];
   int carry = 0;
   for (int base = 0; base < nb; base += kScanTile) {
@@ -98,7 +109,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_sums(int32_t *bsum, int n
   }
 }
 
-__global__ void k_scan_add(int32_t *out, const int32_t *bsum, long m) {
+__global__ void k_scan_add(int32_t *out, const int32_t *bsum, long m, const uint32_t *gate) {
+  if (gated_off(gate)) return;
   const long i = (long)blockIdx.x * kScanTile + threadIdx.x;
   const int add = bsum[blockIdx.x];
   for (int k = 0; k < kScanItems; k++) {
@@ -109,11 +121,11 @@ __global__ void k_scan_add(int32_t *out, const int32_t *bsum, long m) {
 
 long scan_scratch_ints(long m) { return (m + kScanTile - 1) / kScanTile + 1; }
 
-void launch_scan(const int32_t *in, int32_t *out, long m, int32_t *scratch, hipStream_t s) {
+void launch_scan(const int32_t *in, int32_t *out, long m, int32_t *scratch, hipStream_t s, const uint32_t *gate) {
   const int nb = (int)((m + kScanTile - 1) / kScanTile);
-  k_scan_tiles<<<nb, kScanThreads, 0, s>>>(in, out, scratch, m);
-  k_scan_sums<<<1, kScanThreads, 0, s>>>(scratch, nb);
-  k_scan_add<<<nb, kScanThreads, 0, s>>>(out, scratch, m);
+  k_scan_tiles<<<nb, kScanThreads, 0, s>>>(in, out, scratch, m, gate);
+  k_scan_sums<<<1, kScanThreads, 0, s>>>(scratch, nb, gate);
+  k_scan_add<<<nb, kScanThreads, 0, s>>>(out, scratch, m, gate);
 }
 
 // ------------------------------------------------------------------ binning
@@ -122,7 +134,8 @@ void launch_scan(const int32_t *in, int32_t *out, long m, int32_t *scratch, hipS
 // the run's slots.
 template <typename T>
 __global__ void k_bin(Dyn<T> d, Props<T> p, const BedDev *beds, int n, int32_t *key, int32_t *slot,
-                      int32_t *count, uint32_t *status) {
+                      int32_t *count, uint32_t *status, const uint32_t *gate) {
+  if (gated_off(gate)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   int k = -1;
@@ -155,58 +168,70 @@ __global__ void k_bin(Dyn<T> d, Props<T> p, const BedDev *beds, int n, int32_t *
 
 template <typename T>
 void launch_bin(const Dyn<T> &d, const Props<T> &p, const BedDev *beds, int n, int32_t *key, int32_t *slot,
-                int32_t *count, uint32_t *status, hipStream_t s) {
-  k_bin<T><<<(n + 255) / 256, 256, 0, s>>>(d, p, beds, n, key, slot, count, status);
+                int32_t *count, uint32_t *status, hipStream_t s, const uint32_t *gate) {
+  k_bin<T><<<(n + 255) / 256, 256, 0, s>>>(d, p, beds, n, key, slot, count, status, gate);
 }
 
-__global__ void k_scatter(const int32_t *key, const int32_t *slot, const int32_t *start, int n, int32_t *perm) {
+// Counting-sort scatter: parcel i goes to its slot of its cell's range; its x
+// and original id are copied along (cell order), for the in-cell rank.
+__global__ void k_scatter(const int32_t *key, const int32_t *slot, const int32_t *start, const PosRec *pos, int n,
+                          int32_t *perm, CellOrd co, const uint32_t *gate) {
+  if (gated_off(gate)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) perm[start[key[i]] + slot[i]] = i;
+  if (i >= n) return;
+  const int k = key[i];
+  const int j = start[k] + slot[i];
+  const PosRec P = load_pos(pos, i);
+  perm[j] = i;
+  co.x[j] = P.x;
+  co.id[j] = P.id;
+  co.key[j] = k;
 }
-void launch_scatter(const int32_t *key, const int32_t *slot, const int32_t *start, int n, int32_t *perm,
-                    hipStream_t s) {
-  k_scatter<<<(n + 255) / 256, 256, 0, s>>>(key, slot, start, n, perm);
+void launch_scatter(const int32_t *key, const int32_t *slot, const int32_t *start, const PosRec *pos, int n,
+                    int32_t *perm, const CellOrd &co, hipStream_t s, const uint32_t *gate) {
+  k_scatter<<<(n + 255) / 256, 256, 0, s>>>(key, slot, start, pos, n, perm, co, gate);
 }
 
 // Order the parcels of each cell by x, ties by original id (the atomic slot
 // order is not reproducible; x order makes every row of cells x-sorted for the
 // candidate search): every parcel counts the members of its cell that precede
-// it and moves to that rank.
-__global__ void k_cellrank(const int32_t *start, const int32_t *key, const PosRec *pos_old, const int32_t *perm,
-                           int n, int32_t *perm_out) {
+// it and moves to that rank.  The members' x and id are read from the
+// cell-ordered copies of the scatter: one contiguous run per cell, shared by
+// the neighbouring threads of the same cell.
+__global__ void k_cellrank(const int32_t *start, const int32_t *perm, CellOrd co, int n, int32_t *perm_out,
+                           const uint32_t *gate) {
+  if (gated_off(gate)) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  const int v = perm[p];
-  const int c = key[v];
+  const int c = co.key[p];
   const int s = start[c], e = start[c + 1];
-  const PosRec me = load_pos(pos_old, v);
+  const double x = co.x[p];
+  const uint32_t id = co.id[p];
   int rank = 0;
-  // members requested eight at a time, so that their loads overlap
-  constexpr int kB = 8;
-  for (int q0 = s; q0 < e; q0 += kB) {
-    int u[kB];
-#pragma unroll
-    for (int k = 0; k < kB; k++) u[k] = q0 + k < e ? perm[q0 + k] : -1;
-    PosRec o[kB];
-#pragma unroll
-    for (int k = 0; k < kB; k++)
-      if (u[k] >= 0) o[k] = load_pos(pos_old, u[k]);
-#pragma unroll
-    for (int k = 0; k < kB; k++)
-      if (u[k] >= 0) rank += (o[k].x < me.x || (o[k].x == me.x && o[k].id < me.id)) ? 1 : 0;
+#pragma unroll 4
+  for (int q = s; q < e; q++) {
+    const double xq = co.x[q];
+    rank += (xq < x || (xq == x && co.id[q] < id)) ? 1 : 0;
   }
-  perm_out[s + rank] = v;
+  perm_out[s + rank] = perm[p];
 }
-void launch_cellrank(const int32_t *start, const int32_t *key, const PosRec *pos_old, const int32_t *perm, int n,
-                     int32_t *perm_out, hipStream_t s) {
-  k_cellrank<<<(n + 255) / 256, 256, 0, s>>>(start, key, pos_old, perm, n, perm_out);
+void launch_cellrank(const int32_t *start, const int32_t *perm, const CellOrd &co, int n, int32_t *perm_out,
+                     hipStream_t s, const uint32_t *gate) {
+  k_cellrank<<<(n + 255) / 256, 256, 0, s>>>(start, perm, co, n, perm_out, gate);
 }
 
+// Permutation into the spare buffers (the other step buffer and the spare
+// properties), then a copy back: the parcels keep the buffers they live in,
+// so no buffer parity depends on whether a rebuild ran.
 template <typename T>
 __global__ void k_permute(const int32_t *perm, int n, Dyn<T> din, Props<T> pin, Dyn<T> dout, Props<T> pout,
-                          float4 *xref, unsigned *dslot) {
+                          float4 *xref, unsigned *dslot, const uint32_t *gate) {
+  if (gated_off(gate)) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < 2 * kSlots) dslot[j * kSlotPad] = 0u;  // displacement maxima restart at the rebuild
+  if (j < 2 * kSlots) {  // displacement and speed maxima restart at the rebuild
+    dslot[j * kSlotPad] = 0u;
+    dslot[j * kSlotPad + 1] = 0u;
+  }
   if (j >= n) return;
   const int i = perm[j];
   const PosRec P = load_pos(din.pos, i);
@@ -227,14 +252,93 @@ __global__ void k_permute(const int32_t *perm, int n, Dyn<T> din, Props<T> pin, 
 }
 
 template <typename T>
-void launch_permute(const int32_t *perm, int n, const Dyn<T> &din, const Props<T> &pin, const Dyn<T> &dout,
-                    const Props<T> &pout, float4 *xref, unsigned *dslot, hipStream_t s) {
-  k_permute<T><<<(n + 255) / 256, 256, 0, s>>>(perm, n, din, pin, dout, pout, xref, dslot);
+__global__ void k_copy_back(int n, Dyn<T> src, Props<T> psrc, Dyn<T> dst, Props<T> pdst, const uint32_t *gate) {
+  if (gated_off(gate)) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  store_pos(dst.pos, j, load_pos(src.pos, j));
+  dst.vel[j] = src.vel[j];
+  pdst.kcg[j] = psrc.kcg[j];
+  pdst.tag[j] = psrc.tag[j];
+  pdst.nh[j] = psrc.nh[j];
+  pdst.nm[j] = psrc.nm[j];
+  pdst.nw[j] = psrc.nw[j];
+  pdst.nfe[j] = psrc.nfe[j];
+  if (psrc.Tp) {
+    pdst.Tp[j] = psrc.Tp[j];
+    pdst.qrx[j] = psrc.qrx[j];
+    pdst.mcp[j] = psrc.mcp[j];
+  }
+}
+
+template <typename T>
+void launch_permute(const int32_t *perm, int n, const Dyn<T> &d, const Props<T> &p, const Dyn<T> &spare,
+                    const Props<T> &pspare, float4 *xref, unsigned *dslot, hipStream_t s, const uint32_t *gate) {
+  const int g = (std::max(n, 2 * kSlots) + 255) / 256;
+  k_permute<T><<<g, 256, 0, s>>>(perm, n, d, p, spare, pspare, xref, dslot, gate);
+  k_copy_back<T><<<(n + 255) / 256, 256, 0, s>>>(n, spare, pspare, d, p, gate);
+}
+
+// Contact springs of every parcel (old sorted order) before a rebuild,
+// compacted: carry[k * N + p] for its k-th contact (bits 0..47 of the mask in
+// ascending slot), carry_meta[p] = (wall bits << 16) | count.  The build
+// carries them to the new lists by matching partner ids.
+template <typename T>
+__global__ void k_carry(Nbr<T> nb, int n, Spring<T> *carry, uint32_t *carry_meta, const uint32_t *gate) {
+  if (gated_off(gate)) return;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const long N = n;
+  const uint64_t m = nb.mask[p];
+  uint64_t b = m & ((1ull << kWallBit) - 1ull);
+  uint32_t k = 0;
+  for (; b; b &= b - 1, k++) {
+    const int q = __ffsll((unsigned long long)b) - 1;
+    carry[(long)k * N + p] = nb.hist[(long)q * N + p];
+  }
+  carry_meta[p] = ((uint32_t)(m >> kWallBit) << 16) | k;
+}
+
+template <typename T>
+void launch_carry(const Nbr<T> &nb, int n, Spring<T> *carry, uint32_t *carry_meta, hipStream_t s,
+                  const uint32_t *gate) {
+  k_carry<T><<<(n + 255) / 256, 256, 0, s>>>(nb, n, carry, carry_meta, gate);
+}
+
+// Decide whether the lists must be rebuilt before the next `horizon` steps:
+// D, the largest displacement of any parcel since the last rebuild (exact,
+// from the FP32 reference positions), and V, the largest speed, both of the
+// last step.  The lists hold every pair that can touch while D < skin/2, so
+// they are rebuilt when D + grow V, with grow = 2 x horizon x dt (speeds may
+// double within the horizon), could reach skin/2.  The step kernel's own
+// exact check stays as the safety net.  One block of 64 threads.
+__global__ void k_rebuild_check(const unsigned *dslot, int par_last, float lim, float grow, int force, uint32_t *flag,
+                                unsigned long long *count) {
+  const int t = threadIdx.x;
+  float d2 = __uint_as_float(dslot[(par_last * kSlots + t) * kSlotPad]);
+  float v2 = __uint_as_float(dslot[(par_last * kSlots + t) * kSlotPad + 1]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    d2 = fmaxf(d2, __shfl_xor(d2, o, 64));
+    v2 = fmaxf(v2, __shfl_xor(v2, o, 64));
+  }
+  if (t == 0) {
+    const bool rb = force || !(sqrtf(d2) + grow * sqrtf(v2) < lim);
+    *flag = rb ? 1u : 0u;
+    if (rb) *count += 1ull;
+  }
+}
+
+void launch_rebuild_check(const unsigned *dslot, int par_last, double skin, double dt, int horizon, int force,
+                          uint32_t *flag, unsigned long long *count, hipStream_t s) {
+  const float lim = 0.5f * (float)skin - 1e-7f;
+  k_rebuild_check<<<1, 64, 0, s>>>(dslot, par_last, lim, (float)(2.0 * horizon * dt), force, flag, count);
 }
 
 // ------------------------------------------------------------------ work items
 __global__ void k_item_flags(const Item *items, int n_items, const BedDev *beds, const int32_t *start,
-                             int32_t *flags) {
+                             int32_t *flags, const uint32_t *gate) {
+  if (gated_off(gate)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t > n_items) return;
   if (t == n_items) {
@@ -250,7 +354,8 @@ __global__ void k_item_flags(const Item *items, int n_items, const BedDev *beds,
 }
 
 __global__ void k_item_compact(const int32_t *flags, const int32_t *offs, int n_items, int32_t *list,
-                               int32_t *count) {
+                               int32_t *count, const uint32_t *gate) {
+  if (gated_off(gate)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t > n_items) return;
   if (t == n_items) {
@@ -261,10 +366,11 @@ __global__ void k_item_compact(const int32_t *flags, const int32_t *offs, int n_
 }
 
 void launch_items(const Item *items, int n_items, const BedDev *beds, const int32_t *start, int32_t *flags,
-                  int32_t *offs, int32_t *scratch, int32_t *list, int32_t *count, hipStream_t s) {
-  k_item_flags<<<(n_items + 256) / 256, 256, 0, s>>>(items, n_items, beds, start, flags);
-  launch_scan(flags, offs, n_items + 1, scratch, s);
-  k_item_compact<<<(n_items + 256) / 256, 256, 0, s>>>(flags, offs, n_items, list, count);
+                  int32_t *offs, int32_t *scratch, int32_t *list, int32_t *count, hipStream_t s,
+                  const uint32_t *gate) {
+  k_item_flags<<<(n_items + 256) / 256, 256, 0, s>>>(items, n_items, beds, start, flags, gate);
+  launch_scan(flags, offs, n_items + 1, scratch, s, gate);
+  k_item_compact<<<(n_items + 256) / 256, 256, 0, s>>>(flags, offs, n_items, list, count, gate);
 }
 
 // ------------------------------------------------------------------ neighbour build
@@ -280,10 +386,10 @@ void launch_items(const Item *items, int n_items, const BedDev *beds, const int3
 // candidates that touch now (FP32 test with a 1e-4 margin, a superset of the
 // exact contacts) fill slots cap-1, cap-2, ... downwards, the others fill
 // slots 0, 1, ... upwards; cnt packs (near << 16) | far.  The tangential
-// springs of partners in contact before the rebuild are carried over to the
-// near slots by matching original ids, which every spring record carries
-// (read into registers for up to kCarry old contacts; more fall back to a
-// gather loop).
+// springs of partners in contact before the rebuild, compacted by k_carry,
+// are carried over to the near slots by matching original ids, which every
+// spring record carries (read into registers for up to kCarry old contacts;
+// more fall back to a loop).
 constexpr int kCandMax = 2048;
 constexpr int kBuildThreads = 512;
 constexpr int kCarry = 8;  // 78 VGPRs: three 512-thread blocks per CU
@@ -291,6 +397,7 @@ constexpr float kNear = 1.0f + 1e-4f;
 
 template <typename T>
 __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
+  if (gated_off(a.gate)) return;
   __shared__ float4 cpos[kCandMax];
   __shared__ int cidx[kCandMax];
   __shared__ uint32_t cid[kCandMax];
@@ -338,16 +445,14 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
       int nn = 0, nf = 0;  // near / far candidates written
       bool over = false;
       float cut_hi = 0.f;
-      // partners in contact before the rebuild: original ids and old slots
+      // partners in contact before the rebuild: original ids of the first
+      // kCarry carried springs (the rest are matched by a loop)
       uint32_t oid[kCarry];
-      int oslot[kCarry];
-      int po = 0;
-      uint64_t mo = 0, orest = 0, newbits = 0;
+      int po = 0, n_old = 0;
+      uint32_t wallbits = 0;
+      uint64_t newbits = 0;
 #pragma unroll
-      for (int k = 0; k < kCarry; k++) {
-        oid[k] = 0xffffffffu;
-        oslot[k] = 0;
-      }
+      for (int k = 0; k < kCarry; k++) oid[k] = 0xffffffffu;
       if (mine) {
         const PosRec pi = load_pos(a.d.pos, i);
         xi = (float)(pi.x - xr);
@@ -358,18 +463,12 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
         // widest candidate distance along x for this centre
         cut_hi = (rs + (float)B.rmax) * cut_scale + 1e-9f;
         po = a.perm[i];
-        mo = a.nb_old.mask[po];
-        uint64_t b = mo & ((1ull << kWallBit) - 1ull);
+        const uint32_t meta = a.carry_meta[po];
+        n_old = (int)(meta & 0xffffu);
+        wallbits = meta >> 16;
 #pragma unroll
-        for (int k = 0; k < kCarry; k++) {
-          if (b) {
-            const int q = __ffsll((unsigned long long)b) - 1;
-            b &= b - 1;
-            oslot[k] = q;
-            oid[k] = spring_partner(a.nb_old.hist[(long)q * N + po].w);
-          }
-        }
-        orest = b;
+        for (int k = 0; k < kCarry; k++)
+          if (k < n_old) oid[k] = spring_partner(a.carry[(long)k * N + po].w);
       }
       int row = 0;
       while (row < 9) {
@@ -442,24 +541,22 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
               } else if (d2 < sn * sn) {
                 {
                   const int sl = a.cap - 1 - nn;
-                  a.nb_new.idx[(long)sl * N + i] = j;
+                  a.nb.idx[(long)sl * N + i] = j;
                   const uint32_t idn = cid[q];
                   int qo = -1;
 #pragma unroll
                   for (int k = 0; k < kCarry; k++)
-                    if (oid[k] == idn) qo = oslot[k];
-                  for (uint64_t b = orest; b && qo < 0; b &= b - 1) {
-                    const int q2 = __ffsll((unsigned long long)b) - 1;
-                    if (spring_partner(a.nb_old.hist[(long)q2 * N + po].w) == idn) qo = q2;
-                  }
+                    if (oid[k] == idn) qo = k;
+                  for (int k = kCarry; k < n_old && qo < 0; k++)
+                    if (spring_partner(a.carry[(long)k * N + po].w) == idn) qo = k;
                   if (qo >= 0) {
-                    a.nb_new.hist[(long)sl * N + i] = a.nb_old.hist[(long)qo * N + po];
+                    a.nb.hist[(long)sl * N + i] = a.carry[(long)qo * N + po];
                     newbits |= 1ull << sl;
                   }
                 }
                 nn++;
               } else {
-                a.nb_new.idx[(long)nf * N + i] = j;
+                a.nb.idx[(long)nf * N + i] = j;
                 nf++;
               }
             }
@@ -469,8 +566,8 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
       }
       if (mine) {
         if (over) atomicOr(a.status, ST_OVERFLOW);
-        a.nb_new.cnt[i] = (nn << 16) | nf;
-        a.nb_new.mask[i] = newbits | (mo & ~((1ull << kWallBit) - 1ull));
+        a.nb.cnt[i] = (nn << 16) | nf;
+        a.nb.mask[i] = newbits | ((uint64_t)wallbits << kWallBit);
       }
     }
   }
@@ -513,9 +610,10 @@ void launch_pairs(const Dyn<T> &d, const Props<T> &p, const Nbr<T> &nb, int n, i
 
 #define INST(T)                                                                                                   \
   template void launch_bin<T>(const Dyn<T> &, const Props<T> &, const BedDev *, int, int32_t *, int32_t *,       \
-                              int32_t *, uint32_t *, hipStream_t);                                                \
+                              int32_t *, uint32_t *, hipStream_t, const uint32_t *);                              \
   template void launch_permute<T>(const int32_t *, int, const Dyn<T> &, const Props<T> &, const Dyn<T> &,        \
-                                  const Props<T> &, float4 *, unsigned *, hipStream_t);                          \
+                                  const Props<T> &, float4 *, unsigned *, hipStream_t, const uint32_t *);        \
+  template void launch_carry<T>(const Nbr<T> &, int, Spring<T> *, uint32_t *, hipStream_t, const uint32_t *);    \
   template void launch_build_nbr<T>(const NbrBuild<T> &, int, hipStream_t);                                      \
   template void launch_pairs<T>(const Dyn<T> &, const Props<T> &, const Nbr<T> &, int, int, uint32_t *, long,         \
                                 unsigned long long *, hipStream_t);

@@ -56,7 +56,7 @@ __global__ void k_occ_flags(const int32_t *start, const int32_t *cell_bed, const
   }
   flags[c] = any ? 1 : 0;
   if (any) return;
-  o.eps_ctx[c] = 1.0;
+  if (o.eps_ctx) o.eps_ctx[c] = 1.0;
   if (o.eps) o.eps[c] = 1.0;
   if (o.np) o.np[c] = 0.0;
   if (!sums) return;
@@ -271,39 +271,55 @@ void launch_react(const ReactArgs<T> &a, hipStream_t s) {
   k_react<T><<<(a.n + 255) / 256, 256, 0, s>>>(a);
 }
 
+// Cell sums of the per-parcel sources: one 16-lane group per occupied gas
+// cell of the compacted list (as the deposit), and zeros written to the
+// empty cells by one thread each.
 __global__ void __launch_bounds__(256) k_cellsum(const double *pm, int n, const int32_t *start, const int32_t *order,
-                                                 const int32_t *cell_bed, const BedDev *beds, int n_gas,
-                                                 CellSumOut o) {
-  const int gc = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
+                                                 const int32_t *cell_bed, const BedDev *beds, const int32_t *list,
+                                                 const int32_t *list_count, CellSumOut o) {
   const int sl = threadIdx.x % kGroup;
-  const bool valid = gc < n_gas;
-  const int c = valid ? gc : n_gas - 1;
-  const GasCellRanges R(beds[cell_bed[c]], c);
-  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int r = 0; r < R.f * R.f; r++) {
-    const int k0 = R.row_key(r);
-    const int e = start[k0 + R.f];
-    for (int t = start[k0] + sl; t < e; t += kGroup) {
-      const int j = order[t];
+  const int n_list = *list_count;
+  const int groups = gridDim.x * (blockDim.x / kGroup);
+  for (int gi = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup; gi < n_list; gi += groups) {
+    const int c = list[gi];
+    const GasCellRanges R(beds[cell_bed[c]], c);
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int r = 0; r < R.f * R.f; r++) {
+      const int k0 = R.row_key(r);
+      const int e = start[k0 + R.f];
+      for (int t = start[k0] + sl; t < e; t += kGroup) {
+        const int j = order[t];
 #pragma unroll
-      for (int q = 0; q < 8; q++)
-        if (q < o.rows) s[q] += pm[(long)q * n + j];
+        for (int q = 0; q < 8; q++)
+          if (q < o.rows) s[q] += pm[(long)q * n + j];
+      }
     }
-  }
-#pragma unroll
-  for (int q = 0; q < 8; q++)
-    if (q < o.rows) s[q] = group_sum(s[q]);
-  if (valid && sl == 0) {
 #pragma unroll
     for (int q = 0; q < 8; q++)
-      if (q < o.rows && o.o[q]) o.o[q][c] = s[q];
+      if (q < o.rows) s[q] = group_sum(s[q]);
+    if (sl == 0) {
+#pragma unroll
+      for (int q = 0; q < 8; q++)
+        if (q < o.rows && o.o[q]) o.o[q][c] = s[q];
+    }
   }
 }
 
+__global__ void k_cellsum_empty(const int32_t *flags, int n_gas, CellSumOut o) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_gas || flags[c]) return;
+#pragma unroll
+  for (int q = 0; q < 8; q++)
+    if (q < o.rows && o.o[q]) o.o[q][c] = 0.0;
+}
+
 void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t *order, const int32_t *cell_bed,
-                    const BedDev *beds, int n_gas, const CellSumOut &o, hipStream_t s) {
-  const long threads = (long)n_gas * kGroup;
-  k_cellsum<<<(int)((threads + 255) / 256), 256, 0, s>>>(pm, n, start, order, cell_bed, beds, n_gas, o);
+                    const BedDev *beds, int n_gas, const int32_t *flags, const int32_t *list,
+                    const int32_t *list_count, int max_list, const CellSumOut &o, hipStream_t s) {
+  k_cellsum_empty<<<(n_gas + 255) / 256, 256, 0, s>>>(flags, n_gas, o);
+  const int groups_per_block = 256 / kGroup;
+  const int blocks = std::max(1, std::min((max_list + groups_per_block - 1) / groups_per_block, 8192));
+  k_cellsum<<<blocks, 256, 0, s>>>(pm, n, start, order, cell_bed, beds, list, list_count, o);
 }
 
 // Bed-mean f_ov weighted by k^3 N_Fe: every bed's parcel range (contiguous,
@@ -607,6 +623,46 @@ void launch_gas_species(const GasArgs &g, const double *eps, const int32_t *cell
                         double *o2, double *o3, uint32_t *status, hipStream_t s) {
   k_gas_species<<<(n_gas + 255) / 256, 256, 0, s>>>(g, eps, cell_bed, beds, n_gas, dt, sumEQ, sumES, xin1, xin2, o1,
                                                     o2, o3, status);
+}
+
+// Gas-side momentum step of the two-way coupling (eqs. e4-1, e4-2 with the
+// interphase source of eqs. e3-27, e3-27a) on the frozen pressure field, one
+// thread per cell:
+//   eps rho (u' - u) / dt = -eps grad p + eps rho g + K_gp u' - K_gp u_p,
+// K_gp u_g implicit, K_gp u_p explicit, with K_gp = -sum K / V_cell and
+// K_gp u_p = -sum K v / V_cell from the drag sums of the last deposit, so the
+// gas takes exactly the drag the parcels feel.  Convection and the viscous
+// and pseudo-turbulent stresses belong to the gas solver.
+__global__ void k_gas_momentum(GasArgs g, const double *eps, const int32_t *cell_bed, const BedDev *beds, int n_gas,
+                               double dt, double gx, double gy, double gz, const double *sK, const double *sKu,
+                               const double *sKv, const double *sKw, double *uo, double *vo, double *wo,
+                               uint32_t *status) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_gas) return;
+  const BedDev &B = beds[cell_bed[c]];
+  const double V = B.h * B.h * B.h;
+  double rho, mu;
+  gas_props_h2(g.T[c], g.p[c], g.xH2[c], g.xH2O[c], g.xN2[c], 1.0, rho, mu);
+  const double e = eps[c];
+  const double den = e * rho / dt + sK[c] / V;
+  const double u[3] = {g.ug[c], g.vg[c], g.wg[c]};
+  const double gp[3] = {g.dpdx[c], g.dpdy[c], g.dpdz[c]};
+  const double gv[3] = {gx, gy, gz};
+  const double Kv[3] = {sKu[c], sKv[c], sKw[c]};
+  double r[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) r[a] = (e * rho * u[a] / dt - e * gp[a] + e * rho * gv[a] + Kv[a] / V) / den;
+  uo[c] = r[0];
+  vo[c] = r[1];
+  wo[c] = r[2];
+  if (!(isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]))) atomicOr(status, ST_NONFINITE);
+}
+
+void launch_gas_momentum(const GasArgs &g, const double *eps, const int32_t *cell_bed, const BedDev *beds, int n_gas,
+                         double dt, const double grav[3], const double *sK, const double *sKu, const double *sKv,
+                         const double *sKw, double *uo, double *vo, double *wo, uint32_t *status, hipStream_t s) {
+  k_gas_momentum<<<(n_gas + 255) / 256, 256, 0, s>>>(g, eps, cell_bed, beds, n_gas, dt, grav[0], grav[1], grav[2], sK,
+                                                     sKu, sKv, sKw, uo, vo, wo, status);
 }
 
 #define INST(T)                                                                                                    \

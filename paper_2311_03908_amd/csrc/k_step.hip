@@ -88,8 +88,8 @@ __device__ __forceinline__ void land_wait() { __builtin_amdgcn_s_waitcnt(0x0F70)
 // walls, body and gas forces, integration.  Accumulates the displacement
 // maximum and the contact counts of the calling thread.
 template <typename T>
-__device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, float &dmax2, int &n_pp, int &n_w,
-                                            unsigned char *wl) {
+__device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, float &dmax2, float &vmax2, int &n_pp,
+                                            int &n_w, unsigned char *wl) {
   const long N = a.n;
   {
     const PosRec P = load_pos(a.in.pos, i);
@@ -309,6 +309,7 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
       const float4 xr = a.xref[i];
       const float ex = (float)Po.x - xr.x, ey = (float)Po.y - xr.y, ez = (float)Po.z - xr.z;
       dmax2 = fmaxf(dmax2, ex * ex + ey * ey + ez * ez);
+      vmax2 = fmaxf(vmax2, v2);
       if (!(isfinite(Po.x) && isfinite(Po.y) && isfinite(Po.z) && isfinite(v2) &&
             isfinite((float)(Vo.w[0] + Vo.w[1] + Vo.w[2]))))
         atomicOr(a.status, ST_NONFINITE);
@@ -320,19 +321,21 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
 // atomic per wave into one of kSlots padded slots (so waves rarely contend
 // and retire independently, with no block barrier)
 template <typename T>
-__device__ __forceinline__ void step_flush(const StepArgs<T> &a, float dmax2, int n_pp, int n_w) {
+__device__ __forceinline__ void step_flush(const StepArgs<T> &a, float dmax2, float vmax2, int n_pp, int n_w) {
   if (a.mode != 0) return;
-  float m = dmax2;
+  float m = dmax2, v = vmax2;
   int c0 = n_pp, c1 = n_w;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     m = fmaxf(m, __shfl_xor(m, o, 64));
+    v = fmaxf(v, __shfl_xor(v, o, 64));
     c0 += __shfl_xor(c0, o, 64);
     c1 += __shfl_xor(c1, o, 64);
   }
   if ((threadIdx.x & 63) == 0) {
     const int sl = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kSlots - 1));
     atomicMax(a.dslot + (a.par * kSlots + sl) * kSlotPad, __float_as_uint(m));
+    atomicMax(a.dslot + (a.par * kSlots + sl) * kSlotPad + 1, __float_as_uint(v));
     if (a.count) {
       if (c0) atomicAdd(a.cslot + sl * kSlotPad64, (unsigned long long)c0);
       if (c1) atomicAdd(a.cslot + sl * kSlotPad64 + 1, (unsigned long long)c1);
@@ -348,7 +351,8 @@ __device__ __forceinline__ void step_skin_check(const StepArgs<T> &a) {
   if (a.mode == 0 && blockIdx.x == 0 && threadIdx.x < 64) {
     unsigned *src = a.dslot + ((a.par ^ 1) * kSlots + threadIdx.x) * kSlotPad;
     float d2 = __uint_as_float(*src);
-    *src = 0u;
+    src[0] = 0u;
+    src[1] = 0u;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) d2 = fmaxf(d2, __shfl_xor(d2, o, 64));
     const float lim = 0.5f * (float)a.ph.skin - 1e-7f;  // FP32 reference positions
@@ -363,11 +367,11 @@ __global__ void __launch_bounds__(512, sizeof(T) == 4 ? 5 : 1) k_step(StepArgs<T
   extern __shared__ __align__(16) unsigned char lds[];
   const int i = (a.xcd > 1 ? xcd_block(a.xcd) : (int)blockIdx.x) * blockDim.x + threadIdx.x;
   step_skin_check(a);
-  float dmax2 = 0.0f;
+  float dmax2 = 0.0f, vmax2 = 0.0f;
   int n_pp = 0, n_w = 0;
   unsigned char *wl = lds + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * kLandWaveBytes;
-  if (i < a.n) step_parcel(a, i, dmax2, n_pp, n_w, wl);
-  step_flush(a, dmax2, n_pp, n_w);
+  if (i < a.n) step_parcel(a, i, dmax2, vmax2, n_pp, n_w, wl);
+  step_flush(a, dmax2, vmax2, n_pp, n_w);
 }
 
 template <typename T>

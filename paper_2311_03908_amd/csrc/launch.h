@@ -16,31 +16,54 @@ constexpr int kItemX = 16;
 // apart) by per-wave atomics, and summed by their readers
 constexpr int kSlots = 64, kSlotPad = 32, kSlotPad64 = 16;
 
-void launch_fill_i32(int32_t *p, int32_t v, long n, hipStream_t s);
+// Launchers of the rebuild chain take `gate` (a device word; null: always
+// run): with *gate == 0 their kernels return at once.
+void launch_fill_i32(int32_t *p, int32_t v, long n, hipStream_t s, const uint32_t *gate = nullptr);
 void launch_fill_u32(uint32_t *p, uint32_t v, long n, hipStream_t s);
 // exclusive prefix sum of m ints; scratch needs scan_scratch_ints(m) ints
 long scan_scratch_ints(long m);
-void launch_scan(const int32_t *in, int32_t *out, long m, int32_t *scratch, hipStream_t s);
+void launch_scan(const int32_t *in, int32_t *out, long m, int32_t *scratch, hipStream_t s,
+                 const uint32_t *gate = nullptr);
 
 template <typename T>
-void launch_bin(const Dyn<T> &d, const Props<T> &p, const BedDev *beds, int n, int32_t *key,
-                int32_t *slot, int32_t *count, uint32_t *status, hipStream_t s);
-void launch_scatter(const int32_t *key, const int32_t *slot, const int32_t *start, int n, int32_t *perm,
-                    hipStream_t s);
-void launch_cellrank(const int32_t *start, const int32_t *key, const PosRec *pos_old, const int32_t *perm, int n,
-                     int32_t *perm_out, hipStream_t s);
+void launch_bin(const Dyn<T> &d, const Props<T> &p, const BedDev *beds, int n, int32_t *key, int32_t *slot,
+                int32_t *count, uint32_t *status, hipStream_t s, const uint32_t *gate = nullptr);
+// x, original id and DEM cell of the parcels in the scatter's cell order
+struct CellOrd {
+  double *x;
+  uint32_t *id;
+  int32_t *key;
+};
+void launch_scatter(const int32_t *key, const int32_t *slot, const int32_t *start, const PosRec *pos, int n,
+                    int32_t *perm, const CellOrd &co, hipStream_t s, const uint32_t *gate = nullptr);
+void launch_cellrank(const int32_t *start, const int32_t *perm, const CellOrd &co, int n, int32_t *perm_out,
+                     hipStream_t s, const uint32_t *gate = nullptr);
+// permute (d, p) by perm through the spare buffers and copy back, so the
+// parcels stay in d and p; resets the displacement maxima and xref
 template <typename T>
-void launch_permute(const int32_t *perm, int n, const Dyn<T> &din, const Props<T> &pin, const Dyn<T> &dout,
-                    const Props<T> &pout, float4 *xref, unsigned *dslot, hipStream_t s);
+void launch_permute(const int32_t *perm, int n, const Dyn<T> &d, const Props<T> &p, const Dyn<T> &spare,
+                    const Props<T> &pspare, float4 *xref, unsigned *dslot, hipStream_t s, const uint32_t *gate);
+// compact the contact springs of the current lists (carry[k * N + p],
+// carry_meta[p] = (wall bits << 16) | count) before a rebuild
+template <typename T>
+void launch_carry(const Nbr<T> &nb, int n, Spring<T> *carry, uint32_t *carry_meta, hipStream_t s,
+                  const uint32_t *gate);
+// set *flag when the lists could go stale within `horizon` steps (or force)
+void launch_rebuild_check(const unsigned *dslot, int par_last, double skin, double dt, int horizon, int force,
+                          uint32_t *flag, unsigned long long *count, hipStream_t s);
 void launch_items(const Item *items, int n_items, const BedDev *beds, const int32_t *start, int32_t *flags,
-                  int32_t *offs, int32_t *scratch, int32_t *list, int32_t *count, hipStream_t s);
+                  int32_t *offs, int32_t *scratch, int32_t *list, int32_t *count, hipStream_t s,
+                  const uint32_t *gate);
 
 template <typename T>
 struct NbrBuild {
-  Dyn<T> d;             // new sorted state
-  Props<T> p;           // new sorted properties
+  Dyn<T> d;             // sorted state (after the permutation)
+  Props<T> p;           // sorted properties
   const int32_t *perm;  // new position -> old position
-  Nbr<T> nb_new, nb_old;
+  Nbr<T> nb;            // the lists written
+  const Spring<T> *carry;       // springs of the old lists (launch_carry), by old position
+  const uint32_t *carry_meta;
+  const uint32_t *gate;
   const BedDev *beds;
   const int32_t *start;
   const Item *items;
@@ -70,7 +93,7 @@ struct StepArgs {
   uint32_t *status;
   const double *Tg;              // gas temperature per cell (energy equation)
   const float4 *xref;            // positions at the last rebuild (FP32)
-  unsigned *dslot;               // [2][kSlots] padded: max squared displacement (this step: par)
+  unsigned *dslot;               // [2][kSlots] padded: max squared displacement (+0), speed (+1); this step: par
   unsigned long long *cslot;     // [kSlots] padded: pp and wall contacts (mode 0 with count)
   int n, par, mode;              // mode 0: integrate; 1: write forces; 2: timing dry run
   int count;                     // 1: add this step's contacts to counters
@@ -90,7 +113,7 @@ void launch_gas_table(const GasArgs &g, const double *eps, const int32_t *cell_b
 
 // ---------------------------------------------------------------- k_couple.hip
 struct DepositOut {
-  double *eps_ctx;  // context voidage (always written)
+  double *eps_ctx;  // context voidage (null: not written; the occupied list only)
   double *eps, *np, *sumK, *sumKu, *sumKv, *sumKw, *sumKs;
 };
 void launch_occupied(const int32_t *start, const int32_t *cell_bed, const BedDev *beds, int n_gas, bool sums,
@@ -126,12 +149,17 @@ void launch_react(const ReactArgs<T> &a, hipStream_t s);
 void launch_gas_species(const GasArgs &g, const double *eps, const int32_t *cell_bed, const BedDev *beds, int n_gas,
                         double dt, const double *sumEQ, const double *sumES, double xin1, double xin2, double *o1,
                         double *o2, double *o3, uint32_t *status, hipStream_t s);
+void launch_gas_momentum(const GasArgs &g, const double *eps, const int32_t *cell_bed, const BedDev *beds, int n_gas,
+                         double dt, const double grav[3], const double *sK, const double *sKu, const double *sKv,
+                         const double *sKw, double *uo, double *vo, double *wo, uint32_t *status, hipStream_t s);
 struct CellSumOut {
   double *o[8];  // per-cell sums of the pm rows (null: not written)
   int rows;      // 4, or 8 with the energy equation
 };
+// cell sums over the occupied cells of launch_occupied (flags, list, count)
 void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t *order, const int32_t *cell_bed,
-                    const BedDev *beds, int n_gas, const CellSumOut &o, hipStream_t s);
+                    const BedDev *beds, int n_gas, const int32_t *flags, const int32_t *list,
+                    const int32_t *list_count, int max_list, const CellSumOut &o, hipStream_t s);
 constexpr int kBedChunk = 4096;  // parcels per partial sum of the bed means
 void launch_bedsum(const double *pw, int n, const int32_t *start, const BedDev *beds, int n_beds, int4 *chunks,
                    int max_chunks, double *partial, double *bed_fov, hipStream_t s);

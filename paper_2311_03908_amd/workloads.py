@@ -117,12 +117,12 @@ class Workload:
         return int(self.gas["T"].shape[0])
 
 
-# Neighbour-list skins: a parcel may move skin/2 between builds; the fine
-# parcels are carried at up to the gas speed (0.3-0.5 m/s), so skin/2 must
-# exceed rebuild_every * dt * 0.4 m/s.
+# Neighbour lists: checked every check_every steps (and at every coupling)
+# and rebuilt on the device when the largest displacement since the last
+# build plus 2 check_every dt times the largest speed could reach skin/2.
 def base_params(**kw) -> dict:
     p = dict(kn=1000.0, e_p=0.9, mu_s=0.3, mu_r=0.0, kt_over_kn=2.0 / 7.0, gt_over_gn=0.0,
-             eps_min=0.35, skin=5e-5, g=(0.0, 0.0, -9.81), dt=1e-5, rebuild_every=10,
+             eps_min=0.35, skin=5e-5, g=(0.0, 0.0, -9.81), dt=1e-5, check_every=10,
              max_nbr=48, ergun_printed=0, energy_on=0)
     p.update(kw)
     return p
@@ -362,12 +362,12 @@ def cfg1(n=2048, seed=1, steps=1000):
     ore = Ore(xi0=1.0 - rho / RHO_TRUE[0], d_pore_cm=3.3e-6)
     parcels = _parcels(pos, d_p, 1.0, np.zeros(n), np.zeros(n), {0: rho}, {0: HEMATITE_WT})
     gas = _gas(rng, [bed], 1073.0, 1.0, 0.0, (0.0, 0.0, 0.5), 0.0, False)
-    params = base_params(dt=1e-5, skin=1e-4, rebuild_every=10)
+    params = base_params(dt=1e-5, skin=1e-4, check_every=10)
     return Workload("cfg1", "fp64", params, [bed], [ore], parcels, gas, np.array([0]), steps, 10)
 
 
 def _cfg_cyl(name, n, N0, R0, H0, h, refine, d_sampler, k, ores, ore_split, T, xh2, seed, steps,
-             dt=5e-6, couple=20, precision="mixed", skin=6e-5, u=0.3, classes=8, rebuild=10, kn=1000.0):
+             dt=5e-6, couple=20, precision="mixed", skin=6e-5, u=0.3, classes=8, check=10, kn=1000.0):
     rng = np.random.Generator(np.random.PCG64(seed))
     s = (n / float(N0)) ** (1.0 / 3.0)
     R = R0 * s
@@ -387,7 +387,7 @@ def _cfg_cyl(name, n, N0, R0, H0, h, refine, d_sampler, k, ores, ore_split, T, x
     parcels = _parcels(pos, d_p, k, ore_idx, np.zeros(n), rho_of, wt_of)
     parcels = _shuffle_ids(rng, parcels)
     gas = _gas(rng, [bed], T, xh2, 0.0, (0.0, 0.0, u), 0.1 * u, True)
-    params = base_params(dt=dt, skin=skin, rebuild_every=rebuild, kn=kn)
+    params = base_params(dt=dt, skin=skin, check_every=check, kn=kn)
     return Workload(name, precision, params, [bed], ores, parcels, gas, np.array([0]), steps, couple)
 
 
@@ -407,20 +407,31 @@ def _lognormal_dp(rng, m):
     return 100e-6 * np.exp(0.3 * z)
 
 
-def cfg3(n=2_000_000, seed=3, steps=500, u=0.01, kn=200.0):
-    """The 2M-parcel bed.  Gas upflow 0.01 m/s, below the minimum fluidization
-    velocity of the median real particle (about 0.014 m/s for 100 um ore in H2
-    at 1073 K), so the bed is a fixed bed, the regime the paper's hematite bed
-    starts in.  kn = 200 N/m: a linear stiffness of the size a Hertzian contact
-    with the paper's Y = 1e7 Pa at u_c = 1 m/s gives for these parcels, and one
-    that keeps the contact of the smallest parcels (d = 0.2 mm, 3 sigma below
-    the median) resolved at dt = 5 us (kn = 1000 N/m would make it unstable).
-    Neighbour lists are rebuilt every 60 steps (skin 0.1 mm); the voidage and
-    source deposits re-sort by cell at every coupling on their own."""
+def cfg3(n=2_000_000, seed=3, steps=500, u=0.01, kn=200.0, xh2=1.0):
+    """The 2M-parcel bed.  By default gas upflow 0.01 m/s of pure H2, below the
+    minimum fluidization velocity of the median real particle (about
+    0.014 m/s for 100 um ore in H2 at 1073 K), so the bed is a fixed bed, the
+    regime the paper's hematite bed starts in; fluidized() gives the
+    described 0.3 m/s of 90 % H2.  kn = 200 N/m: a linear stiffness of the
+    size a Hertzian contact with the paper's Y = 1e7 Pa at u_c = 1 m/s gives
+    for these parcels, and one that keeps the contact of the smallest parcels
+    (d = 0.2 mm, 3 sigma below the median) resolved at dt = 5 us (kn = 1000
+    N/m would make it unstable).  Skin 0.1 mm, lists checked at every coupling
+    (20 steps); the voidage and source deposits re-sort by cell at every
+    coupling on their own."""
     ores = [Ore(xi0=0.05, d_pore_cm=3.3e-6), Ore(xi0=0.25, d_pore_cm=9.5e-6)]
     return _cfg_cyl("cfg3", n, 2_000_000, 50e-3, 600e-3, 1.5625e-3, 1, _lognormal_dp, 5.0, ores,
-                    lambda rng, m: (rng.random(m) < 0.5).astype(np.int32), 1073.0, 1.0, seed, steps,
-                    skin=1e-4, rebuild=60, u=u, kn=kn)
+                    lambda rng, m: (rng.random(m) < 0.5).astype(np.int32), 1073.0, xh2, seed, steps,
+                    skin=1e-4, check=20, u=u, kn=kn)
+
+
+def fluidized(w):
+    """The same bed (same parcels and state) under the 2M-parcel bed's
+    described gas: 0.3 m/s upflow with a seeded +-10 % perturbation per cell,
+    90 % H2 and N2 at 1073 K."""
+    rng = np.random.Generator(np.random.PCG64(33))
+    gas = _gas(rng, w.beds, 1073.0, 0.9, 0.0, (0.0, 0.0, 0.3), 0.03, True)
+    return dataclasses.replace(w, gas=gas)
 
 
 def cfg4(n=500_000, seed=4, steps=20_000):
@@ -467,9 +478,7 @@ def cfg5(n_beds=64, seed=5, steps=1000, n_scale=1.0):
     rng = np.random.Generator(np.random.PCG64(ss.spawn(1)[0]))
     gas = _gas(rng, beds, Ts, xs, 0.0, (0.0, 0.0, 0.5), 0.0, False)
     offs = np.concatenate([[0], np.cumsum([bd.n_cells for bd in beds])[:-1]])
-    # lists rebuilt every 40 steps: the skin holds while no parcel moves more
-    # than skin/2 in 40 steps (0.5 m/s); the step reports a violation
-    params = base_params(dt=5e-6, skin=2e-4, rebuild_every=40)
+    params = base_params(dt=5e-6, skin=2e-4, check_every=20)
     return Workload("cfg5", "mixed", params, beds, [ore], parcels, gas, offs, steps, 20)
 
 
@@ -530,8 +539,7 @@ def sweep(n_scale=1.0, seed=6, steps=500, beds=SWEEP_BEDS):
     parcels = {k: np.ascontiguousarray(np.concatenate([p[k] for p in parts])) for k in parts[0]}
     gas = {k: np.ascontiguousarray(np.concatenate([g[k] for g in gases])) for k in gases[0]}
     offs = np.concatenate([[0], np.cumsum([bd.n_cells for bd in bl])[:-1]])
-    # lists rebuilt every 40 steps: the skin holds up to 0.25 m/s
-    params = base_params(dt=5e-6, skin=1e-4, rebuild_every=40, kn=100.0)
+    params = base_params(dt=5e-6, skin=1e-4, check_every=20, kn=100.0)
     return Workload("sweep", "mixed", params, bl, ores, parcels, gas, offs, steps, 20)
 
 

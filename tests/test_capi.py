@@ -58,6 +58,7 @@ def test_host_validation_rejects_null_and_bad_arguments():
     assert L.dem_pairs(None, None, 0, None) == -1
     xin = (C.c_double * 2)(0.7, 0.0)
     assert L.dem_gas_species(None, 1e-4, None, None, None, xin, None, None, None) == -1
+    assert L.dem_gas_momentum(None, 1e-4, None, None, None, None, None, None, None, None) == -1
     assert L.dem_react(None, 1e-4, None, None, None, None) == -1
     assert L.dem_set_launch(None, 64, 1, 1024) == -1
 
@@ -77,7 +78,7 @@ def test_bad_grid_rejected_on_host():
     ores[0].xi0, ores[0].d_pore_cm, ores[0].tau = 0.3, 1e-6, 2.0
     P = capi.DemParams()
     P.precision, P.n_beds, P.beds, P.n_ores, P.ores = 0, 1, beds, 1, ores
-    P.kn, P.e_p, P.mu_s, P.kt_over_kn, P.eps_min, P.dt, P.max_nbr, P.rebuild_every = 1e3, 0.9, 0.3, 0.28, 0.35, 1e-5, 16, 10
+    P.kn, P.e_p, P.mu_s, P.kt_over_kn, P.eps_min, P.dt, P.max_nbr, P.check_every = 1e3, 0.9, 0.3, 0.28, 0.35, 1e-5, 16, 10
     dummy = C.c_double(0)
     pc = capi.DemParcels(*[C.cast(C.byref(dummy), C.c_void_p)] * 17)
     h = C.c_void_p()

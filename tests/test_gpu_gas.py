@@ -118,3 +118,64 @@ def test_outputs_aliasing_the_gas_inputs_are_rejected():
     assert call(x["a"], x["a"], x["c"]) == capi.DEMRX_EINVAL
     assert call(x["a"], x["b"], x["c"]) == 0
     bed.sync()
+
+
+# ------------------------------------------------------------- momentum
+MOM = ("sumK", "sumKu", "sumKv", "sumKw")
+
+
+@pytest.mark.parametrize("case", ["cfg1_fp64", "cfg2_mixed", "cfg2_full_size"])
+def test_gas_momentum_at_identical_state(case):
+    """The gas-side momentum step (eqs. e4-1, e4-2) from the particles' drag
+    sums, against the oracle's: new gas velocities within 1e-12 relative to
+    the largest velocity of the field."""
+    if case == "cfg1_fp64":
+        w = W.with_velocities(W.squeeze(W.cfg1(), 0.995, 0), 51)
+    elif case == "cfg2_mixed":
+        w = W.with_velocities(W.squeeze(W.cfg2(n=3000, seed=52), 0.995, 0), 52, vscale=0.03)
+    else:
+        w = W.with_velocities(W.squeeze(W.cfg2(), 0.985, 0), 54, vscale=0.03)
+    _say(f"[gas momentum] {case} n={w.n}")
+    bed = Bed(w)
+    ora = O.Oracle(w)
+    cg = bed.couple()
+    co = ora.couple()
+    dt = 20 * w.params["dt"]
+    og = bed.gas_momentum(dt, cg, update=False)
+    oo = ora.gas_momentum(dt, co)
+    scale = max(np.max(np.abs(w.gas[k])) for k in ("ug", "vg", "wg"))
+    for k in ("ug", "vg", "wg"):
+        err = float(np.max(np.abs(_np(og[k]) - oo[k]))) / scale
+        _say(f"  {k}: {err:.2e}")
+        assert err <= 1e-12, k
+    # the parcels slowed the gas where they sit
+    assert np.max(np.abs(oo["wg"] - (w.gas["wg"] - 9.81 * dt))) > 1e-6 * scale
+
+
+def test_coupled_momentum_intervals_fp64():
+    """DEM steps, deposit, reaction and the gas momentum step, four times,
+    with the new gas velocity fed back to the particles: parcel positions
+    within 1e-4 d and gas velocities within 1e-9 (FP64 path)."""
+    w = W.with_velocities(W.squeeze(W.cfg1(), 0.995, 0), 53)
+    bed = Bed(w)
+    ora = O.Oracle(w)
+    g = dict(w.gas)
+    dt = 20 * w.params["dt"]
+    for it in range(4):
+        bed.step(20)
+        ora.step(20)
+        cg = bed.couple()
+        co = ora.couple()
+        bed.react(dt, keys=SRC)
+        ora.react(dt)
+        bed.gas_momentum(dt, cg)
+        g.update(ora.gas_momentum(dt, co))
+        ora.set_gas(g)
+    for k in ("ug", "vg", "wg"):
+        err = float(np.max(np.abs(_np(bed.gas_t[k]) - g[k])))
+        _say(f"[gas momentum] coupled {k}: {err:.2e}")
+        assert err <= 1e-9, k
+    sg, so = bed.state(), ora.state()
+    d = w.parcels["d"].astype(np.float64)
+    dx = np.sqrt(sum((_np(sg[k]) - so[k]) ** 2 for k in ("x", "y", "z")))
+    assert np.max(dx / d) <= 1e-4

@@ -343,3 +343,29 @@ def test_force_scale_bounds_the_net_force_and_torque():
     clear = ones[(pos[ones, 2] - R[ones] > 0.0)]
     assert clear.size > 0
     assert np.allclose(Fsb[clear], np.linalg.norm(Fb[clear], axis=1), rtol=1e-12)
+
+
+def test_perturbed_step_harness():
+    """The trajectory tests' noise-floor harness (Oracle.step_perturbed): with
+    rel = 0 it is ora_step bit for bit; with rel > 0 one step changes each
+    velocity component by exactly dt rel S_F / m (S_F the force-term scale)
+    in a sign fixed per parcel and component."""
+    w = W.with_velocities(W.squeeze(W.cfg2(n=1500, seed=8), 0.98, 0), 8, vscale=0.03, wscale=20.0)
+    a, b, c = O.Oracle(w), O.Oracle(w), O.Oracle(w)
+    a.step(3)
+    b.step_perturbed(3, 0.0, 5)
+    sa, sb = a.state(), b.state()
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+    Fs, _ = c.force_scale()
+    m = c.state()["mass"]
+    ref = O.Oracle(w)
+    ref.step(1)
+    rel = 1e-6
+    c.step_perturbed(1, rel, 5)
+    sr, sc = ref.state(), c.state()
+    dt = w.params["dt"]
+    for k in ("vx", "vy", "vz"):
+        dv = sc[k] - sr[k]
+        assert np.allclose(np.abs(dv), dt * rel * Fs / m, rtol=1e-6, atol=1e-18), k
+        assert 0.3 < np.mean(dv > 0) < 0.7

@@ -83,3 +83,96 @@ def test_h2_taken_matches_the_particle_rate_for_a_small_step():
     c_tot = p / (8.314 * T)
     taken = eps * c_tot * (0.6 - out["xH2"]) * 2.016e-3 * V  # kg; total moles unchanged (1:1)
     assert np.allclose(taken, rate * dt, rtol=1e-4)
+
+
+# ------------------------------------------------------------- momentum
+def _momentum_bed(v_scale=0.05, u=(0.0, 0.0, 0.5), grad_p=(0.0, 0.0, 0.0)):
+    """Parcels without contacts spread over a few gas cells, in random motion."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    pos = [(0.003 + 0.004 * i, 0.005 + 0.002 * (j % 2), 0.007 + 0.003 * j) for i in range(3) for j in range(3)]
+    v = rng.uniform(-v_scale, v_scale, (len(pos), 3))
+    w = box_workload(pos, 2.5e-4, k=2.0, u=u, v=v, L=(0.012, 0.012, 0.016), h=2e-3, grad_p=grad_p)
+    return w
+
+
+def _cell_of(w, st):
+    b = w.beds[0]
+    q = [np.clip(np.floor((st[a] - b.origin[k]) / b.h), 0, b.n[k] - 1).astype(int)
+         for k, a in enumerate(("x", "y", "z"))]
+    return q[0] + b.n[0] * (q[1] + b.n[1] * q[2])
+
+
+def test_gas_momentum_balances_the_particle_drag():
+    """Newton's third law across the phases: over a short step the gas of
+    each cell loses, per unit time, the drag that the particle side's force
+    routine applies to the cell's parcels (gravity and pressure gradient
+    off, no contacts)."""
+    w = _momentum_bed()
+    ora = O.Oracle(w, g=(0.0, 0.0, 0.0))
+    F, _ = ora.forces()
+    st = ora.state()
+    cells = _cell_of(w, st)
+    sums = ora.couple()
+    dt = 1e-10
+    new = ora.gas_momentum(dt, sums)
+    rho, _ = O.gas_props(1073.0, 101325.0, 1.0, 0.0, 0.0)
+    V = w.beds[0].h ** 3
+    eps = st["eps"]
+    for c in np.unique(cells):
+        for a, k in enumerate(("ug", "vg", "wg")):
+            gain = eps[c] * rho * V * (new[k][c] - w.gas[k][c]) / dt
+            drag = F[cells == c, a].sum()
+            assert gain == pytest.approx(-drag, rel=1e-6, abs=1e-12 * np.abs(F).max())
+    assert np.abs(F).max() > 0
+
+
+def test_gas_momentum_relaxes_exponentially_to_the_parcels_velocity():
+    """A cell holding parcels, pressure gradient hydrostatic (it cancels the
+    gas weight): the exact solution of eps rho du/dt = -(sum K / V)(u - u*)
+    relaxes u to u* = sum K v / sum K at the rate r = sum K / (eps rho V).
+    Repeated implicit steps converge to it at first order."""
+    rho, _ = O.gas_props(1073.0, 101325.0, 1.0, 0.0, 0.0)
+    w = _momentum_bed(u=(0.02, -0.01, 0.5), grad_p=(0.0, 0.0, -9.81 * rho))
+    ora = O.Oracle(w)
+    st = ora.state()
+    sums = ora.couple()
+    c = int(np.bincount(_cell_of(w, st)).argmax())
+    V = w.beds[0].h ** 3
+    r = sums["sumK"][c] / (st["eps"][c] * rho * V)
+    T = 2.0 / r
+    errs = []
+    for nsub in (50, 100, 200):
+        gas = dict(w.gas)
+        ora.set_gas(gas)
+        for _ in range(nsub):
+            out = ora.gas_momentum(T / nsub, sums)
+            gas = {**gas, **out}
+            ora.set_gas(gas)
+        e = []
+        for k, s in (("ug", "sumKu"), ("vg", "sumKv"), ("wg", "sumKw")):
+            ustar = sums[s][c] / sums["sumK"][c]
+            exact = ustar + (w.gas[k][c] - ustar) * np.exp(-r * T)
+            e.append(abs(gas[k][c] - exact) / abs(w.gas[k][c] - ustar))
+        errs.append(max(e))
+    assert errs[0] < 0.02
+    assert errs[1] == pytest.approx(errs[0] / 2, rel=0.05)
+    assert errs[2] == pytest.approx(errs[1] / 2, rel=0.05)
+
+
+def test_gas_momentum_without_parcels():
+    """An empty cell accelerates freely, du/dt = g - grad p / rho; with a
+    hydrostatic pressure gradient the gas stays at rest."""
+    rho, _ = O.gas_props(1073.0, 101325.0, 1.0, 0.0, 0.0)
+    w = _momentum_bed(u=(0.0, 0.1, 0.3))
+    ora = O.Oracle(w)
+    st = ora.state()
+    empty = np.setdiff1d(np.arange(ora.n_cells), _cell_of(w, st))
+    z = np.zeros(ora.n_cells)
+    sums = {"sumK": z, "sumKu": z, "sumKv": z, "sumKw": z}
+    dt = 1e-4
+    out = ora.gas_momentum(dt, sums)
+    assert np.allclose(out["wg"][empty], 0.3 - 9.81 * dt, rtol=1e-13)
+    assert np.allclose(out["vg"][empty], 0.1, rtol=1e-13)
+    ws = _momentum_bed(u=(0.0, 0.0, 0.0), grad_p=(0.0, 0.0, -9.81 * rho))
+    out = O.Oracle(ws).gas_momentum(dt, sums)
+    assert np.max(np.abs(out["wg"][empty])) < 1e-15
