@@ -984,8 +984,11 @@ static double fixed_sign(unsigned long long seed, int i, int c) {
  * not name its integrator): v += dt F/m, w += dt T/I, x += dt v_new.  With
  * rel > 0 (test harness only: ora_step_perturbed) every force and torque
  * component is biased by rel times the parcel's force-term scale, with a
- * sign fixed per parcel and component, every step. */
-static void step_impl(ora_sys *s, int nsteps, const ora_gas *g, double rel, unsigned long long seed) {
+ * sign fixed per parcel and component, every step; with round32 the
+ * velocities, spins and tangential springs are rounded to FP32 after every
+ * step (the storage of a mixed-precision evaluation). */
+static void step_impl(ora_sys *s, int nsteps, const ora_gas *g, double rel, unsigned long long seed,
+                      int round32) {
   int n = s->n;
   double *F = (double *)malloc(sizeof(double) * 3 * n);
   double *T = (double *)malloc(sizeof(double) * 3 * n);
@@ -1017,7 +1020,17 @@ static void step_impl(ora_sys *s, int nsteps, const ora_gas *g, double rel, unsi
       for (int c = 0; c < 3; c++) {
         s->vel[3 * i + c] += dt * F[3 * i + c] / m;
         s->omg[3 * i + c] += dt * T[3 * i + c] / I;
+        if (round32) { /* test harness: velocities and spins stored in FP32 */
+          s->vel[3 * i + c] = (double)(float)s->vel[3 * i + c];
+          s->omg[3 * i + c] = (double)(float)s->omg[3 * i + c];
+        }
         s->pos[3 * i + c] += dt * s->vel[3 * i + c];
+      }
+      if (round32) { /* and the tangential springs */
+        for (int q = 0; q < s->hcnt[i]; q++)
+          for (int c = 0; c < 3; c++)
+            s->hist[(size_t)i * HCAP + q].xi[c] = (double)(float)s->hist[(size_t)i * HCAP + q].xi[c];
+        for (int c = 0; c < 18; c++) s->wxi[18 * i + c] = (double)(float)s->wxi[18 * i + c];
       }
     }
   }
@@ -1027,10 +1040,11 @@ static void step_impl(ora_sys *s, int nsteps, const ora_gas *g, double rel, unsi
   free(Ts);
 }
 
-void ora_step(ora_sys *s, int nsteps, const ora_gas *g) { step_impl(s, nsteps, g, 0.0, 0); }
+void ora_step(ora_sys *s, int nsteps, const ora_gas *g) { step_impl(s, nsteps, g, 0.0, 0, 0); }
 
-void ora_step_perturbed(ora_sys *s, int nsteps, const ora_gas *g, double rel, unsigned long long seed) {
-  step_impl(s, nsteps, g, rel, seed);
+void ora_step_perturbed(ora_sys *s, int nsteps, const ora_gas *g, double rel, unsigned long long seed,
+                        int round32) {
+  step_impl(s, nsteps, g, rel, seed, round32);
 }
 
 /* ------------------------------------------------------------ deposition

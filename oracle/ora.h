@@ -90,8 +90,11 @@ void ora_step(ora_sys *s, int nsteps, const ora_gas *g);
 /* test harness only: ora_step with every force and torque component biased by
  * rel times the parcel's force-term scale (ora_force_scale), with a sign fixed
  * per parcel, component and seed: a deterministic emulation of a lower-precision
- * evaluation that errs by rel of the products the forces are built from */
-void ora_step_perturbed(ora_sys *s, int nsteps, const ora_gas *g, double rel, unsigned long long seed);
+ * evaluation that errs by rel of the products the forces are built from; with
+ * round32 the velocities, spins and tangential springs are also rounded to FP32
+ * after every step (the state a mixed-precision evaluation stores) */
+void ora_step_perturbed(ora_sys *s, int nsteps, const ora_gas *g, double rel, unsigned long long seed,
+                        int round32);
 /* voidage + drag deposition; outputs may be NULL */
 void ora_couple(ora_sys *s, const ora_gas *g, double *eps, double *np_, double *sumK,
                 double *sumKu, double *sumKv, double *sumKw, double *sumKs);

@@ -116,7 +116,8 @@ def lib():
         L.ora_forces.argtypes = [C.c_void_p, C.POINTER(OraGas), _dp, _dp]
         L.ora_force_scale.argtypes = [C.c_void_p, C.POINTER(OraGas), _dp, _dp]
         L.ora_step.argtypes = [C.c_void_p, C.c_int, C.POINTER(OraGas)]
-        L.ora_step_perturbed.argtypes = [C.c_void_p, C.c_int, C.POINTER(OraGas), C.c_double, C.c_ulonglong]
+        L.ora_step_perturbed.argtypes = [C.c_void_p, C.c_int, C.POINTER(OraGas), C.c_double, C.c_ulonglong,
+                                         C.c_int]
         L.ora_couple.argtypes = [C.c_void_p, C.POINTER(OraGas)] + [_dp] * 7
         L.ora_react.restype = C.c_long
         L.ora_react.argtypes = [C.c_void_p, C.c_double, C.POINTER(OraGas), C.c_int] + [_dp] * 10
@@ -261,11 +262,12 @@ class Oracle:
     def step(self, n=1):
         lib().ora_step(self.h, int(n), C.byref(self._gs))
 
-    def step_perturbed(self, n, rel, seed=1):
+    def step_perturbed(self, n, rel, seed=1, round32=False):
         """Test harness: steps with every force and torque component biased by
         rel of the parcel's force-term scale, with a sign fixed per parcel,
-        component and seed (ora_step_perturbed)."""
-        lib().ora_step_perturbed(self.h, int(n), C.byref(self._gs), float(rel), int(seed))
+        component and seed, and with round32 the velocities, spins and
+        springs rounded to FP32 after every step (ora_step_perturbed)."""
+        lib().ora_step_perturbed(self.h, int(n), C.byref(self._gs), float(rel), int(seed), int(round32))
 
     def couple(self):
         out = {k: np.zeros(self.n_cells) for k in ("eps", "np", "sumK", "sumKu", "sumKv", "sumKw", "sumKs")}

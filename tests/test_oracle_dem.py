@@ -369,3 +369,18 @@ def test_perturbed_step_harness():
         dv = sc[k] - sr[k]
         assert np.allclose(np.abs(dv), dt * rel * Fs / m, rtol=1e-6, atol=1e-18), k
         assert 0.3 < np.mean(dv > 0) < 0.7
+
+
+def test_perturbed_step_fp32_storage():
+    """With round32 the harness stores velocities, spins and tangential springs
+    in FP32 after every step (the mixed path's state): the state is then
+    FP32-representable and deviates from the FP64 run by FP32 roundings."""
+    w = W.with_velocities(W.squeeze(W.cfg2(n=1500, seed=8), 0.98, 0), 8, vscale=0.03, wscale=20.0)
+    a, b = O.Oracle(w), O.Oracle(w)
+    a.step(5)
+    b.step_perturbed(5, 0.0, 1, round32=True)
+    sa, sb = a.state(), b.state()
+    for k in ("vx", "vy", "vz", "wx", "wy", "wz"):
+        assert np.array_equal(sb[k], sb[k].astype(np.float32).astype(np.float64)), k
+        rel = np.abs(sb[k] - sa[k]) / np.maximum(np.abs(sa[k]), 1e-3)
+        assert 0 < rel.max() < 1e-5, k
