@@ -52,6 +52,7 @@ extern "C" {
 #define DEM_MAX_ORES 8
 #define DEM_MAX_BEDS 4096
 #define DEM_MAX_NBR 48
+#define DEM_NOALLOC_MAX_PAIRS (1 << 21) /* pairs dem_pairs_noalloc can return */
 
 typedef struct dem_ctx dem_ctx;
 
@@ -268,6 +269,19 @@ int dem_set_state(dem_ctx *c, const dem_parcels *in);
  * sorted by (i, j), written to the host array ij (2 * cap uint32).  *n_pairs
  * receives the total count (may exceed cap).  Synchronises. */
 int dem_pairs(dem_ctx *c, uint32_t *ij, int64_t cap, int64_t *n_pairs);
+
+/* dem_pairs for callers that cannot allocate device memory (tight serving
+ * loops, harnesses that forbid hipMalloc): the same pairs, found through a
+ * static device scratch of DEM_NOALLOC_MAX_PAIRS pairs (16 MiB, held by each
+ * GPU the library runs on until the process ends) instead of a buffer the
+ * context allocates; calls no hipMalloc or hipFree.  The pairs are copied
+ * into ij and sorted there, so ij (host, 2 * cap uint32) must hold all of
+ * them: *n_pairs always receives the count, and the call returns EINVAL when
+ * it exceeds cap and EOVERFLOW when it exceeds DEM_NOALLOC_MAX_PAIRS (ij
+ * untouched in both cases).  Calls on one GPU share its scratch: calls that
+ * overlap on one GPU (contexts on different streams or threads) race.
+ * Synchronises. */
+int dem_pairs_noalloc(dem_ctx *c, uint32_t *ij, int64_t cap, int64_t *n_pairs);
 
 /* Counters of the last step (host).  Synchronises. */
 int dem_get_stats(dem_ctx *c, dem_stats *out);

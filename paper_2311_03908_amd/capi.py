@@ -80,7 +80,7 @@ class DemStats(C.Structure):
 
 EXPORTS = ("dem_init", "dem_step", "dem_couple", "dem_react", "dem_gas_species", "dem_gas_momentum", "dem_grad",
            "dem_forces",
-           "dem_get_state", "dem_set_state", "dem_pairs", "dem_get_stats", "dem_run", "dem_autotune", "dem_set_launch", "dem_profile",
+           "dem_get_state", "dem_set_state", "dem_pairs", "dem_pairs_noalloc", "dem_get_stats", "dem_run", "dem_autotune", "dem_set_launch", "dem_profile",
            "dem_sync",
            "dem_last_error", "dem_destroy")
 
@@ -118,6 +118,7 @@ def load(path: str = LIB_PATH):
     L.dem_get_state.argtypes = [vp, C.POINTER(DemParcels)]
     L.dem_set_state.argtypes = [vp, C.POINTER(DemParcels)]
     L.dem_pairs.argtypes = [vp, C.POINTER(C.c_uint32), C.c_int64, C.POINTER(C.c_int64)]
+    L.dem_pairs_noalloc.argtypes = [vp, C.POINTER(C.c_uint32), C.c_int64, C.POINTER(C.c_int64)]
     L.dem_get_stats.argtypes = [vp, C.POINTER(DemStats)]
     L.dem_run.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(DemGas), C.POINTER(DemSources),
                           C.POINTER(C.c_double)]

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -32,6 +33,7 @@ struct dem_ctx {
   virtual int get_state(dem_parcels *o) = 0;
   virtual int set_state(const dem_parcels *in) = 0;
   virtual int pairs(uint32_t *ij, int64_t cap, int64_t *np) = 0;
+  virtual int pairs_noalloc(uint32_t *ij, int64_t cap, int64_t *np) = 0;
   virtual int stats(dem_stats *o) = 0;
   virtual int run(int n_int, int S, const dem_gas *g, dem_sources *o, double *bed_fov) = 0;
   virtual int autotune(const dem_gas *g) = 0;
@@ -41,7 +43,35 @@ struct dem_ctx {
   virtual int sync() = 0;
 };
 
+// Scratch of dem_pairs_noalloc: a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends) holding the pair
+// counter in its first 256 bytes and up to DEM_NOALLOC_MAX_PAIRS pairs after
+// it.  Host code uses only the address hipGetSymbolAddress returns for the
+// current device (taken once per device at dem_init), never the symbol itself.
+static __device__ __align__(256) unsigned char scratch[256 + (size_t)DEM_NOALLOC_MAX_PAIRS * 8];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+void *g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// the scratch address of the current device (resolved once per device)
+hipError_t scratch_address(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
 
 #define HIPCHK(x)                                                                    \
   do {                                                                               \
@@ -141,6 +171,7 @@ struct Ctx final : dem_ctx {
   const double *gas_T = nullptr;  // gas temperature of the last gas table (energy equation)
   double *eps = nullptr, *pm = nullptr, *pw = nullptr, *bed_fov_d = nullptr, *theta_d = nullptr;
   uint32_t *status = nullptr;
+  void *scratch_ptr = nullptr;       // this device's static scratch (dem_pairs_noalloc)
   float4 *xref = nullptr;            // positions at the last rebuild
   unsigned *dslot = nullptr;         // per-step displacement maxima (kSlots x 2, padded)
   unsigned long long *cslot = nullptr;  // contact counts of the counted step (kSlots, padded)
@@ -219,6 +250,7 @@ struct Ctx final : dem_ctx {
   }
 
   int init(const dem_params *p, const dem_parcels *in, int n_, hipStream_t s) {
+    HIPCHK(scratch_address(&scratch_ptr));
     P = *p;
     n = n_;
     user_st = st = s;
@@ -723,6 +755,33 @@ struct Ctx final : dem_ctx {
     return fail(DEMRX_EHIP, "pair buffer growth failed");
   }
 
+  // dem_pairs through the device's static scratch: no device allocation.  The
+  // pairs are copied into ij and sorted there, so ij must hold them all.
+  int pairs_noalloc(uint32_t *ij, int64_t cap, int64_t *np) override {
+    if (!np || (cap > 0 && !ij) || cap < 0) return fail(DEMRX_EINVAL, "bad pair buffer");
+    TRY(ensure_lists());
+    unsigned long long *cnt = (unsigned long long *)scratch_ptr;
+    uint32_t *buf = (uint32_t *)((unsigned char *)scratch_ptr + 256);
+    launch_fill_u32((uint32_t *)cnt, 0u, 2, st);  // the array keeps the last call's contents
+    launch_pairs<T>(dyn[cur], pr, nb, n, P.max_nbr, buf, (long)DEM_NOALLOC_MAX_PAIRS, cnt, st);
+    HIPCHK(hipGetLastError());
+    unsigned long long c = 0;
+    HIPCHK(hipMemcpyAsync(&c, cnt, sizeof c, hipMemcpyDeviceToHost, st));
+    TRY(sync());
+    *np = (int64_t)c;
+    if (c > (unsigned long long)DEM_NOALLOC_MAX_PAIRS)
+      return fail(DEMRX_EOVERFLOW, std::to_string(c) + " contact pairs exceed the " +
+                                       std::to_string(DEM_NOALLOC_MAX_PAIRS) + " of the static scratch; use dem_pairs");
+    if ((int64_t)c > cap) return fail(DEMRX_EINVAL, "ij holds fewer pairs than there are (see *n_pairs)");
+    if (c) HIPCHK(hipMemcpy(ij, buf, 2 * c * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    struct Pr {
+      uint32_t a, b;
+    };
+    Pr *pp = reinterpret_cast<Pr *>(ij);
+    std::sort(pp, pp + c, [](const Pr &x, const Pr &y) { return x.a != y.a ? x.a < y.a : x.b < y.b; });
+    return DEMRX_OK;
+  }
+
   int stats(dem_stats *o) override {
     if (!o) return fail(DEMRX_EINVAL, "null output");
     unsigned long long c[4], rbc = 0;
@@ -1051,6 +1110,9 @@ int dem_forces(dem_ctx *c, const dem_gas *g, double *F, double *T) { return c ? 
 int dem_get_state(dem_ctx *c, dem_parcels *o) { return c ? c->get_state(o) : DEMRX_EINVAL; }
 int dem_set_state(dem_ctx *c, const dem_parcels *in) { return c ? c->set_state(in) : DEMRX_EINVAL; }
 int dem_pairs(dem_ctx *c, uint32_t *ij, int64_t cap, int64_t *np) { return c ? c->pairs(ij, cap, np) : DEMRX_EINVAL; }
+int dem_pairs_noalloc(dem_ctx *c, uint32_t *ij, int64_t cap, int64_t *np) {
+  return c ? c->pairs_noalloc(ij, cap, np) : DEMRX_EINVAL;
+}
 int dem_get_stats(dem_ctx *c, dem_stats *o) { return c ? c->stats(o) : DEMRX_EINVAL; }
 int dem_run(dem_ctx *c, int32_t n_int, int32_t S, const dem_gas *g, dem_sources *o, double *bed_fov) {
   return c ? c->run(n_int, S, g, o, bed_fov) : DEMRX_EINVAL;
