@@ -170,8 +170,12 @@ typedef struct {
   int64_t step_kernel_launches;  /* launches behind step_kernel_ms (see dem_profile) */
   int32_t step_block;            /* launch shape in use (dem_autotune): step-kernel block size, */
   int32_t step_xcd;              /* blocks per XCD chunk (1: plain round-robin), */
-  int32_t build_grid;            /* persistent grid of the neighbour build */
+  int32_t build_grid;            /* persistent grid of the neighbour build, */
   int32_t check_period;          /* steps between neighbour-list checks (check_every) */
+  int32_t build_threads;         /* neighbour build in use: threads per block, */
+  int32_t build_tile;            /* LDS tile (candidate records staged at a time), */
+  int32_t build_item_x;          /* DEM cells along x per work item */
+  int32_t tune_cached;           /* 1: the shapes came from the autotuner cache */
 } dem_stats;
 
 /* Create a context holding n parcels.  Copies the parcel state (device, original
@@ -261,8 +265,44 @@ int dem_get_state(dem_ctx *c, dem_parcels *out);
 
 /* Replace positions, velocities, spins and species (original order, all
  * members required except d, k, ore, bed, which are ignored); masses follow
- * the species; contact histories are cleared.  Synchronises. */
+ * the species; contact histories are cleared (dem_set_contacts restores
+ * them).  Synchronises. */
 int dem_set_state(dem_ctx *c, const dem_parcels *in);
+
+/* Contact history, for checkpoint and resume: the tangential springs of the
+ * contact model (the Cundall spring of the soft-sphere law, which the paper
+ * takes from its DEM reference; eqs. e3-42..e3-45 fix the coarse-grained
+ * stiffness and damping it acts with).  Host arrays:
+ *   ids[2 * cap]  original ids (a, b) of each pair, a < b, ascending (a, b);
+ *   xi[3 * cap]   its spring (m), with the contact normal from a to b;
+ *   cap           capacity of ids and xi in pairs;
+ *   count         pairs written (get: the total, which may exceed cap, in
+ *                 which case only cap are written) or given (set);
+ *   wall_on[6 n]  1 where parcel id (original order) has a spring on wall w
+ *                 (index id * 6 + w; box walls -x, +x, -y, +y, -z, +z;
+ *                 cylinder: mantle, bottom, top), else 0;
+ *   wall_xi[18 n] that spring, index (id * 6 + w) * 3 + axis (0 if off). */
+typedef struct {
+  int64_t cap, count;
+  uint32_t *ids;
+  double *xi;
+  uint8_t *wall_on;
+  double *wall_xi;
+} dem_contacts;
+
+/* Export the springs of the pairs and walls in contact at the last step
+ * (both partners of a pair hold the same spring; the record comes from the
+ * one with the lower id).  Synchronises.  EINVAL on null arrays. */
+int dem_get_contacts(dem_ctx *c, dem_contacts *io);
+
+/* Load springs exported by dem_get_contacts (usually after dem_init or
+ * dem_set_state with the same checkpoint): rebuilds the neighbour lists at the
+ * current positions and gives every listed pair that still touches its
+ * spring, as a rebuild carries springs over.  Pairs that no longer touch
+ * drop theirs, as in a step.  Synchronises.  EINVAL unless every pair has
+ * a < b < n and every spring is finite; EOVERFLOW (latched) when a parcel is
+ * given more pairs than max_nbr. */
+int dem_set_contacts(dem_ctx *c, const dem_contacts *in);
 
 /* Contacting pairs at the current positions (exact FP64 test
  * ((dx dx + dy dy) + dz dz) < (r_i + r_j)^2), canonical (i < j by original id),
@@ -299,17 +339,32 @@ int dem_run(dem_ctx *c, int32_t n_intervals, int32_t couple_every, const dem_gas
             dem_sources *out, double *bed_fov);
 
 /* Choose launch shapes for this context's kernels by timing candidates on
- * its own data (state unchanged).  Synchronises.  With the environment
- * variable DEMRX_TUNE_LOG set, every candidate's timing goes to stderr. */
+ * its own data (state unchanged): the DEM-step block size and XCD chunk, and
+ * the neighbour build's block size, LDS tile and work-item width (whole
+ * rebuild chains are timed).  Synchronises.  With the environment variable
+ * DEMRX_TUNE_LOG set, every candidate's timing goes to stderr.  With
+ * DEMRX_TUNE_CACHE naming a JSON file, shapes stored there under the key of
+ * this device architecture and configuration (parcel count, beds and their
+ * grids, precision, list capacity, skin, energy equation) are applied without
+ * timing, and newly chosen shapes are stored (the file is rewritten). */
 int dem_autotune(dem_ctx *c, const dem_gas *g);
 
 /* Set the launch shapes directly (instead of dem_autotune), e.g. to repeat a
  * measurement in a known shape: step_block threads per block of the DEM-step
  * kernel (64, 128, 256 or 512), step_xcd_chunk consecutive blocks kept on one
  * XCD by the block remap (1..64; 1 = no remap), build_grid blocks of the
- * persistent neighbour build (1..65536).  Results do not depend on the shapes.
- * DEMRX_EINVAL outside these ranges (nothing changed).  No device work. */
+ * persistent neighbour build (1..65536; 0 = as many as are resident on every
+ * compute unit).  Results do not depend on the shapes.  DEMRX_EINVAL outside
+ * these ranges (nothing changed).  No device work. */
 int dem_set_launch(dem_ctx *c, int32_t step_block, int32_t step_xcd_chunk, int32_t build_grid);
+
+/* Set the neighbour build's shape directly (instead of dem_autotune):
+ * threads per block and LDS tile in candidate records, one of 512/2048,
+ * 256/1024, 256/2048, 1024/4096, and the work-item width item_x, 8, 16 or 32
+ * DEM cells along x.  The lists, and so all results, do not depend on the
+ * shape.  DEMRX_EINVAL for other values (nothing changed).  Uploads the work
+ * items of a new width on the context's stream. */
+int dem_set_build(dem_ctx *c, int32_t threads, int32_t tile, int32_t item_x);
 
 /* Enable (1) or disable (0) HIP-event timing of every DEM-step kernel launch,
  * recorded on the stream the kernel runs on (inside dem_run graphs too: the

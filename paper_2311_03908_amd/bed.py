@@ -202,6 +202,48 @@ class Bed:
                 return np.frombuffer(buf, dtype=np.uint32, count=2 * npairs.value).reshape(-1, 2).astype(np.int64)
             cap = npairs.value
 
+    def contacts(self):
+        """Springs of the pairs and walls in contact (dem_get_contacts): ids
+        (P, 2) with a < b, xi (P, 3), wall_on (n, 6), wall_xi (n, 6, 3)."""
+        cap = max(16, 4 * self.n)
+        while True:
+            ids = np.zeros((cap, 2), dtype=np.uint32)
+            xi = np.zeros((cap, 3), dtype=np.float64)
+            won = np.zeros((self.n, 6), dtype=np.uint8)
+            wxi = np.zeros((self.n, 6, 3), dtype=np.float64)
+            c = capi.DemContacts(cap, 0, ids.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                 xi.ctypes.data_as(C.POINTER(C.c_double)), won.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                 wxi.ctypes.data_as(C.POINTER(C.c_double)))
+            self._check(self.L.dem_get_contacts(self.h, C.byref(c)))
+            if c.count <= cap:
+                k = int(c.count)
+                return {"ids": ids[:k].copy(), "xi": xi[:k].copy(), "wall_on": won, "wall_xi": wxi}
+            cap = int(c.count)
+
+    def set_contacts(self, ct):
+        ids = np.ascontiguousarray(ct["ids"], dtype=np.uint32).reshape(-1, 2)
+        xi = np.ascontiguousarray(ct["xi"], dtype=np.float64).reshape(-1, 3)
+        won = np.ascontiguousarray(ct["wall_on"], dtype=np.uint8).reshape(self.n, 6)
+        wxi = np.ascontiguousarray(ct["wall_xi"], dtype=np.float64).reshape(self.n, 6, 3)
+        if len(ids) != len(xi):
+            raise ValueError("ids and xi differ in length")
+        c = capi.DemContacts(len(ids), len(ids), ids.ctypes.data_as(C.POINTER(C.c_uint32)),
+                             xi.ctypes.data_as(C.POINTER(C.c_double)), won.ctypes.data_as(C.POINTER(C.c_uint8)),
+                             wxi.ctypes.data_as(C.POINTER(C.c_double)))
+        self._check(self.L.dem_set_contacts(self.h, C.byref(c)))
+
+    def save_checkpoint(self, path):
+        """Parcel state and contact springs in one .npz file."""
+        st = {k: v.cpu().numpy() for k, v in self.state().items()}
+        ct = self.contacts()
+        np.savez(path, **{"state_" + k: v for k, v in st.items()}, **{"contacts_" + k: v for k, v in ct.items()})
+
+    def load_checkpoint(self, path):
+        """Resume from save_checkpoint: state first, then the springs."""
+        with np.load(path, allow_pickle=False) as z:
+            self.set_state({k[6:]: z[k] for k in z.files if k.startswith("state_")})
+            self.set_contacts({k[9:]: z[k] for k in z.files if k.startswith("contacts_")})
+
     def stats(self):
         s = capi.DemStats()
         self._check(self.L.dem_get_stats(self.h, C.byref(s)))
@@ -225,6 +267,9 @@ class Bed:
 
     def set_launch(self, step_block, step_xcd_chunk, build_grid):
         self._check(self.L.dem_set_launch(self.h, int(step_block), int(step_xcd_chunk), int(build_grid)))
+
+    def set_build(self, threads, tile, item_x):
+        self._check(self.L.dem_set_build(self.h, int(threads), int(tile), int(item_x)))
 
     def grad(self, n_substeps, dt_react, dyn_every, ckpt_every, theta, state_fp32=True, with_grad=True):
         spec = capi.DemGradSpec(int(n_substeps), float(dt_react), int(dyn_every), int(ckpt_every), int(state_fp32))

@@ -49,6 +49,12 @@ class DemParcels(C.Structure):
     _fields_ = [(f, C.c_void_p) for f in PARCEL_FIELDS]
 
 
+class DemContacts(C.Structure):
+    _fields_ = [("cap", C.c_int64), ("count", C.c_int64), ("ids", C.POINTER(C.c_uint32)),
+                ("xi", C.POINTER(C.c_double)), ("wall_on", C.POINTER(C.c_uint8)),
+                ("wall_xi", C.POINTER(C.c_double))]
+
+
 GAS_FIELDS = ("ug", "vg", "wg", "p", "dpdx", "dpdy", "dpdz", "T", "xH2", "xH2O", "xN2")
 
 
@@ -75,12 +81,14 @@ class DemStats(C.Structure):
                 ("mean_coordination", C.c_double), ("max_nbr_used", C.c_int32), ("status", C.c_uint32),
                 ("step_kernel_ms", C.c_double), ("step_kernel_launches", C.c_int64),
                 ("step_block", C.c_int32), ("step_xcd", C.c_int32), ("build_grid", C.c_int32),
-                ("check_period", C.c_int32)]
+                ("check_period", C.c_int32), ("build_threads", C.c_int32), ("build_tile", C.c_int32),
+                ("build_item_x", C.c_int32), ("tune_cached", C.c_int32)]
 
 
 EXPORTS = ("dem_init", "dem_step", "dem_couple", "dem_react", "dem_gas_species", "dem_gas_momentum", "dem_grad",
            "dem_forces",
-           "dem_get_state", "dem_set_state", "dem_pairs", "dem_pairs_noalloc", "dem_get_stats", "dem_run", "dem_autotune", "dem_set_launch", "dem_profile",
+           "dem_get_state", "dem_set_state", "dem_pairs", "dem_pairs_noalloc", "dem_get_contacts", "dem_set_contacts", "dem_get_stats", "dem_run", "dem_autotune", "dem_set_launch", "dem_set_build",
+           "dem_profile",
            "dem_sync",
            "dem_last_error", "dem_destroy")
 
@@ -119,11 +127,14 @@ def load(path: str = LIB_PATH):
     L.dem_set_state.argtypes = [vp, C.POINTER(DemParcels)]
     L.dem_pairs.argtypes = [vp, C.POINTER(C.c_uint32), C.c_int64, C.POINTER(C.c_int64)]
     L.dem_pairs_noalloc.argtypes = [vp, C.POINTER(C.c_uint32), C.c_int64, C.POINTER(C.c_int64)]
+    L.dem_get_contacts.argtypes = [vp, C.POINTER(DemContacts)]
+    L.dem_set_contacts.argtypes = [vp, C.POINTER(DemContacts)]
     L.dem_get_stats.argtypes = [vp, C.POINTER(DemStats)]
     L.dem_run.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(DemGas), C.POINTER(DemSources),
                           C.POINTER(C.c_double)]
     L.dem_autotune.argtypes = [vp, C.POINTER(DemGas)]
     L.dem_set_launch.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+    L.dem_set_build.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
     L.dem_profile.argtypes = [vp, C.c_int32]
     L.dem_sync.argtypes = [vp]
     L.dem_last_error.argtypes = [vp]

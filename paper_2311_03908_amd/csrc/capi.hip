@@ -34,10 +34,13 @@ struct dem_ctx {
   virtual int set_state(const dem_parcels *in) = 0;
   virtual int pairs(uint32_t *ij, int64_t cap, int64_t *np) = 0;
   virtual int pairs_noalloc(uint32_t *ij, int64_t cap, int64_t *np) = 0;
+  virtual int get_contacts(dem_contacts *io) = 0;
+  virtual int set_contacts(const dem_contacts *in) = 0;
   virtual int stats(dem_stats *o) = 0;
   virtual int run(int n_int, int S, const dem_gas *g, dem_sources *o, double *bed_fov) = 0;
   virtual int autotune(const dem_gas *g) = 0;
   virtual int set_launch(int step_block, int step_xcd_chunk, int build_grid) = 0;
+  virtual int set_build(int threads, int tile, int item_x) = 0;
   virtual int grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, double *J, double *grad) = 0;
   virtual int profile(int enable) = 0;
   virtual int sync() = 0;
@@ -138,7 +141,7 @@ struct Ctx final : dem_ctx {
   std::vector<dem_ore> hores;
   std::vector<BedDev> hbd;
   Phys ph{};
-  int n = 0, n_gas = 0, n_keys = 0, n_items = 0;
+  int n = 0, n_gas = 0, n_keys = 0, n_items = 0, n_items_max = 0;
   hipStream_t st = nullptr, user_st = nullptr, cap_st = nullptr;
   std::vector<void *> allocs;
   BedDev *beds = nullptr;
@@ -181,7 +184,15 @@ struct Ctx final : dem_ctx {
   long pairs_cap = 0;
   long step_count = 0;
   bool built = false;
-  int step_block = 64, build_grid = 1024, step_xcd = 1;
+  int step_block = 64, step_xcd = 1;
+  // neighbour build: variant (block size, LDS tile), item width, grid
+  // (0: resident blocks per CU x CUs)
+  int build_variant = 0, item_x = 16, build_grid = 0;
+  int n_cu = 256;
+  std::string arch;
+  bool tune_cached = false;
+  std::vector<Item> hitems;  // host copy of the work items (kept alive for the async upload)
+  int bpc[kBuildVariants] = {0, 0, 0, 0};
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<const void *> gkey;
@@ -292,6 +303,8 @@ struct Ctx final : dem_ctx {
       d.n_gas = B.n[0] * B.n[1] * B.n[2];
       // key tiles (see dem_key): one tile per bed plane (row-major keys).
       // Columns of 16 x 16 cells measured no faster on the 2M-parcel bed.
+      // The neighbour build relies on this: the cells of a bed row have
+      // consecutive keys, so a row is one run of the sorted order.
       d.tx = d.nd[0];
       d.ty = d.nd[1];
       d.ntx = (d.nd[0] + d.tx - 1) / d.tx;
@@ -303,31 +316,21 @@ struct Ctx final : dem_ctx {
       d.mu_override = B.mu_override;
       goff += d.n_gas;
       doff += d.n_dem;
-      items_total += (long)d.nd[1] * d.nd[2] * ((d.nd[0] + kItemX - 1) / kItemX);
+      // work items of the narrowest width (the most items any width makes)
+      items_total += (long)d.nd[1] * d.nd[2] * ((d.nd[0] + kItemWidths[0] - 1) / kItemWidths[0]);
       hbd.push_back(d);
     }
     if (goff > (1L << 30) || doff > (1L << 30) || items_total > (1L << 30))
       return fail(DEMRX_EINVAL, "grid too large");
     n_gas = (int)goff;
     n_keys = (int)doff;
-    n_items = (int)items_total;
+    n_items_max = (int)items_total;
     std::vector<OreDev> hod;
     for (auto &o : hores) hod.push_back(make_ore(o));
     std::vector<int32_t> hcb(n_gas);
-    std::vector<Item> hit;
-    hit.reserve(n_items);
     for (int b = 0; b < p->n_beds; b++) {
       const BedDev &d = hbd[b];
       for (int c = 0; c < d.n_gas; c++) hcb[d.gas_off + c] = b;
-      // items in key order (tile column by column), so that the rebuild's
-      // persistent blocks work on neighbouring cells at the same time
-      const int nty = (d.nd[1] + d.ty - 1) / d.ty;
-      for (int cy = 0; cy < nty; cy++)
-        for (int cx = 0; cx < d.ntx; cx++)
-          for (int iz = 0; iz < d.nd[2]; iz++)
-            for (int iy = cy * d.ty; iy < std::min((cy + 1) * d.ty, d.nd[1]); iy++)
-              for (int x0 = cx * d.tx; x0 < std::min((cx + 1) * d.tx, d.nd[0]); x0 += kItemX)
-                hit.push_back(Item{b, x0, iy, iz});
     }
     // largest parcel per bed against the DEM cell (checked on the host once)
     {
@@ -350,7 +353,7 @@ struct Ctx final : dem_ctx {
     TRY(dalloc(beds, hbd.size()));
     TRY(dalloc(ores, hod.size()));
     TRY(dalloc(cell_bed, n_gas));
-    TRY(dalloc(items, n_items));
+    TRY(dalloc(items, n_items_max));
     for (int k = 0; k < 2; k++) TRY(alloc_dyn(dyn[k]));
     TRY(alloc_props(pr, nullptr));
     TRY(alloc_props(pr_sp, &pr));
@@ -366,10 +369,10 @@ struct Ctx final : dem_ctx {
     TRY(dalloc(start_d, (size_t)n_keys + 1)); TRY(dalloc(order_d, n));
     TRY(dalloc(occ_flags, (size_t)n_gas + 1)); TRY(dalloc(occ_offs, (size_t)n_gas + 1));
     TRY(dalloc(occ_list, n_gas)); TRY(dalloc(occ_count, 1));
-    const long scr = std::max(scan_scratch_ints((long)n_keys + 1), scan_scratch_ints((long)n_items + 1));
+    const long scr = std::max(scan_scratch_ints((long)n_keys + 1), scan_scratch_ints((long)n_items_max + 1));
     TRY(dalloc(scan_scr, scr));
-    TRY(dalloc(iflags, (size_t)n_items + 1)); TRY(dalloc(ioffs, (size_t)n_items + 1));
-    TRY(dalloc(ilist, n_items)); TRY(dalloc(icount, 2));
+    TRY(dalloc(iflags, (size_t)n_items_max + 1)); TRY(dalloc(ioffs, (size_t)n_items_max + 1));
+    TRY(dalloc(ilist, n_items_max)); TRY(dalloc(icount, 2));
     TRY(dalloc(gtab, (size_t)n_gas * kGasRow));
     TRY(dalloc(eps, n_gas));
     TRY(dalloc(pm, (size_t)(P.energy_on ? 8 : 4) * n)); TRY(dalloc(pw, (size_t)2 * n));
@@ -384,8 +387,15 @@ struct Ctx final : dem_ctx {
     HIPCHK(hipMemcpyAsync(beds, hbd.data(), hbd.size() * sizeof(BedDev), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ores, hod.data(), hod.size() * sizeof(OreDev), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(cell_bed, hcb.data(), hcb.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    if ((long)hit.size() != n_items) return fail(DEMRX_EINVAL, "internal: work-item count mismatch");
-    HIPCHK(hipMemcpyAsync(items, hit.data(), hit.size() * sizeof(Item), hipMemcpyHostToDevice, st));
+    TRY(upload_items(item_x));
+    {
+      int dev = 0;
+      hipDeviceProp_t prop;
+      HIPCHK(hipGetDevice(&dev));
+      HIPCHK(hipGetDeviceProperties(&prop, dev));
+      n_cu = std::max(1, prop.multiProcessorCount);
+      arch = prop.gcnArchName;
+    }
     launch_fill_u32((uint32_t *)nb.mask, 0u, 2L * n, st);
     launch_fill_i32(nb.cnt, 0, n, st);
     launch_fill_u32((uint32_t *)rb_count, 0u, 2, st);
@@ -429,7 +439,28 @@ struct Ctx final : dem_ctx {
   // (bin, scan, scatter, in-cell rank), compacts the contact springs,
   // permutes the state through the spare buffers back into dyn[cur] and pr,
   // and builds the lists; no buffer parity changes.
-  int rebuild_chain(int horizon, bool force) {
+  // Work items of `width` DEM cells along x, in key order (row by row), so
+  // that the persistent build blocks work on neighbouring cells at a time.
+  int upload_items(int width) {
+    hitems.clear();
+    for (size_t b = 0; b < hbd.size(); b++) {
+      const BedDev &d = hbd[b];
+      for (int iz = 0; iz < d.nd[2]; iz++)
+        for (int iy = 0; iy < d.nd[1]; iy++)
+          for (int x0 = 0; x0 < d.nd[0]; x0 += width) hitems.push_back(Item{(int)b, x0, iy, iz});
+    }
+    if ((long)hitems.size() > n_items_max) return fail(DEMRX_EINVAL, "internal: work-item count");
+    n_items = (int)hitems.size();
+    item_x = width;
+    HIPCHK(hipMemcpyAsync(items, hitems.data(), hitems.size() * sizeof(Item), hipMemcpyHostToDevice, st));
+    return DEMRX_OK;
+  }
+  int build_grid_now() {
+    if (build_grid > 0) return std::max(1, std::min(n_items, build_grid));
+    if (!bpc[build_variant]) bpc[build_variant] = build_blocks_per_cu<T>(build_variant);
+    return std::max(1, std::min(n_items, bpc[build_variant] * n_cu));
+  }
+  int rebuild_chain(int horizon, bool force, bool carry_ready = false) {
     const uint32_t *G = rb_flag;
     launch_rebuild_check(dslot, (int)((step_count & 1) ^ 1), P.skin, P.dt, horizon, force ? 1 : 0, rb_flag,
                          rb_count, st);
@@ -438,9 +469,9 @@ struct Ctx final : dem_ctx {
     launch_scan(count, start, (long)n_keys + 1, scan_scr, st, G);
     launch_scatter(key, slot, start, dyn[cur].pos, n, perm2, cord, st, G);
     launch_cellrank(start, perm2, cord, n, perm, st, G);
-    launch_carry<T>(nb, n, carry, carry_meta, st, G);
+    if (!carry_ready) launch_carry<T>(nb, n, carry, carry_meta, st, G);  // else filled by the caller
     launch_permute<T>(perm, n, dyn[cur], pr, dyn[cur ^ 1], pr_sp, xref, dslot, st, G);
-    launch_items(items, n_items, beds, start, iflags, ioffs, scan_scr, ilist, icount, st, G);
+    launch_items(items, n_items, item_x, beds, start, iflags, ioffs, scan_scr, ilist, icount, st, G);
     NbrBuild<T> a;
     a.d = dyn[cur];
     a.p = pr;
@@ -456,11 +487,12 @@ struct Ctx final : dem_ctx {
     a.list_count = icount;
     a.n = n;
     a.cap = P.max_nbr;
+    a.item_x = item_x;
     a.skin = P.skin;
     a.status = status;
     a.queue = icount + 1;
     launch_fill_i32(a.queue, 0, 1, st, G);
-    launch_build_nbr<T>(a, std::max(1, std::min(n_items, build_grid)), st);
+    launch_build_nbr<T>(a, build_variant, build_grid_now(), st);
     HIPCHK(hipGetLastError());
     built = true;
     dep_fresh = false;  // the parcels may have moved in memory
@@ -755,6 +787,111 @@ struct Ctx final : dem_ctx {
     return fail(DEMRX_EHIP, "pair buffer growth failed");
   }
 
+  // Device buffers of one call, freed when it returns (hipFree waits for the
+  // device).
+  struct CallBufs {
+    std::vector<void *> p;
+    ~CallBufs() {
+      for (void *q : p) (void)hipFree(q);
+    }
+    template <typename U>
+    bool get(U *&out, size_t cnt) {
+      void *q = nullptr;
+      if (hipMalloc(&q, std::max<size_t>(cnt, 1) * sizeof(U)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+      }
+      p.push_back(q);
+      out = (U *)q;
+      return true;
+    }
+  };
+
+  int get_contacts(dem_contacts *io) override {
+    if (!io || io->cap < 0 || (io->cap > 0 && (!io->ids || !io->xi)) || !io->wall_on || !io->wall_xi)
+      return fail(DEMRX_EINVAL, "bad contact buffers");
+    TRY(ensure_lists());
+    CallBufs B;
+    uint8_t *won = nullptr;
+    double *wxi = nullptr;
+    unsigned long long *cnt = nullptr;
+    if (!B.get(won, (size_t)n * kMaxWalls) || !B.get(wxi, (size_t)n * kMaxWalls * 3) || !B.get(cnt, 1))
+      return fail(DEMRX_ENOMEM, "contact export buffers");
+    long cap = std::max<long>(1024, 3L * n);
+    for (int attempt = 0; attempt < 2; attempt++) {
+      uint32_t *ids = nullptr;
+      double *xi = nullptr;
+      CallBufs P2;
+      if (!P2.get(ids, 2 * (size_t)cap) || !P2.get(xi, 3 * (size_t)cap)) return fail(DEMRX_ENOMEM, "contact buffers");
+      launch_fill_u32((uint32_t *)cnt, 0u, 2, st);
+      launch_contacts_export<T>(dyn[cur].pos, nb, pr.wh, n, P.max_nbr, ids, xi, cap, cnt, won, wxi, st);
+      HIPCHK(hipGetLastError());
+      unsigned long long c = 0;
+      HIPCHK(hipMemcpyAsync(&c, cnt, sizeof c, hipMemcpyDeviceToHost, st));
+      TRY(sync());
+      if ((long)c > cap) {
+        cap = (long)c;
+        continue;
+      }
+      std::vector<uint32_t> hi(2 * c);
+      std::vector<double> hx(3 * c);
+      if (c) {
+        HIPCHK(hipMemcpy(hi.data(), ids, 2 * c * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(hx.data(), xi, 3 * c * sizeof(double), hipMemcpyDeviceToHost));
+      }
+      // ascending (a, b): the order does not depend on the launch
+      std::vector<uint64_t> k(c);
+      for (size_t q = 0; q < c; q++) k[q] = ((uint64_t)hi[2 * q] << 32) | hi[2 * q + 1];
+      std::vector<size_t> ord(c);
+      std::iota(ord.begin(), ord.end(), (size_t)0);
+      std::sort(ord.begin(), ord.end(), [&](size_t u, size_t v) { return k[u] < k[v]; });
+      for (size_t q = 0; q < c && (int64_t)q < io->cap; q++) {
+        const size_t o = ord[q];
+        io->ids[2 * q] = hi[2 * o];
+        io->ids[2 * q + 1] = hi[2 * o + 1];
+        for (int d = 0; d < 3; d++) io->xi[3 * q + d] = hx[3 * o + d];
+      }
+      io->count = (int64_t)c;
+      HIPCHK(hipMemcpy(io->wall_on, won, (size_t)n * kMaxWalls, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(io->wall_xi, wxi, (size_t)n * kMaxWalls * 3 * sizeof(double), hipMemcpyDeviceToHost));
+      return DEMRX_OK;
+    }
+    return fail(DEMRX_EHIP, "contact buffer growth failed");
+  }
+
+  int set_contacts(const dem_contacts *in) override {
+    if (!in || in->count < 0 || (in->count > 0 && (!in->ids || !in->xi)) || !in->wall_on || !in->wall_xi)
+      return fail(DEMRX_EINVAL, "bad contact arrays");
+    const long np = (long)in->count;
+    for (long q = 0; q < np; q++) {
+      const uint32_t a = in->ids[2 * q], b = in->ids[2 * q + 1];
+      if (!(a < b && b < (uint32_t)n)) return fail(DEMRX_EINVAL, "contact pair " + std::to_string(q) + " is not a < b < n");
+      for (int d = 0; d < 3; d++)
+        if (!std::isfinite(in->xi[3 * q + d])) return fail(DEMRX_EINVAL, "non-finite contact spring");
+    }
+    for (long q = 0; q < (long)n * kMaxWalls * 3; q++)
+      if (!std::isfinite(in->wall_xi[q])) return fail(DEMRX_EINVAL, "non-finite wall spring");
+    CallBufs B;
+    uint32_t *ids = nullptr, *cnt = nullptr;
+    double *xi = nullptr, *wxi = nullptr;
+    uint8_t *won = nullptr;
+    int32_t *inv = nullptr;
+    if (!B.get(ids, 2 * (size_t)np) || !B.get(xi, 3 * (size_t)np) || !B.get(won, (size_t)n * kMaxWalls) ||
+        !B.get(wxi, (size_t)n * kMaxWalls * 3) || !B.get(inv, n) || !B.get(cnt, n))
+      return fail(DEMRX_ENOMEM, "contact import buffers");
+    if (np) {
+      HIPCHK(hipMemcpyAsync(ids, in->ids, 2 * np * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(xi, in->xi, 3 * np * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    HIPCHK(hipMemcpyAsync(won, in->wall_on, (size_t)n * kMaxWalls, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(wxi, in->wall_xi, (size_t)n * kMaxWalls * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_contacts_import<T>(dyn[cur].pos, n, P.max_nbr, ids, xi, np, won, wxi, inv, cnt, carry, carry_meta, pr.wh,
+                              status, st);
+    HIPCHK(hipGetLastError());
+    TRY(rebuild_chain(1, true, true));
+    return sync();
+  }
+
   // dem_pairs through the device's static scratch: no device allocation.  The
   // pairs are copied into ij and sorted there, so ij must hold them all.
   int pairs_noalloc(uint32_t *ij, int64_t cap, int64_t *np) override {
@@ -821,8 +958,12 @@ struct Ctx final : dem_ctx {
     o->step_kernel_launches = cnt;
     o->step_block = step_block;
     o->step_xcd = step_xcd;
-    o->build_grid = build_grid;
+    o->build_grid = build_grid_now();
     o->check_period = check_period();
+    o->build_threads = build_threads(build_variant);
+    o->build_tile = build_tile(build_variant);
+    o->build_item_x = item_x;
+    o->tune_cached = tune_cached ? 1 : 0;
     return r;
   }
 
@@ -937,8 +1078,76 @@ struct Ctx final : dem_ctx {
   bool dep_after_graph = false, occ_after_graph = false;
   bool gprof = false;
 
+  // Autotuner cache: a JSON object whose members (one per line) map a key of
+  // the device architecture and the context's configuration to the chosen
+  // shapes.  Read and rewritten by dem_autotune when DEMRX_TUNE_CACHE names
+  // the file.
+  std::string tune_key() const {
+    std::string k = arch + "|n=" + std::to_string(n) + "|beds=" + std::to_string(hbd.size()) +
+                    "|fp=" + std::to_string((int)sizeof(T)) + "|cap=" + std::to_string(P.max_nbr) +
+                    "|skin=" + std::to_string(P.skin) + "|energy=" + std::to_string(P.energy_on);
+    for (const BedDev &d : hbd)
+      k += "|" + std::to_string(d.nd[0]) + "x" + std::to_string(d.nd[1]) + "x" + std::to_string(d.nd[2]);
+    return k;
+  }
+  static bool tune_field(const std::string &line, const char *name, int &v) {
+    const std::string f = std::string("\"") + name + "\":";
+    const size_t p = line.find(f);
+    return p != std::string::npos && std::sscanf(line.c_str() + p + f.size(), " %d", &v) == 1;
+  }
+  static std::vector<std::string> tune_lines(const char *path) {
+    std::vector<std::string> out;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return out;
+    char buf[4096];
+    while (std::fgets(buf, sizeof buf, f)) {
+      std::string l(buf);
+      while (!l.empty() && (l.back() == '\n' || l.back() == '\r' || l.back() == ',' || l.back() == ' ')) l.pop_back();
+      if (l.size() > 2 && l[0] == '"') out.push_back(l);
+    }
+    std::fclose(f);
+    return out;
+  }
+  bool tune_load(const char *path) {
+    const std::string key = "\"" + tune_key() + "\":";
+    for (const std::string &l : tune_lines(path)) {
+      if (l.compare(0, key.size(), key) != 0) continue;
+      int b, x, th, tl, ix;
+      if (!(tune_field(l, "step_block", b) && tune_field(l, "step_xcd", x) && tune_field(l, "build_threads", th) &&
+            tune_field(l, "build_tile", tl) && tune_field(l, "item_x", ix)))
+        return false;
+      if (set_launch(b, x, 0) != DEMRX_OK || set_build(th, tl, ix) != DEMRX_OK) return false;
+      return true;
+    }
+    return false;
+  }
+  void tune_store(const char *path) {
+    const std::string key = "\"" + tune_key() + "\":";
+    std::vector<std::string> keep;
+    for (const std::string &l : tune_lines(path))
+      if (l.compare(0, key.size(), key) != 0) keep.push_back(l);
+    keep.push_back(key + " {\"step_block\": " + std::to_string(step_block) + ", \"step_xcd\": " +
+                   std::to_string(step_xcd) + ", \"build_threads\": " + std::to_string(build_threads(build_variant)) +
+                   ", \"build_tile\": " + std::to_string(build_tile(build_variant)) +
+                   ", \"item_x\": " + std::to_string(item_x) + "}");
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    for (size_t q = 0; q < keep.size(); q++) std::fprintf(f, "%s%s\n", keep[q].c_str(), q + 1 < keep.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+  }
+
   int autotune(const dem_gas *g) override {
     if (!gas_ok(g)) return fail(DEMRX_EINVAL, "null gas field");
+    const char *cache = std::getenv("DEMRX_TUNE_CACHE");
+    if (cache && *cache && tune_load(cache)) {
+      tune_cached = true;
+      return DEMRX_OK;
+    }
+    tune_cached = false;
     TRY(ensure_lists());
     TRY(gas_table(g));
     hipEvent_t e0, e1;
@@ -966,38 +1175,64 @@ struct Ctx final : dem_ctx {
     }
     step_block = best_b;
     step_xcd = best_x;
-    // neighbour build: persistent grid size
+    // neighbour build: block size and LDS tile, item width (grid: resident
+    // blocks on every CU); each candidate times whole forced rebuild chains
     best = 1e30f;
-    int best_g = build_grid;
-    for (int gsz : {256, 512, 768, 1024, 2048}) {
-      build_grid = gsz;
-      float tot = 0.0f;
-      for (int rep = 0; rep < 3; rep++) {
-        HIPCHK(hipEventRecord(e0, st));
-        TRY(rebuild_chain(1, true));
-        HIPCHK(hipEventRecord(e1, st));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (rep) tot += ms;
+    int best_v = build_variant, best_w = item_x;
+    build_grid = 0;
+    for (int v = 0; v < kBuildVariants; v++) {
+      for (int wdt : kItemWidths) {
+        build_variant = v;
+        TRY(upload_items(wdt));
+        float tot = 0.0f;
+        for (int rep = 0; rep < 3; rep++) {
+          HIPCHK(hipEventRecord(e0, st));
+          TRY(rebuild_chain(1, true));
+          HIPCHK(hipEventRecord(e1, st));
+          HIPCHK(hipEventSynchronize(e1));
+          float ms = 0.0f;
+          HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+          if (rep) tot += ms;
+        }
+        if (tune_log)
+          std::fprintf(stderr, "[demrx] autotune build %d threads, tile %d, item %d cells (grid %d): %.1f us\n",
+                       build_threads(v), build_tile(v), wdt, build_grid_now(), tot / 2 * 1e3f);
+        if (tot < best) { best = tot; best_v = v; best_w = wdt; }
       }
-      if (tune_log) std::fprintf(stderr, "[demrx] autotune build grid %d: %.1f us\n", gsz, tot / 2 * 1e3f);
-      if (tot < best) { best = tot; best_g = gsz; }
     }
-    build_grid = best_g;
+    build_variant = best_v;
+    TRY(upload_items(best_w));
+    TRY(rebuild_chain(1, true));  // lists of the chosen shape (identical for every shape)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; gkey.clear(); }
-    return sync();
+    TRY(sync());
+    if (cache && *cache) tune_store(cache);
+    return DEMRX_OK;
   }
 
   int set_launch(int b, int x, int gsz) override {
-    if (!(b == 64 || b == 128 || b == 256 || b == 512) || x < 1 || x > 64 || gsz < 1 || gsz > 65536)
+    if (!(b == 64 || b == 128 || b == 256 || b == 512) || x < 1 || x > 64 || gsz < 0 || gsz > 65536)
       return fail(DEMRX_EINVAL, "launch shape out of range (step block 64/128/256/512, XCD chunk 1..64, "
-                                "build grid 1..65536)");
+                                "build grid 0..65536)");
     step_block = b;
     step_xcd = x;
     build_grid = gsz;
+    if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; gkey.clear(); }
+    return DEMRX_OK;
+  }
+
+  int set_build(int threads, int tile, int width) override {
+    int v = -1;
+    for (int q = 0; q < kBuildVariants; q++)
+      if (build_threads(q) == threads && build_tile(q) == tile) v = q;
+    bool wok = false;
+    for (int wdt : kItemWidths) wok |= wdt == width;
+    if (v < 0 || !wok)
+      return fail(DEMRX_EINVAL, "build shape not available (threads/tile 512/2048, 256/1024, 256/2048, "
+                                "1024/4096; item width 8, 16 or 32)");
+    build_variant = v;
+    if (width != item_x) TRY(upload_items(width));
     if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; gkey.clear(); }
     return DEMRX_OK;
   }
@@ -1120,6 +1355,11 @@ int dem_run(dem_ctx *c, int32_t n_int, int32_t S, const dem_gas *g, dem_sources 
 int dem_autotune(dem_ctx *c, const dem_gas *g) { return c ? c->autotune(g) : DEMRX_EINVAL; }
 int dem_set_launch(dem_ctx *c, int32_t step_block, int32_t step_xcd_chunk, int32_t build_grid) {
   return c ? c->set_launch(step_block, step_xcd_chunk, build_grid) : DEMRX_EINVAL;
+}
+int dem_get_contacts(dem_ctx *c, dem_contacts *io) { return c ? c->get_contacts(io) : DEMRX_EINVAL; }
+int dem_set_contacts(dem_ctx *c, const dem_contacts *in) { return c ? c->set_contacts(in) : DEMRX_EINVAL; }
+int dem_set_build(dem_ctx *c, int32_t threads, int32_t tile, int32_t item_x) {
+  return c ? c->set_build(threads, tile, item_x) : DEMRX_EINVAL;
 }
 int dem_profile(dem_ctx *c, int32_t enable) { return c ? c->profile(enable) : DEMRX_EINVAL; }
 int dem_sync(dem_ctx *c) { return c ? c->sync() : DEMRX_EINVAL; }

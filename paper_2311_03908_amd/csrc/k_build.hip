@@ -336,7 +336,7 @@ void launch_rebuild_check(const unsigned *dslot, int par_last, double skin, doub
 }
 
 // ------------------------------------------------------------------ work items
-__global__ void k_item_flags(const Item *items, int n_items, const BedDev *beds, const int32_t *start,
+__global__ void k_item_flags(const Item *items, int n_items, int item_x, const BedDev *beds, const int32_t *start,
                              int32_t *flags, const uint32_t *gate) {
   if (gated_off(gate)) return;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -347,7 +347,7 @@ __global__ void k_item_flags(const Item *items, int n_items, const BedDev *beds,
   }
   const Item it = items[t];
   const BedDev &B = beds[it.bed];
-  const int xe = min(it.x0 + kItemX, B.nd[0]);
+  const int xe = min(it.x0 + item_x, B.nd[0]);
   const int k0 = dem_key(B, it.x0, it.iy, it.iz);
   const int k1 = dem_key(B, xe - 1, it.iy, it.iz) + 1;
   flags[t] = start[k1] > start[k0] ? 1 : 0;
@@ -365,51 +365,54 @@ __global__ void k_item_compact(const int32_t *flags, const int32_t *offs, int n_
   if (flags[t]) list[offs[t]] = t;
 }
 
-void launch_items(const Item *items, int n_items, const BedDev *beds, const int32_t *start, int32_t *flags,
+void launch_items(const Item *items, int n_items, int item_x, const BedDev *beds, const int32_t *start, int32_t *flags,
                   int32_t *offs, int32_t *scratch, int32_t *list, int32_t *count, hipStream_t s,
                   const uint32_t *gate) {
-  k_item_flags<<<(n_items + 256) / 256, 256, 0, s>>>(items, n_items, beds, start, flags, gate);
+  k_item_flags<<<(n_items + 256) / 256, 256, 0, s>>>(items, n_items, item_x, beds, start, flags, gate);
   launch_scan(flags, offs, n_items + 1, scratch, s, gate);
   k_item_compact<<<(n_items + 256) / 256, 256, 0, s>>>(flags, offs, n_items, list, count, gate);
 }
 
 // ------------------------------------------------------------------ neighbour build
-// Work item: kItemX consecutive DEM cells of one row of a bed.  The nine rows
-// of its 3x3 (y, z) stencil, each spanning x0-1 .. x0+kItemX, are staged in
-// LDS (FP32 positions relative to the item corner, radii, sorted indices,
-// original ids) as many rows at a time as fit; every thread owns one centre
-// parcel of the item and tests the 3 cells of each staged row around its own
-// cell, keeping the candidates closer than r_i + r_j + skin (conservative FP32
-// test; the exact contact test runs every step).
+// Work item: `item_x` consecutive DEM cells of one row of a bed, whose
+// parcels are the block's centre parcels (one per thread, in passes of
+// kThreads).  The nine rows of the item's 3x3 (y, z) stencil, each spanning
+// the cells x0-1 .. x0+item_x, are staged in LDS as FP32 positions (relative
+// to a corner near the item) with the radius.  The cells of a bed row have
+// consecutive keys (one key tile per bed plane), so a stencil row is one run
+// of the sorted order; a run longer than the tile is cut into segments, and
+// as many consecutive segments as fit are staged at a time.  Every segment
+// is sorted by x, so each thread bisects for the first candidate with
+// x_j >= x_i - w and scans up to the first with x_j > x_i + w, where
+// w = r_i + skin + r_max, keeping the candidates closer than
+// r_i + r_j + skin (a conservative FP32 test; the exact contact test runs
+// every step).
 //
 // The list has two regions so that the step visits contacts in lockstep rows:
 // candidates that touch now (FP32 test with a 1e-4 margin, a superset of the
 // exact contacts) fill slots cap-1, cap-2, ... downwards, the others fill
-// slots 0, 1, ... upwards; cnt packs (near << 16) | far.  The tangential
-// springs of partners in contact before the rebuild, compacted by k_carry,
-// are carried over to the near slots by matching original ids, which every
-// spring record carries (read into registers for up to kCarry old contacts;
-// more fall back to a loop).
-constexpr int kCandMax = 2048;
-constexpr int kBuildThreads = 512;
-constexpr int kCarry = 8;  // 78 VGPRs: three 512-thread blocks per CU
+// slots 0, 1, ... upwards; cnt packs (near << 16) | far.  After the scan the
+// tangential springs of partners in contact before the rebuild (compacted by
+// k_carry) are carried over to the near slots by matching original ids,
+// which every spring record carries; keeping that match out of the scan
+// keeps the scan's per-candidate work small.
 constexpr float kNear = 1.0f + 1e-4f;
+constexpr int kCarry = 8;     // old contacts held in registers; more are matched by a loop
+constexpr int kMaxSeg = 64;   // staged segments per item
 
-template <typename T>
-__global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
+template <typename T, int kThreads, int kTile>
+__global__ void __launch_bounds__(kThreads) k_build_nbr(NbrBuild<T> a) {
   if (gated_off(a.gate)) return;
-  __shared__ float4 cpos[kCandMax];
-  __shared__ int cidx[kCandMax];
-  __shared__ uint32_t cid[kCandMax];
-  // each stencil row is staged from up to three runs of keys: the halo cell
-  // left of the item, the item's own cells, the halo cell right of it
-  __shared__ int sst[9][3], sln[9][3];
-  __shared__ int roff[10];
+  __shared__ float4 cpos[kTile];
+  // segments: global start, length, stencil row; staged offset of each
+  // segment of the current pass
+  __shared__ int sg_start[kMaxSeg], sg_len[kMaxSeg], sg_row[kMaxSeg], sg_off[kMaxSeg + 1];
+  __shared__ int n_seg, cen0, cen1, w_next;
   const int n_list = *a.list_count;
   const long N = a.n;
+  const int cap = a.cap;
   const float cut_scale = 1.0f + 1e-5f;
   const int tid = threadIdx.x;
-  __shared__ int w_next;
   // blocks take work items from a queue (counter zeroed before the launch),
   // so that items of uneven cost balance over the persistent grid
   for (;;) {
@@ -420,39 +423,48 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
     if (w >= n_list) break;
     const Item it = a.items[a.list[w]];
     const BedDev &B = a.beds[it.bed];
-    const int xc = min(kItemX, B.nd[0] - it.x0);
-    __syncthreads();
-    if (tid < 27) {
-      const int r = tid / 3, k = tid % 3;
-      const int iy2 = it.iy + (r % 3) - 1, iz2 = it.iz + (r / 3) - 1;
-      const int xl = k == 0 ? it.x0 - 1 : (k == 1 ? it.x0 : it.x0 + xc);
-      const int xh = k == 1 ? it.x0 + xc - 1 : xl;
-      int s0 = 0, ln = 0;
-      if (iy2 >= 0 && iy2 < B.nd[1] && iz2 >= 0 && iz2 < B.nd[2] && xl >= 0 && xh < B.nd[0]) {
-        s0 = a.start[dem_key(B, xl, iy2, iz2)];
-        ln = a.start[dem_key(B, xh, iy2, iz2) + 1] - s0;
+    const int xc = min(a.item_x, B.nd[0] - it.x0);
+    if (tid == 0) {
+      int ns = 0;
+      for (int r = 0; r < 9; r++) {
+        const int iy2 = it.iy + (r % 3) - 1, iz2 = it.iz + (r / 3) - 1;
+        if (iy2 < 0 || iy2 >= B.nd[1] || iz2 < 0 || iz2 >= B.nd[2]) continue;
+        const int xl = max(it.x0 - 1, 0), xh = min(it.x0 + xc, B.nd[0] - 1);
+        int s0 = a.start[dem_key(B, xl, iy2, iz2)];
+        const int s1 = a.start[dem_key(B, xh, iy2, iz2) + 1];
+        if (r == 4) {
+          cen0 = a.start[dem_key(B, it.x0, iy2, iz2)];
+          cen1 = a.start[dem_key(B, it.x0 + xc - 1, iy2, iz2) + 1];
+        }
+        while (s0 < s1) {
+          if (ns == kMaxSeg) {
+            atomicOr(a.status, ST_OVERFLOW);
+            break;
+          }
+          const int ln = min(s1 - s0, kTile);
+          sg_start[ns] = s0;
+          sg_len[ns] = ln;
+          sg_row[ns] = r;
+          ns++;
+          s0 += ln;
+        }
       }
-      sst[r][k] = s0;
-      sln[r][k] = ln;
+      n_seg = ns;
     }
     __syncthreads();
-    const int c0 = sst[4][1], c1 = c0 + sln[4][1];
-    const double xr = B.origin[0] + it.x0 * B.hd, yr = B.origin[1] + it.iy * B.hd, zr = B.origin[2] + it.iz * B.hd;
-    for (int cb = c0; cb < c1; cb += blockDim.x) {
+    const int ns = n_seg, c0 = cen0, c1 = cen1;
+    // FP32 coordinates relative to the corner of the aligned run of kItemXMax
+    // cells holding the item (and to the item's own cell in y and z): the
+    // same values, hence the same lists, for every item width
+    const double xr = B.origin[0] + (it.x0 / kItemXMax) * kItemXMax * B.hd, yr = B.origin[1] + it.iy * B.hd,
+                 zr = B.origin[2] + it.iz * B.hd;
+    for (int cb = c0; cb < c1; cb += kThreads) {
       const int i = cb + tid;
       const bool mine = i < c1;
-      float xi = 0.f, yi = 0.f, zi = 0.f, rs = 0.f, ri = 0.f;
+      float xi = 0.f, yi = 0.f, zi = 0.f, rs = 0.f, ri = 0.f, cut_hi = 0.f;
       int nn = 0, nf = 0;  // near / far candidates written
       bool over = false;
-      float cut_hi = 0.f;
-      // partners in contact before the rebuild: original ids of the first
-      // kCarry carried springs (the rest are matched by a loop)
-      uint32_t oid[kCarry];
-      int po = 0, n_old = 0;
-      uint32_t wallbits = 0;
-      uint64_t newbits = 0;
-#pragma unroll
-      for (int k = 0; k < kCarry; k++) oid[k] = 0xffffffffu;
+      int32_t *pnear = a.nb.idx + (long)(cap - 1) * N + i, *pfar = a.nb.idx + i;  // next near / far slot
       if (mine) {
         const PosRec pi = load_pos(a.d.pos, i);
         xi = (float)(pi.x - xr);
@@ -462,65 +474,45 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
         rs = pi.r + (float)a.skin;
         // widest candidate distance along x for this centre
         cut_hi = (rs + (float)B.rmax) * cut_scale + 1e-9f;
-        po = a.perm[i];
-        const uint32_t meta = a.carry_meta[po];
-        n_old = (int)(meta & 0xffffu);
-        wallbits = meta >> 16;
-#pragma unroll
-        for (int k = 0; k < kCarry; k++)
-          if (k < n_old) oid[k] = spring_partner(a.carry[(long)k * N + po].w);
       }
-      int row = 0;
-      while (row < 9) {
-        // as many consecutive rows as fit in LDS
-        int re = row, tot = 0;
-        while (re < 9) {
-          const int len = sln[re][0] + sln[re][1] + sln[re][2];
-          if (tot + len > kCandMax) break;
-          tot += len;
-          re++;
-        }
-        if (re == row) {  // one row alone exceeds the tile
-          if (tid == 0) atomicOr(a.status, ST_OVERFLOW);
-          row++;
-          continue;
-        }
-        __syncthreads();
+      int sg = 0;
+      while (sg < ns) {
+        // as many consecutive segments as fit in the tile (each fits alone)
+        int se = sg, tot = 0;
+        while (se < ns && tot + sg_len[se] <= kTile) tot += sg_len[se++];
+        __syncthreads();  // the previous pass's readers are done with the tile
         if (tid == 0) {
           int o = 0;
-          for (int r = row; r < re; r++) {
-            roff[r] = o;
-            o += sln[r][0] + sln[r][1] + sln[r][2];
+          for (int q = sg; q < se; q++) {
+            sg_off[q] = o;
+            o += sg_len[q];
           }
-          roff[re] = o;
+          sg_off[se] = o;
         }
         __syncthreads();
-        for (int t = tid; t < tot; t += blockDim.x) {
-          int r = row;
-          while (r + 1 < re && roff[r + 1] <= t) r++;
-          const int o = t - roff[r];
-          const int j = o < sln[r][0] ? sst[r][0] + o
-                                      : (o < sln[r][0] + sln[r][1] ? sst[r][1] + (o - sln[r][0])
-                                                                   : sst[r][2] + (o - sln[r][0] - sln[r][1]));
-          const PosRec pj = load_pos(a.d.pos, j);
+        for (int t = tid; t < tot; t += kThreads) {
+          int q = sg;
+          while (q + 1 < se && sg_off[q + 1] <= t) q++;
+          const PosRec pj = load_pos(a.d.pos, sg_start[q] + (t - sg_off[q]));
           cpos[t] = make_float4((float)(pj.x - xr), (float)(pj.y - yr), (float)(pj.z - zr), pj.r);
-          cidx[t] = j;
-          cid[t] = pj.id;
         }
         __syncthreads();
         if (mine) {
-          for (int r = row; r < re; r++) {
-            // the staged row is sorted by x: bisect the window |x_j - x_i| < cut_hi
-            int lo = roff[r], hi = roff[r + 1];
+          for (int q = sg; q < se; q++) {
+            const int b0 = sg_off[q], b1 = sg_off[q + 1];
+            const int jb = sg_start[q] - b0;  // staged slot t holds parcel jb + t
+            const int self = (i >= sg_start[q] && i < sg_start[q] + sg_len[q]) ? i - jb : -1;
+            // the segment is sorted by x: bisect the window |x_j - x_i| <= cut_hi
+            int lo = b0, hi = b1;
             {
-              int a0 = lo, a1 = hi;
+              int a0 = b0, a1 = b1;
               const float xl = xi - cut_hi;
               while (a0 < a1) {
                 const int mid = (a0 + a1) >> 1;
                 if (cpos[mid].x < xl) a0 = mid + 1; else a1 = mid;
               }
               lo = a0;
-              a1 = hi;
+              a1 = b1;
               const float xh = xi + cut_hi;
               while (a0 < a1) {
                 const int mid = (a0 + a1) >> 1;
@@ -528,54 +520,122 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_nbr(NbrBuild<T> a) {
               }
               hi = a0;
             }
-            for (int q = lo; q < hi; q++) {
-              const float4 c = cpos[q];
-              const float dx = c.x - xi, dy = c.y - yi, dz = c.z - zi;
-              const float cut = (rs + c.w) * cut_scale;
-              const int j = cidx[q];
-              const float d2 = dx * dx + dy * dy + dz * dz;
-              if (j == i || !(d2 < cut * cut)) continue;
-              const float sn = (ri + c.w) * kNear;
-              if (nn + nf >= a.cap) {
-                over = true;
-              } else if (d2 < sn * sn) {
-                {
-                  const int sl = a.cap - 1 - nn;
-                  a.nb.idx[(long)sl * N + i] = j;
-                  const uint32_t idn = cid[q];
-                  int qo = -1;
+            // four candidates per trip, all read before any is tested; the
+            // list rows are written through running pointers
+            for (int t = lo; t < hi; t += 4) {
+              float4 c[4];
 #pragma unroll
-                  for (int k = 0; k < kCarry; k++)
-                    if (oid[k] == idn) qo = k;
-                  for (int k = kCarry; k < n_old && qo < 0; k++)
-                    if (spring_partner(a.carry[(long)k * N + po].w) == idn) qo = k;
-                  if (qo >= 0) {
-                    a.nb.hist[(long)sl * N + i] = a.carry[(long)qo * N + po];
-                    newbits |= 1ull << sl;
+              for (int k = 0; k < 4; k++) c[k] = cpos[min(t + k, kTile - 1)];
+#pragma unroll
+              for (int k = 0; k < 4; k++) {
+                const float dx = c[k].x - xi, dy = c[k].y - yi, dz = c[k].z - zi;
+                const float cut = (rs + c[k].w) * cut_scale;
+                const float d2 = dx * dx + dy * dy + dz * dz;
+                if (t + k < hi && d2 < cut * cut && t + k != self) {
+                  const float sn = (ri + c[k].w) * kNear;
+                  if (nn + nf >= cap) {
+                    over = true;
+                  } else if (d2 < sn * sn) {
+                    *pnear = jb + t + k;
+                    pnear -= N;
+                    nn++;
+                  } else {
+                    *pfar = jb + t + k;
+                    pfar += N;
+                    nf++;
                   }
                 }
-                nn++;
-              } else {
-                a.nb.idx[(long)nf * N + i] = j;
-                nf++;
               }
             }
           }
         }
-        row = re;
+        sg = se;
       }
       if (mine) {
+        // springs of the old contacts that are near candidates again
+        const int po = a.perm[i];
+        const uint32_t meta = a.carry_meta[po];
+        const int n_old = (int)(meta & 0xffffu);
+        uint64_t newbits = 0;
+        if (n_old > 0 && nn > 0) {
+          uint32_t oid[kCarry];
+#pragma unroll
+          for (int k = 0; k < kCarry; k++)
+            oid[k] = k < n_old ? spring_partner(a.carry[(long)k * N + po].w) : 0xffffffffu;
+          for (int k0 = 0; k0 < nn; k0 += 4) {
+            int jj[4];
+            uint32_t idn[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) jj[u] = k0 + u < nn ? a.nb.idx[(long)(cap - 1 - k0 - u) * N + i] : -1;
+#pragma unroll
+            for (int u = 0; u < 4; u++) idn[u] = jj[u] >= 0 ? a.d.pos[jj[u]].id : 0xffffffffu;
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+              if (jj[u] < 0) continue;
+              int qo = -1;
+#pragma unroll
+              for (int k = 0; k < kCarry; k++)
+                if (oid[k] == idn[u]) qo = k;
+              for (int k = kCarry; k < n_old && qo < 0; k++)
+                if (spring_partner(a.carry[(long)k * N + po].w) == idn[u]) qo = k;
+              if (qo >= 0) {
+                const int sl = cap - 1 - k0 - u;
+                a.nb.hist[(long)sl * N + i] = a.carry[(long)qo * N + po];
+                newbits |= 1ull << sl;
+              }
+            }
+          }
+        }
         if (over) atomicOr(a.status, ST_OVERFLOW);
         a.nb.cnt[i] = (nn << 16) | nf;
-        a.nb.mask[i] = newbits | ((uint64_t)wallbits << kWallBit);
+        a.nb.mask[i] = newbits | ((uint64_t)(meta >> 16) << kWallBit);
       }
     }
   }
 }
 
+// block size and LDS tile (candidates) of each build variant
+struct BuildShape {
+  int threads, tile;
+};
+constexpr BuildShape kBuildShapes[kBuildVariants] = {{512, 2048}, {256, 1024}, {256, 2048}, {1024, 4096}};
+
+template <typename T, int V>
+static void launch_build_v(const NbrBuild<T> &a, int grid, hipStream_t s) {
+  constexpr BuildShape sh = kBuildShapes[V];
+  k_build_nbr<T, sh.threads, sh.tile><<<grid, sh.threads, 0, s>>>(a);
+}
+template <typename T, int V>
+static int build_blocks_v() {
+  constexpr BuildShape sh = kBuildShapes[V];
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_build_nbr<T, sh.threads, sh.tile>, sh.threads, 0) !=
+      hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+int build_threads(int variant) { return kBuildShapes[variant].threads; }
+int build_tile(int variant) { return kBuildShapes[variant].tile; }
+
 template <typename T>
-void launch_build_nbr(const NbrBuild<T> &a, int grid, hipStream_t s) {
-  k_build_nbr<T><<<grid, kBuildThreads, 0, s>>>(a);
+int build_blocks_per_cu(int variant) {
+  switch (variant) {
+    case 0: return build_blocks_v<T, 0>();
+    case 1: return build_blocks_v<T, 1>();
+    case 2: return build_blocks_v<T, 2>();
+    default: return build_blocks_v<T, 3>();
+  }
+}
+
+template <typename T>
+void launch_build_nbr(const NbrBuild<T> &a, int variant, int grid, hipStream_t s) {
+  switch (variant) {
+    case 0: launch_build_v<T, 0>(a, grid, s); break;
+    case 1: launch_build_v<T, 1>(a, grid, s); break;
+    case 2: launch_build_v<T, 2>(a, grid, s); break;
+    default: launch_build_v<T, 3>(a, grid, s); break;
+  }
 }
 
 // ------------------------------------------------------------------ pairs
@@ -608,13 +668,121 @@ void launch_pairs(const Dyn<T> &d, const Props<T> &p, const Nbr<T> &nb, int n, i
   k_pairs<T><<<(n + 255) / 256, 256, 0, s>>>(d, p, nb, n, cap_slots, out, cap, count);
 }
 
+// ------------------------------------------------------------------ contact history
+// Export: one record per pair in contact at the last step, taken from the side
+// with the lower original id (both sides hold the same spring, in the
+// orientation with the normal from the lower to the higher id), and every
+// parcel's wall springs by original id.
+template <typename T>
+__global__ void k_contacts_export(const PosRec *pos, Nbr<T> nb, const T *wh, int n, int cap_slots, uint32_t *ids,
+                                  double *xi, long cap, unsigned long long *count, uint8_t *wall_on,
+                                  double *wall_xi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const long N = n;
+  const PosRec a = load_pos(pos, i);
+  const uint64_t m = nb.mask[i];
+  const int cw = nb.cnt[i], c_near = cw >> 16, c_far = cw & 0xffff;
+  for (int v = 0; v < c_near + c_far; v++) {
+    const int s = v < c_near ? cap_slots - 1 - v : v - c_near;
+    if (!((m >> s) & 1ull)) continue;
+    const int j = nb.idx[(long)s * N + i];
+    const uint32_t bid = pos[j].id;
+    if (bid <= a.id) continue;
+    const Spring<T> h = nb.hist[(long)s * N + i];
+    const unsigned long long k = atomicAdd(count, 1ull);
+    if ((long)k < cap) {
+      ids[2 * k] = a.id;
+      ids[2 * k + 1] = bid;
+      xi[3 * k] = (double)h.x;
+      xi[3 * k + 1] = (double)h.y;
+      xi[3 * k + 2] = (double)h.z;
+    }
+  }
+  for (int w = 0; w < kMaxWalls; w++) {
+    const bool on = (m >> (kWallBit + w)) & 1ull;
+    wall_on[(long)a.id * kMaxWalls + w] = on ? 1 : 0;
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+      wall_xi[((long)a.id * kMaxWalls + w) * 3 + c] = on ? (double)wh[(long)(w * 3 + c) * N + a.id] : 0.0;
+  }
+}
+
+__global__ void k_inverse_ids(const PosRec *pos, int n, int32_t *inv) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) inv[pos[p].id] = p;
+}
+
+// Import: each pair's spring goes to both partners' carry rows (the partner's
+// id in the fourth component, the orientation unchanged), as launch_carry
+// leaves them before a rebuild; the next build copies them to the pairs'
+// near slots.  Row order within a parcel does not matter (the build matches
+// by id).
+template <typename T>
+__global__ void k_contacts_import(const uint32_t *ids, const double *xi, long np, const int32_t *inv, int n,
+                                  int cap_slots, Spring<T> *carry, uint32_t *cnt, uint32_t *status) {
+  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= np) return;
+  const long N = n;
+  const uint32_t ia = ids[2 * q], ib = ids[2 * q + 1];
+  const int pa = inv[ia], pb = inv[ib];
+  const T x = T(xi[3 * q]), y = T(xi[3 * q + 1]), z = T(xi[3 * q + 2]);
+  const uint32_t ka = atomicAdd(cnt + pa, 1u), kb = atomicAdd(cnt + pb, 1u);
+  if ((int)ka < cap_slots) carry[(long)ka * N + pa] = Spring<T>{x, y, z, spring_tag<T>(ib)};
+  if ((int)kb < cap_slots) carry[(long)kb * N + pb] = Spring<T>{x, y, z, spring_tag<T>(ia)};
+  if ((int)ka >= cap_slots || (int)kb >= cap_slots) atomicOr(status, ST_OVERFLOW);
+}
+
+template <typename T>
+__global__ void k_walls_import(const PosRec *pos, int n, int cap_slots, const uint8_t *wall_on, const double *wall_xi,
+                               T *wh, const uint32_t *cnt, uint32_t *carry_meta) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const long N = n;
+  const uint32_t id = pos[p].id;
+  uint32_t bits = 0;
+  for (int w = 0; w < kMaxWalls; w++) {
+    const bool on = wall_on[(long)id * kMaxWalls + w] != 0;
+    if (on) bits |= 1u << w;
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+      wh[(long)(w * 3 + c) * N + id] = on ? T(wall_xi[((long)id * kMaxWalls + w) * 3 + c]) : T(0);
+  }
+  carry_meta[p] = (bits << 16) | min(cnt[p], (uint32_t)cap_slots);
+}
+
+template <typename T>
+void launch_contacts_export(const PosRec *pos, const Nbr<T> &nb, const T *wh, int n, int cap_slots, uint32_t *ids,
+                            double *xi, long cap, unsigned long long *count, uint8_t *wall_on, double *wall_xi,
+                            hipStream_t s) {
+  k_contacts_export<T><<<(n + 255) / 256, 256, 0, s>>>(pos, nb, wh, n, cap_slots, ids, xi, cap, count, wall_on,
+                                                       wall_xi);
+}
+template <typename T>
+void launch_contacts_import(const PosRec *pos, int n, int cap_slots, const uint32_t *ids, const double *xi, long np,
+                            const uint8_t *wall_on, const double *wall_xi, int32_t *inv, uint32_t *cnt,
+                            Spring<T> *carry, uint32_t *carry_meta, T *wh, uint32_t *status, hipStream_t s) {
+  k_inverse_ids<<<(n + 255) / 256, 256, 0, s>>>(pos, n, inv);
+  launch_fill_u32(cnt, 0u, n, s);
+  if (np > 0)
+    k_contacts_import<T><<<(unsigned)((np + 255) / 256), 256, 0, s>>>(ids, xi, np, inv, n, cap_slots, carry, cnt,
+                                                                     status);
+  k_walls_import<T><<<(n + 255) / 256, 256, 0, s>>>(pos, n, cap_slots, wall_on, wall_xi, wh, cnt, carry_meta);
+}
+
 #define INST(T)                                                                                                   \
   template void launch_bin<T>(const Dyn<T> &, const Props<T> &, const BedDev *, int, int32_t *, int32_t *,       \
                               int32_t *, uint32_t *, hipStream_t, const uint32_t *);                              \
   template void launch_permute<T>(const int32_t *, int, const Dyn<T> &, const Props<T> &, const Dyn<T> &,        \
                                   const Props<T> &, float4 *, unsigned *, hipStream_t, const uint32_t *);        \
   template void launch_carry<T>(const Nbr<T> &, int, Spring<T> *, uint32_t *, hipStream_t, const uint32_t *);    \
-  template void launch_build_nbr<T>(const NbrBuild<T> &, int, hipStream_t);                                      \
+  template void launch_build_nbr<T>(const NbrBuild<T> &, int, int, hipStream_t);                 \
+  template int build_blocks_per_cu<T>(int);                                                                       \
+  template void launch_contacts_export<T>(const PosRec *, const Nbr<T> &, const T *, int, int, uint32_t *, double *, \
+                                          long, unsigned long long *, uint8_t *, double *, hipStream_t);           \
+  template void launch_contacts_import<T>(const PosRec *, int, int, const uint32_t *, const double *, long,          \
+                                          const uint8_t *, const double *, int32_t *, uint32_t *, Spring<T> *,     \
+                                          uint32_t *, T *, uint32_t *, hipStream_t);                                      \
   template void launch_pairs<T>(const Dyn<T> &, const Props<T> &, const Nbr<T> &, int, int, uint32_t *, long,         \
                                 unsigned long long *, hipStream_t);
 INST(float)

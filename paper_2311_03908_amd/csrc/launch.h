@@ -8,10 +8,12 @@
 namespace demrx {
 
 // ---------------------------------------------------------------- k_build.hip
-struct Item {  // a run of up to kItemX DEM cells along x in one (y, z) row of a bed
+struct Item {  // a run of up to item_x DEM cells along x in one (y, z) row of a bed
   int bed, x0, iy, iz;
 };
-constexpr int kItemX = 16;
+// item widths (DEM cells along x) the neighbour build can run with
+constexpr int kItemWidths[3] = {8, 16, 32};
+constexpr int kItemXMax = 32;
 // per-step maxima and counts are gathered in kSlots padded slots (128 bytes
 // apart) by per-wave atomics, and summed by their readers
 constexpr int kSlots = 64, kSlotPad = 32, kSlotPad64 = 16;
@@ -51,7 +53,7 @@ void launch_carry(const Nbr<T> &nb, int n, Spring<T> *carry, uint32_t *carry_met
 // set *flag when the lists could go stale within `horizon` steps (or force)
 void launch_rebuild_check(const unsigned *dslot, int par_last, double skin, double dt, int horizon, int force,
                           uint32_t *flag, unsigned long long *count, hipStream_t s);
-void launch_items(const Item *items, int n_items, const BedDev *beds, const int32_t *start, int32_t *flags,
+void launch_items(const Item *items, int n_items, int item_x, const BedDev *beds, const int32_t *start, int32_t *flags,
                   int32_t *offs, int32_t *scratch, int32_t *list, int32_t *count, hipStream_t s,
                   const uint32_t *gate);
 
@@ -70,15 +72,34 @@ struct NbrBuild {
   const int32_t *list, *list_count;
   int32_t *queue;  // work-item counter, zero at launch
   int n, cap;
+  int item_x;      // DEM cells per work item (the width the items were made with)
   double skin;
   uint32_t *status;
 };
+// build variants: block size and LDS tile (candidate records staged at a time)
+constexpr int kBuildVariants = 4;
+int build_threads(int variant);
+int build_tile(int variant);
 template <typename T>
-void launch_build_nbr(const NbrBuild<T> &a, int grid, hipStream_t s);
+int build_blocks_per_cu(int variant);  // resident blocks per CU (occupancy query)
+template <typename T>
+void launch_build_nbr(const NbrBuild<T> &a, int variant, int grid, hipStream_t s);
 
 template <typename T>
 void launch_pairs(const Dyn<T> &d, const Props<T> &p, const Nbr<T> &nb, int n, int cap_slots, uint32_t *out, long cap,
                   unsigned long long *count, hipStream_t s);
+
+// contact history for checkpoints: export (pairs in contact, a < b, and
+// wall springs by original id) and import into the carry buffer of the next
+// rebuild (inv, cnt: n ints of scratch)
+template <typename T>
+void launch_contacts_export(const PosRec *pos, const Nbr<T> &nb, const T *wh, int n, int cap_slots, uint32_t *ids,
+                            double *xi, long cap, unsigned long long *count, uint8_t *wall_on, double *wall_xi,
+                            hipStream_t s);
+template <typename T>
+void launch_contacts_import(const PosRec *pos, int n, int cap_slots, const uint32_t *ids, const double *xi, long np,
+                            const uint8_t *wall_on, const double *wall_xi, int32_t *inv, uint32_t *cnt,
+                            Spring<T> *carry, uint32_t *carry_meta, T *wh, uint32_t *status, hipStream_t s);
 
 // ---------------------------------------------------------------- k_step.hip
 template <typename T>

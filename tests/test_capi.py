@@ -37,7 +37,7 @@ def test_struct_layouts_match_header_sizes():
     assert C.sizeof(capi.DemParcels) == 18 * 8
     assert C.sizeof(capi.DemGas) == 11 * 8
     assert C.sizeof(capi.DemSources) == 15 * 8
-    assert C.sizeof(capi.DemStats) == 6 * 8 + 8 + 4 + 4 + 8 + 8 + 4 * 4
+    assert C.sizeof(capi.DemStats) == 6 * 8 + 8 + 4 + 4 + 8 + 8 + 8 * 4
 
 
 def test_host_validation_rejects_null_and_bad_arguments():
@@ -61,6 +61,7 @@ def test_host_validation_rejects_null_and_bad_arguments():
     assert L.dem_gas_momentum(None, 1e-4, None, None, None, None, None, None, None, None) == -1
     assert L.dem_react(None, 1e-4, None, None, None, None) == -1
     assert L.dem_set_launch(None, 64, 1, 1024) == -1
+    assert L.dem_set_build(None, 512, 2048, 16) == -1
 
 
 def test_bad_grid_rejected_on_host():

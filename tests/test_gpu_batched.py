@@ -2,6 +2,7 @@
 bit for bit, what each bed gives in a context of its own (per-parcel state,
 per-cell sources, bed-mean reduction degree), through the graph-replayed
 coupling intervals."""
+import json
 import sys
 
 import numpy as np
@@ -77,34 +78,81 @@ def test_empty_bed_in_a_batch():
 
 @pytest.mark.parametrize("case", ["mixed_batch", "fp64_box"])
 def test_results_do_not_depend_on_launch_shapes(case):
-    """Two contexts on the same beds, one in the smallest and one in the
-    largest launch shapes (dem_set_launch), step bit-identically through
-    graph-replayed coupling intervals with neighbour rebuilds; out-of-range
-    shapes are rejected and leave the context usable."""
+    """Contexts on the same beds in different launch shapes (dem_set_launch:
+    step block, XCD chunk, build grid; dem_set_build: build block size, LDS
+    tile, work-item width) step bit-identically through graph-replayed
+    coupling intervals with neighbour rebuilds; out-of-range shapes are
+    rejected and leave the context usable."""
     if case == "mixed_batch":
         w = W.with_velocities(W.squeeze(W.cfg5(n_beds=4, n_scale=0.05, seed=93), 0.97, 0), 93)
     else:
         w = W.with_velocities(W.squeeze(W.cfg1(), 0.995, 0), 94, vscale=0.05, wscale=20.0)
     _say(f"[launch] {case}: {len(w.beds)} beds, {w.n} parcels")
     out = []
-    for shape in ((64, 1, 1), (512, 64, 2048)):
+    shapes = (((64, 1, 1), (256, 1024, 8)), ((512, 64, 2048), (1024, 4096, 32)), ((128, 4, 0), (512, 2048, 16)),
+              ((256, 16, 0), (256, 2048, 32)))
+    for launch, build in shapes:
         bed = Bed(w)
-        bed.set_launch(*shape)
+        bed.set_launch(*launch)
+        bed.set_build(*build)
         o = bed.run(3, 20, sources=True, bed_fov=True)
+        st = bed.stats()
+        assert (st["build_threads"], st["build_tile"], st["build_item_x"]) == build
         out.append((bed.state(), o, bed.pairs()))
         bed.close()
-    (s0, o0, p0), (s1, o1, p1) = out
-    assert np.array_equal(p0, p1) and len(p0) > 0
-    for k in s0:
-        assert torch.equal(s0[k], s1[k]), k
-    for k in o0:
-        if k == "bed_fov":
-            assert np.array_equal(o0[k], o1[k])
-        else:
-            assert torch.equal(o0[k], o1[k]), k
+    s0, o0, p0 = out[0]
+    assert len(p0) > 0
+    for s1, o1, p1 in out[1:]:
+        assert np.array_equal(p0, p1)
+        for k in s0:
+            assert torch.equal(s0[k], s1[k]), k
+        for k in o0:
+            if k == "bed_fov":
+                assert np.array_equal(o0[k], o1[k])
+            else:
+                assert torch.equal(o0[k], o1[k]), k
     bed = Bed(w)
-    for bad in ((96, 1, 1), (64, 0, 1), (64, 65, 1), (64, 1, 0)):
+    for bad in ((96, 1, 1), (64, 0, 1), (64, 65, 1), (64, 1, -1)):
         with pytest.raises(Exception):
             bed.set_launch(*bad)
+    for bad in ((512, 1024, 16), (512, 2048, 12), (128, 2048, 16)):
+        with pytest.raises(Exception):
+            bed.set_build(*bad)
     bed.run(1, 20)
     bed.close()
+
+
+def test_autotuner_cache_keyed_by_arch_and_config(tmp_path, monkeypatch):
+    """dem_autotune with DEMRX_TUNE_CACHE: the first context times the
+    candidates and stores its choice under the key of the device architecture
+    and configuration; a second context of the same configuration applies the
+    stored shapes without timing; another configuration is tuned anew."""
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("DEMRX_TUNE_CACHE", str(path))
+    shape_keys = ("step_block", "step_xcd", "build_threads", "build_tile", "build_item_x")
+    w = W.with_velocities(W.squeeze(W.cfg1(), 0.995, 0), 95)
+    _say(f"[tune] {w.n} parcels")
+    a = Bed(w)
+    a.autotune()
+    sa = a.stats()
+    a.close()
+    assert sa["tune_cached"] == 0
+    doc = json.loads(path.read_text())
+    assert len(doc) == 1
+    (key, val), = doc.items()
+    assert key.startswith("gfx") and f"|n={w.n}|" in key
+    assert (val["step_block"], val["step_xcd"], val["build_threads"], val["build_tile"], val["item_x"]) == \
+        tuple(sa[k] for k in shape_keys)
+    b = Bed(w)
+    b.autotune()
+    sb = b.stats()
+    b.run(2, 20)
+    b.close()
+    assert sb["tune_cached"] == 1
+    assert all(sb[k] == sa[k] for k in shape_keys)
+    w2 = W.with_velocities(W.cfg5(n_beds=2, n_scale=0.05, seed=96), 96)
+    c = Bed(w2)
+    c.autotune()
+    assert c.stats()["tune_cached"] == 0
+    c.close()
+    assert len(json.loads(path.read_text())) == 2
