@@ -172,6 +172,7 @@ struct Ctx final : dem_ctx {
   T *gtab = nullptr;
   ThermoTab *thermo = nullptr;    // energy equation only
   const double *gas_T = nullptr;  // gas temperature of the last gas table (energy equation)
+  double *rtab = nullptr;  // per-cell reaction quantities (launch_react_table)
   double *eps = nullptr, *pm = nullptr, *pw = nullptr, *bed_fov_d = nullptr, *theta_d = nullptr;
   uint32_t *status = nullptr;
   void *scratch_ptr = nullptr;       // this device's static scratch (dem_pairs_noalloc)
@@ -375,6 +376,7 @@ struct Ctx final : dem_ctx {
     TRY(dalloc(ilist, n_items_max)); TRY(dalloc(icount, 2));
     TRY(dalloc(gtab, (size_t)n_gas * kGasRow));
     TRY(dalloc(eps, n_gas));
+    TRY(dalloc(rtab, (size_t)n_gas * kReactRow));
     TRY(dalloc(pm, (size_t)(P.energy_on ? 8 : 4) * n)); TRY(dalloc(pw, (size_t)2 * n));
     if (P.energy_on) {
       TRY(dalloc(thermo, 1));
@@ -653,6 +655,17 @@ struct Ctx final : dem_ctx {
     a.ores = ores;
     a.thermo = thermo;
     a.theta = theta_dev;
+    a.rtab = nullptr;
+    if (P.n_ores <= kReactRow - 10) {
+      // gas-cell quantities once per occupied cell of the current order
+      if (!occ_fresh) {
+        launch_occupied(start_d, cell_bed, beds, n_gas, false, DepositOut{}, occ_flags, occ_offs, scan_scr, occ_list,
+                        occ_count, st);
+        occ_fresh = true;
+      }
+      launch_react_table(a.g, cell_bed, beds, ores, P.n_ores, theta_dev, occ_list, occ_count, n_gas, rtab, st);
+      a.rtab = rtab;
+    }
     a.dt = dt;
     a.n = n;
     a.update_mass = update_mass;

@@ -77,7 +77,7 @@ __global__ void k_occ_compact(const int32_t *flags, const int32_t *offs, int n_g
   if (flags[c]) list[offs[c]] = c;
 }
 
-template <typename T>
+template <typename T, bool kGanser>
 __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g, const int32_t *start,
                                                  const int32_t *order, const int32_t *cell_bed, const BedDev *beds,
                                                  const OreDev *ores, Phys ph, const int32_t *list, const int32_t *list_count, int sums,
@@ -127,9 +127,12 @@ __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g
         const double V = kPi / 6.0 * dd * dd * dd;
         const double dpj = dd / (double)p.kcg[j];  // real-particle diameter
         const bool dense = eps < 0.8;
-        const double K = (ph.ganser ? drag_beta<double>(ph, ores[ore_of(p.tag[j])], B, dense, eps, rho, mu, slip, dpj)
-                                    : beta_over_epsp<double>(dense, eps, rho, mu, slip, dpj, ph.ergun_printed)) *
-                         V;
+        double beta;
+        if constexpr (kGanser)
+          beta = drag_beta<double>(ph, ores[ore_of(p.tag[j])], B, dense, eps, rho, mu, slip, dpj);
+        else
+          beta = beta_over_epsp<double>(dense, eps, rho, mu, slip, dpj, ph.ergun_printed);
+        const double K = beta * V;
         sK += K;
         sKu += K * vx;
         sKv += K * vy;
@@ -167,15 +170,63 @@ void launch_deposit(const Dyn<T> &d, const Props<T> &p, const GasArgs &g, const 
                     const DepositOut &o, hipStream_t s) {
   const int groups_per_block = 256 / kGroup;
   const int blocks = std::max(1, std::min((max_list + groups_per_block - 1) / groups_per_block, 8192));
-  k_deposit<T><<<blocks, 256, 0, s>>>(d, p, g, start, order, cell_bed, beds, ores, ph, list, list_count, sums ? 1 : 0,
-                                      o);
+  // the drag law is a template parameter: the sphericity-corrected law
+  // holds many more registers, which the spherical case does not pay for
+  if (ph.ganser)
+    k_deposit<T, true><<<blocks, 256, 0, s>>>(d, p, g, start, order, cell_bed, beds, ores, ph, list, list_count,
+                                              sums ? 1 : 0, o);
+  else
+    k_deposit<T, false><<<blocks, 256, 0, s>>>(d, p, g, start, order, cell_bed, beds, ores, ph, list, list_count,
+                                               sums ? 1 : 0, o);
 }
 
 // ------------------------------------------------------------------ reaction
 // Environment of a parcel from its gas cell (NGP) and slip, then the update of
 // its species (uscm_step), its mass (eq. e3-4), its cell sources (eqs. e2-25,
 // e3-52, e4-8) and its weighted reduction degree.
-template <typename T>
+// Quantities of the update that depend on the gas cell only, once per occupied
+// cell (the same functions of the same inputs as per parcel, so the same
+// values): H2 fraction, equilibria and rate constants at T_g (eqs. e2-1-3,
+// e2-12, e2-13), density and viscosity (eqs. e3-53, e3-55, e3-56), the
+// molecular and each ore's pore diffusivity (eqs. e2-27..e2-29).
+__global__ void k_react_table(GasArgs g, const int32_t *cell_bed, const BedDev *beds, const OreDev *ores, int n_ores,
+                              const double *theta, const int32_t *list, const int32_t *list_count, double *tab) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= *list_count) return;
+  const int c = list[t];
+  const BedDev &B = beds[cell_bed[c]];
+  const double Tg = g.T[c], p = g.p[c], xa = g.xH2[c], xb = g.xH2O[c], xn = g.xN2[c];
+  const double *th = theta ? theta : B.theta;
+  double *r = tab + (long)c * kReactRow;
+  r[0] = xb > 0.0 ? xa / (xa + xb) : (xa > 0.0 ? 1.0 : 0.0);
+  const double RT = kRg * Tg;
+  const double Kc[3] = {exp(1433.4 / Tg + 9.08), exp(-7393.9 / Tg + 7.56), exp(-2023.8 / Tg + 1.24)};
+#pragma unroll
+  for (int q = 0; q < 3; q++) {
+    r[1 + q] = 1.0 / (Kc[q] + 1.0);
+    r[4 + q] = (Kc[q] / (1.0 + Kc[q])) / exp(th[2 * q] - th[2 * q + 1] / RT);
+  }
+  double rho, mu;
+  gas_props_h2(Tg, p, xa, xb, xn, B.mu_override, rho, mu);
+  r[7] = rho;
+  r[8] = mu;
+  for (int o = 0; o < n_ores; o++) {
+    const PoreDiff Dd = pore_diffusion(Tg, p, xa, xb, xn, ores[o].d_pore_cm);
+    r[9] = Dd.Dm;
+    r[10 + o] = Dd.D;
+  }
+}
+
+void launch_react_table(const GasArgs &g, const int32_t *cell_bed, const BedDev *beds, const OreDev *ores,
+                        int n_ores, const double *theta, const int32_t *list, const int32_t *list_count, int max_list,
+                        double *tab, hipStream_t s) {
+  k_react_table<<<(max_list + 255) / 256, 256, 0, s>>>(g, cell_bed, beds, ores, n_ores, theta, list, list_count, tab);
+}
+
+// The energy equation (kThermo) moves the interface reactions and the pore
+// diffusion to the particle temperature, so those stay per parcel; without it
+// they come from the cell table when one is given.
+template <typename T, bool kThermo>
 __global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n) return;
@@ -189,27 +240,45 @@ __global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
   const int c = cl.gas;
   const double Tg = a.g.T[c], p = a.g.p[c], xa = a.g.xH2[c], xb = a.g.xH2O[c], xn = a.g.xN2[c];
   const double *th = a.theta ? a.theta : B.theta;
+  const double *rw = a.rtab ? a.rtab + (long)c * kReactRow : nullptr;
   // with the energy equation the interface reactions and the pore diffusion
   // run at the particle temperature; film, density and concentration at T_g
-  const double Tk = a.thermo ? a.p.Tp[j] : Tg;
+  const double Tk = kThermo ? a.p.Tp[j] : Tg;
   const double RT = kRg * Tg, RTk = kRg * Tk;
   UscmEnv<double> e;
-  e.x = xb > 0.0 ? xa / (xa + xb) : (xa > 0.0 ? 1.0 : 0.0);
-  // Table 2 equilibria (eq. e2-1-3) and Arrhenius constants (eq. e2-13)
-  const double Kc[3] = {exp(1433.4 / Tk + 9.08), exp(-7393.9 / Tk + 7.56), exp(-2023.8 / Tk + 1.24)};
+  if (!kThermo && rw) {
+    e.x = rw[0];
 #pragma unroll
-  for (int q = 0; q < 3; q++) {
-    e.xeq[q] = 1.0 / (Kc[q] + 1.0);
-    e.kk[q] = (Kc[q] / (1.0 + Kc[q])) / exp(th[2 * q] - th[2 * q + 1] / RTk);
+    for (int q = 0; q < 3; q++) {
+      e.xeq[q] = rw[1 + q];
+      e.kk[q] = rw[4 + q];
+    }
+  } else {
+    e.x = xb > 0.0 ? xa / (xa + xb) : (xa > 0.0 ? 1.0 : 0.0);
+    // Table 2 equilibria (eq. e2-1-3) and Arrhenius constants (eq. e2-13)
+    const double Kc[3] = {exp(1433.4 / Tk + 9.08), exp(-7393.9 / Tk + 7.56), exp(-2023.8 / Tk + 1.24)};
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      e.xeq[q] = 1.0 / (Kc[q] + 1.0);
+      e.kk[q] = (Kc[q] / (1.0 + Kc[q])) / exp(th[2 * q] - th[2 * q + 1] / RTk);
+    }
   }
   const double kcg = (double)a.p.kcg[j];
   const double dp = 2.0 * (double)P.r / kcg, rp = 0.5 * dp, Ap = kPi * dp * dp;
-  const PoreDiff Dd = pore_diffusion(Tg, p, xa, xb, xn, O.d_pore_cm);
-  const double Dpore = a.thermo ? pore_diffusion(Tk, p, xa, xb, xn, O.d_pore_cm).D : Dd.D;
+  PoreDiff Dd;
+  double rho, mu;
+  if (rw) {
+    Dd.Dm = rw[9];
+    Dd.D = rw[10 + ore_of(tag)];
+    rho = rw[7];
+    mu = rw[8];
+  } else {
+    Dd = pore_diffusion(Tg, p, xa, xb, xn, O.d_pore_cm);
+    gas_props_h2(Tg, p, xa, xb, xn, B.mu_override, rho, mu);
+  }
+  const double Dpore = kThermo ? pore_diffusion(Tk, p, xa, xb, xn, O.d_pore_cm).D : Dd.D;
 #pragma unroll
   for (int q = 0; q < 3; q++) e.rpD[q] = rp / (Dpore * O.xi_layer[q] / O.tau);
-  double rho, mu;
-  gas_props_h2(Tg, p, xa, xb, xn, B.mu_override, rho, mu);
   const double sx = a.g.ug[c] - (double)Vr.v[0], sy = a.g.vg[c] - (double)Vr.v[1], sz = a.g.wg[c] - (double)Vr.v[2];
   const double slip = sqrt(sx * sx + sy * sy + sz * sz);
   e.F = film_resistance(rho, mu, Dd.Dm, a.eps[c], dp, slip);
@@ -230,7 +299,7 @@ __global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
   const double E = -Ap / Tg;                 // eq. e4-8 with eta_H2 = -1
   a.pm[2 * N + j] = k3 * E * Qn;
   a.pm[3 * N + j] = k3 * E * Sn;
-  if (a.thermo) {
+  if constexpr (kThermo) {
     const ThermoTab &tt = *a.thermo;
     // eqs. e3-18..e3-21 with the k^3 of eqs. e3-49, e3-50: enthalpies at T_p
     // of the solid species' mole changes and of the H2 taken / H2O given
@@ -268,7 +337,10 @@ __global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
 
 template <typename T>
 void launch_react(const ReactArgs<T> &a, hipStream_t s) {
-  k_react<T><<<(a.n + 255) / 256, 256, 0, s>>>(a);
+  if (a.thermo)
+    k_react<T, true><<<(a.n + 255) / 256, 256, 0, s>>>(a);
+  else
+    k_react<T, false><<<(a.n + 255) / 256, 256, 0, s>>>(a);
 }
 
 // Cell sums of the per-parcel sources: one 16-lane group per occupied gas
@@ -326,14 +398,45 @@ void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t
 // keys are bed-major) is cut into chunks of kBedChunk parcels; one block sums
 // each chunk with a fixed shuffle/LDS tree, then one thread per bed adds its
 // chunks in order.  Deterministic, and parallel for a single large bed.
-__global__ void k_bed_chunks(const int32_t *start, const BedDev *beds, int n_beds, int4 *chunks, int max_chunks) {
-  if (threadIdx.x != 0) return;
-  int c = 0;
-  for (int b = 0; b < n_beds; b++) {
-    const int s = start[beds[b].dem_off], e = start[beds[b].dem_off + beds[b].n_dem];
-    for (int q = s; q < e && c < max_chunks - 1; q += kBedChunk) chunks[c++] = make_int4(b, q, min(q + kBedChunk, e), 0);
+__global__ void __launch_bounds__(256) k_bed_chunks(const int32_t *start, const BedDev *beds, int n_beds,
+                                                    int4 *chunks, int max_chunks) {
+  // beds in groups of 256: chunk counts, their prefix, then every thread
+  // writes chunks of the group (its bed found by bisecting the prefix)
+  __shared__ int cnt[256], off[257];
+  int base = 0;
+  for (int b0 = 0; b0 < n_beds; b0 += 256) {
+    const int b = b0 + (int)threadIdx.x;
+    int c = 0;
+    if (b < n_beds) {
+      const int s0 = start[beds[b].dem_off], e0 = start[beds[b].dem_off + beds[b].n_dem];
+      c = (e0 - s0 + kBedChunk - 1) / kBedChunk;
+    }
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int o = base;
+      for (int q = 0; q < 256; q++) {
+        off[q] = o;
+        o += cnt[q];
+      }
+      off[256] = o;
+    }
+    __syncthreads();
+    for (int k = off[0] + (int)threadIdx.x; k < off[256]; k += 256) {
+      int lo = 0, hi = 256;  // last q with off[q] <= k
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= k) lo = mid; else hi = mid;
+      }
+      const BedDev &B = beds[b0 + lo];
+      const int sb = start[B.dem_off], eb = start[B.dem_off + B.n_dem];
+      const int q0 = sb + (k - off[lo]) * kBedChunk;
+      if (k < max_chunks - 1) chunks[k] = make_int4(b0 + lo, q0, min(q0 + kBedChunk, eb), 0);
+    }
+    base = off[256];
+    __syncthreads();
   }
-  chunks[max_chunks - 1] = make_int4(c, 0, 0, 0);  // chunk count
+  if (threadIdx.x == 0) chunks[max_chunks - 1] = make_int4(min(base, max_chunks - 1), 0, 0, 0);  // chunk count
 }
 
 __global__ void __launch_bounds__(256) k_chunk_sum(const double *pw, int n, const int4 *chunks, int max_chunks,
@@ -403,7 +506,7 @@ __global__ void __launch_bounds__(256) k_bed_final(const int4 *chunks, int max_c
 
 void launch_bedsum(const double *pw, int n, const int32_t *start, const BedDev *beds, int n_beds, int4 *chunks,
                    int max_chunks, double *partial, double *bed_fov, hipStream_t s) {
-  k_bed_chunks<<<1, 64, 0, s>>>(start, beds, n_beds, chunks, max_chunks);
+  k_bed_chunks<<<1, 256, 0, s>>>(start, beds, n_beds, chunks, max_chunks);
   k_chunk_sum<<<max_chunks - 1, 256, 0, s>>>(pw, n, chunks, max_chunks, partial);
   k_bed_final<<<n_beds, 256, 0, s>>>(chunks, max_chunks, partial, bed_fov);
 }

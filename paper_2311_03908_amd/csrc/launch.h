@@ -156,6 +156,7 @@ struct ReactArgs {
   const OreDev *ores;
   const ThermoTab *thermo;  // energy equation on (null: isothermal at the gas temperature)
   const double *theta;  // 6 values overriding every bed's, or null
+  const double *rtab;   // per-cell quantities (launch_react_table) of the occupied cells, or null
   double dt;
   int n;
   int update_mass;
@@ -167,6 +168,13 @@ struct ReactArgs {
 };
 template <typename T>
 void launch_react(const ReactArgs<T> &a, hipStream_t s);
+// per occupied gas cell: H2 fraction, equilibria, rate constants, density,
+// viscosity, molecular and each ore's pore diffusivity (kReactRow doubles a
+// cell; up to kReactRow - 10 ores)
+constexpr int kReactRow = 16;
+void launch_react_table(const GasArgs &g, const int32_t *cell_bed, const BedDev *beds, const OreDev *ores,
+                        int n_ores, const double *theta, const int32_t *list, const int32_t *list_count, int max_list,
+                        double *tab, hipStream_t s);
 void launch_gas_species(const GasArgs &g, const double *eps, const int32_t *cell_bed, const BedDev *beds, int n_gas,
                         double dt, const double *sumEQ, const double *sumES, double xin1, double xin2, double *o1,
                         double *o2, double *o3, uint32_t *status, hipStream_t s);
