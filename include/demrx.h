@@ -39,7 +39,7 @@ extern "C" {
 #define DEMRX_EHIP -2       /* a HIP runtime call failed */
 #define DEMRX_EOVERFLOW -3  /* a parcel has more neighbour candidates than max_nbr */
 #define DEMRX_EDOMAIN -4    /* a parcel centre left its bed's grid */
-#define DEMRX_ENONFINITE -5 /* non-finite parcel state or gas input */
+#define DEMRX_ENONFINITE -5 /* non-finite parcel state, or gas input in a cell whose drag row is computed */
 #define DEMRX_ENOMEM -6     /* device allocation failed */
 #define DEMRX_ESKIN -7      /* displacement bound since the last neighbour build exceeded skin/2 */
 
@@ -191,7 +191,11 @@ int dem_init(const dem_params *p, const dem_parcels *in, int32_t n, void *stream
  * The neighbour lists are checked every check_every steps and rebuilt on the
  * device when the displacement bound requires it (no host synchronisation);
  * a step that still finds a parcel moved by skin/2 since the last build
- * latches DEMRX_ESKIN. */
+ * latches DEMRX_ESKIN.  The per-cell drag rows (gas velocity, voidage,
+ * pressure gradient, density, viscosity) are computed once per call; right
+ * after a coupling deposit only for each bed's gas layers that parcels can
+ * reach in n_steps steps (the occupied layers widened by
+ * (n_steps / check_every + 3) skin / 2 and one layer), else for every cell. */
 int dem_step(dem_ctx *c, int32_t n_steps, const dem_gas *g);
 
 /* Coupling deposit (eqs. e3-25, e3-27a, e4-1): voidage and drag sums per gas

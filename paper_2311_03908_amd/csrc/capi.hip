@@ -173,6 +173,7 @@ struct Ctx final : dem_ctx {
   ThermoTab *thermo = nullptr;    // energy equation only
   const double *gas_T = nullptr;  // gas temperature of the last gas table (energy equation)
   double *rtab = nullptr;  // per-cell reaction quantities (launch_react_table)
+  int2 *zrange = nullptr;  // per bed, the gas layers the drag table covers
   double *eps = nullptr, *pm = nullptr, *pw = nullptr, *bed_fov_d = nullptr, *theta_d = nullptr;
   uint32_t *status = nullptr;
   void *scratch_ptr = nullptr;       // this device's static scratch (dem_pairs_noalloc)
@@ -376,6 +377,7 @@ struct Ctx final : dem_ctx {
     TRY(dalloc(ilist, n_items_max)); TRY(dalloc(icount, 2));
     TRY(dalloc(gtab, (size_t)n_gas * kGasRow));
     TRY(dalloc(eps, n_gas));
+    TRY(dalloc(zrange, hbd.size()));
     TRY(dalloc(rtab, (size_t)n_gas * kReactRow));
     TRY(dalloc(pm, (size_t)(P.energy_on ? 8 : 4) * n)); TRY(dalloc(pw, (size_t)2 * n));
     if (P.energy_on) {
@@ -533,8 +535,31 @@ struct Ctx final : dem_ctx {
     return DEMRX_OK;
   }
 
-  int gas_table(const dem_gas *g) {
-    launch_gas_table<T>(gas_args(g), eps, cell_bed, beds, thermo, n_gas, gtab, status, st);
+  // Occupied cells of the current positions (voidage untouched).
+  int ensure_occ() {
+    TRY(ensure_dep());
+    if (!occ_fresh) {
+      launch_occupied(start_d, cell_bed, beds, n_gas, false, DepositOut{}, occ_flags, occ_offs, scan_scr, occ_list,
+                      occ_count, st);
+      occ_fresh = true;
+    }
+    return DEMRX_OK;
+  }
+
+  // The drag table.  With a horizon (the steps it serves) and an occupied
+  // list of the current positions, only each bed's layers that parcels can
+  // reach are computed: within h steps, with the lists checked every C
+  // steps, a parcel moves less than (h / C + 3) skin / 2 (at most h / C + 1
+  // rebuilds, each window held below skin / 2 by the step's own check, plus
+  // the window running at the start).  Otherwise every row is computed.
+  int gas_table(const dem_gas *g, int horizon = -1) {
+    const int2 *zr = nullptr;
+    if (horizon >= 0 && occ_fresh && dep_fresh) {
+      const double reach = ((double)(horizon / check_period()) + 3.0) * 0.5 * P.skin;
+      launch_occ_zrange(occ_list, occ_count, beds, P.n_beds, reach, zrange, st);
+      zr = zrange;
+    }
+    launch_gas_table<T>(gas_args(g), eps, cell_bed, beds, thermo, n_gas, zr, gtab, status, st);
     gas_T = g->T;
     HIPCHK(hipGetLastError());
     return DEMRX_OK;
@@ -616,7 +641,7 @@ struct Ctx final : dem_ctx {
     if (ns < 0) return fail(DEMRX_EINVAL, "n_steps < 0");
     if (!gas_ok(g)) return fail(DEMRX_EINVAL, "null gas field");
     if (ns == 0) return DEMRX_OK;
-    TRY(gas_table(g));
+    TRY(gas_table(g, ns));
     for (int s = 0; s < ns; s++) {
       if (s == ns - 1) launch_fill_u32((uint32_t *)cslot, 0u, 2 * kSlots * kSlotPad64, st);
       TRY(step_checked(s == ns - 1));
@@ -734,7 +759,7 @@ struct Ctx final : dem_ctx {
   int forces(const dem_gas *g, double *F, double *Tq) override {
     if (!gas_ok(g) || !F || !Tq) return fail(DEMRX_EINVAL, "null argument");
     TRY(ensure_lists());
-    TRY(gas_table(g));
+    TRY(gas_table(g, 0));
     StepArgs<T> a = step_args(1);
     a.Fout = F;
     a.Tout = Tq;
@@ -983,7 +1008,8 @@ struct Ctx final : dem_ctx {
   // One coupling interval of the hot path: S DEM steps (each with the list
   // check in front of it when one is due), the deposit and the reaction.
   int interval(int S, const dem_gas *g, dem_sources *o) {
-    TRY(gas_table(g));
+    TRY(ensure_occ());
+    TRY(gas_table(g, S));
     for (int s = 0; s < S; s++) {
       if (s == S - 1) launch_fill_u32((uint32_t *)cslot, 0u, 2 * kSlots * kSlotPad64, st);  // last step counts
       TRY(step_checked(s == S - 1));
@@ -1025,6 +1051,7 @@ struct Ctx final : dem_ctx {
       HIPCHK(hipEventCreateWithFlags(&ev_b, hipEventDisableTiming));
     }
     if (!built) TRY(rebuild_chain(1, true));  // a forced first build stays out of the graph
+    TRY(ensure_occ());  // every interval, the first included, starts from a fresh occupied list
     HIPCHK(hipEventRecord(ev_a, user_st));
     HIPCHK(hipStreamWaitEvent(cap_st, ev_a, 0));
     st = cap_st;

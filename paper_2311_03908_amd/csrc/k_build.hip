@@ -195,29 +195,50 @@ void launch_scatter(const int32_t *key, const int32_t *slot, const int32_t *star
 // Order the parcels of each cell by x, ties by original id (the atomic slot
 // order is not reproducible; x order makes every row of cells x-sorted for the
 // candidate search): every parcel counts the members of its cell that precede
-// it and moves to that rank.  The members' x and id are read from the
-// cell-ordered copies of the scatter: one contiguous run per cell, shared by
-// the neighbouring threads of the same cell.
-__global__ void k_cellrank(const int32_t *start, const int32_t *perm, CellOrd co, int n, int32_t *perm_out,
-                           const uint32_t *gate) {
+// it and moves to that rank.  The members' x and id come from the cell-ordered
+// copies of the scatter, one contiguous run per cell; each block first stages
+// its window of those copies (its own positions and kRankHalo on either side)
+// in LDS, and reads from there whenever its parcel's cell lies inside it.
+constexpr int kRankBlock = 256, kRankHalo = 64;
+
+__global__ void __launch_bounds__(kRankBlock) k_cellrank(const int32_t *start, const int32_t *perm, CellOrd co, int n,
+                                                         int32_t *perm_out, const uint32_t *gate) {
   if (gated_off(gate)) return;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double sx[kRankBlock + 2 * kRankHalo];
+  __shared__ uint32_t sid[kRankBlock + 2 * kRankHalo];
+  const int w0 = (int)blockIdx.x * kRankBlock - kRankHalo;  // first position of the window
+  for (int t = threadIdx.x; t < kRankBlock + 2 * kRankHalo; t += kRankBlock) {
+    const int q = w0 + t;
+    if (q >= 0 && q < n) {
+      sx[t] = co.x[q];
+      sid[t] = co.id[q];
+    }
+  }
+  __syncthreads();
+  const int p = (int)blockIdx.x * kRankBlock + (int)threadIdx.x;
   if (p >= n) return;
   const int c = co.key[p];
   const int s = start[c], e = start[c + 1];
-  const double x = co.x[p];
-  const uint32_t id = co.id[p];
+  const double x = sx[p - w0];
+  const uint32_t id = sid[p - w0];
   int rank = 0;
+  if (s >= w0 && e <= w0 + kRankBlock + 2 * kRankHalo) {
+    for (int q = s - w0; q < e - w0; q++) {
+      const double xq = sx[q];
+      rank += (xq < x || (xq == x && sid[q] < id)) ? 1 : 0;
+    }
+  } else {
 #pragma unroll 4
-  for (int q = s; q < e; q++) {
-    const double xq = co.x[q];
-    rank += (xq < x || (xq == x && co.id[q] < id)) ? 1 : 0;
+    for (int q = s; q < e; q++) {
+      const double xq = co.x[q];
+      rank += (xq < x || (xq == x && co.id[q] < id)) ? 1 : 0;
+    }
   }
   perm_out[s + rank] = perm[p];
 }
 void launch_cellrank(const int32_t *start, const int32_t *perm, const CellOrd &co, int n, int32_t *perm_out,
                      hipStream_t s, const uint32_t *gate) {
-  k_cellrank<<<(n + 255) / 256, 256, 0, s>>>(start, perm, co, n, perm_out, gate);
+  k_cellrank<<<(n + kRankBlock - 1) / kRankBlock, kRankBlock, 0, s>>>(start, perm, co, n, perm_out, gate);
 }
 
 // Permutation into the spare buffers (the other step buffer and the spare
@@ -292,9 +313,23 @@ __global__ void k_carry(Nbr<T> nb, int n, Spring<T> *carry, uint32_t *carry_meta
   const uint64_t m = nb.mask[p];
   uint64_t b = m & ((1ull << kWallBit) - 1ull);
   uint32_t k = 0;
-  for (; b; b &= b - 1, k++) {
-    const int q = __ffsll((unsigned long long)b) - 1;
-    carry[(long)k * N + p] = nb.hist[(long)q * N + p];
+  // four springs per round trip: all four loads before the stores
+  while (b) {
+    int q[4];
+    Spring<T> h[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      q[u] = b ? __ffsll((unsigned long long)b) - 1 : -1;
+      b &= b ? b - 1 : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (q[u] >= 0) h[u] = nb.hist[(long)q[u] * N + p];
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (q[u] >= 0) carry[(long)(k + u) * N + p] = h[u];
+#pragma unroll
+    for (int u = 0; u < 4; u++) k += q[u] >= 0 ? 1u : 0u;
   }
   carry_meta[p] = ((uint32_t)(m >> kWallBit) << 16) | k;
 }
@@ -407,6 +442,7 @@ __global__ void __launch_bounds__(kThreads) k_build_nbr(NbrBuild<T> a) {
   // segments: global start, length, stencil row; staged offset of each
   // segment of the current pass
   __shared__ int sg_start[kMaxSeg], sg_len[kMaxSeg], sg_row[kMaxSeg], sg_off[kMaxSeg + 1];
+  __shared__ int row_s[9], row_e[9];
   __shared__ int n_seg, cen0, cen1, w_next;
   const int n_list = *a.list_count;
   const long N = a.n;
@@ -424,18 +460,29 @@ __global__ void __launch_bounds__(kThreads) k_build_nbr(NbrBuild<T> a) {
     const Item it = a.items[a.list[w]];
     const BedDev &B = a.beds[it.bed];
     const int xc = min(a.item_x, B.nd[0] - it.x0);
-    if (tid == 0) {
-      int ns = 0;
-      for (int r = 0; r < 9; r++) {
-        const int iy2 = it.iy + (r % 3) - 1, iz2 = it.iz + (r / 3) - 1;
-        if (iy2 < 0 || iy2 >= B.nd[1] || iz2 < 0 || iz2 >= B.nd[2]) continue;
+    // the nine stencil rows' runs, one thread each, then their segments
+    if (tid < 9) {
+      const int r = tid;
+      const int iy2 = it.iy + (r % 3) - 1, iz2 = it.iz + (r / 3) - 1;
+      int s0 = 0, s1 = 0;
+      if (iy2 >= 0 && iy2 < B.nd[1] && iz2 >= 0 && iz2 < B.nd[2]) {
         const int xl = max(it.x0 - 1, 0), xh = min(it.x0 + xc, B.nd[0] - 1);
-        int s0 = a.start[dem_key(B, xl, iy2, iz2)];
-        const int s1 = a.start[dem_key(B, xh, iy2, iz2) + 1];
+        s0 = a.start[dem_key(B, xl, iy2, iz2)];
+        s1 = a.start[dem_key(B, xh, iy2, iz2) + 1];
         if (r == 4) {
           cen0 = a.start[dem_key(B, it.x0, iy2, iz2)];
           cen1 = a.start[dem_key(B, it.x0 + xc - 1, iy2, iz2) + 1];
         }
+      }
+      row_s[r] = s0;
+      row_e[r] = s1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int ns = 0;
+      for (int r = 0; r < 9; r++) {
+        int s0 = row_s[r];
+        const int s1 = row_e[r];
         while (s0 < s1) {
           if (ns == kMaxSeg) {
             atomicOr(a.status, ST_OVERFLOW);

@@ -130,7 +130,11 @@ struct GasArgs {
 };
 template <typename T>
 void launch_gas_table(const GasArgs &g, const double *eps, const int32_t *cell_bed, const BedDev *beds,
-                      const ThermoTab *thermo, int n_gas, T *gtab, uint32_t *status, hipStream_t s);
+                      const ThermoTab *thermo, int n_gas, const int2 *zr, T *gtab, uint32_t *status, hipStream_t s);
+// per bed, the gas-cell layers [x, y] that parcels of the occupied list can
+// reach within `reach` metres (zr: n_beds entries)
+void launch_occ_zrange(const int32_t *list, const int32_t *count, const BedDev *beds, int n_beds, double reach,
+                       int2 *zr, hipStream_t s);
 
 // ---------------------------------------------------------------- k_couple.hip
 struct DepositOut {

@@ -179,3 +179,29 @@ def test_coupled_momentum_intervals_fp64():
     d = w.parcels["d"].astype(np.float64)
     dx = np.sqrt(sum((_np(sg[k]) - so[k]) ** 2 for k in ("x", "y", "z")))
     assert np.max(dx / d) <= 1e-4
+
+
+@pytest.mark.parametrize("case", ["cfg3_mixed", "cfg5_batched"])
+def test_drag_rows_restricted_to_reachable_layers(case):
+    """Right after a coupling deposit, dem_step computes the drag rows only for
+    the gas layers its parcels can reach; stepping from there is bit-identical
+    to stepping with every row computed (a bed whose cell order was dropped by
+    a list check before the steps)."""
+    if case == "cfg3_mixed":
+        w = W.with_velocities(W.cfg3(n=20000, seed=41), 41, vscale=0.03, wscale=20.0)
+    else:
+        w = W.with_velocities(W.cfg5(n_beds=3, n_scale=0.05, seed=42), 42)
+    out = []
+    for drop in (False, True):
+        bed = Bed(w)
+        bed.couple()
+        if drop:
+            bed.pairs()  # the list check leaves the deposit's cell order stale
+        bed.step(20)
+        F, T = bed.forces()
+        out.append((bed.state(), F, T))
+        bed.close()
+    (s0, F0, T0), (s1, F1, T1) = out
+    for k in s0:
+        assert torch.equal(s0[k], s1[k]), k
+    assert torch.equal(F0, F1) and torch.equal(T0, T1)
