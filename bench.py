@@ -353,6 +353,8 @@ def main():
     ap.add_argument("--settled", default=None, help="start from a state saved by --save-settled")
     ap.add_argument("--launch", default=None, metavar="B,X,G",
                     help="fixed launch shapes (step block, XCD chunk, build grid) instead of autotuning")
+    ap.add_argument("--build", default=None, metavar="T,L,W",
+                    help="with --launch: neighbour-build threads per block, LDS tile and item width")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (64-bed), adjoint (500k-parcel gradient) and kinetic-sweep legs")
     ap.add_argument("--skin", type=float, default=None, help="neighbour-list skin (m) of the timed run")
@@ -413,6 +415,8 @@ def main():
     bed = Bed(w, device="cuda:0")
     if args.launch:
         bed.set_launch(*[int(v) for v in args.launch.split(",")])
+        if args.build:
+            bed.set_build(*[int(v) for v in args.build.split(",")])
     else:
         bed.autotune()
     bed.run(warm_int, S, sources=True)

@@ -382,108 +382,6 @@ void launch_step(const StepArgs<T> &a, int block, hipStream_t s) {
 }
 
 
-// ------------------------------------------------------------------ gas table
-// Ideal-gas density (eq. e3-53) and mass-weighted viscosity (eqs. e3-55,
-// e3-56, Table C2) of each cell, with the cell's velocity, voidage and
-// pressure gradient, packed in one row for the drag gather; with the energy
-// equation also the conductivity and Pr^(1/3) (eqs. e3-13, e3-57..e3-59).
-__device__ __forceinline__ void gas_rho_mu(double T, double p, double x1, double x2, double x3, double mu_fix,
-                                           double &rho, double &mu) {
-  const double M1 = 2.016, M2 = 18.015, M3 = 28.013;  // g/mol H2, H2O, N2
-  const double Mg = x1 * M1 + x2 * M2 + x3 * M3;
-  rho = p * (Mg * 1e-3) / (kRg * T);
-  if (mu_fix > 0.0) {
-    mu = mu_fix;
-    return;
-  }
-  const double m1 = 2.85e-6 + 2.16e-8 * T - 3.78e-12 * T * T;
-  const double m2 = -4.44e-6 + 4.52e-8 * T - 3.20e-12 * T * T;
-  const double m3 = 7.86e-6 + 3.87e-8 * T - 5.11e-12 * T * T;
-  mu = (x1 * M1 * m1 + x2 * M2 * m2 + x3 * M3 * m3) / Mg;
-}
-
-template <typename T>
-__global__ void k_gas_table(GasArgs g, const double *eps, const int32_t *cell_bed, const BedDev *beds,
-                            const ThermoTab *thermo, int n_gas, const int2 *zr, T *gtab, uint32_t *status) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_gas) return;
-  if (zr) {  // only the layers of its bed that parcels can reach
-    const int b = cell_bed[c];
-    const BedDev &B = beds[b];
-    const int z = (c - B.gas_off) / (B.n[0] * B.n[1]);
-    if (z < zr[b].x || z > zr[b].y) return;
-  }
-  double rho, mu;
-  gas_rho_mu(g.T[c], g.p[c], g.xH2[c], g.xH2O[c], g.xN2[c], beds[cell_bed[c]].mu_override, rho, mu);
-  T *r = gtab + (long)c * kGasRow;
-  r[0] = T(g.ug[c]);
-  r[1] = T(g.vg[c]);
-  r[2] = T(g.wg[c]);
-  r[3] = T(eps[c]);
-  r[4] = T(g.dpdx[c]);
-  r[5] = T(g.dpdy[c]);
-  r[6] = T(g.dpdz[c]);
-  r[7] = T(rho);
-  r[8] = T(mu);
-  r[9] = r[10] = T(0);
-  r[11] = T(eps[c] < 0.8 ? 1 : 0);  // drag branch, decided in FP64
-  double lam = 1.0, cp = 1.0;
-  if (thermo) {
-    gas_heat_props(*thermo, g.T[c], g.xH2[c], g.xH2O[c], g.xN2[c], lam, cp);
-    r[9] = T(lam);
-    r[10] = T(cbrt(cp * mu / lam));
-  }
-  if (!(lam > 0.0 && cp > 0.0 && isfinite(g.T[c])) ||
-      !(isfinite(rho) && isfinite(mu) && isfinite(g.ug[c] + g.vg[c] + g.wg[c]) &&
-        isfinite(g.dpdx[c] + g.dpdy[c] + g.dpdz[c])) || !(rho > 0.0) || !(mu > 0.0))
-    atomicOr(status, ST_NONFINITE);
-}
-
-template <typename T>
-void launch_gas_table(const GasArgs &g, const double *eps, const int32_t *cell_bed, const BedDev *beds,
-                      const ThermoTab *thermo, int n_gas, const int2 *zr, T *gtab, uint32_t *status, hipStream_t s) {
-  k_gas_table<T><<<(n_gas + 255) / 256, 256, 0, s>>>(g, eps, cell_bed, beds, thermo, n_gas, zr, gtab, status);
-}
-
-// Layers of each bed that parcels can reach: the occupied list is sorted by
-// cell and cells are numbered bed by bed, z outermost, so a bed's first and
-// last listed cells hold its lowest and highest occupied layers; the range
-// is widened by `reach` metres and one layer.  An empty bed gets an empty
-// range.
-__global__ void k_occ_zrange(const int32_t *list, const int32_t *count, const BedDev *beds, int n_beds, double reach,
-                             int2 *zr) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n_beds) return;
-  const BedDev &B = beds[b];
-  const int m = *count;
-  auto first_at_least = [&](int v) {
-    int lo = 0, hi = m;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (list[mid] < v) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-  };
-  const int i0 = first_at_least(B.gas_off), i1 = first_at_least(B.gas_off + B.n_gas);
-  if (i0 >= i1) {
-    zr[b] = make_int2(1, 0);
-    return;
-  }
-  const int layer = B.n[0] * B.n[1];
-  const int margin = (int)ceil(reach / B.h) + 1;
-  const int z0 = (list[i0] - B.gas_off) / layer, z1 = (list[i1 - 1] - B.gas_off) / layer;
-  zr[b] = make_int2(max(z0 - margin, 0), min(z1 + margin, B.n[2] - 1));
-}
-void launch_occ_zrange(const int32_t *list, const int32_t *count, const BedDev *beds, int n_beds, double reach,
-                       int2 *zr, hipStream_t s) {
-  k_occ_zrange<<<(n_beds + 63) / 64, 64, 0, s>>>(list, count, beds, n_beds, reach, zr);
-}
-
 template void launch_step<float>(const StepArgs<float> &, int, hipStream_t);
 template void launch_step<double>(const StepArgs<double> &, int, hipStream_t);
-template void launch_gas_table<float>(const GasArgs &, const double *, const int32_t *, const BedDev *,
-                                      const ThermoTab *, int, const int2 *, float *, uint32_t *, hipStream_t);
-template void launch_gas_table<double>(const GasArgs &, const double *, const int32_t *, const BedDev *,
-                                       const ThermoTab *, int, const int2 *, double *, uint32_t *, hipStream_t);
-
 }  // namespace demrx
