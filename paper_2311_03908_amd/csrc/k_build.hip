@@ -313,14 +313,16 @@ __global__ void k_carry(Nbr<T> nb, int n, Spring<T> *carry, uint32_t *carry_meta
   const uint64_t m = nb.mask[p];
   uint64_t b = m & ((1ull << kWallBit) - 1ull);
   uint32_t k = 0;
-  // four springs per round trip: all four loads before the stores
+  // four springs per round trip (all four loads before the stores), from the
+  // highest slot down: the near region's contacts fill the top slots of
+  // nearly every parcel, so a wave's loads of one round trip share rows
   while (b) {
     int q[4];
     Spring<T> h[4];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
-      q[u] = b ? __ffsll((unsigned long long)b) - 1 : -1;
-      b &= b ? b - 1 : 0ull;
+      q[u] = b ? 63 - __clzll((long long)b) : -1;
+      b &= b ? ~(1ull << (q[u] & 63)) : 0ull;
     }
 #pragma unroll
     for (int u = 0; u < 4; u++)
