@@ -151,8 +151,8 @@ struct Ctx final : dem_ctx {
   Dyn<T> dyn[2]{};  // step buffers: a step reads dyn[cur] and writes dyn[cur ^ 1]
   Props<T> pr{}, pr_sp{};  // properties and the spare the rebuild permutes into
   Nbr<T> nb{};
-  Spring<T> *carry = nullptr;      // springs carried across a rebuild (launch_carry)
-  uint32_t *carry_meta = nullptr;
+  Spring<T> *carry = nullptr;      // springs carried across a rebuild (launch_permute)
+  uint64_t *carry_mask = nullptr;  // old contact masks by new position (launch_permute)
   uint32_t *rb_flag = nullptr;     // set by the rebuild check: rebuild at this check point
   unsigned long long *rb_count = nullptr;  // rebuilds done (device counter)
   int cur = 0;
@@ -258,7 +258,7 @@ struct Ctx final : dem_ctx {
     TRY(dalloc(b.hist, (size_t)kMaxNbr * n));
     TRY(dalloc(b.mask, n));
     TRY(dalloc(carry, (size_t)kMaxNbr * n));
-    TRY(dalloc(carry_meta, n));
+    TRY(dalloc(carry_mask, n));
     return DEMRX_OK;
   }
 
@@ -440,9 +440,9 @@ struct Ctx final : dem_ctx {
   // (or when forced); every kernel of the chain returns at once when it is
   // clear, so the chain's place in a captured graph is fixed while whether it
   // runs is decided on the device.  A rebuild sorts the parcels by DEM cell
-  // (bin, scan, scatter, in-cell rank), compacts the contact springs,
-  // permutes the state through the spare buffers back into dyn[cur] and pr,
-  // and builds the lists; no buffer parity changes.
+  // (bin, scan, scatter, in-cell rank), permutes the state through the spare
+  // buffers back into dyn[cur] and pr (moving the contact springs to the new
+  // positions on the way), and builds the lists; no buffer parity changes.
   // Work items of `width` DEM cells along x, in key order (row by row), so
   // that the persistent build blocks work on neighbouring cells at a time.
   int upload_items(int width) {
@@ -464,7 +464,7 @@ struct Ctx final : dem_ctx {
     if (!bpc[build_variant]) bpc[build_variant] = build_blocks_per_cu<T>(build_variant);
     return std::max(1, std::min(n_items, bpc[build_variant] * n_cu));
   }
-  int rebuild_chain(int horizon, bool force, bool carry_ready = false) {
+  int rebuild_chain(int horizon, bool force) {
     const uint32_t *G = rb_flag;
     launch_rebuild_check(dslot, (int)((step_count & 1) ^ 1), P.skin, P.dt, horizon, force ? 1 : 0, rb_flag,
                          rb_count, st);
@@ -473,16 +473,14 @@ struct Ctx final : dem_ctx {
     launch_scan(count, start, (long)n_keys + 1, scan_scr, st, G);
     launch_scatter(key, slot, start, dyn[cur].pos, n, perm2, cord, st, G);
     launch_cellrank(start, perm2, cord, n, perm, st, G);
-    if (!carry_ready) launch_carry<T>(nb, n, carry, carry_meta, st, G);  // else filled by the caller
-    launch_permute<T>(perm, n, dyn[cur], pr, dyn[cur ^ 1], pr_sp, xref, dslot, st, G);
+    launch_permute<T>(perm, n, dyn[cur], pr, dyn[cur ^ 1], pr_sp, xref, dslot, nb, carry, carry_mask, st, G);
     launch_items(items, n_items, item_x, beds, start, iflags, ioffs, scan_scr, ilist, icount, st, G);
     NbrBuild<T> a;
     a.d = dyn[cur];
     a.p = pr;
-    a.perm = perm;
     a.nb = nb;
     a.carry = carry;
-    a.carry_meta = carry_meta;
+    a.carry_mask = carry_mask;
     a.gate = G;
     a.beds = beds;
     a.start = start;
@@ -923,10 +921,9 @@ struct Ctx final : dem_ctx {
     }
     HIPCHK(hipMemcpyAsync(won, in->wall_on, (size_t)n * kMaxWalls, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(wxi, in->wall_xi, (size_t)n * kMaxWalls * 3 * sizeof(double), hipMemcpyHostToDevice, st));
-    launch_contacts_import<T>(dyn[cur].pos, n, P.max_nbr, ids, xi, np, won, wxi, inv, cnt, carry, carry_meta, pr.wh,
-                              status, st);
+    launch_contacts_import<T>(dyn[cur].pos, n, P.max_nbr, ids, xi, np, won, wxi, inv, cnt, nb, pr.wh, status, st);
     HIPCHK(hipGetLastError());
-    TRY(rebuild_chain(1, true, true));
+    TRY(rebuild_chain(1, true));
     return sync();
   }
 

@@ -246,29 +246,52 @@ void launch_cellrank(const int32_t *start, const int32_t *perm, const CellOrd &c
 // so no buffer parity depends on whether a rebuild ran.
 template <typename T>
 __global__ void k_permute(const int32_t *perm, int n, Dyn<T> din, Props<T> pin, Dyn<T> dout, Props<T> pout,
-                          float4 *xref, unsigned *dslot, const uint32_t *gate) {
+                          float4 *xref, unsigned *dslot, Nbr<T> nb, Spring<T> *carry, uint64_t *carry_mask,
+                          const uint32_t *gate) {
   if (gated_off(gate)) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < 2 * kSlots) {  // displacement and speed maxima restart at the rebuild
     dslot[j * kSlotPad] = 0u;
     dslot[j * kSlotPad + 1] = 0u;
   }
-  if (j >= n) return;
-  const int i = perm[j];
-  const PosRec P = load_pos(din.pos, i);
-  store_pos(dout.pos, j, P);
-  xref[j] = make_float4((float)P.x, (float)P.y, (float)P.z, 0.0f);
-  dout.vel[j] = din.vel[i];
-  pout.kcg[j] = pin.kcg[i];
-  pout.tag[j] = pin.tag[i];
-  pout.nh[j] = pin.nh[i];
-  pout.nm[j] = pin.nm[i];
-  pout.nw[j] = pin.nw[i];
-  pout.nfe[j] = pin.nfe[i];
-  if (pin.Tp) {
-    pout.Tp[j] = pin.Tp[i];
-    pout.qrx[j] = pin.qrx[i];
-    pout.mcp[j] = pin.mcp[i];
+  const bool live = j < n;
+  const int i = live ? perm[j] : 0;
+  if (live) {
+    const PosRec P = load_pos(din.pos, i);
+    store_pos(dout.pos, j, P);
+    xref[j] = make_float4((float)P.x, (float)P.y, (float)P.z, 0.0f);
+    dout.vel[j] = din.vel[i];
+    pout.kcg[j] = pin.kcg[i];
+    pout.tag[j] = pin.tag[i];
+    pout.nh[j] = pin.nh[i];
+    pout.nm[j] = pin.nm[i];
+    pout.nw[j] = pin.nw[i];
+    pout.nfe[j] = pin.nfe[i];
+    if (pin.Tp) {
+      pout.Tp[j] = pin.Tp[i];
+      pout.qrx[j] = pin.qrx[i];
+      pout.mcp[j] = pin.mcp[i];
+    }
+  }
+  // the contact springs of the old lists move to the new position in their
+  // own slots (carry[s * N + j]) with the old contact mask; the wave visits
+  // the union of its lanes' contact slots, so each visit reads and writes
+  // one row of consecutive parcels
+  const long N = n;
+  const uint64_t m = live ? nb.mask[i] : 0ull;
+  if (live) carry_mask[j] = m;
+  const uint64_t b = m & ((1ull << kWallBit) - 1ull);
+  uint32_t lo = (uint32_t)b, hi = (uint32_t)(b >> 32);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo |= __shfl_xor(lo, o, 64);
+    hi |= __shfl_xor(hi, o, 64);
+  }
+  uint64_t u = ((uint64_t)__builtin_amdgcn_readfirstlane(hi) << 32) | __builtin_amdgcn_readfirstlane(lo);
+  while (u) {
+    const int sl = __ffsll((unsigned long long)u) - 1;
+    u &= u - 1;
+    if ((b >> sl) & 1ull) carry[(long)sl * N + j] = nb.hist[(long)sl * N + i];
   }
 }
 
@@ -294,52 +317,11 @@ __global__ void k_copy_back(int n, Dyn<T> src, Props<T> psrc, Dyn<T> dst, Props<
 
 template <typename T>
 void launch_permute(const int32_t *perm, int n, const Dyn<T> &d, const Props<T> &p, const Dyn<T> &spare,
-                    const Props<T> &pspare, float4 *xref, unsigned *dslot, hipStream_t s, const uint32_t *gate) {
+                    const Props<T> &pspare, float4 *xref, unsigned *dslot, const Nbr<T> &nb, Spring<T> *carry,
+                    uint64_t *carry_mask, hipStream_t s, const uint32_t *gate) {
   const int g = (std::max(n, 2 * kSlots) + 255) / 256;
-  k_permute<T><<<g, 256, 0, s>>>(perm, n, d, p, spare, pspare, xref, dslot, gate);
+  k_permute<T><<<g, 256, 0, s>>>(perm, n, d, p, spare, pspare, xref, dslot, nb, carry, carry_mask, gate);
   k_copy_back<T><<<(n + 255) / 256, 256, 0, s>>>(n, spare, pspare, d, p, gate);
-}
-
-// Contact springs of every parcel (old sorted order) before a rebuild,
-// compacted: carry[k * N + p] for its k-th contact (bits 0..47 of the mask in
-// ascending slot), carry_meta[p] = (wall bits << 16) | count.  The build
-// carries them to the new lists by matching partner ids.
-template <typename T>
-__global__ void k_carry(Nbr<T> nb, int n, Spring<T> *carry, uint32_t *carry_meta, const uint32_t *gate) {
-  if (gated_off(gate)) return;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const long N = n;
-  const uint64_t m = nb.mask[p];
-  uint64_t b = m & ((1ull << kWallBit) - 1ull);
-  uint32_t k = 0;
-  // four springs per round trip (all four loads before the stores), from the
-  // highest slot down: the near region's contacts fill the top slots of
-  // nearly every parcel, so a wave's loads of one round trip share rows
-  while (b) {
-    int q[4];
-    Spring<T> h[4];
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      q[u] = b ? 63 - __clzll((long long)b) : -1;
-      b &= b ? ~(1ull << (q[u] & 63)) : 0ull;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; u++)
-      if (q[u] >= 0) h[u] = nb.hist[(long)q[u] * N + p];
-#pragma unroll
-    for (int u = 0; u < 4; u++)
-      if (q[u] >= 0) carry[(long)(k + u) * N + p] = h[u];
-#pragma unroll
-    for (int u = 0; u < 4; u++) k += q[u] >= 0 ? 1u : 0u;
-  }
-  carry_meta[p] = ((uint32_t)(m >> kWallBit) << 16) | k;
-}
-
-template <typename T>
-void launch_carry(const Nbr<T> &nb, int n, Spring<T> *carry, uint32_t *carry_meta, hipStream_t s,
-                  const uint32_t *gate) {
-  k_carry<T><<<(n + 255) / 256, 256, 0, s>>>(nb, n, carry, carry_meta, gate);
 }
 
 // Decide whether the lists must be rebuilt before the next `horizon` steps:
@@ -429,8 +411,9 @@ void launch_items(const Item *items, int n_items, int item_x, const BedDev *beds
 // candidates that touch now (FP32 test with a 1e-4 margin, a superset of the
 // exact contacts) fill slots cap-1, cap-2, ... downwards, the others fill
 // slots 0, 1, ... upwards; cnt packs (near << 16) | far.  After the scan the
-// tangential springs of partners in contact before the rebuild (compacted by
-// k_carry) are carried over to the near slots by matching original ids,
+// tangential springs of partners in contact before the rebuild (moved to
+// the new positions by the permutation) are carried over to the near slots
+// by matching original ids,
 // which every spring record carries; keeping that match out of the scan
 // keeps the scan's per-candidate work small.
 constexpr float kNear = 1.0f + 1e-4f;
@@ -601,16 +584,22 @@ __global__ void __launch_bounds__(kThreads) k_build_nbr(NbrBuild<T> a) {
         sg = se;
       }
       if (mine) {
-        // springs of the old contacts that are near candidates again
-        const int po = a.perm[i];
-        const uint32_t meta = a.carry_meta[po];
-        const int n_old = (int)(meta & 0xffffu);
+        // springs of the old contacts that are near candidates again (the
+        // permutation left them at the new position, in their old slots)
+        const uint64_t om = a.carry_mask[i];
+        uint64_t rest = om & ((1ull << kWallBit) - 1ull);
         uint64_t newbits = 0;
-        if (n_old > 0 && nn > 0) {
+        if (rest && nn > 0) {
+          // partner ids and slots of the first kCarry old contacts; the rest
+          // are matched by a loop over their bits
           uint32_t oid[kCarry];
+          int osl[kCarry];
 #pragma unroll
-          for (int k = 0; k < kCarry; k++)
-            oid[k] = k < n_old ? spring_partner(a.carry[(long)k * N + po].w) : 0xffffffffu;
+          for (int k = 0; k < kCarry; k++) {
+            osl[k] = rest ? __ffsll((unsigned long long)rest) - 1 : 0;
+            oid[k] = rest ? spring_partner(a.carry[(long)osl[k] * N + i].w) : 0xffffffffu;
+            rest &= rest ? rest - 1 : 0ull;
+          }
           for (int k0 = 0; k0 < nn; k0 += 4) {
             int jj[4];
             uint32_t idn[4];
@@ -621,15 +610,17 @@ __global__ void __launch_bounds__(kThreads) k_build_nbr(NbrBuild<T> a) {
 #pragma unroll
             for (int u = 0; u < 4; u++) {
               if (jj[u] < 0) continue;
-              int qo = -1;
+              int qs = -1;
 #pragma unroll
               for (int k = 0; k < kCarry; k++)
-                if (oid[k] == idn[u]) qo = k;
-              for (int k = kCarry; k < n_old && qo < 0; k++)
-                if (spring_partner(a.carry[(long)k * N + po].w) == idn[u]) qo = k;
-              if (qo >= 0) {
+                if (oid[k] == idn[u]) qs = osl[k];
+              for (uint64_t r = rest; r && qs < 0; r &= r - 1) {
+                const int sl2 = __ffsll((unsigned long long)r) - 1;
+                if (spring_partner(a.carry[(long)sl2 * N + i].w) == idn[u]) qs = sl2;
+              }
+              if (qs >= 0) {
                 const int sl = cap - 1 - k0 - u;
-                a.nb.hist[(long)sl * N + i] = a.carry[(long)qo * N + po];
+                a.nb.hist[(long)sl * N + i] = a.carry[(long)qs * N + i];
                 newbits |= 1ull << sl;
               }
             }
@@ -637,7 +628,7 @@ __global__ void __launch_bounds__(kThreads) k_build_nbr(NbrBuild<T> a) {
         }
         if (over) atomicOr(a.status, ST_OVERFLOW);
         a.nb.cnt[i] = (nn << 16) | nf;
-        a.nb.mask[i] = newbits | ((uint64_t)(meta >> 16) << kWallBit);
+        a.nb.mask[i] = newbits | (om & ~((1ull << kWallBit) - 1ull));
       }
     }
   }
@@ -762,14 +753,14 @@ __global__ void k_inverse_ids(const PosRec *pos, int n, int32_t *inv) {
   if (p < n) inv[pos[p].id] = p;
 }
 
-// Import: each pair's spring goes to both partners' carry rows (the partner's
-// id in the fourth component, the orientation unchanged), as launch_carry
-// leaves them before a rebuild; the next build copies them to the pairs'
-// near slots.  Row order within a parcel does not matter (the build matches
-// by id).
+// Import: each pair's spring goes into both partners' current lists (slots
+// 0, 1, ... in arrival order, the partner's id in the fourth component, the
+// orientation unchanged) with the contact bits of those slots set, as a step
+// leaves them; the next rebuild carries them to the pairs' near slots by
+// id, so the slot order does not matter.
 template <typename T>
 __global__ void k_contacts_import(const uint32_t *ids, const double *xi, long np, const int32_t *inv, int n,
-                                  int cap_slots, Spring<T> *carry, uint32_t *cnt, uint32_t *status) {
+                                  int cap_slots, Spring<T> *hist, uint32_t *cnt, uint32_t *status) {
   const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= np) return;
   const long N = n;
@@ -777,27 +768,28 @@ __global__ void k_contacts_import(const uint32_t *ids, const double *xi, long np
   const int pa = inv[ia], pb = inv[ib];
   const T x = T(xi[3 * q]), y = T(xi[3 * q + 1]), z = T(xi[3 * q + 2]);
   const uint32_t ka = atomicAdd(cnt + pa, 1u), kb = atomicAdd(cnt + pb, 1u);
-  if ((int)ka < cap_slots) carry[(long)ka * N + pa] = Spring<T>{x, y, z, spring_tag<T>(ib)};
-  if ((int)kb < cap_slots) carry[(long)kb * N + pb] = Spring<T>{x, y, z, spring_tag<T>(ia)};
+  if ((int)ka < cap_slots) hist[(long)ka * N + pa] = Spring<T>{x, y, z, spring_tag<T>(ib)};
+  if ((int)kb < cap_slots) hist[(long)kb * N + pb] = Spring<T>{x, y, z, spring_tag<T>(ia)};
   if ((int)ka >= cap_slots || (int)kb >= cap_slots) atomicOr(status, ST_OVERFLOW);
 }
 
 template <typename T>
 __global__ void k_walls_import(const PosRec *pos, int n, int cap_slots, const uint8_t *wall_on, const double *wall_xi,
-                               T *wh, const uint32_t *cnt, uint32_t *carry_meta) {
+                               T *wh, const uint32_t *cnt, uint64_t *mask) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const long N = n;
   const uint32_t id = pos[p].id;
-  uint32_t bits = 0;
+  uint64_t bits = 0;
   for (int w = 0; w < kMaxWalls; w++) {
     const bool on = wall_on[(long)id * kMaxWalls + w] != 0;
-    if (on) bits |= 1u << w;
+    if (on) bits |= 1ull << w;
 #pragma unroll
     for (int c = 0; c < 3; c++)
       wh[(long)(w * 3 + c) * N + id] = on ? T(wall_xi[((long)id * kMaxWalls + w) * 3 + c]) : T(0);
   }
-  carry_meta[p] = (bits << 16) | min(cnt[p], (uint32_t)cap_slots);
+  const uint32_t k = min(cnt[p], (uint32_t)cap_slots);
+  mask[p] = (bits << kWallBit) | ((1ull << k) - 1ull);
 }
 
 template <typename T>
@@ -810,28 +802,28 @@ void launch_contacts_export(const PosRec *pos, const Nbr<T> &nb, const T *wh, in
 template <typename T>
 void launch_contacts_import(const PosRec *pos, int n, int cap_slots, const uint32_t *ids, const double *xi, long np,
                             const uint8_t *wall_on, const double *wall_xi, int32_t *inv, uint32_t *cnt,
-                            Spring<T> *carry, uint32_t *carry_meta, T *wh, uint32_t *status, hipStream_t s) {
+                            const Nbr<T> &nb, T *wh, uint32_t *status, hipStream_t s) {
   k_inverse_ids<<<(n + 255) / 256, 256, 0, s>>>(pos, n, inv);
   launch_fill_u32(cnt, 0u, n, s);
   if (np > 0)
-    k_contacts_import<T><<<(unsigned)((np + 255) / 256), 256, 0, s>>>(ids, xi, np, inv, n, cap_slots, carry, cnt,
+    k_contacts_import<T><<<(unsigned)((np + 255) / 256), 256, 0, s>>>(ids, xi, np, inv, n, cap_slots, nb.hist, cnt,
                                                                      status);
-  k_walls_import<T><<<(n + 255) / 256, 256, 0, s>>>(pos, n, cap_slots, wall_on, wall_xi, wh, cnt, carry_meta);
+  k_walls_import<T><<<(n + 255) / 256, 256, 0, s>>>(pos, n, cap_slots, wall_on, wall_xi, wh, cnt, nb.mask);
 }
 
 #define INST(T)                                                                                                   \
   template void launch_bin<T>(const Dyn<T> &, const Props<T> &, const BedDev *, int, int32_t *, int32_t *,       \
                               int32_t *, uint32_t *, hipStream_t, const uint32_t *);                              \
   template void launch_permute<T>(const int32_t *, int, const Dyn<T> &, const Props<T> &, const Dyn<T> &,        \
-                                  const Props<T> &, float4 *, unsigned *, hipStream_t, const uint32_t *);        \
-  template void launch_carry<T>(const Nbr<T> &, int, Spring<T> *, uint32_t *, hipStream_t, const uint32_t *);    \
+                                  const Props<T> &, float4 *, unsigned *, const Nbr<T> &, Spring<T> *,           \
+                                  uint64_t *, hipStream_t, const uint32_t *);                                    \
   template void launch_build_nbr<T>(const NbrBuild<T> &, int, int, hipStream_t);                 \
   template int build_blocks_per_cu<T>(int);                                                                       \
   template void launch_contacts_export<T>(const PosRec *, const Nbr<T> &, const T *, int, int, uint32_t *, double *, \
                                           long, unsigned long long *, uint8_t *, double *, hipStream_t);           \
   template void launch_contacts_import<T>(const PosRec *, int, int, const uint32_t *, const double *, long,          \
-                                          const uint8_t *, const double *, int32_t *, uint32_t *, Spring<T> *,     \
-                                          uint32_t *, T *, uint32_t *, hipStream_t);                                      \
+                                          const uint8_t *, const double *, int32_t *, uint32_t *, const Nbr<T> &,  \
+                                          T *, uint32_t *, hipStream_t);                                      \
   template void launch_pairs<T>(const Dyn<T> &, const Props<T> &, const Nbr<T> &, int, int, uint32_t *, long,         \
                                 unsigned long long *, hipStream_t);
 INST(float)

@@ -41,15 +41,13 @@ void launch_scatter(const int32_t *key, const int32_t *slot, const int32_t *star
 void launch_cellrank(const int32_t *start, const int32_t *perm, const CellOrd &co, int n, int32_t *perm_out,
                      hipStream_t s, const uint32_t *gate = nullptr);
 // permute (d, p) by perm through the spare buffers and copy back, so the
-// parcels stay in d and p; resets the displacement maxima and xref
+// parcels stay in d and p; resets the displacement maxima and xref; moves
+// the contact springs of the current lists nb to the new positions in their
+// own slots (carry[s * N + j]) with the old contact masks (carry_mask[j])
 template <typename T>
 void launch_permute(const int32_t *perm, int n, const Dyn<T> &d, const Props<T> &p, const Dyn<T> &spare,
-                    const Props<T> &pspare, float4 *xref, unsigned *dslot, hipStream_t s, const uint32_t *gate);
-// compact the contact springs of the current lists (carry[k * N + p],
-// carry_meta[p] = (wall bits << 16) | count) before a rebuild
-template <typename T>
-void launch_carry(const Nbr<T> &nb, int n, Spring<T> *carry, uint32_t *carry_meta, hipStream_t s,
-                  const uint32_t *gate);
+                    const Props<T> &pspare, float4 *xref, unsigned *dslot, const Nbr<T> &nb, Spring<T> *carry,
+                    uint64_t *carry_mask, hipStream_t s, const uint32_t *gate);
 // set *flag when the lists could go stale within `horizon` steps (or force)
 void launch_rebuild_check(const unsigned *dslot, int par_last, double skin, double dt, int horizon, int force,
                           uint32_t *flag, unsigned long long *count, hipStream_t s);
@@ -61,10 +59,9 @@ template <typename T>
 struct NbrBuild {
   Dyn<T> d;             // sorted state (after the permutation)
   Props<T> p;           // sorted properties
-  const int32_t *perm;  // new position -> old position
   Nbr<T> nb;            // the lists written
-  const Spring<T> *carry;       // springs of the old lists (launch_carry), by old position
-  const uint32_t *carry_meta;
+  const Spring<T> *carry;       // springs of the old lists (launch_permute), by new position and old slot
+  const uint64_t *carry_mask;   // old contact masks by new position
   const uint32_t *gate;
   const BedDev *beds;
   const int32_t *start;
@@ -90,8 +87,8 @@ void launch_pairs(const Dyn<T> &d, const Props<T> &p, const Nbr<T> &nb, int n, i
                   unsigned long long *count, hipStream_t s);
 
 // contact history for checkpoints: export (pairs in contact, a < b, and
-// wall springs by original id) and import into the carry buffer of the next
-// rebuild (inv, cnt: n ints of scratch)
+// wall springs by original id) and import into the current lists, for the
+// next rebuild to carry (inv, cnt: n ints of scratch)
 template <typename T>
 void launch_contacts_export(const PosRec *pos, const Nbr<T> &nb, const T *wh, int n, int cap_slots, uint32_t *ids,
                             double *xi, long cap, unsigned long long *count, uint8_t *wall_on, double *wall_xi,
@@ -99,7 +96,7 @@ void launch_contacts_export(const PosRec *pos, const Nbr<T> &nb, const T *wh, in
 template <typename T>
 void launch_contacts_import(const PosRec *pos, int n, int cap_slots, const uint32_t *ids, const double *xi, long np,
                             const uint8_t *wall_on, const double *wall_xi, int32_t *inv, uint32_t *cnt,
-                            Spring<T> *carry, uint32_t *carry_meta, T *wh, uint32_t *status, hipStream_t s);
+                            const Nbr<T> &nb, T *wh, uint32_t *status, hipStream_t s);
 
 // ---------------------------------------------------------------- k_step.hip
 template <typename T>

@@ -624,6 +624,30 @@ def test_headline_bed_full_size_one_step():
     _full_size_check(W.cfg3, 0.96, "cfg3")
 
 
+def test_neighbour_build_cuts_long_rows_full_size():
+    """On the pressed 2M bed, 32-cell work items with a 1024-record LDS tile
+    stage stencil rows of up to about 2,000 parcels, which the build cuts into
+    segments.  The pairs found through those lists equal the oracle's, and
+    the forces equal, bit for bit, those from 8-cell items with a 2048 tile
+    (no row is cut there)."""
+    w = W.with_velocities(W.squeeze(W.cfg3(), 0.97, 0), 8, vscale=0.03, wscale=20.0)
+    _say(f"[segments] {w.n} parcels")
+    po = O.Oracle(w).pairs()
+    out = []
+    for shape in ((256, 1024, 32), (512, 2048, 8)):
+        bed = Bed(w)
+        bed.set_build(*shape)
+        bed.set_contacts(bed.contacts())  # rebuild the lists in this shape
+        st = bed.stats()
+        assert (st["build_threads"], st["build_tile"], st["build_item_x"]) == shape
+        pg = bed.pairs()
+        assert len(po) > 10000 and np.array_equal(pg, po), shape
+        out.append(bed.forces())
+        bed.close()
+    (F0, T0), (F1, T1) = out
+    assert torch.equal(F0, F1) and torch.equal(T0, T1)
+
+
 def _nonspherical(w, psi=0.86):
     return W.dataclasses.replace(w, ores=[W.dataclasses.replace(o, psi=psi) for o in w.ores])
 
