@@ -153,7 +153,7 @@ struct Ctx final : dem_ctx {
   Nbr<T> nb{};
   Spring<T> *carry = nullptr;      // springs carried across a rebuild (launch_permute)
   uint64_t *carry_mask = nullptr;  // old contact masks by new position (launch_permute)
-  uint32_t *rb_flag = nullptr;     // set by the rebuild check: rebuild at this check point
+  uint32_t *rb_flag = nullptr;     // set by the rebuild check: [0] rebuild at this check point, [1] its complement
   unsigned long long *rb_count = nullptr;  // rebuilds done (device counter)
   int cur = 0;
   int32_t *key = nullptr, *slot = nullptr, *count = nullptr, *start = nullptr, *perm = nullptr, *scan_scr = nullptr;
@@ -186,6 +186,9 @@ struct Ctx final : dem_ctx {
   long pairs_cap = 0;
   long step_count = 0;
   bool built = false;
+  // step count of the last rebuild check: while no step has followed it,
+  // rb_flag tells whether the parcels were sorted at the current positions
+  long chain_step = -1;
   int step_block = 64, step_xcd = 1;
   // neighbour build: variant (block size, LDS tile), item width, grid
   // (0: resident blocks per CU x CUs)
@@ -360,7 +363,7 @@ struct Ctx final : dem_ctx {
     TRY(alloc_props(pr, nullptr));
     TRY(alloc_props(pr_sp, &pr));
     TRY(alloc_nbr(nb));
-    TRY(dalloc(rb_flag, 1));
+    TRY(dalloc(rb_flag, 2));
     TRY(dalloc(rb_count, 1));
     TRY(dalloc(key, n)); TRY(dalloc(slot, n)); TRY(dalloc(perm, n)); TRY(dalloc(perm2, n));
     TRY(dalloc(cord.x, n)); TRY(dalloc(cord.id, n)); TRY(dalloc(cord.key, n));
@@ -466,6 +469,7 @@ struct Ctx final : dem_ctx {
   }
   int rebuild_chain(int horizon, bool force) {
     const uint32_t *G = rb_flag;
+    chain_step = step_count;
     launch_rebuild_check(dslot, (int)((step_count & 1) ^ 1), P.skin, P.dt, horizon, force ? 1 : 0, rb_flag,
                          rb_count, st);
     launch_fill_i32(count, 0, (long)n_keys + 1, st, G);
@@ -503,13 +507,18 @@ struct Ctx final : dem_ctx {
 
   // Cell order of the current positions (bin, scan, scatter, in-cell rank):
   // the parcels stay where they are; deposits and cell sums read them through
-  // order_d.  Deterministic like the full sort.
+  // order_d.  Deterministic like the full sort.  Right after a rebuild check
+  // (no step since), a rebuild has left the parcels in exactly this order
+  // when it ran: then the sort is skipped on the device and the order is
+  // the identity over the rebuild's cell offsets.
   int resort() {
-    launch_fill_i32(count, 0, (long)n_keys + 1, st);
-    launch_bin<T>(dyn[cur], pr, beds, n, key, slot, count, status, st);
-    launch_scan(count, start_d, (long)n_keys + 1, scan_scr, st);
-    launch_scatter(key, slot, start_d, dyn[cur].pos, n, perm2, cord, st);
-    launch_cellrank(start_d, perm2, cord, n, order_d, st);
+    const uint32_t *G = chain_step == step_count ? rb_flag + 1 : nullptr;
+    if (G) launch_cell_identity(order_d, n, start, start_d, (long)n_keys + 1, st, rb_flag);
+    launch_fill_i32(count, 0, (long)n_keys + 1, st, G);
+    launch_bin<T>(dyn[cur], pr, beds, n, key, slot, count, status, st, G);
+    launch_scan(count, start_d, (long)n_keys + 1, scan_scr, st, G);
+    launch_scatter(key, slot, start_d, dyn[cur].pos, n, perm2, cord, st, G);
+    launch_cellrank(start_d, perm2, cord, n, order_d, st, G);
     HIPCHK(hipGetLastError());
     dep_fresh = true;
     occ_fresh = false;
@@ -600,8 +609,11 @@ struct Ctx final : dem_ctx {
     return DEMRX_OK;
   }
 
-  // The lists are checked before every step whose index is a multiple of
-  // check_every, eagerly and in graphs alike, so both take the same decisions.
+  // The lists are checked at every step count that is a multiple of
+  // check_every: right after the step that reaches it (so that a coupling
+  // there finds the parcels sorted when they were rebuilt), or before the
+  // next step when no check has run at that count yet.  Eager calls and
+  // graphs take the same decisions.
   int check_period() const { return std::max(1, P.check_every); }
   bool check_due() const { return !built || step_count % check_period() == 0; }
   // steps from a due check to the next one
@@ -631,8 +643,10 @@ struct Ctx final : dem_ctx {
 
   // One step with the list check in front of it when one is due.
   int step_checked(bool count = false) {
-    if (check_due()) TRY(rebuild_chain(check_horizon(), !built));
-    return step_one(count);
+    if (check_due() && chain_step != step_count) TRY(rebuild_chain(check_horizon(), !built));
+    TRY(step_one(count));
+    if (check_due()) TRY(rebuild_chain(check_horizon(), false));
+    return DEMRX_OK;
   }
 
   int step(int ns, const dem_gas *g) override {
@@ -1049,6 +1063,9 @@ struct Ctx final : dem_ctx {
     }
     if (!built) TRY(rebuild_chain(1, true));  // a forced first build stays out of the graph
     TRY(ensure_occ());  // every interval, the first included, starts from a fresh occupied list
+    // whether the lists were checked at the current positions decides the
+    // first step's check, so it is part of what the graph bakes in
+    k.push_back((const void *)(intptr_t)(chain_step == step_count ? 1 : 0));
     HIPCHK(hipEventRecord(ev_a, user_st));
     HIPCHK(hipStreamWaitEvent(cap_st, ev_a, 0));
     st = cap_st;
@@ -1072,6 +1089,7 @@ struct Ctx final : dem_ctx {
       const int s_cur = cur;
       const long s_sc = step_count;
       const bool s_dep = dep_fresh, s_occ = occ_fresh;
+      const long s_chain = chain_step;
       HIPCHK(hipStreamBeginCapture(cap_st, hipStreamCaptureModeRelaxed));
       capturing = true;
       prof_capture.clear();
@@ -1093,6 +1111,8 @@ struct Ctx final : dem_ctx {
       gprof = prof;
       dep_after_graph = dep_fresh;
       occ_after_graph = occ_fresh;
+      chain_after_graph = chain_step == step_count;
+      chain_step = s_chain;
       cur = s_cur;
       step_count = s_sc;
       dep_fresh = s_dep;
@@ -1108,11 +1128,12 @@ struct Ctx final : dem_ctx {
       step_count += (long)G * S;
       dep_fresh = dep_after_graph;
       occ_fresh = occ_after_graph;
+      chain_step = chain_after_graph ? step_count : -1;
     }
     for (int q = 0; q < n_int % G; q++) TRY(interval(S, g, o));
     return DEMRX_OK;
   }
-  bool dep_after_graph = false, occ_after_graph = false;
+  bool dep_after_graph = false, occ_after_graph = false, chain_after_graph = false;
   bool gprof = false;
 
   // Autotuner cache: a JSON object whose members (one per line) map a key of

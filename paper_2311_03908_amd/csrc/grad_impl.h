@@ -185,6 +185,7 @@ int Ctx<T>::grad(const dem_grad_spec *s, const dem_gas *g, const double *theta, 
   step_count = sc0;
   built = true;
   dep_fresh = false;
+  chain_step = -1;
   const Dyn<T> &d1 = dyn[cur];
   const Props<T> &p1 = pr;
   const Nbr<T> &b1 = nb;

@@ -343,7 +343,8 @@ __global__ void k_rebuild_check(const unsigned *dslot, int par_last, float lim, 
   }
   if (t == 0) {
     const bool rb = force || !(sqrtf(d2) + grow * sqrtf(v2) < lim);
-    *flag = rb ? 1u : 0u;
+    flag[0] = rb ? 1u : 0u;
+    flag[1] = rb ? 0u : 1u;
     if (rb) *count += 1ull;
   }
 }
@@ -352,6 +353,22 @@ void launch_rebuild_check(const unsigned *dslot, int par_last, double skin, doub
                           uint32_t *flag, unsigned long long *count, hipStream_t s) {
   const float lim = 0.5f * (float)skin - 1e-7f;
   k_rebuild_check<<<1, 64, 0, s>>>(dslot, par_last, lim, (float)(2.0 * horizon * dt), force, flag, count);
+}
+
+__global__ void k_cell_identity(int32_t *order, int n, const int32_t *start, int32_t *start_d, long n_start,
+                                const uint32_t *gate) {
+  if (gated_off(gate)) return;
+  const long m = n > n_start ? (long)n : n_start;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < m; k += (long)gridDim.x * blockDim.x) {
+    if (k < n) order[k] = (int32_t)k;
+    if (k < n_start) start_d[k] = start[k];
+  }
+}
+
+void launch_cell_identity(int32_t *order, int n, const int32_t *start, int32_t *start_d, long n_start, hipStream_t s,
+                          const uint32_t *gate) {
+  k_cell_identity<<<grid_for(n > n_start ? (long)n : n_start, 256), 256, 0, s>>>(order, n, start, start_d, n_start,
+                                                                                   gate);
 }
 
 // ------------------------------------------------------------------ work items

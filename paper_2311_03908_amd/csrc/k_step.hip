@@ -101,7 +101,6 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
     const T zi_ = Vi.zeta;
     const uint32_t idi = P.id;
     const int32_t tag = a.pr.tag[i];
-    const int cnt = a.nb.cnt[i];
     const uint64_t mold = a.nb.mask[i];
     uint64_t mnew = 0;
     T F[3] = {T(0), T(0), T(0)}, Tq[3] = {T(0), T(0), T(0)};
@@ -114,7 +113,29 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
     // slot-major tangential springs of one visit are contiguous rows.
     // Indices and position records are requested kPre slots at a time so
     // that the gathers overlap; the records land in the wave's LDS rows.
+    // Both loops run to the wave's largest count (cmax), the same for every
+    // lane, so the lanes leave them together.
+    const int cnt = a.nb.cnt[i];
     const int c_near = cnt >> 16, c_far = cnt & 0xffff;
+    // the wave's largest near and far counts.  Active lanes are a prefix of
+    // the wave (the parcels past the end sit in its top lanes); a value read
+    // from an inactive lane counts 0.  In the xor butterfly, lane 0 then
+    // still combines every active lane: whenever it (or a lane feeding it)
+    // reads an inactive lane, every lane behind that one is past the end too.
+    int2 cmax;
+    {
+      const uint64_t act = __builtin_amdgcn_read_exec();
+      const int lane = (int)(threadIdx.x & 63);
+      int cn = c_near, cf = c_far;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const bool on = (act >> (lane ^ o)) & 1ull;
+        const int vn = __shfl_xor(cn, o, 64), vf = __shfl_xor(cf, o, 64);
+        cn = max(cn, on ? vn : 0);
+        cf = max(cf, on ? vf : 0);
+      }
+      cmax = make_int2(__builtin_amdgcn_readfirstlane(cn), __builtin_amdgcn_readfirstlane(cf));
+    }
     const int cap = a.ph.max_nbr;
     uint64_t cbits = 0;
     auto pair = [&](int s, int j, const PosRec &Q) {
@@ -174,7 +195,7 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
       n_pp++;
     };
     constexpr int kPre = kLand;
-    for (int t0 = 0; t0 < c_near; t0 += kPre) {
+    for (int t0 = 0; t0 < cmax.x; t0 += kPre) {
       int jj[kPre];
 #pragma unroll
       for (int k = 0; k < kPre; k++) jj[k] = (t0 + k < c_near) ? a.nb.idx[(long)(cap - 1 - t0 - k) * N + i] : -1;
@@ -192,7 +213,7 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
       int jn[kPre];
 #pragma unroll
       for (int k = 0; k < kPre; k++) jn[k] = (k < c_far) ? a.nb.idx[(long)k * N + i] : -1;
-      for (int t0 = 0; t0 < c_far; t0 += kPre) {
+      for (int t0 = 0; t0 < cmax.y; t0 += kPre) {
         int jj[kPre];
 #pragma unroll
         for (int k = 0; k < kPre; k++) jj[k] = jn[k];

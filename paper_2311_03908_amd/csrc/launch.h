@@ -48,9 +48,14 @@ template <typename T>
 void launch_permute(const int32_t *perm, int n, const Dyn<T> &d, const Props<T> &p, const Dyn<T> &spare,
                     const Props<T> &pspare, float4 *xref, unsigned *dslot, const Nbr<T> &nb, Spring<T> *carry,
                     uint64_t *carry_mask, hipStream_t s, const uint32_t *gate);
-// set *flag when the lists could go stale within `horizon` steps (or force)
+// flag[0] = 1 when the lists could go stale within `horizon` steps (or
+// force), else 0; flag[1] = its complement
 void launch_rebuild_check(const unsigned *dslot, int par_last, double skin, double dt, int horizon, int force,
                           uint32_t *flag, unsigned long long *count, hipStream_t s);
+// the cell order of parcels that a rebuild has just sorted: order[k] = k and
+// start_d = start (n_start offsets); gated like the rebuild chain
+void launch_cell_identity(int32_t *order, int n, const int32_t *start, int32_t *start_d, long n_start, hipStream_t s,
+                          const uint32_t *gate);
 void launch_items(const Item *items, int n_items, int item_x, const BedDev *beds, const int32_t *start, int32_t *flags,
                   int32_t *offs, int32_t *scratch, int32_t *list, int32_t *count, hipStream_t s,
                   const uint32_t *gate);
