@@ -166,9 +166,11 @@ struct Ctx final : dem_ctx {
   bool occ_fresh = false;  // occupied-cell list of the current cell order
   int32_t *occ_flags = nullptr, *occ_offs = nullptr, *occ_list = nullptr, *occ_count = nullptr;
   int4 *bchunks = nullptr;
+  bool bchunks_ready = false;  // chunk table of the bed means built (it never changes)
   double *bpartial = nullptr;
   int max_chunks = 0;
-  int32_t *iflags = nullptr, *ioffs = nullptr, *ilist = nullptr, *icount = nullptr;
+  int32_t *ilist = nullptr, *icount = nullptr;  // work items holding parcels; [0] count, [1] build queue
+  int32_t *ibcount = nullptr;                    // items holding parcels per 256 (launch_items)
   T *gtab = nullptr;
   ThermoTab *thermo = nullptr;    // energy equation only
   const double *gas_T = nullptr;  // gas temperature of the last gas table (energy equation)
@@ -374,10 +376,8 @@ struct Ctx final : dem_ctx {
     TRY(dalloc(start_d, (size_t)n_keys + 1)); TRY(dalloc(order_d, n));
     TRY(dalloc(occ_flags, (size_t)n_gas + 1)); TRY(dalloc(occ_offs, (size_t)n_gas + 1));
     TRY(dalloc(occ_list, n_gas)); TRY(dalloc(occ_count, 1));
-    const long scr = std::max(scan_scratch_ints((long)n_keys + 1), scan_scratch_ints((long)n_items_max + 1));
-    TRY(dalloc(scan_scr, scr));
-    TRY(dalloc(iflags, (size_t)n_items_max + 1)); TRY(dalloc(ioffs, (size_t)n_items_max + 1));
-    TRY(dalloc(ilist, n_items_max)); TRY(dalloc(icount, 2));
+    TRY(dalloc(scan_scr, scan_scratch_ints((long)n_keys + 1)));
+    TRY(dalloc(ilist, n_items_max)); TRY(dalloc(icount, 2)); TRY(dalloc(ibcount, n_items_max / 256 + 1));
     TRY(dalloc(gtab, (size_t)n_gas * kGasRow));
     TRY(dalloc(eps, n_gas));
     TRY(dalloc(zrange, hbd.size()));
@@ -410,6 +410,7 @@ struct Ctx final : dem_ctx {
     launch_fill_u32(dslot, 0u, 2 * kSlots * kSlotPad, st);
     launch_fill_u32((uint32_t *)cslot, 0u, 2 * kSlots * kSlotPad64, st);
     launch_fill_u32((uint32_t *)counters, 0u, 8, st);
+    launch_fill_i32(count, 0, (long)n_keys + 1, st);  // cell counters: zero between sorts
     launch_init<T>(*in, n, ph, p->n_ores, thermo, dyn[0], pr, status, st);
     HIPCHK(hipGetLastError());
     TRY(check_status());
@@ -471,14 +472,14 @@ struct Ctx final : dem_ctx {
     const uint32_t *G = rb_flag;
     chain_step = step_count;
     launch_rebuild_check(dslot, (int)((step_count & 1) ^ 1), P.skin, P.dt, horizon, force ? 1 : 0, rb_flag,
-                         rb_count, st);
-    launch_fill_i32(count, 0, (long)n_keys + 1, st, G);
+                         rb_count, icount, st);
+    // the cell counters are zero here: every scan of them clears them
     launch_bin<T>(dyn[cur], pr, beds, n, key, slot, count, status, st, G);
-    launch_scan(count, start, (long)n_keys + 1, scan_scr, st, G);
+    launch_scan(count, start, (long)n_keys + 1, scan_scr, st, G, true);
     launch_scatter(key, slot, start, dyn[cur].pos, n, perm2, cord, st, G);
     launch_cellrank(start, perm2, cord, n, perm, st, G);
     launch_permute<T>(perm, n, dyn[cur], pr, dyn[cur ^ 1], pr_sp, xref, dslot, nb, carry, carry_mask, st, G);
-    launch_items(items, n_items, item_x, beds, start, iflags, ioffs, scan_scr, ilist, icount, st, G);
+    launch_items(items, n_items, item_x, beds, start, ibcount, ilist, icount, st, G);
     NbrBuild<T> a;
     a.d = dyn[cur];
     a.p = pr;
@@ -496,8 +497,7 @@ struct Ctx final : dem_ctx {
     a.item_x = item_x;
     a.skin = P.skin;
     a.status = status;
-    a.queue = icount + 1;
-    launch_fill_i32(a.queue, 0, 1, st, G);
+    a.queue = icount + 1;  // zeroed by the check
     launch_build_nbr<T>(a, build_variant, build_grid_now(), st);
     HIPCHK(hipGetLastError());
     built = true;
@@ -514,9 +514,8 @@ struct Ctx final : dem_ctx {
   int resort() {
     const uint32_t *G = chain_step == step_count ? rb_flag + 1 : nullptr;
     if (G) launch_cell_identity(order_d, n, start, start_d, (long)n_keys + 1, st, rb_flag);
-    launch_fill_i32(count, 0, (long)n_keys + 1, st, G);
     launch_bin<T>(dyn[cur], pr, beds, n, key, slot, count, status, st, G);
-    launch_scan(count, start_d, (long)n_keys + 1, scan_scr, st, G);
+    launch_scan(count, start_d, (long)n_keys + 1, scan_scr, st, G, true);
     launch_scatter(key, slot, start_d, dyn[cur].pos, n, perm2, cord, st, G);
     launch_cellrank(start_d, perm2, cord, n, order_d, st, G);
     HIPCHK(hipGetLastError());
@@ -725,7 +724,12 @@ struct Ctx final : dem_ctx {
         launch_cellsum(pm, n, start_d, order_d, cell_bed, beds, n_gas, occ_flags, occ_list, occ_count, n_gas, cs, st);
       }
     }
-    if (bed_sum) launch_bedsum(pw, n, start, beds, P.n_beds, bchunks, max_chunks, bpartial, bed_fov_d, st);
+    if (bed_sum) {
+      // the table is built at the first eager call (a graph being captured
+      // builds its own until then: captured work runs only when launched)
+      launch_bedsum(pw, n, start, beds, P.n_beds, bchunks, max_chunks, bpartial, bed_fov_d, !bchunks_ready, st);
+      if (!capturing) bchunks_ready = true;
+    }
     HIPCHK(hipGetLastError());
     return DEMRX_OK;
   }
@@ -1063,6 +1067,10 @@ struct Ctx final : dem_ctx {
     }
     if (!built) TRY(rebuild_chain(1, true));  // a forced first build stays out of the graph
     TRY(ensure_occ());  // every interval, the first included, starts from a fresh occupied list
+    if (!bchunks_ready) {  // the chunk table of the bed means, once and outside the graph
+      launch_bedsum(nullptr, n, start, beds, P.n_beds, bchunks, max_chunks, bpartial, bed_fov_d, true, st);
+      bchunks_ready = true;
+    }
     // whether the lists were checked at the current positions decides the
     // first step's check, so it is part of what the graph bakes in
     k.push_back((const void *)(intptr_t)(chain_step == step_count ? 1 : 0));

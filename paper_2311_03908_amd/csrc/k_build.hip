@@ -63,8 +63,13 @@ __device__ int block_exclusive_scan(int v, int *lds, int &total) {
   return r;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const int32_t *in, int32_t *out, int32_t *bsum, long m,
-                                                              const uint32_t *gate) {
+// Exclusive scan: tiles, then the tile sums (one block), then the offsets.
+// With `clear` the input is zeroed as it is read (a counter array that must
+// start its next use at zero).  (A single-pass variant that lets the last
+// tile's block scan the tile sums needs a device-scope fence per block,
+// which writes back the XCD's L2 each time: slower here than a launch.)
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(int32_t *in, int32_t *out, int32_t *bsum, long m,
+                                                              int clear, const uint32_t *gate) {
   if (gated_off(gate)) return;
   __shared__ int lds[16];
   const long base = (long)blockIdx.x * kScanTile + (long)threadIdx.x * kScanItems;
@@ -74,6 +79,11 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const int32_t *in, 
   for (int k = 0; k < kScanItems; k++) {
     v[k] = (base + k < m) ? in[base + k] : 0;
     sum += v[k];
+  }
+  if (clear) {
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++)
+      if (base + k < m) in[base + k] = 0;
   }
   int total;
   int run = block_exclusive_scan(sum, lds, total);
@@ -121,9 +131,10 @@ __global__ void k_scan_add(int32_t *out, const int32_t *bsum, long m, const uint
 
 long scan_scratch_ints(long m) { return (m + kScanTile - 1) / kScanTile + 1; }
 
-void launch_scan(const int32_t *in, int32_t *out, long m, int32_t *scratch, hipStream_t s, const uint32_t *gate) {
+void launch_scan(int32_t *in, int32_t *out, long m, int32_t *scratch, hipStream_t s, const uint32_t *gate,
+                 bool clear) {
   const int nb = (int)((m + kScanTile - 1) / kScanTile);
-  k_scan_tiles<<<nb, kScanThreads, 0, s>>>(in, out, scratch, m, gate);
+  k_scan_tiles<<<nb, kScanThreads, 0, s>>>(in, out, scratch, m, clear ? 1 : 0, gate);
   k_scan_sums<<<1, kScanThreads, 0, s>>>(scratch, nb, gate);
   k_scan_add<<<nb, kScanThreads, 0, s>>>(out, scratch, m, gate);
 }
@@ -332,7 +343,7 @@ void launch_permute(const int32_t *perm, int n, const Dyn<T> &d, const Props<T> 
 // double within the horizon), could reach skin/2.  The step kernel's own
 // exact check stays as the safety net.  One block of 64 threads.
 __global__ void k_rebuild_check(const unsigned *dslot, int par_last, float lim, float grow, int force, uint32_t *flag,
-                                unsigned long long *count) {
+                                unsigned long long *count, int32_t *zero2) {
   const int t = threadIdx.x;
   float d2 = __uint_as_float(dslot[(par_last * kSlots + t) * kSlotPad]);
   float v2 = __uint_as_float(dslot[(par_last * kSlots + t) * kSlotPad + 1]);
@@ -346,13 +357,15 @@ __global__ void k_rebuild_check(const unsigned *dslot, int par_last, float lim, 
     flag[0] = rb ? 1u : 0u;
     flag[1] = rb ? 0u : 1u;
     if (rb) *count += 1ull;
+    zero2[0] = 0;  // item count and build queue of the chain behind the check
+    zero2[1] = 0;
   }
 }
 
 void launch_rebuild_check(const unsigned *dslot, int par_last, double skin, double dt, int horizon, int force,
-                          uint32_t *flag, unsigned long long *count, hipStream_t s) {
+                          uint32_t *flag, unsigned long long *count, int32_t *zero2, hipStream_t s) {
   const float lim = 0.5f * (float)skin - 1e-7f;
-  k_rebuild_check<<<1, 64, 0, s>>>(dslot, par_last, lim, (float)(2.0 * horizon * dt), force, flag, count);
+  k_rebuild_check<<<1, 64, 0, s>>>(dslot, par_last, lim, (float)(2.0 * horizon * dt), force, flag, count, zero2);
 }
 
 __global__ void k_cell_identity(int32_t *order, int n, const int32_t *start, int32_t *start_d, long n_start,
@@ -372,41 +385,63 @@ void launch_cell_identity(int32_t *order, int n, const int32_t *start, int32_t *
 }
 
 // ------------------------------------------------------------------ work items
-__global__ void k_item_flags(const Item *items, int n_items, int item_x, const BedDev *beds, const int32_t *start,
-                             int32_t *flags, const uint32_t *gate) {
-  if (gated_off(gate)) return;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t > n_items) return;
-  if (t == n_items) {
-    flags[t] = 0;
-    return;
-  }
+// The work items that hold parcels, in key order, in two launches: each
+// block counts its items holding parcels, then each block adds up the counts
+// of the blocks before it and writes its items there (wave ballots give the
+// order inside the block).  The build's queue counter starts at zero: the
+// rebuild check clears it.
+__device__ __forceinline__ bool item_has_parcels(const Item *items, int t, int item_x, const BedDev *beds,
+                                                 const int32_t *start) {
   const Item it = items[t];
   const BedDev &B = beds[it.bed];
   const int xe = min(it.x0 + item_x, B.nd[0]);
-  const int k0 = dem_key(B, it.x0, it.iy, it.iz);
-  const int k1 = dem_key(B, xe - 1, it.iy, it.iz) + 1;
-  flags[t] = start[k1] > start[k0] ? 1 : 0;
+  return start[dem_key(B, xe - 1, it.iy, it.iz) + 1] > start[dem_key(B, it.x0, it.iy, it.iz)];
 }
 
-__global__ void k_item_compact(const int32_t *flags, const int32_t *offs, int n_items, int32_t *list,
-                               int32_t *count, const uint32_t *gate) {
+__global__ void __launch_bounds__(256) k_item_counts(const Item *items, int n_items, int item_x, const BedDev *beds,
+                                                     const int32_t *start, int32_t *bcount, const uint32_t *gate) {
   if (gated_off(gate)) return;
+  __shared__ int wsum[4];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t > n_items) return;
-  if (t == n_items) {
-    *count = offs[n_items];
-    return;
-  }
-  if (flags[t]) list[offs[t]] = t;
+  const bool f = t < n_items && item_has_parcels(items, t, item_x, beds, start);
+  const uint64_t bal = __ballot(f);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = __popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) bcount[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
-void launch_items(const Item *items, int n_items, int item_x, const BedDev *beds, const int32_t *start, int32_t *flags,
-                  int32_t *offs, int32_t *scratch, int32_t *list, int32_t *count, hipStream_t s,
-                  const uint32_t *gate) {
-  k_item_flags<<<(n_items + 256) / 256, 256, 0, s>>>(items, n_items, item_x, beds, start, flags, gate);
-  launch_scan(flags, offs, n_items + 1, scratch, s, gate);
-  k_item_compact<<<(n_items + 256) / 256, 256, 0, s>>>(flags, offs, n_items, list, count, gate);
+__global__ void __launch_bounds__(256) k_items(const Item *items, int n_items, int item_x, const BedDev *beds,
+                                               const int32_t *start, const int32_t *bcount, int32_t *list,
+                                               int32_t *count, const uint32_t *gate) {
+  if (gated_off(gate)) return;
+  __shared__ int wsum[4], part[256];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  // this block's offset: the counts of the blocks before it
+  int o = 0;
+  for (int q = threadIdx.x; q < (int)blockIdx.x; q += blockDim.x) o += bcount[q];
+  part[threadIdx.x] = o;
+  const bool f = t < n_items && item_has_parcels(items, t, item_x, beds, start);
+  const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+  const uint64_t bal = __ballot(f);
+  if (lane == 0) wsum[w] = __popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int base = 0;
+    for (int q = 0; q < (int)blockDim.x; q++) base += part[q];
+    part[0] = base;
+    if (blockIdx.x == gridDim.x - 1) *count = base + wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  }
+  __syncthreads();
+  int off = part[0];
+  for (int q = 0; q < w; q++) off += wsum[q];
+  if (f) list[off + __popcll(bal & ((1ull << lane) - 1ull))] = t;
+}
+
+void launch_items(const Item *items, int n_items, int item_x, const BedDev *beds, const int32_t *start,
+                  int32_t *bcount, int32_t *list, int32_t *count, hipStream_t s, const uint32_t *gate) {
+  const int nb = (n_items + 255) / 256;
+  k_item_counts<<<nb, 256, 0, s>>>(items, n_items, item_x, beds, start, bcount, gate);
+  k_items<<<nb, 256, 0, s>>>(items, n_items, item_x, beds, start, bcount, list, count, gate);
 }
 
 // ------------------------------------------------------------------ neighbour build

@@ -461,13 +461,26 @@ void launch_react(const ReactArgs<T> &a, hipStream_t s) {
 // Cell sums of the per-parcel sources: one 16-lane group per occupied gas
 // cell of the compacted list (as the deposit), and zeros written to the
 // empty cells by one thread each.
+// Cell sums of the per-parcel sources in one launch: the first `be` blocks
+// write zeros for the empty cells, the others sum each listed (occupied)
+// cell with a 16-lane group.
 __global__ void __launch_bounds__(256) k_cellsum(const double *pm, int n, const int32_t *start, const int32_t *order,
-                                                 const int32_t *cell_bed, const BedDev *beds, const int32_t *list,
-                                                 const int32_t *list_count, CellSumOut o) {
+                                                 const int32_t *cell_bed, const BedDev *beds, const int32_t *flags,
+                                                 int n_gas, int be, const int32_t *list, const int32_t *list_count,
+                                                 CellSumOut o) {
+  if ((int)blockIdx.x < be) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n_gas; c += be * blockDim.x) {
+      if (flags[c]) continue;
+#pragma unroll
+      for (int q = 0; q < 8; q++)
+        if (q < o.rows && o.o[q]) o.o[q][c] = 0.0;
+    }
+    return;
+  }
   const int sl = threadIdx.x % kGroup;
   const int n_list = *list_count;
-  const int groups = gridDim.x * (blockDim.x / kGroup);
-  for (int gi = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup; gi < n_list; gi += groups) {
+  const int groups = ((int)gridDim.x - be) * (blockDim.x / kGroup);
+  for (int gi = (((int)blockIdx.x - be) * blockDim.x + threadIdx.x) / kGroup; gi < n_list; gi += groups) {
     const int c = list[gi];
     const GasCellRanges R(beds[cell_bed[c]], c);
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -492,21 +505,13 @@ __global__ void __launch_bounds__(256) k_cellsum(const double *pm, int n, const 
   }
 }
 
-__global__ void k_cellsum_empty(const int32_t *flags, int n_gas, CellSumOut o) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_gas || flags[c]) return;
-#pragma unroll
-  for (int q = 0; q < 8; q++)
-    if (q < o.rows && o.o[q]) o.o[q][c] = 0.0;
-}
-
 void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t *order, const int32_t *cell_bed,
                     const BedDev *beds, int n_gas, const int32_t *flags, const int32_t *list,
                     const int32_t *list_count, int max_list, const CellSumOut &o, hipStream_t s) {
-  k_cellsum_empty<<<(n_gas + 255) / 256, 256, 0, s>>>(flags, n_gas, o);
+  const int be = std::max(1, std::min((n_gas + 255) / 256, 2048));
   const int groups_per_block = 256 / kGroup;
-  const int blocks = std::max(1, std::min((max_list + groups_per_block - 1) / groups_per_block, 8192));
-  k_cellsum<<<blocks, 256, 0, s>>>(pm, n, start, order, cell_bed, beds, list, list_count, o);
+  const int bs = std::max(1, std::min((max_list + groups_per_block - 1) / groups_per_block, 8192));
+  k_cellsum<<<be + bs, 256, 0, s>>>(pm, n, start, order, cell_bed, beds, flags, n_gas, be, list, list_count, o);
 }
 
 // Bed-mean f_ov weighted by k^3 N_Fe: every bed's parcel range (contiguous,
@@ -620,8 +625,9 @@ __global__ void __launch_bounds__(256) k_bed_final(const int4 *chunks, int max_c
 }
 
 void launch_bedsum(const double *pw, int n, const int32_t *start, const BedDev *beds, int n_beds, int4 *chunks,
-                   int max_chunks, double *partial, double *bed_fov, hipStream_t s) {
-  k_bed_chunks<<<1, 256, 0, s>>>(start, beds, n_beds, chunks, max_chunks);
+                   int max_chunks, double *partial, double *bed_fov, bool table, hipStream_t s) {
+  if (table) k_bed_chunks<<<1, 256, 0, s>>>(start, beds, n_beds, chunks, max_chunks);
+  if (!pw) return;
   k_chunk_sum<<<max_chunks - 1, 256, 0, s>>>(pw, n, chunks, max_chunks, partial);
   k_bed_final<<<n_beds, 256, 0, s>>>(chunks, max_chunks, partial, bed_fov);
 }

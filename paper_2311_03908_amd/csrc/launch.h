@@ -22,10 +22,11 @@ constexpr int kSlots = 64, kSlotPad = 32, kSlotPad64 = 16;
 // run): with *gate == 0 their kernels return at once.
 void launch_fill_i32(int32_t *p, int32_t v, long n, hipStream_t s, const uint32_t *gate = nullptr);
 void launch_fill_u32(uint32_t *p, uint32_t v, long n, hipStream_t s);
-// exclusive prefix sum of m ints; scratch needs scan_scratch_ints(m) ints
+// exclusive prefix sum of m ints; scratch needs scan_scratch_ints(m) ints;
+// with clear, in is zeroed
 long scan_scratch_ints(long m);
-void launch_scan(const int32_t *in, int32_t *out, long m, int32_t *scratch, hipStream_t s,
-                 const uint32_t *gate = nullptr);
+void launch_scan(int32_t *in, int32_t *out, long m, int32_t *scratch, hipStream_t s, const uint32_t *gate = nullptr,
+                 bool clear = false);
 
 template <typename T>
 void launch_bin(const Dyn<T> &d, const Props<T> &p, const BedDev *beds, int n, int32_t *key, int32_t *slot,
@@ -49,16 +50,17 @@ void launch_permute(const int32_t *perm, int n, const Dyn<T> &d, const Props<T> 
                     const Props<T> &pspare, float4 *xref, unsigned *dslot, const Nbr<T> &nb, Spring<T> *carry,
                     uint64_t *carry_mask, hipStream_t s, const uint32_t *gate);
 // flag[0] = 1 when the lists could go stale within `horizon` steps (or
-// force), else 0; flag[1] = its complement
+// force), else 0; flag[1] = its complement; zero2[0..1] (the work-item count
+// and the build queue of the chain behind the check) set to 0
 void launch_rebuild_check(const unsigned *dslot, int par_last, double skin, double dt, int horizon, int force,
-                          uint32_t *flag, unsigned long long *count, hipStream_t s);
+                          uint32_t *flag, unsigned long long *count, int32_t *zero2, hipStream_t s);
 // the cell order of parcels that a rebuild has just sorted: order[k] = k and
 // start_d = start (n_start offsets); gated like the rebuild chain
 void launch_cell_identity(int32_t *order, int n, const int32_t *start, int32_t *start_d, long n_start, hipStream_t s,
                           const uint32_t *gate);
-void launch_items(const Item *items, int n_items, int item_x, const BedDev *beds, const int32_t *start, int32_t *flags,
-                  int32_t *offs, int32_t *scratch, int32_t *list, int32_t *count, hipStream_t s,
-                  const uint32_t *gate);
+// the work items holding parcels, in key order (bcount: one int per 256 items)
+void launch_items(const Item *items, int n_items, int item_x, const BedDev *beds, const int32_t *start,
+                  int32_t *bcount, int32_t *list, int32_t *count, hipStream_t s, const uint32_t *gate);
 
 template <typename T>
 struct NbrBuild {
@@ -196,8 +198,12 @@ void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t
                     const BedDev *beds, int n_gas, const int32_t *flags, const int32_t *list,
                     const int32_t *list_count, int max_list, const CellSumOut &o, hipStream_t s);
 constexpr int kBedChunk = 4096;  // parcels per partial sum of the bed means
+// bed means; with table set, the chunk table is built first from the beds'
+// parcel ranges (which no rebuild changes: the sort is bed-major and parcels
+// keep their bed), otherwise the table of an earlier call is used; a null
+// pw builds the table only
 void launch_bedsum(const double *pw, int n, const int32_t *start, const BedDev *beds, int n_beds, int4 *chunks,
-                   int max_chunks, double *partial, double *bed_fov, hipStream_t s);
+                   int max_chunks, double *partial, double *bed_fov, bool table, hipStream_t s);
 
 template <typename T>
 void launch_init(const dem_parcels &in, int n, const Phys &ph, int n_ores, const ThermoTab *thermo, const Dyn<T> &d,
