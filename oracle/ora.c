@@ -1419,6 +1419,46 @@ void ora_get(const ora_sys *s, double *x, double *y, double *z, double *vx, doub
   if (eps) memcpy(eps, s->eps, sizeof(double) * s->n_cells);
 }
 
+/* Test harness: the tangential springs held, for setting up both sides of a
+ * comparison from the same contact history.  Pairs (i < j, the spring in the
+ * orientation of i) go to ij / xi up to cap of them (the count is returned);
+ * won (6 per parcel) and wxi (18 per parcel) take the wall springs. */
+long ora_contacts(const ora_sys *s, int *ij, double *xi, long cap, unsigned char *won, double *wxi) {
+  long m = 0;
+  for (int i = 0; i < s->n; i++)
+    for (int q = 0; q < s->hcnt[i]; q++) {
+      if (m < cap) {
+        ij[2 * m] = i;
+        ij[2 * m + 1] = s->hist[(size_t)i * HCAP + q].partner;
+        for (int c = 0; c < 3; c++) xi[3 * m + c] = s->hist[(size_t)i * HCAP + q].xi[c];
+      }
+      m++;
+    }
+  if (won) memcpy(won, s->won, (size_t)6 * s->n);
+  if (wxi) memcpy(wxi, s->wxi, sizeof(double) * 18 * (size_t)s->n);
+  return m;
+}
+
+/* Test harness: replace the springs by the given ones (the layout of
+ * ora_contacts); returns -1 for a pair out of order or range, or when a
+ * parcel would hold more than HCAP partners. */
+int ora_set_contacts(ora_sys *s, const int *ij, const double *xi, long np, const unsigned char *won,
+                     const double *wxi) {
+  for (long m = 0; m < np; m++)
+    if (ij[2 * m] < 0 || ij[2 * m] >= ij[2 * m + 1] || ij[2 * m + 1] >= s->n) return -1;
+  for (int i = 0; i < s->n; i++) s->hcnt[i] = 0;
+  for (long m = 0; m < np; m++) {
+    const int i = ij[2 * m];
+    if (s->hcnt[i] == HCAP) return -1;
+    hist_t *h = &s->hist[(size_t)i * HCAP + s->hcnt[i]++];
+    h->partner = ij[2 * m + 1];
+    for (int c = 0; c < 3; c++) h->xi[c] = xi[3 * m + c];
+  }
+  memcpy(s->won, won, (size_t)6 * s->n);
+  memcpy(s->wxi, wxi, sizeof(double) * 18 * (size_t)s->n);
+  return 0;
+}
+
 /* particle temperatures (K, by id); m C_p,p follows, Q_r + Q_rm restarts at 0 */
 void ora_set_temperature(ora_sys *s, const double *Tp) {
   for (int i = 0; i < s->n; i++) {

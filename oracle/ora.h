@@ -105,6 +105,13 @@ long ora_react(ora_sys *s, double dt, const ora_gas *g, int update_mass, double 
                double *hA, double *hAT, double *Qrm, double *Hr);
 /* energy equation: per-parcel temperatures (K, by id; Q_r + Q_rm restarts at 0)
  * and the current temperature, k^3 (Q_r + Q_rm) and m C_p,p of every parcel */
+/* test harness: export / import of the tangential springs (pairs i < j with
+ * the spring in i's orientation; 6 wall flags and 18 wall-spring components
+ * per parcel); ora_contacts returns the pair count, ora_set_contacts -1 on a
+ * bad pair */
+long ora_contacts(const ora_sys *s, int *ij, double *xi, long cap, unsigned char *won, double *wxi);
+int ora_set_contacts(ora_sys *s, const int *ij, const double *xi, long np, const unsigned char *won,
+                     const double *wxi);
 void ora_set_temperature(ora_sys *s, const double *Tp);
 void ora_get_energy(const ora_sys *s, double *Tp, double *qrx, double *mcp);
 void ora_get(const ora_sys *s, double *x, double *y, double *z, double *vx, double *vy,

@@ -134,6 +134,10 @@ def lib():
         L.ora_nusselt.restype = C.c_double
         L.ora_nusselt.argtypes = [C.c_double] * 3
         L.ora_get.argtypes = [C.c_void_p] + [_dp] * 15
+        L.ora_contacts.restype = C.c_long
+        L.ora_contacts.argtypes = [C.c_void_p, _ip, _dp, C.c_long, C.POINTER(C.c_ubyte), _dp]
+        L.ora_set_contacts.restype = C.c_int
+        L.ora_set_contacts.argtypes = [C.c_void_p, _ip, _dp, C.c_long, C.POINTER(C.c_ubyte), _dp]
         L.ora_grad.argtypes = [C.c_void_p, C.POINTER(OraGas), C.c_int, C.c_double, C.c_int, _dp, _dp, _dp]
         for name in ("ora_e_cgp", "ora_zeta", "ora_knudsen_h2", "ora_keq"):
             getattr(L, name).restype = C.c_double
@@ -317,6 +321,29 @@ class Oracle:
         g = np.zeros(6)
         lib().ora_grad(self.h, C.byref(self._gs), int(n_sub), float(dt_react), int(dyn_every), _p(th), _p(J), _p(g))
         return float(J[0]), g
+
+    def contacts(self):
+        """Tangential springs held: ids (P, 2) with i < j, xi (P, 3) in i's
+        orientation, wall_on (n, 6), wall_xi (n, 6, 3) (ora_contacts)."""
+        cap = max(16, 4 * self.n)
+        while True:
+            ij = np.zeros(2 * cap, np.int32)
+            xi = np.zeros(3 * cap)
+            won = np.zeros(6 * self.n, np.uint8)
+            wxi = np.zeros(18 * self.n)
+            m = lib().ora_contacts(self.h, _p(ij, C.c_int), _p(xi), cap, _p(won, C.c_ubyte), _p(wxi))
+            if m <= cap:
+                return {"ids": ij[: 2 * m].reshape(-1, 2).astype(np.uint32), "xi": xi[: 3 * m].reshape(-1, 3),
+                        "wall_on": won.reshape(self.n, 6), "wall_xi": wxi.reshape(self.n, 6, 3)}
+            cap = int(m)
+
+    def set_contacts(self, ct):
+        ij = np.ascontiguousarray(ct["ids"], dtype=np.int32).reshape(-1)
+        xi = np.ascontiguousarray(ct["xi"], dtype=np.float64).reshape(-1)
+        won = np.ascontiguousarray(ct["wall_on"], dtype=np.uint8).reshape(-1)
+        wxi = np.ascontiguousarray(ct["wall_xi"], dtype=np.float64).reshape(-1)
+        if lib().ora_set_contacts(self.h, _p(ij, C.c_int), _p(xi), len(ij) // 2, _p(won, C.c_ubyte), _p(wxi)) != 0:
+            raise ValueError("bad contact pairs")
 
     def state(self):
         keys = ("x", "y", "z", "vx", "vy", "vz", "wx", "wy", "wz", "nh", "nm", "nw", "nfe", "mass")

@@ -171,6 +171,70 @@ def test_forces_touching_mixed(case):
         ora.step(1)
 
 
+
+def _springs32(ct):
+    """A contact history with its springs rounded to FP32 (what the mixed
+    path holds), so that both sides start from the same values."""
+    out = dict(ct)
+    out["xi"] = ct["xi"].astype(np.float32).astype(np.float64)
+    out["wall_xi"] = ct["wall_xi"].astype(np.float32).astype(np.float64)
+    return out
+
+
+@pytest.mark.parametrize("case", list(TOUCHING))
+def test_forces_with_carried_springs_mixed(case):
+    """Mixed precision with tangential springs carried: both sides start from
+    an oracle state three steps into a pressed, sliding bed together with the
+    oracle's springs (FP32-rounded), and their forces and torques agree to
+    the force gate.  Then both step once; the springs the mixed path carries
+    out of that step, evaluated by the oracle at the oracle's state, give the
+    forces that the oracle's own springs give, to the same gate (parcels of
+    a pair that is in contact on one side only are reported and must be
+    rare)."""
+    w = _rolling(TOUCHING[case]())
+    ora = O.Oracle(w)
+    ora.step(3)
+    ct = _springs32(ora.contacts())
+    _say(f"[carried] {case} n={w.n} pair springs={len(ct['ids'])} wall springs={int(ct['wall_on'].sum())}")
+    assert len(ct["ids"]) >= 50
+    wk = _from_state(w, ora.state())
+    ok = O.Oracle(wk)
+    ok.set_contacts(ct)
+    bed = Bed(wk)
+    bed.set_contacts(ct)
+    mass = ok.state()["mass"]
+    rg = mass * 9.81 * 0.5 * w.parcels["d"].astype(np.float64)
+    Fo, To = ok.forces()
+    Fs, Ts = ok.force_scale()
+    Fg, Tg = bed.forces()
+    ef = _force_err(_np(Fg), Fo, mass, Fs)
+    et = _torque_err(_np(Tg), To, rg, Ts)
+    _say(f"  same springs: force err {ef:.2e} torque err {et:.2e}")
+    assert ef <= 1e-5 and et <= 1e-5, (ef, et)
+    ok.step(1)
+    bed.step(1)
+    cg = bed.contacts()
+    co = _springs32(ok.contacts())
+    ws = _from_state(wk, ok.state())
+    with_gpu, with_ora = O.Oracle(ws), O.Oracle(ws)
+    with_gpu.set_contacts(cg)
+    with_ora.set_contacts(co)
+    F2, T2 = with_gpu.forces()
+    F3, T3 = with_ora.forces()
+    Fs3, Ts3 = with_ora.force_scale()
+    pg = {tuple(p) for p in cg["ids"].tolist()}
+    po = {tuple(p) for p in co["ids"].tolist()}
+    odd = np.unique(np.array(sorted(pg ^ po), dtype=np.int64).reshape(-1))
+    keep = np.ones(w.n, bool)
+    keep[odd] = False
+    ef2 = _force_err(F2[keep], F3[keep], mass[keep], Fs3[keep])
+    et2 = _torque_err(T2[keep], T3[keep], rg[keep], Ts3[keep])
+    _say(f"  carried out of one step: {len(pg & po)} pairs on both sides, {len(pg ^ po)} on one side; "
+         f"force err {ef2:.2e} torque err {et2:.2e}")
+    assert len(pg ^ po) <= max(2, len(po) // 100)
+    assert ef2 <= 1e-5 and et2 <= 1e-5, (ef2, et2)
+
+
 def _drag_branch_edge():
     """A cfg5-type bed in which one gas cell's FP64 voidage lies just below
     the 0.8 switch of the Gidaspow drag but rounds to 0.8 in FP32: one

@@ -386,3 +386,33 @@ def test_perturbed_step_fp32_storage():
         floor = 1e-3 if k[0] == "v" else 1e-3 / (0.5 * d)  # 1 mm/s at the surface
         rel = np.abs(sb[k] - sa[k]) / np.maximum(np.abs(sa[k]), floor)
         assert 0 < rel.max() < 1e-4, k
+
+
+def test_spring_export_import_round_trip():
+    """The oracle's spring export and import (test harness for comparisons
+    that start both sides from one contact history): a round trip keeps the
+    springs and the forces bit for bit, the springs carry the torques of a
+    pressed, sliding bed (dropping them changes them), and a pair out of
+    order is refused."""
+    w = W.with_velocities(W.squeeze(W.cfg2(n=3000, seed=22), 0.98, 0), 31, vscale=0.03, wscale=20.0)
+    w.params["gt_over_gn"] = 0.2
+    ora = O.Oracle(w)
+    ora.step(3)
+    ct = ora.contacts()
+    assert len(ct["ids"]) > 50 and ct["wall_on"].sum() > 5
+    assert np.all(ct["ids"][:, 0] < ct["ids"][:, 1])
+    F0, T0 = ora.forces()
+    ora.set_contacts(ct)
+    F1, T1 = ora.forces()
+    assert np.array_equal(F0, F1) and np.array_equal(T0, T1)
+    ct2 = ora.contacts()
+    assert all(np.array_equal(ct[k], ct2[k]) for k in ct)
+    none = {"ids": ct["ids"][:0], "xi": ct["xi"][:0], "wall_on": np.zeros_like(ct["wall_on"]),
+            "wall_xi": np.zeros_like(ct["wall_xi"])}
+    ora.set_contacts(none)
+    _, T2 = ora.forces()
+    assert np.max(np.abs(T2 - T0)) > 0.1 * np.max(np.abs(T0))
+    bad = dict(ct)
+    bad["ids"] = ct["ids"][:, ::-1].copy()
+    with pytest.raises(ValueError):
+        ora.set_contacts(bad)
