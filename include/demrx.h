@@ -188,8 +188,10 @@ int dem_init(const dem_params *p, const dem_parcels *in, int32_t n, void *stream
 /* Advance n_steps DEM steps with the gas frozen (eq. e3-3, e3-6; semi-implicit
  * Euler): contact detection, soft-sphere parcel-parcel and parcel-wall forces,
  * Gidaspow drag with the voidage of the last deposit, gravity and -V grad p.
- * The neighbour lists are checked every check_every steps and rebuilt on the
- * device when the displacement bound requires it (no host synchronisation);
+ * The neighbour lists are checked at every step count that is a multiple of
+ * check_every (right after the step that reaches it, or before the next step
+ * when that count has not been checked yet) and rebuilt on the device when
+ * the displacement bound requires it (no host synchronisation);
  * a step that still finds a parcel moved by skin/2 since the last build
  * latches DEMRX_ESKIN.  The per-cell drag rows (gas velocity, voidage,
  * pressure gradient, density, viscosity) are computed once per call; right
@@ -331,12 +333,14 @@ int dem_pairs_noalloc(dem_ctx *c, uint32_t *ij, int64_t cap, int64_t *n_pairs);
 int dem_get_stats(dem_ctx *c, dem_stats *out);
 
 /* Replay the full hot path -- couple_every DEM steps with the neighbour-list
- * check (and, when the displacement bound requires it, the rebuild) at the
- * first step of the interval and every check_every steps after it, the
- * coupling deposit and the reaction update (dt_cfd = couple_every * dt) --
- * n_intervals times from a HIP graph of two intervals captured on first use
- * (recaptured if the arguments change).  Whether a check rebuilds is decided
- * on the device, so the replays need no host synchronisation.  out and
+ * check (and, when the displacement bound requires it, the rebuild) at every
+ * step count that is a multiple of check_every, the coupling deposit and the
+ * reaction update (dt_cfd = couple_every * dt) -- n_intervals times from a
+ * HIP graph of the fewest intervals whose steps are a multiple of 2 and of
+ * check_every, captured on first use (recaptured if the arguments change).
+ * Whether a check rebuilds is decided on the device, so the replays need no
+ * host synchronisation; a coupling right after a rebuild reuses its sort of
+ * the parcels by cell.  out and
  * bed_fov (host) may be NULL; bed_fov receives the values after the last
  * interval and makes the call synchronise. */
 int dem_run(dem_ctx *c, int32_t n_intervals, int32_t couple_every, const dem_gas *g,
