@@ -148,10 +148,22 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
       // both partners obtain bit-identical values with opposite signs
       const bool ifirst = idi < Q.id;
       const T sgn = ifirst ? T(1) : T(-1);
-      const double dist = sqrt(d2);
-      const T inv = T(1) / T(dist);
+      // unit normal and overlap: in mixed precision from the single-precision
+      // reciprocal square root of the FP64 d^2, with the overlap as
+      // (s^2 - d^2) / (s + d) (the difference taken in FP64, the distance in
+      // the denominator needed only to FP32 accuracy); in FP64 from the
+      // correctly rounded distance
+      T inv, delta;
+      if constexpr (sizeof(T) == 4) {
+        const float d2f = (float)d2;
+        inv = __builtin_amdgcn_rsqf(d2f);
+        delta = (float)fma(sr, sr, -d2) * __builtin_amdgcn_rcpf((float)sr + d2f * inv);
+      } else {
+        const double dist = sqrt(d2);
+        inv = T(1) / T(dist);
+        delta = T(sr - dist);
+      }
       const T n[3] = {T(ifirst ? dx : -dx) * inv, T(ifirst ? dy : -dy) * inv, T(ifirst ? dz : -dz) * inv};
-      const T delta = T(sr - dist);
       const VelRec<T> Vj = a.in.vel[j];
       const T rj = T(Q.r);
       const T ra = ifirst ? ri : rj, rb = ifirst ? rj : ri;
