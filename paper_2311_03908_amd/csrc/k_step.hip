@@ -10,15 +10,44 @@
 
 namespace demrx {
 
+// Reciprocal, square root and reciprocal square root of the contact law: in
+// mixed precision the hardware's single-precision instructions (about 1 ulp;
+// the forces keep to the FP32 gate), in FP64 the correctly rounded ones.
+template <typename T>
+__device__ __forceinline__ T law_rcp(T a) {
+  return T(1) / a;
+}
+template <>
+__device__ __forceinline__ float law_rcp<float>(float a) {
+  return __builtin_amdgcn_rcpf(a);
+}
+template <typename T>
+__device__ __forceinline__ T law_sqrt(T a) {
+  return tsqrt<T>(a);
+}
+template <>
+__device__ __forceinline__ float law_sqrt<float>(float a) {
+  return __builtin_amdgcn_sqrtf(a);
+}
+template <typename T>
+__device__ __forceinline__ T law_rsq(T a) {
+  return T(1) / tsqrt<T>(a);
+}
+template <>
+__device__ __forceinline__ float law_rsq<float>(float a) {
+  return __builtin_amdgcn_rsqf(a);
+}
+
 // Linear spring-dashpot normal force (no tensile clamp) and Cundall tangential
-// spring with Coulomb cap, in the orientation of body a; n points from a to b.
-// The paper defers the contact model to another work; the damping ratio
-// follows the coarse-grained restitution of eqs. e3-44/e3-45.
+// spring with Coulomb cap, in the orientation of body a; n points from a to b;
+// ikt = 1 / k_t.  The paper defers the contact model to another work; the
+// damping ratio follows the coarse-grained restitution of eqs. e3-44/e3-45.
 template <typename T>
 __device__ __forceinline__ void contact_force(const Phys &ph, T mstar, T zeta, T delta, const T n[3], const T vrel[3],
-                                              const T xin[3], T F[3], T Ft[3], T xo[3], T &fn_abs) {
+                                              const T xin[3], T F[3], T Ft[3], T xo[3], T &fn_abs,
+                                              T ikt) {
   const T kn = T(ph.kn), dt = T(ph.dt);
-  const T gn = T(2) * zeta * tsqrt<T>(mstar * kn);
+  const T gn = T(2) * zeta * law_sqrt<T>(mstar * kn);
   const T vn = vrel[0] * n[0] + vrel[1] * n[1] + vrel[2] * n[2];
   const T fn = -(kn * delta + gn * vn);
   T vt[3];
@@ -30,14 +59,14 @@ __device__ __forceinline__ void contact_force(const Phys &ph, T mstar, T zeta, T
   const T kt = T(ph.kt), gt = T(ph.gt_ratio) * gn;
 #pragma unroll
   for (int a = 0; a < 3; a++) Ft[a] = -kt * xo[a] - gt * vt[a];
-  const T ftm = tsqrt<T>(Ft[0] * Ft[0] + Ft[1] * Ft[1] + Ft[2] * Ft[2]);
+  const T ft2 = Ft[0] * Ft[0] + Ft[1] * Ft[1] + Ft[2] * Ft[2];
   const T cap = T(ph.mu_s) * fabs(fn);
-  if (ftm > cap) {
-    const T sc = cap / ftm;
+  if (ft2 > cap * cap) {
+    const T sc = cap * law_rsq<T>(ft2);
 #pragma unroll
     for (int a = 0; a < 3; a++) {
       Ft[a] *= sc;
-      xo[a] = -(Ft[a] + gt * vt[a]) / kt;
+      xo[a] = -(Ft[a] + gt * vt[a]) * ikt;
     }
   }
 #pragma unroll
@@ -106,6 +135,7 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
     T F[3] = {T(0), T(0), T(0)}, Tq[3] = {T(0), T(0), T(0)};
     const T wmag = tsqrt<T>(Vi.w[0] * Vi.w[0] + Vi.w[1] * Vi.w[1] + Vi.w[2] * Vi.w[2]);
     const bool roll = a.ph.mu_r > 0.0 && wmag > T(0);
+    const T ikt = T(1.0 / a.ph.kt);  // 1 / k_t
     // The list holds the candidates touching at the last rebuild in slots
     // cap-1, cap-2, ... ("near") and the others in slots 0, 1, ... ("far").
     // Each region is visited in lockstep across the wave (near first, where
@@ -156,8 +186,8 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
       T inv, delta;
       if constexpr (sizeof(T) == 4) {
         const float d2f = (float)d2;
-        inv = __builtin_amdgcn_rsqf(d2f);
-        delta = (float)fma(sr, sr, -d2) * __builtin_amdgcn_rcpf((float)sr + d2f * inv);
+        inv = law_rsq<float>(d2f);
+        delta = (float)fma(sr, sr, -d2) * law_rcp<float>((float)sr + d2f * inv);
       } else {
         const double dist = sqrt(d2);
         inv = T(1) / T(dist);
@@ -179,7 +209,7 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
       cross(ws, n, cr);
 #pragma unroll
       for (int c = 0; c < 3; c++) vrel[c] += cr[c];
-      const T mstar = ma * mb / (ma + mb);
+      const T mstar = ma * mb * law_rcp<T>(ma + mb);
       const T zeta = zi_ > Vj.zeta ? zi_ : Vj.zeta;
       T xin[3] = {T(0), T(0), T(0)};
       if ((mold >> s) & 1ull) {
@@ -189,7 +219,7 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
         xin[2] = h.z;
       }
       T Fa[3], Ft[3], xo[3], fnabs;
-      contact_force<T>(a.ph, mstar, zeta, delta, n, vrel, xin, Fa, Ft, xo, fnabs);
+      contact_force<T>(a.ph, mstar, zeta, delta, n, vrel, xin, Fa, Ft, xo, fnabs, ikt);
       T tq[3];
       cross(n, Ft, tq);
 #pragma unroll
@@ -259,7 +289,7 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
           for (int c = 0; c < 3; c++) xin[c] = a.pr.wh[(long)(w * 3 + c) * N + idi];
         }
         T Fa[3], Ft[3], xo[3], fnabs;
-        contact_force<T>(a.ph, mi, zi_, T(delw), n, vrel, xin, Fa, Ft, xo, fnabs);
+        contact_force<T>(a.ph, mi, zi_, T(delw), n, vrel, xin, Fa, Ft, xo, fnabs, ikt);
         T tq[3];
         cross(n, Ft, tq);
 #pragma unroll
