@@ -275,6 +275,13 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
     auto bed_terms = [&](const BedDev &B) {
       // walls: same law against a body of infinite mass and radius at rest
       for (int w = 0; w < B.n_walls; w++) {
+        // a parcel well inside the cylinder's side wall (rho^2 below
+        // (R - r)^2 by a relative margin far above rounding) cannot touch
+        // it: the square root and the normal are computed only near it
+        if (B.wall_kind == DEM_WALL_CYL && w == 0) {
+          const double rx = xi - B.cx, ry = yi - B.cy, gap = B.R - (double)rif;
+          if (gap > 0.0 && rx * rx + ry * ry < gap * gap * (1.0 - 1e-9)) continue;
+        }
         double nv[3];
         const double phi = wall_clearance(B, w, xi, yi, zi, nv);
         const double delw = (double)rif - phi;
