@@ -230,7 +230,11 @@ __device__ __forceinline__ double tsqrt<double>(double a) { return sqrt(a); }
 template <typename T>
 __device__ __forceinline__ T tpow(T a, T e);
 template <>
-__device__ __forceinline__ float tpow<float>(float a, float e) { return powf(a, e); }
+__device__ __forceinline__ float tpow<float>(float a, float e) {
+  // a^e for a >= 0 from the hardware's base-2 logarithm and exponential
+  // (a few ulp, within the mixed path's FP32 gate; a = 0 gives 0 for e > 0)
+  return __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(a));
+}
 template <>
 __device__ __forceinline__ double tpow<double>(double a, double e) { return pow(a, e); }
 
