@@ -243,8 +243,10 @@ __device__ __forceinline__ double tpow<double>(double a, double e) { return pow(
 // Wen-Yu with Schiller-Naumann C_D (Re of eq. e2-23) at eps_g >= 0.8.
 // The branch is chosen by the caller (dense: eps_g < 0.8, decided on the
 // FP64 voidage, so that an FP32 evaluation takes the branch the FP64 one does).
+// The same with eps^-2.65 of the dilute branch passed in (epse), for callers
+// that hold it per gas cell.
 template <typename T>
-__device__ __forceinline__ T beta_over_epsp(bool dense, T eps, T rho, T mu, T slip, T dp, int printed) {
+__device__ __forceinline__ T beta_over_epsp_e(bool dense, T eps, T epse, T rho, T mu, T slip, T dp, int printed) {
   const T ep = T(1) - eps;
   if (dense) {
     const T inertial = printed ? T(1.75) * eps * rho * slip / (dp * ep) : T(1.75) * rho * slip / dp;
@@ -252,7 +254,11 @@ __device__ __forceinline__ T beta_over_epsp(bool dense, T eps, T rho, T mu, T sl
   }
   const T re = rho * eps * dp * slip / mu;
   const T cdre = re < T(1000) ? T(24) * (T(1) + T(0.15) * tpow<T>(re, T(0.687))) : T(0.44) * re;
-  return T(0.75) * cdre * mu * tpow<T>(eps, T(-2.65)) / (dp * dp);
+  return T(0.75) * cdre * mu * epse / (dp * dp);
+}
+template <typename T>
+__device__ __forceinline__ T beta_over_epsp(bool dense, T eps, T rho, T mu, T slip, T dp, int printed) {
+  return beta_over_epsp_e<T>(dense, eps, dense ? T(0) : tpow<T>(eps, T(-2.65)), rho, mu, slip, dp, printed);
 }
 
 // Gidaspow-Ganser drag of particles of sphericity psi (eqs. e3-5-2..e3-5-5),
@@ -261,8 +267,8 @@ __device__ __forceinline__ T beta_over_epsp(bool dense, T eps, T rho, T mu, T sl
 // single-particle C_D with K1 = 1/(1/3 + 2/3 psi^-1/2) - 2.25 dp / Dbed and
 // K2 = 10^(1.8148 (-log10 psi)^0.5743) (K1, K2 passed in, per parcel).
 template <typename T>
-__device__ __forceinline__ T beta_ganser_over_epsp(bool dense, T eps, T rho, T mu, T slip, T dp, T psi, T K1, T K2,
-                                                   int printed) {
+__device__ __forceinline__ T beta_ganser_over_epsp_e(bool dense, T eps, T epse, T rho, T mu, T slip, T dp, T psi, T K1,
+                                                     T K2, int printed) {
   const T ep = T(1) - eps;
   if (dense) {
     const T inertial =
@@ -273,19 +279,30 @@ __device__ __forceinline__ T beta_ganser_over_epsp(bool dense, T eps, T rho, T m
   const T x = re * K1 * K2;
   const T cdre = T(24) / K1 * (T(1) + T(0.1118) * tpow<T>(x, T(0.6567))) +
                  (x > T(0) ? T(0.4305) * K2 * re / (T(1) + T(3305) / x) : T(0));
-  return T(0.75) * cdre * mu * tpow<T>(eps, T(-2.65)) / (dp * dp);
+  return T(0.75) * cdre * mu * epse / (dp * dp);
+}
+template <typename T>
+__device__ __forceinline__ T beta_ganser_over_epsp(bool dense, T eps, T rho, T mu, T slip, T dp, T psi, T K1, T K2,
+                                                   int printed) {
+  return beta_ganser_over_epsp_e<T>(dense, eps, dense ? T(0) : tpow<T>(eps, T(-2.65)), rho, mu, slip, dp, psi, K1, K2,
+                                    printed);
 }
 
 // drag coefficient over eps_p of one parcel of ore O in bed B: Gidaspow for
 // spheres, Gidaspow-Ganser for a sphericity in (0, 1]
 template <typename T>
-__device__ __forceinline__ T drag_beta(const Phys &ph, const OreDev &O, const BedDev &B, bool dense, T eps, T rho,
-                                       T mu, T slip, T dp) {
+__device__ __forceinline__ T drag_beta_e(const Phys &ph, const OreDev &O, const BedDev &B, bool dense, T eps, T epse,
+                                         T rho, T mu, T slip, T dp) {
   if (ph.ganser && O.psi > 0.0) {
     const T K1 = T(O.k1_shape) - T(2.25) * dp / T(B.dbed);
-    return beta_ganser_over_epsp<T>(dense, eps, rho, mu, slip, dp, T(O.psi), K1, T(O.k2), ph.ergun_printed);
+    return beta_ganser_over_epsp_e<T>(dense, eps, epse, rho, mu, slip, dp, T(O.psi), K1, T(O.k2), ph.ergun_printed);
   }
-  return beta_over_epsp<T>(dense, eps, rho, mu, slip, dp, ph.ergun_printed);
+  return beta_over_epsp_e<T>(dense, eps, epse, rho, mu, slip, dp, ph.ergun_printed);
+}
+template <typename T>
+__device__ __forceinline__ T drag_beta(const Phys &ph, const OreDev &O, const BedDev &B, bool dense, T eps, T rho,
+                                       T mu, T slip, T dp) {
+  return drag_beta_e<T>(ph, O, B, dense, eps, dense ? T(0) : tpow<T>(eps, T(-2.65)), rho, mu, slip, dp);
 }
 
 // Per-gas-cell drag table row, three quads: (ug vg wg eps) (dpdx dpdy dpdz rho)

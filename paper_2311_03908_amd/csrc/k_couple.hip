@@ -228,6 +228,9 @@ __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g
     double rho, mu;
     gas_props_h2(g.T[c], g.p[c], g.xH2[c], g.xH2O[c], g.xN2[c], B.mu_override, rho, mu);
     const double ug = g.ug[c], vg = g.vg[c], wg = g.wg[c];
+    // the drag branch and the dilute branch's eps^-2.65, once per cell
+    const bool dense = eps < 0.8;
+    const double epse = dense ? 0.0 : pow(eps, -2.65);
     double sK = 0, sKu = 0, sKv = 0, sKw = 0, sKs = 0;
     for (int r = 0; r < R.f * R.f; r++) {
       const int k0 = R.row_key(r);
@@ -241,12 +244,11 @@ __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g
         const double dd = 2.0 * (double)d.pos[j].r;
         const double V = kPi / 6.0 * dd * dd * dd;
         const double dpj = dd / (double)p.kcg[j];  // real-particle diameter
-        const bool dense = eps < 0.8;
         double beta;
         if constexpr (kGanser)
-          beta = drag_beta<double>(ph, ores[ore_of(p.tag[j])], B, dense, eps, rho, mu, slip, dpj);
+          beta = drag_beta_e<double>(ph, ores[ore_of(p.tag[j])], B, dense, eps, epse, rho, mu, slip, dpj);
         else
-          beta = beta_over_epsp<double>(dense, eps, rho, mu, slip, dpj, ph.ergun_printed);
+          beta = beta_over_epsp_e<double>(dense, eps, epse, rho, mu, slip, dpj, ph.ergun_printed);
         const double K = beta * V;
         sK += K;
         sKu += K * vx;
