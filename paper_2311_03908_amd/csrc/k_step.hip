@@ -83,9 +83,10 @@ __device__ __forceinline__ void cross(const T a[3], const T b[3], T c[3]) {
 
 // Neighbour position records requested kLand at a time land in LDS
 // (global_load_lds: 16 B per lane and instruction, written lane-major as a
-// 1 KB row) instead of registers.  That frees the 32 VGPRs the records in
-// flight took, which brings the kernel to 5 waves per SIMD; each wave owns
-// kLand record rows of 2 KB (8 KB, so 20 waves fill a CU's 160 KB of LDS).
+// 1 KB row) instead of registers.  That leaves the registers to the near
+// slots' velocity records and springs, which are requested with the position
+// records (mixed precision: 125 VGPRs, 4 waves per SIMD); each wave owns
+// kLand record rows of 2 KB (8 KB; 16 waves take 128 KB of a CU's 160 KB).
 // The rows are read back by the lane that requested them, after a wait on
 // the vector-memory counter, which the LDS writes of these loads decrement.
 constexpr int kLand = 4;
@@ -168,7 +169,9 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
     }
     const int cap = a.ph.max_nbr;
     uint64_t cbits = 0;
-    auto pair = [&](int s, int j, const PosRec &Q) {
+    // pv / ph: the partner's velocity record and the spring, when the caller
+    // has already requested them (null: loaded here, after the test)
+    auto pair = [&](int s, int j, const PosRec &Q, const VelRec<T> *pv, const Spring<T> *ph) {
       const double dx = Q.x - xi, dy = Q.y - yi, dz = Q.z - zi;
       const double d2 = dist2_exact(dx, dy, dz);
       const double sr = (double)rif + (double)Q.r;
@@ -194,7 +197,7 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
         delta = T(sr - dist);
       }
       const T n[3] = {T(ifirst ? dx : -dx) * inv, T(ifirst ? dy : -dy) * inv, T(ifirst ? dz : -dz) * inv};
-      const VelRec<T> Vj = a.in.vel[j];
+      const VelRec<T> Vj = pv ? *pv : a.in.vel[j];
       const T rj = T(Q.r);
       const T ra = ifirst ? ri : rj, rb = ifirst ? rj : ri;
       const T ma = ifirst ? mi : Vj.m, mb = ifirst ? Vj.m : mi;
@@ -213,7 +216,7 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
       const T zeta = zi_ > Vj.zeta ? zi_ : Vj.zeta;
       T xin[3] = {T(0), T(0), T(0)};
       if ((mold >> s) & 1ull) {
-        const Spring<T> h = a.nb.hist[(long)s * N + i];
+        const Spring<T> h = ph ? *ph : a.nb.hist[(long)s * N + i];
         xin[0] = h.x;
         xin[1] = h.y;
         xin[2] = h.z;
@@ -237,17 +240,40 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
       n_pp++;
     };
     constexpr int kPre = kLand;
+    // in FP64 the requested records would take 64 more registers
+    constexpr bool kNearPrefetch = sizeof(T) == 4;
     for (int t0 = 0; t0 < cmax.x; t0 += kPre) {
       int jj[kPre];
 #pragma unroll
       for (int k = 0; k < kPre; k++) jj[k] = (t0 + k < c_near) ? a.nb.idx[(long)(cap - 1 - t0 - k) * N + i] : -1;
+      // every row is requested (a slot past the lane's count lands parcel
+      // 0's record, never read), so the requests go out back to back
 #pragma unroll
-      for (int k = 0; k < kPre; k++)
-        if (jj[k] >= 0) land_pos(a.in.pos, jj[k], wl + k * 2048);
-      land_wait();
+      for (int k = 0; k < kPre; k++) land_pos(a.in.pos, jj[k] >= 0 ? jj[k] : 0, wl + k * 2048);
+      if constexpr (kNearPrefetch) {
+        // a near slot is nearly always a contact: its partner's velocity
+        // record and its spring are requested with the position records,
+        // so the group waits for memory once
+        VelRec<T> vv[kPre];
+        Spring<T> hh[kPre];
 #pragma unroll
-      for (int k = 0; k < kPre; k++)
-        if (jj[k] >= 0) pair(cap - 1 - t0 - k, jj[k], landed_pos(wl + k * 2048));
+        for (int k = 0; k < kPre; k++)
+          if (jj[k] >= 0) vv[k] = a.in.vel[jj[k]];
+#pragma unroll
+        for (int k = 0; k < kPre; k++) {
+          const int s = cap - 1 - t0 - k;
+          if (jj[k] >= 0 && ((mold >> s) & 1ull)) hh[k] = a.nb.hist[(long)s * N + i];
+        }
+        land_wait();
+#pragma unroll
+        for (int k = 0; k < kPre; k++)
+          if (jj[k] >= 0) pair(cap - 1 - t0 - k, jj[k], landed_pos(wl + k * 2048), &vv[k], &hh[k]);
+      } else {
+        land_wait();
+#pragma unroll
+        for (int k = 0; k < kPre; k++)
+          if (jj[k] >= 0) pair(cap - 1 - t0 - k, jj[k], landed_pos(wl + k * 2048), nullptr, nullptr);
+      }
     }
     {
       // far region: the next group's indices are requested while the
@@ -267,7 +293,7 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
         land_wait();
 #pragma unroll
         for (int k = 0; k < kPre; k++)
-          if (jj[k] >= 0) pair(t0 + k, jj[k], landed_pos(wl + k * 2048));
+          if (jj[k] >= 0) pair(t0 + k, jj[k], landed_pos(wl + k * 2048), nullptr, nullptr);
       }
     }
     mnew = cbits;
@@ -433,7 +459,7 @@ __device__ __forceinline__ void step_skin_check(const StepArgs<T> &a) {
 // One thread per parcel over the sorted order; (block / 64) * 8 KB of dynamic
 // LDS for the landed neighbour records.
 template <typename T>
-__global__ void __launch_bounds__(512, sizeof(T) == 4 ? 5 : 1) k_step(StepArgs<T> a) {
+__global__ void __launch_bounds__(512, sizeof(T) == 4 ? 4 : 1) k_step(StepArgs<T> a) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int i = (a.xcd > 1 ? xcd_block(a.xcd) : (int)blockIdx.x) * blockDim.x + threadIdx.x;
   step_skin_check(a);
