@@ -581,6 +581,7 @@ struct Ctx final : dem_ctx {
     a.beds = beds;
     a.ores = ores;
     a.ph = ph;
+    a.bed0 = hbd[0];
     a.status = status;
     a.Tg = gas_T;
     a.xref = xref;

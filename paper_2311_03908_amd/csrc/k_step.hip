@@ -373,9 +373,12 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
         }
       }
     };
-    // with a single bed its record is read through uniform (scalar) loads
+    // with a single bed its record comes from the kernel arguments (scalar
+    // loads, which need no wait on vector memory; a record in global memory
+    // is read through vector loads, as the kernel also stores to global
+    // memory, and each of its reads costs a memory round trip)
     if (a.ph.n_beds == 1)
-      bed_terms(a.beds[0]);
+      bed_terms(a.bed0);
     else
       bed_terms(a.beds[bed_of(tag)]);
     if (a.mode == 1) {

@@ -115,6 +115,7 @@ struct StepArgs {
   const BedDev *beds;
   const OreDev *ores;
   Phys ph;
+  BedDev bed0;                   // copy of beds[0] (the records never change after init)
   uint32_t *status;
   const double *Tg;              // gas temperature per cell (energy equation)
   const float4 *xref;            // positions at the last rebuild (FP32)
