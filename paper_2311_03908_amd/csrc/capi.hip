@@ -533,9 +533,9 @@ struct Ctx final : dem_ctx {
   // voidage (and drag sums) of every gas cell from the current cell order:
   // empty cells directly, occupied cells through their compacted list
   int deposit(const GasArgs &g, bool sums, const DepositOut &o) {
-    launch_occupied(start_d, cell_bed, beds, n_gas, sums, o, occ_flags, occ_offs, scan_scr, occ_list, occ_count, st);
+    launch_occupied(start_d, cell_bed, bsel(), n_gas, sums, o, occ_flags, occ_offs, scan_scr, occ_list, occ_count, st);
     occ_fresh = true;
-    launch_deposit<T>(dyn[cur], pr, g, start_d, order_d, cell_bed, beds, ores, ph, occ_list, occ_count, n_gas,
+    launch_deposit<T>(dyn[cur], pr, g, start_d, order_d, cell_bed, bsel(), ores, ph, occ_list, occ_count, n_gas,
                       sums, o, st);
     HIPCHK(hipGetLastError());
     return DEMRX_OK;
@@ -545,7 +545,7 @@ struct Ctx final : dem_ctx {
   int ensure_occ() {
     TRY(ensure_dep());
     if (!occ_fresh) {
-      launch_occupied(start_d, cell_bed, beds, n_gas, false, DepositOut{}, occ_flags, occ_offs, scan_scr, occ_list,
+      launch_occupied(start_d, cell_bed, bsel(), n_gas, false, DepositOut{}, occ_flags, occ_offs, scan_scr, occ_list,
                       occ_count, st);
       occ_fresh = true;
     }
@@ -569,6 +569,14 @@ struct Ctx final : dem_ctx {
     gas_T = g->T;
     HIPCHK(hipGetLastError());
     return DEMRX_OK;
+  }
+
+  BedSel bsel() const {
+    BedSel b;
+    b.beds = beds;
+    b.n_beds = (int)hbd.size();
+    b.one = hbd[0];
+    return b;
   }
 
   StepArgs<T> step_args(int mode) {
@@ -688,7 +696,7 @@ struct Ctx final : dem_ctx {
     a.p = pr;
     a.g = gas_args(g);
     a.eps = eps;
-    a.beds = beds;
+    a.bs = bsel();
     a.ores = ores;
     a.thermo = thermo;
     a.theta = theta_dev;
@@ -696,7 +704,7 @@ struct Ctx final : dem_ctx {
     if (P.n_ores <= kReactRow - 10) {
       // gas-cell quantities once per occupied cell of the current order
       if (!occ_fresh) {
-        launch_occupied(start_d, cell_bed, beds, n_gas, false, DepositOut{}, occ_flags, occ_offs, scan_scr, occ_list,
+        launch_occupied(start_d, cell_bed, bsel(), n_gas, false, DepositOut{}, occ_flags, occ_offs, scan_scr, occ_list,
                         occ_count, st);
         occ_fresh = true;
       }
@@ -718,11 +726,11 @@ struct Ctx final : dem_ctx {
       for (int q = 0; q < cs.rows; q++) any |= cs.o[q] != nullptr;
       if (any) {
         if (!occ_fresh) {  // occupied cells of the current order, voidage untouched
-          launch_occupied(start_d, cell_bed, beds, n_gas, false, DepositOut{}, occ_flags, occ_offs, scan_scr, occ_list,
+          launch_occupied(start_d, cell_bed, bsel(), n_gas, false, DepositOut{}, occ_flags, occ_offs, scan_scr, occ_list,
                           occ_count, st);
           occ_fresh = true;
         }
-        launch_cellsum(pm, n, start_d, order_d, cell_bed, beds, n_gas, occ_flags, occ_list, occ_count, n_gas, cs, st);
+        launch_cellsum(pm, n, start_d, order_d, cell_bed, bsel(), n_gas, occ_flags, occ_list, occ_count, n_gas, cs, st);
       }
     }
     if (bed_sum) {

@@ -155,7 +155,7 @@ template void launch_gas_table<double>(const GasArgs &, const double *, const in
 // thread per cell writes the outputs of an empty cell (voidage 1, zero sums)
 // and flags the others, which are compacted (scan) into a list; the deposit
 // then runs one 16-lane group per listed cell.
-__global__ void k_occ_flags(const int32_t *start, const int32_t *cell_bed, const BedDev *beds, int n_gas, int sums,
+__global__ void k_occ_flags(const int32_t *start, const int32_t *cell_bed, BedSel bs, int n_gas, int sums,
                             DepositOut o, int32_t *flags) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c > n_gas) return;
@@ -163,12 +163,14 @@ __global__ void k_occ_flags(const int32_t *start, const int32_t *cell_bed, const
     flags[c] = 0;
     return;
   }
-  const GasCellRanges R(beds[cell_bed[c]], c);
   bool any = false;
-  for (int r = 0; r < R.f * R.f && !any; r++) {
-    const int k0 = R.row_key(r);
-    any = start[k0 + R.f] > start[k0];
-  }
+  on_bed(bs, [&] { return cell_bed[c]; }, [&](const BedDev &B) {
+    const GasCellRanges R(B, c);
+    for (int r = 0; r < R.f * R.f && !any; r++) {
+      const int k0 = R.row_key(r);
+      any = start[k0 + R.f] > start[k0];
+    }
+  });
   flags[c] = any ? 1 : 0;
   if (any) return;
   if (o.eps_ctx) o.eps_ctx[c] = 1.0;
@@ -194,25 +196,43 @@ __global__ void k_occ_compact(const int32_t *flags, const int32_t *offs, int n_g
 
 template <typename T, bool kGanser>
 __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g, const int32_t *start,
-                                                 const int32_t *order, const int32_t *cell_bed, const BedDev *beds,
+                                                 const int32_t *order, const int32_t *cell_bed, BedSel bs,
                                                  const OreDev *ores, Phys ph, const int32_t *list, const int32_t *list_count, int sums,
                                                  DepositOut o) {
   const int sl = threadIdx.x % kGroup;
   const int n_list = *list_count;
   const int groups = gridDim.x * (blockDim.x / kGroup);
-  for (int gi = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup; gi < n_list; gi += groups) {
-    const int c = list[gi];
-    const BedDev &B = beds[cell_bed[c]];
+  // Each lane takes the parcels sl, sl + 16, ... of every row of the cell,
+  // two per trip with both records requested before either is used; the
+  // sums run in that order, then over the group's lanes.
+  auto cell = [&](const BedDev &B, const int c) {
     const GasCellRanges R(B, c);
+    // the cell's gas state, requested with the first parcel records
+    double Tc = 0.0, pc = 0.0, x1 = 0.0, x2 = 0.0, x3 = 0.0, ug = 0.0, vg = 0.0, wg = 0.0;
+    if (sums) {
+      Tc = g.T[c];
+      pc = g.p[c];
+      x1 = g.xH2[c];
+      x2 = g.xH2O[c];
+      x3 = g.xN2[c];
+      ug = g.ug[c];
+      vg = g.vg[c];
+      wg = g.wg[c];
+    }
     double sv = 0.0, cnt = 0.0;
     for (int r = 0; r < R.f * R.f; r++) {
       const int k0 = R.row_key(r);
       const int e = start[k0 + R.f];
-      for (int q = start[k0] + sl; q < e; q += kGroup) {
-        const int j = order[q];
-        const double dd = 2.0 * (double)d.pos[j].r;
-        sv += kPi / 6.0 * dd * dd * dd;
+      for (int q = start[k0] + sl; q < e; q += 2 * kGroup) {
+        const bool two = q + kGroup < e;
+        const int j0 = order[q], j1 = two ? order[q + kGroup] : j0;
+        const double d0 = 2.0 * (double)d.pos[j0].r, d1 = 2.0 * (double)d.pos[j1].r;
+        sv += kPi / 6.0 * d0 * d0 * d0;
         cnt += 1.0;
+        if (two) {
+          sv += kPi / 6.0 * d1 * d1 * d1;
+          cnt += 1.0;
+        }
       }
     }
     sv = group_sum(sv);
@@ -224,37 +244,44 @@ __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g
       if (o.eps) o.eps[c] = eps;
       if (o.np) o.np[c] = cnt;
     }
-    if (!sums) continue;
+    if (!sums) return;
     double rho, mu;
-    gas_props_h2(g.T[c], g.p[c], g.xH2[c], g.xH2O[c], g.xN2[c], B.mu_override, rho, mu);
-    const double ug = g.ug[c], vg = g.vg[c], wg = g.wg[c];
+    gas_props_h2(Tc, pc, x1, x2, x3, B.mu_override, rho, mu);
     // the drag branch and the dilute branch's eps^-2.65, once per cell
     const bool dense = eps < 0.8;
     const double epse = dense ? 0.0 : pow(eps, -2.65);
     double sK = 0, sKu = 0, sKv = 0, sKw = 0, sKs = 0;
+    auto add = [&](const VelRec<T> &vr, float rj, float kj, int32_t tj) {
+      const double vx = (double)vr.v[0], vy = (double)vr.v[1], vz = (double)vr.v[2];
+      const double sx = ug - vx, sy = vg - vy, sz = wg - vz;
+      const double slip = sqrt(sx * sx + sy * sy + sz * sz);
+      const double dd = 2.0 * (double)rj;
+      const double V = kPi / 6.0 * dd * dd * dd;
+      const double dpj = dd / (double)kj;  // real-particle diameter
+      double beta;
+      if constexpr (kGanser)
+        beta = drag_beta_e<double>(ph, ores[ore_of(tj)], B, dense, eps, epse, rho, mu, slip, dpj);
+      else
+        beta = beta_over_epsp_e<double>(dense, eps, epse, rho, mu, slip, dpj, ph.ergun_printed);
+      const double K = beta * V;
+      sK += K;
+      sKu += K * vx;
+      sKv += K * vy;
+      sKw += K * vz;
+      sKs += K * slip;
+    };
     for (int r = 0; r < R.f * R.f; r++) {
       const int k0 = R.row_key(r);
       const int e = start[k0 + R.f];
-      for (int q = start[k0] + sl; q < e; q += kGroup) {
-        const int j = order[q];
-        const VelRec<T> vr = d.vel[j];
-        const double vx = (double)vr.v[0], vy = (double)vr.v[1], vz = (double)vr.v[2];
-        const double sx = ug - vx, sy = vg - vy, sz = wg - vz;
-        const double slip = sqrt(sx * sx + sy * sy + sz * sz);
-        const double dd = 2.0 * (double)d.pos[j].r;
-        const double V = kPi / 6.0 * dd * dd * dd;
-        const double dpj = dd / (double)p.kcg[j];  // real-particle diameter
-        double beta;
-        if constexpr (kGanser)
-          beta = drag_beta_e<double>(ph, ores[ore_of(p.tag[j])], B, dense, eps, epse, rho, mu, slip, dpj);
-        else
-          beta = beta_over_epsp_e<double>(dense, eps, epse, rho, mu, slip, dpj, ph.ergun_printed);
-        const double K = beta * V;
-        sK += K;
-        sKu += K * vx;
-        sKv += K * vy;
-        sKw += K * vz;
-        sKs += K * slip;
+      for (int q = start[k0] + sl; q < e; q += 2 * kGroup) {
+        const bool two = q + kGroup < e;
+        const int j0 = order[q], j1 = two ? order[q + kGroup] : j0;
+        const VelRec<T> v0 = d.vel[j0], v1 = d.vel[j1];
+        const float r0 = d.pos[j0].r, r1 = d.pos[j1].r;
+        const float c0 = p.kcg[j0], c1 = p.kcg[j1];
+        const int32_t t0 = kGanser ? p.tag[j0] : 0, t1 = kGanser ? p.tag[j1] : 0;
+        add(v0, r0, c0, t0);
+        if (two) add(v1, r1, c1, t1);
       }
     }
     sK = group_sum(sK);
@@ -269,20 +296,24 @@ __global__ void __launch_bounds__(256) k_deposit(Dyn<T> d, Props<T> p, GasArgs g
       if (o.sumKw) o.sumKw[c] = sKw;
       if (o.sumKs) o.sumKs[c] = sKs;
     }
+  };
+  for (int gi = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup; gi < n_list; gi += groups) {
+    const int c = list[gi];
+    on_bed(bs, [&] { return cell_bed[c]; }, [&](const BedDev &B) { cell(B, c); });
   }
 }
 
-void launch_occupied(const int32_t *start, const int32_t *cell_bed, const BedDev *beds, int n_gas, bool sums,
+void launch_occupied(const int32_t *start, const int32_t *cell_bed, const BedSel &bs, int n_gas, bool sums,
                      const DepositOut &o, int32_t *flags, int32_t *offs, int32_t *scratch, int32_t *list,
                      int32_t *count, hipStream_t s) {
-  k_occ_flags<<<(n_gas + 256) / 256, 256, 0, s>>>(start, cell_bed, beds, n_gas, sums ? 1 : 0, o, flags);
+  k_occ_flags<<<(n_gas + 256) / 256, 256, 0, s>>>(start, cell_bed, bs, n_gas, sums ? 1 : 0, o, flags);
   launch_scan(flags, offs, n_gas + 1, scratch, s);
   k_occ_compact<<<(n_gas + 256) / 256, 256, 0, s>>>(flags, offs, n_gas, list, count);
 }
 
 template <typename T>
 void launch_deposit(const Dyn<T> &d, const Props<T> &p, const GasArgs &g, const int32_t *start,
-                    const int32_t *order, const int32_t *cell_bed, const BedDev *beds, const OreDev *ores,
+                    const int32_t *order, const int32_t *cell_bed, const BedSel &bs, const OreDev *ores,
                     const Phys &ph, const int32_t *list, const int32_t *list_count, int max_list, bool sums,
                     const DepositOut &o, hipStream_t s) {
   const int groups_per_block = 256 / kGroup;
@@ -290,10 +321,10 @@ void launch_deposit(const Dyn<T> &d, const Props<T> &p, const GasArgs &g, const 
   // the drag law is a template parameter: the sphericity-corrected law
   // holds many more registers, which the spherical case does not pay for
   if (ph.ganser)
-    k_deposit<T, true><<<blocks, 256, 0, s>>>(d, p, g, start, order, cell_bed, beds, ores, ph, list, list_count,
+    k_deposit<T, true><<<blocks, 256, 0, s>>>(d, p, g, start, order, cell_bed, bs, ores, ph, list, list_count,
                                               sums ? 1 : 0, o);
   else
-    k_deposit<T, false><<<blocks, 256, 0, s>>>(d, p, g, start, order, cell_bed, beds, ores, ph, list, list_count,
+    k_deposit<T, false><<<blocks, 256, 0, s>>>(d, p, g, start, order, cell_bed, bs, ores, ph, list, list_count,
                                                sums ? 1 : 0, o);
 }
 
@@ -344,11 +375,7 @@ void launch_react_table(const GasArgs &g, const int32_t *cell_bed, const BedDev 
 // diffusion to the particle temperature, so those stay per parcel; without it
 // they come from the cell table when one is given.
 template <typename T, bool kThermo>
-__global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= a.n) return;
-  const int32_t tag = a.p.tag[j];
-  const BedDev &B = a.beds[bed_of(tag)];
+__device__ __forceinline__ void react_parcel(const ReactArgs<T> &a, const int j, const int32_t tag, const BedDev &B) {
   const OreDev &O = a.ores[ore_of(tag)];
   const PosRec P = load_pos(a.d.pos, j);
   const VelRec<T> Vr = a.d.vel[j];
@@ -452,6 +479,14 @@ __global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
   if (!(isfinite(fov) && n[0] >= 0.0 && n[1] >= 0.0 && n[2] >= 0.0)) atomicOr(a.status, ST_NONFINITE);
 }
 
+template <typename T, bool kThermo>
+__global__ void __launch_bounds__(256) k_react(ReactArgs<T> a) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n) return;
+  const int32_t tag = a.p.tag[j];
+  on_bed(a.bs, [&] { return bed_of(tag); }, [&](const BedDev &B) { react_parcel<T, kThermo>(a, j, tag, B); });
+}
+
 template <typename T>
 void launch_react(const ReactArgs<T> &a, hipStream_t s) {
   if (a.thermo)
@@ -460,14 +495,12 @@ void launch_react(const ReactArgs<T> &a, hipStream_t s) {
     k_react<T, false><<<(a.n + 255) / 256, 256, 0, s>>>(a);
 }
 
-// Cell sums of the per-parcel sources: one 16-lane group per occupied gas
-// cell of the compacted list (as the deposit), and zeros written to the
-// empty cells by one thread each.
 // Cell sums of the per-parcel sources in one launch: the first `be` blocks
 // write zeros for the empty cells, the others sum each listed (occupied)
-// cell with a 16-lane group.
+// cell with a 16-lane group (lanes take the parcels as in the deposit, two
+// per trip).
 __global__ void __launch_bounds__(256) k_cellsum(const double *pm, int n, const int32_t *start, const int32_t *order,
-                                                 const int32_t *cell_bed, const BedDev *beds, const int32_t *flags,
+                                                 const int32_t *cell_bed, BedSel bs, const int32_t *flags,
                                                  int n_gas, int be, const int32_t *list, const int32_t *list_count,
                                                  CellSumOut o) {
   if ((int)blockIdx.x < be) {
@@ -484,18 +517,31 @@ __global__ void __launch_bounds__(256) k_cellsum(const double *pm, int n, const 
   const int groups = ((int)gridDim.x - be) * (blockDim.x / kGroup);
   for (int gi = (((int)blockIdx.x - be) * blockDim.x + threadIdx.x) / kGroup; gi < n_list; gi += groups) {
     const int c = list[gi];
-    const GasCellRanges R(beds[cell_bed[c]], c);
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int r = 0; r < R.f * R.f; r++) {
-      const int k0 = R.row_key(r);
-      const int e = start[k0 + R.f];
-      for (int t = start[k0] + sl; t < e; t += kGroup) {
-        const int j = order[t];
+    on_bed(bs, [&] { return cell_bed[c]; }, [&](const BedDev &B) {
+      const GasCellRanges R(B, c);
+      for (int r = 0; r < R.f * R.f; r++) {
+        const int k0 = R.row_key(r);
+        const int e = start[k0 + R.f];
+        for (int t = start[k0] + sl; t < e; t += 2 * kGroup) {
+          const bool two = t + kGroup < e;
+          const int j0 = order[t], j1 = two ? order[t + kGroup] : j0;
+          double v0[8], v1[8];
 #pragma unroll
-        for (int q = 0; q < 8; q++)
-          if (q < o.rows) s[q] += pm[(long)q * n + j];
+          for (int q = 0; q < 8; q++)
+            if (q < o.rows) {
+              v0[q] = pm[(long)q * n + j0];
+              v1[q] = pm[(long)q * n + j1];
+            }
+#pragma unroll
+          for (int q = 0; q < 8; q++)
+            if (q < o.rows) {
+              s[q] += v0[q];
+              if (two) s[q] += v1[q];
+            }
+        }
       }
-    }
+    });
 #pragma unroll
     for (int q = 0; q < 8; q++)
       if (q < o.rows) s[q] = group_sum(s[q]);
@@ -508,12 +554,12 @@ __global__ void __launch_bounds__(256) k_cellsum(const double *pm, int n, const 
 }
 
 void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t *order, const int32_t *cell_bed,
-                    const BedDev *beds, int n_gas, const int32_t *flags, const int32_t *list,
+                    const BedSel &bs, int n_gas, const int32_t *flags, const int32_t *list,
                     const int32_t *list_count, int max_list, const CellSumOut &o, hipStream_t s) {
   const int be = std::max(1, std::min((n_gas + 255) / 256, 2048));
   const int groups_per_block = 256 / kGroup;
-  const int bs = std::max(1, std::min((max_list + groups_per_block - 1) / groups_per_block, 8192));
-  k_cellsum<<<be + bs, 256, 0, s>>>(pm, n, start, order, cell_bed, beds, flags, n_gas, be, list, list_count, o);
+  const int nbs = std::max(1, std::min((max_list + groups_per_block - 1) / groups_per_block, 8192));
+  k_cellsum<<<be + nbs, 256, 0, s>>>(pm, n, start, order, cell_bed, bs, flags, n_gas, be, list, list_count, o);
 }
 
 // Bed-mean f_ov weighted by k^3 N_Fe: every bed's parcel range (contiguous,
@@ -893,7 +939,7 @@ void launch_gas_momentum(const GasArgs &g, const double *eps, const int32_t *cel
 
 #define INST(T)                                                                                                    \
   template void launch_deposit<T>(const Dyn<T> &, const Props<T> &, const GasArgs &, const int32_t *,             \
-                                  const int32_t *, const int32_t *, const BedDev *, const OreDev *, const Phys &, \
+                                  const int32_t *, const int32_t *, const BedSel &, const OreDev *, const Phys &, \
                                   const int32_t *, const int32_t *, int, bool, const DepositOut &, hipStream_t);  \
   template void launch_react<T>(const ReactArgs<T> &, hipStream_t);                                               \
   template void launch_init<T>(const dem_parcels &, int, const Phys &, int, const ThermoTab *, const Dyn<T> &,    \

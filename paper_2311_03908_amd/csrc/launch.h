@@ -142,16 +142,32 @@ void launch_occ_zrange(const int32_t *list, const int32_t *count, const BedDev *
                        int2 *zr, hipStream_t s);
 
 // ---------------------------------------------------------------- k_couple.hip
+// The beds' records as the coupling kernels read them: a single bed's record
+// travels in the kernel arguments (scalar loads, no wait on vector memory);
+// with several beds each is read from the device array.
+struct BedSel {
+  const BedDev *beds;
+  int n_beds;
+  BedDev one;  // copy of beds[0] (the records never change after init)
+};
+// f(record of bed index()); index() is evaluated only with several beds
+template <typename I, typename F>
+__device__ __forceinline__ void on_bed(const BedSel &s, I &&index, F &&f) {
+  if (s.n_beds == 1)
+    f(s.one);
+  else
+    f(s.beds[index()]);
+}
 struct DepositOut {
   double *eps_ctx;  // context voidage (null: not written; the occupied list only)
   double *eps, *np, *sumK, *sumKu, *sumKv, *sumKw, *sumKs;
 };
-void launch_occupied(const int32_t *start, const int32_t *cell_bed, const BedDev *beds, int n_gas, bool sums,
+void launch_occupied(const int32_t *start, const int32_t *cell_bed, const BedSel &bs, int n_gas, bool sums,
                      const DepositOut &o, int32_t *flags, int32_t *offs, int32_t *scratch, int32_t *list,
                      int32_t *count, hipStream_t s);
 template <typename T>
 void launch_deposit(const Dyn<T> &d, const Props<T> &p, const GasArgs &g, const int32_t *start,
-                    const int32_t *order, const int32_t *cell_bed, const BedDev *beds, const OreDev *ores,
+                    const int32_t *order, const int32_t *cell_bed, const BedSel &bs, const OreDev *ores,
                     const Phys &ph, const int32_t *list, const int32_t *list_count, int max_list, bool sums, const DepositOut &o,
                     hipStream_t s);
 
@@ -161,7 +177,7 @@ struct ReactArgs {
   Props<T> p;
   GasArgs g;
   const double *eps;
-  const BedDev *beds;
+  BedSel bs;
   const OreDev *ores;
   const ThermoTab *thermo;  // energy equation on (null: isothermal at the gas temperature)
   const double *theta;  // 6 values overriding every bed's, or null
@@ -196,7 +212,7 @@ struct CellSumOut {
 };
 // cell sums over the occupied cells of launch_occupied (flags, list, count)
 void launch_cellsum(const double *pm, int n, const int32_t *start, const int32_t *order, const int32_t *cell_bed,
-                    const BedDev *beds, int n_gas, const int32_t *flags, const int32_t *list,
+                    const BedSel &bs, int n_gas, const int32_t *flags, const int32_t *list,
                     const int32_t *list_count, int max_list, const CellSumOut &o, hipStream_t s);
 constexpr int kBedChunk = 4096;  // parcels per partial sum of the bed means
 // bed means; with table set, the chunk table is built first from the beds'
