@@ -601,6 +601,8 @@ struct Ctx final : dem_ctx {
     a.mode = mode;
     a.xcd = step_xcd;
     a.Fout = a.Tout = nullptr;
+    a.hist_w = mode == 2 ? carry : nb.hist;
+    a.mask_w = mode == 2 ? carry_mask : nb.mask;
     return a;
   }
 
@@ -1234,8 +1236,10 @@ struct Ctx final : dem_ctx {
     for (int b : {64, 128, 256, 512}) {
       for (int x : {1, 4, 16, 64}) {
         step_xcd = x;
+        // candidates lie within a few per cent of each other: eight timed
+        // launches each (after one untimed) keep the pick above the noise
         float tot = 0.0f;
-        for (int rep = 0; rep < 4; rep++) {
+        for (int rep = 0; rep < 9; rep++) {
           HIPCHK(hipEventRecord(e0, st));
           launch_step<T>(step_args(2), b, st);
           HIPCHK(hipEventRecord(e1, st));
@@ -1244,7 +1248,7 @@ struct Ctx final : dem_ctx {
           HIPCHK(hipEventElapsedTime(&ms, e0, e1));
           if (rep) tot += ms;
         }
-        if (tune_log) std::fprintf(stderr, "[demrx] autotune step block %d xcd chunk %d: %.1f us\n", b, x, tot / 3 * 1e3f);
+        if (tune_log) std::fprintf(stderr, "[demrx] autotune step block %d xcd chunk %d: %.1f us\n", b, x, tot / 8 * 1e3f);
         if (tot < best) { best = tot; best_b = b; best_x = x; }
       }
     }

@@ -4,8 +4,9 @@
 // One thread per parcel in cell-sorted order; the step reads buffer `in` and
 // writes buffer `out`, so no parcel sees a partner's updated state.  Mode 0
 // integrates; mode 1 writes the forces and torques instead (state unchanged);
-// mode 2 is the autotuner's timing run, which skips the spring, mask and
-// reduction writes.
+// mode 2 is the autotuner's timing run: it writes the springs and masks to
+// the spare buffers of the rebuild (same addresses within them, so the same
+// memory pattern) and skips the reductions.
 #include "launch.h"
 
 namespace demrx {
@@ -234,9 +235,7 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
 #pragma unroll
         for (int c = 0; c < 3; c++) Tq[c] -= T(a.ph.mu_r) * fnabs * Vi.w[c] / wmag;
       }
-      if (a.mode == 0) {
-        a.nb.hist[(long)s * N + i] = Spring<T>{xo[0], xo[1], xo[2], spring_tag<T>(Q.id)};
-      }
+      if (a.mode != 1) a.hist_w[(long)s * N + i] = Spring<T>{xo[0], xo[1], xo[2], spring_tag<T>(Q.id)};
       n_pp++;
     };
     constexpr int kPre = kLand;
@@ -403,7 +402,7 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
       Po.z = zi + a.ph.dt * (double)Vo.v[2];
       store_pos(a.out.pos, i, Po);
       a.out.vel[i] = Vo;
-      if (a.mode == 0 && mnew != mold) a.nb.mask[i] = mnew;
+      if (a.mode != 1 && mnew != mold) a.mask_w[i] = mnew;
       const float v2 = (float)(Vo.v[0] * Vo.v[0] + Vo.v[1] * Vo.v[1] + Vo.v[2] * Vo.v[2]);
       const float4 xr = a.xref[i];
       const float ex = (float)Po.x - xr.x, ey = (float)Po.y - xr.y, ez = (float)Po.z - xr.z;

@@ -125,6 +125,8 @@ struct StepArgs {
   int count;                     // 1: add this step's contacts to counters
   int xcd;                       // >1: XCD chunk of consecutive blocks (see xcd_block)
   double *Fout, *Tout;
+  Spring<T> *hist_w;             // where the springs and masks are written: nb.hist and
+  uint64_t *mask_w;              // nb.mask, or the rebuild's spare buffers in mode 2
 };
 template <typename T>
 void launch_step(const StepArgs<T> &a, int block, hipStream_t s);
