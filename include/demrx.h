@@ -347,8 +347,9 @@ int dem_run(dem_ctx *c, int32_t n_intervals, int32_t couple_every, const dem_gas
             dem_sources *out, double *bed_fov);
 
 /* Choose launch shapes for this context's kernels by timing candidates on
- * its own data (state unchanged): the DEM-step block size and XCD chunk, and
- * the neighbour build's block size, LDS tile and work-item width (whole
+ * its own data (state unchanged): the DEM-step block size and XCD chunk (a
+ * full step whose springs and contact masks go to internal spare buffers),
+ * and the neighbour build's block size, LDS tile and work-item width (whole
  * rebuild chains are timed).  Synchronises.  With the environment variable
  * DEMRX_TUNE_LOG set, every candidate's timing goes to stderr.  With
  * DEMRX_TUNE_CACHE naming a JSON file, shapes stored there under the key of
