@@ -122,6 +122,29 @@ def test_results_do_not_depend_on_launch_shapes(case):
     bed.close()
 
 
+def test_autotune_leaves_state_and_springs_unchanged():
+    """dem_autotune times step candidates (full steps whose springs and
+    contact masks go to spare buffers) and whole forced rebuild chains on the
+    context's own data: the state and the contact springs it leaves are the
+    ones it found, bit for bit."""
+    w = W.with_velocities(W.squeeze(W.cfg3(n=20000, seed=23), 0.98, 0), 95, vscale=0.03, wscale=20.0)
+    _say(f"[autotune] state and springs, n={w.n}")
+    bed = Bed(w)
+    bed.step(40)
+    s0, c0 = bed.state(), bed.contacts()
+    assert len(c0["ids"]) > 100
+    bed.autotune()
+    s1, c1 = bed.state(), bed.contacts()
+    for k in s0:
+        assert torch.equal(s0[k], s1[k]), k
+    o0, o1 = np.lexsort(c0["ids"].T[::-1]), np.lexsort(c1["ids"].T[::-1])
+    assert np.array_equal(c0["ids"][o0], c1["ids"][o1])
+    assert np.array_equal(c0["xi"][o0], c1["xi"][o1])
+    assert np.array_equal(c0["wall_on"], c1["wall_on"])
+    assert np.array_equal(c0["wall_xi"], c1["wall_xi"])
+    bed.close()
+
+
 def test_autotuner_cache_keyed_by_arch_and_config(tmp_path, monkeypatch):
     """dem_autotune with DEMRX_TUNE_CACHE: the first context times the
     candidates and stores its choice under the key of the device architecture
