@@ -86,7 +86,7 @@ __device__ __forceinline__ void cross(const T a[3], const T b[3], T c[3]) {
 // (global_load_lds: 16 B per lane and instruction, written lane-major as a
 // 1 KB row) instead of registers.  That leaves the registers to the near
 // slots' velocity records and springs, which are requested with the position
-// records (mixed precision: 125 VGPRs, 4 waves per SIMD); each wave owns
+// records (mixed precision: 124 VGPRs, 4 waves per SIMD); each wave owns
 // kLand record rows of 2 KB (8 KB; 16 waves take 128 KB of a CU's 160 KB).
 // The rows are read back by the lane that requested them, after a wait on
 // the vector-memory counter, which the LDS writes of these loads decrement.
@@ -146,7 +146,9 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
     // Indices and position records are requested kPre slots at a time so
     // that the gathers overlap; the records land in the wave's LDS rows.
     // Both loops run to the wave's largest count (cmax), the same for every
-    // lane, so the lanes leave them together.
+    // lane, so the lanes leave them together.  A wave raises its issue
+    // priority while it requests a group's records, so that its loads go
+    // out ahead of other waves' arithmetic on the SIMD.
     const int cnt = a.nb.cnt[i];
     const int c_near = cnt >> 16, c_far = cnt & 0xffff;
     // the wave's largest near and far counts.  Active lanes are a prefix of
@@ -243,6 +245,7 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
     constexpr bool kNearPrefetch = sizeof(T) == 4;
     for (int t0 = 0; t0 < cmax.x; t0 += kPre) {
       int jj[kPre];
+      __builtin_amdgcn_s_setprio(2);
 #pragma unroll
       for (int k = 0; k < kPre; k++) jj[k] = (t0 + k < c_near) ? a.nb.idx[(long)(cap - 1 - t0 - k) * N + i] : -1;
       // every row is requested (a slot past the lane's count lands parcel
@@ -263,11 +266,13 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
           const int s = cap - 1 - t0 - k;
           if (jj[k] >= 0 && ((mold >> s) & 1ull)) hh[k] = a.nb.hist[(long)s * N + i];
         }
+        __builtin_amdgcn_s_setprio(0);
         land_wait();
 #pragma unroll
         for (int k = 0; k < kPre; k++)
           if (jj[k] >= 0) pair(cap - 1 - t0 - k, jj[k], landed_pos(wl + k * 2048), &vv[k], &hh[k]);
       } else {
+        __builtin_amdgcn_s_setprio(0);
         land_wait();
 #pragma unroll
         for (int k = 0; k < kPre; k++)
@@ -284,11 +289,13 @@ __device__ __forceinline__ void step_parcel(const StepArgs<T> &a, const int i, f
         int jj[kPre];
 #pragma unroll
         for (int k = 0; k < kPre; k++) jj[k] = jn[k];
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int k = 0; k < kPre; k++)
           if (jj[k] >= 0) land_pos(a.in.pos, jj[k], wl + k * 2048);
 #pragma unroll
         for (int k = 0; k < kPre; k++) jn[k] = (t0 + kPre + k < c_far) ? a.nb.idx[(long)(t0 + kPre + k) * N + i] : -1;
+        __builtin_amdgcn_s_setprio(0);
         land_wait();
 #pragma unroll
         for (int k = 0; k < kPre; k++)
